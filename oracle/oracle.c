@@ -1,0 +1,459 @@
+/*
+ * FP64 CPU oracle for high-precision single-source Personalized PageRank
+ * (Wu, Gan, Wei, Zhang: "Unifying the Global and Local Approaches: An
+ * Efficient Power Iteration with Forward Push", SIGMOD 2021).
+ *
+ * TEST INFRASTRUCTURE.  Only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark load this library.  It shares no code, header, table or
+ * helper with the GPU library; every routine is a plain, sequential, obviously
+ * correct restatement of a definition or algorithm of the paper, in double
+ * precision, with no blocking, fusion or reordering beyond what that passage
+ * states.
+ *
+ * Graph: CSR of out-edges (Section 2): row_ptr[n+1] (int64), col[m] (int32);
+ * d_v = row_ptr[v+1] - row_ptr[v] >= 1 (no dead ends, Section 2).  The
+ * transition matrix P has row v equal to A_v / d_v (Section 2).
+ *
+ * Readings of points the paper leaves open (each is repeated in the design
+ * notes of the repository):
+ *  - a push snapshots x = r(v), sets r(v) = 0, then distributes; the printed
+ *    order (distribute, then zero) loses mass on a self-loop (Section 3.2);
+ *  - "u is active" is the strict test r(u) > d_u * rmax with rmax = lambda / m
+ *    and the product taken in double precision (Section 3.2, Algorithm 3);
+ *  - "Q.size() <= scanThreshold = n/4" is the integer test 4 |Q| <= n at the
+ *    head of the local loop (Algorithm 3);
+ *  - r_sum is maintained incrementally inside the local loop and recomputed
+ *    exactly (Neumaier summation) after the local phase and after every scan
+ *    or sweep; termination uses the recomputed value (Algorithm 3);
+ *  - an epoch whose condition already fails runs zero scans (Algorithm 3);
+ *  - the paper's epoch loop condition r_sum > m * rmax' is used as printed.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+
+typedef struct {
+    int64_t pushes;          /* push operations performed */
+    int64_t edge_pushes;     /* residue updates: sum of d_v over pushes (Section 8) */
+    int32_t local_levels;    /* iterations S^(j) processed by the local phase (Section 4.2) */
+    int32_t sweeps;          /* global scans (Algorithm 3) or simultaneous sweeps (Eq. 7) */
+    int32_t scans_per_epoch[8];
+    int32_t switched;        /* 1 if the global phase ran */
+    int32_t pad;
+    double r_sum;            /* exact residue sum at return */
+} oracle_stats;
+
+/* ------------------------------------------------------------------ */
+/* Compensated (Neumaier) summation of a vector.                        */
+/* ------------------------------------------------------------------ */
+double oracle_sum(int64_t len, const double* x) {
+    double s = 0.0, c = 0.0;
+    for (int64_t i = 0; i < len; ++i) {
+        double t = s + x[i];
+        if (fabs(s) >= fabs(x[i])) c += (s - t) + x[i];
+        else c += (x[i] - t) + s;
+        s = t;
+    }
+    return s + c;
+}
+
+static double sum_abs(int64_t len, const double* x) {
+    double s = 0.0, c = 0.0;
+    for (int64_t i = 0; i < len; ++i) {
+        double a = fabs(x[i]);
+        double t = s + a;
+        if (s >= a) c += (s - t) + a; else c += (a - t) + s;
+        s = t;
+    }
+    return s + c;
+}
+
+/* ------------------------------------------------------------------ */
+/* In-edge lists (CSC) by counting sort: for every edge (v, u) of the   */
+/* CSR, v is appended to the in-list of u while v runs 0..n-1, so each  */
+/* in-list is ascending.  Also the out-degree table d_v (Section 2).    */
+/* ------------------------------------------------------------------ */
+int oracle_csc(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col,
+               int64_t* col_ptr, int32_t* row_idx, int32_t* deg_out) {
+    if (row_ptr[n] != m) return -1;
+    for (int32_t u = 0; u <= n; ++u) col_ptr[u] = 0;
+    for (int64_t e = 0; e < m; ++e) col_ptr[col[e] + 1]++;
+    for (int32_t u = 0; u < n; ++u) col_ptr[u + 1] += col_ptr[u];
+    int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n > 0 ? n : 1));
+    if (!fill) return -2;
+    for (int32_t u = 0; u < n; ++u) fill[u] = col_ptr[u];
+    for (int32_t v = 0; v < n; ++v) {
+        deg_out[v] = (int32_t)(row_ptr[v + 1] - row_ptr[v]);
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) row_idx[fill[col[e]]++] = v;
+    }
+    free(fill);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* The push operation on v (Section 3.2): alpha of r(v) moves to the    */
+/* reserve of v, the rest is split evenly over the out-neighbours, and  */
+/* r(v) becomes 0.                                                      */
+/* ------------------------------------------------------------------ */
+void oracle_push(const int64_t* row_ptr, const int32_t* col, double alpha,
+                 double* pi, double* r, int32_t v) {
+    double x = r[v];
+    int64_t d = row_ptr[v + 1] - row_ptr[v];
+    r[v] = 0.0;
+    pi[v] += alpha * x;
+    double inc = (1.0 - alpha) * x / (double)d;
+    for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) r[col[e]] += inc;
+}
+
+/* ------------------------------------------------------------------ */
+/* First-In-First-Out Forward Push (Algorithm 2), with the iteration    */
+/* sets S^(j) of Section 4.2 recorded: S^(0) = {s}; S^(j+1) holds the   */
+/* nodes appended while the nodes of S^(j) are processed.               */
+/* trace_nodes / trace_levels (nullable, trace_cap entries) receive the */
+/* popped node and its iteration j, in pop order.                       */
+/* Returns the number of pushes, or -2 if memory runs out.              */
+/* ------------------------------------------------------------------ */
+int64_t oracle_fifo_fwdpush(int32_t n, const int64_t* row_ptr, const int32_t* col,
+                            int32_t s, double alpha, double rmax, double* pi, double* r,
+                            int32_t* trace_nodes, int32_t* trace_levels, int64_t trace_cap,
+                            oracle_stats* st) {
+    int32_t* q = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t* qlev = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    uint8_t* inq = (uint8_t*)calloc((size_t)n, 1);
+    if (!q || !qlev || !inq) { free(q); free(qlev); free(inq); return -2; }
+    for (int32_t v = 0; v < n; ++v) { pi[v] = 0.0; r[v] = 0.0; }
+    r[s] = 1.0;
+    /* circular FIFO of capacity n: a node is in it at most once */
+    int64_t head = 0, size = 0, pushes = 0, edges = 0;
+    int32_t maxlev = 0;
+    q[0] = s; qlev[0] = 0; inq[s] = 1; size = 1;
+    while (size > 0) {
+        int32_t v = q[head % n];
+        int32_t lev = qlev[head % n];
+        head++; size--;
+        inq[v] = 0;
+        if (trace_nodes && pushes < trace_cap) { trace_nodes[pushes] = v; trace_levels[pushes] = lev; }
+        if (lev > maxlev) maxlev = lev;
+        double x = r[v];
+        int64_t d = row_ptr[v + 1] - row_ptr[v];
+        r[v] = 0.0;
+        pi[v] += alpha * x;
+        double inc = (1.0 - alpha) * x / (double)d;
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+            int32_t u = col[e];
+            r[u] += inc;
+            double du = (double)(row_ptr[u + 1] - row_ptr[u]);
+            if (r[u] > du * rmax && !inq[u]) {
+                int64_t tail = (head + size) % n;
+                q[tail] = u; qlev[tail] = lev + 1; inq[u] = 1; size++;
+            }
+        }
+        pushes++;
+        edges += d;
+    }
+    if (st) {
+        memset(st, 0, sizeof(*st));
+        st->pushes = pushes; st->edge_pushes = edges; st->local_levels = maxlev + 1;
+        st->r_sum = oracle_sum(n, r);
+    }
+    free(q); free(qlev); free(inq);
+    return pushes;
+}
+
+/* ------------------------------------------------------------------ */
+/* Power Iteration with Forward Push (Algorithm 3, Section 5), as       */
+/* printed: a FIFO local phase with rmax = lambda/m while the queue is  */
+/* non-empty, holds at most n/4 nodes and r_sum > lambda; then, if      */
+/* r_sum > lambda, epochs i = 1..8 of in-place sequential scans over    */
+/* v = 0..n-1 with rmax' = lambda^(i/8)/m, each epoch scanning while    */
+/* r_sum > m rmax'.  Pushes inside a scan are asynchronous: a node uses */
+/* residue it received earlier in the same scan.                        */
+/* rsum_trace (nullable, trace_cap entries): exact r_sum after the      */
+/* local phase and after each scan.  Returns the number of trace        */
+/* entries written, or -2 if memory runs out.                           */
+/* ------------------------------------------------------------------ */
+int oracle_powerpush(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col,
+                     int32_t s, double alpha, double lambda, double* pi, double* r,
+                     oracle_stats* st, double* rsum_trace, int32_t trace_cap) {
+    const int epoch_num = 8;
+    int32_t* q = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t* qlev = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    uint8_t* inq = (uint8_t*)calloc((size_t)n, 1);
+    if (!q || !qlev || !inq) { free(q); free(qlev); free(inq); return -2; }
+    oracle_stats S;
+    memset(&S, 0, sizeof(S));
+    int ntr = 0;
+    for (int32_t v = 0; v < n; ++v) { pi[v] = 0.0; r[v] = 0.0; }
+    r[s] = 1.0;
+    double r_sum = 1.0;
+    double rmax = lambda / (double)m;
+    int64_t head = 0, size = 1;
+    int32_t maxlev = 0;
+    q[0] = s; qlev[0] = 0; inq[s] = 1;
+    /* local phase */
+    while (size > 0 && 4 * size <= (int64_t)n && r_sum > lambda) {
+        int32_t v = q[head % n];
+        int32_t lev = qlev[head % n];
+        head++; size--;
+        inq[v] = 0;
+        if (lev > maxlev) maxlev = lev;
+        double x = r[v];
+        int64_t d = row_ptr[v + 1] - row_ptr[v];
+        r[v] = 0.0;
+        pi[v] += alpha * x;
+        r_sum -= alpha * x;
+        double inc = (1.0 - alpha) * x / (double)d;
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+            int32_t u = col[e];
+            r[u] += inc;
+            double du = (double)(row_ptr[u + 1] - row_ptr[u]);
+            if (!inq[u] && r[u] > du * rmax) {
+                int64_t tail = (head + size) % n;
+                q[tail] = u; qlev[tail] = lev + 1; inq[u] = 1; size++;
+            }
+        }
+        S.pushes++;
+        S.edge_pushes += d;
+    }
+    S.local_levels = maxlev + 1;
+    r_sum = oracle_sum(n, r);
+    if (rsum_trace && ntr < trace_cap) rsum_trace[ntr++] = r_sum;
+    /* global phase: sequential scans in epochs */
+    if (r_sum > lambda) {
+        S.switched = 1;
+        for (int i = 1; i <= epoch_num; ++i) {
+            double rmax_i = pow(lambda, (double)i / (double)epoch_num) / (double)m;
+            while (r_sum > (double)m * rmax_i) {
+                int64_t pushed = 0;
+                for (int32_t v = 0; v < n; ++v) {
+                    int64_t d = row_ptr[v + 1] - row_ptr[v];
+                    if (r[v] > (double)d * rmax_i) {
+                        double x = r[v];
+                        r[v] = 0.0;
+                        pi[v] += alpha * x;
+                        double inc = (1.0 - alpha) * x / (double)d;
+                        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) r[col[e]] += inc;
+                        pushed++;
+                        S.edge_pushes += d;
+                    }
+                }
+                S.pushes += pushed;
+                S.sweeps++;
+                S.scans_per_epoch[i - 1]++;
+                r_sum = oracle_sum(n, r);
+                if (rsum_trace && ntr < trace_cap) rsum_trace[ntr++] = r_sum;
+                if (pushed == 0) break;
+            }
+        }
+    }
+    S.r_sum = r_sum;
+    if (st) *st = S;
+    free(q); free(qlev); free(inq);
+    return ntr;
+}
+
+/* ------------------------------------------------------------------ */
+/* One Simultaneous Forward Push iteration (Section 4.1, Eq. 7): every  */
+/* node with non-zero residue pushes its residue r_in(v) at once, so    */
+/* r_out = (1 - alpha) r_in P and pi += alpha r_in.  Pushes run over    */
+/* v = 0..n-1 and each node's out-list in CSR order.                    */
+/* ------------------------------------------------------------------ */
+void oracle_sim_sweep(int32_t n, const int64_t* row_ptr, const int32_t* col, double alpha,
+                      const double* r_in, double* r_out, double* pi) {
+    for (int32_t u = 0; u < n; ++u) r_out[u] = 0.0;
+    for (int32_t v = 0; v < n; ++v) {
+        double x = r_in[v];
+        if (x == 0.0) continue;
+        int64_t d = row_ptr[v + 1] - row_ptr[v];
+        pi[v] += alpha * x;
+        double inc = (1.0 - alpha) * x / (double)d;
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) r_out[col[e]] += inc;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* The level-synchronous schedule that the GPU path runs, stated with   */
+/* the paper's objects:                                                 */
+/*  - local phase: the iterations S^(j) of Section 4.2, each performed  */
+/*    simultaneously (every node of S^(j) pushes the residue it held at */
+/*    the start of the iteration; Section 4.1); S^(j+1) is the set of   */
+/*    nodes whose residue became active during iteration j.  The phase  */
+/*    runs while S^(j) is non-empty, r_sum > lambda and the switch rule */
+/*    allows it;                                                        */
+/*  - global phase: Simultaneous Forward Push with rmax = 0 (Eq. 7),    */
+/*    identical to power iteration by Lemma 1, until r_sum <= lambda.   */
+/* Switch rule 0: continue while 4 |S^(j)| <= n (Algorithm 3's          */
+/* scanThreshold = n/4).  Rule 1: continue while                        */
+/* switch_param * sum_{v in S^(j)} d_v <= m (edge volume).              */
+/* The local r_sum is updated as r_sum - alpha * sum_{v in S^(j)} x_v   */
+/* per iteration (Eq. 8) and recomputed exactly when the phase ends;    */
+/* the global phase recomputes it exactly after every sweep.            */
+/* Per iteration j (nullable arrays of level_cap entries): level_sizes  */
+/* receives |S^(j)|, level_vols sum_{v in S^(j)} d_v, level_rsum the    */
+/* r_sum at the start of iteration j (used to check Eq. 9).             */
+/* Returns 0, or -2 if memory runs out.                                 */
+/* ------------------------------------------------------------------ */
+int oracle_powerpush_sync(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col,
+                          int32_t s, double alpha, double lambda, int switch_rule,
+                          double switch_param, double* pi, double* r, oracle_stats* st,
+                          double* rsum_trace, int32_t trace_cap,
+                          int32_t* level_sizes, int64_t* level_vols, double* level_rsum,
+                          int32_t level_cap) {
+    int32_t* F = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t* F2 = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    double* x = (double*)malloc(sizeof(double) * (size_t)n);
+    double* r2 = (double*)malloc(sizeof(double) * (size_t)n);
+    int32_t* mark = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    if (!F || !F2 || !x || !r2 || !mark) { free(F); free(F2); free(x); free(r2); free(mark); return -2; }
+    oracle_stats S;
+    memset(&S, 0, sizeof(S));
+    int ntr = 0;
+    for (int32_t v = 0; v < n; ++v) { pi[v] = 0.0; r[v] = 0.0; mark[v] = -1; }
+    r[s] = 1.0;
+    double r_sum = 1.0;
+    double rmax = lambda / (double)m;
+    int64_t nf = 1;
+    F[0] = s;
+    int32_t level = 0;
+    for (;;) {
+        if (nf == 0 || !(r_sum > lambda)) break;
+        int64_t vol = 0;
+        for (int64_t i = 0; i < nf; ++i) vol += row_ptr[F[i] + 1] - row_ptr[F[i]];
+        if (switch_rule == 0 && !(4 * nf <= (int64_t)n)) break;
+        if (switch_rule == 1 && !(switch_param * (double)vol <= (double)m)) break;
+        if (level < level_cap) {
+            if (level_sizes) level_sizes[level] = (int32_t)nf;
+            if (level_vols) level_vols[level] = vol;
+            if (level_rsum) level_rsum[level] = r_sum;
+        }
+        /* snapshot: every node of S^(j) pushes the residue it holds now */
+        double taken = 0.0;
+        for (int64_t i = 0; i < nf; ++i) {
+            int32_t v = F[i];
+            x[i] = r[v];
+            r[v] = 0.0;
+            pi[v] += alpha * x[i];
+            taken += alpha * x[i];
+        }
+        /* distribute; a node joins S^(j+1) the first time its residue is active */
+        int64_t nf2 = 0;
+        for (int64_t i = 0; i < nf; ++i) {
+            int32_t v = F[i];
+            int64_t d = row_ptr[v + 1] - row_ptr[v];
+            double inc = (1.0 - alpha) * x[i] / (double)d;
+            for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+                int32_t u = col[e];
+                r[u] += inc;
+                double du = (double)(row_ptr[u + 1] - row_ptr[u]);
+                if (mark[u] != level + 1 && r[u] > du * rmax) { mark[u] = level + 1; F2[nf2++] = u; }
+            }
+        }
+        S.pushes += nf;
+        S.edge_pushes += vol;
+        r_sum -= taken;
+        int32_t* t = F; F = F2; F2 = t;
+        nf = nf2;
+        level++;
+    }
+    S.local_levels = level;
+    r_sum = oracle_sum(n, r);
+    if (rsum_trace && ntr < trace_cap) rsum_trace[ntr++] = r_sum;
+    if (r_sum > lambda) S.switched = 1;
+    while (r_sum > lambda) {
+        oracle_sim_sweep(n, row_ptr, col, alpha, r, r2, pi);
+        memcpy(r, r2, sizeof(double) * (size_t)n);
+        S.sweeps++;
+        S.edge_pushes += m;
+        S.pushes += n;
+        r_sum = oracle_sum(n, r);
+        if (rsum_trace && ntr < trace_cap) rsum_trace[ntr++] = r_sum;
+    }
+    S.r_sum = r_sum;
+    if (st) *st = S;
+    free(F); free(F2); free(x); free(r2); free(mark);
+    return ntr;
+}
+
+/* ------------------------------------------------------------------ */
+/* Power iteration (Section 3.1, Eqs. 3-5): gamma^(0) = e_s,            */
+/* gamma^(j+1) = (1 - alpha) gamma^(j) P, and the estimate after K      */
+/* iterations is sum_{k<K} alpha gamma^(k), whose l1 error is exactly   */
+/* (1 - alpha)^K (Eq. 6).  The estimate is accumulated with Neumaier    */
+/* compensation so that it serves as the converged truth.               */
+/* ------------------------------------------------------------------ */
+int oracle_powitr(int32_t n, const int64_t* row_ptr, const int32_t* col, int32_t s,
+                  double alpha, int32_t K, double* pi_out) {
+    double* g = (double*)calloc((size_t)n, sizeof(double));
+    double* g2 = (double*)malloc(sizeof(double) * (size_t)n);
+    double* comp = (double*)calloc((size_t)n, sizeof(double));
+    if (!g || !g2 || !comp) { free(g); free(g2); free(comp); return -2; }
+    for (int32_t v = 0; v < n; ++v) pi_out[v] = 0.0;
+    g[s] = 1.0;
+    for (int32_t j = 0; j < K; ++j) {
+        for (int32_t v = 0; v < n; ++v) {
+            double a = alpha * g[v];
+            double t = pi_out[v] + a;
+            if (fabs(pi_out[v]) >= fabs(a)) comp[v] += (pi_out[v] - t) + a;
+            else comp[v] += (a - t) + pi_out[v];
+            pi_out[v] = t;
+        }
+        for (int32_t u = 0; u < n; ++u) g2[u] = 0.0;
+        for (int32_t v = 0; v < n; ++v) {
+            if (g[v] == 0.0) continue;
+            int64_t d = row_ptr[v + 1] - row_ptr[v];
+            double inc = (1.0 - alpha) * g[v] / (double)d;
+            for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) g2[col[e]] += inc;
+        }
+        double* t = g; g = g2; g2 = t;
+    }
+    for (int32_t v = 0; v < n; ++v) pi_out[v] += comp[v];
+    free(g); free(g2); free(comp);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Residual certificate, from the linear system of Eq. 1:               */
+/*   rt = e_s - (pi_hat - (1 - alpha) pi_hat P) / alpha.                */
+/* Since the PPR vectors pi_v are the rows of alpha (I - (1-alpha)P)^-1,*/
+/* pi_s - pi_hat = sum_v rt(v) pi_v, and with ||pi_v||_1 = 1            */
+/* (Section 2), ||pi_hat - pi_s||_1 <= ||rt||_1, with equality when     */
+/* rt >= 0.  Returns ||rt||_1 (compensated); rt is written if non-null. */
+/* ------------------------------------------------------------------ */
+double oracle_certificate(int32_t n, const int64_t* row_ptr, const int32_t* col, int32_t s,
+                          double alpha, const double* pi_hat, double* rt_out) {
+    double* q = (double*)calloc((size_t)n, sizeof(double));   /* q = pi_hat P */
+    double* rt = rt_out ? rt_out : (double*)malloc(sizeof(double) * (size_t)n);
+    if (!q || !rt) { free(q); if (!rt_out) free(rt); return -1.0; }
+    for (int32_t v = 0; v < n; ++v) {
+        if (pi_hat[v] == 0.0) continue;
+        int64_t d = row_ptr[v + 1] - row_ptr[v];
+        double inc = pi_hat[v] / (double)d;
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) q[col[e]] += inc;
+    }
+    for (int32_t u = 0; u < n; ++u)
+        rt[u] = (u == s ? 1.0 : 0.0) - (pi_hat[u] - (1.0 - alpha) * q[u]) / alpha;
+    double l1 = sum_abs(n, rt);
+    free(q);
+    if (!rt_out) free(rt);
+    return l1;
+}
+
+/* ------------------------------------------------------------------ */
+/* Several independent queries of Algorithm 3, one per thread; used to  */
+/* time the oracle on the host's cores.  pi_out / r_out hold count rows */
+/* of n doubles.  Returns 0, or -2 if a query ran out of memory.        */
+/* ------------------------------------------------------------------ */
+int oracle_powerpush_many(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col,
+                          const int32_t* sources, int32_t count, double alpha, double lambda,
+                          double* pi_out, double* r_out, oracle_stats* st, int32_t threads) {
+    int rc = 0;
+    #pragma omp parallel for schedule(dynamic, 1) num_threads(threads) reduction(min:rc)
+    for (int32_t i = 0; i < count; ++i) {
+        int k = oracle_powerpush(n, m, row_ptr, col, sources[i], alpha, lambda,
+                                 pi_out + (int64_t)i * n, r_out + (int64_t)i * n,
+                                 st ? st + i : NULL, NULL, 0);
+        if (k < 0) rc = k;
+    }
+    return rc;
+}
