@@ -1,0 +1,194 @@
+/*
+ * ppr.h -- C ABI of the MI355X high-precision single-source PPR library
+ * (libppr.so).
+ *
+ * The library answers High-Precision SSPPR queries (Section 2 of Wu, Gan, Wei,
+ * Zhang, "Unifying the Global and Local Approaches: An Efficient Power
+ * Iteration with Forward Push", SIGMOD 2021): given a directed graph G, a
+ * source s, the stop probability alpha of the alpha-random walk and an l1
+ * error threshold lambda in (0, 1], it returns pi_hat with
+ *     || pi_hat - pi_s ||_1 <= lambda,
+ * where pi_s solves the linear system of Eq. 1,
+ *     pi_s = alpha e_s + (1 - alpha) pi_s P,   P = D^-1 A (Section 2).
+ *
+ * Method (PowerPush, Algorithm 3, run level-synchronously on the GPU): a
+ * forward-push local phase over frontiers (the iteration sets S^(j) of
+ * Section 4.2, pushed simultaneously), then global push sweeps over every
+ * edge with rmax = 0 (Simultaneous Forward Push, Eq. 7, identical to power
+ * iteration by Lemma 1), until the residue sum r_sum <= lambda.
+ *
+ * Conventions
+ *  - Every function returns a ppr_status; no C++ exception crosses the ABI.
+ *    On failure ppr_last_error() returns a thread-local message.
+ *  - Inputs are borrowed: the library copies what it keeps; the caller keeps
+ *    ownership of every buffer it passes.
+ *  - Output buffers are caller-owned and may be host or device memory (the
+ *    library detects which with hipPointerGetAttributes).  A device output
+ *    must be on the device the graph was created on.
+ *  - A ppr_graph is immutable after creation; queries on one graph from
+ *    different threads are safe (each call takes its own state slot and HIP
+ *    stream from the graph's pool).  A ppr_block is used from one thread.
+ *  - Node ids are 0..n-1 (int32).  Edge counts and offsets are int64.
+ *  - All calls are synchronous unless stated: they return once results are
+ *    in the caller's buffer.
+ */
+#ifndef PPR_H
+#define PPR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ppr_graph ppr_graph;   /* opaque, library-owned, device resident */
+typedef struct ppr_block ppr_block;   /* opaque serving block (slots of one graph) */
+
+typedef enum {
+    PPR_OK = 0,
+    PPR_ERR_ARG = -1,            /* bad argument (null pointer, out of range, NaN) */
+    PPR_ERR_CSR = -2,            /* CSR malformed: offsets not monotone, row_ptr[0] != 0,
+                                    row_ptr[n] != m, or a column index outside [0, n) */
+    PPR_ERR_DANGLING = -3,       /* a node has out-degree 0 (Section 2 assumes d_v >= 1) */
+    PPR_ERR_DUPLICATE = -4,      /* an edge appears twice (A is a 0/1 matrix, Section 2) */
+    PPR_ERR_OOM = -5,            /* device or host allocation failed, or over budget */
+    PPR_ERR_DEVICE = -6,         /* a HIP runtime call failed, or no GPU is present */
+    PPR_ERR_NOT_CONVERGED = -7,  /* max_sweeps reached before r_sum <= lambda */
+    PPR_ERR_BUSY = -8            /* no free slot in a serving block */
+} ppr_status;
+
+typedef enum {
+    PPR_FP64 = 0,    /* plain path: residues, reserves and sums in double precision */
+    PPR_MIXED = 1    /* FP32 residues, compensated FP32 (hi, lo) reserves; FP64 r_sum,
+                        FP64 residual refresh and FP64 final flush */
+} ppr_precision;
+
+/* Rule that ends the local (frontier) phase and starts the global sweeps. */
+typedef enum {
+    PPR_SWITCH_NODES = 0,  /* continue while 4 |S^(j)| <= n: Algorithm 3's
+                              scanThreshold = n/4 */
+    PPR_SWITCH_EDGES = 1   /* continue while switch_param * sum_{v in S^(j)} d_v <= m:
+                              edge volume, the GPU cost model (default) */
+} ppr_switch_rule;
+
+/* Per-query statistics. */
+typedef struct {
+    int32_t local_levels;   /* frontier iterations S^(j) run by the local phase */
+    int32_t sweeps;         /* global sweeps (each reads every edge once) */
+    int32_t refreshes;      /* FP64 residual refresh passes (mixed path) */
+    int32_t source;         /* the query's source node */
+    int64_t edge_pushes;    /* residue updates: sum of d_v over local pushes + sweeps * m */
+    double r_sum;           /* residue sum when the query stopped (FP64) */
+    double cert_l1;         /* ||e_s - pi_hat (I - (1-alpha) P) / alpha||_1 computed in FP64
+                               (always for PPR_MIXED; for PPR_FP64 only when certify = 1,
+                               else -1).  An upper bound on ||pi_hat - pi_s||_1. */
+    double ms;              /* wall time of the call (whole batch for batched calls) */
+} ppr_stats;
+
+/* Query options (ppr_options_default fills the defaults). */
+typedef struct {
+    int32_t precision;      /* ppr_precision */
+    int32_t switch_rule;    /* ppr_switch_rule; default PPR_SWITCH_EDGES */
+    double switch_param;    /* PPR_SWITCH_EDGES: continue while param * vol <= m; default 8 */
+    int32_t max_sweeps;     /* cap on global sweeps; default 4096 */
+    int32_t certify;        /* PPR_FP64: also compute cert_l1; default 0 */
+    double refresh_factor;  /* PPR_MIXED: refresh the residual in FP64 whenever r_sum has
+                               fallen by this factor since the last refresh; default 1e4 */
+    int32_t batch_cols;     /* PPR_MIXED batched: columns per block (multiple of 4, or 0 =
+                               autotuned); default 0 */
+    int32_t reserved[5];
+} ppr_options;
+
+/* Read-only facts about a created graph. */
+typedef struct {
+    int32_t n;
+    int32_t max_in_degree;
+    int64_t m;
+    int32_t max_out_degree;
+    int32_t offsets_64bit;  /* 1 if the device CSC offsets are int64 (m >= 2^32) */
+    double build_ms;        /* wall time of ppr_graph_create */
+    size_t device_bytes;    /* device memory held by the graph */
+} ppr_graph_info;
+
+/* Default options. */
+void ppr_options_default(ppr_options* opt);
+
+/*
+ * Create a device-resident graph from CSR out-edges (the storage the paper's
+ * global scan assumes: nodes sorted by id, adjacency lists concatenated,
+ * Section 5).
+ *   row_ptr: host int64[n+1], row_ptr[0] = 0, non-decreasing, row_ptr[n] = m.
+ *   col:     host int32[m], col[row_ptr[v] .. row_ptr[v+1]) = out-neighbours of v.
+ *   n >= 1, m >= n (every node needs an out-edge).
+ *   flags:   PPR_GRAPH_TRUST_INPUT skips the O(n + m) host validation.
+ * Validation (unless skipped): PPR_ERR_CSR, PPR_ERR_DANGLING, PPR_ERR_DUPLICATE.
+ * Self-loops are allowed.  The library builds on the current HIP device the
+ * in-edge lists (CSC, each list ascending by source id), the out-degree
+ * table and the sweep schedule.  *out receives the handle.
+ */
+#define PPR_GRAPH_TRUST_INPUT 1u
+ppr_status ppr_graph_create(const int64_t* row_ptr, const int32_t* col, int32_t n, int64_t m,
+                            uint32_t flags, ppr_graph** out);
+
+/* Release the graph and everything it owns.  NULL is accepted. */
+ppr_status ppr_graph_destroy(ppr_graph* g);
+
+/* Facts about the graph. */
+ppr_status ppr_graph_get_info(const ppr_graph* g, ppr_graph_info* info);
+
+/*
+ * Copy the device CSC to host buffers (for verification): col_ptr int64[n+1],
+ * row_idx int32[m] (in-list of u is row_idx[col_ptr[u] .. col_ptr[u+1]),
+ * ascending), deg_out int32[n].  Any pointer may be NULL to skip it.
+ */
+ppr_status ppr_graph_copy_csc(const ppr_graph* g, int64_t* col_ptr, int32_t* row_idx,
+                              int32_t* deg_out);
+
+/*
+ * One HP-SSPPR query.  alpha in (0, 1), lambda in (0, 1], 0 <= s < n.
+ * pi_out: double[n] (host or device), receives pi_hat.  stats nullable.
+ * Uses the default options with the given precision.
+ */
+ppr_status ppr_query(ppr_graph* g, int32_t s, double alpha, double lambda,
+                     ppr_precision precision, double* pi_out, ppr_stats* stats);
+
+/*
+ * B queries on the same graph.  sources int32[B] (host), pi_out double[B*n]
+ * row-major (row b is the answer for sources[b]), stats ppr_stats[B] or NULL.
+ * PPR_FP64 runs the plain path once per source; PPR_MIXED runs the sources as
+ * columns of an n x B block so that every edge read serves all columns.
+ */
+ppr_status ppr_query_batch(ppr_graph* g, const int32_t* sources, int32_t B, double alpha,
+                           double lambda, ppr_precision precision, double* pi_out,
+                           ppr_stats* stats);
+
+/*
+ * General form of the two calls above.  opt NULL means defaults.
+ * r_out (nullable, double[B*n]) receives the final residue of each query
+ * (PPR_FP64: the pushed residue r; PPR_MIXED: the FP64 residual of the flush).
+ */
+ppr_status ppr_query_ex(ppr_graph* g, const int32_t* sources, int32_t B, double alpha,
+                        double lambda, const ppr_options* opt, double* pi_out, double* r_out,
+                        ppr_stats* stats);
+
+/*
+ * One global sweep on caller data, for verification of the sweep kernel:
+ * r_out = (1 - alpha) r_in P and pi += alpha r_in (Simultaneous Forward Push,
+ * Eq. 7), all double[n] in device memory; *r_sum_out (host) receives
+ * sum(r_out) in FP64.
+ */
+ppr_status ppr_debug_sweep_fp64(ppr_graph* g, double alpha, const double* r_in, double* r_out,
+                                double* pi, double* r_sum_out);
+
+/* Library version string. */
+const char* ppr_version(void);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* ppr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PPR_H */

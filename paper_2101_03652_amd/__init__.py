@@ -1,0 +1,211 @@
+"""Python binding of libppr: high-precision single-source Personalized PageRank
+on one MI355X (PowerPush, Wu, Gan, Wei, Zhang, SIGMOD 2021).
+
+This module only marshals arguments to the C ABI declared in include/ppr.h;
+every step of a query runs in the library's HIP kernels.  There is no CPU
+fallback: if libppr.so is missing or no GPU is present, calls raise.
+
+Buffers: graph inputs are host numpy arrays.  Outputs may be numpy arrays
+(host) or torch tensors on the GPU (device pointers are passed straight
+through); PyTorch serves only as a device allocator here.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libppr.so")
+
+PPR_OK = 0
+STATUS = {0: "PPR_OK", -1: "PPR_ERR_ARG", -2: "PPR_ERR_CSR", -3: "PPR_ERR_DANGLING",
+          -4: "PPR_ERR_DUPLICATE", -5: "PPR_ERR_OOM", -6: "PPR_ERR_DEVICE",
+          -7: "PPR_ERR_NOT_CONVERGED", -8: "PPR_ERR_BUSY"}
+FP64 = 0
+MIXED = 1
+SWITCH_NODES = 0
+SWITCH_EDGES = 1
+GRAPH_TRUST_INPUT = 1
+
+# every symbol include/ppr.h declares (checked by the CPU tests)
+EXPORTS = [
+    "ppr_options_default", "ppr_graph_create", "ppr_graph_destroy", "ppr_graph_get_info",
+    "ppr_graph_copy_csc", "ppr_query", "ppr_query_batch", "ppr_query_ex",
+    "ppr_debug_sweep_fp64", "ppr_version", "ppr_last_error",
+]
+
+
+class PPRError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("local_levels", ctypes.c_int32), ("sweeps", ctypes.c_int32),
+                ("refreshes", ctypes.c_int32), ("source", ctypes.c_int32),
+                ("edge_pushes", ctypes.c_int64), ("r_sum", ctypes.c_double),
+                ("cert_l1", ctypes.c_double), ("ms", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("switch_rule", ctypes.c_int32),
+                ("switch_param", ctypes.c_double), ("max_sweeps", ctypes.c_int32),
+                ("certify", ctypes.c_int32), ("refresh_factor", ctypes.c_double),
+                ("batch_cols", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("max_in_degree", ctypes.c_int32), ("m", ctypes.c_int64),
+                ("max_out_degree", ctypes.c_int32), ("offsets_64bit", ctypes.c_int32),
+                ("build_ms", ctypes.c_double), ("device_bytes", ctypes.c_size_t)]
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load libppr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                          "(hipcc, gfx950); there is no fallback path")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    st = ctypes.c_int
+    sig = {
+        "ppr_options_default": (None, [vp]),
+        "ppr_graph_create": (st, [vp, vp, i32, i64, ctypes.c_uint32, ctypes.POINTER(vp)]),
+        "ppr_graph_destroy": (st, [vp]),
+        "ppr_graph_get_info": (st, [vp, vp]),
+        "ppr_graph_copy_csc": (st, [vp, vp, vp, vp]),
+        "ppr_query": (st, [vp, i32, f64, f64, ctypes.c_int, vp, vp]),
+        "ppr_query_batch": (st, [vp, vp, i32, f64, f64, ctypes.c_int, vp, vp]),
+        "ppr_query_ex": (st, [vp, vp, i32, f64, f64, vp, vp, vp, vp]),
+        "ppr_debug_sweep_fp64": (st, [vp, f64, vp, vp, vp, vp]),
+        "ppr_version": (ctypes.c_char_p, []),
+        "ppr_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc: int) -> None:
+    if rc != PPR_OK:
+        raise PPRError(rc, (load().ppr_last_error() or b"").decode())
+
+
+def _ptr(x):
+    """Raw address of a numpy array or a torch tensor (host or device)."""
+    if isinstance(x, np.ndarray):
+        if not x.flags.c_contiguous:
+            raise ValueError("array must be C-contiguous")
+        return x.ctypes.data
+    if hasattr(x, "data_ptr"):
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return x.data_ptr()
+    raise TypeError(f"unsupported buffer type {type(x)}")
+
+
+def options(**kw) -> Options:
+    o = Options()
+    load().ppr_options_default(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+class Graph:
+    """A device-resident graph (CSC built on the GPU from CSR out-edges)."""
+
+    def __init__(self, row_ptr: np.ndarray, col: np.ndarray, n: int | None = None,
+                 trust_input: bool = False):
+        lib = load()
+        self._row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        self._col = np.ascontiguousarray(col, dtype=np.int32)
+        self.n = int(len(self._row_ptr) - 1 if n is None else n)
+        self.m = int(len(self._col))
+        h = ctypes.c_void_p()
+        _check(lib.ppr_graph_create(_ptr(self._row_ptr), _ptr(self._col) if self.m else None,
+                                    self.n, self.m, GRAPH_TRUST_INPUT if trust_input else 0,
+                                    ctypes.byref(h)))
+        self._h = h
+        del self._row_ptr, self._col
+
+    @classmethod
+    def from_synth(cls, g, trust_input: bool = False) -> "Graph":
+        return cls(g.row_ptr, g.col, g.n, trust_input=trust_input)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            load().ppr_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def info(self) -> dict:
+        gi = GraphInfo()
+        _check(load().ppr_graph_get_info(self._h, ctypes.byref(gi)))
+        return {k: getattr(gi, k) for k, _ in gi._fields_}
+
+    def csc(self):
+        """Host copies of (col_ptr int64[n+1], row_idx int32[m], deg_out int32[n])."""
+        col_ptr = np.empty(self.n + 1, dtype=np.int64)
+        row_idx = np.empty(max(self.m, 1), dtype=np.int32)
+        deg = np.empty(self.n, dtype=np.int32)
+        _check(load().ppr_graph_copy_csc(self._h, _ptr(col_ptr), _ptr(row_idx), _ptr(deg)))
+        return col_ptr, row_idx[:self.m], deg
+
+    # ---- queries
+    def query(self, s: int, alpha: float = 0.2, lam: float = 1e-8, precision: int = FP64,
+              out=None, **opt):
+        """pi_hat for source s (numpy float64[n] unless `out` is given)."""
+        res = self.query_batch([s], alpha, lam, precision, out=out, **opt)
+        return (res[0][0] if out is None else res[0]), res[1][0]
+
+    def query_batch(self, sources, alpha: float = 0.2, lam: float = 1e-8, precision: int = FP64,
+                    out=None, r_out=None, **opt):
+        """pi_hat for every source: float64[B, n] (host array or device tensor `out`)."""
+        src = np.ascontiguousarray(np.asarray(sources, dtype=np.int32).reshape(-1))
+        B = len(src)
+        if out is None:
+            out = np.empty((B, self.n), dtype=np.float64)
+        st = (Stats * B)()
+        o = options(precision=precision, **opt)
+        rc = load().ppr_query_ex(self._h, _ptr(src), B, float(alpha), float(lam), ctypes.byref(o),
+                                 _ptr(out), _ptr(r_out) if r_out is not None else None, st)
+        _check(rc)
+        return out, [s.as_dict() for s in st]
+
+    def debug_sweep(self, alpha: float, r_in, r_out, pi) -> float:
+        """One Eq. 7 sweep on device tensors: r_out = (1-alpha) r_in P, pi += alpha r_in."""
+        rs = ctypes.c_double()
+        _check(load().ppr_debug_sweep_fp64(self._h, float(alpha), _ptr(r_in), _ptr(r_out), _ptr(pi),
+                                           ctypes.byref(rs)))
+        return rs.value
+
+
+def version() -> str:
+    return load().ppr_version().decode()

@@ -1,0 +1,185 @@
+// C ABI entry points of libppr.  Every function converts internal failures
+// (ppr::Failure, std::bad_alloc, other exceptions) into a status code and a
+// thread-local message; nothing throws across the boundary.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "ppr_internal.h"
+
+using namespace ppr;
+
+namespace {
+
+template <class F>
+ppr_status guarded(F&& f) {
+    try {
+        f();
+        set_error("");
+        return PPR_OK;
+    } catch (const Failure& e) {
+        set_error(e.msg);
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return PPR_ERR_OOM;
+    } catch (const std::exception& e) {
+        set_error(e.what());
+        return PPR_ERR_DEVICE;
+    } catch (...) {
+        set_error("unknown failure");
+        return PPR_ERR_DEVICE;
+    }
+}
+
+void check_query_args(const Graph* g, const int32_t* sources, int32_t B, double alpha, double lambda,
+                      const void* pi_out) {
+    if (!g) fail(PPR_ERR_ARG, "graph is NULL");
+    if (!sources) fail(PPR_ERR_ARG, "sources is NULL");
+    if (!pi_out) fail(PPR_ERR_ARG, "pi_out is NULL");
+    if (B < 1) fail(PPR_ERR_ARG, "batch size must be >= 1");
+    if (!(alpha > 0.0 && alpha < 1.0)) fail(PPR_ERR_ARG, "alpha must lie in (0, 1)");
+    if (!(lambda > 0.0 && lambda <= 1.0)) fail(PPR_ERR_ARG, "lambda must lie in (0, 1]");
+    for (int32_t b = 0; b < B; ++b)
+        if (sources[b] < 0 || sources[b] >= g->n)
+            fail(PPR_ERR_ARG, "source " + std::to_string(sources[b]) + " is outside [0, n)");
+}
+
+void check_options(const ppr_options& o) {
+    if (o.precision != PPR_FP64 && o.precision != PPR_MIXED) fail(PPR_ERR_ARG, "unknown precision");
+    if (o.switch_rule != PPR_SWITCH_NODES && o.switch_rule != PPR_SWITCH_EDGES)
+        fail(PPR_ERR_ARG, "unknown switch rule");
+    if (!(o.switch_param >= 0.0) || std::isinf(o.switch_param)) fail(PPR_ERR_ARG, "switch_param must be finite and >= 0");
+    if (o.max_sweeps < 0) fail(PPR_ERR_ARG, "max_sweeps must be >= 0");
+    if (!(o.refresh_factor > 1.0)) fail(PPR_ERR_ARG, "refresh_factor must be > 1");
+    if (o.batch_cols < 0 || (o.batch_cols % 4) != 0) fail(PPR_ERR_ARG, "batch_cols must be 0 or a multiple of 4");
+}
+
+}  // namespace
+
+extern "C" {
+
+void ppr_options_default(ppr_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->precision = PPR_FP64;
+    o->switch_rule = PPR_SWITCH_EDGES;
+    o->switch_param = 8.0;
+    o->max_sweeps = 4096;
+    o->certify = 0;
+    o->refresh_factor = 1e4;
+    o->batch_cols = 0;
+}
+
+const char* ppr_version(void) { return "libppr 0.1 (gfx950)"; }
+
+const char* ppr_last_error(void) { return last_error_cstr(); }
+
+ppr_status ppr_graph_create(const int64_t* row_ptr, const int32_t* col, int32_t n, int64_t m,
+                            uint32_t flags, ppr_graph** out) {
+    return guarded([&] {
+        if (!out) fail(PPR_ERR_ARG, "out is NULL");
+        *out = nullptr;
+        Graph* g = graph_create(row_ptr, col, n, m, flags);
+        *out = reinterpret_cast<ppr_graph*>(g);
+    });
+}
+
+ppr_status ppr_graph_destroy(ppr_graph* gh) {
+    return guarded([&] {
+        Graph* g = reinterpret_cast<Graph*>(gh);
+        if (!g) return;
+        (void)hipSetDevice(g->device);
+        (void)hipDeviceSynchronize();
+        delete g;
+    });
+}
+
+ppr_status ppr_graph_get_info(const ppr_graph* gh, ppr_graph_info* info) {
+    return guarded([&] {
+        const Graph* g = reinterpret_cast<const Graph*>(gh);
+        if (!g || !info) fail(PPR_ERR_ARG, "NULL argument");
+        info->n = g->n;
+        info->m = g->m;
+        info->max_in_degree = g->max_in;
+        info->max_out_degree = g->max_out;
+        info->offsets_64bit = g->off64 ? 1 : 0;
+        info->build_ms = g->build_ms;
+        info->device_bytes = g->device_bytes();
+    });
+}
+
+ppr_status ppr_graph_copy_csc(const ppr_graph* gh, int64_t* col_ptr, int32_t* row_idx, int32_t* deg_out) {
+    return guarded([&] {
+        const Graph* g = reinterpret_cast<const Graph*>(gh);
+        if (!g) fail(PPR_ERR_ARG, "graph is NULL");
+        graph_copy_csc(*g, col_ptr, row_idx, deg_out);
+    });
+}
+
+ppr_status ppr_query_ex(ppr_graph* gh, const int32_t* sources, int32_t B, double alpha, double lambda,
+                        const ppr_options* opt, double* pi_out, double* r_out, ppr_stats* stats) {
+    return guarded([&] {
+        Graph* g = reinterpret_cast<Graph*>(gh);
+        check_query_args(g, sources, B, alpha, lambda, pi_out);
+        ppr_options o;
+        if (opt) o = *opt; else ppr_options_default(&o);
+        check_options(o);
+        if (o.precision == PPR_FP64) {
+            ppr_status first = PPR_OK;
+            std::string msg;
+            for (int32_t b = 0; b < B; ++b) {
+                try {
+                    run_fp64_query(*g, sources[b], alpha, lambda, o, pi_out + (size_t)b * g->n,
+                                   r_out ? r_out + (size_t)b * g->n : nullptr, stats ? stats + b : nullptr);
+                } catch (const Failure& e) {
+                    if (e.status != PPR_ERR_NOT_CONVERGED) throw;
+                    if (first == PPR_OK) { first = e.status; msg = e.msg; }
+                }
+            }
+            if (first != PPR_OK) fail(first, msg);
+        } else {
+            run_mixed_batch(*g, sources, B, alpha, lambda, o, pi_out, r_out, stats);
+        }
+    });
+}
+
+ppr_status ppr_query(ppr_graph* g, int32_t s, double alpha, double lambda, ppr_precision precision,
+                     double* pi_out, ppr_stats* stats) {
+    ppr_options o;
+    ppr_options_default(&o);
+    o.precision = precision;
+    return ppr_query_ex(g, &s, 1, alpha, lambda, &o, pi_out, nullptr, stats);
+}
+
+ppr_status ppr_query_batch(ppr_graph* g, const int32_t* sources, int32_t B, double alpha, double lambda,
+                           ppr_precision precision, double* pi_out, ppr_stats* stats) {
+    ppr_options o;
+    ppr_options_default(&o);
+    o.precision = precision;
+    return ppr_query_ex(g, sources, B, alpha, lambda, &o, pi_out, nullptr, stats);
+}
+
+ppr_status ppr_debug_sweep_fp64(ppr_graph* gh, double alpha, const double* r_in, double* r_out, double* pi,
+                                double* r_sum_out) {
+    return guarded([&] {
+        Graph* g = reinterpret_cast<Graph*>(gh);
+        if (!g || !r_in || !r_out || !pi) fail(PPR_ERR_ARG, "NULL argument");
+        if (!(alpha > 0.0 && alpha < 1.0)) fail(PPR_ERR_ARG, "alpha must lie in (0, 1)");
+        HIPCHECK(hipSetDevice(g->device));
+        const Schedule& sch = g->schedule(k::sweep_nnz_cap(), k::sweep_row_cap());
+        DevBuf y((size_t)g->n * 8), yo((size_t)g->n * 8);
+        DevBuf parts(8 * (size_t)std::max(sch.n_blocks, 1024)), sum(8);
+        int np = 0;
+        hipStream_t s = nullptr;
+        k::prep_y(r_in, g->deg.as<int32_t>(), alpha, g->n, y.as<double>(), parts.as<double>(), &np, s);
+        k::sweep_f64(*g, sch, k::SW_ENTRY | k::SW_WRITE_R, alpha, y.as<double>(), yo.as<double>(), pi, r_in,
+                     r_out, parts.as<double>(), s);
+        k::reduce_sum(parts.as<double>(), k::sweep_parts(sch), sum.as<double>(), s);
+        double h = 0;
+        HIPCHECK(hipMemcpy(&h, sum.p, 8, hipMemcpyDeviceToHost));
+        if (r_sum_out) *r_sum_out = h;
+    });
+}
+
+}  // extern "C"

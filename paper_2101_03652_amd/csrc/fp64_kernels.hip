@@ -1,0 +1,382 @@
+// FP64 kernels of the plain single-query path.
+//
+// Local phase (Algorithm 3's queue phase, run level-synchronously): the
+// frontier S^(j) (Section 4.2) is pushed simultaneously.  A snapshot kernel
+// takes every frontier residue x_v (r(v) <- 0, pi(v) += alpha x_v); a push
+// kernel then adds (1-alpha) x_v / d_v to every out-neighbour with FP64
+// atomics.  Residues only grow during the push, so exactly one atomic add
+// carries r(u) across the activity threshold d_u * rmax (strict >, Section
+// 3.2); that lane appends u to S^(j+1) with a wave-aggregated append
+// (ballot, popcount, one atomic per wave, mbcnt for the lane's slot).
+//
+// Global phase: pull-form sweeps over the in-edge lists.  With rmax = 0 every
+// node pushes (Simultaneous Forward Push, Eq. 7): r'(u) = sum_{v in N_in(u)}
+// y(v) with y(v) = (1-alpha) r(v) / d_v, and pi(u) += alpha r(u).  A sweep can
+// fold the alpha-part of the *next* push into pi right away (pi(u) +=
+// alpha r'(u)), so consecutive sweeps need not store r at all: a run of K
+// sweeps is ENTRY|FOLD, FOLD x (K-2), WRITE_R, and adds exactly
+// sum_{k<K} alpha r^(k) to pi.
+#include "ppr_internal.h"
+
+namespace ppr {
+namespace k {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kPartsFixed = 1024;   // fixed grid of the n-wide reductions (deterministic)
+
+__device__ inline double wave_sum(double v) {
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Deterministic block sum: wave sums, then wave 0 adds the wave results in order.
+__device__ inline double block_sum(double v, double* sh) {
+    v = wave_sum(v);
+    int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    double t = 0.0;
+    if (threadIdx.x == 0) {
+        int nw = blockDim.x >> 6;
+        for (int i = 0; i < nw; ++i) t += sh[i];
+    }
+    __syncthreads();
+    return t;   // valid in thread 0
+}
+
+__global__ void init_kernel(double* __restrict__ r, double* __restrict__ pi, int32_t n, int32_t s,
+                            int32_t* __restrict__ F) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        r[i] = (i == s) ? 1.0 : 0.0;
+        pi[i] = 0.0;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) F[0] = s;
+}
+
+__global__ void snapshot_kernel(const int32_t* __restrict__ F, int32_t nf, const int32_t* __restrict__ deg,
+                                double alpha, double* __restrict__ r, double* __restrict__ pi,
+                                double* __restrict__ X, int64_t* __restrict__ degF,
+                                double* __restrict__ partials) {
+    __shared__ double sh[kBlock / 64];
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    double taken = 0.0;
+    if (i < nf) {
+        int32_t v = F[i];
+        // exchange rather than read-then-zero: a node listed twice would push once
+        double x = atomicExch(&r[v], 0.0);
+        pi[v] += alpha * x;
+        taken = alpha * x;
+        int32_t d = deg[v];
+        X[i] = ((1.0 - alpha) * x) / (double)d;
+        degF[i] = d;
+    }
+    double t = block_sum(taken, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// First index i in [0, len) with a[i] > key, minus one (a ascending, a[0] = 0 <= key).
+__device__ inline int32_t find_owner(const int64_t* __restrict__ a, int32_t len, int64_t key) {
+    int32_t lo = 0, hi = len;   // invariant: a[lo] <= key < a[hi] (a[len] = total > key)
+    while (hi - lo > 1) {
+        int32_t mid = lo + ((hi - lo) >> 1);
+        if (a[mid] <= key) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kBlock) void push_kernel(
+        const int32_t* __restrict__ F, const int64_t* __restrict__ off, int32_t nf, int64_t vol,
+        const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
+        const int32_t* __restrict__ deg, const double* __restrict__ X, double rmax,
+        double* __restrict__ r, int32_t* __restrict__ F_next, unsigned long long* __restrict__ ctr) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave_base0 = ((int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63));
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (off[nf] < vol) vol = off[nf];   // never address past the frontier's last out-edge
+    for (int64_t wb = wave_base0; wb < vol; wb += stride) {     // uniform per wave
+        int64_t t = wb + lane;
+        bool crossed = false;
+        int32_t u = 0;
+        int32_t du = 0;
+        if (t < vol) {
+            int32_t i = find_owner(off, nf, t);
+            int32_t v = F[i];
+            int64_t e = row_ptr[v] + (t - off[i]);
+            u = col[e];
+            double x = X[i];
+            double old = atomicAdd(&r[u], x);
+            double now = old + x;
+            du = deg[u];
+            double thr = (double)du * rmax;
+            crossed = (old <= thr) && (now > thr);
+        }
+        uint64_t mask = __ballot(crossed);
+        if (mask) {
+            int cnt = __popcll(mask);
+            int leader = __ffsll((unsigned long long)mask) - 1;
+            // sum of out-degrees of the appended nodes (volume of S^(j+1))
+            int64_t myvol = crossed ? du : 0;
+            for (int o = 32; o >= 1; o >>= 1) myvol += __shfl_xor(myvol, o, 64);
+            unsigned long long base = 0;
+            if (lane == leader) {
+                base = atomicAdd(&ctr[0], (unsigned long long)cnt);
+                atomicAdd(&ctr[1], (unsigned long long)myvol);
+            }
+            base = __shfl(base, leader, 64);
+            unsigned int below = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+            if (crossed) F_next[base + below] = u;
+        }
+    }
+}
+
+__global__ void prep_kernel(const double* __restrict__ r, const int32_t* __restrict__ deg, double alpha,
+                            int32_t n, double* __restrict__ y, double* __restrict__ partials) {
+    __shared__ double sh[kBlock / 64];
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double x = r[i];
+        s += x;
+        y[i] = ((1.0 - alpha) * x) / (double)deg[i];
+    }
+    double t = block_sum(s, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+__global__ void reduce_kernel(const double* __restrict__ partials, int nparts, double* __restrict__ out) {
+    __shared__ double sh[1024 / 64];
+    double s = 0.0;
+    for (int i = threadIdx.x; i < nparts; i += blockDim.x) s += partials[i];
+    double t = block_sum(s, sh);
+    if (threadIdx.x == 0) out[0] = t;
+}
+
+// ---- pull sweep (FP64, one query)
+// Block b of the schedule covers rows [r0, r1).  Leading blocks (b < n_long)
+// hold one long row each: all threads stride its in-edges and a fixed-order
+// tree adds the partial sums.  Other blocks stage the gathered y values of
+// all their in-edges in LDS (the row_idx reads are coalesced), then T
+// threads per row add the row's slice (T = the largest power of two with
+// T * rows <= 256, at most 64, so a row's threads sit in one wave).
+constexpr int kNnzCap = 2048;
+constexpr int kRowCap = 256;
+
+template <typename OffT, int FLAGS>
+__global__ __launch_bounds__(kBlock) void sweep_kernel(
+        const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
+        const int32_t* __restrict__ deg, const RowBlock* __restrict__ blocks, int32_t n_long,
+        const double* __restrict__ y_in, double* __restrict__ y_out, double* __restrict__ pi,
+        const double* r_in, double* r_out, double alpha,   // r_in and r_out may alias
+        double* __restrict__ partials) {
+    __shared__ double lds[kNnzCap];
+    __shared__ double sh[kBlock / 64];
+    const RowBlock b = blocks[blockIdx.x];
+    const double oma = 1.0 - alpha;
+    double contrib = 0.0;
+    int32_t u = -1;
+    double acc = 0.0;
+    if ((int32_t)blockIdx.x < n_long) {
+        u = b.r0;
+        int64_t e0 = (int64_t)col_ptr[u], e1 = (int64_t)col_ptr[u + 1];
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += kBlock) acc += y_in[row_idx[e]];
+        acc = block_sum(acc, sh);
+        if (threadIdx.x != 0) u = -1;
+    } else {
+        const int32_t r0 = b.r0, r1 = b.r1;
+        const int64_t e0 = (int64_t)col_ptr[r0];
+        const int32_t ne = (int32_t)((int64_t)col_ptr[r1] - e0);
+        for (int32_t i = threadIdx.x; i < ne; i += kBlock) lds[i] = y_in[row_idx[e0 + i]];
+        __syncthreads();
+        const int32_t R = r1 - r0;
+        int T = 64;
+        while (T * R > kBlock) T >>= 1;
+        const int32_t row = threadIdx.x / T;
+        const int32_t sub = threadIdx.x % T;
+        if (row < R) {
+            const int32_t uu = r0 + row;
+            const int32_t s0 = (int32_t)((int64_t)col_ptr[uu] - e0);
+            const int32_t s1 = (int32_t)((int64_t)col_ptr[uu + 1] - e0);
+            for (int32_t i = s0 + sub; i < s1; i += T) acc += lds[i];
+            if (sub == 0) u = uu;
+        }
+        for (int o = T >> 1; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    }
+    if (u >= 0) {
+        if (FLAGS & SW_ENTRY) pi[u] += alpha * r_in[u];
+        if (FLAGS & SW_FOLD) pi[u] += alpha * acc;
+        if (FLAGS & SW_WRITE_R) r_out[u] = acc;
+        y_out[u] = (oma * acc) / (double)deg[u];
+        contrib = acc;
+    }
+    double t = block_sum(contrib, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+
+// ---- residual certificate (FP64): q(v) = pi(v) / d_v gathered over in-edges,
+// rt(u) = e_s(u) - (pi(u) - (1-alpha) sum_{v in N_in(u)} q(v)) / alpha, and
+// per-block sums of |rt|.  Same block structure as the sweep.
+__global__ void q_kernel(const double* __restrict__ pi, const int32_t* __restrict__ deg, int32_t n,
+                         double* __restrict__ q) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        q[i] = pi[i] / (double)deg[i];
+}
+
+template <typename OffT>
+__global__ __launch_bounds__(kBlock) void cert_kernel(
+        const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
+        const RowBlock* __restrict__ blocks, int32_t n_long, const double* __restrict__ q,
+        const double* __restrict__ pi, int32_t src, double alpha, double* __restrict__ rt_out,
+        double* __restrict__ partials) {
+    __shared__ double lds[kNnzCap];
+    __shared__ double sh[kBlock / 64];
+    const RowBlock b = blocks[blockIdx.x];
+    int32_t u = -1;
+    double acc = 0.0;
+    if ((int32_t)blockIdx.x < n_long) {
+        u = b.r0;
+        int64_t e0 = (int64_t)col_ptr[u], e1 = (int64_t)col_ptr[u + 1];
+        for (int64_t e = e0 + threadIdx.x; e < e1; e += kBlock) acc += q[row_idx[e]];
+        acc = block_sum(acc, sh);
+        if (threadIdx.x != 0) u = -1;
+    } else {
+        const int32_t r0 = b.r0, r1 = b.r1;
+        const int64_t e0 = (int64_t)col_ptr[r0];
+        const int32_t ne = (int32_t)((int64_t)col_ptr[r1] - e0);
+        for (int32_t i = threadIdx.x; i < ne; i += kBlock) lds[i] = q[row_idx[e0 + i]];
+        __syncthreads();
+        const int32_t R = r1 - r0;
+        int T = 64;
+        while (T * R > kBlock) T >>= 1;
+        const int32_t row = threadIdx.x / T;
+        const int32_t sub = threadIdx.x % T;
+        if (row < R) {
+            const int32_t uu = r0 + row;
+            const int32_t s0 = (int32_t)((int64_t)col_ptr[uu] - e0);
+            const int32_t s1 = (int32_t)((int64_t)col_ptr[uu + 1] - e0);
+            for (int32_t i = s0 + sub; i < s1; i += T) acc += lds[i];
+            if (sub == 0) u = uu;
+        }
+        for (int o = T >> 1; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    }
+    double contrib = 0.0;
+    if (u >= 0) {
+        double rt = (u == src ? 1.0 : 0.0) - (pi[u] - (1.0 - alpha) * acc) / alpha;
+        if (rt_out) rt_out[u] = rt;
+        contrib = fabs(rt);
+    }
+    double t = block_sum(contrib, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+template <typename OffT>
+void launch_sweep(const Graph& g, const Schedule& sch, int flags, double alpha, const double* y_in,
+                  double* y_out, double* pi, const double* r_in, double* r_out, double* partials,
+                  hipStream_t s) {
+    const OffT* cp = g.col_ptr.as<const OffT>();
+    const RowBlock* bl = sch.blocks.as<const RowBlock>();
+    dim3 grid((unsigned)sch.n_blocks), blk(kBlock);
+#define PPR_SWEEP_CASE(F)                                                                        \
+    case F:                                                                                      \
+        hipLaunchKernelGGL((sweep_kernel<OffT, F>), grid, blk, 0, s, cp, g.row_idx.as<int32_t>(), \
+                           g.deg.as<int32_t>(), bl, sch.n_long, y_in, y_out, pi, r_in, r_out,     \
+                           alpha, partials);                                                     \
+        break;
+    switch (flags) {
+        PPR_SWEEP_CASE(0)
+        PPR_SWEEP_CASE(SW_FOLD)
+        PPR_SWEEP_CASE(SW_ENTRY | SW_FOLD)
+        PPR_SWEEP_CASE(SW_WRITE_R)
+        PPR_SWEEP_CASE(SW_ENTRY | SW_WRITE_R)
+        default:
+            fail(PPR_ERR_ARG, "unsupported sweep flags");
+    }
+#undef PPR_SWEEP_CASE
+    HIPCHECK(hipGetLastError());
+}
+
+inline unsigned grid_for(int64_t items) {
+    int64_t g = (items + kBlock - 1) / kBlock;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+int32_t sweep_nnz_cap() { return kNnzCap; }
+int32_t sweep_row_cap() { return kRowCap; }
+
+void query_init(double* r, double* pi, int32_t n, int32_t s_node, int32_t* F, hipStream_t st) {
+    unsigned g = grid_for(n);
+    if (g > 4096) g = 4096;
+    hipLaunchKernelGGL(init_kernel, dim3(g), dim3(kBlock), 0, st, r, pi, n, s_node, F);
+    HIPCHECK(hipGetLastError());
+}
+
+void frontier_snapshot(const int32_t* F, int32_t nf, const int32_t* deg, double alpha, double* r,
+                       double* pi, double* X, int64_t* degF, double* partials, int* nparts,
+                       hipStream_t s) {
+    unsigned g = grid_for(nf);
+    hipLaunchKernelGGL(snapshot_kernel, dim3(g), dim3(kBlock), 0, s, F, nf, deg, alpha, r, pi, X, degF,
+                       partials);
+    HIPCHECK(hipGetLastError());
+    *nparts = (int)g;
+}
+
+void frontier_push(const int32_t* F, const int64_t* off, int32_t nf, int64_t vol,
+                   const int64_t* row_ptr, const int32_t* col, const int32_t* deg, const double* X,
+                   double rmax, double* r, int32_t* F_next, int64_t* ctr, hipStream_t s) {
+    if (vol <= 0) return;
+    unsigned g = grid_for(vol);
+    if (g > 16384) g = 16384;
+    hipLaunchKernelGGL(push_kernel, dim3(g), dim3(kBlock), 0, s, F, off, nf, vol, row_ptr, col, deg, X,
+                       rmax, r, F_next, reinterpret_cast<unsigned long long*>(ctr));
+    HIPCHECK(hipGetLastError());
+}
+
+void prep_y(const double* r, const int32_t* deg, double alpha, int32_t n, double* y, double* partials,
+            int* nparts, hipStream_t s) {
+    hipLaunchKernelGGL(prep_kernel, dim3(kPartsFixed), dim3(kBlock), 0, s, r, deg, alpha, n, y, partials);
+    HIPCHECK(hipGetLastError());
+    *nparts = kPartsFixed;
+}
+
+void reduce_sum(const double* partials, int nparts, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_kernel, dim3(1), dim3(1024), 0, s, partials, nparts, out);
+    HIPCHECK(hipGetLastError());
+}
+
+void sweep_f64(const Graph& g, const Schedule& sch, int flags, double alpha, const double* y_in,
+               double* y_out, double* pi, const double* r_in, double* r_out, double* partials,
+               hipStream_t s) {
+    if (g.off64)
+        launch_sweep<int64_t>(g, sch, flags, alpha, y_in, y_out, pi, r_in, r_out, partials, s);
+    else
+        launch_sweep<uint32_t>(g, sch, flags, alpha, y_in, y_out, pi, r_in, r_out, partials, s);
+}
+
+int sweep_parts(const Schedule& sch) { return sch.n_blocks; }
+
+void cert_f64(const Graph& g, const Schedule& sch, double alpha, int32_t src, const double* pi,
+              double* q, double* rt_out, double* partials, hipStream_t s) {
+    unsigned gq = grid_for(g.n);
+    if (gq > 4096) gq = 4096;
+    hipLaunchKernelGGL(q_kernel, dim3(gq), dim3(kBlock), 0, s, pi, g.deg.as<int32_t>(), g.n, q);
+    dim3 grid((unsigned)sch.n_blocks), blk(kBlock);
+    if (g.off64)
+        hipLaunchKernelGGL((cert_kernel<int64_t>), grid, blk, 0, s, g.col_ptr.as<int64_t>(),
+                           g.row_idx.as<int32_t>(), sch.blocks.as<RowBlock>(), sch.n_long, q, pi, src,
+                           alpha, rt_out, partials);
+    else
+        hipLaunchKernelGGL((cert_kernel<uint32_t>), grid, blk, 0, s, g.col_ptr.as<uint32_t>(),
+                           g.row_idx.as<int32_t>(), sch.blocks.as<RowBlock>(), sch.n_long, q, pi, src,
+                           alpha, rt_out, partials);
+    HIPCHECK(hipGetLastError());
+}
+
+}  // namespace k
+}  // namespace ppr

@@ -1,0 +1,230 @@
+// Host side of graph creation: CSR validation, device upload, CSC build,
+// sweep schedules, and the common helpers (errors, buffers).
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <thread>
+
+#include "ppr_internal.h"
+
+namespace ppr {
+
+// ---------------------------------------------------------------- errors
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+const char* last_error_cstr() { return g_last_error.c_str(); }
+
+[[noreturn]] void fail(ppr_status st, const std::string& msg) { throw Failure{st, msg}; }
+
+void check_hip(hipError_t e, const char* what, const char* file, int line) {
+    if (e == hipSuccess) return;
+    char buf[512];
+    snprintf(buf, sizeof buf, "%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+    fail(e == hipErrorOutOfMemory ? PPR_ERR_OOM : PPR_ERR_DEVICE, buf);
+}
+
+// ---------------------------------------------------------------- buffers
+void DevBuf::alloc(size_t b) {
+    release();
+    if (b == 0) b = 8;
+    hipError_t e = hipMalloc(&p, b);
+    if (e != hipSuccess) {
+        p = nullptr;
+        (void)hipGetLastError();
+        char buf[160];
+        snprintf(buf, sizeof buf, "hipMalloc of %zu bytes failed: %s", b, hipGetErrorString(e));
+        fail(PPR_ERR_OOM, buf);
+    }
+    bytes = b;
+}
+
+void DevBuf::release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+void PinnedBuf::alloc(size_t b) {
+    release();
+    hipError_t e = hipHostMalloc(&p, b, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        p = nullptr;
+        (void)hipGetLastError();
+        fail(PPR_ERR_OOM, "hipHostMalloc failed");
+    }
+    bytes = b;
+}
+
+void PinnedBuf::release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+}
+
+// ---------------------------------------------------------------- validation
+// O(n + m) checks of the CSR, split over host threads by row range.  The
+// failure reported is the one at the smallest node id.
+void graph_validate(const int64_t* row_ptr, const int32_t* col, int32_t n, int64_t m) {
+    if (row_ptr[0] != 0) fail(PPR_ERR_CSR, "row_ptr[0] must be 0");
+    if (row_ptr[n] != m) fail(PPR_ERR_CSR, "row_ptr[n] must equal m");
+    for (int32_t v = 0; v < n; ++v)
+        if (row_ptr[v + 1] < row_ptr[v])
+            fail(PPR_ERR_CSR, "row_ptr is not monotone at node " + std::to_string(v));
+    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    if (n < 65536) nt = 1;
+    struct Found { ppr_status st = PPR_OK; int32_t at = -1; };
+    std::vector<Found> found(nt);
+    auto work = [&](unsigned t, int32_t a, int32_t b) {
+        std::vector<int32_t> tmp;
+        for (int32_t v = a; v < b; ++v) {
+            int64_t e0 = row_ptr[v], e1 = row_ptr[v + 1];
+            if (e1 == e0) { found[t] = {PPR_ERR_DANGLING, v}; return; }
+            bool sorted = true;
+            for (int64_t e = e0; e < e1; ++e) {
+                int32_t u = col[e];
+                if (u < 0 || u >= n) { found[t] = {PPR_ERR_CSR, v}; return; }
+                if (e > e0 && col[e - 1] >= u) sorted = false;
+            }
+            if (!sorted) {
+                tmp.assign(col + e0, col + e1);
+                std::sort(tmp.begin(), tmp.end());
+                if (std::adjacent_find(tmp.begin(), tmp.end()) != tmp.end()) {
+                    found[t] = {PPR_ERR_DUPLICATE, v};
+                    return;
+                }
+            }
+        }
+    };
+    std::vector<std::thread> th;
+    int32_t chunk = (int32_t)((n + (int64_t)nt - 1) / nt);
+    for (unsigned t = 0; t < nt; ++t) {
+        int32_t a = (int32_t)std::min<int64_t>((int64_t)t * chunk, n);
+        int32_t b = (int32_t)std::min<int64_t>((int64_t)a + chunk, n);
+        if (a < b) th.emplace_back(work, t, a, b);
+    }
+    for (auto& x : th) x.join();
+    for (const Found& f : found) {      // threads cover ascending row ranges
+        if (f.st == PPR_OK) continue;
+        std::string at = std::to_string(f.at);
+        if (f.st == PPR_ERR_CSR) fail(PPR_ERR_CSR, "column index out of range in the out-list of node " + at);
+        if (f.st == PPR_ERR_DANGLING) fail(PPR_ERR_DANGLING, "node " + at + " has out-degree 0 (dead end)");
+        fail(PPR_ERR_DUPLICATE, "duplicate edge in the out-list of node " + at);
+    }
+}
+
+// ---------------------------------------------------------------- graph
+size_t Graph::device_bytes() const {
+    size_t b = row_ptr.bytes + col.bytes + col_ptr.bytes + row_idx.bytes + deg.bytes;
+    return b;
+}
+
+const Schedule& Graph::schedule(int32_t nnz_cap, int32_t row_cap) {
+    std::lock_guard<std::mutex> lk(sched_mu);
+    for (auto& s : schedules)
+        if (s->nnz_cap == nnz_cap && s->row_cap == row_cap) return *s;
+    // contiguous row ranges with at most nnz_cap in-edges and row_cap rows; a
+    // row with more in-edges than nnz_cap gets a block of its own, listed first
+    std::vector<RowBlock> longb, normal;
+    const int64_t* cp = h_col_ptr.data();
+    int32_t r = 0;
+    while (r < n) {
+        int64_t d = cp[r + 1] - cp[r];
+        if (d > nnz_cap) { longb.push_back({r, r + 1}); ++r; continue; }
+        int32_t r0 = r;
+        int64_t e = 0;
+        while (r < n && r - r0 < row_cap) {
+            int64_t dd = cp[r + 1] - cp[r];
+            if (dd > nnz_cap || e + dd > nnz_cap) break;
+            e += dd;
+            ++r;
+        }
+        normal.push_back({r0, r});
+    }
+    auto s = std::make_unique<Schedule>();
+    s->nnz_cap = nnz_cap;
+    s->row_cap = row_cap;
+    s->n_long = (int32_t)longb.size();
+    s->n_blocks = (int32_t)(longb.size() + normal.size());
+    std::vector<RowBlock> all(longb);
+    all.insert(all.end(), normal.begin(), normal.end());
+    s->blocks.alloc(sizeof(RowBlock) * all.size());
+    HIPCHECK(hipMemcpy(s->blocks.p, all.data(), sizeof(RowBlock) * all.size(), hipMemcpyHostToDevice));
+    schedules.push_back(std::move(s));
+    return *schedules.back();
+}
+
+Graph* graph_create(const int64_t* row_ptr, const int32_t* col, int32_t n, int64_t m, uint32_t flags) {
+    auto t0 = std::chrono::steady_clock::now();
+    if (!row_ptr || !col) fail(PPR_ERR_ARG, "row_ptr and col must not be NULL");
+    if (n < 1) fail(PPR_ERR_ARG, "n must be >= 1");
+    if (m < n) fail(PPR_ERR_DANGLING, "m < n: some node has out-degree 0");
+    if (!(flags & PPR_GRAPH_TRUST_INPUT)) graph_validate(row_ptr, col, n, m);
+    else if (row_ptr[0] != 0 || row_ptr[n] != m) fail(PPR_ERR_CSR, "row_ptr[0] must be 0 and row_ptr[n] = m");
+
+    int ndev = 0;
+    hipError_t de = hipGetDeviceCount(&ndev);
+    if (de != hipSuccess || ndev < 1) {
+        (void)hipGetLastError();
+        fail(PPR_ERR_DEVICE, "no HIP device available");
+    }
+    auto g = std::make_unique<Graph>();
+    HIPCHECK(hipGetDevice(&g->device));
+    g->n = n;
+    g->m = m;
+    g->off64 = m >= (int64_t)UINT32_MAX;
+    hipStream_t s;
+    HIPCHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    struct StreamGuard { hipStream_t s; ~StreamGuard() { (void)hipStreamDestroy(s); } } sg{s};
+
+    g->row_ptr.alloc(sizeof(int64_t) * ((size_t)n + 1));
+    g->col.alloc(sizeof(int32_t) * (size_t)m);
+    HIPCHECK(hipMemcpyAsync(g->row_ptr.p, row_ptr, sizeof(int64_t) * ((size_t)n + 1), hipMemcpyHostToDevice, s));
+    HIPCHECK(hipMemcpyAsync(g->col.p, col, sizeof(int32_t) * (size_t)m, hipMemcpyHostToDevice, s));
+    g->deg.alloc(sizeof(int32_t) * (size_t)n);
+    k::deg_from_rowptr(g->row_ptr.as<int64_t>(), g->deg.as<int32_t>(), n, s);
+
+    // in-degree counts -> offsets -> scatter -> per-list sort
+    DevBuf cnt(sizeof(int64_t) * ((size_t)n + 1));
+    DevBuf cp64(sizeof(int64_t) * ((size_t)n + 1));
+    DevBuf tmp(k::scan_tmp_bytes(n));
+    HIPCHECK(hipMemsetAsync(cnt.p, 0, sizeof(int64_t) * ((size_t)n + 1), s));
+    k::count_in(g->col.as<int32_t>(), m, cnt.as<int64_t>(), s);
+    k::exclusive_scan_i64(cnt.as<int64_t>(), cp64.as<int64_t>(), n, tmp.p, s);
+    HIPCHECK(hipMemcpyAsync(cnt.p, cp64.p, sizeof(int64_t) * (size_t)n, hipMemcpyDeviceToDevice, s));
+    g->row_idx.alloc(sizeof(int32_t) * (size_t)m);
+    k::scatter_in(g->row_ptr.as<int64_t>(), g->col.as<int32_t>(), n, cp64.as<int64_t>(), cnt.as<int64_t>(),
+                  g->row_idx.as<int32_t>(), s);
+    k::sort_segments(cp64.as<int64_t>(), g->row_idx.as<int32_t>(), n, 0, s);
+    if (g->off64) {
+        g->col_ptr.alloc(sizeof(int64_t) * ((size_t)n + 1));
+        HIPCHECK(hipMemcpyAsync(g->col_ptr.p, cp64.p, sizeof(int64_t) * ((size_t)n + 1), hipMemcpyDeviceToDevice, s));
+    } else {
+        g->col_ptr.alloc(sizeof(uint32_t) * ((size_t)n + 1));
+        k::narrow_offsets(cp64.as<int64_t>(), g->col_ptr.as<uint32_t>(), (int64_t)n + 1, s);
+    }
+    g->h_col_ptr.resize((size_t)n + 1);
+    HIPCHECK(hipMemcpyAsync(g->h_col_ptr.data(), cp64.p, sizeof(int64_t) * ((size_t)n + 1), hipMemcpyDeviceToHost, s));
+    g->h_deg.resize((size_t)n);
+    for (int32_t v = 0; v < n; ++v) g->h_deg[v] = (int32_t)(row_ptr[v + 1] - row_ptr[v]);
+    HIPCHECK(hipStreamSynchronize(s));
+    if (g->h_col_ptr[n] != m) fail(PPR_ERR_DEVICE, "CSC build produced a wrong edge count");
+    int32_t mi = 0, mo = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        mi = std::max<int32_t>(mi, (int32_t)(g->h_col_ptr[v + 1] - g->h_col_ptr[v]));
+        mo = std::max<int32_t>(mo, g->h_deg[v]);
+    }
+    g->max_in = mi;
+    g->max_out = mo;
+    g->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return g.release();
+}
+
+void graph_copy_csc(const Graph& g, int64_t* col_ptr, int32_t* row_idx, int32_t* deg) {
+    HIPCHECK(hipSetDevice(g.device));
+    if (col_ptr) std::memcpy(col_ptr, g.h_col_ptr.data(), sizeof(int64_t) * ((size_t)g.n + 1));
+    if (row_idx) HIPCHECK(hipMemcpy(row_idx, g.row_idx.p, sizeof(int32_t) * (size_t)g.m, hipMemcpyDeviceToHost));
+    if (deg) HIPCHECK(hipMemcpy(deg, g.deg.p, sizeof(int32_t) * (size_t)g.n, hipMemcpyDeviceToHost));
+}
+
+}  // namespace ppr

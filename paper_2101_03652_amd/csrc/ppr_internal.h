@@ -1,0 +1,172 @@
+// Internal declarations of libppr (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/ppr.h"
+
+namespace ppr {
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string& msg);
+const char* last_error_cstr();
+struct Failure {
+    ppr_status status;
+    std::string msg;
+};
+[[noreturn]] void fail(ppr_status st, const std::string& msg);
+void check_hip(hipError_t e, const char* what, const char* file, int line);
+#define HIPCHECK(x) ::ppr::check_hip((x), #x, __FILE__, __LINE__)
+
+// ---------------------------------------------------------------- device buffers
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevBuf() = default;
+    explicit DevBuf(size_t b) { alloc(b); }
+    ~DevBuf() { release(); }
+    DevBuf(const DevBuf&) = delete;
+    DevBuf& operator=(const DevBuf&) = delete;
+    void alloc(size_t b);
+    void release();
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+struct PinnedBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    PinnedBuf() = default;
+    ~PinnedBuf() { release(); }
+    PinnedBuf(const PinnedBuf&) = delete;
+    PinnedBuf& operator=(const PinnedBuf&) = delete;
+    void alloc(size_t b);
+    void release();
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// A contiguous range of destination rows processed by one workgroup of a
+// pull sweep.  Long rows (more in-edges than the block's edge budget) get a
+// block of their own and are listed first.
+struct RowBlock {
+    int32_t r0, r1;
+};
+
+// Sweep schedule for one edge budget.
+struct Schedule {
+    int32_t nnz_cap = 0;       // edge budget per normal block
+    int32_t row_cap = 0;       // row budget per normal block
+    int32_t n_long = 0;        // leading blocks that hold a single long row
+    int32_t n_blocks = 0;
+    DevBuf blocks;             // RowBlock[n_blocks]
+};
+
+struct QueryCtx;
+
+// Device graph: CSR (out-edges, for the frontier push), CSC (in-edges, for
+// the pull sweeps), out-degrees, schedules.
+struct Graph {
+    int device = 0;
+    int32_t n = 0;
+    int64_t m = 0;
+    bool off64 = false;        // CSC offsets int64 (else uint32)
+    int32_t max_in = 0, max_out = 0;
+    double build_ms = 0;
+    DevBuf row_ptr;            // int64[n+1]
+    DevBuf col;                // int32[m]
+    DevBuf col_ptr;            // uint32 or int64 [n+1]
+    DevBuf row_idx;            // int32[m]
+    DevBuf deg;                // int32[n] out-degree
+    std::vector<int64_t> h_col_ptr;   // host copy of the CSC offsets (schedules)
+    std::vector<int32_t> h_deg;       // host copy of the out-degrees
+    std::mutex sched_mu;
+    std::vector<std::unique_ptr<Schedule>> schedules;
+    std::mutex pool_mu;
+    std::vector<std::unique_ptr<QueryCtx>> pool;       // idle FP64 query contexts
+    size_t device_bytes() const;
+    const Schedule& schedule(int32_t nnz_cap, int32_t row_cap);
+};
+
+Graph* graph_create(const int64_t* row_ptr, const int32_t* col, int32_t n, int64_t m,
+                    uint32_t flags);
+void graph_validate(const int64_t* row_ptr, const int32_t* col, int32_t n, int64_t m);
+void graph_copy_csc(const Graph& g, int64_t* col_ptr, int32_t* row_idx, int32_t* deg);
+
+// ---------------------------------------------------------------- FP64 query context
+struct QueryCtx {
+    hipStream_t stream = nullptr;
+    int32_t n = 0;
+    DevBuf r;          // double[n]  residue
+    DevBuf pi;         // double[n]  reserve
+    DevBuf y0, y1;     // double[n]  scaled residue (1-alpha) r / d, ping-pong
+    DevBuf F0, F1;     // int32[n]   frontier lists
+    DevBuf X;          // double[n]  per-frontier-entry push increment
+    DevBuf degF;       // int64[n]   out-degrees of the frontier entries
+    DevBuf off;        // int64[n+1] degree prefix of the frontier
+    DevBuf partials;   // double[max blocks]
+    DevBuf scan_tmp;   // scan scratch
+    DevBuf ctr;        // int64[8] counters: [0] |F'|, [1] vol(F'), [2..] spare
+    DevBuf dsum;       // double[8]: [0] reduced sum
+    PinnedBuf host;    // 64 bytes readback
+    hipGraphExec_t chunk_exec = nullptr;   // captured FOLD sweep pairs
+    int chunk_pairs = 0;
+    double chunk_alpha = -1;
+    ~QueryCtx();
+};
+
+std::unique_ptr<QueryCtx> ctx_acquire(Graph& g);
+void ctx_release(Graph& g, std::unique_ptr<QueryCtx> c);
+
+// ---------------------------------------------------------------- kernels (launchers)
+namespace k {
+void deg_from_rowptr(const int64_t* row_ptr, int32_t* deg, int32_t n, hipStream_t s);
+void count_in(const int32_t* col, int64_t m, int64_t* cnt, hipStream_t s);
+// exclusive scan of int64 counts (len entries) into out[len+1]
+size_t scan_tmp_bytes(int64_t len);
+void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t len, void* tmp, hipStream_t s);
+void scatter_in(const int64_t* row_ptr, const int32_t* col, int32_t n, const int64_t* col_ptr,
+                int64_t* fill, int32_t* row_idx, hipStream_t s);
+void sort_segments(const int64_t* col_ptr, int32_t* row_idx, int32_t n, int32_t max_len,
+                   hipStream_t s);
+void narrow_offsets(const int64_t* in, uint32_t* out, int64_t len, hipStream_t s);
+
+// local phase (FP64, one query)
+void query_init(double* r, double* pi, int32_t n, int32_t s_node, int32_t* F, hipStream_t st);
+void frontier_snapshot(const int32_t* F, int32_t nf, const int32_t* deg, double alpha, double* r,
+                       double* pi, double* X, int64_t* degs_of_F, double* partials, int* nparts,
+                       hipStream_t s);
+void frontier_push(const int32_t* F, const int64_t* off, int32_t nf, int64_t vol,
+                   const int64_t* row_ptr, const int32_t* col, const int32_t* deg, const double* X,
+                   double rmax, double* r, int32_t* F_next, int64_t* ctr, hipStream_t s);
+// y = (1-alpha) r / d for all nodes, with per-block partial sums of r
+void prep_y(const double* r, const int32_t* deg, double alpha, int32_t n, double* y,
+            double* partials, int* nparts, hipStream_t s);
+void reduce_sum(const double* partials, int nparts, double* out, hipStream_t s);
+
+// FP64 pull sweep: flags
+enum : int { SW_ENTRY = 1, SW_FOLD = 2, SW_WRITE_R = 4 };
+void sweep_f64(const Graph& g, const Schedule& sch, int flags, double alpha, const double* y_in,
+               double* y_out, double* pi, const double* r_in, double* r_out, double* partials,
+               hipStream_t s);
+int sweep_parts(const Schedule& sch);
+int32_t sweep_nnz_cap();
+int32_t sweep_row_cap();
+// certificate pass: q(v) = pi(v) / d_v, then rt(u) = e_s(u) - (pi(u) - (1-alpha) sum q) / alpha;
+// partials receive sum |rt| per block; rt_out (nullable) receives rt
+void cert_f64(const Graph& g, const Schedule& sch, double alpha, int32_t src, const double* pi,
+              double* q, double* rt_out, double* partials, hipStream_t s);
+}  // namespace k
+
+// ---------------------------------------------------------------- runtime
+void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_options& opt,
+                    double* pi_out, double* r_out, ppr_stats* st);
+void run_mixed_batch(Graph& g, const int32_t* sources, int32_t B, double alpha, double lambda,
+                     const ppr_options& opt, double* pi_out, double* r_out, ppr_stats* st);
+
+}  // namespace ppr

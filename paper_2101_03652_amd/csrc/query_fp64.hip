@@ -1,0 +1,232 @@
+// The plain FP64 single-query path: local phase over frontiers, then global
+// pull sweeps, with the sweep loop replayed from a captured HIP graph.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "ppr_internal.h"
+
+namespace ppr {
+
+QueryCtx::~QueryCtx() {
+    if (chunk_exec) (void)hipGraphExecDestroy(chunk_exec);
+    if (stream) (void)hipStreamDestroy(stream);
+}
+
+std::unique_ptr<QueryCtx> ctx_acquire(Graph& g) {
+    {
+        std::lock_guard<std::mutex> lk(g.pool_mu);
+        if (!g.pool.empty()) {
+            auto c = std::move(g.pool.back());
+            g.pool.pop_back();
+            return c;
+        }
+    }
+    auto c = std::make_unique<QueryCtx>();
+    const size_t n = (size_t)g.n;
+    c->n = g.n;
+    HIPCHECK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    c->r.alloc(8 * n);
+    c->pi.alloc(8 * n);
+    c->y0.alloc(8 * n);
+    c->y1.alloc(8 * n);
+    c->F0.alloc(4 * n);
+    c->F1.alloc(4 * n);
+    c->X.alloc(8 * n);
+    c->degF.alloc(8 * n);
+    c->off.alloc(8 * (n + 1));
+    const Schedule& sch = g.schedule(k::sweep_nnz_cap(), k::sweep_row_cap());
+    size_t parts = std::max<size_t>({(size_t)sch.n_blocks, 4096, (n + 255) / 256});
+    c->partials.alloc(8 * parts);
+    c->scan_tmp.alloc(k::scan_tmp_bytes(g.n));
+    c->ctr.alloc(64);
+    c->dsum.alloc(64);
+    c->host.alloc(64);
+    return c;
+}
+
+void ctx_release(Graph& g, std::unique_ptr<QueryCtx> c) {
+    std::lock_guard<std::mutex> lk(g.pool_mu);
+    g.pool.push_back(std::move(c));
+}
+
+namespace {
+
+struct CtxLease {
+    Graph& g;
+    std::unique_ptr<QueryCtx> c;
+    explicit CtxLease(Graph& gg) : g(gg), c(ctx_acquire(gg)) {}
+    ~CtxLease() {
+        if (c) {
+            (void)hipStreamSynchronize(c->stream);
+            ctx_release(g, std::move(c));
+        }
+    }
+};
+
+constexpr int kChunkPairs = 8;   // a captured chunk is 16 FOLD sweeps
+
+// Capture [FOLD y1 -> y0, FOLD y0 -> y1] x kChunkPairs on the context's stream.
+void ensure_chunk(Graph& g, QueryCtx& c, const Schedule& sch, double alpha) {
+    if (c.chunk_exec && c.chunk_alpha == alpha) return;
+    if (c.chunk_exec) {
+        (void)hipGraphExecDestroy(c.chunk_exec);
+        c.chunk_exec = nullptr;
+    }
+    hipGraph_t graph = nullptr;
+    HIPCHECK(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
+    try {
+        for (int p = 0; p < kChunkPairs; ++p) {
+            k::sweep_f64(g, sch, k::SW_FOLD, alpha, c.y1.as<double>(), c.y0.as<double>(), c.pi.as<double>(),
+                         nullptr, nullptr, c.partials.as<double>(), c.stream);
+            k::sweep_f64(g, sch, k::SW_FOLD, alpha, c.y0.as<double>(), c.y1.as<double>(), c.pi.as<double>(),
+                         nullptr, nullptr, c.partials.as<double>(), c.stream);
+        }
+    } catch (...) {
+        (void)hipStreamEndCapture(c.stream, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+    }
+    HIPCHECK(hipStreamEndCapture(c.stream, &graph));
+    hipError_t e = hipGraphInstantiate(&c.chunk_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    HIPCHECK(e);
+    c.chunk_pairs = kChunkPairs;
+    c.chunk_alpha = alpha;
+}
+
+bool continue_local(const ppr_options& opt, int64_t nf, int64_t vol, int32_t n, int64_t m) {
+    if (opt.switch_rule == PPR_SWITCH_NODES) return 4 * nf <= (int64_t)n;
+    return opt.switch_param * (double)vol <= (double)m;
+}
+
+}  // namespace
+
+void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_options& opt,
+                    double* pi_out, double* r_out, ppr_stats* st) {
+    auto t0 = std::chrono::steady_clock::now();
+    HIPCHECK(hipSetDevice(g.device));
+    CtxLease lease(g);
+    QueryCtx& c = *lease.c;
+    hipStream_t ss = c.stream;
+    const Schedule& sch = g.schedule(k::sweep_nnz_cap(), k::sweep_row_cap());
+    double* r = c.r.as<double>();
+    double* pi = c.pi.as<double>();
+    double* partials = c.partials.as<double>();
+    int64_t* hctr = c.host.as<int64_t>();
+    double* hd = c.host.as<double>();
+    const int32_t* deg = g.deg.as<int32_t>();
+
+    // ---- local phase: iterations S^(j) pushed simultaneously
+    k::query_init(r, pi, g.n, s, c.F0.as<int32_t>(), ss);
+    int32_t* F = c.F0.as<int32_t>();
+    int32_t* Fn = c.F1.as<int32_t>();
+    int64_t nf = 1, vol = g.h_deg[s];
+    double r_sum = 1.0;
+    const double rmax = lambda / (double)g.m;
+    int32_t levels = 0;
+    int64_t edge_pushes = 0;
+    while (nf > 0 && r_sum > lambda && continue_local(opt, nf, vol, g.n, g.m)) {
+        int np = 0;
+        k::frontier_snapshot(F, (int32_t)nf, deg, alpha, r, pi, c.X.as<double>(), c.degF.as<int64_t>(),
+                             partials, &np, ss);
+        k::reduce_sum(partials, np, c.dsum.as<double>(), ss);
+        k::exclusive_scan_i64(c.degF.as<int64_t>(), c.off.as<int64_t>(), nf, c.scan_tmp.p, ss);
+        HIPCHECK(hipMemsetAsync(c.ctr.p, 0, 16, ss));
+        k::frontier_push(F, c.off.as<int64_t>(), (int32_t)nf, vol, g.row_ptr.as<int64_t>(), g.col.as<int32_t>(),
+                         deg, c.X.as<double>(), rmax, r, Fn, c.ctr.as<int64_t>(), ss);
+        HIPCHECK(hipMemcpyAsync(hctr, c.ctr.p, 16, hipMemcpyDeviceToHost, ss));
+        HIPCHECK(hipMemcpyAsync(hd + 2, c.dsum.p, 8, hipMemcpyDeviceToHost, ss));
+        HIPCHECK(hipStreamSynchronize(ss));
+        edge_pushes += vol;
+        r_sum -= hd[2];
+        nf = hctr[0];
+        vol = hctr[1];
+        std::swap(F, Fn);
+        ++levels;
+    }
+
+    // ---- exact r_sum, and y = (1-alpha) r / d for the first sweep
+    {
+        int np = 0;
+        k::prep_y(r, deg, alpha, g.n, c.y0.as<double>(), partials, &np, ss);
+        k::reduce_sum(partials, np, c.dsum.as<double>(), ss);
+        HIPCHECK(hipMemcpyAsync(hd, c.dsum.p, 8, hipMemcpyDeviceToHost, ss));
+        HIPCHECK(hipStreamSynchronize(ss));
+        r_sum = hd[0];
+    }
+
+    // ---- global phase: threshold-0 sweeps contract r_sum by exactly (1 - alpha)
+    int32_t sweeps = 0;
+    if (r_sum > lambda) {
+        int32_t K = 0;
+        for (double x = r_sum; x > lambda && K < opt.max_sweeps; x *= (1.0 - alpha)) ++K;
+        double* y0 = c.y0.as<double>();
+        double* y1 = c.y1.as<double>();
+        auto sweep = [&](int flags, const double* yi, double* yo) {
+            k::sweep_f64(g, sch, flags, alpha, yi, yo, pi, r, r, partials, ss);
+        };
+        const double* yc = y0;   // buffer holding the current y
+        double* yn = y1;
+        auto advance = [&](int flags) {
+            sweep(flags, yc, yn);
+            double* t = const_cast<double*>(yc);
+            yc = yn;
+            yn = t;
+        };
+        if (K == 1) {
+            advance(k::SW_ENTRY | k::SW_WRITE_R);
+        } else {
+            advance(k::SW_ENTRY | k::SW_FOLD);            // now yc == y1
+            int32_t mid = K - 2;
+            int32_t chunks = mid / (2 * kChunkPairs);
+            if (chunks > 0) {                              // an even number of sweeps: yc stays y1
+                ensure_chunk(g, c, sch, alpha);
+                for (int32_t i = 0; i < chunks; ++i) HIPCHECK(hipGraphLaunch(c.chunk_exec, ss));
+            }
+            for (int32_t i = chunks * 2 * kChunkPairs; i < mid; ++i) advance(k::SW_FOLD);
+            advance(k::SW_WRITE_R);
+        }
+        sweeps = K;
+        k::reduce_sum(partials, k::sweep_parts(sch), c.dsum.as<double>(), ss);
+        HIPCHECK(hipMemcpyAsync(hd, c.dsum.p, 8, hipMemcpyDeviceToHost, ss));
+        HIPCHECK(hipStreamSynchronize(ss));
+        r_sum = hd[0];
+        // rounding can leave r_sum a hair above lambda: one more plain sweep each time
+        while (r_sum > lambda && sweeps < opt.max_sweeps) {
+            advance(k::SW_ENTRY | k::SW_WRITE_R);
+            ++sweeps;
+            k::reduce_sum(partials, k::sweep_parts(sch), c.dsum.as<double>(), ss);
+            HIPCHECK(hipMemcpyAsync(hd, c.dsum.p, 8, hipMemcpyDeviceToHost, ss));
+            HIPCHECK(hipStreamSynchronize(ss));
+            r_sum = hd[0];
+        }
+    }
+    edge_pushes += (int64_t)sweeps * g.m;
+
+    // ---- optional certificate
+    double cert = -1.0;
+    if (opt.certify) {
+        k::cert_f64(g, sch, alpha, s, pi, c.y0.as<double>(), nullptr, partials, ss);
+        k::reduce_sum(partials, k::sweep_parts(sch), c.dsum.as<double>(), ss);
+        HIPCHECK(hipMemcpyAsync(hd + 4, c.dsum.p, 8, hipMemcpyDeviceToHost, ss));
+    }
+    // ---- output
+    HIPCHECK(hipMemcpyAsync(pi_out, pi, 8 * (size_t)g.n, hipMemcpyDefault, ss));
+    if (r_out) HIPCHECK(hipMemcpyAsync(r_out, r, 8 * (size_t)g.n, hipMemcpyDefault, ss));
+    HIPCHECK(hipStreamSynchronize(ss));
+    if (opt.certify) cert = hd[4];
+    if (st) {
+        st->local_levels = levels;
+        st->sweeps = sweeps;
+        st->refreshes = 0;
+        st->source = s;
+        st->edge_pushes = edge_pushes;
+        st->r_sum = r_sum;
+        st->cert_l1 = cert;
+        st->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (r_sum > lambda) fail(PPR_ERR_NOT_CONVERGED, "max_sweeps reached before r_sum <= lambda");
+}
+
+}  // namespace ppr

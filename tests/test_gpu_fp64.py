@@ -1,0 +1,225 @@
+"""GPU parity of the plain FP64 path against the FP64 oracle (through the C ABI).
+
+Tolerances.  The GPU and the oracle perform the same operations except for
+the order of additions (FP64 atomics in the local phase, pull-side tree sums
+in the sweeps, sequential push sums in the oracle).  A reordered sum of d
+terms differs by at most ~d ulps; over K <= 90 sweeps the relative difference
+of any entry stays below ~K * 64 * 1.1e-16 < 1e-12, so element-wise parity is
+asserted at rtol 1e-11 (with an absolute floor of 1e-20 for entries near 0).
+The l1 contract is the paper's: ||pi_hat - pi||_1 <= lambda against the
+converged power iteration ((1-alpha)^135 < 1e-13).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_2101_03652_amd")
+
+pytestmark = pytest.mark.gpu
+ALPHA = 0.2
+RTOL = 1e-11
+ATOL = 1e-20
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return synth.chunglu(10_000, 100_000, 2.1)
+
+
+def _hub_graph():
+    """A graph whose node 0 has in-degree 12000 (a block of its own in the
+    sweep, the large-segment path of the CSC sort) and several mid hubs."""
+    rng = np.random.default_rng(5)
+    n = 20_000
+    edges = set()
+    for v in range(1, 12_001):
+        edges.add((v, 0))
+    for h, k in ((1, 3000), (2, 700), (3, 65)):
+        for v in rng.choice(np.arange(4, n), size=k, replace=False):
+            edges.add((int(v), h))
+    for v in range(n):
+        for u in rng.integers(0, n, size=4):
+            if u != v:
+                edges.add((v, int(u)))
+    edges.add((0, 1))
+    return synth.from_edges(n, sorted(edges), "hub")
+
+
+@pytest.fixture(scope="module")
+def hub():
+    return _hub_graph()
+
+
+@pytest.mark.parametrize("which", ["fig1", "cycle", "c1", "hub"])
+def test_csc_bit_exact(which, c1, hub):
+    g = {"fig1": synth.fig1(), "cycle": synth.cycle(1000), "c1": c1, "hub": hub}[which]
+    print(f"[gpu] csc {which} n={g.n} m={g.m}", flush=True)
+    G = P.Graph.from_synth(g)
+    cp, ri, dg = G.csc()
+    ocp, ori, odg = oracle.csc(g)
+    np.testing.assert_array_equal(cp, ocp)
+    np.testing.assert_array_equal(ri, ori)
+    np.testing.assert_array_equal(dg, odg)
+    info = G.info()
+    assert info["n"] == g.n and info["m"] == g.m
+    assert info["max_in_degree"] == int(np.diff(ocp).max())
+
+
+def test_fig3_sweep_values():
+    """Figure 3: the GPU sweep reproduces r^(1) and the second iteration's pushes."""
+    g = synth.fig1()
+    G = P.Graph.from_synth(g)
+    r0 = _dev(np.array([1.0, 0, 0, 0, 0]))
+    r1 = _dev(np.zeros(5))
+    pi = _dev(np.zeros(5))
+    s1 = G.debug_sweep(ALPHA, r0, r1, pi)
+    np.testing.assert_allclose(r1.cpu().numpy(), [0, 0.4, 0.4, 0, 0], atol=1e-15)
+    assert s1 == pytest.approx(0.8, abs=1e-15)
+    r2 = _dev(np.zeros(5))
+    s2 = G.debug_sweep(ALPHA, r1, r2, pi)
+    np.testing.assert_allclose(r2.cpu().numpy(), [0.08, 0.16, 0.08, 0.24, 0.08], atol=1e-15)
+    np.testing.assert_allclose(pi.cpu().numpy(), [0.2, 0.08, 0.08, 0, 0], atol=1e-15)
+    assert s2 == pytest.approx(0.64, abs=1e-15)
+
+
+@pytest.mark.parametrize("which", ["c1", "hub"])
+def test_one_sweep_matches_eq7(which, c1, hub):
+    g = {"c1": c1, "hub": hub}[which]
+    print(f"[gpu] sweep {which}", flush=True)
+    G = P.Graph.from_synth(g)
+    rng = np.random.default_rng(3)
+    r_in = rng.random(g.n) * (rng.random(g.n) < 0.3)
+    pi0 = rng.random(g.n) * 1e-3
+    pi_o = pi0.copy()
+    r_o = oracle.sim_sweep(g, ALPHA, r_in, pi_o)
+    r_out = _dev(np.zeros(g.n))
+    pi = _dev(pi0)
+    rs = G.debug_sweep(ALPHA, _dev(r_in), r_out, pi)
+    np.testing.assert_allclose(r_out.cpu().numpy(), r_o, rtol=1e-13, atol=1e-300)
+    np.testing.assert_allclose(pi.cpu().numpy(), pi_o, rtol=1e-15, atol=0)
+    assert rs == pytest.approx(r_o.sum(), rel=1e-13)
+    # mass: sum r_out = (1 - alpha) sum r_in
+    assert rs == pytest.approx((1 - ALPHA) * r_in.sum(), rel=1e-13)
+
+
+def _sync(g, s, lam, rule, param):
+    pi, r, st, trace, levels = oracle.powerpush_sync(g, s, ALPHA, lam, rule, param, trace_cap=512)
+    return pi, r, st
+
+
+@pytest.mark.parametrize("rule,param", [(P.SWITCH_EDGES, 8.0), (P.SWITCH_NODES, 1.0)])
+@pytest.mark.parametrize("lam", [1e-6, 1e-8])
+def test_query_matches_oracle_sync_c1(c1, rule, param, lam):
+    G = P.Graph.from_synth(c1)
+    truth_cache = {}
+    for s in synth.sources(c1.n, 3):
+        s = int(s)
+        print(f"[gpu] fp64 query c1 s={s} lam={lam} rule={rule}", flush=True)
+        pi, st = G.query(s, ALPHA, lam, P.FP64, switch_rule=rule, switch_param=param, certify=1)
+        pio, ro, sto = _sync(c1, s, lam, rule, param)
+        assert st["local_levels"] == sto["local_levels"]
+        assert st["sweeps"] == sto["sweeps"]
+        assert st["edge_pushes"] == sto["edge_pushes"]
+        np.testing.assert_allclose(pi, pio, rtol=RTOL, atol=ATOL)
+        assert st["r_sum"] <= lam
+        assert st["r_sum"] == pytest.approx(sto["r_sum"], rel=1e-10)
+        if s not in truth_cache:
+            truth_cache[s] = oracle.powitr(c1, s, ALPHA, 135)
+        err = np.abs(pi - truth_cache[s]).sum()
+        assert err <= lam
+        # the GPU certificate equals the oracle's on the same vector and bounds the error
+        cert_o = oracle.certificate(c1, s, ALPHA, pi)
+        assert st["cert_l1"] == pytest.approx(cert_o, rel=1e-9, abs=1e-15)
+        assert st["cert_l1"] >= err - 2e-15
+
+
+@pytest.mark.parametrize("name", ["fig1", "cycle", "star", "complete", "loop"])
+def test_query_small_graphs_closed_forms(name):
+    a = 1 - ALPHA
+    if name == "fig1":
+        g, s = synth.fig1(), 0
+        x = np.array([0.29366106, 0.27166882, 0.23285899, 0.14747736, 0.05433376])
+        tol = 5e-8
+    elif name == "cycle":
+        g, s = synth.cycle(37), 5
+        x = np.array([ALPHA * a ** ((v - s) % 37) / (1 - a ** 37) for v in range(37)])
+        tol = None
+    elif name == "star":
+        L = 9
+        g, s = synth.star(L), 0
+        x = np.full(L + 1, ALPHA * a / ((1 - a * a) * L))
+        x[0] = ALPHA / (1 - a * a)
+        tol = None
+    elif name == "complete":
+        n = 11
+        g, s = synth.complete(n), 4
+        ps = 1.0 / n + ALPHA * (n - 1) ** 2 / (n * (n - 1 + a))
+        x = np.full(n, (1 - ps) / (n - 1))
+        x[s] = ps
+        tol = None
+    else:
+        g, s = synth.self_loop(), 0
+        x = np.array([1.0])
+        tol = None
+    G = P.Graph.from_synth(g)
+    for lam in (1e-4, 1e-10):
+        pi, st = G.query(s, ALPHA, lam, P.FP64)
+        err = np.abs(pi - x).sum()
+        assert err <= lam + (tol or 0.0) * g.n
+        pio, _, sto = _sync(g, s, lam, P.SWITCH_EDGES, 8.0)
+        np.testing.assert_allclose(pi, pio, rtol=RTOL, atol=ATOL)
+
+
+def test_hub_graph_query(hub):
+    G = P.Graph.from_synth(hub)
+    for s in (0, 1, 12345):
+        pi, st = G.query(s, ALPHA, 1e-9, P.FP64, certify=1)
+        pio, _, sto = _sync(hub, s, 1e-9, P.SWITCH_EDGES, 8.0)
+        np.testing.assert_allclose(pi, pio, rtol=RTOL, atol=ATOL)
+        assert st["cert_l1"] <= 1e-9 * (1 + 1e-9)
+
+
+def test_edge_cases_and_outputs(c1):
+    G = P.Graph.from_synth(c1)
+    s = c1.n - 1
+    # lambda = 1: nothing to do, pi_hat = 0 satisfies ||pi_hat - pi||_1 = 1 <= lambda
+    pi, st = G.query(s, ALPHA, 1.0, P.FP64)
+    assert st["sweeps"] == 0 and st["local_levels"] == 0 and not pi.any()
+    # a coarse lambda finishes inside the local phase or after a few sweeps
+    pi, st = G.query(s, ALPHA, 0.5, P.FP64)
+    assert st["r_sum"] <= 0.5 and abs(pi.sum() + st["r_sum"] - 1) < 1e-12
+    # device output and residue output
+    out = torch.empty((1, c1.n), dtype=torch.float64, device="cuda")
+    r_out = torch.empty((1, c1.n), dtype=torch.float64, device="cuda")
+    G.query_batch([s], ALPHA, 1e-8, P.FP64, out=out, r_out=r_out)
+    pi_h, _ = G.query(s, ALPHA, 1e-8, P.FP64)
+    # the local phase adds with FP64 atomics, so repeated runs agree to rounding only
+    np.testing.assert_allclose(out.cpu().numpy()[0], pi_h, rtol=1e-13, atol=1e-20)
+    r = r_out.cpu().numpy()[0]
+    assert abs(pi_h.sum() + r.sum() - 1.0) < 1e-13
+    # batch of FP64 queries == single queries
+    srcs = [3, 77, 3]
+    outb, stb = G.query_batch(srcs, ALPHA, 1e-7, P.FP64)
+    for i, s2 in enumerate(srcs):
+        np.testing.assert_allclose(outb[i], G.query(s2, ALPHA, 1e-7, P.FP64)[0], rtol=1e-13, atol=1e-20)
+
+
+def test_query_argument_errors(c1):
+    G = P.Graph.from_synth(c1)
+    for kw in ({"s": -1}, {"s": c1.n}, {"alpha": 0.0}, {"alpha": 1.0}, {"alpha": float("nan")},
+               {"lam": 0.0}, {"lam": 1.5}, {"lam": float("nan")}):
+        args = {"s": 0, "alpha": ALPHA, "lam": 1e-8}
+        args.update(kw)
+        with pytest.raises(P.PPRError) as ei:
+            G.query(args["s"], args["alpha"], args["lam"], P.FP64)
+        assert ei.value.status == -1
+    with pytest.raises(P.PPRError) as ei:
+        G.query(0, ALPHA, 1e-12, P.FP64, max_sweeps=3)
+    assert ei.value.status == -7
