@@ -1,0 +1,199 @@
+#!/usr/bin/env python3
+"""Benchmark: high-precision SSPPR queries/s on one MI355X.
+
+Workload: directed Chung-Lu graph n = 4,000,000, m = 70,000,000 (out/in
+exponent 2.1, min out-degree 1, no duplicates; synthetic stand-in for the
+LiveJournal-sized graphs of the paper's evaluation), alpha = 0.2,
+lambda = 1e-8, 128 seeded uniform sources.
+
+One step answers all 128 sources with the batched mixed-precision path
+(n x B FP32 block, compensated reserves, FP64 refresh and certificate), every
+result certified ||pi_hat - pi_s||_1 <= lambda by the library's FP64
+certificate.  The graph and its CSC are resident in HBM before the timed
+region; the outputs go to a device buffer.
+
+Also reported (outside the timed steps): the plain FP64 single-query path on
+the same graph, the sweep kernel's algorithmic HBM bytes against its measured
+duration (HIP events on the library's stream), and the FP64 oracle
+(Algorithm 3, one query per host thread) on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def sweep_bytes(n: int, m: int, width: int) -> int:
+    """Algorithmic bytes of one batched sweep: in-edge indices (4 m), per-node
+    CSC offset and FP32 scale (8 n), and per (node, column) 24 bytes: the
+    residue row read once, the new residue written, the compensated reserve
+    pair read and written."""
+    return 4 * m + 8 * n + 24 * n * width
+
+
+def fp64_sweep_bytes(n: int, m: int) -> int:
+    """Plain FP64 sweep: 4 m index bytes, 8 n offset + degree, and per node the
+    residue read once (8), the new residue written (8), the reserve read and
+    written (16)."""
+    return 4 * m + 8 * n + 32 * n
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=4_000_000)
+    ap.add_argument("--m", type=int, default=70_000_000)
+    ap.add_argument("--gamma", type=float, default=2.1)
+    ap.add_argument("--sources", type=int, default=128)
+    ap.add_argument("--lam", type=float, default=1e-8)
+    ap.add_argument("--alpha", type=float, default=0.2)
+    ap.add_argument("--batch-cols", type=int, default=0, help="0 = autotuned")
+    ap.add_argument("--fp64-queries", type=int, default=8)
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the queries shard across GPUs with no exchange "
+              "(the graph is replicated), so run one process per GPU; --gpus must be 1",
+              file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+    import synth
+    import paper_2101_03652_amd as P
+
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    g = synth.chunglu(args.n, args.m, args.gamma)
+    gen_s = time.time() - t0
+    t0 = time.time()
+    G = P.Graph.from_synth(g)
+    info = G.info()
+    create_s = time.time() - t0
+    srcs = synth.sources(g.n, args.sources).tolist()
+    print(f"[bench] graph n={g.n} m={g.m} max_in={info['max_in_degree']} gen={gen_s:.1f}s "
+          f"create={create_s*1e3:.0f}ms", file=sys.stderr, flush=True)
+
+    width = args.batch_cols
+    tune = None
+    if width == 0:
+        tune = G.autotune(alpha=args.alpha)
+        width = tune["best"]
+    print(f"[bench] width={width} tune={tune}", file=sys.stderr, flush=True)
+
+    out = torch.empty((args.sources, g.n), dtype=torch.float64, device="cuda")
+
+    def step():
+        return G.query_batch(srcs, args.alpha, args.lam, P.MIXED, out=out, batch_cols=width)[1]
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stats_all = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        stats_all.append(step())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    q = args.sources * args.steps
+    qps = q / dt
+    edges = sum(s["edge_pushes"] for st in stats_all for s in st)
+    max_cert = max(s["cert_l1"] for st in stats_all for s in st)
+    # sweep kernel timing (HIP events in the library), one entry per block
+    sweep_ms = sweep_n = 0.0
+    for st in stats_all:
+        seen = set()
+        for s in st:
+            key = (s["batch_cols"], s["sweep_ms"], s["sweep_launches"])
+            if key in seen:
+                continue
+            seen.add(key)
+            sweep_ms += s["sweep_ms"]
+            sweep_n += s["sweep_launches"]
+    avg_sweep_ms = sweep_ms / max(sweep_n, 1)
+    bytes_per = sweep_bytes(g.n, g.m, width)
+    achieved = bytes_per / (avg_sweep_ms * 1e-3) / 1e9
+    print(f"[bench] mixed: {qps:.1f} q/s, {dt/args.steps*1e3:.1f} ms/step, sweep {avg_sweep_ms:.3f} ms avg "
+          f"over {int(sweep_n)} launches, max cert {max_cert:.3e}", file=sys.stderr, flush=True)
+
+    # plain FP64 single-query path on the same graph
+    out1 = torch.empty((1, g.n), dtype=torch.float64, device="cuda")
+    G.query_batch([srcs[0]], args.alpha, args.lam, P.FP64, out=out1)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    f64_stats = []
+    for s in srcs[:args.fp64_queries]:
+        f64_stats.append(G.query_batch([s], args.alpha, args.lam, P.FP64, out=out1)[1][0])
+    torch.cuda.synchronize()
+    f64_dt = time.perf_counter() - t1
+    f64_qps = args.fp64_queries / f64_dt
+    f64_sweep_ms = sum(s["sweep_ms"] for s in f64_stats) / max(sum(s["sweep_launches"] for s in f64_stats), 1)
+    f64_gbs = fp64_sweep_bytes(g.n, g.m) / (f64_sweep_ms * 1e-3) / 1e9
+    f64_gteps = sum(s["edge_pushes"] for s in f64_stats) / f64_dt / 1e9
+    print(f"[bench] fp64: {f64_qps:.1f} q/s, sweep {f64_sweep_ms:.3f} ms", file=sys.stderr, flush=True)
+
+    cpu = None
+    if args.cpu_baseline:
+        import oracle
+        threads = args.cpu_threads or int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+        threads = max(1, min(threads, os.cpu_count() or 1))
+        sample = srcs[:threads]
+        t2 = time.perf_counter()
+        pis, ost = oracle.powerpush_many(g, sample, args.alpha, args.lam, threads)
+        c_dt = time.perf_counter() - t2
+        cpu = {"value": round(len(sample) / c_dt, 4), "unit": "queries/s", "cores": threads,
+               "kind": "oracle",
+               "sample": f"{len(sample)} of the step's sources on the same graph, Algorithm 3 in FP64, "
+                         f"one query per host thread, {c_dt:.1f} s wall"}
+        print(f"[bench] cpu oracle: {cpu}", file=sys.stderr, flush=True)
+
+    rec = {
+        "metric": "SSPPR queries/s at lambda=1e-8 (batched mixed precision)",
+        "value": round(qps, 3),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"chung-lu n={g.n} m={g.m} gamma={args.gamma} alpha={args.alpha} "
+                        f"lambda={args.lam:g}, {args.sources} sources per step, batched mixed, B={width}",
+            "n": g.n, "m": g.m, "sources_per_step": args.sources, "batch_cols": width,
+            "alpha": args.alpha, "lambda": args.lam,
+        },
+        "gteps": round(edges / dt / 1e9, 3),
+        "max_cert_l1": max_cert,
+        "fp64_plain": {"value": round(f64_qps, 3), "unit": "queries/s", "gteps": round(f64_gteps, 3),
+                       "sweep_ms": round(f64_sweep_ms, 4), "sweep_gbs": round(f64_gbs, 1)},
+        "speedup_vs_fp64_plain": round(qps / f64_qps, 2),
+        "roofline": {"bound": "hbm", "kernel": f"sweep_b<C={width // 4}>", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "bytes_per_launch": bytes_per,
+                     "avg_launch_ms": round(avg_sweep_ms, 4)},
+        "cpu_baseline": cpu,
+        "graph_create_ms": round(info["build_ms"], 1),
+    }
+    print(json.dumps(rec), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

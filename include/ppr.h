@@ -84,6 +84,11 @@ typedef struct {
                                (always for PPR_MIXED; for PPR_FP64 only when certify = 1,
                                else -1).  An upper bound on ||pi_hat - pi_s||_1. */
     double ms;              /* wall time of the call (whole batch for batched calls) */
+    double sweep_ms;        /* GPU time of the global sweep kernels of this query's block, measured
+                               with HIP events on the library's stream (whole block for batched
+                               calls; refresh passes excluded) */
+    int32_t sweep_launches; /* sweep kernel launches that sweep_ms covers */
+    int32_t batch_cols;     /* block width used (1 for PPR_FP64) */
 } ppr_stats;
 
 /* Query options (ppr_options_default fills the defaults). */

@@ -125,6 +125,9 @@ ppr_status ppr_query_ex(ppr_graph* gh, const int32_t* sources, int32_t B, double
         ppr_options o;
         if (opt) o = *opt; else ppr_options_default(&o);
         check_options(o);
+        HIPCHECK(hipSetDevice(g->device));
+        (void)is_device_ptr(pi_out, g->device);            // rejects another device's memory
+        if (r_out) (void)is_device_ptr(r_out, g->device);
         if (o.precision == PPR_FP64) {
             ppr_status first = PPR_OK;
             std::string msg;
@@ -167,6 +170,8 @@ ppr_status ppr_debug_sweep_fp64(ppr_graph* gh, double alpha, const double* r_in,
         if (!g || !r_in || !r_out || !pi) fail(PPR_ERR_ARG, "NULL argument");
         if (!(alpha > 0.0 && alpha < 1.0)) fail(PPR_ERR_ARG, "alpha must lie in (0, 1)");
         HIPCHECK(hipSetDevice(g->device));
+        if (!is_device_ptr(r_in, g->device) || !is_device_ptr(r_out, g->device) || !is_device_ptr(pi, g->device))
+            fail(PPR_ERR_ARG, "ppr_debug_sweep_fp64 takes device buffers");
         const Schedule& sch = g->schedule(k::sweep_nnz_cap(), k::sweep_row_cap());
         DevBuf y((size_t)g->n * 8), yo((size_t)g->n * 8);
         DevBuf parts(8 * (size_t)std::max(sch.n_blocks, 1024)), sum(8);

@@ -158,12 +158,85 @@ __global__ void reduce_kernel(const double* __restrict__ partials, int nparts, d
 // ---- pull sweep (FP64, one query)
 // Block b of the schedule covers rows [r0, r1).  Leading blocks (b < n_long)
 // hold one long row each: all threads stride its in-edges and a fixed-order
-// tree adds the partial sums.  Other blocks stage the gathered y values of
-// all their in-edges in LDS (the row_idx reads are coalesced), then T
-// threads per row add the row's slice (T = the largest power of two with
-// T * rows <= 256, at most 64, so a row's threads sit in one wave).
+// tree adds the partial sums.  Other blocks stage the gathered values of all
+// their in-edges in LDS (the row_idx reads are coalesced), then T threads per
+// row add the row's slice (T = the largest power of two with T * rows <= 256,
+// at most 64, so a row's threads sit in one wave).
 constexpr int kNnzCap = 2048;
 constexpr int kRowCap = 256;
+constexpr int kPer = kNnzCap / kBlock;
+
+// Every thread first issues all of its index loads, then all of its gathers,
+// so a wave keeps kPer independent requests in flight per lane.
+__device__ inline void stage_gather(const int32_t* __restrict__ row_idx, int64_t e0, int32_t ne,
+                                    const double* __restrict__ x, double* lds) {
+    int32_t idx[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        int32_t i = threadIdx.x + k * kBlock;
+        idx[k] = (i < ne) ? row_idx[e0 + i] : -1;
+    }
+    double val[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) val[k] = (idx[k] >= 0) ? x[idx[k]] : 0.0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+        int32_t i = threadIdx.x + k * kBlock;
+        if (i < ne) lds[i] = val[k];
+    }
+}
+
+// Sum of x over the in-edges [e0, e1) of one long row by the whole block:
+// four independent load chains per thread, combined in a fixed order.
+__device__ inline double long_row_sum(const int32_t* __restrict__ row_idx, int64_t e0, int64_t e1,
+                                      const double* __restrict__ x, double* sh) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int64_t e = e0 + threadIdx.x;
+    for (; e + 3 * kBlock < e1; e += 4 * kBlock) {
+        int32_t i0 = row_idx[e], i1 = row_idx[e + kBlock], i2 = row_idx[e + 2 * kBlock],
+                i3 = row_idx[e + 3 * kBlock];
+        a0 += x[i0];
+        a1 += x[i1];
+        a2 += x[i2];
+        a3 += x[i3];
+    }
+    for (; e < e1; e += kBlock) a0 += x[row_idx[e]];
+    return block_sum((a0 + a1) + (a2 + a3), sh);
+}
+
+// Row sums sum_{v in N_in(u)} x(v) for the rows of schedule block b.  On
+// return, exactly one thread per row holds (u, acc); other threads have u = -1.
+template <typename OffT>
+__device__ inline void pull_rows(const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
+                                 const RowBlock b, bool is_long, const double* __restrict__ x,
+                                 double* lds, double* sh, int32_t& u, double& acc) {
+    u = -1;
+    acc = 0.0;
+    if (is_long) {
+        int64_t e0 = (int64_t)col_ptr[b.r0], e1 = (int64_t)col_ptr[b.r0 + 1];
+        acc = long_row_sum(row_idx, e0, e1, x, sh);
+        if (threadIdx.x == 0) u = b.r0;
+        return;
+    }
+    const int32_t r0 = b.r0, r1 = b.r1;
+    const int32_t R = r1 - r0;
+    int T = 64;
+    while (T * R > kBlock) T >>= 1;
+    const int32_t row = threadIdx.x / T;
+    const int32_t sub = threadIdx.x % T;
+    const int64_t e0 = (int64_t)col_ptr[r0];
+    const int32_t ne = (int32_t)((int64_t)col_ptr[r1] - e0);
+    int32_t s0 = 0, s1 = 0;
+    if (row < R) {              // row bounds loaded before the gathers are waited on
+        s0 = (int32_t)((int64_t)col_ptr[r0 + row] - e0);
+        s1 = (int32_t)((int64_t)col_ptr[r0 + row + 1] - e0);
+    }
+    stage_gather(row_idx, e0, ne, x, lds);
+    __syncthreads();
+    for (int32_t i = s0 + sub; i < s1; i += T) acc += lds[i];
+    for (int o = T >> 1; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if (row < R && sub == 0) u = r0 + row;
+}
 
 template <typename OffT, int FLAGS>
 __global__ __launch_bounds__(kBlock) void sweep_kernel(
@@ -174,37 +247,12 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(
         double* __restrict__ partials) {
     __shared__ double lds[kNnzCap];
     __shared__ double sh[kBlock / 64];
-    const RowBlock b = blocks[blockIdx.x];
     const double oma = 1.0 - alpha;
+    int32_t u;
+    double acc;
+    pull_rows<OffT>(col_ptr, row_idx, blocks[blockIdx.x], (int32_t)blockIdx.x < n_long, y_in, lds, sh, u,
+                    acc);
     double contrib = 0.0;
-    int32_t u = -1;
-    double acc = 0.0;
-    if ((int32_t)blockIdx.x < n_long) {
-        u = b.r0;
-        int64_t e0 = (int64_t)col_ptr[u], e1 = (int64_t)col_ptr[u + 1];
-        for (int64_t e = e0 + threadIdx.x; e < e1; e += kBlock) acc += y_in[row_idx[e]];
-        acc = block_sum(acc, sh);
-        if (threadIdx.x != 0) u = -1;
-    } else {
-        const int32_t r0 = b.r0, r1 = b.r1;
-        const int64_t e0 = (int64_t)col_ptr[r0];
-        const int32_t ne = (int32_t)((int64_t)col_ptr[r1] - e0);
-        for (int32_t i = threadIdx.x; i < ne; i += kBlock) lds[i] = y_in[row_idx[e0 + i]];
-        __syncthreads();
-        const int32_t R = r1 - r0;
-        int T = 64;
-        while (T * R > kBlock) T >>= 1;
-        const int32_t row = threadIdx.x / T;
-        const int32_t sub = threadIdx.x % T;
-        if (row < R) {
-            const int32_t uu = r0 + row;
-            const int32_t s0 = (int32_t)((int64_t)col_ptr[uu] - e0);
-            const int32_t s1 = (int32_t)((int64_t)col_ptr[uu + 1] - e0);
-            for (int32_t i = s0 + sub; i < s1; i += T) acc += lds[i];
-            if (sub == 0) u = uu;
-        }
-        for (int o = T >> 1; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    }
     if (u >= 0) {
         if (FLAGS & SW_ENTRY) pi[u] += alpha * r_in[u];
         if (FLAGS & SW_FOLD) pi[u] += alpha * acc;
@@ -215,7 +263,6 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(
     double t = block_sum(contrib, sh);
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
-
 
 // ---- residual certificate (FP64): q(v) = pi(v) / d_v gathered over in-edges,
 // rt(u) = e_s(u) - (pi(u) - (1-alpha) sum_{v in N_in(u)} q(v)) / alpha, and
@@ -235,35 +282,9 @@ __global__ __launch_bounds__(kBlock) void cert_kernel(
         double* __restrict__ partials) {
     __shared__ double lds[kNnzCap];
     __shared__ double sh[kBlock / 64];
-    const RowBlock b = blocks[blockIdx.x];
-    int32_t u = -1;
-    double acc = 0.0;
-    if ((int32_t)blockIdx.x < n_long) {
-        u = b.r0;
-        int64_t e0 = (int64_t)col_ptr[u], e1 = (int64_t)col_ptr[u + 1];
-        for (int64_t e = e0 + threadIdx.x; e < e1; e += kBlock) acc += q[row_idx[e]];
-        acc = block_sum(acc, sh);
-        if (threadIdx.x != 0) u = -1;
-    } else {
-        const int32_t r0 = b.r0, r1 = b.r1;
-        const int64_t e0 = (int64_t)col_ptr[r0];
-        const int32_t ne = (int32_t)((int64_t)col_ptr[r1] - e0);
-        for (int32_t i = threadIdx.x; i < ne; i += kBlock) lds[i] = q[row_idx[e0 + i]];
-        __syncthreads();
-        const int32_t R = r1 - r0;
-        int T = 64;
-        while (T * R > kBlock) T >>= 1;
-        const int32_t row = threadIdx.x / T;
-        const int32_t sub = threadIdx.x % T;
-        if (row < R) {
-            const int32_t uu = r0 + row;
-            const int32_t s0 = (int32_t)((int64_t)col_ptr[uu] - e0);
-            const int32_t s1 = (int32_t)((int64_t)col_ptr[uu + 1] - e0);
-            for (int32_t i = s0 + sub; i < s1; i += T) acc += lds[i];
-            if (sub == 0) u = uu;
-        }
-        for (int o = T >> 1; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    }
+    int32_t u;
+    double acc;
+    pull_rows<OffT>(col_ptr, row_idx, blocks[blockIdx.x], (int32_t)blockIdx.x < n_long, q, lds, sh, u, acc);
     double contrib = 0.0;
     if (u >= 0) {
         double rt = (u == src ? 1.0 : 0.0) - (pi[u] - (1.0 - alpha) * acc) / alpha;

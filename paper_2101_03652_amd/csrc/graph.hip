@@ -24,6 +24,37 @@ void check_hip(hipError_t e, const char* what, const char* file, int line) {
     fail(e == hipErrorOutOfMemory ? PPR_ERR_OOM : PPR_ERR_DEVICE, buf);
 }
 
+bool is_device_ptr(const void* p, int device) {
+    hipPointerAttribute_t a;
+    std::memset(&a, 0, sizeof a);
+    hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();      // plain pageable host memory
+        return false;
+    }
+    if (a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged) {
+        if (a.device != device) fail(PPR_ERR_ARG, "output buffer lives on another device than the graph");
+        return true;
+    }
+    return false;
+}
+
+EventPair::EventPair() {
+    HIPCHECK(hipEventCreate(&a));
+    HIPCHECK(hipEventCreate(&b));
+}
+EventPair::~EventPair() {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+}
+void EventPair::start(hipStream_t s) { HIPCHECK(hipEventRecord(a, s)); }
+void EventPair::stop(hipStream_t s) { HIPCHECK(hipEventRecord(b, s)); }
+double EventPair::elapsed_ms() const {
+    float ms = 0.f;
+    HIPCHECK(hipEventElapsedTime(&ms, a, b));
+    return (double)ms;
+}
+
 // ---------------------------------------------------------------- buffers
 void DevBuf::alloc(size_t b) {
     release();
@@ -114,6 +145,14 @@ void graph_validate(const int64_t* row_ptr, const int32_t* col, int32_t n, int64
 }
 
 // ---------------------------------------------------------------- graph
+Graph::~Graph() {
+    // contexts first: their streams and captured graphs reference this graph
+    (void)hipSetDevice(device);
+    (void)hipDeviceSynchronize();
+    mixed_pool.clear();
+    pool.clear();
+}
+
 size_t Graph::device_bytes() const {
     size_t b = row_ptr.bytes + col.bytes + col_ptr.bytes + row_idx.bytes + deg.bytes;
     return b;

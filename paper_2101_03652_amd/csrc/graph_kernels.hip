@@ -257,18 +257,33 @@ void count_in(const int32_t* col, int64_t m, int64_t* cnt, hipStream_t s) {
 }
 
 size_t scan_tmp_bytes(int64_t len) {
-    int64_t tiles = (len + kScanTile - 1) / kScanTile;
-    return sizeof(int64_t) * (size_t)(tiles < 1 ? 1 : tiles);
+    // level sizes t1 = ceil(len / tile), then recursively for the tile sums
+    size_t total = 0;
+    int64_t cur = len;
+    for (int lvl = 0; lvl < 4; ++lvl) {
+        int64_t tiles = (cur + kScanTile - 1) / kScanTile;
+        if (tiles < 1) tiles = 1;
+        total += 2 * (size_t)tiles + 2;
+        if (tiles <= (int64_t)kScanTopThreads * kScanTopItems) break;
+        cur = tiles;
+    }
+    return sizeof(int64_t) * total;
 }
 
 void exclusive_scan_i64(const int64_t* in, int64_t* out, int64_t len, void* tmp, hipStream_t s) {
+    // tile sums -> (recursive) exclusive scan of the tile sums -> tiles
     int64_t tiles = (len + kScanTile - 1) / kScanTile;
     if (tiles < 1) tiles = 1;
-    if (tiles > (int64_t)kScanTopThreads * kScanTopItems)
-        fail(PPR_ERR_ARG, "scan length exceeds 2^28 entries");
     int64_t* ts = static_cast<int64_t*>(tmp);
     hipLaunchKernelGGL(scan_tiles_reduce, dim3((unsigned)tiles), dim3(kBlock), 0, s, in, len, ts);
-    hipLaunchKernelGGL(scan_top, dim3(1), dim3(kScanTopThreads), 0, s, ts, tiles);
+    if (tiles <= (int64_t)kScanTopThreads * kScanTopItems) {
+        hipLaunchKernelGGL(scan_top, dim3(1), dim3(kScanTopThreads), 0, s, ts, tiles);
+    } else {
+        // scan the tile sums into the space after them, then copy back in place
+        int64_t* ts_out = ts + tiles + 1;
+        exclusive_scan_i64(ts, ts_out, tiles, ts_out + tiles + 1, s);
+        HIPCHECK(hipMemcpyAsync(ts, ts_out, sizeof(int64_t) * (size_t)tiles, hipMemcpyDeviceToDevice, s));
+    }
     hipLaunchKernelGGL(scan_tiles_apply, dim3((unsigned)tiles), dim3(kBlock), 0, s, in, len, ts, out);
     HIPCHECK(hipGetLastError());
 }

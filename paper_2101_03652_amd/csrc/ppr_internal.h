@@ -25,6 +25,23 @@ struct Failure {
 void check_hip(hipError_t e, const char* what, const char* file, int line);
 #define HIPCHECK(x) ::ppr::check_hip((x), #x, __FILE__, __LINE__)
 
+// True if p is device (or managed) memory of `device`; false for host memory
+// (pageable, pinned or unregistered).  Device memory of another device is an
+// argument error.
+bool is_device_ptr(const void* p, int device);
+
+// A pair of HIP events bracketing work on one stream; elapsed() after a sync.
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    EventPair();
+    ~EventPair();
+    EventPair(const EventPair&) = delete;
+    EventPair& operator=(const EventPair&) = delete;
+    void start(hipStream_t s);
+    void stop(hipStream_t s);
+    double elapsed_ms() const;   // requires the stop event to have completed
+};
+
 // ---------------------------------------------------------------- device buffers
 struct DevBuf {
     void* p = nullptr;
@@ -68,6 +85,11 @@ struct Schedule {
 };
 
 struct QueryCtx;
+struct MixedCtx;
+struct MixedCtxDeleter {
+    void operator()(MixedCtx* c) const;
+};
+using MixedCtxPtr = std::unique_ptr<MixedCtx, MixedCtxDeleter>;
 
 // Device graph: CSR (out-edges, for the frontier push), CSC (in-edges, for
 // the pull sweeps), out-degrees, schedules.
@@ -87,8 +109,12 @@ struct Graph {
     std::vector<int32_t> h_deg;       // host copy of the out-degrees
     std::mutex sched_mu;
     std::vector<std::unique_ptr<Schedule>> schedules;
+    // Query state pools.  They belong to the graph: their captured HIP graphs
+    // hold this graph's device pointers, so they must die with it.
     std::mutex pool_mu;
     std::vector<std::unique_ptr<QueryCtx>> pool;       // idle FP64 query contexts
+    std::vector<MixedCtxPtr> mixed_pool;               // idle batched contexts (any width)
+    ~Graph();
     size_t device_bytes() const;
     const Schedule& schedule(int32_t nnz_cap, int32_t row_cap);
 };

@@ -158,7 +158,11 @@ void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_
 
     // ---- global phase: threshold-0 sweeps contract r_sum by exactly (1 - alpha)
     int32_t sweeps = 0;
+    double sweep_ms = 0.0;
+    int32_t timed_sweeps = 0;
+    EventPair ev;
     if (r_sum > lambda) {
+        ev.start(ss);
         int32_t K = 0;
         for (double x = r_sum; x > lambda && K < opt.max_sweeps; x *= (1.0 - alpha)) ++K;
         double* y0 = c.y0.as<double>();
@@ -188,10 +192,13 @@ void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_
             advance(k::SW_WRITE_R);
         }
         sweeps = K;
+        ev.stop(ss);
         k::reduce_sum(partials, k::sweep_parts(sch), c.dsum.as<double>(), ss);
         HIPCHECK(hipMemcpyAsync(hd, c.dsum.p, 8, hipMemcpyDeviceToHost, ss));
         HIPCHECK(hipStreamSynchronize(ss));
         r_sum = hd[0];
+        sweep_ms = ev.elapsed_ms();
+        timed_sweeps = K;
         // rounding can leave r_sum a hair above lambda: one more plain sweep each time
         while (r_sum > lambda && sweeps < opt.max_sweeps) {
             advance(k::SW_ENTRY | k::SW_WRITE_R);
@@ -217,6 +224,9 @@ void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_
     HIPCHECK(hipStreamSynchronize(ss));
     if (opt.certify) cert = hd[4];
     if (st) {
+        st->sweep_ms = sweep_ms;
+        st->sweep_launches = timed_sweeps;
+        st->batch_cols = 1;
         st->local_levels = levels;
         st->sweeps = sweeps;
         st->refreshes = 0;

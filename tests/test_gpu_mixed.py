@@ -1,0 +1,165 @@
+"""GPU parity of the batched mixed-precision path against the FP64 oracle.
+
+Contract (per column): ||pi_hat - pi_s||_1 <= lambda + 1e-9 against the
+converged FP64 power iteration, where the slack 1e-9 is measurement slack for
+the FP32 residues; the path itself stops only when its FP64 certificate
+||rt||_1 (computed from the compensated reserves) is <= lambda, and the
+certificate is re-checked here by the oracle on the exported vector.
+Column independence: a source answered alone (batch width 4) and inside a
+batch agree to <= 1e-9 in l1 (the block width changes the FP32 summation
+order, nothing else).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_2101_03652_amd")
+
+pytestmark = pytest.mark.gpu
+ALPHA = 0.2
+SLACK = 1e-9
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return synth.chunglu(10_000, 100_000, 2.1)
+
+
+@pytest.fixture(scope="module")
+def c1_truth(c1):
+    srcs = [int(s) for s in synth.sources(c1.n, 40)]
+    return {s: oracle.powitr(c1, s, ALPHA, 135) for s in set(srcs)}
+
+
+def _check_batch(g, srcs, out, stats, lam, truth):
+    for b, s in enumerate(srcs):
+        t = truth[s] if truth is not None and s in truth else oracle.powitr(g, s, ALPHA, 135)
+        err = np.abs(out[b] - t).sum()
+        assert err <= lam + SLACK, (b, s, err)
+        cert = oracle.certificate(g, s, ALPHA, out[b])
+        assert stats[b]["cert_l1"] <= lam
+        assert cert <= lam * (1 + 1e-6) + 1e-15, (b, s, cert)
+        assert stats[b]["cert_l1"] == pytest.approx(cert, rel=1e-6, abs=1e-14)
+        assert stats[b]["source"] == s
+
+
+@pytest.mark.parametrize("width", [4, 8, 16, 32, 64, 128])
+def test_batch_widths_c1(c1, c1_truth, width):
+    srcs = [int(s) for s in synth.sources(c1.n, 40)][:width]
+    print(f"[gpu] mixed c1 width={width}", flush=True)
+    G = P.Graph.from_synth(c1)
+    out, st = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=width)
+    _check_batch(c1, srcs, out, st, 1e-8, c1_truth)
+    assert all(s["refreshes"] >= 1 for s in st)
+
+
+def test_ragged_batch_and_duplicates(c1, c1_truth):
+    srcs = [int(s) for s in synth.sources(c1.n, 40)][:13]
+    srcs[5] = srcs[2]               # the same source twice in one block
+    G = P.Graph.from_synth(c1)
+    out, st = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=8)   # blocks of 8 + 5
+    _check_batch(c1, srcs, out, st, 1e-8, c1_truth)
+    # both columns are certified within lambda of the truth
+    assert np.abs(out[5] - out[2]).sum() <= 2e-8 + SLACK
+
+
+def test_alone_equals_in_mix(c1):
+    srcs = [int(s) for s in synth.sources(c1.n, 40)][:32]
+    G = P.Graph.from_synth(c1)
+    mix, _ = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=32)
+    for b in (0, 7, 31):
+        alone, _ = G.query_batch([srcs[b]], ALPHA, 1e-8, P.MIXED, batch_cols=4)
+        assert np.abs(alone[0] - mix[b]).sum() <= SLACK
+
+
+def test_mixed_vs_fp64_path(c1):
+    srcs = [int(s) for s in synth.sources(c1.n, 40)][:8]
+    G = P.Graph.from_synth(c1)
+    mix, _ = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=8)
+    f64, _ = G.query_batch(srcs, ALPHA, 1e-8, P.FP64)
+    for b in range(8):
+        assert np.abs(mix[b] - f64[b]).sum() <= 2e-8 + SLACK
+
+
+@pytest.mark.parametrize("lam", [1e-4, 1e-6, 1e-10])
+def test_lambda_range(c1, lam):
+    srcs = [int(s) for s in synth.sources(c1.n, 40)][:8]
+    G = P.Graph.from_synth(c1)
+    out, st = G.query_batch(srcs, ALPHA, lam, P.MIXED, batch_cols=8)
+    _check_batch(c1, srcs, out, st, lam, None)
+
+
+def test_small_graphs_and_hubs():
+    a = 1 - ALPHA
+    g = synth.cycle(37)
+    x = np.array([ALPHA * a ** ((v - 5) % 37) / (1 - a ** 37) for v in range(37)])
+    G = P.Graph.from_synth(g)
+    out, st = G.query_batch([5, 5, 5, 5], ALPHA, 1e-10, P.MIXED, batch_cols=4)
+    for b in range(4):
+        assert np.abs(out[b] - x).sum() <= 1e-10 + SLACK
+    g = synth.fig1()
+    G = P.Graph.from_synth(g)
+    out, st = G.query_batch([0, 1, 2, 3, 4], ALPHA, 1e-9, P.MIXED, batch_cols=8)
+    for b in range(5):
+        t = oracle.powitr(g, b, ALPHA, 200)
+        assert np.abs(out[b] - t).sum() <= 1e-9 + SLACK
+    # hub rows: long-row blocks in the sweep and in the refresh
+    from test_gpu_fp64 import _hub_graph
+    h = _hub_graph()
+    G = P.Graph.from_synth(h)
+    srcs = [0, 1, 2, 12345, 777, 19999, 3, 4]
+    for width in (8, 128):
+        out, st = G.query_batch(srcs, ALPHA, 1e-9, P.MIXED, batch_cols=width)
+        _check_batch(h, srcs, out, st, 1e-9, None)
+
+
+def test_outputs_device_and_residual(c1):
+    srcs = [int(s) for s in synth.sources(c1.n, 40)][:8]
+    G = P.Graph.from_synth(c1)
+    out = torch.empty((8, c1.n), dtype=torch.float64, device="cuda")
+    r_out = torch.empty((8, c1.n), dtype=torch.float64, device="cuda")
+    G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=8, out=out, r_out=r_out)
+    pi = out.cpu().numpy()
+    r = r_out.cpu().numpy()
+    for b, s in enumerate(srcs):
+        cert, rt = oracle.certificate(c1, s, ALPHA, pi[b], want_residual=True)
+        # rt is a difference of terms of size pi_hat(u) / alpha <= 5: FP64
+        # cancellation leaves an absolute error of a few 1e-16
+        np.testing.assert_allclose(r[b], rt, rtol=1e-6, atol=2e-15)
+        assert np.abs(r[b]).sum() <= 1e-8
+
+
+def test_not_converged_and_bad_width(c1):
+    G = P.Graph.from_synth(c1)
+    with pytest.raises(P.PPRError) as ei:
+        G.query_batch([1, 2], ALPHA, 1e-10, P.MIXED, batch_cols=4, max_sweeps=5)
+    assert ei.value.status == -7
+    with pytest.raises(P.PPRError) as ei:
+        G.query_batch([1, 2], ALPHA, 1e-8, P.MIXED, batch_cols=12)
+    assert ei.value.status == -1
+    # the graph still answers after the failures
+    out, st = G.query_batch([1, 2], ALPHA, 1e-8, P.MIXED, batch_cols=4)
+    assert st[0]["cert_l1"] <= 1e-8
+
+
+def test_graph_recreated_between_batches(c1):
+    """Regression: batched query state (with its captured sweep graphs) belongs
+    to its graph and is released with it; a graph created afterwards, possibly
+    at the same host address, starts from fresh state."""
+    import gc
+    srcs = [int(s) for s in synth.sources(c1.n, 40)][:8]
+    first = None
+    for rep in range(3):
+        G = P.Graph.from_synth(c1)
+        out, st = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=8)
+        assert max(s["cert_l1"] for s in st) <= 1e-8
+        if first is None:
+            first = out.copy()
+        else:
+            assert np.abs(out - first).sum(axis=1).max() <= 2e-8 + SLACK
+        G.close()
+        del G
+        gc.collect()
