@@ -186,6 +186,19 @@ ppr_status ppr_query_ex(ppr_graph* g, const int32_t* sources, int32_t B, double 
 ppr_status ppr_debug_sweep_fp64(ppr_graph* g, double alpha, const double* r_in, double* r_out,
                                 double* pi, double* r_sum_out);
 
+/*
+ * Autotuner of the batched path: for each candidate block width (a power of
+ * two in [4, 128]; widths NULL = {8, 16, 32, 64, 128}) whose state fits half
+ * of the free device memory, time a few global sweeps on this graph with
+ * HIP events and pick the width with the lowest time per column-sweep.  The
+ * choice is kept in the graph and used when ppr_options.batch_cols = 0.
+ *   widths: host int32[count] or NULL.  best_width: out.  cost_us: out,
+ *   host double[count] (or [5] when widths is NULL), microseconds per
+ *   column-sweep, -1 for a width skipped for memory; nullable.
+ */
+ppr_status ppr_autotune(ppr_graph* g, double alpha, const int32_t* widths, int32_t count,
+                        int32_t* best_width, double* cost_us);
+
 /* Library version string. */
 const char* ppr_version(void);
 

@@ -33,7 +33,7 @@ GRAPH_TRUST_INPUT = 1
 EXPORTS = [
     "ppr_options_default", "ppr_graph_create", "ppr_graph_destroy", "ppr_graph_get_info",
     "ppr_graph_copy_csc", "ppr_query", "ppr_query_batch", "ppr_query_ex",
-    "ppr_debug_sweep_fp64", "ppr_version", "ppr_last_error",
+    "ppr_debug_sweep_fp64", "ppr_version", "ppr_last_error", "ppr_autotune",
 ]
 
 
@@ -92,6 +92,7 @@ def load() -> ctypes.CDLL:
         "ppr_query_batch": (st, [vp, vp, i32, f64, f64, ctypes.c_int, vp, vp]),
         "ppr_query_ex": (st, [vp, vp, i32, f64, f64, vp, vp, vp, vp]),
         "ppr_debug_sweep_fp64": (st, [vp, f64, vp, vp, vp, vp]),
+        "ppr_autotune": (st, [vp, f64, vp, i32, vp, vp]),
         "ppr_version": (ctypes.c_char_p, []),
         "ppr_last_error": (ctypes.c_char_p, []),
     }
@@ -200,6 +201,18 @@ class Graph:
                                  _ptr(out), _ptr(r_out) if r_out is not None else None, st)
         _check(rc)
         return out, [s.as_dict() for s in st]
+
+    def autotune(self, alpha: float = 0.2, widths=None) -> dict:
+        """Pick the batched block width by timing sweeps on this graph; the
+        choice becomes the default of later batched queries."""
+        w = None if widths is None else np.ascontiguousarray(widths, dtype=np.int32)
+        cnt = 5 if w is None else len(w)
+        cost = np.zeros(cnt, dtype=np.float64)
+        best = ctypes.c_int32()
+        _check(load().ppr_autotune(self._h, float(alpha), _ptr(w) if w is not None else None,
+                                   cnt, ctypes.byref(best), _ptr(cost)))
+        ws = [8, 16, 32, 64, 128] if w is None else w.tolist()
+        return {"best": best.value, "us_per_column_sweep": dict(zip(ws, cost.round(3).tolist()))}
 
     def debug_sweep(self, alpha: float, r_in, r_out, pi) -> float:
         """One Eq. 7 sweep on device tensors: r_out = (1-alpha) r_in P, pi += alpha r_in."""

@@ -213,8 +213,7 @@ __device__ inline void pull_rows(const OffT* __restrict__ col_ptr, const int32_t
     u = -1;
     acc = 0.0;
     if (is_long) {
-        int64_t e0 = (int64_t)col_ptr[b.r0], e1 = (int64_t)col_ptr[b.r0 + 1];
-        acc = long_row_sum(row_idx, e0, e1, x, sh);
+        acc = long_row_sum(row_idx, b.e0, b.e0 + b.ne, x, sh);
         if (threadIdx.x == 0) u = b.r0;
         return;
     }
@@ -224,8 +223,8 @@ __device__ inline void pull_rows(const OffT* __restrict__ col_ptr, const int32_t
     while (T * R > kBlock) T >>= 1;
     const int32_t row = threadIdx.x / T;
     const int32_t sub = threadIdx.x % T;
-    const int64_t e0 = (int64_t)col_ptr[r0];
-    const int32_t ne = (int32_t)((int64_t)col_ptr[r1] - e0);
+    const int64_t e0 = b.e0;
+    const int32_t ne = b.ne;
     int32_t s0 = 0, s1 = 0;
     if (row < R) {              // row bounds loaded before the gathers are waited on
         s0 = (int32_t)((int64_t)col_ptr[r0 + row] - e0);

@@ -169,7 +169,7 @@ const Schedule& Graph::schedule(int32_t nnz_cap, int32_t row_cap) {
     int32_t r = 0;
     while (r < n) {
         int64_t d = cp[r + 1] - cp[r];
-        if (d > nnz_cap) { longb.push_back({r, r + 1}); ++r; continue; }
+        if (d > nnz_cap) { longb.push_back({r, r + 1, 0, 0, 0}); ++r; continue; }
         int32_t r0 = r;
         int64_t e = 0;
         while (r < n && r - r0 < row_cap) {
@@ -178,7 +178,7 @@ const Schedule& Graph::schedule(int32_t nnz_cap, int32_t row_cap) {
             e += dd;
             ++r;
         }
-        normal.push_back({r0, r});
+        normal.push_back({r0, r, 0, 0, 0});
     }
     auto s = std::make_unique<Schedule>();
     s->nnz_cap = nnz_cap;
@@ -187,6 +187,11 @@ const Schedule& Graph::schedule(int32_t nnz_cap, int32_t row_cap) {
     s->n_blocks = (int32_t)(longb.size() + normal.size());
     std::vector<RowBlock> all(longb);
     all.insert(all.end(), normal.begin(), normal.end());
+    for (RowBlock& b : all) {
+        b.e0 = cp[b.r0];
+        b.ne = (int32_t)std::min<int64_t>(cp[b.r1] - cp[b.r0], INT32_MAX);
+        b.pad = 0;
+    }
     s->blocks.alloc(sizeof(RowBlock) * all.size());
     HIPCHECK(hipMemcpy(s->blocks.p, all.data(), sizeof(RowBlock) * all.size(), hipMemcpyHostToDevice));
     schedules.push_back(std::move(s));

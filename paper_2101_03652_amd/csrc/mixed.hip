@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 
 #include "ppr_internal.h"
@@ -238,109 +239,116 @@ __device__ inline float4 f4_shfl_xor(float4 a, int o) {
     return make_float4(__shfl_xor(a.x, o, 64), __shfl_xor(a.y, o, 64), __shfl_xor(a.z, o, 64), __shfl_xor(a.w, o, 64));
 }
 
-template <typename OffT, int C>
-__device__ inline void pull_rows_b(const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
-                                   const RowBlock b, bool is_long, const float4* __restrict__ Y4,
-                                   float4* lds, int32_t& u, int& chunk, float4& acc) {
-    using P = Sw<C>;
-    u = -1;
-    chunk = 0;
-    acc = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (is_long) {
-        const int slot = threadIdx.x / C, c = threadIdx.x % C;
-        const int64_t e0 = (int64_t)col_ptr[b.r0], e1 = (int64_t)col_ptr[b.r0 + 1];
-        float4 a0 = acc, a1 = acc;
-        int64_t e = e0 + slot;
-        for (; e + P::kSlots < e1; e += 2 * P::kSlots) {
-            int32_t v0 = row_idx[e], v1 = row_idx[e + P::kSlots];
-            float4 g0 = Y4[(int64_t)v0 * C + c];
-            float4 g1 = Y4[(int64_t)v1 * C + c];
-            a0 = f4_add(a0, g0);
-            a1 = f4_add(a1, g1);
-        }
-        if (e < e1) a0 = f4_add(a0, Y4[(int64_t)row_idx[e] * C + c]);
-        lds[threadIdx.x] = f4_add(a0, a1);
-        __syncthreads();
-        if (threadIdx.x < C) {
-            float4 t = lds[threadIdx.x];
-            for (int s = 1; s < P::kSlots; ++s) t = f4_add(t, lds[s * C + threadIdx.x]);
-            acc = t;
-            u = b.r0;
-            chunk = threadIdx.x;
-        }
-        return;
-    }
-    const int32_t r0 = b.r0, r1 = b.r1;
-    const int32_t R = r1 - r0;
-    int T = 64 / C < 1 ? 1 : 64 / C;                 // (row, chunk) groups stay inside a wave
-    while (T > 1 && T * R * C > kBlock) T >>= 1;
-    const int32_t grp = threadIdx.x / T;             // (row, chunk) pair
-    const int sub = threadIdx.x % T;
-    const int32_t row = grp / C;
-    const int c = grp % C;
-    const int64_t e0 = (int64_t)col_ptr[r0];
-    const int32_t ne = (int32_t)((int64_t)col_ptr[r1] - e0);
-    int32_t s0 = 0, s1 = 0;
-    if (row < R) {
-        s0 = (int32_t)((int64_t)col_ptr[r0 + row] - e0);
-        s1 = (int32_t)((int64_t)col_ptr[r0 + row + 1] - e0);
-    }
-    // stream phase
-    int32_t vv[P::kItems];
-#pragma unroll
-    for (int k = 0; k < P::kItems; ++k) {
-        int32_t it = threadIdx.x + k * kBlock;
-        int32_t e = it / C;
-        vv[k] = (e < ne) ? row_idx[e0 + e] : -1;
-    }
-    float4 gv[P::kItems];
-#pragma unroll
-    for (int k = 0; k < P::kItems; ++k) {
-        int32_t it = threadIdx.x + k * kBlock;
-        gv[k] = (vv[k] >= 0) ? Y4[(int64_t)vv[k] * C + (it % C)] : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-#pragma unroll
-    for (int k = 0; k < P::kItems; ++k) {
-        int32_t it = threadIdx.x + k * kBlock;
-        if (it / C < ne) lds[it] = gv[k];
-    }
-    __syncthreads();
-    for (int32_t e = s0 + sub; e < s1; e += T) acc = f4_add(acc, lds[e * C + c]);
-    for (int o = T >> 1; o >= 1; o >>= 1) acc = f4_add(acc, f4_shfl_xor(acc, o));
-    if (row < R && sub == 0) {
-        u = r0 + row;
-        chunk = c;
-    }
+__device__ inline float4 f4_mul(float4 a, float4 m) { return make_float4(a.x * m.x, a.y * m.y, a.z * m.z, a.w * m.w); }
+
+// Per-column activity in the current stage: column b runs kb[b] sweeps, the
+// device counter *step counts the sweeps done.  A column whose budget is
+// spent gets y' = 0 (its pending residue is dropped; the next FP64 refresh
+// recomputes the exact residual from S), so its S no longer changes.
+__device__ inline float4 active4(const int32_t* __restrict__ kb, int32_t step, int c) {
+    int4 k = reinterpret_cast<const int4*>(kb)[c];
+    return make_float4(step < k.x ? 1.f : 0.f, step < k.y ? 1.f : 0.f, step < k.z ? 1.f : 0.f,
+                       step < k.w ? 1.f : 0.f);
 }
 
-// ENTRY: the sweep that follows a refresh first folds the alpha-part of the
-// refreshed residue into S (and applies the per-column mask of columns that
-// are still running; finished columns get y' = 0 and keep S unchanged).
+// ENTRY: the first sweep after a refresh also folds the alpha-part of the
+// refreshed residue (still in Y_in) into S.
+//
+// Latency: all loads that do not depend on the gathered data (row bounds,
+// the reserve pair, the scale, the own residue) are issued before the
+// index loads, so a block waits for about two memory round trips (indices,
+// then gathers) instead of four.
 template <typename OffT, int C, bool ENTRY>
 __global__ __launch_bounds__(kBlock) void sweep_b(
         const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
         const RowBlock* __restrict__ blocks, int32_t n_long, const float* __restrict__ scale,
         const float4* __restrict__ Y_in, float4* __restrict__ Y_out, float4* __restrict__ Shi,
-        float4* __restrict__ Slo, const float4* __restrict__ mask) {
+        float4* __restrict__ Slo, const int32_t* __restrict__ kb, const int32_t* __restrict__ step_p) {
+    using P = Sw<C>;
     __shared__ float4 lds[kLdsBytes / 16];
-    int32_t u;
-    int c;
-    float4 acc;
-    pull_rows_b<OffT, C>(col_ptr, row_idx, blocks[blockIdx.x], (int32_t)blockIdx.x < n_long, Y_in, lds, u, c,
-                         acc);
+    const RowBlock b = blocks[blockIdx.x];
+    const int32_t step = *step_p;
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    int32_t u = -1;
+    int c = 0;
+    if ((int32_t)blockIdx.x < n_long) {
+        // one long row: 256 / C slots stride its edges, then a fixed-order sum
+        const int slot = threadIdx.x / C;
+        c = threadIdx.x % C;
+        const int64_t e0 = b.e0, e1 = b.e0 + b.ne;
+        float4 a0 = acc, a1 = acc, a2 = acc, a3 = acc;
+        int64_t e = e0 + slot;
+        for (; e + 3 * P::kSlots < e1; e += 4 * P::kSlots) {
+            int32_t v0 = row_idx[e], v1 = row_idx[e + P::kSlots], v2 = row_idx[e + 2 * P::kSlots],
+                    v3 = row_idx[e + 3 * P::kSlots];
+            float4 g0 = Y_in[(int64_t)v0 * C + c], g1 = Y_in[(int64_t)v1 * C + c];
+            float4 g2 = Y_in[(int64_t)v2 * C + c], g3 = Y_in[(int64_t)v3 * C + c];
+            a0 = f4_add(a0, g0);
+            a1 = f4_add(a1, g1);
+            a2 = f4_add(a2, g2);
+            a3 = f4_add(a3, g3);
+        }
+        for (; e < e1; e += P::kSlots) a0 = f4_add(a0, Y_in[(int64_t)row_idx[e] * C + c]);
+        lds[threadIdx.x] = f4_add(f4_add(a0, a1), f4_add(a2, a3));
+        __syncthreads();
+        if (threadIdx.x < C) {
+            float4 t = lds[threadIdx.x];
+            for (int s2 = 1; s2 < P::kSlots; ++s2) t = f4_add(t, lds[s2 * C + threadIdx.x]);
+            acc = t;
+            u = b.r0;
+        }
+    } else {
+        const int32_t r0 = b.r0;
+        const int32_t R = b.r1 - r0;
+        const int32_t ne = b.ne;
+        const int64_t e0 = b.e0;
+        int T = 64 / C < 1 ? 1 : 64 / C;                // (row, chunk) groups stay inside a wave
+        while (T > 1 && T * R * C > kBlock) T >>= 1;
+        const int32_t grp = threadIdx.x / T;
+        const int sub = threadIdx.x % T;
+        const int32_t row = grp / C;
+        c = grp % C;
+        // independent loads first: row bounds, then the index loads
+        int32_t s0 = 0, s1 = 0;
+        if (row < R) {
+            s0 = (int32_t)((int64_t)col_ptr[r0 + row] - e0);
+            s1 = (int32_t)((int64_t)col_ptr[r0 + row + 1] - e0);
+        }
+        int32_t vv[P::kItems];
+#pragma unroll
+        for (int k = 0; k < P::kItems; ++k) {
+            int32_t it = threadIdx.x + k * kBlock;
+            vv[k] = (it / C < ne) ? row_idx[e0 + it / C] : -1;
+        }
+        float4 gv[P::kItems];
+#pragma unroll
+        for (int k = 0; k < P::kItems; ++k) {
+            int32_t it = threadIdx.x + k * kBlock;
+            gv[k] = (vv[k] >= 0) ? Y_in[(int64_t)vv[k] * C + (it % C)] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int k = 0; k < P::kItems; ++k) {
+            int32_t it = threadIdx.x + k * kBlock;
+            if (it / C < ne) lds[it] = gv[k];
+        }
+        __syncthreads();
+        for (int32_t e = s0 + sub; e < s1; e += T) acc = f4_add(acc, lds[e * C + c]);
+        for (int o = T >> 1; o >= 1; o >>= 1) acc = f4_add(acc, f4_shfl_xor(acc, o));
+        if (row < R && sub == 0) u = r0 + row;
+    }
     if (u < 0) return;
     const int64_t at = (int64_t)u * C + c;
     float4 hi = Shi[at], lo = Slo[at];
-    if (ENTRY) {
-        float4 m = mask[c];
-        float4 y0 = Y_in[at];
-        comp_add(hi.x, lo.x, y0.x * m.x);
-        comp_add(hi.y, lo.y, y0.y * m.y);
-        comp_add(hi.z, lo.z, y0.z * m.z);
-        comp_add(hi.w, lo.w, y0.w * m.w);
-        acc = make_float4(acc.x * m.x, acc.y * m.y, acc.z * m.z, acc.w * m.w);
-    }
     const float sc = scale[u];
+    const float4 m = active4(kb, step, c);
+    if (ENTRY) {
+        float4 y0 = f4_mul(Y_in[at], m);
+        comp_add(hi.x, lo.x, y0.x);
+        comp_add(hi.y, lo.y, y0.y);
+        comp_add(hi.z, lo.z, y0.z);
+        comp_add(hi.w, lo.w, y0.w);
+    }
+    acc = f4_mul(acc, m);
     float4 y = make_float4(sc * acc.x, sc * acc.y, sc * acc.z, sc * acc.w);
     comp_add(hi.x, lo.x, y.x);
     comp_add(hi.y, lo.y, y.y);
@@ -350,6 +358,8 @@ __global__ __launch_bounds__(kBlock) void sweep_b(
     Shi[at] = hi;
     Slo[at] = lo;
 }
+
+__global__ void bump_step(int32_t* step) { step[0] += 1; }
 
 // ---------------------------------------------------------------- refresh (FP64)
 // rt(u) = e_s(u) - d_u S(u) / (1-alpha) + sum_{v in N_in(u)} S(v), all in
@@ -391,7 +401,7 @@ __global__ __launch_bounds__(kBlock) void refresh_b(
         if (bi < n_long) {
             // one long row: slots stride the edges, FP64 partials through LDS
             const int slot = threadIdx.x / C;
-            const int64_t e0 = (int64_t)col_ptr[b.r0], e1 = (int64_t)col_ptr[b.r0 + 1];
+            const int64_t e0 = b.e0, e1 = b.e0 + b.ne;
             for (int64_t e = e0 + slot; e < e1; e += kBlock / C) {
                 int64_t v = row_idx[e];
                 float4 h = Shi[v * C + c], l = Slo[v * C + c];
@@ -419,8 +429,8 @@ __global__ __launch_bounds__(kBlock) void refresh_b(
             __syncthreads();
         } else {
             const int32_t r0 = b.r0, r1 = b.r1;
-            const int64_t e0 = (int64_t)col_ptr[r0];
-            const int32_t ne = (int32_t)((int64_t)col_ptr[r1] - e0);
+            const int64_t e0 = b.e0;
+            const int32_t ne = b.ne;
             int32_t s0 = 0, s1 = 0;
             const bool has = myrow < r1 - r0;
             if (has) {
@@ -562,7 +572,8 @@ struct MixedCtx {
     DevBuf taken;                     // double[Bw]
     DevBuf active;                    // uint8[Bw]
     DevBuf src;                       // int32[Bw]
-    DevBuf mask;                      // float[Bw]
+    DevBuf kb;                        // int32[Bw] per-column sweep budget of the stage
+    DevBuf step;                      // int32[1] sweeps done in the stage
     DevBuf stage;                     // double[Bw][n], host-output staging (lazy)
     PinnedBuf host;
     hipGraphExec_t chunk = nullptr;   // captured plain sweeps Y1->Y0->Y1 ...
@@ -628,7 +639,8 @@ MixedCtxPtr mixed_acquire(Graph& g, int Bw, int64_t fcap) {
     c->taken.alloc(8 * (size_t)Bw);
     c->active.alloc((size_t)Bw);
     c->src.alloc(4 * (size_t)Bw);
-    c->mask.alloc(4 * (size_t)Bw);
+    c->kb.alloc(4 * (size_t)Bw);
+    c->step.alloc(64);
     c->host.alloc(64 + 48 * (size_t)Bw);
     HIPCHECK(hipStreamSynchronize(c->stream));
     return c;
@@ -639,30 +651,26 @@ void mixed_release(Graph& g, MixedCtxPtr c) {
     g.mixed_pool.push_back(std::move(c));
 }
 
+template <typename OffT, int C, bool ENTRY>
+void launch_sweep_b3(Graph& g, MixedCtx& c, const Schedule& sch, const float4* Y4i, float4* Y4o) {
+    hipLaunchKernelGGL((mk::sweep_b<OffT, C, ENTRY>), dim3((unsigned)sch.n_blocks), dim3(mk::kBlock), 0,
+                       c.stream, g.col_ptr.as<OffT>(), g.row_idx.as<int32_t>(), sch.blocks.as<RowBlock>(),
+                       sch.n_long, c.scale.as<float>(), Y4i, Y4o, c.Shi.as<float4>(), c.Slo.as<float4>(),
+                       c.kb.as<int32_t>(), c.step.as<int32_t>());
+    hipLaunchKernelGGL(mk::bump_step, dim3(1), dim3(1), 0, c.stream, c.step.as<int32_t>());
+}
+
 template <int C>
 void launch_sweep_b(Graph& g, MixedCtx& c, bool entry, const float* yin, float* yout) {
     const Schedule& sch = sweep_schedule<C>(g);
-    dim3 grid((unsigned)sch.n_blocks), blk(mk::kBlock);
     auto Y4i = reinterpret_cast<const float4*>(yin);
     auto Y4o = reinterpret_cast<float4*>(yout);
-    auto H = c.Shi.as<float4>();
-    auto L = c.Slo.as<float4>();
-    auto M = c.mask.as<float4>();
-    const RowBlock* bl = sch.blocks.as<RowBlock>();
     if (g.off64) {
-        if (entry)
-            hipLaunchKernelGGL((mk::sweep_b<int64_t, C, true>), grid, blk, 0, c.stream, g.col_ptr.as<int64_t>(),
-                               g.row_idx.as<int32_t>(), bl, sch.n_long, c.scale.as<float>(), Y4i, Y4o, H, L, M);
-        else
-            hipLaunchKernelGGL((mk::sweep_b<int64_t, C, false>), grid, blk, 0, c.stream, g.col_ptr.as<int64_t>(),
-                               g.row_idx.as<int32_t>(), bl, sch.n_long, c.scale.as<float>(), Y4i, Y4o, H, L, M);
+        if (entry) launch_sweep_b3<int64_t, C, true>(g, c, sch, Y4i, Y4o);
+        else launch_sweep_b3<int64_t, C, false>(g, c, sch, Y4i, Y4o);
     } else {
-        if (entry)
-            hipLaunchKernelGGL((mk::sweep_b<uint32_t, C, true>), grid, blk, 0, c.stream, g.col_ptr.as<uint32_t>(),
-                               g.row_idx.as<int32_t>(), bl, sch.n_long, c.scale.as<float>(), Y4i, Y4o, H, L, M);
-        else
-            hipLaunchKernelGGL((mk::sweep_b<uint32_t, C, false>), grid, blk, 0, c.stream, g.col_ptr.as<uint32_t>(),
-                               g.row_idx.as<int32_t>(), bl, sch.n_long, c.scale.as<float>(), Y4i, Y4o, H, L, M);
+        if (entry) launch_sweep_b3<uint32_t, C, true>(g, c, sch, Y4i, Y4o);
+        else launch_sweep_b3<uint32_t, C, false>(g, c, sch, Y4i, Y4o);
     }
     HIPCHECK(hipGetLastError());
 }
@@ -721,11 +729,15 @@ Dispatch dispatch_for(int Bw) {
 }
 
 // Batched form of the switch rule.  Edge rule: a column keeps pushing locally
-// while switch_param * Bw * vol_b <= m, so one level of the whole block moves
-// at most about m / switch_param edges, the bound the single-query path uses.
-bool continue_local(const ppr_options& opt, int64_t nf, int64_t vol, int32_t n, int64_t m, int Bw) {
+// while switch_param * kBatchRef * vol_b <= m, so one level of a block of
+// kBatchRef columns moves at most about m / switch_param edges, the bound of
+// the single-query path.  The rule does not depend on the block width, so a
+// column's schedule is the same whichever block it runs in.
+constexpr double kBatchRef = 32.0;
+
+bool continue_local(const ppr_options& opt, int64_t nf, int64_t vol, int32_t n, int64_t m) {
     if (opt.switch_rule == PPR_SWITCH_NODES) return 4 * nf <= (int64_t)n;
-    return opt.switch_param * (double)Bw * (double)vol <= (double)m;
+    return opt.switch_param * kBatchRef * (double)vol <= (double)m;
 }
 
 constexpr int kChunkSweeps = 16;
@@ -781,7 +793,7 @@ void run_mixed_chunk(Graph& g, MixedCtx& c, const int32_t* sources, int Breal, d
             // a column's next frontier holds at most vol_b entries: it must fit
             // the per-column share of the frontier capacity
             act[b] = (b < Breal && nf_b[b] > 0 && rsum_b[b] > lambda &&
-                      continue_local(opt, nf_b[b], vol_b[b], n, g.m, Bw) &&
+                      continue_local(opt, nf_b[b], vol_b[b], n, g.m) &&
                       vol_b[b] <= c.fcap / Bw) ? 1 : 0;
             if (act[b]) {
                 vol += vol_b[b];
@@ -862,29 +874,30 @@ void run_mixed_chunk(Graph& g, MixedCtx& c, const int32_t* sources, int Breal, d
     double sweep_ms = 0.0;
     int32_t total_sweeps = 0, total_refresh = 0;
     const double oma = 1.0 - alpha;
-    std::vector<float> hmask(Bw, 0.0f);
+    std::vector<int32_t> hkb(Bw, 0);
     for (;;) {
-        double emax = 0.0;
-        for (int b = 0; b < Bw; ++b)
-            if (!done[b]) emax = std::max(emax, err[b]);
-        bool need_final_check = false;
+        // per-column budget: sweeps until err_b has fallen by refresh_factor
+        // (or to lambda / 2); a column's schedule depends on its own error only
         int K = 0;
-        if (emax > 0.0) {
-            double target = std::max(emax / opt.refresh_factor, 0.5 * lambda);
-            for (double x = emax; x > target; x *= oma) ++K;
+        for (int b = 0; b < Bw; ++b) {
+            hkb[b] = 0;
+            if (done[b]) continue;
+            double target = std::max(err[b] / opt.refresh_factor, 0.5 * lambda);
+            int k = 0;
+            for (double x = err[b]; x > target; x *= oma) ++k;
+            hkb[b] = k;
+            K = std::max(K, k);
         }
-        if (K == 0) need_final_check = true;
-        if (total_sweeps + K > opt.max_sweeps) K = std::max(0, opt.max_sweeps - total_sweeps);
+        if (total_sweeps + K > opt.max_sweeps) {
+            K = std::max(0, opt.max_sweeps - total_sweeps);
+            for (int b = 0; b < Bw; ++b) hkb[b] = std::min(hkb[b], K);
+        }
         if (K > 0) {
+            HIPCHECK(hipMemcpyAsync(c.kb.p, hkb.data(), 4 * (size_t)Bw, hipMemcpyHostToDevice, ss));
+            HIPCHECK(hipMemsetAsync(c.step.p, 0, 4, ss));
             ev.start(ss);
-            if (entry) {
-                for (int b = 0; b < Bw; ++b) hmask[b] = done[b] ? 0.0f : 1.0f;
-                HIPCHECK(hipMemcpyAsync(c.mask.p, hmask.data(), 4 * (size_t)Bw, hipMemcpyHostToDevice, ss));
-                advance(true);
-                entry = false;
-            } else {
-                advance(false);
-            }
+            advance(entry);
+            entry = false;
             int rest = K - 1;
             // replay captured chunks of plain sweeps when the buffers line up
             if (rest >= kChunkSweeps && yc == c.Y1.as<float>()) {
@@ -921,8 +934,8 @@ void run_mixed_chunk(Graph& g, MixedCtx& c, const int32_t* sources, int Breal, d
             total_sweeps += K;
             for (int b = 0; b < Bw; ++b)
                 if (!done[b]) {
-                    sweeps_b[b] += K;
-                    err[b] *= std::pow(oma, K);
+                    sweeps_b[b] += hkb[b];
+                    err[b] *= std::pow(oma, hkb[b]);
                 }
         }
         // FP64 refresh: exact residual of the current estimate, and its l1 norm
@@ -948,7 +961,6 @@ void run_mixed_chunk(Graph& g, MixedCtx& c, const int32_t* sources, int Breal, d
         }
         if (all) break;
         if (total_sweeps >= opt.max_sweeps) break;
-        (void)need_final_check;
     }
     // ---- output: the export kernel writes device memory only; a host
     // destination is filled through a device staging buffer
@@ -993,6 +1005,100 @@ void run_mixed_chunk(Graph& g, MixedCtx& c, const int32_t* sources, int Breal, d
 
 }  // namespace
 
+namespace {
+
+int64_t frontier_capacity(const Graph& g, const ppr_options& opt, int Bw) {
+    // a level runs only if the column's next frontier (at most vol_b entries)
+    // fits its share of the capacity
+    int64_t per_col = g.n;
+    if (opt.switch_rule == PPR_SWITCH_EDGES && opt.switch_param > 0)
+        per_col = std::min<int64_t>(per_col, (int64_t)((double)g.m / (opt.switch_param * kBatchRef)) + 1);
+    per_col = std::max<int64_t>(per_col, 1 + g.max_out);
+    return per_col * Bw;
+}
+
+size_t mixed_footprint(const Graph& g, int Bw, int64_t fcap) {
+    const size_t nb = (size_t)g.n * (size_t)Bw;
+    return 16 * nb          // FP64 local-phase scratch
+           + 16 * nb        // Y0, Y1, Shi, Slo
+           + 40 * (size_t)fcap + 4 * (size_t)g.n + ((size_t)1 << 20);
+}
+
+}  // namespace
+
+void autotune_width(Graph& g, double alpha, const int32_t* widths, int32_t count, int32_t* best,
+                    double* cost_us) {
+    HIPCHECK(hipSetDevice(g.device));
+    static const int32_t kDefault[5] = {8, 16, 32, 64, 128};
+    if (!widths) {
+        widths = kDefault;
+        count = 5;
+    }
+    if (count < 1) fail(PPR_ERR_ARG, "no candidate widths");
+    ppr_options opt;
+    ppr_options_default(&opt);
+    size_t free_b = 0, total_b = 0;
+    HIPCHECK(hipMemGetInfo(&free_b, &total_b));
+    double best_cost = 1e300;
+    int best_w = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        int W = widths[i];
+        if (W < 4 || W > 128 || (W & (W - 1))) fail(PPR_ERR_ARG, "candidate widths must be powers of two in [4, 128]");
+        int64_t fcap = frontier_capacity(g, opt, W);
+        // contexts already pooled for this width cost nothing new
+        bool pooled = false;
+        {
+            std::lock_guard<std::mutex> lk(g.pool_mu);
+            for (auto& c : g.mixed_pool) pooled |= (c->Bw == W && c->fcap >= fcap);
+        }
+        if (!pooled && mixed_footprint(g, W, fcap) > free_b / 2) {
+            if (cost_us) cost_us[i] = -1.0;
+            continue;
+        }
+        MixedCtxPtr c = mixed_acquire(g, W, fcap);
+        hipStream_t ss = c->stream;
+        const size_t nb = (size_t)g.n * W;
+        HIPCHECK(hipMemsetAsync(c->Y0.p, 0, 4 * nb, ss));
+        HIPCHECK(hipMemsetAsync(c->Y1.p, 0, 4 * nb, ss));
+        HIPCHECK(hipMemsetAsync(c->Shi.p, 0, 4 * nb, ss));
+        HIPCHECK(hipMemsetAsync(c->Slo.p, 0, 4 * nb, ss));
+        std::vector<int32_t> kb(W, 1 << 30);
+        HIPCHECK(hipMemcpyAsync(c->kb.p, kb.data(), 4 * (size_t)W, hipMemcpyHostToDevice, ss));
+        HIPCHECK(hipMemsetAsync(c->step.p, 0, 4, ss));
+        if (c->alpha != alpha) {
+            hipLaunchKernelGGL(mk::scale_kernel, dim3(1024), dim3(256), 0, ss, g.deg.as<int32_t>(), g.n, alpha,
+                               c->scale.as<float>());
+            HIPCHECK(hipGetLastError());
+            if (c->chunk) {
+                (void)hipGraphExecDestroy(c->chunk);
+                c->chunk = nullptr;
+            }
+            c->alpha = alpha;
+        }
+        Dispatch D = dispatch_for(W);
+        const int reps = 4;
+        D.sweep(g, *c, false, c->Y0.as<float>(), c->Y1.as<float>());     // warm-up
+        EventPair ev;
+        ev.start(ss);
+        for (int r = 0; r < reps; ++r)
+            D.sweep(g, *c, false, (r & 1) ? c->Y1.as<float>() : c->Y0.as<float>(),
+                    (r & 1) ? c->Y0.as<float>() : c->Y1.as<float>());
+        ev.stop(ss);
+        HIPCHECK(hipStreamSynchronize(ss));
+        double us = ev.elapsed_ms() * 1e3 / reps / W;
+        if (cost_us) cost_us[i] = us;
+        // prefer the narrower block unless the wider one is clearly cheaper
+        if (best_w == 0 || us < best_cost * 0.97) {
+            best_cost = us;
+            best_w = W;
+        }
+        mixed_release(g, std::move(c));
+    }
+    if (best_w == 0) fail(PPR_ERR_OOM, "no candidate width fits the device memory budget");
+    g.tuned_width = best_w;
+    if (best) *best = best_w;
+}
+
 int default_batch_width(int32_t B) {
     int w = 4;
     while (w < B && w < 32) w <<= 1;
@@ -1002,17 +1108,11 @@ int default_batch_width(int32_t B) {
 void run_mixed_batch(Graph& g, const int32_t* sources, int32_t B, double alpha, double lambda,
                      const ppr_options& opt, double* pi_out, double* r_out, ppr_stats* st) {
     HIPCHECK(hipSetDevice(g.device));
-    int Bw = opt.batch_cols > 0 ? opt.batch_cols : default_batch_width(B);
+    int Bw = opt.batch_cols > 0 ? opt.batch_cols : (g.tuned_width > 0 ? g.tuned_width : default_batch_width(B));
     if (Bw < 4 || Bw > 128 || (Bw & (Bw - 1))) fail(PPR_ERR_ARG, "batch_cols must be a power of two in [4, 128]");
     // frontier capacity: a column's frontier never exceeds n, nor (edge rule)
     // m / switch_param + 1 entries
-    // frontier capacity per column: a level runs only if the column's next
-    // frontier (at most vol_b entries) fits its share
-    int64_t per_col = g.n;
-    if (opt.switch_rule == PPR_SWITCH_EDGES && opt.switch_param > 0)
-        per_col = std::min<int64_t>(per_col, (int64_t)((double)g.m / (opt.switch_param * Bw)) + 1);
-    per_col = std::max<int64_t>(per_col, 1 + g.max_out);
-    int64_t fcap = per_col * Bw;
+    int64_t fcap = frontier_capacity(g, opt, Bw);
     auto c = mixed_acquire(g, Bw, fcap);
     ppr_status first = PPR_OK;
     std::string msg;

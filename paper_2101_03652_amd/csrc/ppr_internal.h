@@ -72,7 +72,9 @@ struct PinnedBuf {
 // pull sweep.  Long rows (more in-edges than the block's edge budget) get a
 // block of their own and are listed first.
 struct RowBlock {
-    int32_t r0, r1;
+    int32_t r0, r1;      // rows [r0, r1)
+    int32_t ne, pad;     // in-edges of those rows
+    int64_t e0;          // offset of the first in-edge (= col_ptr[r0])
 };
 
 // Sweep schedule for one edge budget.
@@ -114,6 +116,7 @@ struct Graph {
     std::mutex pool_mu;
     std::vector<std::unique_ptr<QueryCtx>> pool;       // idle FP64 query contexts
     std::vector<MixedCtxPtr> mixed_pool;               // idle batched contexts (any width)
+    int tuned_width = 0;                               // autotuner's choice (0 = not tuned)
     ~Graph();
     size_t device_bytes() const;
     const Schedule& schedule(int32_t nnz_cap, int32_t row_cap);
@@ -194,5 +197,7 @@ void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_
                     double* pi_out, double* r_out, ppr_stats* st);
 void run_mixed_batch(Graph& g, const int32_t* sources, int32_t B, double alpha, double lambda,
                      const ppr_options& opt, double* pi_out, double* r_out, ppr_stats* st);
+void autotune_width(Graph& g, double alpha, const int32_t* widths, int32_t count, int32_t* best,
+                    double* cost_us);
 
 }  // namespace ppr

@@ -67,11 +67,16 @@ def test_ragged_batch_and_duplicates(c1, c1_truth):
 
 
 def test_alone_equals_in_mix(c1):
+    """A column's sweep budget depends on its own error only, so a source
+    answered alone and inside a block of 32 runs the same schedule; the two
+    results differ only by FP32 summation order."""
     srcs = [int(s) for s in synth.sources(c1.n, 40)][:32]
     G = P.Graph.from_synth(c1)
-    mix, _ = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=32)
+    mix, smix = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=32)
     for b in (0, 7, 31):
-        alone, _ = G.query_batch([srcs[b]], ALPHA, 1e-8, P.MIXED, batch_cols=4)
+        alone, sal = G.query_batch([srcs[b]], ALPHA, 1e-8, P.MIXED, batch_cols=4)
+        assert sal[0]["sweeps"] == smix[b]["sweeps"]
+        assert sal[0]["refreshes"] == smix[b]["refreshes"]
         assert np.abs(alone[0] - mix[b]).sum() <= SLACK
 
 
@@ -163,3 +168,14 @@ def test_graph_recreated_between_batches(c1):
         G.close()
         del G
         gc.collect()
+
+
+def test_autotune_picks_a_width_and_queries_use_it(c1):
+    G = P.Graph.from_synth(c1)
+    res = G.autotune(ALPHA, widths=[4, 16])
+    assert res["best"] in (4, 16)
+    assert all(v > 0 for v in res["us_per_column_sweep"].values())
+    srcs = [int(s) for s in synth.sources(c1.n, 40)][:6]
+    out, st = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED)          # batch_cols = 0: tuned width
+    assert all(s["batch_cols"] == res["best"] for s in st)
+    assert max(s["cert_l1"] for s in st) <= 1e-8
