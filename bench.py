@@ -33,10 +33,10 @@ HBM_PEAK_GBS = 8000.0
 
 def sweep_bytes(n: int, m: int, width: int) -> int:
     """Algorithmic bytes of one batched sweep: in-edge indices (4 m), per-node
-    CSC offset and FP32 scale (8 n), and per (node, column) 24 bytes: the
-    residue row read once, the new residue written, the compensated reserve
-    pair read and written."""
-    return 4 * m + 8 * n + 24 * n * width
+    CSC offset and FP32 scale (8 n), and per (node, column) 16 bytes: the
+    residue row read once, the new residue written, the per-stage reserve
+    accumulator read and written."""
+    return 4 * m + 8 * n + 16 * n * width
 
 
 def fp64_sweep_bytes(n: int, m: int) -> int:
@@ -44,6 +44,31 @@ def fp64_sweep_bytes(n: int, m: int) -> int:
     residue read once (8), the new residue written (8), the reserve read and
     written (16)."""
     return 4 * m + 8 * n + 32 * n
+
+
+def kernel_source_digest() -> str:
+    """Digest of the batched-path source: counter readings are valid only for
+    the kernel they were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "paper_2101_03652_amd", "csrc", "mixed.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(width: int):
+    """HBM bytes per sweep launch from the committed rocprofv3 counter runs
+    (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter's reading for a
+    plain 1 GiB copy), or None when they were taken on another kernel build
+    or width."""
+    path = os.path.join(ROOT, "profiles", "sweep_b_traffic.json")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_digest") != kernel_source_digest() or t.get("batch_cols") != width:
+        return None
+    return t.get("bytes_per_launch")
 
 
 def main() -> int:
@@ -61,6 +86,8 @@ def main() -> int:
     ap.add_argument("--fp64-queries", type=int, default=8)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--calibrate-copy", type=int, default=0,
+                    help="also copy a 1 GiB device buffer (reference for the HBM byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -130,20 +157,37 @@ def main() -> int:
           f"over {int(sweep_n)} launches, max cert {max_cert:.3e}", file=sys.stderr, flush=True)
 
     # plain FP64 single-query path on the same graph
-    out1 = torch.empty((1, g.n), dtype=torch.float64, device="cuda")
-    G.query_batch([srcs[0]], args.alpha, args.lam, P.FP64, out=out1)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    f64_stats = []
-    for s in srcs[:args.fp64_queries]:
-        f64_stats.append(G.query_batch([s], args.alpha, args.lam, P.FP64, out=out1)[1][0])
-    torch.cuda.synchronize()
-    f64_dt = time.perf_counter() - t1
-    f64_qps = args.fp64_queries / f64_dt
-    f64_sweep_ms = sum(s["sweep_ms"] for s in f64_stats) / max(sum(s["sweep_launches"] for s in f64_stats), 1)
-    f64_gbs = fp64_sweep_bytes(g.n, g.m) / (f64_sweep_ms * 1e-3) / 1e9
-    f64_gteps = sum(s["edge_pushes"] for s in f64_stats) / f64_dt / 1e9
-    print(f"[bench] fp64: {f64_qps:.1f} q/s, sweep {f64_sweep_ms:.3f} ms", file=sys.stderr, flush=True)
+    fp64 = None
+    f64_qps = None
+    if args.fp64_queries > 0:
+        out1 = torch.empty((1, g.n), dtype=torch.float64, device="cuda")
+        G.query_batch([srcs[0]], args.alpha, args.lam, P.FP64, out=out1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        f64_stats = []
+        for s in srcs[:args.fp64_queries]:
+            f64_stats.append(G.query_batch([s], args.alpha, args.lam, P.FP64, out=out1)[1][0])
+        torch.cuda.synchronize()
+        f64_dt = time.perf_counter() - t1
+        f64_qps = args.fp64_queries / f64_dt
+        f64_sweep_ms = sum(s["sweep_ms"] for s in f64_stats) / max(sum(s["sweep_launches"] for s in f64_stats), 1)
+        f64_gbs = fp64_sweep_bytes(g.n, g.m) / (f64_sweep_ms * 1e-3) / 1e9
+        f64_gteps = sum(s["edge_pushes"] for s in f64_stats) / f64_dt / 1e9
+        fp64 = {"value": round(f64_qps, 3), "unit": "queries/s", "gteps": round(f64_gteps, 3),
+                "sweep_ms": round(f64_sweep_ms, 4), "sweep_gbs": round(f64_gbs, 1),
+                "queries": args.fp64_queries}
+        print(f"[bench] fp64: {f64_qps:.1f} q/s, sweep {f64_sweep_ms:.3f} ms", file=sys.stderr, flush=True)
+
+    if args.calibrate_copy:
+        x = torch.empty(2 ** 28, dtype=torch.float32, device="cuda")
+        x.fill_(1.0)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+
+    traffic = measured_traffic(width)
 
     cpu = None
     if args.cpu_baseline:
@@ -181,12 +225,11 @@ def main() -> int:
         },
         "gteps": round(edges / dt / 1e9, 3),
         "max_cert_l1": max_cert,
-        "fp64_plain": {"value": round(f64_qps, 3), "unit": "queries/s", "gteps": round(f64_gteps, 3),
-                       "sweep_ms": round(f64_sweep_ms, 4), "sweep_gbs": round(f64_gbs, 1)},
-        "speedup_vs_fp64_plain": round(qps / f64_qps, 2),
+        "fp64_plain": fp64,
+        "speedup_vs_fp64_plain": round(qps / f64_qps, 2) if f64_qps else None,
         "roofline": {"bound": "hbm", "kernel": f"sweep_b<C={width // 4}>", "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "bytes_per_launch": bytes_per,
+                     "traffic": traffic, "bytes_per_launch": bytes_per,
                      "avg_launch_ms": round(avg_sweep_ms, 4)},
         "cpu_baseline": cpu,
         "graph_create_ms": round(info["build_ms"], 1),

@@ -14,9 +14,11 @@
 //     simultaneously with FP64 atomics into a dense FP64 n x B scratch;
 //  2. conversion of the FP64 state into the FP32 block (the alpha-part of the
 //     remaining residue is folded into S at the same time);
-//  3. stages of FP32 pull sweeps, y'(u) = (1-alpha)/d_u sum_{v in N_in(u)} y(v),
-//     S(u) += y'(u) (the alpha-part of the next push folded in at once, as in
-//     the FP64 path);
+//  3. stages of FP32 pull sweeps, y'(u) = (1-alpha)/d_u sum_{v in N_in(u)} y(v);
+//     the alpha-part of the next push is folded in at once (as in the FP64
+//     path) into a per-stage FP32 accumulator T(u) += y'(u), which is added
+//     into the compensated reserve (S += T, TwoSum) before each refresh, so a
+//     sweep moves 8 bytes of reserve state per (node, column) instead of 16;
 //  4. after each stage an FP64 residual refresh recomputes, from S alone, the
 //     exact residual of the current estimate (Eq. 1):
 //        rt(u) = e_s(u) - d_u S(u) / (1-alpha) + sum_{v in N_in(u)} S(v)
@@ -171,7 +173,8 @@ __global__ __launch_bounds__(kBlock) void push_b(
 // the remaining residue folded in), y = (1-alpha) r / d.
 __global__ void convert_b(int32_t n, int shift, const int32_t* __restrict__ deg, double alpha,
                           double* __restrict__ r64, double* __restrict__ pi64, float* __restrict__ Y,
-                          float* __restrict__ Shi, float* __restrict__ Slo, double* __restrict__ partials) {
+                          float* __restrict__ Shi, float* __restrict__ Slo, float* __restrict__ T,
+                          double* __restrict__ partials) {
     // partials[blockIdx][B]: per-column sum of r (thread's column is fixed: B | blockDim)
     __shared__ double sh[kBlock];
     const int B = 1 << shift;
@@ -190,6 +193,7 @@ __global__ void convert_b(int32_t n, int shift, const int32_t* __restrict__ deg,
         split_double(S, h, l);
         Shi[i] = h;
         Slo[i] = l;
+        T[i] = 0.f;
         r64[i] = 0.0;
         pi64[i] = 0.0;
         acc += r;
@@ -262,8 +266,8 @@ template <typename OffT, int C, bool ENTRY>
 __global__ __launch_bounds__(kBlock) void sweep_b(
         const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
         const RowBlock* __restrict__ blocks, int32_t n_long, const float* __restrict__ scale,
-        const float4* __restrict__ Y_in, float4* __restrict__ Y_out, float4* __restrict__ Shi,
-        float4* __restrict__ Slo, const int32_t* __restrict__ kb, const int32_t* __restrict__ step_p) {
+        const float4* __restrict__ Y_in, float4* __restrict__ Y_out, float4* __restrict__ T,
+        const int32_t* __restrict__ kb, const int32_t* __restrict__ step_p) {
     using P = Sw<C>;
     __shared__ float4 lds[kLdsBytes / 16];
     const RowBlock b = blocks[blockIdx.x];
@@ -338,25 +342,30 @@ __global__ __launch_bounds__(kBlock) void sweep_b(
     }
     if (u < 0) return;
     const int64_t at = (int64_t)u * C + c;
-    float4 hi = Shi[at], lo = Slo[at];
+    float4 t = T[at];
     const float sc = scale[u];
     const float4 m = active4(kb, step, c);
-    if (ENTRY) {
-        float4 y0 = f4_mul(Y_in[at], m);
-        comp_add(hi.x, lo.x, y0.x);
-        comp_add(hi.y, lo.y, y0.y);
-        comp_add(hi.z, lo.z, y0.z);
-        comp_add(hi.w, lo.w, y0.w);
-    }
+    if (ENTRY) t = f4_add(t, f4_mul(Y_in[at], m));
     acc = f4_mul(acc, m);
     float4 y = make_float4(sc * acc.x, sc * acc.y, sc * acc.z, sc * acc.w);
-    comp_add(hi.x, lo.x, y.x);
-    comp_add(hi.y, lo.y, y.y);
-    comp_add(hi.z, lo.z, y.z);
-    comp_add(hi.w, lo.w, y.w);
     Y_out[at] = y;
-    Shi[at] = hi;
-    Slo[at] = lo;
+    T[at] = f4_add(t, y);
+}
+
+// S += T with the compensated add, T = 0 (dense over n x B); run before each
+// refresh so that the refresh and the export see the whole reserve.
+__global__ void flush_b(int64_t total, float* __restrict__ Shi, float* __restrict__ Slo, float* __restrict__ T) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        float t = T[i];
+        if (t != 0.f) {
+            float h = Shi[i], l = Slo[i];
+            comp_add(h, l, t);
+            Shi[i] = h;
+            Slo[i] = l;
+            T[i] = 0.f;
+        }
+    }
 }
 
 __global__ void bump_step(int32_t* step) { step[0] += 1; }
@@ -565,6 +574,7 @@ struct MixedCtx {
     DevBuf F0, F1, X, degF, off;      // frontier (int64 keys), increments, degrees, prefix
     DevBuf scan_tmp;
     DevBuf Y0, Y1, Shi, Slo;          // float[n][Bw]
+    DevBuf T;                         // float[n][Bw] per-stage reserve accumulator
     DevBuf scale;                     // float[n]
     DevBuf partials;                  // double[kGridRed][Bw]
     DevBuf colsum;                    // double[Bw]
@@ -632,6 +642,7 @@ MixedCtxPtr mixed_acquire(Graph& g, int Bw, int64_t fcap) {
     c->Y1.alloc(4 * nb);
     c->Shi.alloc(4 * nb);
     c->Slo.alloc(4 * nb);
+    c->T.alloc(4 * nb);
     c->scale.alloc(4 * n);
     c->partials.alloc(8 * (size_t)mk::kGridRed * Bw);
     c->colsum.alloc(8 * (size_t)Bw);
@@ -655,7 +666,7 @@ template <typename OffT, int C, bool ENTRY>
 void launch_sweep_b3(Graph& g, MixedCtx& c, const Schedule& sch, const float4* Y4i, float4* Y4o) {
     hipLaunchKernelGGL((mk::sweep_b<OffT, C, ENTRY>), dim3((unsigned)sch.n_blocks), dim3(mk::kBlock), 0,
                        c.stream, g.col_ptr.as<OffT>(), g.row_idx.as<int32_t>(), sch.blocks.as<RowBlock>(),
-                       sch.n_long, c.scale.as<float>(), Y4i, Y4o, c.Shi.as<float4>(), c.Slo.as<float4>(),
+                       sch.n_long, c.scale.as<float>(), Y4i, Y4o, c.T.as<float4>(),
                        c.kb.as<int32_t>(), c.step.as<int32_t>());
     hipLaunchKernelGGL(mk::bump_step, dim3(1), dim3(1), 0, c.stream, c.step.as<int32_t>());
 }
@@ -677,6 +688,9 @@ void launch_sweep_b(Graph& g, MixedCtx& c, bool entry, const float* yin, float* 
 
 template <int C>
 void launch_refresh_b(Graph& g, MixedCtx& c, float* yout, double* rt_out) {
+    hipLaunchKernelGGL(mk::flush_b, dim3(2048), dim3(mk::kBlock), 0, c.stream, (int64_t)g.n * c.Bw,
+                       c.Shi.as<float>(), c.Slo.as<float>(), c.T.as<float>());
+    HIPCHECK(hipGetLastError());
     const Schedule& sch = refresh_schedule<C>(g);
     dim3 grid((unsigned)std::min(sch.n_blocks, mk::kGridRed)), blk(mk::kBlock);
     auto H = c.Shi.as<float4>();
@@ -844,7 +858,7 @@ void run_mixed_chunk(Graph& g, MixedCtx& c, const int32_t* sources, int Breal, d
         unsigned gc = 1024;
         hipLaunchKernelGGL(mk::convert_b, dim3(gc), dim3(256), 0, ss, n, c.shift, g.deg.as<int32_t>(), alpha,
                            c.r64.as<double>(), c.pi64.as<double>(), c.Y0.as<float>(), c.Shi.as<float>(),
-                           c.Slo.as<float>(), c.partials.as<double>());
+                           c.Slo.as<float>(), c.T.as<float>(), c.partials.as<double>());
         HIPCHECK(hipGetLastError());
         hipLaunchKernelGGL(mk::reduce_cols, dim3(1), dim3(256), 0, ss, c.partials.as<double>(), (int)gc, Bw,
                            c.colsum.as<double>());
@@ -1020,7 +1034,7 @@ int64_t frontier_capacity(const Graph& g, const ppr_options& opt, int Bw) {
 size_t mixed_footprint(const Graph& g, int Bw, int64_t fcap) {
     const size_t nb = (size_t)g.n * (size_t)Bw;
     return 16 * nb          // FP64 local-phase scratch
-           + 16 * nb        // Y0, Y1, Shi, Slo
+           + 20 * nb        // Y0, Y1, Shi, Slo, T
            + 40 * (size_t)fcap + 4 * (size_t)g.n + ((size_t)1 << 20);
 }
 
@@ -1062,6 +1076,7 @@ void autotune_width(Graph& g, double alpha, const int32_t* widths, int32_t count
         HIPCHECK(hipMemsetAsync(c->Y1.p, 0, 4 * nb, ss));
         HIPCHECK(hipMemsetAsync(c->Shi.p, 0, 4 * nb, ss));
         HIPCHECK(hipMemsetAsync(c->Slo.p, 0, 4 * nb, ss));
+        HIPCHECK(hipMemsetAsync(c->T.p, 0, 4 * nb, ss));
         std::vector<int32_t> kb(W, 1 << 30);
         HIPCHECK(hipMemcpyAsync(c->kb.p, kb.data(), 4 * (size_t)W, hipMemcpyHostToDevice, ss));
         HIPCHECK(hipMemsetAsync(c->step.p, 0, 4, ss));
@@ -1087,8 +1102,8 @@ void autotune_width(Graph& g, double alpha, const int32_t* widths, int32_t count
         HIPCHECK(hipStreamSynchronize(ss));
         double us = ev.elapsed_ms() * 1e3 / reps / W;
         if (cost_us) cost_us[i] = us;
-        // prefer the narrower block unless the wider one is clearly cheaper
-        if (best_w == 0 || us < best_cost * 0.97) {
+        // the narrower block wins ties (within 1%): less memory, lower latency
+        if (best_w == 0 || us < best_cost * 0.99) {
             best_cost = us;
             best_w = W;
         }
