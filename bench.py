@@ -50,7 +50,7 @@ def kernel_source_digest() -> str:
     """Digest of the batched-path source: counter readings are valid only for
     the kernel they were taken on."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2101_03652_amd", "csrc", "mixed.hip")
+    path = os.path.join(ROOT, "paper_2101_03652_amd", "csrc", "mixed_kernels.hip")
     with open(path, "rb") as f:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 

@@ -43,6 +43,7 @@ extern "C" {
 #endif
 
 typedef struct ppr_graph ppr_graph;   /* opaque, library-owned, device resident */
+typedef struct ppr_block ppr_block;   /* opaque serving block: query slots on one graph */
 typedef struct ppr_block ppr_block;   /* opaque serving block (slots of one graph) */
 
 typedef enum {
@@ -198,6 +199,61 @@ ppr_status ppr_debug_sweep_fp64(ppr_graph* g, double alpha, const double* r_in, 
  */
 ppr_status ppr_autotune(ppr_graph* g, double alpha, const int32_t* widths, int32_t count,
                         int32_t* best_width, double* cost_us);
+
+/*
+ * Serving: continuous batching of mixed-precision queries on one graph.
+ *
+ * A block holds `slots` query slots (the columns of one n x slots FP32 state
+ * in device memory).  Each slot answers one single-source query with its own
+ * source and its own lambda, by the same computation as ppr_query_ex with
+ * PPR_MIXED: a frontier local phase over the iteration sets S^(j) of
+ * Section 4.2 in FP64, global sweeps of Eq. 7 in FP32, and FP64 refreshes
+ * whose residual (Eq. 1 rearranged) certifies ||pi_hat - pi_s||_1 <= lambda.
+ * A slot's schedule depends on its own source and lambda only, so a query's
+ * result is the same whichever other queries share the block (up to FP32
+ * summation order).  Slots free up and refill while the others run.
+ *
+ * A block is used by one host thread at a time.  Blocks must be destroyed
+ * before their graph (ppr_graph_destroy returns PPR_ERR_BUSY otherwise).
+ */
+
+/* Create a block.  slots: power of two in [4, 128]; alpha in (0, 1); opt
+ * (nullable): switch rule, max_sweeps (a cap on the block's total sweeps),
+ * refresh_factor; precision is ignored.  PPR_ERR_OOM if the device memory
+ * (ppr_block_footprint) cannot be allocated. */
+ppr_status ppr_block_create(ppr_graph* g, int32_t slots, double alpha, const ppr_options* opt,
+                            ppr_block** out);
+
+/* Destroy a block (waits for its enqueued work).  NULL is a no-op. */
+ppr_status ppr_block_destroy(ppr_block* blk);
+
+/* Device bytes a block of `slots` slots allocates on this graph (for
+ * admission against a memory budget). */
+ppr_status ppr_block_footprint(const ppr_graph* g, int32_t slots, size_t* bytes);
+
+/* Put a query into a free slot; *slot receives its index.  The query starts
+ * at the next ppr_block_step.  PPR_ERR_BUSY if every slot is taken,
+ * PPR_ERR_ARG for a source outside [0, n) or lambda outside (0, 1]. */
+ppr_status ppr_slot_admit(ppr_block* blk, int32_t source, double lambda, int32_t* slot);
+
+/* Advance the block: collect the previous step's results (waiting for them),
+ * run the local phase of newly admitted slots, then enqueue up to max_sweeps
+ * (>= 1) global sweeps and the FP64 refresh of every slot whose stage ends.
+ * Returns once the work is enqueued; ppr_block_poll collects it. */
+ppr_status ppr_block_step(ppr_block* blk, int32_t max_sweeps);
+
+/* Collect the enqueued work if it has finished (wait = 1: wait for it).
+ * done: host uint8[slots] (nullable), 1 for slots holding a certified
+ * result; n_done, n_busy (admitted, not yet retired), ready (1 if nothing
+ * is in flight): nullable outputs. */
+ppr_status ppr_block_poll(ppr_block* blk, int32_t wait, uint8_t* done, int32_t* n_done,
+                          int32_t* n_busy, int32_t* ready);
+
+/* Copy a certified result out and free the slot.  pi_out: double[n], host
+ * or device memory of the graph's device.  stats (nullable): the query's
+ * statistics, ms = time from admission to retirement.  PPR_ERR_BUSY if the
+ * slot holds no certified result. */
+ppr_status ppr_slot_retire(ppr_block* blk, int32_t slot, double* pi_out, ppr_stats* stats);
 
 /* Library version string. */
 const char* ppr_version(void);

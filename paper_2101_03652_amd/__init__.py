@@ -34,6 +34,8 @@ EXPORTS = [
     "ppr_options_default", "ppr_graph_create", "ppr_graph_destroy", "ppr_graph_get_info",
     "ppr_graph_copy_csc", "ppr_query", "ppr_query_batch", "ppr_query_ex",
     "ppr_debug_sweep_fp64", "ppr_version", "ppr_last_error", "ppr_autotune",
+    "ppr_block_create", "ppr_block_destroy", "ppr_block_footprint", "ppr_slot_admit",
+    "ppr_block_step", "ppr_block_poll", "ppr_slot_retire",
 ]
 
 
@@ -93,6 +95,13 @@ def load() -> ctypes.CDLL:
         "ppr_query_ex": (st, [vp, vp, i32, f64, f64, vp, vp, vp, vp]),
         "ppr_debug_sweep_fp64": (st, [vp, f64, vp, vp, vp, vp]),
         "ppr_autotune": (st, [vp, f64, vp, i32, vp, vp]),
+        "ppr_block_create": (st, [vp, i32, f64, vp, ctypes.POINTER(vp)]),
+        "ppr_block_destroy": (st, [vp]),
+        "ppr_block_footprint": (st, [vp, i32, vp]),
+        "ppr_slot_admit": (st, [vp, i32, f64, vp]),
+        "ppr_block_step": (st, [vp, i32]),
+        "ppr_block_poll": (st, [vp, i32, vp, vp, vp, vp]),
+        "ppr_slot_retire": (st, [vp, i32, vp, vp]),
         "ppr_version": (ctypes.c_char_p, []),
         "ppr_last_error": (ctypes.c_char_p, []),
     }
@@ -220,6 +229,64 @@ class Graph:
         _check(load().ppr_debug_sweep_fp64(self._h, float(alpha), _ptr(r_in), _ptr(r_out), _ptr(pi),
                                            ctypes.byref(rs)))
         return rs.value
+
+
+class Block:
+    """A serving block: `slots` query slots on one graph (continuous batching).
+
+    admit() puts a (source, lambda) query into a free slot, step() advances
+    every running slot, poll() collects finished work, retire() copies a
+    certified result out and frees its slot for the next query."""
+
+    def __init__(self, graph: Graph, slots: int, alpha: float = 0.2, **opt):
+        self.graph = graph          # keeps the graph alive while the block exists
+        self.slots = int(slots)
+        self.alpha = float(alpha)
+        o = options(precision=MIXED, **opt)
+        h = ctypes.c_void_p()
+        _check(load().ppr_block_create(graph.handle, self.slots, self.alpha, ctypes.byref(o),
+                                       ctypes.byref(h)))
+        self._h = h
+        self._done = np.zeros(self.slots, dtype=np.uint8)
+
+    @staticmethod
+    def footprint(graph: Graph, slots: int) -> int:
+        b = ctypes.c_size_t()
+        _check(load().ppr_block_footprint(graph.handle, int(slots), ctypes.byref(b)))
+        return b.value
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            load().ppr_block_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def admit(self, source: int, lam: float) -> int:
+        slot = ctypes.c_int32(-1)
+        _check(load().ppr_slot_admit(self._h, int(source), float(lam), ctypes.byref(slot)))
+        return slot.value
+
+    def step(self, max_sweeps: int = 16) -> None:
+        _check(load().ppr_block_step(self._h, int(max_sweeps)))
+
+    def poll(self, wait: bool = False) -> dict:
+        nd, nb, rd = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(load().ppr_block_poll(self._h, 1 if wait else 0, _ptr(self._done), ctypes.byref(nd),
+                                     ctypes.byref(nb), ctypes.byref(rd)))
+        return {"done": np.flatnonzero(self._done).tolist(), "n_done": nd.value, "n_busy": nb.value,
+                "ready": bool(rd.value)}
+
+    def retire(self, slot: int, out=None):
+        if out is None:
+            out = np.empty(self.graph.n, dtype=np.float64)
+        st = Stats()
+        _check(load().ppr_slot_retire(self._h, int(slot), _ptr(out), ctypes.byref(st)))
+        return out, st.as_dict()
 
 
 def version() -> str:

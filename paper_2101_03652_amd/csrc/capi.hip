@@ -89,6 +89,10 @@ ppr_status ppr_graph_destroy(ppr_graph* gh) {
     return guarded([&] {
         Graph* g = reinterpret_cast<Graph*>(gh);
         if (!g) return;
+        {
+            std::lock_guard<std::mutex> lk(g->pool_mu);
+            if (g->live_blocks > 0) fail(PPR_ERR_BUSY, "serving blocks still use this graph");
+        }
         (void)hipSetDevice(g->device);
         (void)hipDeviceSynchronize();
         delete g;
@@ -171,6 +175,66 @@ ppr_status ppr_autotune(ppr_graph* gh, double alpha, const int32_t* widths, int3
         if (!(alpha > 0.0 && alpha < 1.0)) fail(PPR_ERR_ARG, "alpha must lie in (0, 1)");
         if (widths && count < 1) fail(PPR_ERR_ARG, "count must be >= 1");
         autotune_width(*g, alpha, widths, count, best_width, cost_us);
+    });
+}
+
+// ---------------------------------------------------------------- serving
+
+ppr_status ppr_block_create(ppr_graph* gh, int32_t slots, double alpha, const ppr_options* opt, ppr_block** out) {
+    return guarded([&] {
+        Graph* g = reinterpret_cast<Graph*>(gh);
+        if (!g || !out) fail(PPR_ERR_ARG, "NULL argument");
+        *out = nullptr;
+        if (!(alpha > 0.0 && alpha < 1.0)) fail(PPR_ERR_ARG, "alpha must lie in (0, 1)");
+        if (slots < 4 || slots > 128 || (slots & (slots - 1))) fail(PPR_ERR_ARG, "slots must be a power of two in [4, 128]");
+        ppr_options o;
+        if (opt) o = *opt; else ppr_options_default(&o);
+        o.precision = PPR_MIXED;
+        check_options(o);
+        *out = reinterpret_cast<ppr_block*>(serve_block_create(*g, slots, alpha, o));
+    });
+}
+
+ppr_status ppr_block_destroy(ppr_block* blk) {
+    return guarded([&] { serve_block_destroy(blk); });
+}
+
+ppr_status ppr_block_footprint(const ppr_graph* gh, int32_t slots, size_t* bytes) {
+    return guarded([&] {
+        const Graph* g = reinterpret_cast<const Graph*>(gh);
+        if (!g || !bytes) fail(PPR_ERR_ARG, "NULL argument");
+        if (slots < 4 || slots > 128 || (slots & (slots - 1))) fail(PPR_ERR_ARG, "slots must be a power of two in [4, 128]");
+        *bytes = serve_footprint(*g, slots);
+    });
+}
+
+ppr_status ppr_slot_admit(ppr_block* blk, int32_t source, double lambda, int32_t* slot) {
+    return guarded([&] {
+        if (!blk || !slot) fail(PPR_ERR_ARG, "NULL argument");
+        *slot = -1;
+        *slot = serve_admit(blk, source, lambda);
+    });
+}
+
+ppr_status ppr_block_step(ppr_block* blk, int32_t max_sweeps) {
+    return guarded([&] {
+        if (!blk) fail(PPR_ERR_ARG, "block is NULL");
+        serve_step(blk, max_sweeps);
+    });
+}
+
+ppr_status ppr_block_poll(ppr_block* blk, int32_t wait, uint8_t* done, int32_t* n_done, int32_t* n_busy,
+                          int32_t* ready) {
+    return guarded([&] {
+        if (!blk) fail(PPR_ERR_ARG, "block is NULL");
+        serve_poll(blk, wait, done, n_done, n_busy, ready);
+    });
+}
+
+ppr_status ppr_slot_retire(ppr_block* blk, int32_t slot, double* pi_out, ppr_stats* stats) {
+    return guarded([&] {
+        if (!blk) fail(PPR_ERR_ARG, "block is NULL");
+        serve_retire(blk, slot, pi_out, stats);
     });
 }
 

@@ -1,0 +1,90 @@
+// Internal declarations of the batched mixed-precision path (n x B block).
+#pragma once
+
+#include "ppr_internal.h"
+
+namespace ppr {
+
+namespace mk {
+constexpr int kBlock = 256;
+constexpr int kLdsBytes = 32768;   // staging budget of the sweep / refresh blocks
+constexpr int kGridRed = 2048;     // persistent grid of the refresh (fixed -> deterministic sums)
+
+// Sweep blocks: <= kNnz in-edges (B = 4C columns, C float4 chunks) and <= kRows rows.
+template <int C>
+struct Sw {
+    static constexpr int kNnz = kLdsBytes / (16 * C);
+    static constexpr int kRows = kBlock / C;
+    static constexpr int kItems = kNnz * C / kBlock;   // = 8
+    static constexpr int kSlots = kBlock / C;
+};
+// Refresh blocks gather the hi and lo reserve rows (2 x 16 C bytes per edge).
+template <int C>
+struct Rf {
+    static constexpr int kNnz = kLdsBytes / (32 * C);
+    static constexpr int kItems = kNnz * C / kBlock;   // = 4
+    static constexpr int kRows = kBlock / C;
+};
+}  // namespace mk
+
+// Device state of one block of Bw columns on one graph.
+struct MixedCtx {
+    hipStream_t stream = nullptr;
+    int32_t n = 0;
+    int Bw = 0, shift = 0;
+    double alpha = -1.0;              // alpha the scale table holds
+    int64_t fcap = 0;                 // frontier capacity (entries)
+    DevBuf r64, pi64;                 // double[n][Bw]  local-phase scratch, zero between uses
+    DevBuf F0, F1, X, degF, off;      // frontier (int64 keys), increments, degrees, prefix
+    DevBuf scan_tmp;
+    DevBuf Y0, Y1;                    // float[n][Bw]   residue still to push, y = (1-alpha) r / d
+    DevBuf Shi, Slo;                  // float[n][Bw]   compensated reserve (y domain)
+    DevBuf T;                         // float[n][Bw]   per-stage reserve accumulator
+    DevBuf scale;                     // float[n]       (1-alpha) / d_u
+    DevBuf partials;                  // double[kGridRed][Bw]
+    DevBuf colsum;                    // double[Bw]
+    DevBuf ctr;                       // tail + per-column counts + per-column volumes
+    DevBuf taken;                     // double[Bw]
+    DevBuf active;                    // uint8[Bw]  local phase: column pushes this level
+    DevBuf src;                       // int32[Bw]  source per column (-1: free)
+    DevBuf kb;                        // int32[Bw]  sweeps each column runs in this launch sequence
+    DevBuf entry;                     // int32[Bw]  1: fold the refreshed residue on the first sweep
+    DevBuf rmask;                     // int32[Bw]  1: refresh writes this column's residue
+    DevBuf cmask;                     // int32[Bw]  1: conversion writes this column
+    DevBuf rmaxb;                     // double[Bw] lambda_b / m: activity threshold per column
+    DevBuf step;                      // int32[1]   sweeps done in the current sequence
+    DevBuf stage;                     // double[Bw][n] host-output staging (lazy)
+    PinnedBuf host;                   // readback area
+    hipGraphExec_t chunk = nullptr;   // captured sweep chunk Y1 -> Y0 -> ... -> Y1
+    const float* ycur = nullptr;      // buffer holding the current residue rows
+    ~MixedCtx();
+};
+
+MixedCtxPtr mixed_acquire(Graph& g, int Bw, int64_t fcap);
+void mixed_release(Graph& g, MixedCtxPtr c);
+int64_t frontier_capacity(const Graph& g, const ppr_options& opt, int Bw);
+size_t mixed_footprint(const Graph& g, int Bw, int64_t fcap);
+
+// Launchers (mixed_kernels.hip).  All run on c.stream.
+namespace mk {
+void set_scale(Graph& g, MixedCtx& c, double alpha);
+// r64 = e_s for the columns with cmask = 1
+void init_sources(MixedCtx& c);
+void snapshot(MixedCtx& c, const Graph& g, const int64_t* F, int64_t nf, double alpha);
+// rmax per column: c.rmaxb (lambda_b / m)
+void push(MixedCtx& c, const Graph& g, const int64_t* F, int64_t nf, int64_t vol, int64_t* F_next);
+// FP64 scratch -> block for the columns with cmask = 1 (others untouched); per-column sums of r -> colsum
+void convert(MixedCtx& c, const Graph& g, double alpha);
+// build the graph's sweep and refresh schedules for this width (they allocate,
+// so this runs before any stream capture)
+void prepare(MixedCtx& c, const Graph& g);
+// one sweep Y_in -> Y_out (budgets kb, entry flags, device step counter), then step += 1
+void sweep(MixedCtx& c, const Graph& g, const float* y_in, float* y_out);
+// S += T, T = 0; then for columns with rmask = 1 write y~ into `y` (in place);
+// per-column sums of |rt| (all columns) -> colsum; rt_out (nullable): column-major FP64 residual
+void refresh(MixedCtx& c, const Graph& g, float* y, double* rt_out);
+void export_cols(MixedCtx& c, const Graph& g, int b0, int count, double* out);   // out[count][n]
+void export_col(MixedCtx& c, const Graph& g, int b, double* out);                // out[n]
+}  // namespace mk
+
+}  // namespace ppr

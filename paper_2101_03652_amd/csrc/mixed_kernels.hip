@@ -1,0 +1,685 @@
+// Kernels of the batched mixed-precision path: B sources as the columns of an
+// n x B block.
+//
+// State (node-major: the B values of one node are contiguous, so one edge's
+// gather reads one contiguous B*4-byte row):
+//   Y[n][B]         FP32, y = (1 - alpha) r / d_u: the residue still to push
+//   Shi, Slo[n][B]  FP32 pair, S = Shi + Slo kept with TwoSum (Knuth): the
+//                   compensated reserve in the y domain, pi_hat(u) = alpha d_u S(u) / (1 - alpha)
+//   T[n][B]         FP32 per-stage accumulator of reserve increments
+//
+// Columns are independent: each one is a query with its own source, its own
+// lambda and its own schedule.
+//  - local phase (FP64): the iteration sets S^(j) of Section 4.2 pushed
+//    simultaneously, one frontier list of (node << log2 B | column) keys, FP64
+//    atomics into a dense FP64 scratch; then conversion into the block (the
+//    alpha-part of the remaining residue folded into S at once);
+//  - sweeps (FP32): y'(u) = (1-alpha)/d_u sum_{v in N_in(u)} y(v) (Eq. 7 in the
+//    y domain); the alpha-part of the new residue goes into T at once.  Per
+//    column a budget kb[b]: the column runs sweeps while step < kb[b], then
+//    gets y' = 0 (its pending residue is dropped: the next refresh recomputes
+//    the exact residual from S) and its reserve stops changing;
+//  - refresh (FP64): S += T, then from S alone the exact residual of the
+//    current estimate (Eq. 1 rearranged)
+//        rt(u) = e_s(u) - d_u S(u) / (1 - alpha) + sum_{v in N_in(u)} S(v),
+//    whose l1 norm certifies ||pi_hat - pi_s||_1 <= ||rt||_1; for the columns
+//    being refreshed y~ = (1-alpha) rt / d replaces the drifting FP32 residue,
+//    and the first sweep after that folds its alpha-part into T (entry flag).
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "mixed_internal.h"
+
+namespace ppr {
+namespace mk {
+
+namespace {
+
+// ---------------------------------------------------------------- helpers
+// Knuth's TwoSum: s + e == a + b exactly.
+__device__ inline void two_sum(float a, float b, float& s, float& e) {
+    s = a + b;
+    float bp = s - a;
+    float ap = s - bp;
+    e = (a - ap) + (b - bp);
+}
+
+// (hi, lo) += y, compensated: the rounding error of hi + y is carried in lo
+// and the pair is renormalised (Fast2Sum) so that |lo| <= ulp(hi) / 2.
+__device__ inline void comp_add(float& hi, float& lo, float y) {
+    float s, e;
+    two_sum(hi, y, s, e);
+    float t = lo + e;
+    float h = s + t;
+    lo = t - (h - s);
+    hi = h;
+}
+
+__device__ inline void split_double(double x, float& hi, float& lo) {
+    hi = (float)x;
+    lo = (float)(x - (double)hi);
+}
+
+__device__ inline float4 f4_add(float4 a, float4 b) { return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w); }
+__device__ inline float4 f4_mul(float4 a, float4 m) { return make_float4(a.x * m.x, a.y * m.y, a.z * m.z, a.w * m.w); }
+__device__ inline float4 f4_shfl_xor(float4 a, int o) {
+    return make_float4(__shfl_xor(a.x, o, 64), __shfl_xor(a.y, o, 64), __shfl_xor(a.z, o, 64), __shfl_xor(a.w, o, 64));
+}
+__device__ inline float4 flag4(int4 f) {
+    return make_float4(f.x ? 1.f : 0.f, f.y ? 1.f : 0.f, f.z ? 1.f : 0.f, f.w ? 1.f : 0.f);
+}
+
+// ---------------------------------------------------------------- local phase
+__global__ void init_sources_k(const int32_t* __restrict__ src, const int32_t* __restrict__ cmask, int32_t Bw,
+                               int shift, double* __restrict__ r64) {
+    int b = threadIdx.x;
+    if (b < Bw && cmask[b]) {
+        int32_t s = src[b];
+        if (s >= 0) r64[((int64_t)s << shift) + b] = 1.0;
+    }
+}
+
+// Frontier entry i: key = (node << shift) | column.  Columns whose local
+// phase is over (active[b] == 0) are skipped; their residue stays in place.
+__global__ void snapshot_k(const int64_t* __restrict__ F, int64_t nf, int shift,
+                           const uint8_t* __restrict__ active, const int32_t* __restrict__ deg, double alpha,
+                           double* __restrict__ r64, double* __restrict__ pi64, double* __restrict__ X,
+                           int64_t* __restrict__ degF, double* __restrict__ taken) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nf) return;
+    int64_t key = F[i];
+    int32_t b = (int32_t)(key & ((1 << shift) - 1));
+    int32_t v = (int32_t)(key >> shift);
+    if (!active[b]) {
+        X[i] = 0.0;
+        degF[i] = 0;
+        return;
+    }
+    double x = atomicExch(&r64[key], 0.0);      // a key listed twice would push once
+    pi64[key] += alpha * x;
+    atomicAdd(&taken[b], alpha * x);
+    int32_t d = deg[v];
+    X[i] = ((1.0 - alpha) * x) / (double)d;
+    degF[i] = d;
+}
+
+// First index i with a[i] <= key < a[i+1] (a ascending, a[0] = 0 <= key < a[len]).
+__device__ inline int64_t find_owner64(const int64_t* __restrict__ a, int64_t len, int64_t key) {
+    int64_t lo = 0, hi = len;
+    while (hi - lo > 1) {
+        int64_t mid = lo + ((hi - lo) >> 1);
+        if (a[mid] <= key) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// Edge slot t of the frontier's out-edges: r(u) += X (FP64 atomic).  Residues
+// only grow here, so exactly one add carries r(u) across d_u * rmax; that
+// lane appends (u, column) to the next frontier (ballot, one atomic per wave).
+__global__ __launch_bounds__(kBlock) void push_k(
+        const int64_t* __restrict__ F, const int64_t* __restrict__ off, int64_t nf, int64_t vol, int shift,
+        const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const int32_t* __restrict__ deg,
+        const double* __restrict__ X, const double* __restrict__ rmaxb, double* __restrict__ r64,
+        int64_t* __restrict__ F_next,
+        int64_t cap, unsigned long long* __restrict__ tail, unsigned long long* __restrict__ cnt_b,
+        unsigned long long* __restrict__ vol_b) {
+    const int lane = threadIdx.x & 63;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (off[nf] < vol) vol = off[nf];
+    for (int64_t wb = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); wb < vol; wb += stride) {
+        int64_t t = wb + lane;
+        bool crossed = false;
+        int64_t tkey = 0;
+        if (t < vol) {
+            int64_t i = find_owner64(off, nf, t);
+            int64_t key = F[i];
+            int32_t b = (int32_t)(key & ((1 << shift) - 1));
+            int32_t v = (int32_t)(key >> shift);
+            int64_t e = row_ptr[v] + (t - off[i]);
+            int32_t u = col[e];
+            tkey = ((int64_t)u << shift) + b;
+            double x = X[i];
+            double old = atomicAdd(&r64[tkey], x);
+            double now = old + x;
+            int32_t du = deg[u];
+            double thr = (double)du * rmaxb[b];     // rmax = lambda_b / m of this column
+            crossed = (old <= thr) && (now > thr);
+            if (crossed) {
+                atomicAdd(&cnt_b[b], 1ull);
+                atomicAdd(&vol_b[b], (unsigned long long)du);
+            }
+        }
+        uint64_t mask = __ballot(crossed);
+        if (mask) {
+            int leader = __ffsll((unsigned long long)mask) - 1;
+            unsigned long long base = 0;
+            if (lane == leader) base = atomicAdd(tail, (unsigned long long)__popcll(mask));
+            base = __shfl(base, leader, 64);
+            unsigned int below = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+            // the host sizes F_next for the worst case; the guard keeps a
+            // violation of that bound from writing out of bounds (the host
+            // then sees tail > cap and fails the call)
+            if (crossed && (int64_t)(base + below) < cap) F_next[base + below] = tkey;
+        }
+    }
+}
+
+// FP64 scratch -> FP32 block for the columns with cmask = 1, dense over
+// (u, b): y = (1-alpha) r / d, S = (1-alpha) pi / (alpha d) + y (the
+// alpha-part of the remaining residue folded in), T = 0; the scratch of those
+// columns is cleared.  partials[block][B]: per-column sums of r.
+__global__ void convert_k(int32_t n, int shift, const int32_t* __restrict__ deg, double alpha,
+                          const int32_t* __restrict__ cmask, double* __restrict__ r64, double* __restrict__ pi64,
+                          float* __restrict__ Y, float* __restrict__ Shi, float* __restrict__ Slo,
+                          float* __restrict__ T, double* __restrict__ partials) {
+    __shared__ double sh[kBlock];
+    __shared__ int32_t cm[128];
+    const int B = 1 << shift;
+    if (threadIdx.x < B) cm[threadIdx.x] = cmask[threadIdx.x];
+    __syncthreads();
+    const int64_t total = (int64_t)n << shift;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;     // a multiple of B
+    const int b = threadIdx.x & (B - 1);                          // this thread's column, fixed
+    double acc = 0.0;
+    if (cm[b]) {
+        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+            double r = r64[i];
+            double p = pi64[i];
+            int32_t u = (int32_t)(i >> shift);
+            double d = (double)deg[u];
+            double y = ((1.0 - alpha) * r) / d;
+            double S = ((1.0 - alpha) * p) / (alpha * d) + y;
+            Y[i] = (float)y;
+            float h, l;
+            split_double(S, h, l);
+            Shi[i] = h;
+            Slo[i] = l;
+            T[i] = 0.f;
+            r64[i] = 0.0;
+            pi64[i] = 0.0;
+            acc += r;
+        }
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x < B) {
+        double t = 0.0;
+        for (int j = threadIdx.x; j < kBlock; j += B) t += sh[j];
+        partials[(int64_t)blockIdx.x * B + threadIdx.x] = t;
+    }
+}
+
+__global__ void reduce_cols_k(const double* __restrict__ partials, int nparts, int B, double* __restrict__ out) {
+    int b = blockIdx.x * blockDim.x + threadIdx.x;      // one thread per column, fixed order
+    if (b >= B) return;
+    double t = 0.0;
+    for (int i = 0; i < nparts; ++i) t += partials[(int64_t)i * B + b];
+    out[b] = t;
+}
+
+__global__ void scale_k(const int32_t* __restrict__ deg, int32_t n, double alpha, float* __restrict__ scale) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        scale[i] = (float)((1.0 - alpha) / (double)deg[i]);
+}
+
+// ---------------------------------------------------------------- sweep
+// Schedule blocks: <= Sw<C>::kNnz in-edges and <= Sw<C>::kRows rows, or one
+// long row.  All loads that do not depend on gathered data (row bounds,
+// indices) are issued first; every thread then has kItems float4 gathers in
+// flight, staged in LDS; T threads per (row, chunk) add the row's slice.
+// Long rows: 256 / C slots stride the row's edges, summed in a fixed order.
+template <typename OffT, int C>
+__global__ __launch_bounds__(kBlock) void sweep_k(
+        const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
+        const RowBlock* __restrict__ blocks, int32_t n_long, const float* __restrict__ scale,
+        const float4* __restrict__ Y_in, float4* __restrict__ Y_out, float4* __restrict__ T,
+        const int32_t* __restrict__ kb, const int32_t* __restrict__ entry, const int32_t* __restrict__ step_p) {
+    using P = Sw<C>;
+    __shared__ float4 lds[kLdsBytes / 16];
+    const RowBlock b = blocks[blockIdx.x];
+    const int32_t step = *step_p;
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    int32_t u = -1;
+    int c = 0;
+    if ((int32_t)blockIdx.x < n_long) {
+        const int slot = threadIdx.x / C;
+        c = threadIdx.x % C;
+        const int64_t e0 = b.e0, e1 = b.e0 + b.ne;
+        float4 a0 = acc, a1 = acc, a2 = acc, a3 = acc;
+        int64_t e = e0 + slot;
+        for (; e + 3 * P::kSlots < e1; e += 4 * P::kSlots) {
+            int32_t v0 = row_idx[e], v1 = row_idx[e + P::kSlots], v2 = row_idx[e + 2 * P::kSlots],
+                    v3 = row_idx[e + 3 * P::kSlots];
+            float4 g0 = Y_in[(int64_t)v0 * C + c], g1 = Y_in[(int64_t)v1 * C + c];
+            float4 g2 = Y_in[(int64_t)v2 * C + c], g3 = Y_in[(int64_t)v3 * C + c];
+            a0 = f4_add(a0, g0);
+            a1 = f4_add(a1, g1);
+            a2 = f4_add(a2, g2);
+            a3 = f4_add(a3, g3);
+        }
+        for (; e < e1; e += P::kSlots) a0 = f4_add(a0, Y_in[(int64_t)row_idx[e] * C + c]);
+        lds[threadIdx.x] = f4_add(f4_add(a0, a1), f4_add(a2, a3));
+        __syncthreads();
+        if (threadIdx.x < C) {
+            float4 t = lds[threadIdx.x];
+            for (int s2 = 1; s2 < P::kSlots; ++s2) t = f4_add(t, lds[s2 * C + threadIdx.x]);
+            acc = t;
+            u = b.r0;
+        }
+    } else {
+        const int32_t r0 = b.r0;
+        const int32_t R = b.r1 - r0;
+        const int32_t ne = b.ne;
+        const int64_t e0 = b.e0;
+        int T2 = 64 / C < 1 ? 1 : 64 / C;               // (row, chunk) groups stay inside a wave
+        while (T2 > 1 && T2 * R * C > kBlock) T2 >>= 1;
+        const int32_t grp = threadIdx.x / T2;
+        const int sub = threadIdx.x % T2;
+        const int32_t row = grp / C;
+        c = grp % C;
+        int32_t s0 = 0, s1 = 0;
+        if (row < R) {
+            s0 = (int32_t)((int64_t)col_ptr[r0 + row] - e0);
+            s1 = (int32_t)((int64_t)col_ptr[r0 + row + 1] - e0);
+        }
+        int32_t vv[P::kItems];
+#pragma unroll
+        for (int k = 0; k < P::kItems; ++k) {
+            int32_t it = threadIdx.x + k * kBlock;
+            vv[k] = (it / C < ne) ? row_idx[e0 + it / C] : -1;
+        }
+        float4 gv[P::kItems];
+#pragma unroll
+        for (int k = 0; k < P::kItems; ++k) {
+            int32_t it = threadIdx.x + k * kBlock;
+            gv[k] = (vv[k] >= 0) ? Y_in[(int64_t)vv[k] * C + (it % C)] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int k = 0; k < P::kItems; ++k) {
+            int32_t it = threadIdx.x + k * kBlock;
+            if (it / C < ne) lds[it] = gv[k];
+        }
+        __syncthreads();
+        for (int32_t e = s0 + sub; e < s1; e += T2) acc = f4_add(acc, lds[e * C + c]);
+        for (int o = T2 >> 1; o >= 1; o >>= 1) acc = f4_add(acc, f4_shfl_xor(acc, o));
+        if (row < R && sub == 0) u = r0 + row;
+    }
+    if (u < 0) return;
+    const int64_t at = (int64_t)u * C + c;
+    float4 t = T[at];
+    const float sc = scale[u];
+    const int4 kb4 = reinterpret_cast<const int4*>(kb)[c];
+    const float4 m = make_float4(step < kb4.x ? 1.f : 0.f, step < kb4.y ? 1.f : 0.f, step < kb4.z ? 1.f : 0.f,
+                                 step < kb4.w ? 1.f : 0.f);
+    if (step == 0) {
+        const float4 en = flag4(reinterpret_cast<const int4*>(entry)[c]);
+        if (en.x + en.y + en.z + en.w != 0.f) t = f4_add(t, f4_mul(f4_mul(Y_in[at], en), m));
+    }
+    acc = f4_mul(acc, m);
+    float4 y = make_float4(sc * acc.x, sc * acc.y, sc * acc.z, sc * acc.w);
+    Y_out[at] = y;
+    T[at] = f4_add(t, y);
+}
+
+__global__ void bump_step_k(int32_t* step) { step[0] += 1; }
+
+// S += T (compensated), T = 0, dense over n x B.
+__global__ void flush_k(int64_t total, float* __restrict__ Shi, float* __restrict__ Slo, float* __restrict__ T) {
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+        float t = T[i];
+        if (t != 0.f) {
+            float h = Shi[i], l = Slo[i];
+            comp_add(h, l, t);
+            Shi[i] = h;
+            Slo[i] = l;
+            T[i] = 0.f;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- refresh (FP64)
+// Persistent grid: block k handles schedule blocks k, k + G, ...; thread t
+// always works on chunk t % C (one thread per (row, chunk), rows <= 256 / C),
+// so the per-column sums of |rt| are fixed-order and deterministic.
+template <typename OffT, int C>
+__global__ __launch_bounds__(kBlock) void refresh_k(
+        const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
+        const RowBlock* __restrict__ blocks, int32_t n_blocks, int32_t n_long,
+        const int32_t* __restrict__ deg, const float4* __restrict__ Shi, const float4* __restrict__ Slo,
+        const int32_t* __restrict__ src, const int32_t* __restrict__ rmask, double alpha,
+        float4* __restrict__ Y, double* __restrict__ rt_out, int32_t n, double* __restrict__ partials) {
+    using P = Rf<C>;
+    __shared__ float4 lds_h[P::kNnz * C];
+    __shared__ float4 lds_l[P::kNnz * C];
+    __shared__ double red[kBlock * 4];
+    const int c = threadIdx.x % C;
+    const int32_t myrow = threadIdx.x / C;
+    double cs0 = 0.0, cs1 = 0.0, cs2 = 0.0, cs3 = 0.0;   // |rt| of columns 4c..4c+3
+    const double inv_oma = 1.0 / (1.0 - alpha);
+    const double oma = 1.0 - alpha;
+    const int4 s4 = reinterpret_cast<const int4*>(src)[c];
+    const int4 w4 = reinterpret_cast<const int4*>(rmask)[c];
+    const bool write_any = (w4.x | w4.y | w4.z | w4.w) != 0;
+    for (int32_t bi = blockIdx.x; bi < n_blocks; bi += gridDim.x) {
+        const RowBlock b = blocks[bi];
+        int32_t u = -1;
+        double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
+        if (bi < n_long) {
+            const int slot = threadIdx.x / C;
+            const int64_t e0 = b.e0, e1 = b.e0 + b.ne;
+            for (int64_t e = e0 + slot; e < e1; e += kBlock / C) {
+                int64_t v = row_idx[e];
+                float4 h = Shi[v * C + c], l = Slo[v * C + c];
+                g0 += (double)h.x + (double)l.x;
+                g1 += (double)h.y + (double)l.y;
+                g2 += (double)h.z + (double)l.z;
+                g3 += (double)h.w + (double)l.w;
+            }
+            red[threadIdx.x * 4 + 0] = g0;
+            red[threadIdx.x * 4 + 1] = g1;
+            red[threadIdx.x * 4 + 2] = g2;
+            red[threadIdx.x * 4 + 3] = g3;
+            __syncthreads();
+            if (threadIdx.x < C) {
+                g0 = g1 = g2 = g3 = 0.0;
+                for (int s2 = 0; s2 < kBlock / C; ++s2) {
+                    int t = s2 * C + threadIdx.x;
+                    g0 += red[t * 4 + 0];
+                    g1 += red[t * 4 + 1];
+                    g2 += red[t * 4 + 2];
+                    g3 += red[t * 4 + 3];
+                }
+                u = b.r0;
+            }
+            __syncthreads();
+        } else {
+            const int32_t r0 = b.r0, r1 = b.r1;
+            const int64_t e0 = b.e0;
+            const int32_t ne = b.ne;
+            int32_t s0 = 0, s1 = 0;
+            const bool has = myrow < r1 - r0;
+            if (has) {
+                s0 = (int32_t)((int64_t)col_ptr[r0 + myrow] - e0);
+                s1 = (int32_t)((int64_t)col_ptr[r0 + myrow + 1] - e0);
+            }
+            int32_t vv[P::kItems];
+#pragma unroll
+            for (int k = 0; k < P::kItems; ++k) {
+                int32_t it = threadIdx.x + k * kBlock;
+                vv[k] = (it / C < ne) ? row_idx[e0 + it / C] : -1;
+            }
+            float4 hv[P::kItems], lv[P::kItems];
+#pragma unroll
+            for (int k = 0; k < P::kItems; ++k) {
+                int32_t it = threadIdx.x + k * kBlock;
+                if (vv[k] >= 0) {
+                    hv[k] = Shi[(int64_t)vv[k] * C + (it % C)];
+                    lv[k] = Slo[(int64_t)vv[k] * C + (it % C)];
+                } else {
+                    hv[k] = lv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < P::kItems; ++k) {
+                int32_t it = threadIdx.x + k * kBlock;
+                if (it / C < ne) {
+                    lds_h[it] = hv[k];
+                    lds_l[it] = lv[k];
+                }
+            }
+            __syncthreads();
+            for (int32_t e = s0; e < s1; ++e) {
+                float4 h = lds_h[e * C + c], l = lds_l[e * C + c];
+                g0 += (double)h.x + (double)l.x;
+                g1 += (double)h.y + (double)l.y;
+                g2 += (double)h.z + (double)l.z;
+                g3 += (double)h.w + (double)l.w;
+            }
+            if (has) u = r0 + myrow;
+            __syncthreads();
+        }
+        if (u >= 0) {
+            const int64_t at = (int64_t)u * C + c;
+            const double d = (double)deg[u];
+            float4 h = Shi[at], l = Slo[at];
+            double S0 = (double)h.x + (double)l.x, S1 = (double)h.y + (double)l.y;
+            double S2 = (double)h.z + (double)l.z, S3 = (double)h.w + (double)l.w;
+            double t0 = (s4.x == u ? 1.0 : 0.0) - d * S0 * inv_oma + g0;
+            double t1 = (s4.y == u ? 1.0 : 0.0) - d * S1 * inv_oma + g1;
+            double t2 = (s4.z == u ? 1.0 : 0.0) - d * S2 * inv_oma + g2;
+            double t3 = (s4.w == u ? 1.0 : 0.0) - d * S3 * inv_oma + g3;
+            cs0 += fabs(t0);
+            cs1 += fabs(t1);
+            cs2 += fabs(t2);
+            cs3 += fabs(t3);
+            if (write_any) {
+                float4 y = Y[at];
+                if (w4.x) y.x = (float)(oma * t0 / d);
+                if (w4.y) y.y = (float)(oma * t1 / d);
+                if (w4.z) y.z = (float)(oma * t2 / d);
+                if (w4.w) y.w = (float)(oma * t3 / d);
+                Y[at] = y;
+            }
+            if (rt_out) {   // column-major FP64 residual [B][n]
+                rt_out[(int64_t)(4 * c + 0) * n + u] = t0;
+                rt_out[(int64_t)(4 * c + 1) * n + u] = t1;
+                rt_out[(int64_t)(4 * c + 2) * n + u] = t2;
+                rt_out[(int64_t)(4 * c + 3) * n + u] = t3;
+            }
+        }
+    }
+    // per-column sums: threads with the same chunk hold columns 4c..4c+3
+    red[threadIdx.x * 4 + 0] = cs0;
+    red[threadIdx.x * 4 + 1] = cs1;
+    red[threadIdx.x * 4 + 2] = cs2;
+    red[threadIdx.x * 4 + 3] = cs3;
+    __syncthreads();
+    if (threadIdx.x < C) {
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        for (int t = threadIdx.x; t < kBlock; t += C) {
+            a0 += red[t * 4 + 0];
+            a1 += red[t * 4 + 1];
+            a2 += red[t * 4 + 2];
+            a3 += red[t * 4 + 3];
+        }
+        double* out = partials + (int64_t)blockIdx.x * (4 * C) + 4 * threadIdx.x;
+        out[0] = a0;
+        out[1] = a1;
+        out[2] = a2;
+        out[3] = a3;
+    }
+}
+
+// ---------------------------------------------------------------- export
+// pi_hat(u, b) = alpha d_u (Shi + Slo) / (1 - alpha) for columns [b0, b0 +
+// count), written row-major [count][n] through an LDS transpose of
+// kNodes nodes x B columns.
+template <int C>
+struct Ex {
+    static constexpr int kNodes = (4 * C >= 128) ? 32 : 64;
+};
+
+template <int C>
+__global__ __launch_bounds__(kBlock) void export_k(int32_t n, int32_t b0, int32_t count,
+                                                   const int32_t* __restrict__ deg, double alpha,
+                                                   const float* __restrict__ Shi, const float* __restrict__ Slo,
+                                                   double* __restrict__ out) {
+    constexpr int B = 4 * C;
+    constexpr int kNodes = Ex<C>::kNodes;
+    __shared__ double tile[kNodes * (B + 1)];
+    const int64_t u0 = (int64_t)blockIdx.x * kNodes;
+    const double f = alpha / (1.0 - alpha);
+    for (int i = threadIdx.x; i < kNodes * B; i += kBlock) {
+        int du = i / B, b = i % B;
+        int64_t u = u0 + du;
+        double v = 0.0;
+        if (u < n) v = f * (double)deg[u] * ((double)Shi[u * B + b] + (double)Slo[u * B + b]);
+        tile[du * (B + 1) + b] = v;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kNodes * B; i += kBlock) {
+        int b = i / kNodes, du = i % kNodes;
+        int64_t u = u0 + du;
+        if (b >= b0 && b < b0 + count && u < n) out[(int64_t)(b - b0) * n + u] = tile[du * (B + 1) + b];
+    }
+}
+
+__global__ void export_col_k(int32_t n, int shift, int32_t b, const int32_t* __restrict__ deg, double alpha,
+                             const float* __restrict__ Shi, const float* __restrict__ Slo, double* __restrict__ out) {
+    const double f = alpha / (1.0 - alpha);
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
+        int64_t i = (u << shift) + b;
+        out[u] = f * (double)deg[u] * ((double)Shi[i] + (double)Slo[i]);
+    }
+}
+
+// ---------------------------------------------------------------- launch helpers
+template <int C>
+const Schedule& sweep_schedule(Graph& g) { return g.schedule(Sw<C>::kNnz, Sw<C>::kRows); }
+template <int C>
+const Schedule& refresh_schedule(Graph& g) { return g.schedule(Rf<C>::kNnz, Rf<C>::kRows); }
+
+template <int C>
+void sweep_c(MixedCtx& c, Graph& g, const float* yin, float* yout) {
+    const Schedule& sch = sweep_schedule<C>(g);
+    auto Y4i = reinterpret_cast<const float4*>(yin);
+    auto Y4o = reinterpret_cast<float4*>(yout);
+    dim3 grid((unsigned)sch.n_blocks), blk(kBlock);
+    if (g.off64)
+        hipLaunchKernelGGL((sweep_k<int64_t, C>), grid, blk, 0, c.stream, g.col_ptr.as<int64_t>(),
+                           g.row_idx.as<int32_t>(), sch.blocks.as<RowBlock>(), sch.n_long, c.scale.as<float>(), Y4i,
+                           Y4o, c.T.as<float4>(), c.kb.as<int32_t>(), c.entry.as<int32_t>(), c.step.as<int32_t>());
+    else
+        hipLaunchKernelGGL((sweep_k<uint32_t, C>), grid, blk, 0, c.stream, g.col_ptr.as<uint32_t>(),
+                           g.row_idx.as<int32_t>(), sch.blocks.as<RowBlock>(), sch.n_long, c.scale.as<float>(), Y4i,
+                           Y4o, c.T.as<float4>(), c.kb.as<int32_t>(), c.entry.as<int32_t>(), c.step.as<int32_t>());
+    hipLaunchKernelGGL(bump_step_k, dim3(1), dim3(1), 0, c.stream, c.step.as<int32_t>());
+    HIPCHECK(hipGetLastError());
+}
+
+template <int C>
+void refresh_c(MixedCtx& c, Graph& g, float* y, double* rt_out) {
+    hipLaunchKernelGGL(flush_k, dim3(2048), dim3(kBlock), 0, c.stream, (int64_t)g.n * c.Bw, c.Shi.as<float>(),
+                       c.Slo.as<float>(), c.T.as<float>());
+    const Schedule& sch = refresh_schedule<C>(g);
+    dim3 grid((unsigned)std::min(sch.n_blocks, kGridRed)), blk(kBlock);
+    auto H = c.Shi.as<float4>();
+    auto L = c.Slo.as<float4>();
+    auto Y4 = reinterpret_cast<float4*>(y);
+    if (g.off64)
+        hipLaunchKernelGGL((refresh_k<int64_t, C>), grid, blk, 0, c.stream, g.col_ptr.as<int64_t>(),
+                           g.row_idx.as<int32_t>(), sch.blocks.as<RowBlock>(), sch.n_blocks, sch.n_long,
+                           g.deg.as<int32_t>(), H, L, c.src.as<int32_t>(), c.rmask.as<int32_t>(), c.alpha, Y4,
+                           rt_out, g.n, c.partials.as<double>());
+    else
+        hipLaunchKernelGGL((refresh_k<uint32_t, C>), grid, blk, 0, c.stream, g.col_ptr.as<uint32_t>(),
+                           g.row_idx.as<int32_t>(), sch.blocks.as<RowBlock>(), sch.n_blocks, sch.n_long,
+                           g.deg.as<int32_t>(), H, L, c.src.as<int32_t>(), c.rmask.as<int32_t>(), c.alpha, Y4,
+                           rt_out, g.n, c.partials.as<double>());
+    hipLaunchKernelGGL(reduce_cols_k, dim3(1), dim3(256), 0, c.stream, c.partials.as<double>(), (int)grid.x, c.Bw,
+                       c.colsum.as<double>());
+    HIPCHECK(hipGetLastError());
+}
+
+template <int C>
+void export_c(MixedCtx& c, Graph& g, int b0, int count, double* out) {
+    constexpr int kNodes = Ex<C>::kNodes;
+    unsigned grid = (unsigned)((g.n + kNodes - 1) / kNodes);
+    hipLaunchKernelGGL((export_k<C>), dim3(grid), dim3(kBlock), 0, c.stream, g.n, b0, count, g.deg.as<int32_t>(),
+                       c.alpha, c.Shi.as<float>(), c.Slo.as<float>(), out);
+    HIPCHECK(hipGetLastError());
+}
+
+template <class F>
+void by_width(int Bw, F&& f) {
+    switch (Bw) {
+        case 4: f(std::integral_constant<int, 1>()); break;
+        case 8: f(std::integral_constant<int, 2>()); break;
+        case 16: f(std::integral_constant<int, 4>()); break;
+        case 32: f(std::integral_constant<int, 8>()); break;
+        case 64: f(std::integral_constant<int, 16>()); break;
+        case 128: f(std::integral_constant<int, 32>()); break;
+        default: fail(PPR_ERR_ARG, "block width must be a power of two in [4, 128]");
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+void set_scale(Graph& g, MixedCtx& c, double alpha) {
+    hipLaunchKernelGGL(scale_k, dim3(1024), dim3(kBlock), 0, c.stream, g.deg.as<int32_t>(), g.n, alpha,
+                       c.scale.as<float>());
+    HIPCHECK(hipGetLastError());
+}
+
+void init_sources(MixedCtx& c) {
+    hipLaunchKernelGGL(init_sources_k, dim3(1), dim3(128), 0, c.stream, c.src.as<int32_t>(), c.cmask.as<int32_t>(),
+                       c.Bw, c.shift, c.r64.as<double>());
+    HIPCHECK(hipGetLastError());
+}
+
+void snapshot(MixedCtx& c, const Graph& g, const int64_t* F, int64_t nf, double alpha) {
+    unsigned gs = (unsigned)((nf + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(snapshot_k, dim3(gs), dim3(kBlock), 0, c.stream, F, nf, c.shift, c.active.as<uint8_t>(),
+                       g.deg.as<int32_t>(), alpha, c.r64.as<double>(), c.pi64.as<double>(), c.X.as<double>(),
+                       c.degF.as<int64_t>(), c.taken.as<double>());
+    HIPCHECK(hipGetLastError());
+}
+
+void push(MixedCtx& c, const Graph& g, const int64_t* F, int64_t nf, int64_t vol, int64_t* F_next) {
+    if (vol <= 0) return;
+    unsigned gp = (unsigned)std::min<int64_t>((vol + kBlock - 1) / kBlock, 16384);
+    auto* ctr = reinterpret_cast<unsigned long long*>(c.ctr.p);
+    hipLaunchKernelGGL(push_k, dim3(gp), dim3(kBlock), 0, c.stream, F, c.off.as<int64_t>(), nf, vol, c.shift,
+                       g.row_ptr.as<int64_t>(), g.col.as<int32_t>(), g.deg.as<int32_t>(), c.X.as<double>(),
+                       c.rmaxb.as<double>(), c.r64.as<double>(), F_next, c.fcap, ctr, ctr + 1, ctr + 1 + c.Bw);
+    HIPCHECK(hipGetLastError());
+}
+
+void convert(MixedCtx& c, const Graph& g, double alpha) {
+    const unsigned gc = 1024;
+    hipLaunchKernelGGL(convert_k, dim3(gc), dim3(kBlock), 0, c.stream, g.n, c.shift, g.deg.as<int32_t>(), alpha,
+                       c.cmask.as<int32_t>(), c.r64.as<double>(), c.pi64.as<double>(),
+                       const_cast<float*>(c.ycur), c.Shi.as<float>(), c.Slo.as<float>(), c.T.as<float>(),
+                       c.partials.as<double>());
+    hipLaunchKernelGGL(reduce_cols_k, dim3(1), dim3(256), 0, c.stream, c.partials.as<double>(), (int)gc, c.Bw,
+                       c.colsum.as<double>());
+    HIPCHECK(hipGetLastError());
+}
+
+void prepare(MixedCtx& c, const Graph& g) {
+    Graph& gg = const_cast<Graph&>(g);
+    by_width(c.Bw, [&](auto cc) {
+        (void)sweep_schedule<decltype(cc)::value>(gg);
+        (void)refresh_schedule<decltype(cc)::value>(gg);
+    });
+}
+
+void sweep(MixedCtx& c, const Graph& g, const float* y_in, float* y_out) {
+    Graph& gg = const_cast<Graph&>(g);
+    by_width(c.Bw, [&](auto cc) { sweep_c<decltype(cc)::value>(c, gg, y_in, y_out); });
+}
+
+void refresh(MixedCtx& c, const Graph& g, float* y, double* rt_out) {
+    Graph& gg = const_cast<Graph&>(g);
+    by_width(c.Bw, [&](auto cc) { refresh_c<decltype(cc)::value>(c, gg, y, rt_out); });
+}
+
+void export_cols(MixedCtx& c, const Graph& g, int b0, int count, double* out) {
+    Graph& gg = const_cast<Graph&>(g);
+    by_width(c.Bw, [&](auto cc) { export_c<decltype(cc)::value>(c, gg, b0, count, out); });
+}
+
+void export_col(MixedCtx& c, const Graph& g, int b, double* out) {
+    hipLaunchKernelGGL(export_col_k, dim3(2048), dim3(kBlock), 0, c.stream, g.n, c.shift, b, g.deg.as<int32_t>(),
+                       c.alpha, c.Shi.as<float>(), c.Slo.as<float>(), out);
+    HIPCHECK(hipGetLastError());
+}
+
+}  // namespace mk
+}  // namespace ppr

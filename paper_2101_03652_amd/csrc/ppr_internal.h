@@ -117,6 +117,7 @@ struct Graph {
     std::vector<std::unique_ptr<QueryCtx>> pool;       // idle FP64 query contexts
     std::vector<MixedCtxPtr> mixed_pool;               // idle batched contexts (any width)
     int tuned_width = 0;                               // autotuner's choice (0 = not tuned)
+    int live_blocks = 0;                               // serving blocks on this graph (pool_mu)
     ~Graph();
     size_t device_bytes() const;
     const Schedule& schedule(int32_t nnz_cap, int32_t row_cap);
@@ -199,5 +200,14 @@ void run_mixed_batch(Graph& g, const int32_t* sources, int32_t B, double alpha, 
                      const ppr_options& opt, double* pi_out, double* r_out, ppr_stats* st);
 void autotune_width(Graph& g, double alpha, const int32_t* widths, int32_t count, int32_t* best,
                     double* cost_us);
+
+// serving blocks (continuous batching); the handle is an opaque Block*
+void* serve_block_create(Graph& g, int32_t slots, double alpha, const ppr_options& opt);
+void serve_block_destroy(void* blk);
+int32_t serve_admit(void* blk, int32_t s, double lambda);
+void serve_step(void* blk, int32_t max_sweeps);
+void serve_poll(void* blk, int wait, uint8_t* done, int32_t* n_done, int32_t* n_busy, int32_t* ready);
+void serve_retire(void* blk, int32_t slot, double* pi_out, ppr_stats* st);
+size_t serve_footprint(const Graph& g, int32_t slots);
 
 }  // namespace ppr
