@@ -97,7 +97,7 @@ typedef struct {
     int32_t precision;      /* ppr_precision */
     int32_t switch_rule;    /* ppr_switch_rule; default PPR_SWITCH_EDGES */
     double switch_param;    /* PPR_SWITCH_EDGES: continue while param * vol <= m; default 8 */
-    int32_t max_sweeps;     /* cap on global sweeps; default 4096 */
+    int32_t max_sweeps;     /* cap on the global sweeps of each query; default 4096 */
     int32_t certify;        /* PPR_FP64: also compute cert_l1; default 0 */
     double refresh_factor;  /* PPR_MIXED: refresh the residual in FP64 whenever r_sum has
                                fallen by this factor since the last refresh; default 1e4 */
@@ -218,7 +218,7 @@ ppr_status ppr_autotune(ppr_graph* g, double alpha, const int32_t* widths, int32
  */
 
 /* Create a block.  slots: power of two in [4, 128]; alpha in (0, 1); opt
- * (nullable): switch rule, max_sweeps (a cap on the block's total sweeps),
+ * (nullable): switch rule, max_sweeps (a cap on each query's sweeps),
  * refresh_factor; precision is ignored.  PPR_ERR_OOM if the device memory
  * (ppr_block_footprint) cannot be allocated. */
 ppr_status ppr_block_create(ppr_graph* g, int32_t slots, double alpha, const ppr_options* opt,
@@ -243,16 +243,18 @@ ppr_status ppr_slot_admit(ppr_block* blk, int32_t source, double lambda, int32_t
 ppr_status ppr_block_step(ppr_block* blk, int32_t max_sweeps);
 
 /* Collect the enqueued work if it has finished (wait = 1: wait for it).
- * done: host uint8[slots] (nullable), 1 for slots holding a certified
- * result; n_done, n_busy (admitted, not yet retired), ready (1 if nothing
+ * done: host uint8[slots] (nullable), 1 for slots holding a finished query
+ * (certified, or at its sweep cap); n_done, n_busy (admitted, not yet retired), ready (1 if nothing
  * is in flight): nullable outputs. */
 ppr_status ppr_block_poll(ppr_block* blk, int32_t wait, uint8_t* done, int32_t* n_done,
                           int32_t* n_busy, int32_t* ready);
 
-/* Copy a certified result out and free the slot.  pi_out: double[n], host
- * or device memory of the graph's device.  stats (nullable): the query's
- * statistics, ms = time from admission to retirement.  PPR_ERR_BUSY if the
- * slot holds no certified result. */
+/* Copy a finished query's result out and free the slot.  pi_out: double[n],
+ * host or device memory of the graph's device.  stats (nullable): the
+ * query's statistics, ms = time from admission to retirement.  PPR_ERR_BUSY
+ * if the slot holds no finished query.  PPR_ERR_NOT_CONVERGED if the query
+ * reached max_sweeps with its certificate above lambda: pi_out and stats
+ * still receive its estimate and certificate, and the slot is freed. */
 ppr_status ppr_slot_retire(ppr_block* blk, int32_t slot, double* pi_out, ppr_stats* stats);
 
 /* Library version string. */

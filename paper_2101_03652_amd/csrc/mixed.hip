@@ -141,6 +141,7 @@ struct Block {
         int32_t stage_left = 0;      // sweeps left in the current stage
         bool entry = false;          // fold the refreshed residue on the next sweep
         bool refreshing = false;     // in the refresh whose result is in flight
+        bool failed = false;         // reached max_sweeps with a certificate above lambda
         double cert = -1.0;
         int32_t levels = 0, sweeps = 0, refreshes = 0;
         int64_t edges = 0;
@@ -368,6 +369,9 @@ struct Block {
             sl.err = hcol[b];
             if (hcol[b] <= sl.lambda) {
                 sl.state = DONE;
+            } else if (out_of_sweeps(sl)) {
+                sl.state = DONE;
+                sl.failed = true;
             } else {
                 sl.entry = true;
                 sl.stage_left = stage_length(sl);
@@ -377,7 +381,9 @@ struct Block {
         return true;
     }
 
-    bool exhausted() const { return opt.max_sweeps > 0 && total_sweeps >= opt.max_sweeps; }
+    // per-query cap on global sweeps (opt.max_sweeps)
+    int32_t sweeps_left(const Slot& sl) const { return std::max(0, opt.max_sweeps - sl.sweeps); }
+    bool out_of_sweeps(const Slot& sl) const { return sl.sweeps >= opt.max_sweeps; }
 
     // Enqueue up to max_sweeps sweeps and the refreshes of the slots whose
     // stage ends; their results are taken by collect().
@@ -387,16 +393,15 @@ struct Block {
         hipStream_t ss = c->stream;
         int32_t K = 0;
         for (const Slot& sl : slots)
-            if (sl.state == RUNNING) K = std::max(K, sl.stage_left);
-        if (opt.max_sweeps > 0) K = std::min<int32_t>(K, std::max(0, opt.max_sweeps - total_sweeps));
+            if (sl.state == RUNNING) K = std::max(K, std::min(sl.stage_left, sweeps_left(sl)));
         K = std::min(K, max_sweeps);
         if (K > 0) {
             std::vector<int32_t> hkb(Bw, 0), hen(Bw, 0);
             for (int b = 0; b < Bw; ++b) {
                 Slot& sl = slots[b];
                 if (sl.state != RUNNING) continue;
-                hkb[b] = std::min(sl.stage_left, K);
-                hen[b] = sl.entry ? 1 : 0;
+                hkb[b] = std::min(std::min(sl.stage_left, sweeps_left(sl)), K);
+                hen[b] = (sl.entry && hkb[b] > 0) ? 1 : 0;
             }
             upload_i32(c->kb, hkb);
             upload_i32(c->entry, hen);
@@ -428,13 +433,13 @@ struct Block {
                 if (hkb[b] > 0) sl.entry = false;
             }
         }
-        // refresh the slots whose stage has ended (every running slot once
-        // the sweep budget is spent, so that each gets a final certificate)
+        // refresh the slots whose stage has ended, and those out of sweeps
+        // (their final certificate)
         std::vector<int32_t> hr(Bw, 0);
         bool any = false;
         for (int b = 0; b < Bw; ++b) {
             Slot& sl = slots[b];
-            if (sl.state == RUNNING && (sl.stage_left <= 0 || exhausted())) {
+            if (sl.state == RUNNING && (sl.stage_left <= 0 || out_of_sweeps(sl))) {
                 hr[b] = 1;
                 sl.refreshing = true;
                 any = true;
@@ -472,7 +477,8 @@ struct Block {
         st->batch_cols = Bw;
     }
 
-    // Export slot b (DONE) into out[n] (host or device) and free the slot.
+    // Export slot b (DONE) into out[n] (host or device) and free the slot;
+    // a slot that ended at its sweep cap is exported too, then reported.
     void retire(int b, double* out, ppr_stats* st) {
         if (b < 0 || b >= Bw) fail(PPR_ERR_ARG, "slot out of range");
         if (slots[b].state != DONE) fail(PPR_ERR_BUSY, "slot has no certified result yet");
@@ -486,7 +492,9 @@ struct Block {
         }
         HIPCHECK(hipStreamSynchronize(ss));
         if (st) fill_stats(b, st, now_ms() - slots[b].t_admit);
+        const bool failed = slots[b].failed;
         slots[b] = Slot();
+        if (failed) fail(PPR_ERR_NOT_CONVERGED, "max_sweeps reached before the certificate fell to lambda");
     }
 };
 
@@ -501,10 +509,9 @@ void run_mixed_chunk(Block& blk, const int32_t* sources, int Breal, double lambd
     MixedCtx& c = *blk.c;
     for (int b = 0; b < Breal; ++b)
         if (blk.admit(sources[b], lambda) != b) fail(PPR_ERR_ARG, "internal: batch slot order");
-    while (!blk.settled()) {
+    while (!blk.settled()) {     // each slot ends: certified, or at its sweep cap
         blk.step(1 << 30);
         blk.collect(true);
-        if (blk.exhausted()) break;
     }
     // ---- output: the export kernel writes device memory only; a host
     // destination is filled through a device staging buffer
@@ -529,7 +536,7 @@ void run_mixed_chunk(Block& blk, const int32_t* sources, int Breal, double lambd
     const double ms = now_ms() - t0;
     bool failed = false;
     for (int b = 0; b < Breal; ++b) {
-        if (blk.slots[b].state != DONE) failed = true;
+        if (blk.slots[b].failed) failed = true;
         if (st) blk.fill_stats(b, st + b, ms);
         blk.slots[b] = Block::Slot();
     }

@@ -115,6 +115,7 @@ class Server:
         self.committed = self.graph_bytes
         self.peak_committed = self.committed
         self.refused = 0
+        self.failed = 0
         self.completed = []                                   # (Request, latency_ms, stats)
         self._rid = 0
         # one pinned host buffer per graph receives retired results
@@ -183,7 +184,12 @@ class Server:
                 continue
             for slot in st["done"]:
                 req = self.slot_req[i].pop(slot)
-                _, stats = blk.retire(slot, out=self._host[i])
+                try:
+                    _, stats = blk.retire(slot, out=self._host[i])
+                except self.P.PPRError as e:          # reached its sweep cap uncertified
+                    self.failed += 1
+                    req.future.set_exception(e)
+                    continue
                 t_done = time.perf_counter()
                 lat = (t_done - req.t_arrival) * 1e3
                 self.completed.append((req, lat, stats))
@@ -214,11 +220,14 @@ class Server:
 
 # ---------------------------------------------------------------- measurement
 
-def replay(server: Server, t_off, gid, lam, sources, timeout_s: float = 900.0) -> dict:
+def replay(server: Server, t_off, gid, lam, sources, timeout_s: float = 900.0, progress: int = 0) -> dict:
     """Open-loop replay of an arrival trace; returns latency percentiles (ms)
-    over the trace's queries, throughput and refusals."""
+    over the trace's queries, throughput, refusals and failures.  progress > 0
+    prints a line to stderr every `progress` completed queries."""
     n0 = len(server.completed)
     r0 = server.refused
+    f0 = server.failed
+    shown = 0
     start = time.perf_counter()
     k = 0
     N = len(t_off)
@@ -229,6 +238,10 @@ def replay(server: Server, t_off, gid, lam, sources, timeout_s: float = 900.0) -
             server.submit(int(gid[k]), int(sources[k]), float(lam[k]), t_arrival=start + float(t_off[k]))
             k += 1
         busy = server.pump()
+        done = len(server.completed) - n0
+        if progress and done >= shown + progress:
+            shown = done - done % progress
+            print(f"[serve] {done}/{N} served, {time.perf_counter() - start:.1f} s", file=sys.stderr, flush=True)
         if k >= N and not busy:
             break
         if now > t_end:
@@ -237,7 +250,8 @@ def replay(server: Server, t_off, gid, lam, sources, timeout_s: float = 900.0) -
             time.sleep(min(0.0005, max(0.0, start + t_off[k] - time.perf_counter())))
     wall = time.perf_counter() - start
     lats = [lat for _, lat, _ in server.completed[n0:]]
-    return {"queries": N, "served": len(lats), "refused": server.refused - r0, "wall_s": round(wall, 3),
+    return {"queries": N, "served": len(lats), "refused": server.refused - r0,
+            "not_converged": server.failed - f0, "wall_s": round(wall, 3),
             "qps": round(len(lats) / wall, 3), "p50_ms": round(percentile(lats, 50), 3),
             "p99_ms": round(percentile(lats, 99), 3), "max_cert_l1": max((s["cert_l1"] for _, _, s in
                                                                           server.completed[n0:]), default=None)}
@@ -274,18 +288,22 @@ def main() -> int:
     budget = int(args.budget_gib * 2**30) if args.budget_gib > 0 else resident + int(0.9 * free)
     srv = Server(Gs, budget, slots=args.slots, alpha=args.alpha, sweeps_per_step=args.sweeps_per_step)
 
+    # per graph a pool of seeded uniform sources; query k takes entry k of its graph's pool
+    pools = [synth.sources(G.n, args.queries, seed=3652 + i) for i, G in enumerate(Gs)]
+
+    def pick(gid):
+        return [int(pools[int(gi)][k]) for k, gi in enumerate(gid)]
+
     # saturated throughput of the mix: every query queued at once
     t_off, gid, lam = poisson_trace(1e9, args.queries, len(Gs), seed=1)
-    src = [int(synth.sources(Gs[int(gi)].n, 1, seed=7000 + k)[0]) for k, gi in enumerate(gid)]
-    sat = replay(srv, np.zeros(args.queries), gid, lam, src)
+    sat = replay(srv, np.zeros(args.queries), gid, lam, pick(gid), progress=50)
     print(f"[serve] saturated: {sat}", file=sys.stderr, flush=True)
     out = {"graphs": args.graphs, "slots": args.slots, "alpha": args.alpha, "budget_bytes": budget,
            "saturated": sat, "rates": []}
     for frac in (float(x) for x in args.rates.split(",")):
         rate = frac * sat["qps"]
         t_off, gid, lam = poisson_trace(rate, args.queries, len(Gs), seed=int(frac * 1000) + 11)
-        src = [int(synth.sources(Gs[int(gi)].n, 1, seed=9000 + k)[0]) for k, gi in enumerate(gid)]
-        r = replay(srv, t_off, gid, lam, src)
+        r = replay(srv, t_off, gid, lam, pick(gid), progress=50)
         r["rate_frac"] = frac
         r["rate_qps"] = round(rate, 3)
         out["rates"].append(r)

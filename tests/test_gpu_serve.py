@@ -151,3 +151,41 @@ def test_server_two_graphs_budget_and_results(c1):
     srv.close()
     G1.close()
     G2.close()
+
+
+def test_sweep_cap_is_per_query(c1):
+    """max_sweeps caps each query, not the block's lifetime: a block that has
+    run many more sweeps than the cap in total still finishes new queries
+    (regression: a block-wide count stopped all sweeping once it passed the
+    cap), and a query that reaches the cap uncertified is retired with
+    PPR_ERR_NOT_CONVERGED and frees its slot."""
+    print("[gpu] serve sweep cap per query", flush=True)
+    G = P.Graph.from_synth(c1)
+    srcs = [int(s) for s in synth.sources(c1.n, 10)]
+    blk = P.Block(G, 4, ALPHA, max_sweeps=120)
+    total = 0
+    for k in range(6):                      # ~62 sweeps each at lambda = 1e-6
+        slot = blk.admit(srcs[k], 1e-6)
+        for _ in range(1000):
+            blk.step(16)
+            if blk.poll(wait=True)["n_done"] == 1:
+                break
+        out, st = blk.retire(slot)
+        total += st["sweeps"]
+        assert st["cert_l1"] <= 1e-6
+        assert st["sweeps"] <= 120
+    assert total > 120
+    slot = blk.admit(srcs[7], 1e-10)        # needs ~100 sweeps: cap below that
+    blk.close()
+    blk = P.Block(G, 4, ALPHA, max_sweeps=20)
+    slot = blk.admit(srcs[7], 1e-10)
+    for _ in range(1000):
+        blk.step(16)
+        if blk.poll(wait=True)["n_done"] == 1:
+            break
+    with pytest.raises(P.PPRError) as ei:
+        blk.retire(slot)
+    assert ei.value.status == -7
+    assert blk.poll()["n_busy"] == 0
+    blk.close()
+    G.close()
