@@ -103,7 +103,12 @@ typedef struct {
                                fallen by this factor since the last refresh; default 1e4 */
     int32_t batch_cols;     /* PPR_MIXED batched: columns per block (multiple of 4, or 0 =
                                autotuned); default 0 */
-    int32_t reserved[5];
+    int32_t sweep_chunks;   /* PPR_MIXED: row chunks per global sweep.  1 = every sweep is
+                               one Eq. 7 step (Jacobi order); G > 1 = block Gauss-Seidel
+                               order: the rows of chunk j see the residues that chunks
+                               0..j-1 produced in the same sweep, as the in-place scan of
+                               Algorithm 3 does; 0 = chosen from m (default) */
+    int32_t reserved[4];
 } ppr_options;
 
 /* Read-only facts about a created graph. */

@@ -61,7 +61,8 @@ class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("switch_rule", ctypes.c_int32),
                 ("switch_param", ctypes.c_double), ("max_sweeps", ctypes.c_int32),
                 ("certify", ctypes.c_int32), ("refresh_factor", ctypes.c_double),
-                ("batch_cols", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("batch_cols", ctypes.c_int32), ("sweep_chunks", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 class GraphInfo(ctypes.Structure):

@@ -53,6 +53,7 @@ void check_options(const ppr_options& o) {
     if (o.max_sweeps < 0) fail(PPR_ERR_ARG, "max_sweeps must be >= 0");
     if (!(o.refresh_factor > 1.0)) fail(PPR_ERR_ARG, "refresh_factor must be > 1");
     if (o.batch_cols < 0 || (o.batch_cols % 4) != 0) fail(PPR_ERR_ARG, "batch_cols must be 0 or a multiple of 4");
+    if (o.sweep_chunks < 0 || o.sweep_chunks > 64) fail(PPR_ERR_ARG, "sweep_chunks must lie in [0, 64]");
 }
 
 }  // namespace

@@ -158,42 +158,90 @@ size_t Graph::device_bytes() const {
     return b;
 }
 
-const Schedule& Graph::schedule(int32_t nnz_cap, int32_t row_cap) {
+const Schedule& Graph::schedule(int32_t nnz_cap, int32_t row_cap, int32_t chunks, bool split) {
     std::lock_guard<std::mutex> lk(sched_mu);
+    chunks = std::max<int32_t>(1, std::min<int32_t>(chunks, n));
     for (auto& s : schedules)
-        if (s->nnz_cap == nnz_cap && s->row_cap == row_cap) return *s;
-    // contiguous row ranges with at most nnz_cap in-edges and row_cap rows; a
-    // row with more in-edges than nnz_cap gets a block of its own, listed first
-    std::vector<RowBlock> longb, normal;
+        if (s->nnz_cap == nnz_cap && s->row_cap == row_cap && s->chunks == chunks && s->split == split) return *s;
+    // Row chunks: contiguous row ranges of about m / chunks in-edges each
+    // (boundaries depend on the graph alone).  Inside a chunk, contiguous row
+    // ranges with at most nnz_cap in-edges and row_cap rows.  A row with more
+    // in-edges than nnz_cap either gets a block of its own, listed first, or
+    // (split) is cut into pieces of nnz_cap in-edges whose partial sums are
+    // added afterwards.
     const int64_t* cp = h_col_ptr.data();
-    int32_t r = 0;
-    while (r < n) {
-        int64_t d = cp[r + 1] - cp[r];
-        if (d > nnz_cap) { longb.push_back({r, r + 1, 0, 0, 0}); ++r; continue; }
-        int32_t r0 = r;
-        int64_t e = 0;
-        while (r < n && r - r0 < row_cap) {
-            int64_t dd = cp[r + 1] - cp[r];
-            if (dd > nnz_cap || e + dd > nnz_cap) break;
-            e += dd;
-            ++r;
-        }
-        normal.push_back({r0, r, 0, 0, 0});
+    std::vector<int32_t> lo(chunks + 1, n);
+    lo[0] = 0;
+    for (int32_t j = 1; j < chunks; ++j) {
+        const int64_t want = (int64_t)((double)m * j / chunks);
+        int32_t r = (int32_t)(std::lower_bound(cp, cp + n + 1, want) - cp);
+        lo[j] = std::max(lo[j - 1], std::min(r, n));
     }
+    std::vector<RowBlock> all;
+    std::vector<LongRow> lrows;
+    std::vector<int32_t> first(chunks + 1, 0), nlong(chunks, 0), lr_first(chunks + 1, 0);
+    int32_t slot = 0;
+    for (int32_t j = 0; j < chunks; ++j) {
+        std::vector<RowBlock> longb, normal;
+        lr_first[j] = (int32_t)lrows.size();
+        int32_t r = lo[j];
+        const int32_t rend = lo[j + 1];
+        while (r < rend) {
+            int64_t d = cp[r + 1] - cp[r];
+            if (d > nnz_cap) {
+                if (split) {
+                    const int32_t np = (int32_t)((d + nnz_cap - 1) / nnz_cap);
+                    lrows.push_back({r, slot, np, 0});
+                    for (int32_t p = 0; p < np; ++p) {
+                        const int64_t e = cp[r] + (int64_t)p * nnz_cap;
+                        longb.push_back({r, r + 1, (int32_t)std::min<int64_t>(nnz_cap, cp[r + 1] - e), slot++, e});
+                    }
+                } else {
+                    longb.push_back({r, r + 1, 0, -1, 0});
+                }
+                ++r;
+                continue;
+            }
+            int32_t r0 = r;
+            int64_t e = 0;
+            while (r < rend && r - r0 < row_cap) {
+                int64_t dd = cp[r + 1] - cp[r];
+                if (dd > nnz_cap || e + dd > nnz_cap) break;
+                e += dd;
+                ++r;
+            }
+            normal.push_back({r0, r, 0, -1, 0});
+        }
+        first[j] = (int32_t)all.size();
+        nlong[j] = split ? 0 : (int32_t)longb.size();
+        all.insert(all.end(), longb.begin(), longb.end());
+        all.insert(all.end(), normal.begin(), normal.end());
+    }
+    first[chunks] = (int32_t)all.size();
+    lr_first[chunks] = (int32_t)lrows.size();
     auto s = std::make_unique<Schedule>();
     s->nnz_cap = nnz_cap;
     s->row_cap = row_cap;
-    s->n_long = (int32_t)longb.size();
-    s->n_blocks = (int32_t)(longb.size() + normal.size());
-    std::vector<RowBlock> all(longb);
-    all.insert(all.end(), normal.begin(), normal.end());
+    s->chunks = chunks;
+    s->split = split;
+    s->n_long = nlong[0];
+    s->n_blocks = (int32_t)all.size();
+    s->n_pieces = slot;
+    s->first = first;
+    s->nlong = nlong;
+    s->lo = lo;
+    s->lr_first = lr_first;
     for (RowBlock& b : all) {
+        if (b.piece >= 0) continue;         // pieces carry their own edge range
         b.e0 = cp[b.r0];
         b.ne = (int32_t)std::min<int64_t>(cp[b.r1] - cp[b.r0], INT32_MAX);
-        b.pad = 0;
     }
-    s->blocks.alloc(sizeof(RowBlock) * all.size());
-    HIPCHECK(hipMemcpy(s->blocks.p, all.data(), sizeof(RowBlock) * all.size(), hipMemcpyHostToDevice));
+    s->blocks.alloc(sizeof(RowBlock) * std::max<size_t>(all.size(), 1));
+    if (!all.empty())
+        HIPCHECK(hipMemcpy(s->blocks.p, all.data(), sizeof(RowBlock) * all.size(), hipMemcpyHostToDevice));
+    s->longrows.alloc(sizeof(LongRow) * std::max<size_t>(lrows.size(), 1));
+    if (!lrows.empty())
+        HIPCHECK(hipMemcpy(s->longrows.p, lrows.data(), sizeof(LongRow) * lrows.size(), hipMemcpyHostToDevice));
     schedules.push_back(std::move(s));
     return *schedules.back();
 }

@@ -47,6 +47,14 @@ bool continue_local(const ppr_options& opt, int64_t nf, int64_t vol, int32_t n, 
     return opt.switch_param * kBatchRef * (double)vol <= (double)m;
 }
 
+// Row chunks per sweep: about 2M in-edges per chunk keep each launch filling
+// the device; at most 8 (beyond that the launches cost more than the few
+// sweeps they save).
+int sweep_chunks(const Graph& g, const ppr_options& opt) {
+    if (opt.sweep_chunks > 0) return opt.sweep_chunks;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(8, g.m >> 21));
+}
+
 double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -67,8 +75,13 @@ int64_t frontier_capacity(const Graph& g, const ppr_options& opt, int Bw) {
 
 size_t mixed_footprint(const Graph& g, int Bw, int64_t fcap) {
     const size_t nb = (size_t)g.n * (size_t)Bw;
+    // long-row pieces: each holds nnz_cap = kLdsBytes / (4 Bw) in-edges of a
+    // row with more than nnz_cap, so there are fewer than 2 m / nnz_cap
+    const size_t nnz_cap = (size_t)mk::kLdsBytes / (4 * (size_t)Bw);
+    const size_t pieces = 2 * (size_t)g.m / nnz_cap + 1;
     return 16 * nb                       // FP64 local-phase scratch
            + 20 * nb                     // Y0, Y1, Shi, Slo, T
+           + 4 * (size_t)Bw * pieces     // partial sums of the pieces
            + 40 * (size_t)fcap + 4 * (size_t)g.n + ((size_t)1 << 20);
 }
 
@@ -139,10 +152,14 @@ struct Block {
         double lambda = 0.0;
         double err = 0.0;            // bound on ||pi_hat - pi_s||_1 (exact right after a refresh)
         int32_t stage_left = 0;      // sweeps left in the current stage
-        bool entry = false;          // fold the refreshed residue on the next sweep
+        bool entry = false;          // the residue is fresh: the next sweep folds its alpha-part
+                                     // and pulls it along every in-edge
         bool refreshing = false;     // in the refresh whose result is in flight
         bool failed = false;         // reached max_sweeps with a certificate above lambda
         double cert = -1.0;
+        double rho = 0.0;            // per-sweep contraction of err the stage lengths assume
+        double stage_err0 = 0.0;     // err when the current stage started
+        int32_t stage_sweeps = 0;    // sweeps run in the current stage
         int32_t levels = 0, sweeps = 0, refreshes = 0;
         int64_t edges = 0;
         double t_admit = 0.0;
@@ -167,6 +184,14 @@ struct Block {
     Block(Graph& gg, int width, double a, const ppr_options& o) : g(gg), Bw(width), alpha(a), opt(o) {
         if (Bw < 4 || Bw > 128 || (Bw & (Bw - 1))) fail(PPR_ERR_ARG, "block width must be a power of two in [4, 128]");
         c = mixed_acquire(g, Bw, frontier_capacity(g, opt, Bw));
+        const int chunks = sweep_chunks(g, opt);
+        if (c->chunks != chunks) {
+            if (c->chunk) {
+                (void)hipGraphExecDestroy(c->chunk);
+                c->chunk = nullptr;
+            }
+            c->chunks = chunks;
+        }
         mk::prepare(*c, g);
         slots.resize(Bw);
         HIPCHECK(hipEventCreateWithFlags(&ev_ready, hipEventDisableTiming));
@@ -214,8 +239,35 @@ struct Block {
     int32_t stage_length(const Slot& sl) const {
         double target = std::max(sl.err / opt.refresh_factor, 0.5 * sl.lambda);
         int32_t k = 0;
-        for (double x = sl.err; x > target; x *= (1.0 - alpha)) ++k;
+        for (double x = sl.err; x > target && k < (1 << 20); x *= sl.rho) ++k;
         return std::max<int32_t>(k, 1);
+    }
+
+    // A stage starts (after the conversion or a refresh) with err known exactly.
+    void start_stage(Slot& sl) {
+        sl.stage_err0 = sl.err;
+        sl.stage_sweeps = 0;
+        sl.stage_left = stage_length(sl);
+    }
+
+    // Contraction the first stage assumes: exactly 1 - alpha for Jacobi
+    // sweeps; for block Gauss-Seidel sweeps a prior of (1 - alpha)^1.4 (on
+    // power-law graphs they contract like (1 - alpha)^1.5 .. (1 - alpha)^1.7);
+    // a stage that falls short is simply followed by another.
+    double first_rate() const { return c->chunks <= 1 ? 1.0 - alpha : std::pow(1.0 - alpha, 1.4); }
+
+    // Contraction for the next stage's length.  A Jacobi sweep (one chunk)
+    // contracts the residue mass by exactly 1 - alpha (Eq. 6, Lemma 1).  In
+    // block Gauss-Seidel order every pending unit of mass is pushed at least
+    // once per sweep, so 1 - alpha still bounds the contraction; the measured
+    // rate of the stage just ended (rounded towards 1 - alpha) sets the next
+    // stage's length, and a stage that falls short is followed by another.
+    void update_rate(Slot& sl, double cert) const {
+        if (c->chunks <= 1 || sl.stage_sweeps <= 0 || !(sl.stage_err0 > 0.0) || !(cert > 0.0)) return;
+        double r = std::pow(cert / sl.stage_err0, 1.0 / sl.stage_sweeps);
+        r = std::pow(r, 0.95);
+        r = std::ceil(r * 1024.0) / 1024.0;
+        sl.rho = std::min(1.0 - alpha, std::max(0.05, r));
     }
 
     void upload_i32(DevBuf& d, const std::vector<int32_t>& h) {
@@ -309,8 +361,9 @@ struct Block {
             Slot& sl = slots[b];
             sl.state = RUNNING;
             sl.err = (1.0 - alpha) * hcol[b];
-            sl.entry = false;
-            sl.stage_left = stage_length(sl);
+            sl.entry = true;
+            sl.rho = first_rate();
+            start_stage(sl);
         }
     }
 
@@ -366,6 +419,7 @@ struct Block {
             sl.refreshing = false;
             sl.refreshes += 1;
             sl.cert = hcol[b];
+            update_rate(sl, hcol[b]);
             sl.err = hcol[b];
             if (hcol[b] <= sl.lambda) {
                 sl.state = DONE;
@@ -374,7 +428,7 @@ struct Block {
                 sl.failed = true;
             } else {
                 sl.entry = true;
-                sl.stage_left = stage_length(sl);
+                start_stage(sl);
             }
         }
         inflight = false;
@@ -428,8 +482,9 @@ struct Block {
                 Slot& sl = slots[b];
                 if (sl.state != RUNNING) continue;
                 sl.sweeps += hkb[b];
+                sl.stage_sweeps += hkb[b];
                 sl.stage_left -= hkb[b];
-                sl.err *= std::pow(1.0 - alpha, hkb[b]);
+                sl.err *= std::pow(sl.rho, hkb[b]);
                 if (hkb[b] > 0) sl.entry = false;
             }
         }

@@ -7,7 +7,7 @@ namespace ppr {
 
 namespace mk {
 constexpr int kBlock = 256;
-constexpr int kLdsBytes = 32768;   // staging budget of the sweep / refresh blocks
+constexpr int kLdsBytes = 16384;   // staging budget of the sweep / refresh blocks
 constexpr int kGridRed = 2048;     // persistent grid of the refresh (fixed -> deterministic sums)
 
 // Sweep blocks: <= kNnz in-edges (B = 4C columns, C float4 chunks) and <= kRows rows.
@@ -15,14 +15,14 @@ template <int C>
 struct Sw {
     static constexpr int kNnz = kLdsBytes / (16 * C);
     static constexpr int kRows = kBlock / C;
-    static constexpr int kItems = kNnz * C / kBlock;   // = 8
+    static constexpr int kItems = kNnz * C / kBlock;   // = 4
     static constexpr int kSlots = kBlock / C;
 };
 // Refresh blocks gather the hi and lo reserve rows (2 x 16 C bytes per edge).
 template <int C>
 struct Rf {
     static constexpr int kNnz = kLdsBytes / (32 * C);
-    static constexpr int kItems = kNnz * C / kBlock;   // = 4
+    static constexpr int kItems = kNnz * C / kBlock;   // = 2
     static constexpr int kRows = kBlock / C;
 };
 }  // namespace mk
@@ -32,6 +32,7 @@ struct MixedCtx {
     hipStream_t stream = nullptr;
     int32_t n = 0;
     int Bw = 0, shift = 0;
+    int chunks = 1;                   // row chunks per sweep (block Gauss-Seidel order when > 1)
     double alpha = -1.0;              // alpha the scale table holds
     int64_t fcap = 0;                 // frontier capacity (entries)
     DevBuf r64, pi64;                 // double[n][Bw]  local-phase scratch, zero between uses
@@ -54,6 +55,7 @@ struct MixedCtx {
     DevBuf rmaxb;                     // double[Bw] lambda_b / m: activity threshold per column
     DevBuf step;                      // int32[1]   sweeps done in the current sequence
     DevBuf stage;                     // double[Bw][n] host-output staging (lazy)
+    DevBuf piece_part;                // float[pieces][Bw]: partial sums of long-row pieces
     PinnedBuf host;                   // readback area
     hipGraphExec_t chunk = nullptr;   // captured sweep chunk Y1 -> Y0 -> ... -> Y1
     const float* ycur = nullptr;      // buffer holding the current residue rows

@@ -15,7 +15,10 @@
 //    atomics into a dense FP64 scratch; then conversion into the block (the
 //    alpha-part of the remaining residue folded into S at once);
 //  - sweeps (FP32): y'(u) = (1-alpha)/d_u sum_{v in N_in(u)} y(v) (Eq. 7 in the
-//    y domain); the alpha-part of the new residue goes into T at once.  Per
+//    y domain), over row chunks in block Gauss-Seidel order (the rows of a
+//    chunk see the residues earlier chunks produced in the same sweep, as the
+//    in-place scan of Algorithm 3 does); the alpha-part of the new residue
+//    goes into T at once.  Per
 //    column a budget kb[b]: the column runs sweeps while step < kb[b], then
 //    gets y' = 0 (its pending residue is dropped: the next refresh recomputes
 //    the exact residual from S) and its reserve stops changing;
@@ -167,9 +170,11 @@ __global__ __launch_bounds__(kBlock) void push_k(
 }
 
 // FP64 scratch -> FP32 block for the columns with cmask = 1, dense over
-// (u, b): y = (1-alpha) r / d, S = (1-alpha) pi / (alpha d) + y (the
-// alpha-part of the remaining residue folded in), T = 0; the scratch of those
-// columns is cleared.  partials[block][B]: per-column sums of r.
+// (u, b): y = (1-alpha) r / d, S = (1-alpha) pi / (alpha d), T = 0; the
+// scratch of those columns is cleared.  The residue is fresh (nobody has
+// pulled it), so the first sweep of the column runs with its entry flag:
+// it folds the alpha-part into T and pulls y along every in-edge.
+// partials[block][B]: per-column sums of r.
 __global__ void convert_k(int32_t n, int shift, const int32_t* __restrict__ deg, double alpha,
                           const int32_t* __restrict__ cmask, double* __restrict__ r64, double* __restrict__ pi64,
                           float* __restrict__ Y, float* __restrict__ Shi, float* __restrict__ Slo,
@@ -190,7 +195,7 @@ __global__ void convert_k(int32_t n, int shift, const int32_t* __restrict__ deg,
             int32_t u = (int32_t)(i >> shift);
             double d = (double)deg[u];
             double y = ((1.0 - alpha) * r) / d;
-            double S = ((1.0 - alpha) * p) / (alpha * d) + y;
+            double S = ((1.0 - alpha) * p) / (alpha * d);
             Y[i] = (float)y;
             float h, l;
             split_double(S, h, l);
@@ -226,88 +231,38 @@ __global__ void scale_k(const int32_t* __restrict__ deg, int32_t n, double alpha
 }
 
 // ---------------------------------------------------------------- sweep
-// Schedule blocks: <= Sw<C>::kNnz in-edges and <= Sw<C>::kRows rows, or one
-// long row.  All loads that do not depend on gathered data (row bounds,
-// indices) are issued first; every thread then has kItems float4 gathers in
-// flight, staged in LDS; T threads per (row, chunk) add the row's slice.
-// Long rows: 256 / C slots stride the row's edges, summed in a fixed order.
-template <typename OffT, int C>
-__global__ __launch_bounds__(kBlock) void sweep_k(
-        const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
-        const RowBlock* __restrict__ blocks, int32_t n_long, const float* __restrict__ scale,
-        const float4* __restrict__ Y_in, float4* __restrict__ Y_out, float4* __restrict__ T,
-        const int32_t* __restrict__ kb, const int32_t* __restrict__ entry, const int32_t* __restrict__ step_p) {
-    using P = Sw<C>;
-    __shared__ float4 lds[kLdsBytes / 16];
-    const RowBlock b = blocks[blockIdx.x];
-    const int32_t step = *step_p;
-    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-    int32_t u = -1;
-    int c = 0;
-    if ((int32_t)blockIdx.x < n_long) {
-        const int slot = threadIdx.x / C;
-        c = threadIdx.x % C;
-        const int64_t e0 = b.e0, e1 = b.e0 + b.ne;
-        float4 a0 = acc, a1 = acc, a2 = acc, a3 = acc;
-        int64_t e = e0 + slot;
-        for (; e + 3 * P::kSlots < e1; e += 4 * P::kSlots) {
-            int32_t v0 = row_idx[e], v1 = row_idx[e + P::kSlots], v2 = row_idx[e + 2 * P::kSlots],
-                    v3 = row_idx[e + 3 * P::kSlots];
-            float4 g0 = Y_in[(int64_t)v0 * C + c], g1 = Y_in[(int64_t)v1 * C + c];
-            float4 g2 = Y_in[(int64_t)v2 * C + c], g3 = Y_in[(int64_t)v3 * C + c];
-            a0 = f4_add(a0, g0);
-            a1 = f4_add(a1, g1);
-            a2 = f4_add(a2, g2);
-            a3 = f4_add(a3, g3);
-        }
-        for (; e < e1; e += P::kSlots) a0 = f4_add(a0, Y_in[(int64_t)row_idx[e] * C + c]);
-        lds[threadIdx.x] = f4_add(f4_add(a0, a1), f4_add(a2, a3));
-        __syncthreads();
-        if (threadIdx.x < C) {
-            float4 t = lds[threadIdx.x];
-            for (int s2 = 1; s2 < P::kSlots; ++s2) t = f4_add(t, lds[s2 * C + threadIdx.x]);
-            acc = t;
-            u = b.r0;
-        }
-    } else {
-        const int32_t r0 = b.r0;
-        const int32_t R = b.r1 - r0;
-        const int32_t ne = b.ne;
-        const int64_t e0 = b.e0;
-        int T2 = 64 / C < 1 ? 1 : 64 / C;               // (row, chunk) groups stay inside a wave
-        while (T2 > 1 && T2 * R * C > kBlock) T2 >>= 1;
-        const int32_t grp = threadIdx.x / T2;
-        const int sub = threadIdx.x % T2;
-        const int32_t row = grp / C;
-        c = grp % C;
-        int32_t s0 = 0, s1 = 0;
-        if (row < R) {
-            s0 = (int32_t)((int64_t)col_ptr[r0 + row] - e0);
-            s1 = (int32_t)((int64_t)col_ptr[r0 + row + 1] - e0);
-        }
-        int32_t vv[P::kItems];
-#pragma unroll
-        for (int k = 0; k < P::kItems; ++k) {
-            int32_t it = threadIdx.x + k * kBlock;
-            vv[k] = (it / C < ne) ? row_idx[e0 + it / C] : -1;
-        }
-        float4 gv[P::kItems];
-#pragma unroll
-        for (int k = 0; k < P::kItems; ++k) {
-            int32_t it = threadIdx.x + k * kBlock;
-            gv[k] = (vv[k] >= 0) ? Y_in[(int64_t)vv[k] * C + (it % C)] : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-#pragma unroll
-        for (int k = 0; k < P::kItems; ++k) {
-            int32_t it = threadIdx.x + k * kBlock;
-            if (it / C < ne) lds[it] = gv[k];
-        }
-        __syncthreads();
-        for (int32_t e = s0 + sub; e < s1; e += T2) acc = f4_add(acc, lds[e * C + c]);
-        for (int o = T2 >> 1; o >= 1; o >>= 1) acc = f4_add(acc, f4_shfl_xor(acc, o));
-        if (row < R && sub == 0) u = r0 + row;
-    }
-    if (u < 0) return;
+// One launch handles one row chunk [lo, ...) of the sweep.  Row u of the
+// chunk reads the residue of in-neighbour v from Y_out (produced earlier in
+// this sweep) when v < lo, else from Y_in (the previous sweep): block
+// Gauss-Seidel order, every residue increment still pulled exactly once by
+// each out-neighbour.  With one chunk (lo = 0) this is the plain Eq. 7 step.
+// On the first sweep of a sequence (step == 0) a column with its entry flag
+// set holds a fresh residue in Y_in that nobody has pulled yet: its rows pull
+// it along every in-edge, in addition to the new values of earlier chunks.
+//
+// Schedule blocks hold <= Sw<C>::kNnz in-edges: up to Sw<C>::kRows whole
+// rows, or one piece of a long row.  Row bounds and indices are loaded
+// first; every thread then has kItems float4 gathers in flight, staged in
+// LDS; T2 threads per (row, chunk) add the row's slice.  A piece writes its
+// raw sum to a partial slot; combine_k adds a long row's pieces in slot
+// order and finishes the row.  Y_out is read (rows < lo) and written
+// (rows >= lo) in the same launch, so it carries no __restrict__.
+template <int C>
+__device__ inline float4 gather_gs(const float4* __restrict__ Y_in, const float4* Y_out, int32_t v, int c,
+                                   int32_t lo, bool fresh, float4 enf) {
+    const int64_t i = (int64_t)v * C + c;
+    if (v >= lo) return Y_in[i];
+    float4 g = Y_out[i];
+    if (fresh) g = f4_add(g, f4_mul(Y_in[i], enf));
+    return g;
+}
+
+// y'(u) = scale(u) * acc for the columns inside their sweep budget (0 for the
+// others); T += y' (plus, on an entry sweep, the fresh residue's alpha-part).
+template <int C>
+__device__ inline void finish_row(int32_t u, int c, float4 acc, int32_t step, const float* __restrict__ scale,
+                                  const float4* __restrict__ Y_in, float4* Y_out, float4* __restrict__ T,
+                                  const int32_t* __restrict__ kb, const int32_t* __restrict__ entry) {
     const int64_t at = (int64_t)u * C + c;
     float4 t = T[at];
     const float sc = scale[u];
@@ -322,6 +277,86 @@ __global__ __launch_bounds__(kBlock) void sweep_k(
     float4 y = make_float4(sc * acc.x, sc * acc.y, sc * acc.z, sc * acc.w);
     Y_out[at] = y;
     T[at] = f4_add(t, y);
+}
+
+template <typename OffT, int C>
+__global__ __launch_bounds__(kBlock) void sweep_k(
+        const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
+        const RowBlock* __restrict__ blocks, int32_t lo, const float* __restrict__ scale,
+        const float4* __restrict__ Y_in, float4* Y_out, float4* __restrict__ T,
+        const int32_t* __restrict__ kb, const int32_t* __restrict__ entry, const int32_t* __restrict__ step_p,
+        float4* __restrict__ partials) {
+    using P = Sw<C>;
+    __shared__ float4 lds[kLdsBytes / 16];
+    const RowBlock b = blocks[blockIdx.x];
+    const int32_t step = *step_p;
+    // every item of this thread belongs to column chunk threadIdx.x % C
+    float4 enf = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (step == 0 && lo > 0) enf = flag4(reinterpret_cast<const int4*>(entry)[threadIdx.x % C]);
+    const bool fresh = (enf.x + enf.y + enf.z + enf.w) != 0.f;
+    const bool piece = b.piece >= 0;
+    const int32_t r0 = b.r0;
+    const int32_t R = piece ? 1 : b.r1 - r0;
+    const int32_t ne = b.ne;
+    const int64_t e0 = b.e0;
+    // (row, chunk) groups of T2 consecutive lanes (inside one wave)
+    int T2 = 1;
+    while (T2 < 64 && 2 * T2 * R * C <= kBlock) T2 <<= 1;
+    const int32_t grp = threadIdx.x / T2;
+    const int sub = threadIdx.x % T2;
+    const int32_t row = grp / C;
+    const int c = grp % C;
+    int32_t s0 = 0, s1 = 0;
+    if (row < R) {
+        if (piece) {
+            s1 = ne;
+        } else {
+            s0 = (int32_t)((int64_t)col_ptr[r0 + row] - e0);
+            s1 = (int32_t)((int64_t)col_ptr[r0 + row + 1] - e0);
+        }
+    }
+    int32_t vv[P::kItems];
+#pragma unroll
+    for (int k = 0; k < P::kItems; ++k) {
+        int32_t it = threadIdx.x + k * kBlock;
+        vv[k] = (it / C < ne) ? row_idx[e0 + it / C] : -1;
+    }
+    float4 gv[P::kItems];
+#pragma unroll
+    for (int k = 0; k < P::kItems; ++k) {
+        gv[k] = (vv[k] >= 0) ? gather_gs<C>(Y_in, Y_out, vv[k], threadIdx.x % C, lo, fresh, enf)
+                             : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+#pragma unroll
+    for (int k = 0; k < P::kItems; ++k) {
+        int32_t it = threadIdx.x + k * kBlock;
+        if (it / C < ne) lds[it] = gv[k];
+    }
+    __syncthreads();
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int32_t e = s0 + sub; e < s1; e += T2) acc = f4_add(acc, lds[e * C + c]);
+    for (int o = T2 >> 1; o >= 1; o >>= 1) acc = f4_add(acc, f4_shfl_xor(acc, o));
+    if (row >= R || sub != 0) return;
+    if (piece) {
+        partials[(int64_t)b.piece * C + c] = acc;
+        return;
+    }
+    finish_row<C>(r0 + row, c, acc, step, scale, Y_in, Y_out, T, kb, entry);
+}
+
+// Long rows of one chunk: the pieces' partial sums added in slot order.
+template <int C>
+__global__ __launch_bounds__(kBlock) void combine_k(
+        const LongRow* __restrict__ rows, int32_t count, const float4* __restrict__ partials,
+        const int32_t* __restrict__ step_p, const float* __restrict__ scale, const float4* __restrict__ Y_in,
+        float4* Y_out, float4* __restrict__ T, const int32_t* __restrict__ kb, const int32_t* __restrict__ entry) {
+    const int32_t i = (int32_t)blockIdx.x * (kBlock / C) + (int32_t)threadIdx.x / C;
+    const int c = threadIdx.x % C;
+    if (i >= count) return;
+    const LongRow L = rows[i];
+    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int32_t p = 0; p < L.npieces; ++p) acc = f4_add(acc, partials[(int64_t)(L.first + p) * C + c]);
+    finish_row<C>(L.row, c, acc, *step_p, scale, Y_in, Y_out, T, kb, entry);
 }
 
 __global__ void bump_step_k(int32_t* step) { step[0] += 1; }
@@ -540,24 +575,41 @@ __global__ void export_col_k(int32_t n, int shift, int32_t b, const int32_t* __r
 
 // ---------------------------------------------------------------- launch helpers
 template <int C>
-const Schedule& sweep_schedule(Graph& g) { return g.schedule(Sw<C>::kNnz, Sw<C>::kRows); }
+const Schedule& sweep_schedule(Graph& g, int chunks) { return g.schedule(Sw<C>::kNnz, Sw<C>::kRows, chunks, true); }
 template <int C>
 const Schedule& refresh_schedule(Graph& g) { return g.schedule(Rf<C>::kNnz, Rf<C>::kRows); }
 
 template <int C>
 void sweep_c(MixedCtx& c, Graph& g, const float* yin, float* yout) {
-    const Schedule& sch = sweep_schedule<C>(g);
+    const Schedule& sch = sweep_schedule<C>(g, c.chunks);
     auto Y4i = reinterpret_cast<const float4*>(yin);
     auto Y4o = reinterpret_cast<float4*>(yout);
-    dim3 grid((unsigned)sch.n_blocks), blk(kBlock);
-    if (g.off64)
-        hipLaunchKernelGGL((sweep_k<int64_t, C>), grid, blk, 0, c.stream, g.col_ptr.as<int64_t>(),
-                           g.row_idx.as<int32_t>(), sch.blocks.as<RowBlock>(), sch.n_long, c.scale.as<float>(), Y4i,
-                           Y4o, c.T.as<float4>(), c.kb.as<int32_t>(), c.entry.as<int32_t>(), c.step.as<int32_t>());
-    else
-        hipLaunchKernelGGL((sweep_k<uint32_t, C>), grid, blk, 0, c.stream, g.col_ptr.as<uint32_t>(),
-                           g.row_idx.as<int32_t>(), sch.blocks.as<RowBlock>(), sch.n_long, c.scale.as<float>(), Y4i,
-                           Y4o, c.T.as<float4>(), c.kb.as<int32_t>(), c.entry.as<int32_t>(), c.step.as<int32_t>());
+    const RowBlock* blocks = sch.blocks.as<RowBlock>();
+    const LongRow* lrows = sch.longrows.as<LongRow>();
+    float4* part = c.piece_part.as<float4>();
+    for (int j = 0; j < sch.chunks; ++j) {      // chunk j sees the output of chunks < j
+        const int32_t nb = sch.first[j + 1] - sch.first[j];
+        if (nb == 0) continue;
+        dim3 grid((unsigned)nb), blk(kBlock);
+        const RowBlock* bj = blocks + sch.first[j];
+        if (g.off64)
+            hipLaunchKernelGGL((sweep_k<int64_t, C>), grid, blk, 0, c.stream, g.col_ptr.as<int64_t>(),
+                               g.row_idx.as<int32_t>(), bj, sch.lo[j], c.scale.as<float>(), Y4i, Y4o,
+                               c.T.as<float4>(), c.kb.as<int32_t>(), c.entry.as<int32_t>(), c.step.as<int32_t>(),
+                               part);
+        else
+            hipLaunchKernelGGL((sweep_k<uint32_t, C>), grid, blk, 0, c.stream, g.col_ptr.as<uint32_t>(),
+                               g.row_idx.as<int32_t>(), bj, sch.lo[j], c.scale.as<float>(), Y4i, Y4o,
+                               c.T.as<float4>(), c.kb.as<int32_t>(), c.entry.as<int32_t>(), c.step.as<int32_t>(),
+                               part);
+        const int32_t nl = sch.lr_first[j + 1] - sch.lr_first[j];
+        if (nl > 0) {
+            const int per = kBlock / C;
+            hipLaunchKernelGGL((combine_k<C>), dim3((unsigned)((nl + per - 1) / per)), dim3(kBlock), 0, c.stream,
+                               lrows + sch.lr_first[j], nl, part, c.step.as<int32_t>(), c.scale.as<float>(),
+                               Y4i, Y4o, c.T.as<float4>(), c.kb.as<int32_t>(), c.entry.as<int32_t>());
+        }
+    }
     hipLaunchKernelGGL(bump_step_k, dim3(1), dim3(1), 0, c.stream, c.step.as<int32_t>());
     HIPCHECK(hipGetLastError());
 }
@@ -655,7 +707,15 @@ void convert(MixedCtx& c, const Graph& g, double alpha) {
 void prepare(MixedCtx& c, const Graph& g) {
     Graph& gg = const_cast<Graph&>(g);
     by_width(c.Bw, [&](auto cc) {
-        (void)sweep_schedule<decltype(cc)::value>(gg);
+        const Schedule& sch = sweep_schedule<decltype(cc)::value>(gg, c.chunks);
+        const size_t need = (size_t)std::max(sch.n_pieces, 1) * (size_t)decltype(cc)::value * 16;
+        if (c.piece_part.bytes < need) {
+            if (c.chunk) {                     // a captured chunk holds the old buffer
+                (void)hipGraphExecDestroy(c.chunk);
+                c.chunk = nullptr;
+            }
+            c.piece_part.alloc(need);
+        }
         (void)refresh_schedule<decltype(cc)::value>(gg);
     });
 }

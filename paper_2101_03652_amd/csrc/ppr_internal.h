@@ -70,20 +70,36 @@ struct PinnedBuf {
 
 // A contiguous range of destination rows processed by one workgroup of a
 // pull sweep.  Long rows (more in-edges than the block's edge budget) get a
-// block of their own and are listed first.
+// block of their own, listed first, or are cut into pieces (split schedules).
 struct RowBlock {
     int32_t r0, r1;      // rows [r0, r1)
-    int32_t ne, pad;     // in-edges of those rows
-    int64_t e0;          // offset of the first in-edge (= col_ptr[r0])
+    int32_t ne;          // in-edges of the block
+    int32_t piece;       // -1, or: the block is one piece of the long row r0 and writes
+                         // its partial sum into partial slot `piece`
+    int64_t e0;          // offset of the first in-edge (= col_ptr[r0] unless a piece)
+};
+
+// A long row of a split schedule: its pieces' partial sums are slots
+// [first, first + npieces), added in slot order.
+struct LongRow {
+    int32_t row, first, npieces, pad;
 };
 
 // Sweep schedule for one edge budget.
 struct Schedule {
-    int32_t nnz_cap = 0;       // edge budget per normal block
-    int32_t row_cap = 0;       // row budget per normal block
-    int32_t n_long = 0;        // leading blocks that hold a single long row
+    int32_t nnz_cap = 0;       // edge budget per block
+    int32_t row_cap = 0;       // row budget per block
+    int32_t chunks = 1;        // row chunks (contiguous row ranges of about m / chunks in-edges)
+    bool split = false;        // long rows split into pieces (else one block per long row)
+    int32_t n_long = 0;        // leading blocks that hold a single long row (chunks == 1, !split)
     int32_t n_blocks = 0;
+    int32_t n_pieces = 0;      // partial slots of a split schedule
+    // chunk j: blocks [first[j], first[j+1]), of which the first nlong[j] hold
+    // one long row each (!split); rows [lo[j], lo[j+1]); long rows
+    // [lr_first[j], lr_first[j+1]) of `longrows` (split)
+    std::vector<int32_t> first, nlong, lo, lr_first;
     DevBuf blocks;             // RowBlock[n_blocks]
+    DevBuf longrows;           // LongRow[...] (split)
 };
 
 struct QueryCtx;
@@ -120,7 +136,7 @@ struct Graph {
     int live_blocks = 0;                               // serving blocks on this graph (pool_mu)
     ~Graph();
     size_t device_bytes() const;
-    const Schedule& schedule(int32_t nnz_cap, int32_t row_cap);
+    const Schedule& schedule(int32_t nnz_cap, int32_t row_cap, int32_t chunks = 1, bool split = false);
 };
 
 Graph* graph_create(const int64_t* row_ptr, const int32_t* col, int32_t n, int64_t m,

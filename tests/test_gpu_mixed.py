@@ -46,12 +46,15 @@ def _check_batch(g, srcs, out, stats, lam, truth):
         assert stats[b]["source"] == s
 
 
+@pytest.mark.parametrize("chunks", [1, 4])
 @pytest.mark.parametrize("width", [4, 8, 16, 32, 64, 128])
-def test_batch_widths_c1(c1, c1_truth, width):
+def test_batch_widths_c1(c1, c1_truth, width, chunks):
+    """chunks = 1: every sweep is one Eq. 7 step; chunks = 4: block
+    Gauss-Seidel sweeps over four row chunks."""
     srcs = [int(s) for s in synth.sources(c1.n, 40)][:width]
-    print(f"[gpu] mixed c1 width={width}", flush=True)
+    print(f"[gpu] mixed c1 width={width} chunks={chunks}", flush=True)
     G = P.Graph.from_synth(c1)
-    out, st = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=width)
+    out, st = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=width, sweep_chunks=chunks)
     _check_batch(c1, srcs, out, st, 1e-8, c1_truth)
     assert all(s["refreshes"] >= 1 for s in st)
 
@@ -66,15 +69,16 @@ def test_ragged_batch_and_duplicates(c1, c1_truth):
     assert np.abs(out[5] - out[2]).sum() <= 2e-8 + SLACK
 
 
-def test_alone_equals_in_mix(c1):
+@pytest.mark.parametrize("chunks", [1, 4])
+def test_alone_equals_in_mix(c1, chunks):
     """A column's sweep budget depends on its own error only, so a source
     answered alone and inside a block of 32 runs the same schedule; the two
     results differ only by FP32 summation order."""
     srcs = [int(s) for s in synth.sources(c1.n, 40)][:32]
     G = P.Graph.from_synth(c1)
-    mix, smix = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=32)
+    mix, smix = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=32, sweep_chunks=chunks)
     for b in (0, 7, 31):
-        alone, sal = G.query_batch([srcs[b]], ALPHA, 1e-8, P.MIXED, batch_cols=4)
+        alone, sal = G.query_batch([srcs[b]], ALPHA, 1e-8, P.MIXED, batch_cols=4, sweep_chunks=chunks)
         assert sal[0]["sweeps"] == smix[b]["sweeps"]
         assert sal[0]["refreshes"] == smix[b]["refreshes"]
         assert np.abs(alone[0] - mix[b]).sum() <= SLACK
@@ -83,7 +87,7 @@ def test_alone_equals_in_mix(c1):
 def test_mixed_vs_fp64_path(c1):
     srcs = [int(s) for s in synth.sources(c1.n, 40)][:8]
     G = P.Graph.from_synth(c1)
-    mix, _ = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=8)
+    mix, _ = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=8, sweep_chunks=4)
     f64, _ = G.query_batch(srcs, ALPHA, 1e-8, P.FP64)
     for b in range(8):
         assert np.abs(mix[b] - f64[b]).sum() <= 2e-8 + SLACK
@@ -93,7 +97,7 @@ def test_mixed_vs_fp64_path(c1):
 def test_lambda_range(c1, lam):
     srcs = [int(s) for s in synth.sources(c1.n, 40)][:8]
     G = P.Graph.from_synth(c1)
-    out, st = G.query_batch(srcs, ALPHA, lam, P.MIXED, batch_cols=8)
+    out, st = G.query_batch(srcs, ALPHA, lam, P.MIXED, batch_cols=8, sweep_chunks=4)
     _check_batch(c1, srcs, out, st, lam, None)
 
 
@@ -117,8 +121,9 @@ def test_small_graphs_and_hubs():
     G = P.Graph.from_synth(h)
     srcs = [0, 1, 2, 12345, 777, 19999, 3, 4]
     for width in (8, 128):
-        out, st = G.query_batch(srcs, ALPHA, 1e-9, P.MIXED, batch_cols=width)
-        _check_batch(h, srcs, out, st, 1e-9, None)
+        for chunks in (1, 3):
+            out, st = G.query_batch(srcs, ALPHA, 1e-9, P.MIXED, batch_cols=width, sweep_chunks=chunks)
+            _check_batch(h, srcs, out, st, 1e-9, None)
 
 
 def test_outputs_device_and_residual(c1):

@@ -32,7 +32,7 @@ def test_block_refill_and_alone_equals_in_mix(c1):
     G = P.Graph.from_synth(c1)
     srcs = [int(s) for s in synth.sources(c1.n, 12)]
     lams = [1e-8 if k % 2 == 0 else 1e-6 for k in range(12)]
-    blk = P.Block(G, 4, ALPHA)
+    blk = P.Block(G, 4, ALPHA, sweep_chunks=4)
     pending = list(range(12))
     slot_of = {}
     results = {}
@@ -71,7 +71,7 @@ def test_block_refill_and_alone_equals_in_mix(c1):
         assert cert <= lams[k] * (1 + 1e-6) + 1e-15
         truth = oracle.powitr(c1, srcs[k], ALPHA, 135)
         assert np.abs(out - truth).sum() <= lams[k] + SLACK
-        alone, sal = G.query_batch([srcs[k]], ALPHA, lams[k], P.MIXED, batch_cols=4)
+        alone, sal = G.query_batch([srcs[k]], ALPHA, lams[k], P.MIXED, batch_cols=4, sweep_chunks=4)
         assert np.abs(alone[0] - out).sum() <= SLACK, k
         assert sal[0]["sweeps"] == stats["sweeps"]
         assert sal[0]["refreshes"] == stats["refreshes"]
