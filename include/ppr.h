@@ -193,6 +193,26 @@ ppr_status ppr_debug_sweep_fp64(ppr_graph* g, double alpha, const double* r_in, 
                                 double* pi, double* r_sum_out);
 
 /*
+ * One global sweep of the batched mixed path, for tests: the block
+ * Gauss-Seidel sweep over `chunks` row chunks of about m / chunks in-edges
+ * (chunk j starts at the first row whose CSC offset reaches floor(m j /
+ * chunks)); with chunks = 1 it is the Eq. 7 step.  Row u of chunk j gets
+ *   y_out(u) = (1-alpha)/d_u * ( sum_{v in N_in(u), v <  lo_j} y_out(v)
+ *                              + sum_{v in N_in(u), v >= lo_j} y_in(v)
+ *                              + fresh * sum_{v in N_in(u), v < lo_j} y_in(v) )
+ * per column, i.e. Algorithm 3's in-place scan taken a chunk at a time in the
+ * y domain (y(v) = (1-alpha) r(v) / d_v).  t_out (nullable) receives the
+ * stage accumulator: y_out, plus y_in for the fresh columns.
+ *   B: power of two in [4, 128]; chunks in [1, 64].
+ *   y_in, y_out, t_out: float[n][B] (node-major), host or device memory.
+ *   fresh: host int32[B] (1: the column's y_in is a residue nobody has
+ *   received yet).
+ */
+ppr_status ppr_debug_sweep_mixed(ppr_graph* g, double alpha, int32_t B, int32_t chunks,
+                                 const float* y_in, const int32_t* fresh, float* y_out,
+                                 float* t_out);
+
+/*
  * Autotuner of the batched path: for each candidate block width (a power of
  * two in [4, 128]; widths NULL = {8, 16, 32, 64, 128}) whose state fits half
  * of the free device memory, time a few global sweeps on this graph with

@@ -15,6 +15,9 @@ of the paper it restates:
 - ``powerpush_sync``   -- the level-synchronous schedule of the GPU path:
                           iterations S^(j) pushed simultaneously, then Eq. 7 sweeps
 - ``sim_sweep``        -- one Simultaneous Forward Push iteration (Eq. 7)
+- ``block_gs_sweep``   -- one global sweep in block Gauss-Seidel order (Algorithm 3's
+                          in-place scan taken a chunk of rows at a time; Eq. 7 for one chunk)
+- ``chunk_bounds``     -- the row chunks of about m / chunks in-edges that sweep uses
 - ``powitr``           -- power iteration (Eqs. 3-5), compensated, used as truth
 - ``certificate``      -- ||e_s - pi_hat (I - (1-alpha) P)/alpha||_1 (from Eq. 1)
 
@@ -73,6 +76,8 @@ def _load():
     lib.oracle_sum.argtypes = [i64, vp]
     lib.oracle_csc.restype = ctypes.c_int
     lib.oracle_csc.argtypes = [i32, i64, vp, vp, vp, vp, vp]
+    lib.oracle_block_gs_sweep.restype = None
+    lib.oracle_block_gs_sweep.argtypes = [i32, vp, vp, vp, f64, i32, vp, vp, ctypes.c_int, vp]
     lib.oracle_push.restype = None
     lib.oracle_push.argtypes = [vp, vp, f64, vp, vp, i32]
     lib.oracle_fifo_fwdpush.restype = i64
@@ -191,6 +196,29 @@ def sim_sweep(g, alpha: float, r_in: np.ndarray, pi: np.ndarray):
     assert pi.dtype == np.float64 and pi.flags.c_contiguous
     _load().oracle_sim_sweep(g.n, _p(rp), _p(col), alpha, _p(r_in), _p(r_out), _p(pi))
     return r_out
+
+
+def chunk_bounds(g, chunks: int) -> np.ndarray:
+    """Row chunks of about m / chunks in-edges: lo[j] = the first row whose
+    CSC offset reaches floor(m j / chunks); lo[0] = 0, lo[chunks] = n."""
+    col_ptr, _, _ = csc(g)
+    want = (np.int64(g.m) * np.arange(chunks + 1, dtype=np.int64)) // chunks
+    lo = np.searchsorted(col_ptr, want, side="left").astype(np.int64)
+    lo = np.minimum(lo, g.n)
+    lo[0], lo[-1] = 0, g.n
+    return np.maximum.accumulate(lo).astype(np.int32)
+
+
+def block_gs_sweep(g, alpha: float, lo, y_old, fresh: bool = False, csc_arrays=None) -> np.ndarray:
+    """One global sweep in block Gauss-Seidel order over the row chunks lo
+    (y domain; see oracle_block_gs_sweep).  Returns y_new."""
+    col_ptr, row_idx, deg = csc_arrays if csc_arrays is not None else csc(g)
+    lo = np.ascontiguousarray(lo, dtype=np.int32)
+    y_old = np.ascontiguousarray(y_old, dtype=np.float64)
+    y_new = np.zeros(g.n)
+    _load().oracle_block_gs_sweep(g.n, _p(col_ptr), _p(row_idx), _p(deg), alpha, len(lo) - 1, _p(lo),
+                                  _p(y_old), 1 if fresh else 0, _p(y_new))
+    return y_new
 
 
 def powitr(g, s: int, alpha: float, K: int = 135) -> np.ndarray:

@@ -273,6 +273,44 @@ void oracle_sim_sweep(int32_t n, const int64_t* row_ptr, const int32_t* col, dou
 }
 
 /* ------------------------------------------------------------------ */
+/* One global sweep in block Gauss-Seidel order, written in the y       */
+/* domain: y(v) = (1 - alpha) r(v) / d_v is what each out-neighbour of  */
+/* v receives when v pushes r(v) (the push of Section 3.2).  The rows   */
+/* are cut into chunks [lo[j], lo[j+1]); chunk j is handled after       */
+/* chunks 0..j-1, and node u of chunk j pushes everything it received   */
+/* since its previous push:                                             */
+/*   y_new(u) = (1-alpha)/d_u * ( sum_{v in N_in(u), v <  lo[j]} y_new(v) */
+/*                              + sum_{v in N_in(u), v >= lo[j]} y_old(v) */
+/*                              + fresh * sum_{v in N_in(u), v < lo[j]} y_old(v) ) */
+/* i.e. the in-place scan of Algorithm 3's global phase taken one chunk  */
+/* at a time (a node sees the pushes of earlier chunks made in the same  */
+/* scan).  y_old holds the previous sweep's pushes, of which nodes in    */
+/* later chunks already received their share; with fresh = 1 it holds a  */
+/* residue nobody has received yet (the first sweep after a residue is   */
+/* formed), which every out-neighbour receives in this sweep.  One chunk */
+/* (lo = {0, n}) is Eq. 7.  Uses the CSC of oracle_csc.                  */
+/* ------------------------------------------------------------------ */
+void oracle_block_gs_sweep(int32_t n, const int64_t* col_ptr, const int32_t* row_idx, const int32_t* deg,
+                           double alpha, int32_t chunks, const int32_t* lo, const double* y_old, int fresh,
+                           double* y_new) {
+    for (int32_t j = 0; j < chunks; ++j) {
+        for (int32_t u = lo[j]; u < lo[j + 1]; ++u) {
+            double acc = 0.0;
+            for (int64_t e = col_ptr[u]; e < col_ptr[u + 1]; ++e) {
+                int32_t v = row_idx[e];
+                if (v < lo[j]) {
+                    acc += y_new[v];
+                    if (fresh) acc += y_old[v];
+                } else {
+                    acc += y_old[v];
+                }
+            }
+            y_new[u] = (1.0 - alpha) / (double)deg[u] * acc;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
 /* The level-synchronous schedule that the GPU path runs, stated with   */
 /* the paper's objects:                                                 */
 /*  - local phase: the iterations S^(j) of Section 4.2, each performed  */

@@ -35,7 +35,7 @@ EXPORTS = [
     "ppr_graph_copy_csc", "ppr_query", "ppr_query_batch", "ppr_query_ex",
     "ppr_debug_sweep_fp64", "ppr_version", "ppr_last_error", "ppr_autotune",
     "ppr_block_create", "ppr_block_destroy", "ppr_block_footprint", "ppr_slot_admit",
-    "ppr_block_step", "ppr_block_poll", "ppr_slot_retire",
+    "ppr_block_step", "ppr_block_poll", "ppr_slot_retire", "ppr_debug_sweep_mixed",
 ]
 
 
@@ -96,6 +96,7 @@ def load() -> ctypes.CDLL:
         "ppr_query_ex": (st, [vp, vp, i32, f64, f64, vp, vp, vp, vp]),
         "ppr_debug_sweep_fp64": (st, [vp, f64, vp, vp, vp, vp]),
         "ppr_autotune": (st, [vp, f64, vp, i32, vp, vp]),
+        "ppr_debug_sweep_mixed": (st, [vp, f64, i32, i32, vp, vp, vp, vp]),
         "ppr_block_create": (st, [vp, i32, f64, vp, ctypes.POINTER(vp)]),
         "ppr_block_destroy": (st, [vp]),
         "ppr_block_footprint": (st, [vp, i32, vp]),
@@ -288,6 +289,23 @@ class Block:
         st = Stats()
         _check(load().ppr_slot_retire(self._h, int(slot), _ptr(out), ctypes.byref(st)))
         return out, st.as_dict()
+
+
+def debug_sweep_mixed(graph: "Graph", alpha: float, y_in, fresh, chunks: int = 1, t_out=None):
+    """One batched global sweep (block Gauss-Seidel over `chunks` row chunks).
+    y_in: float32[n, B] (numpy or device tensor); fresh: B flags.  Returns y_out
+    (same kind as y_in)."""
+    B = int(y_in.shape[1])
+    fr = np.ascontiguousarray(np.asarray(fresh, dtype=np.int32).reshape(-1))
+    if len(fr) != B:
+        raise ValueError("fresh needs one flag per column")
+    if isinstance(y_in, np.ndarray):
+        y_out = np.empty_like(y_in)
+    else:
+        y_out = y_in.new_empty(y_in.shape)
+    _check(load().ppr_debug_sweep_mixed(graph.handle, float(alpha), B, int(chunks), _ptr(y_in), _ptr(fr),
+                                        _ptr(y_out), _ptr(t_out) if t_out is not None else None))
+    return y_out
 
 
 def version() -> str:

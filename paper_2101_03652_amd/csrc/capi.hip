@@ -179,6 +179,22 @@ ppr_status ppr_autotune(ppr_graph* gh, double alpha, const int32_t* widths, int3
     });
 }
 
+ppr_status ppr_debug_sweep_mixed(ppr_graph* gh, double alpha, int32_t B, int32_t chunks, const float* y_in,
+                                 const int32_t* fresh, float* y_out, float* t_out) {
+    return guarded([&] {
+        Graph* g = reinterpret_cast<Graph*>(gh);
+        if (!g || !y_in || !fresh || !y_out) fail(PPR_ERR_ARG, "NULL argument");
+        if (!(alpha > 0.0 && alpha < 1.0)) fail(PPR_ERR_ARG, "alpha must lie in (0, 1)");
+        if (B < 4 || B > 128 || (B & (B - 1))) fail(PPR_ERR_ARG, "B must be a power of two in [4, 128]");
+        if (chunks < 1 || chunks > 64) fail(PPR_ERR_ARG, "chunks must lie in [1, 64]");
+        HIPCHECK(hipSetDevice(g->device));
+        (void)is_device_ptr(y_in, g->device);              // rejects another device's memory
+        (void)is_device_ptr(y_out, g->device);
+        if (t_out) (void)is_device_ptr(t_out, g->device);
+        debug_sweep_mixed(*g, alpha, B, chunks, y_in, fresh, y_out, t_out);
+    });
+}
+
 // ---------------------------------------------------------------- serving
 
 ppr_status ppr_block_create(ppr_graph* gh, int32_t slots, double alpha, const ppr_options* opt, ppr_block** out) {

@@ -173,7 +173,7 @@ const Schedule& Graph::schedule(int32_t nnz_cap, int32_t row_cap, int32_t chunks
     std::vector<int32_t> lo(chunks + 1, n);
     lo[0] = 0;
     for (int32_t j = 1; j < chunks; ++j) {
-        const int64_t want = (int64_t)((double)m * j / chunks);
+        const int64_t want = m * (int64_t)j / chunks;      // floor(m j / chunks)
         int32_t r = (int32_t)(std::lower_bound(cp, cp + n + 1, want) - cp);
         lo[j] = std::max(lo[j - 1], std::min(r, n));
     }

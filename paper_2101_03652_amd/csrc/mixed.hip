@@ -695,6 +695,34 @@ void autotune_width(Graph& g, double alpha, const int32_t* widths, int32_t count
     if (best) *best = best_w;
 }
 
+// ======================================================================== one sweep (tests)
+
+void debug_sweep_mixed(Graph& g, double alpha, int32_t B, int32_t chunks, const float* y_in,
+                       const int32_t* fresh, float* y_out, float* t_out) {
+    HIPCHECK(hipSetDevice(g.device));
+    ppr_options opt;
+    ppr_options_default(&opt);
+    opt.sweep_chunks = chunks;
+    Block blk(g, B, alpha, opt);
+    MixedCtx& c = *blk.c;
+    hipStream_t ss = c.stream;
+    const size_t bytes = 4 * (size_t)g.n * (size_t)B;
+    HIPCHECK(hipMemcpyAsync(c.Y0.p, y_in, bytes, hipMemcpyDefault, ss));
+    HIPCHECK(hipMemsetAsync(c.T.p, 0, bytes, ss));
+    std::vector<int32_t> one(B, 1), fr(fresh, fresh + B), zero(B, 0);
+    blk.upload_i32(c.kb, one);
+    blk.upload_i32(c.entry, fr);
+    HIPCHECK(hipMemsetAsync(c.step.p, 0, 4, ss));
+    mk::sweep(c, g, c.Y0.as<float>(), c.Y1.as<float>());
+    HIPCHECK(hipMemcpyAsync(y_out, c.Y1.p, bytes, hipMemcpyDefault, ss));
+    if (t_out) HIPCHECK(hipMemcpyAsync(t_out, c.T.p, bytes, hipMemcpyDefault, ss));
+    blk.upload_i32(c.kb, zero);
+    blk.upload_i32(c.entry, zero);
+    for (DevBuf* d : {&c.Y0, &c.Y1, &c.T}) HIPCHECK(hipMemsetAsync(d->p, 0, d->bytes, ss));
+    HIPCHECK(hipStreamSynchronize(ss));
+    c.ycur = c.Y0.as<float>();
+}
+
 // ======================================================================== serving mechanism
 
 void* serve_block_create(Graph& g, int32_t slots, double alpha, const ppr_options& opt) {

@@ -217,6 +217,9 @@ void run_mixed_batch(Graph& g, const int32_t* sources, int32_t B, double alpha, 
 void autotune_width(Graph& g, double alpha, const int32_t* widths, int32_t count, int32_t* best,
                     double* cost_us);
 
+void debug_sweep_mixed(Graph& g, double alpha, int32_t B, int32_t chunks, const float* y_in,
+                       const int32_t* fresh, float* y_out, float* t_out);
+
 // serving blocks (continuous batching); the handle is an opaque Block*
 void* serve_block_create(Graph& g, int32_t slots, double alpha, const ppr_options& opt);
 void serve_block_destroy(void* blk);

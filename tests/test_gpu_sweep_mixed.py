@@ -1,0 +1,77 @@
+"""The batched mixed path's global sweep against the oracle, element by
+element: one block Gauss-Seidel sweep (Eq. 7 for one chunk) on FP32 inputs,
+computed by the library in FP32 and by the oracle in FP64 from the same
+FP32 values, every column (fresh and continuing ones mixed), widths 4..128,
+1..8 row chunks, long rows cut into pieces (the hub graph).
+
+Tolerance: all inputs are >= 0, so a row sum of k terms in FP32 is within
+(k - 1) u of the exact value relative to itself (u = 2^-24); a row also
+inherits the relative error of the values earlier chunks produced in the
+same sweep, themselves sums of at most max_in terms, and the FP32 scale adds
+one rounding.  Per element: (d_in(u) + max_in + 3) u relative.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_2101_03652_amd")
+
+pytestmark = pytest.mark.gpu
+ALPHA = 0.2
+U = 2.0 ** -24
+
+
+def _graphs():
+    from test_gpu_fp64 import _hub_graph
+    return {"c1": synth.chunglu(10_000, 100_000, 2.1), "hub": _hub_graph()}
+
+
+@pytest.fixture(scope="module")
+def graphs():
+    return _graphs()
+
+
+@pytest.mark.parametrize("name", ["c1", "hub"])
+@pytest.mark.parametrize("width,chunks", [(4, 1), (4, 5), (32, 1), (32, 3), (32, 8), (128, 1), (128, 4)])
+def test_sweep_matches_oracle(graphs, name, width, chunks):
+    g = graphs[name]
+    print(f"[gpu] batched sweep parity {name} width={width} chunks={chunks}", flush=True)
+    G = P.Graph.from_synth(g)
+    rng = np.random.default_rng(width * 100 + chunks)
+    y = rng.random((g.n, width)).astype(np.float32)
+    y[rng.random((g.n, width)) < 0.3] = 0.0             # sparse residues
+    fresh = (rng.random(width) < 0.5).astype(np.int32)
+    fresh[0], fresh[-1] = 1, 0
+    t_out = np.empty_like(y)
+    got = P.debug_sweep_mixed(G, ALPHA, y, fresh, chunks=chunks, t_out=t_out)
+    csc_arrays = oracle.csc(g)
+    col_ptr = csc_arrays[0]
+    din = np.diff(col_ptr).astype(np.float64)
+    lo = oracle.chunk_bounds(g, chunks)
+    tol_rel = (din + din.max() + 3) * U
+    for b in range(width):
+        want = oracle.block_gs_sweep(g, ALPHA, lo, y[:, b].astype(np.float64), bool(fresh[b]),
+                                     csc_arrays=csc_arrays)
+        err = np.abs(got[:, b] - want)
+        assert np.all(err <= tol_rel * want + 1e-38), (b, int(np.argmax(err - tol_rel * want)))
+        # stage accumulator: the new residue, plus the fresh residue's alpha-part
+        t_want = want + (y[:, b] if fresh[b] else 0.0)
+        assert np.all(np.abs(t_out[:, b] - t_want) <= tol_rel * t_want + 2 * U * t_want + 1e-38), b
+    G.close()
+
+
+def test_sweep_device_buffers_and_errors(graphs):
+    g = graphs["c1"]
+    G = P.Graph.from_synth(g)
+    y = torch.rand((g.n, 8), dtype=torch.float32, device="cuda")
+    got = P.debug_sweep_mixed(G, ALPHA, y, [1] * 8, chunks=2)
+    host = P.debug_sweep_mixed(G, ALPHA, y.cpu().numpy(), [1] * 8, chunks=2)
+    assert np.array_equal(got.cpu().numpy(), host)          # same kernels, same order
+    with pytest.raises(P.PPRError):
+        P.debug_sweep_mixed(G, ALPHA, np.zeros((g.n, 6), np.float32), [0] * 6)
+    with pytest.raises(P.PPRError):
+        P.debug_sweep_mixed(G, ALPHA, np.zeros((g.n, 8), np.float32), [0] * 8, chunks=0)
+    G.close()
