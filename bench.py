@@ -32,10 +32,10 @@ HBM_PEAK_GBS = 8000.0
 
 
 def sweep_bytes(n: int, m: int, width: int) -> int:
-    """Algorithmic bytes of one batched sweep: in-edge indices (4 m), per-node
-    CSC offset and FP32 scale (8 n), and per (node, column) 16 bytes: the
-    residue row read once, the new residue written, the per-stage reserve
-    accumulator read and written."""
+    """Algorithmic bytes of one batched global sweep (all its row chunks):
+    in-edge indices (4 m), per-node CSC offset and FP32 scale (8 n), and per
+    (node, column) 16 bytes: the residue row read once, the new residue
+    written, the per-stage reserve accumulator read and written."""
     return 4 * m + 8 * n + 16 * n * width
 
 
@@ -47,28 +47,31 @@ def fp64_sweep_bytes(n: int, m: int) -> int:
 
 
 def kernel_source_digest() -> str:
-    """Digest of the batched-path source: counter readings are valid only for
-    the kernel they were taken on."""
+    """Digest of the batched-path kernel sources: counter readings are valid
+    only for the kernels they were taken on."""
     import hashlib
-    path = os.path.join(ROOT, "paper_2101_03652_amd", "csrc", "mixed_kernels.hip")
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name in ("mixed_kernels.hip", "mixed_internal.h"):
+        with open(os.path.join(ROOT, "paper_2101_03652_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
-def measured_traffic(width: int):
-    """HBM bytes per sweep launch from the committed rocprofv3 counter runs
-    (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter's reading for a
-    plain 1 GiB copy), or None when they were taken on another kernel build
-    or width."""
-    path = os.path.join(ROOT, "profiles", "sweep_b_traffic.json")
+def measured_traffic(width: int, chunks: int):
+    """HBM bytes per global sweep (its sweep_k and combine_k launches) from
+    the committed rocprofv3 counter runs (FETCH_SIZE + WRITE_SIZE, each scaled
+    by the same counter's reading for a plain 1 GiB copy), or None when they
+    were taken on another kernel build, width or chunk count."""
+    path = os.path.join(ROOT, "profiles", "sweep_k_traffic.json")
     try:
         with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("source_digest") != kernel_source_digest() or t.get("batch_cols") != width:
+    if (t.get("source_digest") != kernel_source_digest() or t.get("batch_cols") != width
+            or t.get("sweep_chunks") != chunks):
         return None
-    return t.get("bytes_per_launch")
+    return t.get("bytes_per_sweep")
 
 
 def main() -> int:
@@ -187,7 +190,8 @@ def main() -> int:
         torch.cuda.synchronize()
         del x, y
 
-    traffic = measured_traffic(width)
+    chunks = stats_all[0][0]["sweep_chunks"]
+    traffic = measured_traffic(width, chunks)
 
     cpu = None
     if args.cpu_baseline:
@@ -219,18 +223,24 @@ def main() -> int:
         "data": "synthetic",
         "config": {
             "workload": f"chung-lu n={g.n} m={g.m} gamma={args.gamma} alpha={args.alpha} "
-                        f"lambda={args.lam:g}, {args.sources} sources per step, batched mixed, B={width}",
-            "n": g.n, "m": g.m, "sources_per_step": args.sources, "batch_cols": width,
+                        f"lambda={args.lam:g}, {args.sources} sources per step, batched mixed, B={width}, "
+                        f"{chunks} sweep chunks",
+            "n": g.n, "m": g.m, "sources_per_step": args.sources, "batch_cols": width, "sweep_chunks": chunks,
             "alpha": args.alpha, "lambda": args.lam,
         },
         "gteps": round(edges / dt / 1e9, 3),
         "max_cert_l1": max_cert,
         "fp64_plain": fp64,
         "speedup_vs_fp64_plain": round(qps / f64_qps, 2) if f64_qps else None,
-        "roofline": {"bound": "hbm", "kernel": f"sweep_b<C={width // 4}>", "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": traffic, "bytes_per_launch": bytes_per,
-                     "avg_launch_ms": round(avg_sweep_ms, 4)},
+        # one "launch" here is one global sweep: `chunks` launches of sweep_k
+        # (block Gauss-Seidel row chunks) and their combine_k launches, timed
+        # together with HIP events on the library's stream
+        "roofline": {"bound": "hbm", "kernel": f"sweep_k<C={width // 4}> x{chunks} chunks + combine_k",
+                     "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "traffic_GBps": round(traffic / (avg_sweep_ms * 1e-3) / 1e9, 1) if traffic else None,
+                     "bytes_per_launch": bytes_per, "avg_launch_ms": round(avg_sweep_ms, 4),
+                     "launch": "one global sweep"},
         "cpu_baseline": cpu,
         "graph_create_ms": round(info["build_ms"], 1),
     }

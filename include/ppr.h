@@ -90,6 +90,7 @@ typedef struct {
                                calls; refresh passes excluded) */
     int32_t sweep_launches; /* sweep kernel launches that sweep_ms covers */
     int32_t batch_cols;     /* block width used (1 for PPR_FP64) */
+    int32_t sweep_chunks;   /* row chunks per global sweep (1 = Eq. 7 order) */
 } ppr_stats;
 
 /* Query options (ppr_options_default fills the defaults). */

@@ -51,7 +51,7 @@ class Stats(ctypes.Structure):
                 ("edge_pushes", ctypes.c_int64), ("r_sum", ctypes.c_double),
                 ("cert_l1", ctypes.c_double), ("ms", ctypes.c_double),
                 ("sweep_ms", ctypes.c_double), ("sweep_launches", ctypes.c_int32),
-                ("batch_cols", ctypes.c_int32)]
+                ("batch_cols", ctypes.c_int32), ("sweep_chunks", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

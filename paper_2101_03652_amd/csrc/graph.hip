@@ -158,17 +158,21 @@ size_t Graph::device_bytes() const {
     return b;
 }
 
-const Schedule& Graph::schedule(int32_t nnz_cap, int32_t row_cap, int32_t chunks, bool split) {
+const Schedule& Graph::schedule(int32_t nnz_cap, int32_t row_cap, int32_t chunks, int32_t rounds) {
     std::lock_guard<std::mutex> lk(sched_mu);
     chunks = std::max<int32_t>(1, std::min<int32_t>(chunks, n));
+    const bool split = rounds > 0;
     for (auto& s : schedules)
-        if (s->nnz_cap == nnz_cap && s->row_cap == row_cap && s->chunks == chunks && s->split == split) return *s;
+        if (s->nnz_cap == nnz_cap && s->row_cap == row_cap && s->chunks == chunks && s->split == split &&
+            s->rounds == std::max(rounds, 1))
+            return *s;
     // Row chunks: contiguous row ranges of about m / chunks in-edges each
     // (boundaries depend on the graph alone).  Inside a chunk, contiguous row
     // ranges with at most nnz_cap in-edges and row_cap rows.  A row with more
-    // in-edges than nnz_cap either gets a block of its own, listed first, or
-    // (split) is cut into pieces of nnz_cap in-edges whose partial sums are
-    // added afterwards.
+    // in-edges than nnz_cap gets a block of its own, listed first; with
+    // rounds > 0 that block runs up to `rounds` rounds of nnz_cap in-edges,
+    // and a row longer than that is cut into pieces of rounds * nnz_cap
+    // in-edges whose partial sums are added afterwards.
     const int64_t* cp = h_col_ptr.data();
     std::vector<int32_t> lo(chunks + 1, n);
     lo[0] = 0;
@@ -189,12 +193,15 @@ const Schedule& Graph::schedule(int32_t nnz_cap, int32_t row_cap, int32_t chunks
         while (r < rend) {
             int64_t d = cp[r + 1] - cp[r];
             if (d > nnz_cap) {
-                if (split) {
-                    const int32_t np = (int32_t)((d + nnz_cap - 1) / nnz_cap);
+                const int64_t piece_cap = (int64_t)nnz_cap * rounds;
+                if (split && d <= piece_cap) {
+                    longb.push_back({r, r + 1, (int32_t)d, -2, cp[r]});
+                } else if (split) {
+                    const int32_t np = (int32_t)((d + piece_cap - 1) / piece_cap);
                     lrows.push_back({r, slot, np, 0});
                     for (int32_t p = 0; p < np; ++p) {
-                        const int64_t e = cp[r] + (int64_t)p * nnz_cap;
-                        longb.push_back({r, r + 1, (int32_t)std::min<int64_t>(nnz_cap, cp[r + 1] - e), slot++, e});
+                        const int64_t e = cp[r] + (int64_t)p * piece_cap;
+                        longb.push_back({r, r + 1, (int32_t)std::min<int64_t>(piece_cap, cp[r + 1] - e), slot++, e});
                     }
                 } else {
                     longb.push_back({r, r + 1, 0, -1, 0});
@@ -224,6 +231,7 @@ const Schedule& Graph::schedule(int32_t nnz_cap, int32_t row_cap, int32_t chunks
     s->row_cap = row_cap;
     s->chunks = chunks;
     s->split = split;
+    s->rounds = std::max(rounds, 1);
     s->n_long = nlong[0];
     s->n_blocks = (int32_t)all.size();
     s->n_pieces = slot;
@@ -232,7 +240,7 @@ const Schedule& Graph::schedule(int32_t nnz_cap, int32_t row_cap, int32_t chunks
     s->lo = lo;
     s->lr_first = lr_first;
     for (RowBlock& b : all) {
-        if (b.piece >= 0) continue;         // pieces carry their own edge range
+        if (b.piece != -1) continue;        // long rows and pieces carry their own edge range
         b.e0 = cp[b.r0];
         b.ne = (int32_t)std::min<int64_t>(cp[b.r1] - cp[b.r0], INT32_MAX);
     }

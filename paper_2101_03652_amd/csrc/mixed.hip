@@ -75,10 +75,11 @@ int64_t frontier_capacity(const Graph& g, const ppr_options& opt, int Bw) {
 
 size_t mixed_footprint(const Graph& g, int Bw, int64_t fcap) {
     const size_t nb = (size_t)g.n * (size_t)Bw;
-    // long-row pieces: each holds nnz_cap = kLdsBytes / (4 Bw) in-edges of a
-    // row with more than nnz_cap, so there are fewer than 2 m / nnz_cap
-    const size_t nnz_cap = (size_t)mk::kLdsBytes / (4 * (size_t)Bw);
-    const size_t pieces = 2 * (size_t)g.m / nnz_cap + 1;
+    // long-row pieces: each holds piece_cap = kLongRounds kLdsBytes / (4 Bw)
+    // in-edges of a row with more than piece_cap, so there are fewer than
+    // 2 m / piece_cap
+    const size_t piece_cap = (size_t)mk::kLongRounds * mk::kLdsBytes / (4 * (size_t)Bw);
+    const size_t pieces = 2 * (size_t)g.m / piece_cap + 1;
     return 16 * nb                       // FP64 local-phase scratch
            + 20 * nb                     // Y0, Y1, Shi, Slo, T
            + 4 * (size_t)Bw * pieces     // partial sums of the pieces
@@ -530,6 +531,7 @@ struct Block {
         st->sweep_ms = sweep_ms;
         st->sweep_launches = sweep_launches;
         st->batch_cols = Bw;
+        st->sweep_chunks = c->chunks;
     }
 
     // Export slot b (DONE) into out[n] (host or device) and free the slot;

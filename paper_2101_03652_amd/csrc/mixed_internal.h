@@ -9,6 +9,7 @@ namespace mk {
 constexpr int kBlock = 256;
 constexpr int kLdsBytes = 16384;   // staging budget of the sweep / refresh blocks
 constexpr int kGridRed = 2048;     // persistent grid of the refresh (fixed -> deterministic sums)
+constexpr int kLongRounds = 8;     // edge rounds one sweep block runs on a long row
 
 // Sweep blocks: <= kNnz in-edges (B = 4C columns, C float4 chunks) and <= kRows rows.
 template <int C>

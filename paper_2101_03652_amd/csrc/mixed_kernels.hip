@@ -240,12 +240,13 @@ __global__ void scale_k(const int32_t* __restrict__ deg, int32_t n, double alpha
 // set holds a fresh residue in Y_in that nobody has pulled yet: its rows pull
 // it along every in-edge, in addition to the new values of earlier chunks.
 //
-// Schedule blocks hold <= Sw<C>::kNnz in-edges: up to Sw<C>::kRows whole
-// rows, or one piece of a long row.  Row bounds and indices are loaded
-// first; every thread then has kItems float4 gathers in flight, staged in
-// LDS; T2 threads per (row, chunk) add the row's slice.  A piece writes its
-// raw sum to a partial slot; combine_k adds a long row's pieces in slot
-// order and finishes the row.  Y_out is read (rows < lo) and written
+// Schedule blocks: up to Sw<C>::kRows whole rows with <= Sw<C>::kNnz in-edges
+// (one round), or one long row of up to kLongRounds rounds of Sw<C>::kNnz
+// in-edges, or one piece (kLongRounds rounds) of a longer row.  Per round,
+// indices are loaded first, then every thread has kItems float4 gathers in
+// flight, staged in LDS; T2 threads per (row, chunk) add the row's slice.
+// A piece writes its raw sum to a partial slot; combine_k adds a long row's
+// pieces in slot order and finishes the row.  Y_out is read (rows < lo) and written
 // (rows >= lo) in the same launch, so it carries no __restrict__.
 template <int C>
 __device__ inline float4 gather_gs(const float4* __restrict__ Y_in, const float4* Y_out, int32_t v, int c,
@@ -294,9 +295,9 @@ __global__ __launch_bounds__(kBlock) void sweep_k(
     float4 enf = make_float4(0.f, 0.f, 0.f, 0.f);
     if (step == 0 && lo > 0) enf = flag4(reinterpret_cast<const int4*>(entry)[threadIdx.x % C]);
     const bool fresh = (enf.x + enf.y + enf.z + enf.w) != 0.f;
-    const bool piece = b.piece >= 0;
+    const bool whole = b.piece == -1;              // whole rows, one round
     const int32_t r0 = b.r0;
-    const int32_t R = piece ? 1 : b.r1 - r0;
+    const int32_t R = whole ? b.r1 - r0 : 1;
     const int32_t ne = b.ne;
     const int64_t e0 = b.e0;
     // (row, chunk) groups of T2 consecutive lanes (inside one wave)
@@ -307,37 +308,39 @@ __global__ __launch_bounds__(kBlock) void sweep_k(
     const int32_t row = grp / C;
     const int c = grp % C;
     int32_t s0 = 0, s1 = 0;
-    if (row < R) {
-        if (piece) {
-            s1 = ne;
-        } else {
-            s0 = (int32_t)((int64_t)col_ptr[r0 + row] - e0);
-            s1 = (int32_t)((int64_t)col_ptr[r0 + row + 1] - e0);
-        }
+    if (whole && row < R) {
+        s0 = (int32_t)((int64_t)col_ptr[r0 + row] - e0);
+        s1 = (int32_t)((int64_t)col_ptr[r0 + row + 1] - e0);
     }
-    int32_t vv[P::kItems];
-#pragma unroll
-    for (int k = 0; k < P::kItems; ++k) {
-        int32_t it = threadIdx.x + k * kBlock;
-        vv[k] = (it / C < ne) ? row_idx[e0 + it / C] : -1;
-    }
-    float4 gv[P::kItems];
-#pragma unroll
-    for (int k = 0; k < P::kItems; ++k) {
-        gv[k] = (vv[k] >= 0) ? gather_gs<C>(Y_in, Y_out, vv[k], threadIdx.x % C, lo, fresh, enf)
-                             : make_float4(0.f, 0.f, 0.f, 0.f);
-    }
-#pragma unroll
-    for (int k = 0; k < P::kItems; ++k) {
-        int32_t it = threadIdx.x + k * kBlock;
-        if (it / C < ne) lds[it] = gv[k];
-    }
-    __syncthreads();
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int32_t e = s0 + sub; e < s1; e += T2) acc = f4_add(acc, lds[e * C + c]);
+    // a long row (or piece) runs rounds of P::kNnz in-edges through LDS
+    for (int32_t base = 0; base < ne; base += P::kNnz) {
+        const int32_t nr = min(P::kNnz, ne - base);
+        int32_t vv[P::kItems];
+#pragma unroll
+        for (int k = 0; k < P::kItems; ++k) {
+            int32_t it = threadIdx.x + k * kBlock;
+            vv[k] = (it / C < nr) ? row_idx[e0 + base + it / C] : -1;
+        }
+        float4 gv[P::kItems];
+#pragma unroll
+        for (int k = 0; k < P::kItems; ++k) {
+            gv[k] = (vv[k] >= 0) ? gather_gs<C>(Y_in, Y_out, vv[k], threadIdx.x % C, lo, fresh, enf)
+                                 : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        if (base > 0) __syncthreads();             // the previous round's LDS reads are done
+#pragma unroll
+        for (int k = 0; k < P::kItems; ++k) {
+            int32_t it = threadIdx.x + k * kBlock;
+            if (it / C < nr) lds[it] = gv[k];
+        }
+        __syncthreads();
+        if (!whole && row == 0) { s0 = 0; s1 = nr; }
+        for (int32_t e = s0 + sub; e < s1; e += T2) acc = f4_add(acc, lds[e * C + c]);
+    }
     for (int o = T2 >> 1; o >= 1; o >>= 1) acc = f4_add(acc, f4_shfl_xor(acc, o));
     if (row >= R || sub != 0) return;
-    if (piece) {
+    if (b.piece >= 0) {
         partials[(int64_t)b.piece * C + c] = acc;
         return;
     }
@@ -575,7 +578,9 @@ __global__ void export_col_k(int32_t n, int shift, int32_t b, const int32_t* __r
 
 // ---------------------------------------------------------------- launch helpers
 template <int C>
-const Schedule& sweep_schedule(Graph& g, int chunks) { return g.schedule(Sw<C>::kNnz, Sw<C>::kRows, chunks, true); }
+const Schedule& sweep_schedule(Graph& g, int chunks) {
+    return g.schedule(Sw<C>::kNnz, Sw<C>::kRows, chunks, kLongRounds);
+}
 template <int C>
 const Schedule& refresh_schedule(Graph& g) { return g.schedule(Rf<C>::kNnz, Rf<C>::kRows); }
 

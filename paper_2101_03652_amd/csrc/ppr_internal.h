@@ -74,8 +74,10 @@ struct PinnedBuf {
 struct RowBlock {
     int32_t r0, r1;      // rows [r0, r1)
     int32_t ne;          // in-edges of the block
-    int32_t piece;       // -1, or: the block is one piece of the long row r0 and writes
-                         // its partial sum into partial slot `piece`
+    int32_t piece;       // -1: whole rows [r0, r1) with at most one round of in-edges;
+                         // -2: the whole long row r0, in several rounds;
+                         // >= 0: one piece of the long row r0, whose sum goes to
+                         // partial slot `piece`
     int64_t e0;          // offset of the first in-edge (= col_ptr[r0] unless a piece)
 };
 
@@ -90,7 +92,8 @@ struct Schedule {
     int32_t nnz_cap = 0;       // edge budget per block
     int32_t row_cap = 0;       // row budget per block
     int32_t chunks = 1;        // row chunks (contiguous row ranges of about m / chunks in-edges)
-    bool split = false;        // long rows split into pieces (else one block per long row)
+    bool split = false;        // long rows in rounds / pieces (else one block per long row)
+    int32_t rounds = 1;        // split: edge rounds (of nnz_cap) one block may run
     int32_t n_long = 0;        // leading blocks that hold a single long row (chunks == 1, !split)
     int32_t n_blocks = 0;
     int32_t n_pieces = 0;      // partial slots of a split schedule
@@ -136,7 +139,7 @@ struct Graph {
     int live_blocks = 0;                               // serving blocks on this graph (pool_mu)
     ~Graph();
     size_t device_bytes() const;
-    const Schedule& schedule(int32_t nnz_cap, int32_t row_cap, int32_t chunks = 1, bool split = false);
+    const Schedule& schedule(int32_t nnz_cap, int32_t row_cap, int32_t chunks = 1, int32_t rounds = 0);
 };
 
 Graph* graph_create(const int64_t* row_ptr, const int32_t* col, int32_t n, int64_t m,

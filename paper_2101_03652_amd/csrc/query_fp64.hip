@@ -227,6 +227,7 @@ void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_
         st->sweep_ms = sweep_ms;
         st->sweep_launches = timed_sweeps;
         st->batch_cols = 1;
+        st->sweep_chunks = 1;
         st->local_levels = levels;
         st->sweeps = sweeps;
         st->refreshes = 0;
