@@ -89,6 +89,10 @@ def main() -> int:
     ap.add_argument("--fp64-queries", type=int, default=8)
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--extra-widths", default="8,32",
+                    help="also time one step at these block widths (empty: skip)")
+    ap.add_argument("--single-sources", type=int, default=32,
+                    help="sources answered one at a time by the FP64 and the mixed path (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also copy a 1 GiB device buffer (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -181,6 +185,46 @@ def main() -> int:
                 "queries": args.fp64_queries}
         print(f"[bench] fp64: {f64_qps:.1f} q/s, sweep {f64_sweep_ms:.3f} ms", file=sys.stderr, flush=True)
 
+    # the same step at other block widths (one timed step each)
+    widths = {}
+    for w in [int(x) for x in args.extra_widths.split(",") if x.strip()]:
+        if w == width:
+            continue
+        step_w = lambda: G.query_batch(srcs, args.alpha, args.lam, P.MIXED, out=out, batch_cols=w)[1]
+        step_w()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st_w = step_w()
+        torch.cuda.synchronize()
+        dt_w = time.perf_counter() - t1
+        per_w = st_w[0]["sweep_ms"] / max(st_w[0]["sweep_launches"], 1)
+        widths[str(w)] = {"value": round(args.sources / dt_w, 3), "unit": "queries/s",
+                          "ms_per_sweep": round(per_w, 4),
+                          "sweep_GBps_algorithmic": round(sweep_bytes(g.n, g.m, w) / (per_w * 1e-3) / 1e9, 1)}
+        print(f"[bench] width {w}: {widths[str(w)]}", flush=True, file=sys.stderr)
+
+    # sources one at a time: plain FP64 path against the mixed path (one column)
+    single = {}
+    if args.single_sources > 0:
+        one = torch.empty((1, g.n), dtype=torch.float64, device="cuda")
+        ss = srcs[:args.single_sources]
+        for lam in (1e-6, 1e-8):
+            row = {}
+            for name, prec, extra in (("fp64", P.FP64, {}), ("mixed", P.MIXED, {"batch_cols": 4})):
+                G.query_batch([ss[0]], args.alpha, lam, prec, out=one, **extra)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                certs = []
+                for s_ in ss:
+                    st1 = G.query_batch([s_], args.alpha, lam, prec, out=one, certify=1, **extra)[1][0]
+                    certs.append(st1["cert_l1"])
+                torch.cuda.synchronize()
+                dt1 = time.perf_counter() - t1
+                row[name] = {"value": round(len(ss) / dt1, 3), "unit": "queries/s",
+                             "max_cert_l1": max(certs)}
+            single[f"{lam:g}"] = row
+            print(f"[bench] one at a time, lambda={lam:g}: {row}", flush=True, file=sys.stderr)
+
     if args.calibrate_copy:
         x = torch.empty(2 ** 28, dtype=torch.float32, device="cuda")
         x.fill_(1.0)
@@ -241,7 +285,12 @@ def main() -> int:
                      "traffic_GBps": round(traffic / (avg_sweep_ms * 1e-3) / 1e9, 1) if traffic else None,
                      "bytes_per_launch": bytes_per, "avg_launch_ms": round(avg_sweep_ms, 4),
                      "launch": "one global sweep"},
+        "batched_widths": widths,
+        "single_source": single,
         "cpu_baseline": cpu,
+        "paper_context": {"figure": "PowerPush < 40 s per query (no GPU or throughput figures in the paper)",
+                          "hardware": "one Intel 2.0 GHz CPU server, 144 GB RAM, sequential C++ (GCC 9.3 -O3)",
+                          "precision": "FP64", "workload": "Orkut, n=3.07M, m=234M, alpha=0.2, lambda=min(1e-8, 1/m)"},
         "graph_create_ms": round(info["build_ms"], 1),
     }
     print(json.dumps(rec), flush=True)

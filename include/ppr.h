@@ -133,13 +133,16 @@ void ppr_options_default(ppr_options* opt);
  *   row_ptr: host int64[n+1], row_ptr[0] = 0, non-decreasing, row_ptr[n] = m.
  *   col:     host int32[m], col[row_ptr[v] .. row_ptr[v+1]) = out-neighbours of v.
  *   n >= 1, m >= n (every node needs an out-edge).
- *   flags:   PPR_GRAPH_TRUST_INPUT skips the O(n + m) host validation.
+ *   flags:   PPR_GRAPH_TRUST_INPUT skips the O(n + m) host validation;
+ *            PPR_GRAPH_WIDE_OFFSETS stores the device CSC offsets as int64 even
+ *            when m < 2^32 (they are int64 whenever m >= 2^32).
  * Validation (unless skipped): PPR_ERR_CSR, PPR_ERR_DANGLING, PPR_ERR_DUPLICATE.
  * Self-loops are allowed.  The library builds on the current HIP device the
  * in-edge lists (CSC, each list ascending by source id), the out-degree
  * table and the sweep schedule.  *out receives the handle.
  */
 #define PPR_GRAPH_TRUST_INPUT 1u
+#define PPR_GRAPH_WIDE_OFFSETS 2u
 ppr_status ppr_graph_create(const int64_t* row_ptr, const int32_t* col, int32_t n, int64_t m,
                             uint32_t flags, ppr_graph** out);
 

@@ -28,6 +28,7 @@ MIXED = 1
 SWITCH_NODES = 0
 SWITCH_EDGES = 1
 GRAPH_TRUST_INPUT = 1
+GRAPH_WIDE_OFFSETS = 2
 
 # every symbol include/ppr.h declares (checked by the CPU tests)
 EXPORTS = [
@@ -147,7 +148,7 @@ class Graph:
     """A device-resident graph (CSC built on the GPU from CSR out-edges)."""
 
     def __init__(self, row_ptr: np.ndarray, col: np.ndarray, n: int | None = None,
-                 trust_input: bool = False):
+                 trust_input: bool = False, wide_offsets: bool = False):
         lib = load()
         self._row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
         self._col = np.ascontiguousarray(col, dtype=np.int32)
@@ -155,14 +156,16 @@ class Graph:
         self.m = int(len(self._col))
         h = ctypes.c_void_p()
         _check(lib.ppr_graph_create(_ptr(self._row_ptr), _ptr(self._col) if self.m else None,
-                                    self.n, self.m, GRAPH_TRUST_INPUT if trust_input else 0,
+                                    self.n, self.m,
+                                    (GRAPH_TRUST_INPUT if trust_input else 0) |
+                                    (GRAPH_WIDE_OFFSETS if wide_offsets else 0),
                                     ctypes.byref(h)))
         self._h = h
         del self._row_ptr, self._col
 
     @classmethod
-    def from_synth(cls, g, trust_input: bool = False) -> "Graph":
-        return cls(g.row_ptr, g.col, g.n, trust_input=trust_input)
+    def from_synth(cls, g, trust_input: bool = False, wide_offsets: bool = False) -> "Graph":
+        return cls(g.row_ptr, g.col, g.n, trust_input=trust_input, wide_offsets=wide_offsets)
 
     @property
     def handle(self):

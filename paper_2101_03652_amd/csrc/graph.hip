@@ -259,6 +259,7 @@ Graph* graph_create(const int64_t* row_ptr, const int32_t* col, int32_t n, int64
     if (!row_ptr || !col) fail(PPR_ERR_ARG, "row_ptr and col must not be NULL");
     if (n < 1) fail(PPR_ERR_ARG, "n must be >= 1");
     if (m < n) fail(PPR_ERR_DANGLING, "m < n: some node has out-degree 0");
+    if (flags & ~(PPR_GRAPH_TRUST_INPUT | PPR_GRAPH_WIDE_OFFSETS)) fail(PPR_ERR_ARG, "unknown graph flags");
     if (!(flags & PPR_GRAPH_TRUST_INPUT)) graph_validate(row_ptr, col, n, m);
     else if (row_ptr[0] != 0 || row_ptr[n] != m) fail(PPR_ERR_CSR, "row_ptr[0] must be 0 and row_ptr[n] = m");
 
@@ -272,7 +273,7 @@ Graph* graph_create(const int64_t* row_ptr, const int32_t* col, int32_t n, int64
     HIPCHECK(hipGetDevice(&g->device));
     g->n = n;
     g->m = m;
-    g->off64 = m >= (int64_t)UINT32_MAX;
+    g->off64 = m >= (int64_t)UINT32_MAX || (flags & PPR_GRAPH_WIDE_OFFSETS) != 0;
     hipStream_t s;
     HIPCHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
     struct StreamGuard { hipStream_t s; ~StreamGuard() { (void)hipStreamDestroy(s); } } sg{s};
@@ -322,7 +323,16 @@ Graph* graph_create(const int64_t* row_ptr, const int32_t* col, int32_t n, int64
 
 void graph_copy_csc(const Graph& g, int64_t* col_ptr, int32_t* row_idx, int32_t* deg) {
     HIPCHECK(hipSetDevice(g.device));
-    if (col_ptr) std::memcpy(col_ptr, g.h_col_ptr.data(), sizeof(int64_t) * ((size_t)g.n + 1));
+    if (col_ptr) {   // the device offsets themselves, widened when stored as uint32
+        if (g.off64) {
+            HIPCHECK(hipMemcpy(col_ptr, g.col_ptr.p, sizeof(int64_t) * ((size_t)g.n + 1), hipMemcpyDeviceToHost));
+        } else {
+            std::vector<uint32_t> narrow((size_t)g.n + 1);
+            HIPCHECK(hipMemcpy(narrow.data(), g.col_ptr.p, sizeof(uint32_t) * ((size_t)g.n + 1),
+                               hipMemcpyDeviceToHost));
+            for (size_t i = 0; i < narrow.size(); ++i) col_ptr[i] = (int64_t)narrow[i];
+        }
+    }
     if (row_idx) HIPCHECK(hipMemcpy(row_idx, g.row_idx.p, sizeof(int32_t) * (size_t)g.m, hipMemcpyDeviceToHost));
     if (deg) HIPCHECK(hipMemcpy(deg, g.deg.p, sizeof(int32_t) * (size_t)g.n, hipMemcpyDeviceToHost));
 }

@@ -13,8 +13,8 @@ certified retirement) is libppr's serving block (ppr_block_* / ppr_slot_*).
   that fits (halving down to 4), after destroying idle blocks of other graphs
   if that is what it takes.  A query whose graph cannot get even a 4-slot
   block within the budget, or that finds the graph's queue full, is refused.
-- Blocks of different graphs run on their own streams; the loop never waits
-  on one block while another has finished work to collect.
+- Blocks of different graphs run on their own streams, each driven by its
+  own worker thread, so one block's waits never hold up another's work.
 
 Latency is measured from a query's arrival to its result in host memory.
 """
@@ -91,10 +91,17 @@ class Server:
 
     graphs: list of paper_2101_03652_amd.Graph.  budget_bytes: device memory
     the graphs and blocks may hold together.  keep_results: resolve futures
-    with (pi_hat copy, stats) instead of stats alone."""
+    with (pi_hat copy, stats) instead of stats alone.
+
+    One worker thread per graph drives that graph's block: wait for the
+    block's enqueued work, retire the finished slots, refill the free slots
+    from the graph's queue, enqueue the next sweeps.  The library calls
+    release the interpreter lock, so one block's waits (and the local phase
+    of newly admitted queries) never hold up the others."""
 
     def __init__(self, graphs, budget_bytes: int, slots: int = 32, alpha: float = 0.2,
                  sweeps_per_step: int = 8, max_queue: int = 100000, keep_results: bool = False):
+        import threading
         import torch
         import paper_2101_03652_amd as P
         self.P = P
@@ -108,32 +115,42 @@ class Server:
         self.graph_bytes = sum(int(g.info()["device_bytes"]) for g in self.graphs)
         if self.graph_bytes > self.budget:
             raise ValueError(f"the graphs alone ({self.graph_bytes} B) exceed the budget ({self.budget} B)")
-        self.blocks = [None] * len(self.graphs)
-        self.block_bytes = [0] * len(self.graphs)
+        k = len(self.graphs)
+        self.blocks = [None] * k
+        self.block_bytes = [0] * k
         self.slot_req = [dict() for _ in self.graphs]        # slot -> Request
         self.queues = [deque() for _ in self.graphs]
+        self._in_use = [False] * k                           # a worker is inside its block's step
         self.committed = self.graph_bytes
         self.peak_committed = self.committed
         self.refused = 0
         self.failed = 0
         self.completed = []                                   # (Request, latency_ms, stats)
         self._rid = 0
+        self._error = None
+        self._stop = False
+        self._cv = threading.Condition()
         # one pinned host buffer per graph receives retired results
         self._host = [torch.empty(g.n, dtype=torch.float64, pin_memory=True) for g in self.graphs]
+        self._workers = [threading.Thread(target=self._worker, args=(i,), daemon=True) for i in range(k)]
+        for t in self._workers:
+            t.start()
 
     # -------------------------------------------------------- admission
     def submit(self, graph: int, source: int, lam: float, t_arrival: float | None = None) -> Future:
         req = Request(self._rid, int(graph), int(source), float(lam),
                       time.perf_counter() if t_arrival is None else t_arrival)
-        self._rid += 1
         g = self.graphs[req.graph]
-        if self.blocks[req.graph] is None and \
-                self.graph_bytes + self.P.Block.footprint(g, 4) > self.budget:
-            self._refuse(req, "no block of this graph fits the memory budget")
-        elif len(self.queues[req.graph]) >= self.max_queue:
-            self._refuse(req, "queue full")
-        else:
-            self.queues[req.graph].append(req)
+        small = self.P.Block.footprint(g, 4)
+        with self._cv:
+            self._rid += 1
+            if self.blocks[req.graph] is None and self.graph_bytes + small > self.budget:
+                self._refuse(req, "no block of this graph fits the memory budget")
+            elif len(self.queues[req.graph]) >= self.max_queue:
+                self._refuse(req, "queue full")
+            else:
+                self.queues[req.graph].append(req)
+                self._cv.notify_all()
         return req.future
 
     def _refuse(self, req: Request, why: str) -> None:
@@ -141,9 +158,11 @@ class Server:
         req.future.set_exception(Refused(why))
 
     def _idle(self, i: int) -> bool:
-        return self.blocks[i] is not None and not self.slot_req[i] and not self.queues[i]
+        return (self.blocks[i] is not None and not self.slot_req[i] and not self.queues[i]
+                and not self._in_use[i])
 
     def _open_block(self, i: int) -> bool:
+        """With the lock held: create graph i's block within the budget."""
         g = self.graphs[i]
         fp = lambda w: self.P.Block.footprint(g, w)
         w = choose_slots(self.budget - self.committed, fp, self.max_slots)
@@ -167,55 +186,99 @@ class Server:
         self.committed -= self.block_bytes[i]
         self.block_bytes[i] = 0
 
-    # -------------------------------------------------------- loop
-    def pump(self) -> bool:
-        """One pass over the graphs: collect finished work, retire, refill,
-        step.  Returns True if anything is still queued or running."""
-        busy = False
-        for i, g in enumerate(self.graphs):
-            if self.blocks[i] is None:
-                if not self.queues[i] or not self._open_block(i):
-                    busy |= bool(self.queues[i])
-                    continue
-            blk = self.blocks[i]
-            st = blk.poll(wait=False)
-            if not st["ready"]:
-                busy = True
-                continue
-            for slot in st["done"]:
-                req = self.slot_req[i].pop(slot)
+    # -------------------------------------------------------- workers
+    def _worker(self, i: int) -> None:
+        try:
+            while True:
+                with self._cv:
+                    while not self._stop and not self.queues[i] and not self.slot_req[i]:
+                        self._cv.wait()
+                    if self._stop:
+                        return
+                    if self.blocks[i] is None and not self._open_block(i):
+                        self._cv.wait(0.01)          # budget held by other graphs' blocks
+                        continue
+                    blk = self.blocks[i]
+                    self._in_use[i] = True
                 try:
-                    _, stats = blk.retire(slot, out=self._host[i])
-                except self.P.PPRError as e:          # reached its sweep cap uncertified
+                    self._serve(i, blk)
+                finally:
+                    with self._cv:
+                        self._in_use[i] = False
+                        self._cv.notify_all()
+        except BaseException as e:                    # surfaced by run_until_idle / replay
+            with self._cv:
+                self._error = e
+                self._cv.notify_all()
+
+    def _serve(self, i: int, blk) -> None:
+        st = blk.poll(wait=True)
+        for slot in st["done"]:
+            req = self.slot_req[i][slot]
+            try:
+                _, stats = blk.retire(slot, out=self._host[i])
+                err = None
+            except self.P.PPRError as e:              # reached its sweep cap uncertified
+                stats, err = None, e
+            t_done = time.perf_counter()
+            with self._cv:
+                del self.slot_req[i][slot]
+                if err is not None:
                     self.failed += 1
-                    req.future.set_exception(e)
-                    continue
-                t_done = time.perf_counter()
-                lat = (t_done - req.t_arrival) * 1e3
-                self.completed.append((req, lat, stats))
-                if self.keep_results:
-                    req.future.set_result((self._host[i].numpy().copy(), stats))
                 else:
-                    req.future.set_result(stats)
-            while self.queues[i] and len(self.slot_req[i]) < blk.slots:
-                req = self.queues[i].popleft()
-                slot = blk.admit(req.source, req.lam)
+                    self.completed.append((req, (t_done - req.t_arrival) * 1e3, stats))
+            if err is not None:
+                req.future.set_exception(err)
+            elif self.keep_results:
+                req.future.set_result((self._host[i].numpy().copy(), stats))
+            else:
+                req.future.set_result(stats)
+        with self._cv:
+            take = []
+            while self.queues[i] and len(self.slot_req[i]) + len(take) < blk.slots:
+                take.append(self.queues[i].popleft())
+        for req in take:
+            slot = blk.admit(req.source, req.lam)
+            with self._cv:
                 self.slot_req[i][slot] = req
-            if self.slot_req[i]:
-                blk.step(self.sweeps_per_step)
-                busy = True
-        return busy
+        if self.slot_req[i]:
+            blk.step(self.sweeps_per_step)
+
+    # -------------------------------------------------------- control
+    def busy(self) -> bool:
+        with self._cv:
+            return any(self.queues) or any(self.slot_req)
+
+    def _check(self) -> None:
+        if self._error is not None:
+            raise RuntimeError("serving worker failed") from self._error
+
+    def pump(self) -> bool:
+        """Returns True while anything is queued or running (the workers do the work)."""
+        self._check()
+        return self.busy()
 
     def run_until_idle(self, timeout_s: float = 600.0) -> None:
         t_end = time.perf_counter() + timeout_s
-        while self.pump():
-            if time.perf_counter() > t_end:
-                raise TimeoutError("server did not drain")
+        with self._cv:
+            while any(self.queues) or any(self.slot_req) or any(self._in_use):
+                if self._error is not None:
+                    break
+                if time.perf_counter() > t_end:
+                    raise TimeoutError("server did not drain")
+                self._cv.wait(0.05)
+        self._check()
 
     def close(self) -> None:
-        for i in range(len(self.graphs)):
-            if self.blocks[i] is not None:
-                self._close_block(i)
+        with self._cv:
+            self._stop = True
+            self._cv.notify_all()
+        for t in self._workers:
+            t.join()
+        with self._cv:
+            for i in range(len(self.graphs)):
+                if self.blocks[i] is not None:
+                    self._close_block(i)
 
 
 # ---------------------------------------------------------------- measurement
@@ -229,25 +292,26 @@ def replay(server: Server, t_off, gid, lam, sources, timeout_s: float = 900.0, p
     f0 = server.failed
     shown = 0
     start = time.perf_counter()
-    k = 0
     N = len(t_off)
     t_end = start + timeout_s
-    while True:
-        now = time.perf_counter()
-        while k < N and start + t_off[k] <= now:
-            server.submit(int(gid[k]), int(sources[k]), float(lam[k]), t_arrival=start + float(t_off[k]))
-            k += 1
-        busy = server.pump()
+    for k in range(N):
+        delay = start + float(t_off[k]) - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        server.submit(int(gid[k]), int(sources[k]), float(lam[k]), t_arrival=start + float(t_off[k]))
         done = len(server.completed) - n0
         if progress and done >= shown + progress:
             shown = done - done % progress
             print(f"[serve] {done}/{N} served, {time.perf_counter() - start:.1f} s", file=sys.stderr, flush=True)
-        if k >= N and not busy:
-            break
-        if now > t_end:
+    while server.pump():
+        if time.perf_counter() > t_end:
             raise TimeoutError("replay did not finish")
-        if not busy and k < N:
-            time.sleep(min(0.0005, max(0.0, start + t_off[k] - time.perf_counter())))
+        time.sleep(0.005)
+        done = len(server.completed) - n0
+        if progress and done >= shown + progress:
+            shown = done - done % progress
+            print(f"[serve] {done}/{N} served, {time.perf_counter() - start:.1f} s", file=sys.stderr, flush=True)
+    server.run_until_idle()
     wall = time.perf_counter() - start
     lats = [lat for _, lat, _ in server.completed[n0:]]
     return {"queries": N, "served": len(lats), "refused": server.refused - r0,

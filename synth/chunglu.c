@@ -29,6 +29,16 @@
 #include <string.h>
 #include <math.h>
 #include <omp.h>
+#include <stdio.h>
+
+/* Progress lines on stderr when PPR_SYNTH_VERBOSE is set (large graphs take minutes). */
+static void progress(const char* what, int64_t a) {
+    const char* v = getenv("PPR_SYNTH_VERBOSE");
+    if (v && v[0] && v[0] != '0') {
+        fprintf(stderr, "[synth] %s %lld\n", what, (long long)a);
+        fflush(stderr);
+    }
+}
 
 static inline uint64_t sm64_mix(uint64_t z) {
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
@@ -92,15 +102,58 @@ static double build_cdf(int32_t n, int64_t m, double gamma, double* cdf) {
     return acc;
 }
 
-/* Rank drawn proportionally to the weights: first i with cdf[i] > x. */
-static inline int32_t sample_rank(const double* cdf, int32_t n, double total, uint64_t r) {
-    double x = unit(r) * total;
-    int32_t lo = 0, hi = n - 1;
+/* First i in [lo, hi] with cdf[i] > x (hi if none). */
+static inline int32_t first_above(const double* cdf, int32_t lo, int32_t hi, double x) {
     while (lo < hi) {
         int32_t mid = lo + (hi - lo) / 2;
         if (cdf[mid] > x) hi = mid; else lo = mid + 1;
     }
     return lo;
+}
+
+/* Rank drawn proportionally to the weights: first i with cdf[i] > x. */
+static inline int32_t sample_rank(const double* cdf, int32_t n, double total, uint64_t r) {
+    return first_above(cdf, 0, n - 1, unit(r) * total);
+}
+
+/* The same draw through a guide table (Chen and Asau): guide[k] is the answer
+   for x = k * total / K, so the answer for x in bucket k lies in
+   [guide[k], guide[k+1]]; the two checks catch a bucket index that rounding
+   put next to the right one, and then the full search decides.  Returns
+   exactly what sample_rank returns. */
+typedef struct {
+    const double* cdf;
+    int32_t n;
+    double total, inv;
+    int64_t K;
+    int32_t* guide;
+} sampler_t;
+
+static void sampler_init(sampler_t* S, const double* cdf, int32_t n, double total) {
+    S->cdf = cdf;
+    S->n = n;
+    S->total = total;
+    S->K = n;
+    S->inv = (double)S->K / total;
+    S->guide = (int32_t*)malloc(sizeof(int32_t) * ((size_t)S->K + 1));
+    if (!S->guide) return;
+    int32_t i = 0;
+    for (int64_t k = 0; k <= S->K; ++k) {
+        double x = (double)k * (total / (double)S->K);
+        while (i < n - 1 && !(cdf[i] > x)) ++i;
+        S->guide[k] = i;
+    }
+}
+
+static inline int32_t sampler_draw(const sampler_t* S, uint64_t r) {
+    double x = unit(r) * S->total;
+    int64_t k = (int64_t)(x * S->inv);
+    if (k < 0) k = 0;
+    if (k >= S->K) k = S->K - 1;
+    int32_t lo = S->guide[k], hi = S->guide[k + 1];
+    if ((lo > 0 && S->cdf[lo - 1] > x) || (hi < S->n - 1 && !(S->cdf[hi] > x)))
+        return first_above(S->cdf, 0, S->n - 1, x);
+    return first_above(S->cdf, lo, hi, x);
 }
 
 static void permutation(int32_t n, uint64_t seed, uint64_t stream, int32_t* p) {
@@ -161,11 +214,17 @@ int synth_chunglu(int32_t n, int64_t m, double gamma_out, double gamma_in, uint6
     int64_t* cnt = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n + 1));
     int64_t* fill = (int64_t*)malloc(sizeof(int64_t) * (size_t)n);
     cand_t* cand = NULL; uint32_t* keys = NULL;
+    sampler_t s_out, s_in;
+    s_out.guide = NULL;
+    s_in.guide = NULL;
     if (!cdf_out || !cdf_in || !perm_out || !perm_in || !first || !cnt || !fill) { rc = -2; goto done; }
 
     double tot_out = build_cdf(n, m, gamma_out, cdf_out);
     double tot_in = build_cdf(n, m, gamma_in, cdf_in);
     if (tot_out <= 0.0 || tot_in <= 0.0) { rc = -2; goto done; }
+    sampler_init(&s_out, cdf_out, n, tot_out);
+    sampler_init(&s_in, cdf_in, n, tot_in);
+    if (!s_out.guide || !s_in.guide) { rc = -2; goto done; }
     permutation(n, seed, ST_PERM_OUT, perm_out);
     permutation(n, seed, ST_PERM_IN, perm_in);
 
@@ -175,7 +234,7 @@ int synth_chunglu(int32_t n, int64_t m, double gamma_out, double gamma_in, uint6
         uint64_t att = 0;
         int32_t v;
         do {
-            v = perm_in[sample_rank(cdf_in, n, tot_in, draw(seed, ST_MIN, (uint64_t)u * 64 + att))];
+            v = perm_in[sampler_draw(&s_in, draw(seed, ST_MIN, (uint64_t)u * 64 + att))];
             ++att;
         } while (v == u && att < 64);
         if (v == u) v = (u + 1) % n;
@@ -187,28 +246,31 @@ int synth_chunglu(int32_t n, int64_t m, double gamma_out, double gamma_in, uint6
     for (int attempt = 0; attempt < 16; ++attempt) {
         if (K > (int64_t)0xFFFFFFF0LL) K = (int64_t)0xFFFFFFF0LL;
         free(cand); free(keys); cand = NULL; keys = NULL;
+        progress("candidate draws", K);
         /* pass 1: count the non-self-loop candidates of each source row */
         memset(cnt, 0, sizeof(int64_t) * ((size_t)n + 1));
         #pragma omp parallel for schedule(static)
         for (int64_t k = 0; k < K; ++k) {
-            int32_t u = perm_out[sample_rank(cdf_out, n, tot_out, draw(seed, ST_U, (uint64_t)k))];
-            int32_t v = perm_in[sample_rank(cdf_in, n, tot_in, draw(seed, ST_V, (uint64_t)k))];
+            int32_t u = perm_out[sampler_draw(&s_out, draw(seed, ST_U, (uint64_t)k))];
+            int32_t v = perm_in[sampler_draw(&s_in, draw(seed, ST_V, (uint64_t)k))];
             if (u != v) __atomic_fetch_add(&cnt[u + 1], 1, __ATOMIC_RELAXED);
         }
         for (int32_t u = 0; u < n; ++u) cnt[u + 1] += cnt[u];
         for (int32_t u = 0; u < n; ++u) fill[u] = cnt[u];
         cand = (cand_t*)malloc(sizeof(cand_t) * (size_t)(cnt[n] > 0 ? cnt[n] : 1));
         if (!cand) { rc = -2; goto done; }
+        progress("pass 2, candidates", cnt[n]);
         /* pass 2: redraw and place (order inside a row is fixed by the sort below) */
         #pragma omp parallel for schedule(static)
         for (int64_t k = 0; k < K; ++k) {
-            int32_t u = perm_out[sample_rank(cdf_out, n, tot_out, draw(seed, ST_U, (uint64_t)k))];
-            int32_t v = perm_in[sample_rank(cdf_in, n, tot_in, draw(seed, ST_V, (uint64_t)k))];
+            int32_t u = perm_out[sampler_draw(&s_out, draw(seed, ST_U, (uint64_t)k))];
+            int32_t v = perm_in[sampler_draw(&s_in, draw(seed, ST_V, (uint64_t)k))];
             if (u != v) {
                 int64_t pos = __atomic_fetch_add(&fill[u], 1, __ATOMIC_RELAXED);
                 cand[pos].v = v; cand[pos].k = (uint32_t)k;
             }
         }
+        progress("dedup rows", n);
         /* per row: the first occurrence (smallest k) of each target survives,
            unless the target is the row's guaranteed edge; the rest get v = -1 */
         int64_t survivors = 0;
@@ -236,6 +298,7 @@ int synth_chunglu(int32_t n, int64_t m, double gamma_out, double gamma_in, uint6
             for (int64_t i = 0; i < cnt[n]; ++i) if (cand[i].v >= 0) keys[ns++] = cand[i].k;
             kcut = select_kth(keys, ns, target - 1);
         }
+        progress("assemble, survivors", survivors);
         /* assemble the CSR */
         row_ptr[0] = 0;
         for (int32_t u = 0; u < n; ++u) {
@@ -273,6 +336,6 @@ int synth_chunglu(int32_t n, int64_t m, double gamma_out, double gamma_in, uint6
     rc = -3;
 done:
     free(cdf_out); free(cdf_in); free(perm_out); free(perm_in); free(first);
-    free(cnt); free(fill); free(cand); free(keys);
+    free(cnt); free(fill); free(cand); free(keys); free(s_out.guide); free(s_in.guide);
     return rc;
 }

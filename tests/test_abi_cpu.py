@@ -63,6 +63,25 @@ def test_csr_validation_codes():
     rc, _ = _create([0, 3, 4, 5], [2, 1, 2, 2, 0], 3)
     assert rc == -4
     assert b"duplicate" in P.load().ppr_last_error()
+    # unknown flag bits
+    g = synth.fig1()
+    rc, _ = _create(g.row_ptr, g.col, g.n, flags=4)
+    assert rc == -1 and b"flags" in P.load().ppr_last_error()
+
+
+def test_serving_and_debug_entry_points_reject_bad_arguments():
+    lib = P.load()
+    h = ctypes.c_void_p()
+    assert lib.ppr_block_create(None, 8, 0.2, None, ctypes.byref(h)) == -1
+    assert lib.ppr_block_destroy(None) == 0
+    b = ctypes.c_size_t()
+    assert lib.ppr_block_footprint(None, 8, ctypes.byref(b)) == -1
+    slot = ctypes.c_int32()
+    assert lib.ppr_slot_admit(None, 0, 1e-8, ctypes.byref(slot)) == -1
+    assert lib.ppr_block_step(None, 4) == -1
+    assert lib.ppr_block_poll(None, 0, None, None, None, None) == -1
+    assert lib.ppr_slot_retire(None, 0, None, None) == -1
+    assert lib.ppr_debug_sweep_mixed(None, 0.2, 8, 1, None, None, None, None) == -1
 
 
 def test_null_and_range_arguments():

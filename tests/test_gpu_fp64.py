@@ -57,11 +57,14 @@ def hub():
     return _hub_graph()
 
 
+@pytest.mark.parametrize("wide", [False, True])
 @pytest.mark.parametrize("which", ["fig1", "cycle", "c1", "hub"])
-def test_csc_bit_exact(which, c1, hub):
+def test_csc_bit_exact(which, wide, c1, hub):
+    """wide: int64 device CSC offsets (the layout of graphs with m >= 2^32)."""
     g = {"fig1": synth.fig1(), "cycle": synth.cycle(1000), "c1": c1, "hub": hub}[which]
-    print(f"[gpu] csc {which} n={g.n} m={g.m}", flush=True)
-    G = P.Graph.from_synth(g)
+    print(f"[gpu] csc {which} n={g.n} m={g.m} wide={wide}", flush=True)
+    G = P.Graph.from_synth(g, wide_offsets=wide)
+    assert G.info()["offsets_64bit"] == (1 if wide else 0)
     cp, ri, dg = G.csc()
     ocp, ori, odg = oracle.csc(g)
     np.testing.assert_array_equal(cp, ocp)
@@ -114,10 +117,11 @@ def _sync(g, s, lam, rule, param):
     return pi, r, st
 
 
-@pytest.mark.parametrize("rule,param", [(P.SWITCH_EDGES, 8.0), (P.SWITCH_NODES, 1.0)])
+@pytest.mark.parametrize("rule,param,wide", [(P.SWITCH_EDGES, 8.0, False), (P.SWITCH_NODES, 1.0, False),
+                                             (P.SWITCH_EDGES, 8.0, True)])
 @pytest.mark.parametrize("lam", [1e-6, 1e-8])
-def test_query_matches_oracle_sync_c1(c1, rule, param, lam):
-    G = P.Graph.from_synth(c1)
+def test_query_matches_oracle_sync_c1(c1, rule, param, wide, lam):
+    G = P.Graph.from_synth(c1, wide_offsets=wide)
     truth_cache = {}
     for s in synth.sources(c1.n, 3):
         s = int(s)

@@ -1,0 +1,120 @@
+"""Large graph: directed Chung-Lu n = 40,000,000, m = 1,400,000,000 (exponent
+2.0, min out-degree 1, int32 indices, int64 CSR offsets), alpha = 0.2,
+lambda = 1e-8: a batch of 16 sources through the batched mixed path and one
+source through the plain FP64 path, device outputs.
+
+Checks that hold at any size (a converged power iteration per source is out
+of the oracle's reach here): the device CSC equals the oracle's bit for bit;
+the oracle's FP64 certificate of each checked vector is <= lambda and equals
+the library's; |sum(pi_hat) - 1| <= lambda for every column; the batched
+column and the FP64 result for the same source lie within 2 lambda + 1e-9
+of each other.  The global sweeps' algorithmic bytes per HIP-event second
+are printed (and written to gpurun_out/large.json when that folder exists).
+
+Runs only with PPR_LARGE=1: generating the graph on the host and the
+oracle's O(m) passes take several minutes and ~40 GB of host memory.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+P = pytest.importorskip("paper_2101_03652_amd")
+
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(os.environ.get("PPR_LARGE") != "1",
+                                 reason="large-graph run: set PPR_LARGE=1 (minutes, ~40 GB host memory)")]
+ALPHA = 0.2
+LAM = 1e-8
+N, M = 40_000_000, 1_400_000_000
+REPORT = {}
+
+
+@pytest.fixture(scope="module")
+def c4():
+    print("[gpu] large graph: generating n=40M m=1.4B", flush=True)
+    g = synth.chunglu(N, M, 2.0, cache=False)
+    print("[gpu] large graph generated", flush=True)
+    return g
+
+
+@pytest.fixture(scope="module")
+def G(c4):
+    g = P.Graph.from_synth(c4, trust_input=True)
+    REPORT["graph"] = g.info()
+    print(f"[gpu] large graph resident: {REPORT['graph']}", flush=True)
+    yield g
+    g.close()
+
+
+@pytest.fixture(scope="module")
+def srcs(c4):
+    return [int(s) for s in synth.sources(c4.n, 16)]
+
+
+def _dump():
+    if os.path.isdir("gpurun_out"):
+        with open("gpurun_out/large.json", "w") as f:
+            json.dump(REPORT, f, indent=1, default=float)
+
+
+def test_large_csc_bit_exact(c4, G):
+    cp, ri, dg = G.csc()
+    ocp, ori, odg = oracle.csc(c4)
+    assert np.array_equal(cp, ocp)
+    del ocp, cp
+    assert np.array_equal(dg, odg)
+    assert np.array_equal(ri, ori)
+
+
+@pytest.fixture(scope="module")
+def batched(c4, G, srcs):
+    out = torch.empty((16, c4.n), dtype=torch.float64, device="cuda")
+    G.query_batch(srcs[:4], ALPHA, LAM, P.MIXED, batch_cols=16)          # warm-up (schedules, pools)
+    torch.cuda.synchronize()
+    _, st = G.query_batch(srcs, ALPHA, LAM, P.MIXED, out=out, batch_cols=16)
+    torch.cuda.synchronize()
+    s0 = st[0]
+    per = s0["sweep_ms"] / max(s0["sweep_launches"], 1)
+    bytes_per = 4 * M + 8 * N + 16 * N * 16
+    REPORT["batched"] = {"sources": 16, "batch_cols": 16, "sweep_chunks": s0["sweep_chunks"],
+                         "ms": s0["ms"], "queries_per_s": 16 / (s0["ms"] * 1e-3),
+                         "sweeps_per_query": float(np.mean([s["sweeps"] for s in st])),
+                         "ms_per_sweep": per, "algorithmic_GBps": bytes_per / (per * 1e-3) / 1e9,
+                         "max_cert": max(s["cert_l1"] for s in st)}
+    print(f"[gpu] large batched: {REPORT['batched']}", flush=True)
+    _dump()
+    return out.cpu().numpy(), st
+
+
+def test_large_batched_certified(c4, srcs, batched):
+    host, st = batched
+    assert [s["source"] for s in st] == srcs
+    assert all(s["cert_l1"] <= LAM for s in st)
+    sums = host.sum(axis=1)
+    assert np.all(np.abs(sums - 1.0) <= LAM), np.abs(sums - 1.0).max()
+    for b in (0, 9):
+        cert = oracle.certificate(c4, srcs[b], ALPHA, host[b])
+        assert cert <= LAM * (1 + 1e-6), (b, cert)
+        assert st[b]["cert_l1"] == pytest.approx(cert, rel=1e-6, abs=1e-15)
+
+
+def test_large_fp64_single(c4, G, srcs, batched):
+    out = torch.empty(c4.n, dtype=torch.float64, device="cuda")
+    _, st = G.query(srcs[0], ALPHA, LAM, P.FP64, out=out, certify=1)
+    per = st["sweep_ms"] / max(st["sweep_launches"], 1)
+    REPORT["fp64"] = {"ms": st["ms"], "sweeps": st["sweeps"], "local_levels": st["local_levels"],
+                      "ms_per_sweep": per, "algorithmic_GBps": (4 * M + 8 * N + 32 * N) / (per * 1e-3) / 1e9,
+                      "cert": st["cert_l1"]}
+    print(f"[gpu] large fp64: {REPORT['fp64']}", flush=True)
+    _dump()
+    pi = out.cpu().numpy()
+    assert st["cert_l1"] <= LAM
+    assert oracle.certificate(c4, srcs[0], ALPHA, pi) <= LAM * (1 + 1e-9)
+    assert abs(pi.sum() - 1.0) <= LAM
+    assert np.abs(pi - batched[0][0]).sum() <= 2 * LAM + 1e-9

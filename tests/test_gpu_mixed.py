@@ -124,6 +124,10 @@ def test_small_graphs_and_hubs():
         for chunks in (1, 3):
             out, st = G.query_batch(srcs, ALPHA, 1e-9, P.MIXED, batch_cols=width, sweep_chunks=chunks)
             _check_batch(h, srcs, out, st, 1e-9, None)
+    # int64 CSC offsets (the layout of graphs with m >= 2^32)
+    Gw = P.Graph.from_synth(h, wide_offsets=True)
+    out, st = Gw.query_batch(srcs, ALPHA, 1e-9, P.MIXED, batch_cols=32, sweep_chunks=3)
+    _check_batch(h, srcs, out, st, 1e-9, None)
 
 
 def test_outputs_device_and_residual(c1):

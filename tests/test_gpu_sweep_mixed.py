@@ -34,12 +34,13 @@ def graphs():
     return _graphs()
 
 
-@pytest.mark.parametrize("name", ["c1", "hub"])
+@pytest.mark.parametrize("name", ["c1", "hub", "hub-wide"])
 @pytest.mark.parametrize("width,chunks", [(4, 1), (4, 5), (32, 1), (32, 3), (32, 8), (128, 1), (128, 4)])
 def test_sweep_matches_oracle(graphs, name, width, chunks):
-    g = graphs[name]
+    """hub-wide: the hub graph with int64 device CSC offsets."""
+    g = graphs[name.split("-")[0]]
     print(f"[gpu] batched sweep parity {name} width={width} chunks={chunks}", flush=True)
-    G = P.Graph.from_synth(g)
+    G = P.Graph.from_synth(g, wide_offsets=name.endswith("wide"))
     rng = np.random.default_rng(width * 100 + chunks)
     y = rng.random((g.n, width)).astype(np.float32)
     y[rng.random((g.n, width)) < 0.3] = 0.0             # sparse residues
