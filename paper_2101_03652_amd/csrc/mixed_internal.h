@@ -10,6 +10,7 @@ constexpr int kBlock = 256;
 constexpr int kLdsBytes = 16384;   // staging budget of the sweep / refresh blocks
 constexpr int kGridRed = 2048;     // persistent grid of the refresh (fixed -> deterministic sums)
 constexpr int kLongRounds = 8;     // edge rounds one sweep block runs on a long row
+constexpr int kRefreshRounds = 1 << 20;   // a refresh block runs a long row whole
 
 // Sweep blocks: <= kNnz in-edges (B = 4C columns, C float4 chunks) and <= kRows rows.
 template <int C>
@@ -19,11 +20,13 @@ struct Sw {
     static constexpr int kItems = kNnz * C / kBlock;   // = 4
     static constexpr int kSlots = kBlock / C;
 };
-// Refresh blocks gather the hi and lo reserve rows (2 x 16 C bytes per edge).
+// Refresh blocks gather the hi and lo reserve rows (2 x 16 C bytes per edge)
+// through a 32 KB stage per round.
+constexpr int kRfLdsBytes = 32768;
 template <int C>
 struct Rf {
-    static constexpr int kNnz = kLdsBytes / (32 * C);
-    static constexpr int kItems = kNnz * C / kBlock;   // = 2
+    static constexpr int kNnz = kRfLdsBytes / (32 * C);
+    static constexpr int kItems = kNnz * C / kBlock;   // = 4
     static constexpr int kRows = kBlock / C;
 };
 }  // namespace mk

@@ -380,13 +380,18 @@ __global__ void flush_k(int64_t total, float* __restrict__ Shi, float* __restric
 }
 
 // ---------------------------------------------------------------- refresh (FP64)
-// Persistent grid: block k handles schedule blocks k, k + G, ...; thread t
-// always works on chunk t % C (one thread per (row, chunk), rows <= 256 / C),
-// so the per-column sums of |rt| are fixed-order and deterministic.
+// Persistent grid: block k handles schedule blocks k, k + G, ...  A schedule
+// block is up to Rf<C>::kRows whole rows with <= Rf<C>::kNnz in-edges, or one
+// long row, which the block runs in rounds of Rf<C>::kNnz in-edges.  Per
+// round the hi and lo rows of the in-neighbours are staged in LDS and T2
+// threads per (row, chunk) add them in FP64, then a shuffle tree.  The
+// per-column sums of |rt| are deterministic: after each schedule block the
+// threads c < C add that block's rows in row order into their own
+// accumulators (columns 4c..4c+3), which go to partials[block][B].
 template <typename OffT, int C>
 __global__ __launch_bounds__(kBlock) void refresh_k(
         const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
-        const RowBlock* __restrict__ blocks, int32_t n_blocks, int32_t n_long,
+        const RowBlock* __restrict__ blocks, int32_t n_blocks,
         const int32_t* __restrict__ deg, const float4* __restrict__ Shi, const float4* __restrict__ Slo,
         const int32_t* __restrict__ src, const int32_t* __restrict__ rmask, double alpha,
         float4* __restrict__ Y, double* __restrict__ rt_out, int32_t n, double* __restrict__ partials) {
@@ -394,107 +399,85 @@ __global__ __launch_bounds__(kBlock) void refresh_k(
     __shared__ float4 lds_h[P::kNnz * C];
     __shared__ float4 lds_l[P::kNnz * C];
     __shared__ double red[kBlock * 4];
-    const int c = threadIdx.x % C;
-    const int32_t myrow = threadIdx.x / C;
-    double cs0 = 0.0, cs1 = 0.0, cs2 = 0.0, cs3 = 0.0;   // |rt| of columns 4c..4c+3
+    double cs0 = 0.0, cs1 = 0.0, cs2 = 0.0, cs3 = 0.0;   // threads c < C: |rt| of columns 4c..4c+3
     const double inv_oma = 1.0 / (1.0 - alpha);
     const double oma = 1.0 - alpha;
-    const int4 s4 = reinterpret_cast<const int4*>(src)[c];
-    const int4 w4 = reinterpret_cast<const int4*>(rmask)[c];
-    const bool write_any = (w4.x | w4.y | w4.z | w4.w) != 0;
     for (int32_t bi = blockIdx.x; bi < n_blocks; bi += gridDim.x) {
         const RowBlock b = blocks[bi];
-        int32_t u = -1;
+        const bool whole = b.piece == -1;
+        const int32_t r0 = b.r0;
+        const int32_t R = whole ? b.r1 - r0 : 1;
+        const int32_t ne = b.ne;
+        const int64_t e0 = b.e0;
+        int T2 = 1;
+        while (T2 < 64 && 2 * T2 * R * C <= kBlock) T2 <<= 1;
+        const int32_t grp = threadIdx.x / T2;
+        const int sub = threadIdx.x % T2;
+        const int32_t row = grp / C;
+        const int c = grp % C;
+        int32_t s0 = 0, s1 = 0;
+        if (whole && row < R) {
+            s0 = (int32_t)((int64_t)col_ptr[r0 + row] - e0);
+            s1 = (int32_t)((int64_t)col_ptr[r0 + row + 1] - e0);
+        }
         double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
-        if (bi < n_long) {
-            const int slot = threadIdx.x / C;
-            const int64_t e0 = b.e0, e1 = b.e0 + b.ne;
-            for (int64_t e = e0 + slot; e < e1; e += kBlock / C) {
-                int64_t v = row_idx[e];
-                float4 h = Shi[v * C + c], l = Slo[v * C + c];
-                g0 += (double)h.x + (double)l.x;
-                g1 += (double)h.y + (double)l.y;
-                g2 += (double)h.z + (double)l.z;
-                g3 += (double)h.w + (double)l.w;
-            }
-            red[threadIdx.x * 4 + 0] = g0;
-            red[threadIdx.x * 4 + 1] = g1;
-            red[threadIdx.x * 4 + 2] = g2;
-            red[threadIdx.x * 4 + 3] = g3;
-            __syncthreads();
-            if (threadIdx.x < C) {
-                g0 = g1 = g2 = g3 = 0.0;
-                for (int s2 = 0; s2 < kBlock / C; ++s2) {
-                    int t = s2 * C + threadIdx.x;
-                    g0 += red[t * 4 + 0];
-                    g1 += red[t * 4 + 1];
-                    g2 += red[t * 4 + 2];
-                    g3 += red[t * 4 + 3];
-                }
-                u = b.r0;
-            }
-            __syncthreads();
-        } else {
-            const int32_t r0 = b.r0, r1 = b.r1;
-            const int64_t e0 = b.e0;
-            const int32_t ne = b.ne;
-            int32_t s0 = 0, s1 = 0;
-            const bool has = myrow < r1 - r0;
-            if (has) {
-                s0 = (int32_t)((int64_t)col_ptr[r0 + myrow] - e0);
-                s1 = (int32_t)((int64_t)col_ptr[r0 + myrow + 1] - e0);
-            }
+        for (int32_t base = 0; base < ne; base += P::kNnz) {
+            const int32_t nr = min(P::kNnz, ne - base);
             int32_t vv[P::kItems];
 #pragma unroll
             for (int k = 0; k < P::kItems; ++k) {
                 int32_t it = threadIdx.x + k * kBlock;
-                vv[k] = (it / C < ne) ? row_idx[e0 + it / C] : -1;
+                vv[k] = (it / C < nr) ? row_idx[e0 + base + it / C] : -1;
             }
             float4 hv[P::kItems], lv[P::kItems];
 #pragma unroll
             for (int k = 0; k < P::kItems; ++k) {
-                int32_t it = threadIdx.x + k * kBlock;
+                const int64_t i = (int64_t)vv[k] * C + (threadIdx.x % C);
                 if (vv[k] >= 0) {
-                    hv[k] = Shi[(int64_t)vv[k] * C + (it % C)];
-                    lv[k] = Slo[(int64_t)vv[k] * C + (it % C)];
+                    hv[k] = Shi[i];
+                    lv[k] = Slo[i];
                 } else {
                     hv[k] = lv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
                 }
             }
+            __syncthreads();                       // the previous LDS reads are done
 #pragma unroll
             for (int k = 0; k < P::kItems; ++k) {
                 int32_t it = threadIdx.x + k * kBlock;
-                if (it / C < ne) {
+                if (it / C < nr) {
                     lds_h[it] = hv[k];
                     lds_l[it] = lv[k];
                 }
             }
             __syncthreads();
-            for (int32_t e = s0; e < s1; ++e) {
+            if (!whole && row == 0) { s0 = 0; s1 = nr; }
+            for (int32_t e = s0 + sub; e < s1; e += T2) {
                 float4 h = lds_h[e * C + c], l = lds_l[e * C + c];
                 g0 += (double)h.x + (double)l.x;
                 g1 += (double)h.y + (double)l.y;
                 g2 += (double)h.z + (double)l.z;
                 g3 += (double)h.w + (double)l.w;
             }
-            if (has) u = r0 + myrow;
-            __syncthreads();
         }
-        if (u >= 0) {
+        for (int o = T2 >> 1; o >= 1; o >>= 1) {
+            g0 += __shfl_xor(g0, o, 64);
+            g1 += __shfl_xor(g1, o, 64);
+            g2 += __shfl_xor(g2, o, 64);
+            g3 += __shfl_xor(g3, o, 64);
+        }
+        double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+        if (row < R && sub == 0) {
+            const int32_t u = r0 + row;
             const int64_t at = (int64_t)u * C + c;
             const double d = (double)deg[u];
-            float4 h = Shi[at], l = Slo[at];
-            double S0 = (double)h.x + (double)l.x, S1 = (double)h.y + (double)l.y;
-            double S2 = (double)h.z + (double)l.z, S3 = (double)h.w + (double)l.w;
-            double t0 = (s4.x == u ? 1.0 : 0.0) - d * S0 * inv_oma + g0;
-            double t1 = (s4.y == u ? 1.0 : 0.0) - d * S1 * inv_oma + g1;
-            double t2 = (s4.z == u ? 1.0 : 0.0) - d * S2 * inv_oma + g2;
-            double t3 = (s4.w == u ? 1.0 : 0.0) - d * S3 * inv_oma + g3;
-            cs0 += fabs(t0);
-            cs1 += fabs(t1);
-            cs2 += fabs(t2);
-            cs3 += fabs(t3);
-            if (write_any) {
+            const float4 h = Shi[at], l = Slo[at];
+            const int4 s4 = reinterpret_cast<const int4*>(src)[c];
+            const int4 w4 = reinterpret_cast<const int4*>(rmask)[c];
+            t0 = (s4.x == u ? 1.0 : 0.0) - d * ((double)h.x + (double)l.x) * inv_oma + g0;
+            t1 = (s4.y == u ? 1.0 : 0.0) - d * ((double)h.y + (double)l.y) * inv_oma + g1;
+            t2 = (s4.z == u ? 1.0 : 0.0) - d * ((double)h.z + (double)l.z) * inv_oma + g2;
+            t3 = (s4.w == u ? 1.0 : 0.0) - d * ((double)h.w + (double)l.w) * inv_oma + g3;
+            if (w4.x | w4.y | w4.z | w4.w) {
                 float4 y = Y[at];
                 if (w4.x) y.x = (float)(oma * t0 / d);
                 if (w4.y) y.y = (float)(oma * t1 / d);
@@ -509,26 +492,29 @@ __global__ __launch_bounds__(kBlock) void refresh_k(
                 rt_out[(int64_t)(4 * c + 3) * n + u] = t3;
             }
         }
-    }
-    // per-column sums: threads with the same chunk hold columns 4c..4c+3
-    red[threadIdx.x * 4 + 0] = cs0;
-    red[threadIdx.x * 4 + 1] = cs1;
-    red[threadIdx.x * 4 + 2] = cs2;
-    red[threadIdx.x * 4 + 3] = cs3;
-    __syncthreads();
-    if (threadIdx.x < C) {
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-        for (int t = threadIdx.x; t < kBlock; t += C) {
-            a0 += red[t * 4 + 0];
-            a1 += red[t * 4 + 1];
-            a2 += red[t * 4 + 2];
-            a3 += red[t * 4 + 3];
+        // |rt| of this block's rows into the accumulators of threads c < C, in row order
+        red[threadIdx.x * 4 + 0] = fabs(t0);
+        red[threadIdx.x * 4 + 1] = fabs(t1);
+        red[threadIdx.x * 4 + 2] = fabs(t2);
+        red[threadIdx.x * 4 + 3] = fabs(t3);
+        __syncthreads();
+        if ((int)threadIdx.x < C) {
+            for (int32_t rr = 0; rr < R; ++rr) {
+                const int t = T2 * (rr * C + (int)threadIdx.x);
+                cs0 += red[t * 4 + 0];
+                cs1 += red[t * 4 + 1];
+                cs2 += red[t * 4 + 2];
+                cs3 += red[t * 4 + 3];
+            }
         }
+        __syncthreads();                           // red and the LDS stage are reused
+    }
+    if ((int)threadIdx.x < C) {
         double* out = partials + (int64_t)blockIdx.x * (4 * C) + 4 * threadIdx.x;
-        out[0] = a0;
-        out[1] = a1;
-        out[2] = a2;
-        out[3] = a3;
+        out[0] = cs0;
+        out[1] = cs1;
+        out[2] = cs2;
+        out[3] = cs3;
     }
 }
 
@@ -582,7 +568,9 @@ const Schedule& sweep_schedule(Graph& g, int chunks) {
     return g.schedule(Sw<C>::kNnz, Sw<C>::kRows, chunks, kLongRounds);
 }
 template <int C>
-const Schedule& refresh_schedule(Graph& g) { return g.schedule(Rf<C>::kNnz, Rf<C>::kRows); }
+const Schedule& refresh_schedule(Graph& g) {
+    return g.schedule(Rf<C>::kNnz, Rf<C>::kRows, 1, kRefreshRounds);   // long rows whole, in rounds
+}
 
 template <int C>
 void sweep_c(MixedCtx& c, Graph& g, const float* yin, float* yout) {
@@ -630,12 +618,12 @@ void refresh_c(MixedCtx& c, Graph& g, float* y, double* rt_out) {
     auto Y4 = reinterpret_cast<float4*>(y);
     if (g.off64)
         hipLaunchKernelGGL((refresh_k<int64_t, C>), grid, blk, 0, c.stream, g.col_ptr.as<int64_t>(),
-                           g.row_idx.as<int32_t>(), sch.blocks.as<RowBlock>(), sch.n_blocks, sch.n_long,
+                           g.row_idx.as<int32_t>(), sch.blocks.as<RowBlock>(), sch.n_blocks,
                            g.deg.as<int32_t>(), H, L, c.src.as<int32_t>(), c.rmask.as<int32_t>(), c.alpha, Y4,
                            rt_out, g.n, c.partials.as<double>());
     else
         hipLaunchKernelGGL((refresh_k<uint32_t, C>), grid, blk, 0, c.stream, g.col_ptr.as<uint32_t>(),
-                           g.row_idx.as<int32_t>(), sch.blocks.as<RowBlock>(), sch.n_blocks, sch.n_long,
+                           g.row_idx.as<int32_t>(), sch.blocks.as<RowBlock>(), sch.n_blocks,
                            g.deg.as<int32_t>(), H, L, c.src.as<int32_t>(), c.rmask.as<int32_t>(), c.alpha, Y4,
                            rt_out, g.n, c.partials.as<double>());
     hipLaunchKernelGGL(reduce_cols_k, dim3(1), dim3(256), 0, c.stream, c.partials.as<double>(), (int)grid.x, c.Bw,
