@@ -236,9 +236,12 @@ struct Block {
         return -1;
     }
 
-    // sweeps of one stage: until err has fallen by refresh_factor, or to lambda / 2
+    // Sweeps of one stage: until err has fallen by refresh_factor, or to
+    // 0.8 lambda (the margin covers the FP32 rounding a stage adds and a rate
+    // estimate slightly too optimistic; a stage that still ends above lambda
+    // is followed by another).
     int32_t stage_length(const Slot& sl) const {
-        double target = std::max(sl.err / opt.refresh_factor, 0.5 * sl.lambda);
+        double target = std::max(sl.err / opt.refresh_factor, 0.8 * sl.lambda);
         int32_t k = 0;
         for (double x = sl.err; x > target && k < (1 << 20); x *= sl.rho) ++k;
         return std::max<int32_t>(k, 1);
