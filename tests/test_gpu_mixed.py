@@ -188,3 +188,21 @@ def test_autotune_picks_a_width_and_queries_use_it(c1):
     out, st = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED)          # batch_cols = 0: tuned width
     assert all(s["batch_cols"] == res["best"] for s in st)
     assert max(s["cert_l1"] for s in st) <= 1e-8
+
+
+@pytest.mark.parametrize("self_loops", [False, True])
+@pytest.mark.parametrize("chunks", [1, 5])
+def test_random_small_graphs_vs_dense_solve(self_loops, chunks):
+    """Section 2 allows self-loops (d_v counts them): the batched path on small
+    random graphs against numpy's dense solve of Eq. 1, every source."""
+    from conftest import dense_ppr_matrix
+    for n, p, seed in ((30, 0.2, 1), (120, 0.05, 2), (200, 0.03, 3)):
+        g = synth.random_small(n, p, seed, self_loops=self_loops)
+        Pi = dense_ppr_matrix(g, ALPHA)
+        G = P.Graph.from_synth(g)
+        srcs = list(range(n))
+        out, st = G.query_batch(srcs, ALPHA, 1e-10, P.MIXED, batch_cols=32, sweep_chunks=chunks)
+        err = np.abs(out - Pi).sum(axis=1)
+        assert err.max() <= 1e-10 + SLACK, (n, int(err.argmax()), err.max())
+        assert max(s["cert_l1"] for s in st) <= 1e-10
+        G.close()
