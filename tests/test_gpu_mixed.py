@@ -206,3 +206,39 @@ def test_random_small_graphs_vs_dense_solve(self_loops, chunks):
         assert err.max() <= 1e-10 + SLACK, (n, int(err.argmax()), err.max())
         assert max(s["cert_l1"] for s in st) <= 1e-10
         G.close()
+
+
+def test_concurrent_queries_on_one_graph(c1):
+    """Queries on one graph from several host threads at once (each call takes
+    its own state and stream from the graph's pools) give the results of the
+    same queries run one after another."""
+    import threading
+    srcs = [int(s) for s in synth.sources(c1.n, 40)]
+    G = P.Graph.from_synth(c1)
+    jobs = [("mixed", srcs[8 * k:8 * k + 8]) for k in range(4)] + [("fp64", [srcs[k]]) for k in range(4)]
+
+    def run(kind, ss):
+        if kind == "mixed":
+            return G.query_batch(ss, ALPHA, 1e-8, P.MIXED, batch_cols=8, sweep_chunks=2)[0]
+        return G.query_batch(ss, ALPHA, 1e-8, P.FP64)[0]
+
+    seq = [run(k, ss) for k, ss in jobs]
+    res = [None] * len(jobs)
+    errs = []
+
+    def worker(i):
+        try:
+            for _ in range(3):
+                res[i] = run(*jobs[i])
+        except Exception as e:          # surfaced below
+            errs.append(e)
+
+    th = [threading.Thread(target=worker, args=(i,)) for i in range(len(jobs))]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    assert not errs, errs
+    for i in range(len(jobs)):
+        # FP64 atomics in the local phase may reorder additions: a few ulps
+        assert np.abs(res[i] - seq[i]).sum(axis=1).max() <= 1e-12, i
