@@ -87,6 +87,8 @@ def main() -> int:
     ap.add_argument("--alpha", type=float, default=0.2)
     ap.add_argument("--batch-cols", type=int, default=0, help="0 = autotuned")
     ap.add_argument("--fp64-queries", type=int, default=8)
+    ap.add_argument("--fp64-epoch-queries", type=int, default=4,
+                    help="FP64 queries with Algorithm 3's epoch thresholds in the global phase")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--extra-widths", default="8,32",
@@ -184,6 +186,20 @@ def main() -> int:
                 "sweep_ms": round(f64_sweep_ms, 4), "sweep_gbs": round(f64_gbs, 1),
                 "queries": args.fp64_queries}
         print(f"[bench] fp64: {f64_qps:.1f} q/s, sweep {f64_sweep_ms:.3f} ms", file=sys.stderr, flush=True)
+    if args.fp64_epoch_queries > 0 and fp64 is not None:
+        out1 = torch.empty((1, g.n), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ep = [G.query_batch([s_], args.alpha, args.lam, P.FP64, out=out1, global_rule=P.GLOBAL_EPOCHS)[1][0]
+              for s_ in srcs[:args.fp64_epoch_queries]]
+        torch.cuda.synchronize()
+        ep_dt = time.perf_counter() - t1
+        fp64["epochs"] = {"value": round(len(ep) / ep_dt, 3), "unit": "queries/s",
+                          "scans_per_query": round(sum(e["sweeps"] for e in ep) / len(ep), 1),
+                          "edge_pushes_per_query_over_m": round(sum(e["edge_pushes"] for e in ep) / len(ep) / g.m, 2),
+                          "threshold0_sweeps_per_query": round(sum(e["sweeps"] for e in f64_stats) / len(f64_stats), 1),
+                          "queries": len(ep)}
+        print(f"[bench] fp64 epochs: {fp64['epochs']}", file=sys.stderr, flush=True)
 
     # the same step at other block widths (one timed step each)
     widths = {}

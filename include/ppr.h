@@ -93,6 +93,14 @@ typedef struct {
     int32_t sweep_chunks;   /* row chunks per global sweep (1 = Eq. 7 order) */
 } ppr_stats;
 
+/* Global phase of the PPR_FP64 path. */
+typedef enum {
+    PPR_GLOBAL_SWEEPS = 0,  /* threshold-0 sweeps: every sweep is one Eq. 7 step (default) */
+    PPR_GLOBAL_EPOCHS = 1   /* Algorithm 3's epochs: rmax_i = lambda^(i/8) / m, i = 1..8,
+                               scans while r_sum > m rmax_i; each scan pushes, at once,
+                               the nodes active at its start (r(v) > d_v rmax_i) */
+} ppr_global_rule;
+
 /* Query options (ppr_options_default fills the defaults). */
 typedef struct {
     int32_t precision;      /* ppr_precision */
@@ -109,7 +117,8 @@ typedef struct {
                                order: the rows of chunk j see the residues that chunks
                                0..j-1 produced in the same sweep, as the in-place scan of
                                Algorithm 3 does; 0 = chosen from m (default) */
-    int32_t reserved[4];
+    int32_t global_rule;    /* PPR_FP64: ppr_global_rule; default PPR_GLOBAL_SWEEPS */
+    int32_t reserved[3];
 } ppr_options;
 
 /* Read-only facts about a created graph. */

@@ -13,7 +13,8 @@ of the paper it restates:
 - ``fifo_fwdpush``     -- Algorithm 2, with the iteration sets S^(j) of Section 4.2
 - ``powerpush``        -- Algorithm 3 as printed (FIFO local phase, epochs of scans)
 - ``powerpush_sync``   -- the level-synchronous schedule of the GPU path:
-                          iterations S^(j) pushed simultaneously, then Eq. 7 sweeps
+                          iterations S^(j) pushed simultaneously, then Eq. 7 sweeps, or
+                          Algorithm 3's epochs with each scan taken simultaneously
 - ``sim_sweep``        -- one Simultaneous Forward Push iteration (Eq. 7)
 - ``block_gs_sweep``   -- one global sweep in block Gauss-Seidel order (Algorithm 3's
                           in-place scan taken a chunk of rows at a time; Eq. 7 for one chunk)
@@ -85,7 +86,7 @@ def _load():
     lib.oracle_powerpush.restype = ctypes.c_int
     lib.oracle_powerpush.argtypes = [i32, i64, vp, vp, i32, f64, f64, vp, vp, vp, vp, i32]
     lib.oracle_powerpush_sync.restype = ctypes.c_int
-    lib.oracle_powerpush_sync.argtypes = [i32, i64, vp, vp, i32, f64, f64, ctypes.c_int, f64,
+    lib.oracle_powerpush_sync.argtypes = [i32, i64, vp, vp, i32, f64, f64, ctypes.c_int, f64, ctypes.c_int,
                                           vp, vp, vp, vp, i32, vp, vp, vp, i32]
     lib.oracle_sim_sweep.restype = None
     lib.oracle_sim_sweep.argtypes = [i32, vp, vp, f64, vp, vp, vp]
@@ -165,8 +166,13 @@ SWITCH_NODES = 0   # continue the local phase while 4|S| <= n (Algorithm 3)
 SWITCH_EDGES = 1   # continue while param * vol(S) <= m
 
 
+GLOBAL_SWEEPS = 0   # global phase: threshold-0 sweeps (Eq. 7)
+GLOBAL_EPOCHS = 1   # global phase: Algorithm 3's epochs, each scan taken simultaneously
+
+
 def powerpush_sync(g, s: int, alpha: float, lam: float, switch_rule: int = SWITCH_NODES,
-                   switch_param: float = 1.0, trace_cap: int = 0, level_cap: int = 64):
+                   switch_param: float = 1.0, trace_cap: int = 0, level_cap: int = 64,
+                   global_rule: int = GLOBAL_SWEEPS):
     """Level-synchronous schedule.  Returns (pi, r, stats, rsum_trace, levels) where
     levels is a list of (|S^(j)|, vol(S^(j)), r_sum at the start of iteration j)."""
     rp, col = _g(g)
@@ -178,7 +184,7 @@ def powerpush_sync(g, s: int, alpha: float, lam: float, switch_rule: int = SWITC
     lr = np.zeros(max(level_cap, 1), dtype=np.float64)
     st = Stats()
     k = _load().oracle_powerpush_sync(g.n, g.m, _p(rp), _p(col), int(s), alpha, lam,
-                                      int(switch_rule), float(switch_param), _p(pi), _p(r),
+                                      int(switch_rule), float(switch_param), int(global_rule), _p(pi), _p(r),
                                       ctypes.byref(st), _p(tr) if trace_cap else None, trace_cap,
                                       _p(ls), _p(lv), _p(lr), level_cap)
     if k < 0:

@@ -319,8 +319,10 @@ void oracle_block_gs_sweep(int32_t n, const int64_t* col_ptr, const int32_t* row
 /*    nodes whose residue became active during iteration j.  The phase  */
 /*    runs while S^(j) is non-empty, r_sum > lambda and the switch rule */
 /*    allows it;                                                        */
-/*  - global phase: Simultaneous Forward Push with rmax = 0 (Eq. 7),    */
-/*    identical to power iteration by Lemma 1, until r_sum <= lambda.   */
+/*  - global phase (global_rule 0): Simultaneous Forward Push with      */
+/*    rmax = 0 (Eq. 7), identical to power iteration by Lemma 1, until  */
+/*    r_sum <= lambda; (global_rule 1): Algorithm 3's epochs with each  */
+/*    scan taken simultaneously over the nodes active at its start.     */
 /* Switch rule 0: continue while 4 |S^(j)| <= n (Algorithm 3's          */
 /* scanThreshold = n/4).  Rule 1: continue while                        */
 /* switch_param * sum_{v in S^(j)} d_v <= m (edge volume).              */
@@ -334,7 +336,7 @@ void oracle_block_gs_sweep(int32_t n, const int64_t* col_ptr, const int32_t* row
 /* ------------------------------------------------------------------ */
 int oracle_powerpush_sync(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col,
                           int32_t s, double alpha, double lambda, int switch_rule,
-                          double switch_param, double* pi, double* r, oracle_stats* st,
+                          double switch_param, int global_rule, double* pi, double* r, oracle_stats* st,
                           double* rsum_trace, int32_t trace_cap,
                           int32_t* level_sizes, int64_t* level_vols, double* level_rsum,
                           int32_t level_cap) {
@@ -398,14 +400,56 @@ int oracle_powerpush_sync(int32_t n, int64_t m, const int64_t* row_ptr, const in
     r_sum = oracle_sum(n, r);
     if (rsum_trace && ntr < trace_cap) rsum_trace[ntr++] = r_sum;
     if (r_sum > lambda) S.switched = 1;
-    while (r_sum > lambda) {
-        oracle_sim_sweep(n, row_ptr, col, alpha, r, r2, pi);
-        memcpy(r, r2, sizeof(double) * (size_t)n);
-        S.sweeps++;
-        S.edge_pushes += m;
-        S.pushes += n;
-        r_sum = oracle_sum(n, r);
-        if (rsum_trace && ntr < trace_cap) rsum_trace[ntr++] = r_sum;
+    if (global_rule == 0) {
+        while (r_sum > lambda) {
+            oracle_sim_sweep(n, row_ptr, col, alpha, r, r2, pi);
+            memcpy(r, r2, sizeof(double) * (size_t)n);
+            S.sweeps++;
+            S.edge_pushes += m;
+            S.pushes += n;
+            r_sum = oracle_sum(n, r);
+            if (rsum_trace && ntr < trace_cap) rsum_trace[ntr++] = r_sum;
+        }
+    } else {
+        /* Algorithm 3's epochs (rmax_i = lambda^(i/8) / m, scans while
+           r_sum > m rmax_i, as printed), each scan taken simultaneously: every
+           node active at the start of the scan (r(v) > d_v rmax_i) pushes the
+           residue it holds then (Simultaneous Forward Push of Section 4.1 with
+           threshold rmax_i).  A scan with no active node ends the epoch; scans
+           at rmax_8 = lambda / m continue while rounding leaves r_sum above
+           lambda. */
+        for (int i = 1; i <= 9; ++i) {
+            const int last = (i == 9);
+            double rmax_i = pow(lambda, (double)(last ? 8 : i) / 8.0) / (double)m;
+            for (;;) {
+                if (last ? !(r_sum > lambda) : !(r_sum > (double)m * rmax_i)) break;
+                int64_t nact = 0, vol = 0;
+                for (int32_t v = 0; v < n; ++v) {
+                    int64_t d = row_ptr[v + 1] - row_ptr[v];
+                    if (r[v] > (double)d * rmax_i) {
+                        x[v] = r[v];
+                        r[v] = 0.0;
+                        pi[v] += alpha * x[v];
+                        nact++;
+                        vol += d;
+                    } else {
+                        x[v] = 0.0;
+                    }
+                }
+                if (nact == 0) break;
+                for (int32_t v = 0; v < n; ++v) {
+                    if (x[v] == 0.0) continue;
+                    int64_t d = row_ptr[v + 1] - row_ptr[v];
+                    double inc = (1.0 - alpha) * x[v] / (double)d;
+                    for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) r[col[e]] += inc;
+                }
+                S.sweeps++;
+                S.edge_pushes += vol;
+                S.pushes += nact;
+                r_sum = oracle_sum(n, r);
+                if (rsum_trace && ntr < trace_cap) rsum_trace[ntr++] = r_sum;
+            }
+        }
     }
     S.r_sum = r_sum;
     if (st) *st = S;

@@ -27,6 +27,8 @@ FP64 = 0
 MIXED = 1
 SWITCH_NODES = 0
 SWITCH_EDGES = 1
+GLOBAL_SWEEPS = 0
+GLOBAL_EPOCHS = 1
 GRAPH_TRUST_INPUT = 1
 GRAPH_WIDE_OFFSETS = 2
 
@@ -63,7 +65,7 @@ class Options(ctypes.Structure):
                 ("switch_param", ctypes.c_double), ("max_sweeps", ctypes.c_int32),
                 ("certify", ctypes.c_int32), ("refresh_factor", ctypes.c_double),
                 ("batch_cols", ctypes.c_int32), ("sweep_chunks", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("global_rule", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 class GraphInfo(ctypes.Structure):

@@ -54,6 +54,10 @@ void check_options(const ppr_options& o) {
     if (!(o.refresh_factor > 1.0)) fail(PPR_ERR_ARG, "refresh_factor must be > 1");
     if (o.batch_cols < 0 || (o.batch_cols % 4) != 0) fail(PPR_ERR_ARG, "batch_cols must be 0 or a multiple of 4");
     if (o.sweep_chunks < 0 || o.sweep_chunks > 64) fail(PPR_ERR_ARG, "sweep_chunks must lie in [0, 64]");
+    if (o.global_rule != PPR_GLOBAL_SWEEPS && o.global_rule != PPR_GLOBAL_EPOCHS)
+        fail(PPR_ERR_ARG, "unknown global rule");
+    if (o.global_rule == PPR_GLOBAL_EPOCHS && o.precision != PPR_FP64)
+        fail(PPR_ERR_ARG, "the epoch global phase is a PPR_FP64 option");
 }
 
 }  // namespace

@@ -147,6 +147,29 @@ __global__ void prep_kernel(const double* __restrict__ r, const int32_t* __restr
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
+// Epoch scan snapshot: the active test is the oracle's, r(v) > d_v * rmax in FP64.
+__global__ void threshold_kernel(const int32_t* __restrict__ deg, int32_t n, double alpha, double rmax,
+                                 double* __restrict__ r, double* __restrict__ pi, double* __restrict__ y,
+                                 double* __restrict__ partials) {
+    __shared__ double sh[kBlock / 64];
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    double vol = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double x = r[i];
+        const int32_t d = deg[i];
+        if (x > (double)d * rmax) {
+            r[i] = 0.0;
+            pi[i] += alpha * x;
+            y[i] = ((1.0 - alpha) * x) / (double)d;
+            vol += (double)d;
+        } else {
+            y[i] = 0.0;
+        }
+    }
+    double t = block_sum(vol, sh);
+    if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
 __global__ void reduce_kernel(const double* __restrict__ partials, int nparts, double* __restrict__ out) {
     __shared__ double sh[1024 / 64];
     double s = 0.0;
@@ -255,9 +278,15 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(
     if (u >= 0) {
         if (FLAGS & SW_ENTRY) pi[u] += alpha * r_in[u];
         if (FLAGS & SW_FOLD) pi[u] += alpha * acc;
-        if (FLAGS & SW_WRITE_R) r_out[u] = acc;
-        y_out[u] = (oma * acc) / (double)deg[u];
-        contrib = acc;
+        if (FLAGS & SW_ACCUM) {
+            const double nr = r_in[u] + acc;
+            r_out[u] = nr;
+            contrib = nr;
+        } else {
+            if (FLAGS & SW_WRITE_R) r_out[u] = acc;
+            y_out[u] = (oma * acc) / (double)deg[u];
+            contrib = acc;
+        }
     }
     double t = block_sum(contrib, sh);
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
@@ -313,6 +342,7 @@ void launch_sweep(const Graph& g, const Schedule& sch, int flags, double alpha, 
         PPR_SWEEP_CASE(SW_ENTRY | SW_FOLD)
         PPR_SWEEP_CASE(SW_WRITE_R)
         PPR_SWEEP_CASE(SW_ENTRY | SW_WRITE_R)
+        PPR_SWEEP_CASE(SW_ACCUM)
         default:
             fail(PPR_ERR_ARG, "unsupported sweep flags");
     }
@@ -361,6 +391,14 @@ void frontier_push(const int32_t* F, const int64_t* off, int32_t nf, int64_t vol
 void prep_y(const double* r, const int32_t* deg, double alpha, int32_t n, double* y, double* partials,
             int* nparts, hipStream_t s) {
     hipLaunchKernelGGL(prep_kernel, dim3(kPartsFixed), dim3(kBlock), 0, s, r, deg, alpha, n, y, partials);
+    HIPCHECK(hipGetLastError());
+    *nparts = kPartsFixed;
+}
+
+void threshold_snapshot(const int32_t* deg, int32_t n, double alpha, double rmax, double* r, double* pi,
+                        double* y, double* partials, int* nparts, hipStream_t s) {
+    hipLaunchKernelGGL(threshold_kernel, dim3(kPartsFixed), dim3(kBlock), 0, s, deg, n, alpha, rmax, r, pi, y,
+                       partials);
     HIPCHECK(hipGetLastError());
     *nparts = kPartsFixed;
 }

@@ -198,8 +198,14 @@ void prep_y(const double* r, const int32_t* deg, double alpha, int32_t n, double
             double* partials, int* nparts, hipStream_t s);
 void reduce_sum(const double* partials, int nparts, double* out, hipStream_t s);
 
-// FP64 pull sweep: flags
-enum : int { SW_ENTRY = 1, SW_FOLD = 2, SW_WRITE_R = 4 };
+// Epoch scans: every node with r(v) > d_v rmax pushes now (pi += alpha r,
+// r = 0, y = (1-alpha) r / d_v), the others get y = 0; per-block partial sums
+// of the pushed nodes' out-degrees (the scan's edge pushes)
+void threshold_snapshot(const int32_t* deg, int32_t n, double alpha, double rmax, double* r, double* pi,
+                        double* y, double* partials, int* nparts, hipStream_t s);
+
+// FP64 pull sweep: flags (SW_ACCUM: r_out = r_in + the pulled sum, no y_out)
+enum : int { SW_ENTRY = 1, SW_FOLD = 2, SW_WRITE_R = 4, SW_ACCUM = 8 };
 void sweep_f64(const Graph& g, const Schedule& sch, int flags, double alpha, const double* y_in,
                double* y_out, double* pi, const double* r_in, double* r_out, double* partials,
                hipStream_t s);

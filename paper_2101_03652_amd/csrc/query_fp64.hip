@@ -156,12 +156,46 @@ void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_
         r_sum = hd[0];
     }
 
-    // ---- global phase: threshold-0 sweeps contract r_sum by exactly (1 - alpha)
     int32_t sweeps = 0;
     double sweep_ms = 0.0;
     int32_t timed_sweeps = 0;
     EventPair ev;
-    if (r_sum > lambda) {
+    if (opt.global_rule == PPR_GLOBAL_EPOCHS && r_sum > lambda) {
+        // ---- global phase, Algorithm 3's epochs: rmax_i = lambda^(i/8) / m,
+        // scans while r_sum > m rmax_i (as printed); each scan pushes at once the
+        // nodes active at its start.  A scan with no active node ends the epoch;
+        // scans at rmax_8 continue while rounding leaves r_sum above lambda.
+        ev.start(ss);
+        double* y = c.y0.as<double>();
+        bool capped = false;
+        for (int i = 1; i <= 9 && !capped; ++i) {
+            const bool last = (i == 9);
+            const double rmax_i = std::pow(lambda, (double)(last ? 8 : i) / 8.0) / (double)g.m;
+            for (;;) {
+                if (last ? !(r_sum > lambda) : !(r_sum > (double)g.m * rmax_i)) break;
+                if (sweeps >= opt.max_sweeps) {
+                    capped = true;
+                    break;
+                }
+                int np = 0;
+                k::threshold_snapshot(deg, g.n, alpha, rmax_i, r, pi, y, partials, &np, ss);
+                k::reduce_sum(partials, np, c.dsum.as<double>() + 1, ss);
+                k::sweep_f64(g, sch, k::SW_ACCUM, alpha, y, nullptr, pi, r, r, partials, ss);
+                k::reduce_sum(partials, k::sweep_parts(sch), c.dsum.as<double>(), ss);
+                HIPCHECK(hipMemcpyAsync(hd, c.dsum.p, 16, hipMemcpyDeviceToHost, ss));
+                HIPCHECK(hipStreamSynchronize(ss));
+                if (hd[1] == 0.0) break;      // nothing was active: the scan moved nothing
+                ++sweeps;
+                edge_pushes += (int64_t)hd[1];
+                r_sum = hd[0];
+            }
+        }
+        ev.stop(ss);
+        HIPCHECK(hipStreamSynchronize(ss));
+        sweep_ms = ev.elapsed_ms();
+        timed_sweeps = sweeps;
+    } else if (r_sum > lambda) {
+        // ---- global phase: threshold-0 sweeps contract r_sum by exactly (1 - alpha)
         ev.start(ss);
         int32_t K = 0;
         for (double x = r_sum; x > lambda && K < opt.max_sweeps; x *= (1.0 - alpha)) ++K;
@@ -209,7 +243,7 @@ void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_
             r_sum = hd[0];
         }
     }
-    edge_pushes += (int64_t)sweeps * g.m;
+    if (opt.global_rule != PPR_GLOBAL_EPOCHS) edge_pushes += (int64_t)sweeps * g.m;
 
     // ---- optional certificate
     double cert = -1.0;

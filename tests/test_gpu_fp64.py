@@ -227,3 +227,43 @@ def test_query_argument_errors(c1):
     with pytest.raises(P.PPRError) as ei:
         G.query(0, ALPHA, 1e-12, P.FP64, max_sweeps=3)
     assert ei.value.status == -7
+
+
+@pytest.mark.parametrize("lam", [1e-6, 1e-8])
+def test_epochs_global_phase_matches_oracle(c1, hub, lam):
+    """The PPR_GLOBAL_EPOCHS global phase (Algorithm 3's epochs, each scan taken
+    at once over the nodes active at its start) against the oracle's same
+    schedule: equal local levels, scans and edge pushes, equal vectors to
+    FP64 summation order, and within lambda of the power-iteration truth."""
+    for g, srcs in ((c1, [int(s) for s in synth.sources(c1.n, 3)]), (hub, [0, 12345])):
+        G = P.Graph.from_synth(g)
+        for s in srcs:
+            for param in (8.0, 1e30):          # 1e30: straight to the global phase
+                print(f"[gpu] fp64 epochs n={g.n} s={s} lam={lam} param={param}", flush=True)
+                pi, st = G.query(s, ALPHA, lam, P.FP64, switch_param=param, global_rule=P.GLOBAL_EPOCHS,
+                                 certify=1)
+                pio, ro, sto, _, _ = oracle.powerpush_sync(g, s, ALPHA, lam, P.SWITCH_EDGES, param,
+                                                           global_rule=oracle.GLOBAL_EPOCHS)
+                assert st["local_levels"] == sto["local_levels"]
+                assert st["sweeps"] == sto["sweeps"]
+                assert st["edge_pushes"] == sto["edge_pushes"]
+                np.testing.assert_allclose(pi, pio, rtol=RTOL, atol=ATOL)
+                assert st["r_sum"] <= lam
+                truth = oracle.powitr(g, s, ALPHA, 135)
+                assert np.abs(pi - truth).sum() <= lam
+                # both certificates carry FP64 cancellation error: the terms of
+                # e_s - (pi - (1-alpha) pi P) / alpha reach pi(u) / alpha, so the
+                # two summation orders may differ by ~ (sum pi / alpha) * few ulps
+                assert st["cert_l1"] == pytest.approx(oracle.certificate(g, s, ALPHA, pi), rel=1e-9, abs=2e-14)
+        G.close()
+
+
+def test_epochs_rule_is_fp64_only(c1):
+    G = P.Graph.from_synth(c1)
+    with pytest.raises(P.PPRError) as ei:
+        G.query_batch([1, 2], ALPHA, 1e-8, P.MIXED, batch_cols=4, global_rule=P.GLOBAL_EPOCHS)
+    assert ei.value.status == -1
+    with pytest.raises(P.PPRError) as ei:
+        G.query(1, ALPHA, 1e-8, P.FP64, global_rule=7)
+    assert ei.value.status == -1
+    G.close()

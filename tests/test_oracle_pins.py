@@ -208,7 +208,9 @@ def test_random_graphs_vs_dense_solve(n, p, seed, lam):
     for name, run in (("alg3", lambda: oracle.powerpush(g, s, ALPHA, lam)[:2]),
                       ("sync", lambda: oracle.powerpush_sync(g, s, ALPHA, lam)[:2]),
                       ("sync-edges", lambda: oracle.powerpush_sync(g, s, ALPHA, lam,
-                                                                   oracle.SWITCH_EDGES, 8.0)[:2])):
+                                                                   oracle.SWITCH_EDGES, 8.0)[:2]),
+                      ("sync-epochs", lambda: oracle.powerpush_sync(g, s, ALPHA, lam, oracle.SWITCH_EDGES, 8.0,
+                                                                    global_rule=oracle.GLOBAL_EPOCHS)[:2])):
         pi, r = run()
         err = np.abs(pi - x).sum()
         assert err <= lam, name
@@ -343,3 +345,23 @@ def test_csc_matches_scipy_transpose(c1):
     np.testing.assert_array_equal(col_ptr, A.indptr)
     np.testing.assert_array_equal(row_idx, A.indices)
     np.testing.assert_array_equal(deg, np.diff(c1.row_ptr))
+
+
+@pytest.mark.parametrize("n,p,seed", GRAPHS[:3])
+def test_epochs_schedule_invariant_and_thresholds(n, p, seed):
+    """Algorithm 3's epochs taken simultaneously: the final state satisfies the
+    invariant pi_s = pi_hat + sum_v r(v) pi_v (Section 3.2) with r >= 0, the
+    residue sum is <= lambda, and the scans push fewer edges than threshold-0
+    sweeps to the same lambda (the point of the dynamic threshold).  The switch
+    parameter 1e30 sends the query straight to the global phase."""
+    from conftest import dense_ppr_matrix
+    g = synth.random_small(n, p, seed, self_loops=True)
+    Pi = dense_ppr_matrix(g, ALPHA)
+    s = 2
+    for lam in (1e-6, 1e-10):
+        pi, r, st, _, _ = oracle.powerpush_sync(g, s, ALPHA, lam, oracle.SWITCH_EDGES, 1e30,
+                                                global_rule=oracle.GLOBAL_EPOCHS)
+        assert (r >= 0).all() and r.sum() <= lam
+        np.testing.assert_allclose(pi + r @ Pi, Pi[s], atol=1e-14)
+        _, _, st0, _, _ = oracle.powerpush_sync(g, s, ALPHA, lam, oracle.SWITCH_EDGES, 1e30)
+        assert st["edge_pushes"] < st0["edge_pushes"]
