@@ -77,8 +77,8 @@ def measured_traffic(width: int, chunks: int):
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=4_000_000)
     ap.add_argument("--m", type=int, default=70_000_000)
     ap.add_argument("--gamma", type=float, default=2.1)
@@ -262,8 +262,14 @@ def main() -> int:
         t2 = time.perf_counter()
         pis, ost = oracle.powerpush_many(g, sample, args.alpha, args.lam, threads)
         c_dt = time.perf_counter() - t2
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+        except OSError:
+            pass
         cpu = {"value": round(len(sample) / c_dt, 4), "unit": "queries/s", "cores": threads,
-               "kind": "oracle",
+               "cpu_model": model, "kind": "oracle",
                "sample": f"{len(sample)} of the step's sources on the same graph, Algorithm 3 in FP64, "
                          f"one query per host thread, {c_dt:.1f} s wall"}
         print(f"[bench] cpu oracle: {cpu}", file=sys.stderr, flush=True)
