@@ -180,7 +180,6 @@ struct Block {
     int32_t seq_sweeps = 0;
     double sweep_ms = 0.0;           // accumulated GPU time of the sweeps
     int32_t sweep_launches = 0;
-    int32_t total_sweeps = 0;
 
     Block(Graph& gg, int width, double a, const ppr_options& o) : g(gg), Bw(width), alpha(a), opt(o) {
         if (Bw < 4 || Bw > 128 || (Bw & (Bw - 1))) fail(PPR_ERR_ARG, "block width must be a power of two in [4, 128]");
@@ -481,7 +480,6 @@ struct Block {
             ev_sweep.stop(ss);
             sweep_timed = true;
             seq_sweeps = K;
-            total_sweeps += K;
             for (int b = 0; b < Bw; ++b) {
                 Slot& sl = slots[b];
                 if (sl.state != RUNNING) continue;

@@ -9,7 +9,7 @@ the oracle's FP64 certificate of each checked vector is <= lambda and equals
 the library's; |sum(pi_hat) - 1| <= lambda for every column; the batched
 column and the FP64 result for the same source lie within 2 lambda + 1e-9
 of each other.  The global sweeps' algorithmic bytes per HIP-event second
-are printed (and written to gpurun_out/large.json when that folder exists).
+are printed (and written as JSON to the path in PPR_LARGE_REPORT, if set).
 
 Runs only with PPR_LARGE=1: generating the graph on the host and the
 oracle's O(m) passes take several minutes and ~40 GB of host memory.
@@ -58,8 +58,9 @@ def srcs(c4):
 
 
 def _dump():
-    if os.path.isdir("gpurun_out"):
-        with open("gpurun_out/large.json", "w") as f:
+    path = os.environ.get("PPR_LARGE_REPORT")
+    if path:
+        with open(path, "w") as f:
             json.dump(REPORT, f, indent=1, default=float)
 
 
