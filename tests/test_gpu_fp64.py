@@ -267,3 +267,23 @@ def test_epochs_rule_is_fp64_only(c1):
         G.query(1, ALPHA, 1e-8, P.FP64, global_rule=7)
     assert ei.value.status == -1
     G.close()
+
+
+def test_baselines_power_iteration_and_forward_push(c1):
+    """The FP64 path's two limits: switch_param = 1e30 skips the local phase,
+    so the query is K threshold-0 sweeps from e_s, which Lemma 1 makes equal to
+    K power iterations (Eqs. 3-5); switch_param = 0 never leaves the local
+    phase, which is then the level-synchronous forward push of Algorithm 2
+    with rmax = lambda / m."""
+    G = P.Graph.from_synth(c1)
+    for s in [int(x) for x in synth.sources(c1.n, 2)]:
+        pi, st = G.query(s, ALPHA, 1e-8, P.FP64, switch_param=1e30)
+        assert st["local_levels"] == 0
+        np.testing.assert_allclose(pi, oracle.powitr(c1, s, ALPHA, st["sweeps"]), rtol=RTOL, atol=ATOL)
+        pi, st = G.query(s, ALPHA, 1e-8, P.FP64, switch_param=0.0)
+        assert st["sweeps"] == 0
+        pio, ro, sto = _sync(c1, s, 1e-8, P.SWITCH_EDGES, 0.0)
+        assert st["local_levels"] == sto["local_levels"] and sto["sweeps"] == 0
+        np.testing.assert_allclose(pi, pio, rtol=RTOL, atol=ATOL)
+        assert np.abs(pi - oracle.powitr(c1, s, ALPHA, 135)).sum() <= 1e-8
+    G.close()
