@@ -118,7 +118,13 @@ typedef struct {
                                0..j-1 produced in the same sweep, as the in-place scan of
                                Algorithm 3 does; 0 = chosen from m (default) */
     int32_t global_rule;    /* PPR_FP64: ppr_global_rule; default PPR_GLOBAL_SWEEPS */
-    int32_t reserved[3];
+    double sor_omega;       /* PPR_MIXED with sweep_chunks > 1: over-relaxation factor of the
+                               block Gauss-Seidel sweeps (each node pushes omega times the
+                               residue it received and keeps 1 - omega of it), in (1, 1.9];
+                               0 = off (default).  A column whose measured contraction shows
+                               no gain falls back to 1; the FP64 certificate bounds the
+                               result either way */
+    int32_t reserved[2];
 } ppr_options;
 
 /* Read-only facts about a created graph. */
@@ -216,6 +222,9 @@ ppr_status ppr_debug_sweep_fp64(ppr_graph* g, double alpha, const double* r_in, 
  * per column, i.e. Algorithm 3's in-place scan taken a chunk at a time in the
  * y domain (y(v) = (1-alpha) r(v) / d_v).  t_out (nullable) receives the
  * stage accumulator: y_out, plus y_in for the fresh columns.
+ * With omega (host float[B], nullable) the sweep is over-relaxed: row u
+ * holds p = q_in(u) + the value above, pushes y_out(u) = omega p and keeps
+ * q_out(u) = (1 - omega) p (q_in, q_out: float[n][B]; q_in NULL = zeros).
  *   B: power of two in [4, 128]; chunks in [1, 64].
  *   y_in, y_out, t_out: float[n][B] (node-major), host or device memory.
  *   fresh: host int32[B] (1: the column's y_in is a residue nobody has
@@ -223,7 +232,7 @@ ppr_status ppr_debug_sweep_fp64(ppr_graph* g, double alpha, const double* r_in, 
  */
 ppr_status ppr_debug_sweep_mixed(ppr_graph* g, double alpha, int32_t B, int32_t chunks,
                                  const float* y_in, const int32_t* fresh, float* y_out,
-                                 float* t_out);
+                                 float* t_out, const float* omega, const float* q_in, float* q_out);
 
 /*
  * Autotuner of the batched path: for each candidate block width (a power of

@@ -19,6 +19,7 @@ of the paper it restates:
 - ``block_gs_sweep``   -- one global sweep in block Gauss-Seidel order (Algorithm 3's
                           in-place scan taken a chunk of rows at a time; Eq. 7 for one chunk)
 - ``chunk_bounds``     -- the row chunks of about m / chunks in-edges that sweep uses
+- ``block_sor_sweep``  -- that sweep over-relaxed (successive over-relaxation of it)
 - ``powitr``           -- power iteration (Eqs. 3-5), compensated, used as truth
 - ``certificate``      -- ||e_s - pi_hat (I - (1-alpha) P)/alpha||_1 (from Eq. 1)
 
@@ -79,6 +80,8 @@ def _load():
     lib.oracle_csc.argtypes = [i32, i64, vp, vp, vp, vp, vp]
     lib.oracle_block_gs_sweep.restype = None
     lib.oracle_block_gs_sweep.argtypes = [i32, vp, vp, vp, f64, i32, vp, vp, ctypes.c_int, vp]
+    lib.oracle_block_sor_sweep.restype = None
+    lib.oracle_block_sor_sweep.argtypes = [i32, vp, vp, vp, f64, i32, vp, vp, ctypes.c_int, f64, vp, vp, vp]
     lib.oracle_push.restype = None
     lib.oracle_push.argtypes = [vp, vp, f64, vp, vp, i32]
     lib.oracle_fifo_fwdpush.restype = i64
@@ -225,6 +228,20 @@ def block_gs_sweep(g, alpha: float, lo, y_old, fresh: bool = False, csc_arrays=N
     _load().oracle_block_gs_sweep(g.n, _p(col_ptr), _p(row_idx), _p(deg), alpha, len(lo) - 1, _p(lo),
                                   _p(y_old), 1 if fresh else 0, _p(y_new))
     return y_new
+
+
+def block_sor_sweep(g, alpha: float, lo, y_old, fresh: bool, omega: float, q_in, csc_arrays=None):
+    """One over-relaxed block Gauss-Seidel sweep (see oracle_block_sor_sweep).
+    Returns (y_new, q_out)."""
+    col_ptr, row_idx, deg = csc_arrays if csc_arrays is not None else csc(g)
+    lo = np.ascontiguousarray(lo, dtype=np.int32)
+    y_old = np.ascontiguousarray(y_old, dtype=np.float64)
+    q_in = np.ascontiguousarray(q_in, dtype=np.float64)
+    y_new = np.zeros(g.n)
+    q_out = np.zeros(g.n)
+    _load().oracle_block_sor_sweep(g.n, _p(col_ptr), _p(row_idx), _p(deg), alpha, len(lo) - 1, _p(lo),
+                                   _p(y_old), 1 if fresh else 0, float(omega), _p(q_in), _p(q_out), _p(y_new))
+    return y_new, q_out
 
 
 def powitr(g, s: int, alpha: float, K: int = 135) -> np.ndarray:

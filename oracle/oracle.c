@@ -311,6 +311,37 @@ void oracle_block_gs_sweep(int32_t n, const int64_t* col_ptr, const int32_t* row
 }
 
 /* ------------------------------------------------------------------ */
+/* The same sweep over-relaxed: node u of chunk j holds                  */
+/*   p(u) = q_in(u) + (the block Gauss-Seidel value above)               */
+/* (q_in: what u kept back at its previous push), pushes                 */
+/* y_new(u) = omega p(u) and keeps q_out(u) = (1 - omega) p(u).  In the  */
+/* reserve domain (S = the sum of a node's pushes y) this is successive  */
+/* over-relaxation of the block Gauss-Seidel iteration for Eq. 1;        */
+/* omega = 1 is oracle_block_gs_sweep with q_out = 0.                   */
+/* ------------------------------------------------------------------ */
+void oracle_block_sor_sweep(int32_t n, const int64_t* col_ptr, const int32_t* row_idx, const int32_t* deg,
+                            double alpha, int32_t chunks, const int32_t* lo, const double* y_old, int fresh,
+                            double omega, const double* q_in, double* q_out, double* y_new) {
+    for (int32_t j = 0; j < chunks; ++j) {
+        for (int32_t u = lo[j]; u < lo[j + 1]; ++u) {
+            double acc = 0.0;
+            for (int64_t e = col_ptr[u]; e < col_ptr[u + 1]; ++e) {
+                int32_t v = row_idx[e];
+                if (v < lo[j]) {
+                    acc += y_new[v];
+                    if (fresh) acc += y_old[v];
+                } else {
+                    acc += y_old[v];
+                }
+            }
+            double p = q_in[u] + (1.0 - alpha) / (double)deg[u] * acc;
+            y_new[u] = omega * p;
+            q_out[u] = (1.0 - omega) * p;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
 /* The level-synchronous schedule that the GPU path runs, stated with   */
 /* the paper's objects:                                                 */
 /*  - local phase: the iterations S^(j) of Section 4.2, each performed  */

@@ -65,7 +65,8 @@ class Options(ctypes.Structure):
                 ("switch_param", ctypes.c_double), ("max_sweeps", ctypes.c_int32),
                 ("certify", ctypes.c_int32), ("refresh_factor", ctypes.c_double),
                 ("batch_cols", ctypes.c_int32), ("sweep_chunks", ctypes.c_int32),
-                ("global_rule", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("global_rule", ctypes.c_int32), ("sor_omega", ctypes.c_double),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class GraphInfo(ctypes.Structure):
@@ -99,7 +100,7 @@ def load() -> ctypes.CDLL:
         "ppr_query_ex": (st, [vp, vp, i32, f64, f64, vp, vp, vp, vp]),
         "ppr_debug_sweep_fp64": (st, [vp, f64, vp, vp, vp, vp]),
         "ppr_autotune": (st, [vp, f64, vp, i32, vp, vp]),
-        "ppr_debug_sweep_mixed": (st, [vp, f64, i32, i32, vp, vp, vp, vp]),
+        "ppr_debug_sweep_mixed": (st, [vp, f64, i32, i32, vp, vp, vp, vp, vp, vp, vp]),
         "ppr_block_create": (st, [vp, i32, f64, vp, ctypes.POINTER(vp)]),
         "ppr_block_destroy": (st, [vp]),
         "ppr_block_footprint": (st, [vp, i32, vp]),
@@ -296,10 +297,12 @@ class Block:
         return out, st.as_dict()
 
 
-def debug_sweep_mixed(graph: "Graph", alpha: float, y_in, fresh, chunks: int = 1, t_out=None):
-    """One batched global sweep (block Gauss-Seidel over `chunks` row chunks).
-    y_in: float32[n, B] (numpy or device tensor); fresh: B flags.  Returns y_out
-    (same kind as y_in)."""
+def debug_sweep_mixed(graph: "Graph", alpha: float, y_in, fresh, chunks: int = 1, t_out=None,
+                      omega=None, q_in=None, q_out=None):
+    """One batched global sweep (block Gauss-Seidel over `chunks` row chunks;
+    over-relaxed when `omega`, B factors, is given).  y_in: float32[n, B]
+    (numpy or device tensor); fresh: B flags.  Returns y_out (same kind as
+    y_in); q_out receives what the rows kept back."""
     B = int(y_in.shape[1])
     fr = np.ascontiguousarray(np.asarray(fresh, dtype=np.int32).reshape(-1))
     if len(fr) != B:
@@ -308,8 +311,14 @@ def debug_sweep_mixed(graph: "Graph", alpha: float, y_in, fresh, chunks: int = 1
         y_out = np.empty_like(y_in)
     else:
         y_out = y_in.new_empty(y_in.shape)
+    om = None if omega is None else np.ascontiguousarray(np.asarray(omega, dtype=np.float32).reshape(-1))
+    if om is not None and len(om) != B:
+        raise ValueError("omega needs one factor per column")
     _check(load().ppr_debug_sweep_mixed(graph.handle, float(alpha), B, int(chunks), _ptr(y_in), _ptr(fr),
-                                        _ptr(y_out), _ptr(t_out) if t_out is not None else None))
+                                        _ptr(y_out), _ptr(t_out) if t_out is not None else None,
+                                        _ptr(om) if om is not None else None,
+                                        _ptr(q_in) if q_in is not None else None,
+                                        _ptr(q_out) if q_out is not None else None))
     return y_out
 
 

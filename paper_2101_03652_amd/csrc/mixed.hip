@@ -21,8 +21,15 @@ namespace ppr {
 
 // ======================================================================== contexts
 
+void MixedCtx::drop_chunks() {
+    for (auto& ch : chunk) {
+        if (ch) (void)hipGraphExecDestroy(ch);
+        ch = nullptr;
+    }
+}
+
 MixedCtx::~MixedCtx() {
-    if (chunk) (void)hipGraphExecDestroy(chunk);
+    drop_chunks();
     if (stream) (void)hipStreamDestroy(stream);
 }
 
@@ -81,7 +88,7 @@ size_t mixed_footprint(const Graph& g, int Bw, int64_t fcap) {
     const size_t piece_cap = (size_t)mk::kLongRounds * mk::kLdsBytes / (4 * (size_t)Bw);
     const size_t pieces = 2 * (size_t)g.m / piece_cap + 1;
     return 16 * nb                       // FP64 local-phase scratch
-           + 20 * nb                     // Y0, Y1, Shi, Slo, T
+           + 24 * nb                     // Y0, Y1, Shi, Slo, T, and Q when over-relaxed
            + 4 * (size_t)Bw * pieces     // partial sums of the pieces
            + 40 * (size_t)fcap + 4 * (size_t)g.n + ((size_t)1 << 20);
 }
@@ -128,6 +135,12 @@ MixedCtxPtr mixed_acquire(Graph& g, int Bw, int64_t fcap) {
     c->active.alloc((size_t)Bw);
     for (DevBuf* b : {&c->src, &c->kb, &c->entry, &c->rmask, &c->cmask}) b->alloc(4 * (size_t)Bw);
     c->rmaxb.alloc(8 * (size_t)Bw);
+    c->omega.alloc(4 * (size_t)Bw);
+    {
+        std::vector<float> ones(Bw, 1.0f);
+        HIPCHECK(hipMemcpyAsync(c->omega.p, ones.data(), 4 * (size_t)Bw, hipMemcpyHostToDevice, c->stream));
+        HIPCHECK(hipStreamSynchronize(c->stream));
+    }
     std::vector<int32_t> neg(Bw, -1), zero(Bw, 0);
     HIPCHECK(hipMemcpyAsync(c->src.p, neg.data(), 4 * (size_t)Bw, hipMemcpyHostToDevice, c->stream));
     for (DevBuf* b : {&c->kb, &c->entry, &c->rmask, &c->cmask})
@@ -158,6 +171,7 @@ struct Block {
         bool refreshing = false;     // in the refresh whose result is in flight
         bool failed = false;         // reached max_sweeps with a certificate above lambda
         double cert = -1.0;
+        double omega = 1.0;          // over-relaxation factor of this column's sweeps
         double rho = 0.0;            // per-sweep contraction of err the stage lengths assume
         double stage_err0 = 0.0;     // err when the current stage started
         int32_t stage_sweeps = 0;    // sweeps run in the current stage
@@ -186,21 +200,16 @@ struct Block {
         c = mixed_acquire(g, Bw, frontier_capacity(g, opt, Bw));
         const int chunks = sweep_chunks(g, opt);
         if (c->chunks != chunks) {
-            if (c->chunk) {
-                (void)hipGraphExecDestroy(c->chunk);
-                c->chunk = nullptr;
-            }
+            c->drop_chunks();
             c->chunks = chunks;
         }
         mk::prepare(*c, g);
+        c->sor = false;              // set per launch sequence by step()
         slots.resize(Bw);
         HIPCHECK(hipEventCreateWithFlags(&ev_ready, hipEventDisableTiming));
         if (c->alpha != alpha) {
             mk::set_scale(g, *c, alpha);
-            if (c->chunk) {
-                (void)hipGraphExecDestroy(c->chunk);
-                c->chunk = nullptr;
-            }
+            c->drop_chunks();
             c->alpha = alpha;
         }
     }
@@ -257,7 +266,10 @@ struct Block {
     // sweeps; for block Gauss-Seidel sweeps a prior of (1 - alpha)^1.4 (on
     // power-law graphs they contract like (1 - alpha)^1.5 .. (1 - alpha)^1.7);
     // a stage that falls short is simply followed by another.
-    double first_rate() const { return c->chunks <= 1 ? 1.0 - alpha : std::pow(1.0 - alpha, 1.4); }
+    double first_rate(const Slot& sl) const {
+        if (c->chunks <= 1) return 1.0 - alpha;
+        return std::pow(1.0 - alpha, sl.omega > 1.0 ? 1.8 : 1.4);
+    }
 
     // Contraction for the next stage's length.  A Jacobi sweep (one chunk)
     // contracts the residue mass by exactly 1 - alpha (Eq. 6, Lemma 1).  In
@@ -265,9 +277,20 @@ struct Block {
     // once per sweep, so 1 - alpha still bounds the contraction; the measured
     // rate of the stage just ended (rounded towards 1 - alpha) sets the next
     // stage's length, and a stage that falls short is followed by another.
+    //
+    // Over-relaxation (omega > 1) is kept only while it pays: a stage whose
+    // measured rate is no better than (1 - alpha)^1.4, the rate plain block
+    // Gauss-Seidel order starts from, switches the column back to omega = 1
+    // (over-relaxed pushes can grow the residue on graphs with periodic
+    // structure; the refresh that ends the stage measures it exactly).
     void update_rate(Slot& sl, double cert) const {
         if (c->chunks <= 1 || sl.stage_sweeps <= 0 || !(sl.stage_err0 > 0.0) || !(cert > 0.0)) return;
         double r = std::pow(cert / sl.stage_err0, 1.0 / sl.stage_sweeps);
+        if (sl.omega > 1.0 && !(r < std::pow(1.0 - alpha, 1.4))) {
+            sl.omega = 1.0;
+            sl.rho = first_rate(sl);
+            return;
+        }
         r = std::pow(r, 0.95);
         r = std::ceil(r * 1024.0) / 1024.0;
         sl.rho = std::min(1.0 - alpha, std::max(0.05, r));
@@ -365,7 +388,8 @@ struct Block {
             sl.state = RUNNING;
             sl.err = (1.0 - alpha) * hcol[b];
             sl.entry = true;
-            sl.rho = first_rate();
+            sl.omega = (c->chunks > 1 && opt.sor_omega > 1.0) ? opt.sor_omega : 1.0;
+            sl.rho = first_rate(sl);
             start_stage(sl);
         }
     }
@@ -389,7 +413,7 @@ struct Block {
             throw;
         }
         HIPCHECK(hipStreamEndCapture(ss, &graph));
-        hipError_t e = hipGraphInstantiate(&c->chunk, graph, nullptr, nullptr, 0);
+        hipError_t e = hipGraphInstantiate(&c->chunk[c->sor ? 1 : 0], graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         HIPCHECK(e);
     }
@@ -462,13 +486,26 @@ struct Block {
             }
             upload_i32(c->kb, hkb);
             upload_i32(c->entry, hen);
+            // over-relaxation factors of this sequence (1 for plain columns)
+            std::vector<float> hom(Bw, 1.0f);
+            bool any_sor = false;
+            for (int b = 0; b < Bw; ++b)
+                if (slots[b].state == RUNNING && slots[b].omega != 1.0) {
+                    hom[b] = (float)slots[b].omega;
+                    any_sor = true;
+                }
+            if (any_sor) {
+                mk::ensure_sor(*c);
+                HIPCHECK(hipMemcpyAsync(c->omega.p, hom.data(), 4 * (size_t)Bw, hipMemcpyHostToDevice, ss));
+            }
+            c->sor = any_sor;
             HIPCHECK(hipMemsetAsync(c->step.p, 0, 4, ss));
             ev_sweep.start(ss);
             int rest = K;
             while (rest > 0) {
                 if (rest >= kChunkSweeps && c->ycur == c->Y1.as<float>()) {
-                    if (!c->chunk) capture_chunk();
-                    HIPCHECK(hipGraphLaunch(c->chunk, ss));    // an even count: ycur stays Y1
+                    if (!c->chunk[c->sor ? 1 : 0]) capture_chunk();
+                    HIPCHECK(hipGraphLaunch(c->chunk[c->sor ? 1 : 0], ss));    // even count: ycur stays Y1
                     rest -= kChunkSweeps;
                 } else {
                     float* yo = other(c->ycur);
@@ -701,7 +738,8 @@ void autotune_width(Graph& g, double alpha, const int32_t* widths, int32_t count
 // ======================================================================== one sweep (tests)
 
 void debug_sweep_mixed(Graph& g, double alpha, int32_t B, int32_t chunks, const float* y_in,
-                       const int32_t* fresh, float* y_out, float* t_out) {
+                       const int32_t* fresh, float* y_out, float* t_out, const float* omega,
+                       const float* q_in, float* q_out) {
     HIPCHECK(hipSetDevice(g.device));
     ppr_options opt;
     ppr_options_default(&opt);
@@ -716,9 +754,23 @@ void debug_sweep_mixed(Graph& g, double alpha, int32_t B, int32_t chunks, const 
     blk.upload_i32(c.kb, one);
     blk.upload_i32(c.entry, fr);
     HIPCHECK(hipMemsetAsync(c.step.p, 0, 4, ss));
+    if (omega) {
+        mk::ensure_sor(c);
+        HIPCHECK(hipMemcpyAsync(c.omega.p, omega, 4 * (size_t)B, hipMemcpyHostToDevice, ss));
+        if (q_in) HIPCHECK(hipMemcpyAsync(c.Q.p, q_in, bytes, hipMemcpyDefault, ss));
+        else HIPCHECK(hipMemsetAsync(c.Q.p, 0, bytes, ss));
+        c.sor = true;
+    }
     mk::sweep(c, g, c.Y0.as<float>(), c.Y1.as<float>());
+    c.sor = false;
     HIPCHECK(hipMemcpyAsync(y_out, c.Y1.p, bytes, hipMemcpyDefault, ss));
     if (t_out) HIPCHECK(hipMemcpyAsync(t_out, c.T.p, bytes, hipMemcpyDefault, ss));
+    if (omega && q_out) HIPCHECK(hipMemcpyAsync(q_out, c.Q.p, bytes, hipMemcpyDefault, ss));
+    if (omega) {
+        std::vector<float> ones(B, 1.0f);
+        HIPCHECK(hipMemcpyAsync(c.omega.p, ones.data(), 4 * (size_t)B, hipMemcpyHostToDevice, ss));
+        HIPCHECK(hipMemsetAsync(c.Q.p, 0, bytes, ss));
+    }
     blk.upload_i32(c.kb, zero);
     blk.upload_i32(c.entry, zero);
     for (DevBuf* d : {&c.Y0, &c.Y1, &c.T}) HIPCHECK(hipMemsetAsync(d->p, 0, d->bytes, ss));

@@ -178,7 +178,7 @@ __global__ __launch_bounds__(kBlock) void push_k(
 __global__ void convert_k(int32_t n, int shift, const int32_t* __restrict__ deg, double alpha,
                           const int32_t* __restrict__ cmask, double* __restrict__ r64, double* __restrict__ pi64,
                           float* __restrict__ Y, float* __restrict__ Shi, float* __restrict__ Slo,
-                          float* __restrict__ T, double* __restrict__ partials) {
+                          float* __restrict__ T, float* __restrict__ Q, double* __restrict__ partials) {
     __shared__ double sh[kBlock];
     __shared__ int32_t cm[128];
     const int B = 1 << shift;
@@ -202,6 +202,7 @@ __global__ void convert_k(int32_t n, int shift, const int32_t* __restrict__ deg,
             Shi[i] = h;
             Slo[i] = l;
             T[i] = 0.f;
+            if (Q) Q[i] = 0.f;
             r64[i] = 0.0;
             pi64[i] = 0.0;
             acc += r;
@@ -260,10 +261,14 @@ __device__ inline float4 gather_gs(const float4* __restrict__ Y_in, const float4
 
 // y'(u) = scale(u) * acc for the columns inside their sweep budget (0 for the
 // others); T += y' (plus, on an entry sweep, the fresh residue's alpha-part).
-template <int C>
+// SOR: the node holds p = q + scale(u) * acc (q: what it kept last time),
+// pushes y' = omega p and keeps q' = (1 - omega) p; columns outside their
+// budget keep q.
+template <int C, bool SOR>
 __device__ inline void finish_row(int32_t u, int c, float4 acc, int32_t step, const float* __restrict__ scale,
                                   const float4* __restrict__ Y_in, float4* Y_out, float4* __restrict__ T,
-                                  const int32_t* __restrict__ kb, const int32_t* __restrict__ entry) {
+                                  const int32_t* __restrict__ kb, const int32_t* __restrict__ entry,
+                                  float4* __restrict__ Q, const float* __restrict__ omega) {
     const int64_t at = (int64_t)u * C + c;
     float4 t = T[at];
     const float sc = scale[u];
@@ -276,17 +281,25 @@ __device__ inline void finish_row(int32_t u, int c, float4 acc, int32_t step, co
     }
     acc = f4_mul(acc, m);
     float4 y = make_float4(sc * acc.x, sc * acc.y, sc * acc.z, sc * acc.w);
+    if (SOR) {
+        const float4 q = Q[at];
+        const float4 w = reinterpret_cast<const float4*>(omega)[c];
+        const float4 p = make_float4(q.x + y.x, q.y + y.y, q.z + y.z, q.w + y.w);
+        y = make_float4(m.x * w.x * p.x, m.y * w.y * p.y, m.z * w.z * p.z, m.w * w.w * p.w);
+        Q[at] = make_float4(m.x != 0.f ? (1.f - w.x) * p.x : q.x, m.y != 0.f ? (1.f - w.y) * p.y : q.y,
+                            m.z != 0.f ? (1.f - w.z) * p.z : q.z, m.w != 0.f ? (1.f - w.w) * p.w : q.w);
+    }
     Y_out[at] = y;
     T[at] = f4_add(t, y);
 }
 
-template <typename OffT, int C>
+template <typename OffT, int C, bool SOR>
 __global__ __launch_bounds__(kBlock) void sweep_k(
         const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
         const RowBlock* __restrict__ blocks, int32_t lo, const float* __restrict__ scale,
         const float4* __restrict__ Y_in, float4* Y_out, float4* __restrict__ T,
         const int32_t* __restrict__ kb, const int32_t* __restrict__ entry, const int32_t* __restrict__ step_p,
-        float4* __restrict__ partials) {
+        float4* __restrict__ partials, float4* __restrict__ Q, const float* __restrict__ omega) {
     using P = Sw<C>;
     __shared__ float4 lds[kLdsBytes / 16];
     const RowBlock b = blocks[blockIdx.x];
@@ -344,22 +357,23 @@ __global__ __launch_bounds__(kBlock) void sweep_k(
         partials[(int64_t)b.piece * C + c] = acc;
         return;
     }
-    finish_row<C>(r0 + row, c, acc, step, scale, Y_in, Y_out, T, kb, entry);
+    finish_row<C, SOR>(r0 + row, c, acc, step, scale, Y_in, Y_out, T, kb, entry, Q, omega);
 }
 
 // Long rows of one chunk: the pieces' partial sums added in slot order.
-template <int C>
+template <int C, bool SOR>
 __global__ __launch_bounds__(kBlock) void combine_k(
         const LongRow* __restrict__ rows, int32_t count, const float4* __restrict__ partials,
         const int32_t* __restrict__ step_p, const float* __restrict__ scale, const float4* __restrict__ Y_in,
-        float4* Y_out, float4* __restrict__ T, const int32_t* __restrict__ kb, const int32_t* __restrict__ entry) {
+        float4* Y_out, float4* __restrict__ T, const int32_t* __restrict__ kb, const int32_t* __restrict__ entry,
+        float4* __restrict__ Q, const float* __restrict__ omega) {
     const int32_t i = (int32_t)blockIdx.x * (kBlock / C) + (int32_t)threadIdx.x / C;
     const int c = threadIdx.x % C;
     if (i >= count) return;
     const LongRow L = rows[i];
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int32_t p = 0; p < L.npieces; ++p) acc = f4_add(acc, partials[(int64_t)(L.first + p) * C + c]);
-    finish_row<C>(L.row, c, acc, *step_p, scale, Y_in, Y_out, T, kb, entry);
+    finish_row<C, SOR>(L.row, c, acc, *step_p, scale, Y_in, Y_out, T, kb, entry, Q, omega);
 }
 
 __global__ void bump_step_k(int32_t* step) { step[0] += 1; }
@@ -394,7 +408,8 @@ __global__ __launch_bounds__(kBlock) void refresh_k(
         const RowBlock* __restrict__ blocks, int32_t n_blocks,
         const int32_t* __restrict__ deg, const float4* __restrict__ Shi, const float4* __restrict__ Slo,
         const int32_t* __restrict__ src, const int32_t* __restrict__ rmask, double alpha,
-        float4* __restrict__ Y, double* __restrict__ rt_out, int32_t n, double* __restrict__ partials) {
+        float4* __restrict__ Y, float4* __restrict__ Q, double* __restrict__ rt_out, int32_t n,
+        double* __restrict__ partials) {
     using P = Rf<C>;
     __shared__ float4 lds_h[P::kNnz * C];
     __shared__ float4 lds_l[P::kNnz * C];
@@ -484,6 +499,14 @@ __global__ __launch_bounds__(kBlock) void refresh_k(
                 if (w4.z) y.z = (float)(oma * t2 / d);
                 if (w4.w) y.w = (float)(oma * t3 / d);
                 Y[at] = y;
+                if (Q) {                           // a fresh residue: nothing kept back
+                    float4 q = Q[at];
+                    if (w4.x) q.x = 0.f;
+                    if (w4.y) q.y = 0.f;
+                    if (w4.z) q.z = 0.f;
+                    if (w4.w) q.w = 0.f;
+                    Q[at] = q;
+                }
             }
             if (rt_out) {   // column-major FP64 residual [B][n]
                 rt_out[(int64_t)(4 * c + 0) * n + u] = t0;
@@ -572,39 +595,52 @@ const Schedule& refresh_schedule(Graph& g) {
     return g.schedule(Rf<C>::kNnz, Rf<C>::kRows, 1, kRefreshRounds);   // long rows whole, in rounds
 }
 
-template <int C>
-void sweep_c(MixedCtx& c, Graph& g, const float* yin, float* yout) {
+template <int C, bool SOR>
+void sweep_launch(MixedCtx& c, Graph& g, const float* yin, float* yout) {
     const Schedule& sch = sweep_schedule<C>(g, c.chunks);
     auto Y4i = reinterpret_cast<const float4*>(yin);
     auto Y4o = reinterpret_cast<float4*>(yout);
     const RowBlock* blocks = sch.blocks.as<RowBlock>();
     const LongRow* lrows = sch.longrows.as<LongRow>();
     float4* part = c.piece_part.as<float4>();
+    float4* Q = SOR ? c.Q.as<float4>() : nullptr;
+    const float* om = SOR ? c.omega.as<float>() : nullptr;
     for (int j = 0; j < sch.chunks; ++j) {      // chunk j sees the output of chunks < j
         const int32_t nb = sch.first[j + 1] - sch.first[j];
         if (nb == 0) continue;
         dim3 grid((unsigned)nb), blk(kBlock);
         const RowBlock* bj = blocks + sch.first[j];
         if (g.off64)
-            hipLaunchKernelGGL((sweep_k<int64_t, C>), grid, blk, 0, c.stream, g.col_ptr.as<int64_t>(),
+            hipLaunchKernelGGL((sweep_k<int64_t, C, SOR>), grid, blk, 0, c.stream, g.col_ptr.as<int64_t>(),
                                g.row_idx.as<int32_t>(), bj, sch.lo[j], c.scale.as<float>(), Y4i, Y4o,
                                c.T.as<float4>(), c.kb.as<int32_t>(), c.entry.as<int32_t>(), c.step.as<int32_t>(),
-                               part);
+                               part, Q, om);
         else
-            hipLaunchKernelGGL((sweep_k<uint32_t, C>), grid, blk, 0, c.stream, g.col_ptr.as<uint32_t>(),
+            hipLaunchKernelGGL((sweep_k<uint32_t, C, SOR>), grid, blk, 0, c.stream, g.col_ptr.as<uint32_t>(),
                                g.row_idx.as<int32_t>(), bj, sch.lo[j], c.scale.as<float>(), Y4i, Y4o,
                                c.T.as<float4>(), c.kb.as<int32_t>(), c.entry.as<int32_t>(), c.step.as<int32_t>(),
-                               part);
+                               part, Q, om);
         const int32_t nl = sch.lr_first[j + 1] - sch.lr_first[j];
         if (nl > 0) {
             const int per = kBlock / C;
-            hipLaunchKernelGGL((combine_k<C>), dim3((unsigned)((nl + per - 1) / per)), dim3(kBlock), 0, c.stream,
-                               lrows + sch.lr_first[j], nl, part, c.step.as<int32_t>(), c.scale.as<float>(),
-                               Y4i, Y4o, c.T.as<float4>(), c.kb.as<int32_t>(), c.entry.as<int32_t>());
+            hipLaunchKernelGGL((combine_k<C, SOR>), dim3((unsigned)((nl + per - 1) / per)), dim3(kBlock), 0,
+                               c.stream, lrows + sch.lr_first[j], nl, part, c.step.as<int32_t>(),
+                               c.scale.as<float>(), Y4i, Y4o, c.T.as<float4>(), c.kb.as<int32_t>(),
+                               c.entry.as<int32_t>(), Q, om);
         }
     }
     hipLaunchKernelGGL(bump_step_k, dim3(1), dim3(1), 0, c.stream, c.step.as<int32_t>());
     HIPCHECK(hipGetLastError());
+}
+
+template <int C>
+void sweep_c(MixedCtx& c, Graph& g, const float* yin, float* yout) {
+    if (c.sor) {
+        if (!c.Q.p) fail(PPR_ERR_ARG, "internal: over-relaxed sweep without its state");
+        sweep_launch<C, true>(c, g, yin, yout);
+    } else {
+        sweep_launch<C, false>(c, g, yin, yout);
+    }
 }
 
 template <int C>
@@ -620,12 +656,12 @@ void refresh_c(MixedCtx& c, Graph& g, float* y, double* rt_out) {
         hipLaunchKernelGGL((refresh_k<int64_t, C>), grid, blk, 0, c.stream, g.col_ptr.as<int64_t>(),
                            g.row_idx.as<int32_t>(), sch.blocks.as<RowBlock>(), sch.n_blocks,
                            g.deg.as<int32_t>(), H, L, c.src.as<int32_t>(), c.rmask.as<int32_t>(), c.alpha, Y4,
-                           rt_out, g.n, c.partials.as<double>());
+                           c.Q.as<float4>(), rt_out, g.n, c.partials.as<double>());
     else
         hipLaunchKernelGGL((refresh_k<uint32_t, C>), grid, blk, 0, c.stream, g.col_ptr.as<uint32_t>(),
                            g.row_idx.as<int32_t>(), sch.blocks.as<RowBlock>(), sch.n_blocks,
                            g.deg.as<int32_t>(), H, L, c.src.as<int32_t>(), c.rmask.as<int32_t>(), c.alpha, Y4,
-                           rt_out, g.n, c.partials.as<double>());
+                           c.Q.as<float4>(), rt_out, g.n, c.partials.as<double>());
     hipLaunchKernelGGL(reduce_cols_k, dim3(1), dim3(256), 0, c.stream, c.partials.as<double>(), (int)grid.x, c.Bw,
                        c.colsum.as<double>());
     HIPCHECK(hipGetLastError());
@@ -691,7 +727,7 @@ void convert(MixedCtx& c, const Graph& g, double alpha) {
     hipLaunchKernelGGL(convert_k, dim3(gc), dim3(kBlock), 0, c.stream, g.n, c.shift, g.deg.as<int32_t>(), alpha,
                        c.cmask.as<int32_t>(), c.r64.as<double>(), c.pi64.as<double>(),
                        const_cast<float*>(c.ycur), c.Shi.as<float>(), c.Slo.as<float>(), c.T.as<float>(),
-                       c.partials.as<double>());
+                       c.Q.as<float>(), c.partials.as<double>());
     hipLaunchKernelGGL(reduce_cols_k, dim3(1), dim3(256), 0, c.stream, c.partials.as<double>(), (int)gc, c.Bw,
                        c.colsum.as<double>());
     HIPCHECK(hipGetLastError());
@@ -703,14 +739,18 @@ void prepare(MixedCtx& c, const Graph& g) {
         const Schedule& sch = sweep_schedule<decltype(cc)::value>(gg, c.chunks);
         const size_t need = (size_t)std::max(sch.n_pieces, 1) * (size_t)decltype(cc)::value * 16;
         if (c.piece_part.bytes < need) {
-            if (c.chunk) {                     // a captured chunk holds the old buffer
-                (void)hipGraphExecDestroy(c.chunk);
-                c.chunk = nullptr;
-            }
+            c.drop_chunks();                   // a captured chunk holds the old buffer
             c.piece_part.alloc(need);
         }
         (void)refresh_schedule<decltype(cc)::value>(gg);
     });
+}
+
+void ensure_sor(MixedCtx& c) {
+    if (c.Q.p) return;
+    c.drop_chunks();
+    c.Q.alloc(4 * (size_t)c.n * (size_t)c.Bw);
+    HIPCHECK(hipMemsetAsync(c.Q.p, 0, c.Q.bytes, c.stream));
 }
 
 void sweep(MixedCtx& c, const Graph& g, const float* y_in, float* y_out) {

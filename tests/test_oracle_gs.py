@@ -123,3 +123,55 @@ def test_chunk_bounds_definition():
             want = g.m * j // G
             assert col_ptr[lo[j]] >= want
             assert lo[j] == 0 or col_ptr[lo[j] - 1] < want
+
+
+def test_sor_with_omega_one_is_the_plain_sweep():
+    g = synth.random_small(80, 0.06, 12, self_loops=True)
+    lo = oracle.chunk_bounds(g, 3)
+    rng = np.random.default_rng(4)
+    y = rng.random(g.n)
+    q = rng.random(g.n) * 0.1
+    for fresh in (False, True):
+        ys, qs = oracle.block_sor_sweep(g, ALPHA, lo, y, fresh, 1.0, np.zeros(g.n))
+        np.testing.assert_array_equal(ys, oracle.block_gs_sweep(g, ALPHA, lo, y, fresh))
+        assert not qs.any()
+        # one chunk, a kept residue q: every row sees the previous sweep only,
+        # so y = q + the Eq. 7 value and nothing is kept
+        ys, qs = oracle.block_sor_sweep(g, ALPHA, [0, g.n], y, fresh, 1.0, q)
+        np.testing.assert_allclose(ys, q + oracle.block_gs_sweep(g, ALPHA, [0, g.n], y, fresh), rtol=1e-14)
+        assert not qs.any()
+
+
+@pytest.mark.parametrize("chunks,omega", [(1, 1.05), (4, 1.2), (9, 1.3)])
+def test_sor_increments_equal_reserve_domain_sor(chunks, omega):
+    """Accumulating the over-relaxed sweeps' pushes (S = sum of y) reproduces
+    successive over-relaxation of the block Gauss-Seidel iteration written in
+    the reserve domain with numpy (S(u) <- (1 - omega) S(u) + omega (1-alpha)/d_u
+    (e_s(u) + sum_{v in N_in(u)} S(v)), earlier chunks already updated), which
+    converges to the dense-solve PPR."""
+    g = synth.random_small(90, 0.05, 13)
+    A, d = _A_and_deg(g)
+    s = 4
+    sc = (1 - ALPHA) / d
+    lo = oracle.chunk_bounds(g, chunks)
+    e = np.zeros(g.n)
+    e[s] = 1.0
+    y = sc * e                              # the fresh residue: e_s in the y domain
+    S = y.copy()                            # pushed at the start of the first sweep
+    q = np.zeros(g.n)
+    R = y.copy()                            # reserve-domain iterate after the same start
+    for k in range(40):
+        y, q = oracle.block_sor_sweep(g, ALPHA, lo, y, k == 0, omega, q)
+        S += y
+        Rn = R.copy()
+        for j in range(len(lo) - 1):
+            a, b = lo[j], lo[j + 1]
+            gs = sc[a:b] * (e[a:b] + A.T[a:b] @ Rn)
+            Rn[a:b] = (1 - omega) * R[a:b] + omega * gs
+        R = Rn
+        np.testing.assert_allclose(S, R, rtol=1e-11, atol=1e-15)
+    for k in range(40, 400):
+        y, q = oracle.block_sor_sweep(g, ALPHA, lo, y, False, omega, q)
+        S += y
+    x = dense_ppr(g, s, ALPHA)
+    assert np.abs(ALPHA * d * S / (1 - ALPHA) - x).sum() <= 1e-11
