@@ -251,6 +251,7 @@ def main() -> int:
         del x, y
 
     chunks = stats_all[0][0]["sweep_chunks"]
+    omegas = sorted({round(s["sor_omega"], 4) for sts in stats_all for s in sts})
     traffic = measured_traffic(width, chunks)
 
     cpu = None
@@ -290,8 +291,9 @@ def main() -> int:
         "config": {
             "workload": f"chung-lu n={g.n} m={g.m} gamma={args.gamma} alpha={args.alpha} "
                         f"lambda={args.lam:g}, {args.sources} sources per step, batched mixed, B={width}, "
-                        f"{chunks} sweep chunks",
+                        f"{chunks} sweep chunks, over-relaxation {'/'.join(str(w) for w in omegas)}",
             "n": g.n, "m": g.m, "sources_per_step": args.sources, "batch_cols": width, "sweep_chunks": chunks,
+            "sor_omega_final": omegas,
             "alpha": args.alpha, "lambda": args.lam,
         },
         "gteps": round(edges / dt / 1e9, 3),

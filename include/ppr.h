@@ -44,7 +44,6 @@ extern "C" {
 
 typedef struct ppr_graph ppr_graph;   /* opaque, library-owned, device resident */
 typedef struct ppr_block ppr_block;   /* opaque serving block: query slots on one graph */
-typedef struct ppr_block ppr_block;   /* opaque serving block (slots of one graph) */
 
 typedef enum {
     PPR_OK = 0,
@@ -91,6 +90,7 @@ typedef struct {
     int32_t sweep_launches; /* sweep kernel launches that sweep_ms covers */
     int32_t batch_cols;     /* block width used (1 for PPR_FP64) */
     int32_t sweep_chunks;   /* row chunks per global sweep (1 = Eq. 7 order) */
+    double sor_omega;       /* over-relaxation factor of the query's last stage (1 = none) */
 } ppr_stats;
 
 /* Global phase of the PPR_FP64 path. */
@@ -118,12 +118,13 @@ typedef struct {
                                0..j-1 produced in the same sweep, as the in-place scan of
                                Algorithm 3 does; 0 = chosen from m (default) */
     int32_t global_rule;    /* PPR_FP64: ppr_global_rule; default PPR_GLOBAL_SWEEPS */
-    double sor_omega;       /* PPR_MIXED with sweep_chunks > 1: over-relaxation factor of the
-                               block Gauss-Seidel sweeps (each node pushes omega times the
-                               residue it received and keeps 1 - omega of it), in (1, 1.9];
-                               0 = off (default).  A column whose measured contraction shows
-                               no gain falls back to 1; the FP64 certificate bounds the
-                               result either way */
+    double sor_omega;       /* PPR_MIXED, block Gauss-Seidel order (more than one chunk):
+                               over-relaxation factor of the sweeps (each node pushes omega
+                               times the residue it holds and keeps 1 - omega of it);
+                               0 = automatic: 1.2 when a sweep has more than one chunk
+                               (default); 1 = off; or a factor in (1, 1.9].  A column whose
+                               measured contraction shows no gain falls back to 1; the FP64
+                               certificate bounds the result either way */
     int32_t reserved[2];
 } ppr_options;
 
@@ -223,8 +224,11 @@ ppr_status ppr_debug_sweep_fp64(ppr_graph* g, double alpha, const double* r_in, 
  * y domain (y(v) = (1-alpha) r(v) / d_v).  t_out (nullable) receives the
  * stage accumulator: y_out, plus y_in for the fresh columns.
  * With omega (host float[B], nullable) the sweep is over-relaxed: row u
- * holds p = q_in(u) + the value above, pushes y_out(u) = omega p and keeps
- * q_out(u) = (1 - omega) p (q_in, q_out: float[n][B]; q_in NULL = zeros).
+ * pushes y_out(u) = omega * (the value above) + (1 - omega) * y_in(u) in the
+ * columns that are not fresh, omega * (the value above) in the fresh ones.
+ * This is a node that holds p = q + the value above, pushes omega p and keeps
+ * q' = (1 - omega) p, with q = (1 - omega) / omega * y_in(u) (what it kept
+ * when it pushed y_in(u)); a fresh residue has kept nothing back.
  *   B: power of two in [4, 128]; chunks in [1, 64].
  *   y_in, y_out, t_out: float[n][B] (node-major), host or device memory.
  *   fresh: host int32[B] (1: the column's y_in is a residue nobody has
@@ -232,7 +236,7 @@ ppr_status ppr_debug_sweep_fp64(ppr_graph* g, double alpha, const double* r_in, 
  */
 ppr_status ppr_debug_sweep_mixed(ppr_graph* g, double alpha, int32_t B, int32_t chunks,
                                  const float* y_in, const int32_t* fresh, float* y_out,
-                                 float* t_out, const float* omega, const float* q_in, float* q_out);
+                                 float* t_out, const float* omega);
 
 /*
  * Autotuner of the batched path: for each candidate block width (a power of

@@ -54,7 +54,8 @@ class Stats(ctypes.Structure):
                 ("edge_pushes", ctypes.c_int64), ("r_sum", ctypes.c_double),
                 ("cert_l1", ctypes.c_double), ("ms", ctypes.c_double),
                 ("sweep_ms", ctypes.c_double), ("sweep_launches", ctypes.c_int32),
-                ("batch_cols", ctypes.c_int32), ("sweep_chunks", ctypes.c_int32)]
+                ("batch_cols", ctypes.c_int32), ("sweep_chunks", ctypes.c_int32),
+                ("sor_omega", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -100,7 +101,7 @@ def load() -> ctypes.CDLL:
         "ppr_query_ex": (st, [vp, vp, i32, f64, f64, vp, vp, vp, vp]),
         "ppr_debug_sweep_fp64": (st, [vp, f64, vp, vp, vp, vp]),
         "ppr_autotune": (st, [vp, f64, vp, i32, vp, vp]),
-        "ppr_debug_sweep_mixed": (st, [vp, f64, i32, i32, vp, vp, vp, vp, vp, vp, vp]),
+        "ppr_debug_sweep_mixed": (st, [vp, f64, i32, i32, vp, vp, vp, vp, vp]),
         "ppr_block_create": (st, [vp, i32, f64, vp, ctypes.POINTER(vp)]),
         "ppr_block_destroy": (st, [vp]),
         "ppr_block_footprint": (st, [vp, i32, vp]),
@@ -298,11 +299,11 @@ class Block:
 
 
 def debug_sweep_mixed(graph: "Graph", alpha: float, y_in, fresh, chunks: int = 1, t_out=None,
-                      omega=None, q_in=None, q_out=None):
+                      omega=None):
     """One batched global sweep (block Gauss-Seidel over `chunks` row chunks;
     over-relaxed when `omega`, B factors, is given).  y_in: float32[n, B]
     (numpy or device tensor); fresh: B flags.  Returns y_out (same kind as
-    y_in); q_out receives what the rows kept back."""
+    y_in)."""
     B = int(y_in.shape[1])
     fr = np.ascontiguousarray(np.asarray(fresh, dtype=np.int32).reshape(-1))
     if len(fr) != B:
@@ -316,9 +317,7 @@ def debug_sweep_mixed(graph: "Graph", alpha: float, y_in, fresh, chunks: int = 1
         raise ValueError("omega needs one factor per column")
     _check(load().ppr_debug_sweep_mixed(graph.handle, float(alpha), B, int(chunks), _ptr(y_in), _ptr(fr),
                                         _ptr(y_out), _ptr(t_out) if t_out is not None else None,
-                                        _ptr(om) if om is not None else None,
-                                        _ptr(q_in) if q_in is not None else None,
-                                        _ptr(q_out) if q_out is not None else None))
+                                        _ptr(om) if om is not None else None))
     return y_out
 
 

@@ -54,8 +54,8 @@ void check_options(const ppr_options& o) {
     if (!(o.refresh_factor > 1.0)) fail(PPR_ERR_ARG, "refresh_factor must be > 1");
     if (o.batch_cols < 0 || (o.batch_cols % 4) != 0) fail(PPR_ERR_ARG, "batch_cols must be 0 or a multiple of 4");
     if (o.sweep_chunks < 0 || o.sweep_chunks > 64) fail(PPR_ERR_ARG, "sweep_chunks must lie in [0, 64]");
-    if (!(o.sor_omega == 0.0 || (o.sor_omega > 1.0 && o.sor_omega <= 1.9)))
-        fail(PPR_ERR_ARG, "sor_omega must be 0 (off) or lie in (1, 1.9]");
+    if (!(o.sor_omega == 0.0 || (o.sor_omega >= 1.0 && o.sor_omega <= 1.9)))
+        fail(PPR_ERR_ARG, "sor_omega must be 0 (automatic), 1 (off) or lie in (1, 1.9]");
     if (o.global_rule != PPR_GLOBAL_SWEEPS && o.global_rule != PPR_GLOBAL_EPOCHS)
         fail(PPR_ERR_ARG, "unknown global rule");
     if (o.global_rule == PPR_GLOBAL_EPOCHS && o.precision != PPR_FP64)
@@ -186,8 +186,7 @@ ppr_status ppr_autotune(ppr_graph* gh, double alpha, const int32_t* widths, int3
 }
 
 ppr_status ppr_debug_sweep_mixed(ppr_graph* gh, double alpha, int32_t B, int32_t chunks, const float* y_in,
-                                 const int32_t* fresh, float* y_out, float* t_out, const float* omega,
-                                 const float* q_in, float* q_out) {
+                                 const int32_t* fresh, float* y_out, float* t_out, const float* omega) {
     return guarded([&] {
         Graph* g = reinterpret_cast<Graph*>(gh);
         if (!g || !y_in || !fresh || !y_out) fail(PPR_ERR_ARG, "NULL argument");
@@ -198,12 +197,10 @@ ppr_status ppr_debug_sweep_mixed(ppr_graph* gh, double alpha, int32_t B, int32_t
         (void)is_device_ptr(y_in, g->device);              // rejects another device's memory
         (void)is_device_ptr(y_out, g->device);
         if (t_out) (void)is_device_ptr(t_out, g->device);
-        if (q_in) (void)is_device_ptr(q_in, g->device);
-        if (q_out) (void)is_device_ptr(q_out, g->device);
         if (omega)
             for (int32_t b = 0; b < B; ++b)
                 if (!(omega[b] > 0.0f && omega[b] < 2.0f)) fail(PPR_ERR_ARG, "omega must lie in (0, 2)");
-        debug_sweep_mixed(*g, alpha, B, chunks, y_in, fresh, y_out, t_out, omega, q_in, q_out);
+        debug_sweep_mixed(*g, alpha, B, chunks, y_in, fresh, y_out, t_out, omega);
     });
 }
 

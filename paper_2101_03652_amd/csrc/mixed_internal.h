@@ -60,7 +60,6 @@ struct MixedCtx {
     DevBuf step;                      // int32[1]   sweeps done in the current sequence
     DevBuf stage;                     // double[Bw][n] host-output staging (lazy)
     DevBuf piece_part;                // float[pieces][Bw]: partial sums of long-row pieces
-    DevBuf Q;                         // float[n][Bw]   over-relaxed sweeps: residue a node kept
     DevBuf omega;                     // float[Bw]      over-relaxation factor per column
     bool sor = false;                 // the next sweeps run the over-relaxed update
     PinnedBuf host;                   // readback area
@@ -90,7 +89,6 @@ void convert(MixedCtx& c, const Graph& g, double alpha);
 // so this runs before any stream capture)
 void prepare(MixedCtx& c, const Graph& g);
 // allocate (zeroed) the state of the over-relaxed sweeps
-void ensure_sor(MixedCtx& c);
 // one sweep Y_in -> Y_out (budgets kb, entry flags, device step counter), then step += 1
 void sweep(MixedCtx& c, const Graph& g, const float* y_in, float* y_out);
 // S += T, T = 0; then for columns with rmask = 1 write y~ into `y` (in place);

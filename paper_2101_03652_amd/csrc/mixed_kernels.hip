@@ -178,7 +178,7 @@ __global__ __launch_bounds__(kBlock) void push_k(
 __global__ void convert_k(int32_t n, int shift, const int32_t* __restrict__ deg, double alpha,
                           const int32_t* __restrict__ cmask, double* __restrict__ r64, double* __restrict__ pi64,
                           float* __restrict__ Y, float* __restrict__ Shi, float* __restrict__ Slo,
-                          float* __restrict__ T, float* __restrict__ Q, double* __restrict__ partials) {
+                          float* __restrict__ T, double* __restrict__ partials) {
     __shared__ double sh[kBlock];
     __shared__ int32_t cm[128];
     const int B = 1 << shift;
@@ -202,7 +202,6 @@ __global__ void convert_k(int32_t n, int shift, const int32_t* __restrict__ deg,
             Shi[i] = h;
             Slo[i] = l;
             T[i] = 0.f;
-            if (Q) Q[i] = 0.f;
             r64[i] = 0.0;
             pi64[i] = 0.0;
             acc += r;
@@ -261,33 +260,38 @@ __device__ inline float4 gather_gs(const float4* __restrict__ Y_in, const float4
 
 // y'(u) = scale(u) * acc for the columns inside their sweep budget (0 for the
 // others); T += y' (plus, on an entry sweep, the fresh residue's alpha-part).
-// SOR: the node holds p = q + scale(u) * acc (q: what it kept last time),
-// pushes y' = omega p and keeps q' = (1 - omega) p; columns outside their
-// budget keep q.
+// SOR: the node holds p = q + scale(u) * acc, where q is what it kept back
+// last sweep, pushes y' = omega p and keeps (1 - omega) p.  What it kept back
+// is (1 - omega) / omega times what it pushed, i.e. y' = omega scale(u) acc +
+// (1 - omega) y_prev(u) with y_prev(u) = Y_in(u), its previous push; a fresh
+// residue (entry sweep) has kept nothing back.  A column leaves its budget
+// only at the end of a stage, and the refresh that follows forms a new
+// residue, so no kept-back part outlives a stage.
 template <int C, bool SOR>
 __device__ inline void finish_row(int32_t u, int c, float4 acc, int32_t step, const float* __restrict__ scale,
                                   const float4* __restrict__ Y_in, float4* Y_out, float4* __restrict__ T,
                                   const int32_t* __restrict__ kb, const int32_t* __restrict__ entry,
-                                  float4* __restrict__ Q, const float* __restrict__ omega) {
+                                  const float* __restrict__ omega) {
     const int64_t at = (int64_t)u * C + c;
     float4 t = T[at];
     const float sc = scale[u];
     const int4 kb4 = reinterpret_cast<const int4*>(kb)[c];
     const float4 m = make_float4(step < kb4.x ? 1.f : 0.f, step < kb4.y ? 1.f : 0.f, step < kb4.z ? 1.f : 0.f,
                                  step < kb4.w ? 1.f : 0.f);
+    float4 en = make_float4(0.f, 0.f, 0.f, 0.f);
     if (step == 0) {
-        const float4 en = flag4(reinterpret_cast<const int4*>(entry)[c]);
+        en = flag4(reinterpret_cast<const int4*>(entry)[c]);
         if (en.x + en.y + en.z + en.w != 0.f) t = f4_add(t, f4_mul(f4_mul(Y_in[at], en), m));
     }
     acc = f4_mul(acc, m);
     float4 y = make_float4(sc * acc.x, sc * acc.y, sc * acc.z, sc * acc.w);
     if (SOR) {
-        const float4 q = Q[at];
         const float4 w = reinterpret_cast<const float4*>(omega)[c];
-        const float4 p = make_float4(q.x + y.x, q.y + y.y, q.z + y.z, q.w + y.w);
-        y = make_float4(m.x * w.x * p.x, m.y * w.y * p.y, m.z * w.z * p.z, m.w * w.w * p.w);
-        Q[at] = make_float4(m.x != 0.f ? (1.f - w.x) * p.x : q.x, m.y != 0.f ? (1.f - w.y) * p.y : q.y,
-                            m.z != 0.f ? (1.f - w.z) * p.z : q.z, m.w != 0.f ? (1.f - w.w) * p.w : q.w);
+        const float4 yp = Y_in[at];
+        const float4 k = make_float4(m.x * (1.f - en.x) * (1.f - w.x), m.y * (1.f - en.y) * (1.f - w.y),
+                                     m.z * (1.f - en.z) * (1.f - w.z), m.w * (1.f - en.w) * (1.f - w.w));
+        y = make_float4(w.x * y.x + k.x * yp.x, w.y * y.y + k.y * yp.y, w.z * y.z + k.z * yp.z,
+                        w.w * y.w + k.w * yp.w);
     }
     Y_out[at] = y;
     T[at] = f4_add(t, y);
@@ -299,7 +303,7 @@ __global__ __launch_bounds__(kBlock) void sweep_k(
         const RowBlock* __restrict__ blocks, int32_t lo, const float* __restrict__ scale,
         const float4* __restrict__ Y_in, float4* Y_out, float4* __restrict__ T,
         const int32_t* __restrict__ kb, const int32_t* __restrict__ entry, const int32_t* __restrict__ step_p,
-        float4* __restrict__ partials, float4* __restrict__ Q, const float* __restrict__ omega) {
+        float4* __restrict__ partials, const float* __restrict__ omega) {
     using P = Sw<C>;
     __shared__ float4 lds[kLdsBytes / 16];
     const RowBlock b = blocks[blockIdx.x];
@@ -357,7 +361,7 @@ __global__ __launch_bounds__(kBlock) void sweep_k(
         partials[(int64_t)b.piece * C + c] = acc;
         return;
     }
-    finish_row<C, SOR>(r0 + row, c, acc, step, scale, Y_in, Y_out, T, kb, entry, Q, omega);
+    finish_row<C, SOR>(r0 + row, c, acc, step, scale, Y_in, Y_out, T, kb, entry, omega);
 }
 
 // Long rows of one chunk: the pieces' partial sums added in slot order.
@@ -366,22 +370,29 @@ __global__ __launch_bounds__(kBlock) void combine_k(
         const LongRow* __restrict__ rows, int32_t count, const float4* __restrict__ partials,
         const int32_t* __restrict__ step_p, const float* __restrict__ scale, const float4* __restrict__ Y_in,
         float4* Y_out, float4* __restrict__ T, const int32_t* __restrict__ kb, const int32_t* __restrict__ entry,
-        float4* __restrict__ Q, const float* __restrict__ omega) {
+        const float* __restrict__ omega) {
     const int32_t i = (int32_t)blockIdx.x * (kBlock / C) + (int32_t)threadIdx.x / C;
     const int c = threadIdx.x % C;
     if (i >= count) return;
     const LongRow L = rows[i];
     float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
     for (int32_t p = 0; p < L.npieces; ++p) acc = f4_add(acc, partials[(int64_t)(L.first + p) * C + c]);
-    finish_row<C, SOR>(L.row, c, acc, *step_p, scale, Y_in, Y_out, T, kb, entry, Q, omega);
+    finish_row<C, SOR>(L.row, c, acc, *step_p, scale, Y_in, Y_out, T, kb, entry, omega);
 }
 
 __global__ void bump_step_k(int32_t* step) { step[0] += 1; }
 
 // S += T (compensated), T = 0, dense over n x B.
-__global__ void flush_k(int64_t total, float* __restrict__ Shi, float* __restrict__ Slo, float* __restrict__ T) {
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
+// Only the columns being refreshed (rmask) are flushed: a column's reserve
+// then takes the same roundings whichever other columns share the block and
+// whenever they refresh.  The grid stride is a multiple of the block width,
+// so a thread's column is fixed.
+__global__ void flush_k(int64_t total, int32_t Bw, const int32_t* __restrict__ rmask, float* __restrict__ Shi,
+                        float* __restrict__ Slo, float* __restrict__ T) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (!rmask[i0 & (Bw - 1)]) return;
+    for (int64_t i = i0; i < total; i += stride) {
         float t = T[i];
         if (t != 0.f) {
             float h = Shi[i], l = Slo[i];
@@ -408,7 +419,7 @@ __global__ __launch_bounds__(kBlock) void refresh_k(
         const RowBlock* __restrict__ blocks, int32_t n_blocks,
         const int32_t* __restrict__ deg, const float4* __restrict__ Shi, const float4* __restrict__ Slo,
         const int32_t* __restrict__ src, const int32_t* __restrict__ rmask, double alpha,
-        float4* __restrict__ Y, float4* __restrict__ Q, double* __restrict__ rt_out, int32_t n,
+        float4* __restrict__ Y, double* __restrict__ rt_out, int32_t n,
         double* __restrict__ partials) {
     using P = Rf<C>;
     __shared__ float4 lds_h[P::kNnz * C];
@@ -499,14 +510,6 @@ __global__ __launch_bounds__(kBlock) void refresh_k(
                 if (w4.z) y.z = (float)(oma * t2 / d);
                 if (w4.w) y.w = (float)(oma * t3 / d);
                 Y[at] = y;
-                if (Q) {                           // a fresh residue: nothing kept back
-                    float4 q = Q[at];
-                    if (w4.x) q.x = 0.f;
-                    if (w4.y) q.y = 0.f;
-                    if (w4.z) q.z = 0.f;
-                    if (w4.w) q.w = 0.f;
-                    Q[at] = q;
-                }
             }
             if (rt_out) {   // column-major FP64 residual [B][n]
                 rt_out[(int64_t)(4 * c + 0) * n + u] = t0;
@@ -603,7 +606,6 @@ void sweep_launch(MixedCtx& c, Graph& g, const float* yin, float* yout) {
     const RowBlock* blocks = sch.blocks.as<RowBlock>();
     const LongRow* lrows = sch.longrows.as<LongRow>();
     float4* part = c.piece_part.as<float4>();
-    float4* Q = SOR ? c.Q.as<float4>() : nullptr;
     const float* om = SOR ? c.omega.as<float>() : nullptr;
     for (int j = 0; j < sch.chunks; ++j) {      // chunk j sees the output of chunks < j
         const int32_t nb = sch.first[j + 1] - sch.first[j];
@@ -614,19 +616,19 @@ void sweep_launch(MixedCtx& c, Graph& g, const float* yin, float* yout) {
             hipLaunchKernelGGL((sweep_k<int64_t, C, SOR>), grid, blk, 0, c.stream, g.col_ptr.as<int64_t>(),
                                g.row_idx.as<int32_t>(), bj, sch.lo[j], c.scale.as<float>(), Y4i, Y4o,
                                c.T.as<float4>(), c.kb.as<int32_t>(), c.entry.as<int32_t>(), c.step.as<int32_t>(),
-                               part, Q, om);
+                               part, om);
         else
             hipLaunchKernelGGL((sweep_k<uint32_t, C, SOR>), grid, blk, 0, c.stream, g.col_ptr.as<uint32_t>(),
                                g.row_idx.as<int32_t>(), bj, sch.lo[j], c.scale.as<float>(), Y4i, Y4o,
                                c.T.as<float4>(), c.kb.as<int32_t>(), c.entry.as<int32_t>(), c.step.as<int32_t>(),
-                               part, Q, om);
+                               part, om);
         const int32_t nl = sch.lr_first[j + 1] - sch.lr_first[j];
         if (nl > 0) {
             const int per = kBlock / C;
             hipLaunchKernelGGL((combine_k<C, SOR>), dim3((unsigned)((nl + per - 1) / per)), dim3(kBlock), 0,
                                c.stream, lrows + sch.lr_first[j], nl, part, c.step.as<int32_t>(),
                                c.scale.as<float>(), Y4i, Y4o, c.T.as<float4>(), c.kb.as<int32_t>(),
-                               c.entry.as<int32_t>(), Q, om);
+                               c.entry.as<int32_t>(), om);
         }
     }
     hipLaunchKernelGGL(bump_step_k, dim3(1), dim3(1), 0, c.stream, c.step.as<int32_t>());
@@ -636,7 +638,6 @@ void sweep_launch(MixedCtx& c, Graph& g, const float* yin, float* yout) {
 template <int C>
 void sweep_c(MixedCtx& c, Graph& g, const float* yin, float* yout) {
     if (c.sor) {
-        if (!c.Q.p) fail(PPR_ERR_ARG, "internal: over-relaxed sweep without its state");
         sweep_launch<C, true>(c, g, yin, yout);
     } else {
         sweep_launch<C, false>(c, g, yin, yout);
@@ -645,8 +646,8 @@ void sweep_c(MixedCtx& c, Graph& g, const float* yin, float* yout) {
 
 template <int C>
 void refresh_c(MixedCtx& c, Graph& g, float* y, double* rt_out) {
-    hipLaunchKernelGGL(flush_k, dim3(2048), dim3(kBlock), 0, c.stream, (int64_t)g.n * c.Bw, c.Shi.as<float>(),
-                       c.Slo.as<float>(), c.T.as<float>());
+    hipLaunchKernelGGL(flush_k, dim3(2048), dim3(kBlock), 0, c.stream, (int64_t)g.n * c.Bw, c.Bw,
+                       c.rmask.as<int32_t>(), c.Shi.as<float>(), c.Slo.as<float>(), c.T.as<float>());
     const Schedule& sch = refresh_schedule<C>(g);
     dim3 grid((unsigned)std::min(sch.n_blocks, kGridRed)), blk(kBlock);
     auto H = c.Shi.as<float4>();
@@ -656,12 +657,12 @@ void refresh_c(MixedCtx& c, Graph& g, float* y, double* rt_out) {
         hipLaunchKernelGGL((refresh_k<int64_t, C>), grid, blk, 0, c.stream, g.col_ptr.as<int64_t>(),
                            g.row_idx.as<int32_t>(), sch.blocks.as<RowBlock>(), sch.n_blocks,
                            g.deg.as<int32_t>(), H, L, c.src.as<int32_t>(), c.rmask.as<int32_t>(), c.alpha, Y4,
-                           c.Q.as<float4>(), rt_out, g.n, c.partials.as<double>());
+                           rt_out, g.n, c.partials.as<double>());
     else
         hipLaunchKernelGGL((refresh_k<uint32_t, C>), grid, blk, 0, c.stream, g.col_ptr.as<uint32_t>(),
                            g.row_idx.as<int32_t>(), sch.blocks.as<RowBlock>(), sch.n_blocks,
                            g.deg.as<int32_t>(), H, L, c.src.as<int32_t>(), c.rmask.as<int32_t>(), c.alpha, Y4,
-                           c.Q.as<float4>(), rt_out, g.n, c.partials.as<double>());
+                           rt_out, g.n, c.partials.as<double>());
     hipLaunchKernelGGL(reduce_cols_k, dim3(1), dim3(256), 0, c.stream, c.partials.as<double>(), (int)grid.x, c.Bw,
                        c.colsum.as<double>());
     HIPCHECK(hipGetLastError());
@@ -727,7 +728,7 @@ void convert(MixedCtx& c, const Graph& g, double alpha) {
     hipLaunchKernelGGL(convert_k, dim3(gc), dim3(kBlock), 0, c.stream, g.n, c.shift, g.deg.as<int32_t>(), alpha,
                        c.cmask.as<int32_t>(), c.r64.as<double>(), c.pi64.as<double>(),
                        const_cast<float*>(c.ycur), c.Shi.as<float>(), c.Slo.as<float>(), c.T.as<float>(),
-                       c.Q.as<float>(), c.partials.as<double>());
+                       c.partials.as<double>());
     hipLaunchKernelGGL(reduce_cols_k, dim3(1), dim3(256), 0, c.stream, c.partials.as<double>(), (int)gc, c.Bw,
                        c.colsum.as<double>());
     HIPCHECK(hipGetLastError());
@@ -744,13 +745,6 @@ void prepare(MixedCtx& c, const Graph& g) {
         }
         (void)refresh_schedule<decltype(cc)::value>(gg);
     });
-}
-
-void ensure_sor(MixedCtx& c) {
-    if (c.Q.p) return;
-    c.drop_chunks();
-    c.Q.alloc(4 * (size_t)c.n * (size_t)c.Bw);
-    HIPCHECK(hipMemsetAsync(c.Q.p, 0, c.Q.bytes, c.stream));
 }
 
 void sweep(MixedCtx& c, const Graph& g, const float* y_in, float* y_out) {

@@ -254,7 +254,7 @@ def test_over_relaxed_sweeps_certified(c1, c1_truth, omega):
     G = P.Graph.from_synth(c1)
     out, st = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=32, sweep_chunks=4, sor_omega=omega)
     _check_batch(c1, srcs, out, st, 1e-8, c1_truth)
-    _, st1 = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=32, sweep_chunks=4)
+    _, st1 = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=32, sweep_chunks=4, sor_omega=1.0)
     assert np.mean([s["sweeps"] for s in st]) < np.mean([s["sweeps"] for s in st1])
     for b in (0, 13):
         alone, sal = G.query_batch([srcs[b]], ALPHA, 1e-8, P.MIXED, batch_cols=4, sweep_chunks=4,
@@ -264,17 +264,38 @@ def test_over_relaxed_sweeps_certified(c1, c1_truth, omega):
     G.close()
 
 
+def test_automatic_over_relaxation(c1):
+    """sor_omega = 0 (the default) over-relaxes with 1.2 when a sweep has
+    more than one chunk and not at all with one chunk."""
+    srcs = [int(s) for s in synth.sources(c1.n, 9)][:8]
+    G = P.Graph.from_synth(c1)
+    for chunks, same in ((4, 1.2), (1, 1.0)):
+        out, st = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=8, sweep_chunks=chunks)
+        ref, sref = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=8, sweep_chunks=chunks, sor_omega=same)
+        assert [s["sweeps"] for s in st] == [s["sweeps"] for s in sref]
+        np.testing.assert_array_equal(out, ref)
+        if chunks == 1:
+            assert all(s["sor_omega"] == 1.0 for s in st)
+    with pytest.raises(P.PPRError):
+        G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, sor_omega=0.9)
+    G.close()
+
+
 def test_over_relaxation_falls_back_on_a_cycle():
     """On a directed cycle over-relaxed pushes make the residue grow; the
     refresh that ends the first stage measures it and the column continues
-    with omega = 1, still certified."""
+    with omega = 1, still certified.  (switch_param = 1e30 skips the local
+    phase, which would otherwise finish a cycle on its own.)"""
     a = 1 - ALPHA
     n = 1000
     g = synth.cycle(n)
     x = np.array([ALPHA * a ** ((v - 5) % n) / (1 - a ** n) for v in range(n)])
     G = P.Graph.from_synth(g)
-    out, st = G.query_batch([5, 17], ALPHA, 1e-8, P.MIXED, batch_cols=4, sweep_chunks=4, sor_omega=1.25)
+    out, st = G.query_batch([5, 17], ALPHA, 1e-8, P.MIXED, batch_cols=4, sweep_chunks=4, sor_omega=1.25,
+                            switch_param=1e30)
+    assert st[0]["local_levels"] == 0
     assert st[0]["cert_l1"] <= 1e-8
     assert np.abs(out[0] - x).sum() <= 1e-8 + SLACK
     assert st[0]["refreshes"] >= 2
+    assert st[0]["sor_omega"] == 1.0            # fell back
     G.close()

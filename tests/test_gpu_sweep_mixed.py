@@ -82,31 +82,33 @@ def test_sweep_device_buffers_and_errors(graphs):
 @pytest.mark.parametrize("width,chunks", [(4, 3), (32, 4), (128, 8)])
 def test_over_relaxed_sweep_matches_oracle(graphs, name, width, chunks):
     """The over-relaxed sweep against the oracle's, per column: omega between
-    1 and 1.3 (some exactly 1), kept residues q of either sign, fresh and
-    continuing columns.  Kept residues can be negative, so the rounding bound
-    is taken relative to the same recursion run on absolute values."""
+    1 and 1.3 (some exactly 1), fresh and continuing columns.  The kernel keeps
+    no separate kept-back residue: a continuing row kept (1 - omega) / omega
+    times what it pushed last (y_in), a fresh one nothing; the oracle is given
+    that q explicitly.  q is negative for omega > 1, so the rounding bound is
+    taken relative to the same recursion run on absolute values."""
     g = graphs[name]
     print(f"[gpu] over-relaxed sweep parity {name} width={width} chunks={chunks}", flush=True)
     G = P.Graph.from_synth(g)
     rng = np.random.default_rng(width * 7 + chunks)
     y = rng.random((g.n, width)).astype(np.float32)
     y[rng.random((g.n, width)) < 0.3] = 0.0
-    q = ((rng.random((g.n, width)) - 0.6) * 0.2).astype(np.float32)
     fresh = (rng.random(width) < 0.5).astype(np.int32)
     om = (1.0 + 0.3 * rng.random(width)).astype(np.float32)
     om[0] = 1.0
-    q_out = np.empty_like(y)
-    got = P.debug_sweep_mixed(G, ALPHA, y, fresh, chunks=chunks, omega=om, q_in=q, q_out=q_out)
+    got = P.debug_sweep_mixed(G, ALPHA, y, fresh, chunks=chunks, omega=om)
     csc_arrays = oracle.csc(g)
     din = np.diff(csc_arrays[0]).astype(np.float64)
     lo = oracle.chunk_bounds(g, chunks)
     tol_rel = (din + din.max() + 6) * U
     for b in range(width):
-        yb, qb = y[:, b].astype(np.float64), q[:, b].astype(np.float64)
-        want_y, want_q = oracle.block_sor_sweep(g, ALPHA, lo, yb, bool(fresh[b]), float(om[b]), qb,
-                                                csc_arrays=csc_arrays)
-        mag_y, mag_q = oracle.block_sor_sweep(g, ALPHA, lo, np.abs(yb), bool(fresh[b]), float(om[b]),
-                                              np.abs(qb), csc_arrays=csc_arrays)
+        w = float(om[b])
+        yb = y[:, b].astype(np.float64)
+        qb = np.zeros(g.n) if fresh[b] else (1.0 - w) / w * yb
+        want_y, want_q = oracle.block_sor_sweep(g, ALPHA, lo, yb, bool(fresh[b]), w, qb, csc_arrays=csc_arrays)
+        mag_y, _ = oracle.block_sor_sweep(g, ALPHA, lo, yb, bool(fresh[b]), w, np.abs(qb), csc_arrays=csc_arrays)
         assert np.all(np.abs(got[:, b] - want_y) <= tol_rel * mag_y + 1e-38), b
-        assert np.all(np.abs(q_out[:, b] - want_q) <= tol_rel * np.abs(mag_q) + 1e-38), b
+        # what the row keeps is (1 - omega) / omega times what it pushes: the
+        # next sweep's q, read back from y_out
+        np.testing.assert_allclose(want_q, (1.0 - w) / w * want_y, rtol=1e-13, atol=1e-300)
     G.close()
