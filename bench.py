@@ -31,12 +31,13 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def sweep_bytes(n: int, m: int, width: int) -> int:
+def sweep_bytes(n: int, m: int, width: int, over_relaxed: bool = False) -> int:
     """Algorithmic bytes of one batched global sweep (all its row chunks):
     in-edge indices (4 m), per-node CSC offset and FP32 scale (8 n), and per
     (node, column) 16 bytes: the residue row read once, the new residue
-    written, the per-stage reserve accumulator read and written."""
-    return 4 * m + 8 * n + 16 * n * width
+    written, the per-stage reserve accumulator read and written; over-relaxed
+    sweeps also read the row's previous push (4 more)."""
+    return 4 * m + 8 * n + (20 if over_relaxed else 16) * n * width
 
 
 def fp64_sweep_bytes(n: int, m: int) -> int:
@@ -160,7 +161,8 @@ def main() -> int:
             sweep_ms += s["sweep_ms"]
             sweep_n += s["sweep_launches"]
     avg_sweep_ms = sweep_ms / max(sweep_n, 1)
-    bytes_per = sweep_bytes(g.n, g.m, width)
+    over_relaxed = any(s["sor_omega"] > 1.0 for st in stats_all for s in st)
+    bytes_per = sweep_bytes(g.n, g.m, width, over_relaxed)
     achieved = bytes_per / (avg_sweep_ms * 1e-3) / 1e9
     print(f"[bench] mixed: {qps:.1f} q/s, {dt/args.steps*1e3:.1f} ms/step, sweep {avg_sweep_ms:.3f} ms avg "
           f"over {int(sweep_n)} launches, max cert {max_cert:.3e}", file=sys.stderr, flush=True)
@@ -216,7 +218,8 @@ def main() -> int:
         per_w = st_w[0]["sweep_ms"] / max(st_w[0]["sweep_launches"], 1)
         widths[str(w)] = {"value": round(args.sources / dt_w, 3), "unit": "queries/s",
                           "ms_per_sweep": round(per_w, 4),
-                          "sweep_GBps_algorithmic": round(sweep_bytes(g.n, g.m, w) / (per_w * 1e-3) / 1e9, 1)}
+                          "sweep_GBps_algorithmic": round(sweep_bytes(g.n, g.m, w, any(s["sor_omega"] > 1.0 for s in st_w))
+                                                          / (per_w * 1e-3) / 1e9, 1)}
         print(f"[bench] width {w}: {widths[str(w)]}", flush=True, file=sys.stderr)
 
     # sources one at a time: plain FP64 path against the mixed path (one column)
@@ -252,6 +255,7 @@ def main() -> int:
 
     chunks = stats_all[0][0]["sweep_chunks"]
     omegas = sorted({round(s["sor_omega"], 4) for sts in stats_all for s in sts})
+    sk_name = f"sweep_k<C={width // 4}{', over-relaxed' if over_relaxed else ''}>"
     traffic = measured_traffic(width, chunks)
 
     cpu = None
@@ -303,7 +307,7 @@ def main() -> int:
         # one "launch" here is one global sweep: `chunks` launches of sweep_k
         # (block Gauss-Seidel row chunks) and their combine_k launches, timed
         # together with HIP events on the library's stream
-        "roofline": {"bound": "hbm", "kernel": f"sweep_k<C={width // 4}> x{chunks} chunks + combine_k",
+        "roofline": {"bound": "hbm", "kernel": f"{sk_name} x{chunks} chunks + combine_k",
                      "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "traffic_GBps": round(traffic / (avg_sweep_ms * 1e-3) / 1e9, 1) if traffic else None,
