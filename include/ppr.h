@@ -203,6 +203,41 @@ ppr_status ppr_query_ex(ppr_graph* g, const int32_t* sources, int32_t B, double 
                         double lambda, const ppr_options* opt, double* pi_out, double* r_out,
                         ppr_stats* stats);
 
+/* One point of a convergence trace (see ppr_query_trace). */
+typedef struct {
+    double ms;              /* host time since the call started, taken once the iteration has
+                               completed on the device */
+    double r_sum;           /* residue sum after the iteration (FP64).  The residues of the
+                               PPR_FP64 path stay >= 0, so this is ||pi_hat - pi_s||_1 exactly
+                               (Section 2: pi_s = pi_hat + sum_v r(v) pi_v, ||pi_v||_1 = 1) */
+    int64_t edge_pushes;    /* residue updates so far: sum of d_v over pushed nodes (a
+                               threshold-0 sweep counts m) */
+    int32_t phase;          /* 0: local iteration S^(j); 1: global sweep or scan */
+    int32_t index;          /* 1-based iteration number within its phase */
+} ppr_trace_point;
+
+/*
+ * One PPR_FP64 query that records how its l1 error falls against time and
+ * against residue updates (the quantities of Section 8's convergence
+ * figures): a point after every local iteration and every global sweep or
+ * scan.  Local points carry the running r_sum the switch test uses; global
+ * points the exact sum after that sweep.  The traced run synchronises with
+ * the device after every iteration (an untraced query replays its threshold-0
+ * sweeps from a captured graph), so its times run a few percent above an
+ * untraced query's.  With switch_param = 1e30 the query is power iteration
+ * (Eqs. 3-6), with switch_param = 0 the level-synchronous forward push
+ * (Algorithm 2), with global_rule = PPR_GLOBAL_EPOCHS Algorithm 3's epochs.
+ *   opt: NULL = defaults; opt->precision must be PPR_FP64.
+ *   pi_out: double[n], host or device.
+ *   trace: host array of `capacity` points; *count (host) receives the number
+ *   of iterations run; points beyond capacity are not written.
+ *   Errors as ppr_query_ex; PPR_ERR_ARG if trace or count is NULL while
+ *   capacity > 0, or capacity < 0.
+ */
+ppr_status ppr_query_trace(ppr_graph* g, int32_t s, double alpha, double lambda, const ppr_options* opt,
+                           double* pi_out, ppr_trace_point* trace, int32_t capacity, int32_t* count,
+                           ppr_stats* stats);
+
 /*
  * One global sweep on caller data, for verification of the sweep kernel:
  * r_out = (1 - alpha) r_in P and pi += alpha r_in (Simultaneous Forward Push,

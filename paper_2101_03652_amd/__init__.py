@@ -38,7 +38,7 @@ EXPORTS = [
     "ppr_graph_copy_csc", "ppr_query", "ppr_query_batch", "ppr_query_ex",
     "ppr_debug_sweep_fp64", "ppr_version", "ppr_last_error", "ppr_autotune",
     "ppr_block_create", "ppr_block_destroy", "ppr_block_footprint", "ppr_slot_admit",
-    "ppr_block_step", "ppr_block_poll", "ppr_slot_retire", "ppr_debug_sweep_mixed",
+    "ppr_block_step", "ppr_block_poll", "ppr_slot_retire", "ppr_debug_sweep_mixed", "ppr_query_trace",
 ]
 
 
@@ -59,6 +59,11 @@ class Stats(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# one ppr_trace_point
+TRACE_DTYPE = np.dtype([("ms", np.float64), ("r_sum", np.float64), ("edge_pushes", np.int64),
+                        ("phase", np.int32), ("index", np.int32)])
 
 
 class Options(ctypes.Structure):
@@ -99,6 +104,7 @@ def load() -> ctypes.CDLL:
         "ppr_query": (st, [vp, i32, f64, f64, ctypes.c_int, vp, vp]),
         "ppr_query_batch": (st, [vp, vp, i32, f64, f64, ctypes.c_int, vp, vp]),
         "ppr_query_ex": (st, [vp, vp, i32, f64, f64, vp, vp, vp, vp]),
+        "ppr_query_trace": (st, [vp, i32, f64, f64, vp, vp, vp, i32, vp, vp]),
         "ppr_debug_sweep_fp64": (st, [vp, f64, vp, vp, vp, vp]),
         "ppr_autotune": (st, [vp, f64, vp, i32, vp, vp]),
         "ppr_debug_sweep_mixed": (st, [vp, f64, i32, i32, vp, vp, vp, vp, vp]),
@@ -219,6 +225,24 @@ class Graph:
                                  _ptr(out), _ptr(r_out) if r_out is not None else None, st)
         _check(rc)
         return out, [s.as_dict() for s in st]
+
+    def query_trace(self, s: int, alpha: float = 0.2, lam: float = 1e-8, out=None, capacity: int = 4096,
+                    **opt):
+        """One FP64 query with its convergence trace.  Returns (pi_hat, trace,
+        stats); trace is a structured array with fields ms, r_sum (= the l1
+        error), edge_pushes, phase (0 local, 1 global) and index, one row per
+        iteration."""
+        if out is None:
+            out = np.empty(self.n, dtype=np.float64)
+        tr = np.zeros(capacity, dtype=TRACE_DTYPE)
+        cnt = ctypes.c_int32()
+        st = Stats()
+        o = options(precision=FP64, **opt)
+        _check(load().ppr_query_trace(self._h, int(s), float(alpha), float(lam), ctypes.byref(o), _ptr(out),
+                                      _ptr(tr), int(capacity), ctypes.byref(cnt), ctypes.byref(st)))
+        if cnt.value > capacity:
+            raise PPRError(-1, f"trace needs {cnt.value} points, capacity is {capacity}")
+        return out, tr[:cnt.value].copy(), st.as_dict()
 
     def autotune(self, alpha: float = 0.2, widths=None) -> dict:
         """Pick the batched block width by timing sweeps on this graph; the

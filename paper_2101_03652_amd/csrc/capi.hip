@@ -158,6 +158,34 @@ ppr_status ppr_query_ex(ppr_graph* gh, const int32_t* sources, int32_t B, double
     });
 }
 
+ppr_status ppr_query_trace(ppr_graph* gh, int32_t s, double alpha, double lambda, const ppr_options* opt,
+                           double* pi_out, ppr_trace_point* trace, int32_t capacity, int32_t* count,
+                           ppr_stats* stats) {
+    return guarded([&] {
+        Graph* g = reinterpret_cast<Graph*>(gh);
+        check_query_args(g, &s, 1, alpha, lambda, pi_out);
+        ppr_options o;
+        if (opt) o = *opt; else ppr_options_default(&o);
+        check_options(o);
+        if (o.precision != PPR_FP64) fail(PPR_ERR_ARG, "a traced query runs the PPR_FP64 path");
+        if (capacity < 0 || !count || (capacity > 0 && !trace)) fail(PPR_ERR_ARG, "bad trace buffer");
+        HIPCHECK(hipSetDevice(g->device));
+        (void)is_device_ptr(pi_out, g->device);
+        TraceSink sink;
+        sink.out = trace;
+        sink.cap = capacity;
+        sink.t0 = std::chrono::steady_clock::now();
+        *count = 0;
+        try {
+            run_fp64_query(*g, s, alpha, lambda, o, pi_out, nullptr, stats, &sink);
+        } catch (...) {
+            *count = sink.count;
+            throw;
+        }
+        *count = sink.count;
+    });
+}
+
 ppr_status ppr_query(ppr_graph* g, int32_t s, double alpha, double lambda, ppr_precision precision,
                      double* pi_out, ppr_stats* stats) {
     ppr_options o;

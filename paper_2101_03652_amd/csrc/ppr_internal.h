@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <chrono>
 #include <cstdint>
 #include <cstdio>
 #include <memory>
@@ -219,8 +220,28 @@ void cert_f64(const Graph& g, const Schedule& sch, double alpha, int32_t src, co
 }  // namespace k
 
 // ---------------------------------------------------------------- runtime
+// Convergence trace of one FP64 query: a point per local iteration and per
+// global sweep or scan, written while there is room, counted always.
+struct TraceSink {
+    ppr_trace_point* out = nullptr;
+    int32_t cap = 0;
+    int32_t count = 0;
+    std::chrono::steady_clock::time_point t0;
+    void note(int32_t phase, int32_t index, int64_t edge_pushes, double r_sum) {
+        if (count < cap) {
+            ppr_trace_point& p = out[count];
+            p.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            p.r_sum = r_sum;
+            p.edge_pushes = edge_pushes;
+            p.phase = phase;
+            p.index = index;
+        }
+        ++count;
+    }
+};
+
 void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_options& opt,
-                    double* pi_out, double* r_out, ppr_stats* st);
+                    double* pi_out, double* r_out, ppr_stats* st, TraceSink* trace = nullptr);
 void run_mixed_batch(Graph& g, const int32_t* sources, int32_t B, double alpha, double lambda,
                      const ppr_options& opt, double* pi_out, double* r_out, ppr_stats* st);
 void autotune_width(Graph& g, double alpha, const int32_t* widths, int32_t count, int32_t* best,

@@ -103,7 +103,7 @@ bool continue_local(const ppr_options& opt, int64_t nf, int64_t vol, int32_t n, 
 }  // namespace
 
 void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_options& opt,
-                    double* pi_out, double* r_out, ppr_stats* st) {
+                    double* pi_out, double* r_out, ppr_stats* st, TraceSink* trace) {
     auto t0 = std::chrono::steady_clock::now();
     HIPCHECK(hipSetDevice(g.device));
     CtxLease lease(g);
@@ -144,6 +144,7 @@ void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_
         vol = hctr[1];
         std::swap(F, Fn);
         ++levels;
+        if (trace) trace->note(0, levels, edge_pushes, r_sum);
     }
 
     // ---- exact r_sum, and y = (1-alpha) r / d for the first sweep
@@ -188,6 +189,7 @@ void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_
                 ++sweeps;
                 edge_pushes += (int64_t)hd[1];
                 r_sum = hd[0];
+                if (trace) trace->note(1, sweeps, edge_pushes, r_sum);
             }
         }
         ev.stop(ss);
@@ -212,7 +214,17 @@ void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_
             yc = yn;
             yn = t;
         };
-        if (K == 1) {
+        if (trace) {
+            // the same flag sequence one sweep at a time, each followed by its
+            // exact r_sum (the sweep's partials hold the new residues' sums)
+            for (int32_t j = 1; j <= K; ++j) {
+                advance((j == 1 ? k::SW_ENTRY : 0) | (j == K ? k::SW_WRITE_R : k::SW_FOLD));
+                k::reduce_sum(partials, k::sweep_parts(sch), c.dsum.as<double>(), ss);
+                HIPCHECK(hipMemcpyAsync(hd, c.dsum.p, 8, hipMemcpyDeviceToHost, ss));
+                HIPCHECK(hipStreamSynchronize(ss));
+                trace->note(1, j, edge_pushes + (int64_t)j * g.m, hd[0]);
+            }
+        } else if (K == 1) {
             advance(k::SW_ENTRY | k::SW_WRITE_R);
         } else {
             advance(k::SW_ENTRY | k::SW_FOLD);            // now yc == y1
@@ -241,6 +253,7 @@ void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_
             HIPCHECK(hipMemcpyAsync(hd, c.dsum.p, 8, hipMemcpyDeviceToHost, ss));
             HIPCHECK(hipStreamSynchronize(ss));
             r_sum = hd[0];
+            if (trace) trace->note(1, sweeps, edge_pushes + (int64_t)sweeps * g.m, r_sum);
         }
     }
     if (opt.global_rule != PPR_GLOBAL_EPOCHS) edge_pushes += (int64_t)sweeps * g.m;
