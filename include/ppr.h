@@ -105,7 +105,7 @@ typedef enum {
 typedef struct {
     int32_t precision;      /* ppr_precision */
     int32_t switch_rule;    /* ppr_switch_rule; default PPR_SWITCH_EDGES */
-    double switch_param;    /* PPR_SWITCH_EDGES: continue while param * vol <= m; default 8 */
+    double switch_param;    /* PPR_SWITCH_EDGES: continue while param * vol <= m; default 32 */
     int32_t max_sweeps;     /* cap on the global sweeps of each query; default 4096 */
     int32_t certify;        /* PPR_FP64: also compute cert_l1; default 0 */
     double refresh_factor;  /* PPR_MIXED: refresh the residual in FP64 whenever r_sum has

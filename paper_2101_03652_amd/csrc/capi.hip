@@ -71,7 +71,7 @@ void ppr_options_default(ppr_options* o) {
     std::memset(o, 0, sizeof(*o));
     o->precision = PPR_FP64;
     o->switch_rule = PPR_SWITCH_EDGES;
-    o->switch_param = 8.0;
+    o->switch_param = 32.0;
     o->max_sweeps = 4096;
     o->certify = 0;
     o->refresh_factor = 1e4;

@@ -41,8 +41,25 @@ int main(void) {
     }
     double diff = 0.0;
     for (int i = 0; i < 5; ++i) diff += fabs(pib[i] - pi[i]) + fabs(pib[5 + i] - pi[i]);
+    /* power iteration traced: the l1 error after k sweeps is 0.8^k (Eq. 6) */
+    ppr_options o;
+    ppr_options_default(&o);
+    o.switch_param = 1e30;
+    ppr_trace_point tr[256];
+    int32_t cnt = 0;
+    if (ppr_query_trace(g, 0, 0.2, 1e-12, &o, pi, tr, 256, &cnt, NULL) != PPR_OK) {
+        printf("trace failed: %s\n", ppr_last_error());
+        return 1;
+    }
+    double tdev = 0.0, a = 1.0;
+    for (int k = 0; k < cnt && k < 256; ++k) {
+        a *= 0.8;
+        tdev = fmax(tdev, fabs(tr[k].r_sum - a) / a);
+        if (tr[k].phase != 1 || tr[k].index != k + 1 || tr[k].edge_pushes != 13 * (int64_t)(k + 1)) tdev = 1.0;
+    }
     ppr_graph_destroy(g);
-    printf("fp64 l1 vs printed %.3e, mixed vs fp64 %.3e, sweeps %d\n", err, diff, s.sweeps);
-    /* the printed values carry 8 decimals */
-    return (err <= 5 * 5e-9 + 1e-12 && diff <= 2 * (1e-10 + 1e-12) + 1e-12) ? 0 : 1;
+    printf("fp64 l1 vs printed %.3e, mixed vs fp64 %.3e, sweeps %d, trace points %d (rel dev %.1e)\n", err,
+           diff, s.sweeps, (int)cnt, tdev);
+    /* the printed values carry 8 decimals; ceil(ln 1e-12 / ln 0.8) = 124 sweeps */
+    return (err <= 5 * 5e-9 + 1e-12 && diff <= 2 * (1e-10 + 1e-12) + 1e-12 && cnt == 124 && tdev <= 1e-12) ? 0 : 1;
 }

@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
 def test_options_default():
     o = P.options()
     assert o.precision == P.FP64 and o.switch_rule == P.SWITCH_EDGES
-    assert o.switch_param == 8.0 and o.max_sweeps == 4096 and o.refresh_factor == 1e4
+    assert o.switch_param == 32.0 and o.max_sweeps == 4096 and o.refresh_factor == 1e4
 
 
 def _create(row_ptr, col, n, flags=0):

@@ -177,7 +177,7 @@ def test_query_small_graphs_closed_forms(name):
         pi, st = G.query(s, ALPHA, lam, P.FP64)
         err = np.abs(pi - x).sum()
         assert err <= lam + (tol or 0.0) * g.n
-        pio, _, sto = _sync(g, s, lam, P.SWITCH_EDGES, 8.0)
+        pio, _, sto = _sync(g, s, lam, P.SWITCH_EDGES, P.options().switch_param)
         np.testing.assert_allclose(pi, pio, rtol=RTOL, atol=ATOL)
 
 
@@ -185,7 +185,7 @@ def test_hub_graph_query(hub):
     G = P.Graph.from_synth(hub)
     for s in (0, 1, 12345):
         pi, st = G.query(s, ALPHA, 1e-9, P.FP64, certify=1)
-        pio, _, sto = _sync(hub, s, 1e-9, P.SWITCH_EDGES, 8.0)
+        pio, _, sto = _sync(hub, s, 1e-9, P.SWITCH_EDGES, P.options().switch_param)
         np.testing.assert_allclose(pi, pio, rtol=RTOL, atol=ATOL)
         assert st["cert_l1"] <= 1e-9 * (1 + 1e-9)
 

@@ -51,7 +51,8 @@ def srcs(c2):
 @pytest.fixture(scope="module")
 def sync0(c2, srcs):
     print("[gpu] oracle level-synchronous schedule, source 0", flush=True)
-    pi, r, st, trace, levels = oracle.powerpush_sync(c2, srcs[0], ALPHA, LAM, oracle.SWITCH_EDGES, 8.0)
+    pi, r, st, trace, levels = oracle.powerpush_sync(c2, srcs[0], ALPHA, LAM, oracle.SWITCH_EDGES,
+                                                     P.options().switch_param)
     return pi, st
 
 

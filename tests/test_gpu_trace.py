@@ -60,7 +60,8 @@ def test_powerpush_trace_matches_oracle(c1, lam):
     for s in [int(x) for x in synth.sources(c1.n, 3)]:
         print(f"[gpu] trace powerpush c1 s={s} lam={lam}", flush=True)
         pi, tr, st = G.query_trace(s, ALPHA, lam)
-        pio, ro, sto, otr, levels = oracle.powerpush_sync(c1, s, ALPHA, lam, P.SWITCH_EDGES, 8.0, trace_cap=512)
+        pio, ro, sto, otr, levels = oracle.powerpush_sync(c1, s, ALPHA, lam, P.SWITCH_EDGES, P.options().switch_param,
+                                                            trace_cap=512)
         loc, glo = _check_common(tr, st)
         assert st["local_levels"] == sto["local_levels"] and st["sweeps"] == sto["sweeps"]
         _check_local(loc, levels, otr[0])
@@ -110,7 +111,7 @@ def test_epoch_trace_matches_oracle(c1):
     G = P.Graph.from_synth(c1)
     s = int(synth.sources(c1.n, 3)[2])
     pi, tr, st = G.query_trace(s, ALPHA, 1e-8, global_rule=P.GLOBAL_EPOCHS)
-    pio, ro, sto, otr, levels = oracle.powerpush_sync(c1, s, ALPHA, 1e-8, P.SWITCH_EDGES, 8.0, trace_cap=1024,
+    pio, ro, sto, otr, levels = oracle.powerpush_sync(c1, s, ALPHA, 1e-8, P.SWITCH_EDGES, P.options().switch_param, trace_cap=1024,
                                                       global_rule=oracle.GLOBAL_EPOCHS)
     loc, glo = _check_common(tr, st)
     assert st["sweeps"] == sto["sweeps"] and st["edge_pushes"] == sto["edge_pushes"]
