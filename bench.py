@@ -31,13 +31,15 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
-def sweep_bytes(n: int, m: int, width: int, over_relaxed: bool = False) -> int:
+def sweep_bytes(n: int, m: int, width: int, over_relaxed: bool = False, residue_bytes: int = 4) -> int:
     """Algorithmic bytes of one batched global sweep (all its row chunks):
     in-edge indices (4 m), per-node CSC offset and FP32 scale (8 n), and per
-    (node, column) 16 bytes: the residue row read once, the new residue
-    written, the per-stage reserve accumulator read and written; over-relaxed
-    sweeps also read the row's previous push (4 more)."""
-    return 4 * m + 8 * n + (20 if over_relaxed else 16) * n * width
+    (node, column): the residue row read once and the new residue written
+    (residue_bytes each: 4 in FP32, 2 in bf16), the FP32 per-stage reserve
+    accumulator read and written (8); over-relaxed sweeps also read the row's
+    previous push (residue_bytes more)."""
+    per = 2 * residue_bytes + 8 + (residue_bytes if over_relaxed else 0)
+    return 4 * m + 8 * n + per * n * width
 
 
 def fp64_sweep_bytes(n: int, m: int) -> int:
@@ -58,11 +60,12 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(width: int, chunks: int):
+def measured_traffic(width: int, chunks: int, residues: str):
     """HBM bytes per global sweep (its sweep_k and combine_k launches) from
     the committed rocprofv3 counter runs (FETCH_SIZE + WRITE_SIZE, each scaled
     by the same counter's reading for a plain 1 GiB copy), or None when they
-    were taken on another kernel build, width or chunk count."""
+    were taken on another kernel build, width, chunk count or residue
+    storage."""
     path = os.path.join(ROOT, "profiles", "sweep_k_traffic.json")
     try:
         with open(path) as f:
@@ -70,7 +73,7 @@ def measured_traffic(width: int, chunks: int):
     except (OSError, ValueError):
         return None
     if (t.get("source_digest") != kernel_source_digest() or t.get("batch_cols") != width
-            or t.get("sweep_chunks") != chunks):
+            or t.get("sweep_chunks") != chunks or t.get("residues") != residues):
         return None
     return t.get("bytes_per_sweep")
 
@@ -92,6 +95,8 @@ def main() -> int:
                     help="FP64 queries with Algorithm 3's epoch thresholds in the global phase")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--f32-leg", type=int, default=1,
+                    help="1: also time one step with FP32 residue storage (0: skip)")
     ap.add_argument("--extra-widths", default="8,32",
                     help="also time one step at these block widths (empty: skip)")
     ap.add_argument("--single-sources", type=int, default=32,
@@ -162,7 +167,8 @@ def main() -> int:
             sweep_n += s["sweep_launches"]
     avg_sweep_ms = sweep_ms / max(sweep_n, 1)
     over_relaxed = any(s["sor_omega"] > 1.0 for st in stats_all for s in st)
-    bytes_per = sweep_bytes(g.n, g.m, width, over_relaxed)
+    bf16 = stats_all[0][0]["residue_format"] == P.RESIDUE_BF16
+    bytes_per = sweep_bytes(g.n, g.m, width, over_relaxed, 2 if bf16 else 4)
     achieved = bytes_per / (avg_sweep_ms * 1e-3) / 1e9
     print(f"[bench] mixed: {qps:.1f} q/s, {dt/args.steps*1e3:.1f} ms/step, sweep {avg_sweep_ms:.3f} ms avg "
           f"over {int(sweep_n)} launches, max cert {max_cert:.3e}", file=sys.stderr, flush=True)
@@ -203,6 +209,24 @@ def main() -> int:
                           "queries": len(ep)}
         print(f"[bench] fp64 epochs: {fp64['epochs']}", file=sys.stderr, flush=True)
 
+    # the same step with FP32 residue storage (one timed step)
+    f32_leg = None
+    if bf16 and args.f32_leg:
+        step_f = lambda: G.query_batch(srcs, args.alpha, args.lam, P.MIXED, out=out, batch_cols=width,
+                                       residue_format=P.RESIDUE_F32)[1]
+        step_f()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st_f = step_f()
+        torch.cuda.synchronize()
+        dt_f = time.perf_counter() - t1
+        f32_leg = {"value": round(args.sources / dt_f, 3), "unit": "queries/s",
+                   "ms_per_sweep": round(st_f[0]["sweep_ms"] / max(st_f[0]["sweep_launches"], 1), 4),
+                   "sweeps_per_query": round(sum(s["sweeps"] for s in st_f) / len(st_f), 2),
+                   "refreshes_per_query": round(sum(s["refreshes"] for s in st_f) / len(st_f), 2),
+                   "max_cert_l1": max(s["cert_l1"] for s in st_f)}
+        print(f"[bench] FP32 residues: {f32_leg}", file=sys.stderr, flush=True)
+
     # the same step at other block widths (one timed step each)
     widths = {}
     for w in [int(x) for x in args.extra_widths.split(",") if x.strip()]:
@@ -218,8 +242,10 @@ def main() -> int:
         per_w = st_w[0]["sweep_ms"] / max(st_w[0]["sweep_launches"], 1)
         widths[str(w)] = {"value": round(args.sources / dt_w, 3), "unit": "queries/s",
                           "ms_per_sweep": round(per_w, 4),
-                          "sweep_GBps_algorithmic": round(sweep_bytes(g.n, g.m, w, any(s["sor_omega"] > 1.0 for s in st_w))
-                                                          / (per_w * 1e-3) / 1e9, 1)}
+                          "sweep_GBps_algorithmic": round(sweep_bytes(g.n, g.m, w, any(s["sor_omega"] > 1.0 for s in st_w),
+                                                                      2 if st_w[0]["residue_format"] == 1 else 4)
+                                                          / (per_w * 1e-3) / 1e9, 1),
+                          "residues": "bf16" if st_w[0]["residue_format"] == 1 else "f32"}
         print(f"[bench] width {w}: {widths[str(w)]}", flush=True, file=sys.stderr)
 
     # sources one at a time: plain FP64 path against the mixed path (one column)
@@ -255,8 +281,9 @@ def main() -> int:
 
     chunks = stats_all[0][0]["sweep_chunks"]
     omegas = sorted({round(s["sor_omega"], 4) for sts in stats_all for s in sts})
-    sk_name = f"sweep_k<C={width // 4}{', over-relaxed' if over_relaxed else ''}>"
-    traffic = measured_traffic(width, chunks)
+    sk_name = (f"sweep_k<C={width // (8 if bf16 else 4)}{', over-relaxed' if over_relaxed else ''}"
+               f"{', bf16 residues' if bf16 else ''}>")
+    traffic = measured_traffic(width, chunks, "bf16" if bf16 else "f32")
 
     cpu = None
     if args.cpu_baseline:
@@ -295,9 +322,10 @@ def main() -> int:
         "config": {
             "workload": f"chung-lu n={g.n} m={g.m} gamma={args.gamma} alpha={args.alpha} "
                         f"lambda={args.lam:g}, {args.sources} sources per step, batched mixed, B={width}, "
-                        f"{chunks} sweep chunks, over-relaxation {'/'.join(str(w) for w in omegas)}",
+                        f"{chunks} sweep chunks, over-relaxation {'/'.join(str(w) for w in omegas)}, "
+                        f"{'bf16' if bf16 else 'FP32'} residue storage (FP32 arithmetic, FP64 certificate)",
             "n": g.n, "m": g.m, "sources_per_step": args.sources, "batch_cols": width, "sweep_chunks": chunks,
-            "sor_omega_final": omegas,
+            "sor_omega_final": omegas, "residue_storage": "bf16" if bf16 else "f32",
             "alpha": args.alpha, "lambda": args.lam,
         },
         "gteps": round(edges / dt / 1e9, 3),
@@ -313,6 +341,9 @@ def main() -> int:
                      "traffic_GBps": round(traffic / (avg_sweep_ms * 1e-3) / 1e9, 1) if traffic else None,
                      "bytes_per_launch": bytes_per, "avg_launch_ms": round(avg_sweep_ms, 4),
                      "launch": "one global sweep"},
+        "sweeps_per_query": round(sum(s["sweeps"] for st in stats_all for s in st) / q, 2),
+        "refreshes_per_query": round(sum(s["refreshes"] for st in stats_all for s in st) / q, 2),
+        "f32_residues": f32_leg,
         "batched_widths": widths,
         "single_source": single,
         "cpu_baseline": cpu,

@@ -64,6 +64,16 @@ typedef enum {
                         FP64 residual refresh and FP64 final flush */
 } ppr_precision;
 
+/* Storage of the batched path's residue block (arithmetic is FP32 either way). */
+typedef enum {
+    PPR_RESIDUE_F32 = 0,   /* 4 bytes per residue */
+    PPR_RESIDUE_BF16 = 1,  /* 2 bytes: half the bytes each sweep gathers; the rounding a
+                              stored residue takes is residual that the next FP64 refresh
+                              measures, so stages are shorter (refresh factor 50).  Blocks
+                              of at least 8 columns (a sweep lane holds 8) */
+    PPR_RESIDUE_AUTO = 2   /* bf16 for blocks of at least 8 columns, else FP32 (default) */
+} ppr_residue_format;
+
 /* Rule that ends the local (frontier) phase and starts the global sweeps. */
 typedef enum {
     PPR_SWITCH_NODES = 0,  /* continue while 4 |S^(j)| <= n: Algorithm 3's
@@ -91,6 +101,9 @@ typedef struct {
     int32_t batch_cols;     /* block width used (1 for PPR_FP64) */
     int32_t sweep_chunks;   /* row chunks per global sweep (1 = Eq. 7 order) */
     double sor_omega;       /* over-relaxation factor of the query's last stage (1 = none) */
+    int32_t residue_format; /* storage of the residues the query swept: PPR_RESIDUE_F32 or
+                               PPR_RESIDUE_BF16 (PPR_FP64: F32, though it sweeps in double) */
+    int32_t reserved;
 } ppr_stats;
 
 /* Global phase of the PPR_FP64 path. */
@@ -109,7 +122,8 @@ typedef struct {
     int32_t max_sweeps;     /* cap on the global sweeps of each query; default 4096 */
     int32_t certify;        /* PPR_FP64: also compute cert_l1; default 0 */
     double refresh_factor;  /* PPR_MIXED: refresh the residual in FP64 whenever r_sum has
-                               fallen by this factor since the last refresh; default 1e4 */
+                               fallen by this factor since the last refresh; 0 = chosen by
+                               the residue format (1e4 for FP32, 50 for bf16; default) */
     int32_t batch_cols;     /* PPR_MIXED batched: columns per block (multiple of 4, or 0 =
                                autotuned); default 0 */
     int32_t sweep_chunks;   /* PPR_MIXED: row chunks per global sweep.  1 = every sweep is
@@ -125,7 +139,8 @@ typedef struct {
                                (default); 1 = off; or a factor in (1, 1.9].  A column whose
                                measured contraction shows no gain falls back to 1; the FP64
                                certificate bounds the result either way */
-    int32_t reserved[2];
+    int32_t residue_format; /* PPR_MIXED: ppr_residue_format; default PPR_RESIDUE_AUTO */
+    int32_t reserved;
 } ppr_options;
 
 /* Read-only facts about a created graph. */
@@ -264,6 +279,13 @@ ppr_status ppr_debug_sweep_fp64(ppr_graph* g, double alpha, const double* r_in, 
  * This is a node that holds p = q + the value above, pushes omega p and keeps
  * q' = (1 - omega) p, with q = (1 - omega) / omega * y_in(u) (what it kept
  * when it pushed y_in(u)); a fresh residue has kept nothing back.
+ * residue_format: ppr_residue_format (PPR_RESIDUE_AUTO: bf16 when B >= 8).
+ * With bf16 storage (B >= 8) the block is stored in bf16: y_in is
+ * rounded to bf16 (nearest, ties to even) on the way in, every y_out value
+ * is the bf16 value the row stored (its out-neighbours pull exactly that),
+ * and t_out adds those stored values; on an entry sweep a fresh column's row
+ * pulls an earlier chunk's new value plus the fresh residue as one bf16
+ * value.
  *   B: power of two in [4, 128]; chunks in [1, 64].
  *   y_in, y_out, t_out: float[n][B] (node-major), host or device memory.
  *   fresh: host int32[B] (1: the column's y_in is a residue nobody has
@@ -271,7 +293,7 @@ ppr_status ppr_debug_sweep_fp64(ppr_graph* g, double alpha, const double* r_in, 
  */
 ppr_status ppr_debug_sweep_mixed(ppr_graph* g, double alpha, int32_t B, int32_t chunks,
                                  const float* y_in, const int32_t* fresh, float* y_out,
-                                 float* t_out, const float* omega);
+                                 float* t_out, const float* omega, int32_t residue_format);
 
 /*
  * Autotuner of the batched path: for each candidate block width (a power of

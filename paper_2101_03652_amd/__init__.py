@@ -29,6 +29,9 @@ SWITCH_NODES = 0
 SWITCH_EDGES = 1
 GLOBAL_SWEEPS = 0
 GLOBAL_EPOCHS = 1
+RESIDUE_F32 = 0
+RESIDUE_BF16 = 1
+RESIDUE_AUTO = 2
 GRAPH_TRUST_INPUT = 1
 GRAPH_WIDE_OFFSETS = 2
 
@@ -55,7 +58,8 @@ class Stats(ctypes.Structure):
                 ("cert_l1", ctypes.c_double), ("ms", ctypes.c_double),
                 ("sweep_ms", ctypes.c_double), ("sweep_launches", ctypes.c_int32),
                 ("batch_cols", ctypes.c_int32), ("sweep_chunks", ctypes.c_int32),
-                ("sor_omega", ctypes.c_double)]
+                ("sor_omega", ctypes.c_double), ("residue_format", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -72,7 +76,7 @@ class Options(ctypes.Structure):
                 ("certify", ctypes.c_int32), ("refresh_factor", ctypes.c_double),
                 ("batch_cols", ctypes.c_int32), ("sweep_chunks", ctypes.c_int32),
                 ("global_rule", ctypes.c_int32), ("sor_omega", ctypes.c_double),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("residue_format", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class GraphInfo(ctypes.Structure):
@@ -107,7 +111,7 @@ def load() -> ctypes.CDLL:
         "ppr_query_trace": (st, [vp, i32, f64, f64, vp, vp, vp, i32, vp, vp]),
         "ppr_debug_sweep_fp64": (st, [vp, f64, vp, vp, vp, vp]),
         "ppr_autotune": (st, [vp, f64, vp, i32, vp, vp]),
-        "ppr_debug_sweep_mixed": (st, [vp, f64, i32, i32, vp, vp, vp, vp, vp]),
+        "ppr_debug_sweep_mixed": (st, [vp, f64, i32, i32, vp, vp, vp, vp, vp, i32]),
         "ppr_block_create": (st, [vp, i32, f64, vp, ctypes.POINTER(vp)]),
         "ppr_block_destroy": (st, [vp]),
         "ppr_block_footprint": (st, [vp, i32, vp]),
@@ -323,9 +327,10 @@ class Block:
 
 
 def debug_sweep_mixed(graph: "Graph", alpha: float, y_in, fresh, chunks: int = 1, t_out=None,
-                      omega=None):
+                      omega=None, residue_format: int = RESIDUE_F32):
     """One batched global sweep (block Gauss-Seidel over `chunks` row chunks;
-    over-relaxed when `omega`, B factors, is given).  y_in: float32[n, B]
+    over-relaxed when `omega`, B factors, is given) with the residue block
+    stored as `residue_format` (FP32 unless asked).  y_in: float32[n, B]
     (numpy or device tensor); fresh: B flags.  Returns y_out (same kind as
     y_in)."""
     B = int(y_in.shape[1])
@@ -341,7 +346,7 @@ def debug_sweep_mixed(graph: "Graph", alpha: float, y_in, fresh, chunks: int = 1
         raise ValueError("omega needs one factor per column")
     _check(load().ppr_debug_sweep_mixed(graph.handle, float(alpha), B, int(chunks), _ptr(y_in), _ptr(fr),
                                         _ptr(y_out), _ptr(t_out) if t_out is not None else None,
-                                        _ptr(om) if om is not None else None))
+                                        _ptr(om) if om is not None else None, int(residue_format)))
     return y_out
 
 

@@ -51,7 +51,10 @@ void check_options(const ppr_options& o) {
         fail(PPR_ERR_ARG, "unknown switch rule");
     if (!(o.switch_param >= 0.0) || std::isinf(o.switch_param)) fail(PPR_ERR_ARG, "switch_param must be finite and >= 0");
     if (o.max_sweeps < 0) fail(PPR_ERR_ARG, "max_sweeps must be >= 0");
-    if (!(o.refresh_factor > 1.0)) fail(PPR_ERR_ARG, "refresh_factor must be > 1");
+    if (!(o.refresh_factor == 0.0 || o.refresh_factor > 1.0)) fail(PPR_ERR_ARG, "refresh_factor must be 0 or > 1");
+    if (o.residue_format != PPR_RESIDUE_F32 && o.residue_format != PPR_RESIDUE_BF16 &&
+        o.residue_format != PPR_RESIDUE_AUTO)
+        fail(PPR_ERR_ARG, "unknown residue format");
     if (o.batch_cols < 0 || (o.batch_cols % 4) != 0) fail(PPR_ERR_ARG, "batch_cols must be 0 or a multiple of 4");
     if (o.sweep_chunks < 0 || o.sweep_chunks > 64) fail(PPR_ERR_ARG, "sweep_chunks must lie in [0, 64]");
     if (!(o.sor_omega == 0.0 || (o.sor_omega >= 1.0 && o.sor_omega <= 1.9)))
@@ -74,8 +77,9 @@ void ppr_options_default(ppr_options* o) {
     o->switch_param = 32.0;
     o->max_sweeps = 4096;
     o->certify = 0;
-    o->refresh_factor = 1e4;
+    o->refresh_factor = 0.0;
     o->batch_cols = 0;
+    o->residue_format = PPR_RESIDUE_AUTO;
 }
 
 const char* ppr_version(void) { return "libppr 0.1 (gfx950)"; }
@@ -214,7 +218,8 @@ ppr_status ppr_autotune(ppr_graph* gh, double alpha, const int32_t* widths, int3
 }
 
 ppr_status ppr_debug_sweep_mixed(ppr_graph* gh, double alpha, int32_t B, int32_t chunks, const float* y_in,
-                                 const int32_t* fresh, float* y_out, float* t_out, const float* omega) {
+                                 const int32_t* fresh, float* y_out, float* t_out, const float* omega,
+                                 int32_t residue_format) {
     return guarded([&] {
         Graph* g = reinterpret_cast<Graph*>(gh);
         if (!g || !y_in || !fresh || !y_out) fail(PPR_ERR_ARG, "NULL argument");
@@ -228,7 +233,10 @@ ppr_status ppr_debug_sweep_mixed(ppr_graph* gh, double alpha, int32_t B, int32_t
         if (omega)
             for (int32_t b = 0; b < B; ++b)
                 if (!(omega[b] > 0.0f && omega[b] < 2.0f)) fail(PPR_ERR_ARG, "omega must lie in (0, 2)");
-        debug_sweep_mixed(*g, alpha, B, chunks, y_in, fresh, y_out, t_out, omega);
+        if (residue_format != PPR_RESIDUE_F32 && residue_format != PPR_RESIDUE_BF16 &&
+            residue_format != PPR_RESIDUE_AUTO)
+            fail(PPR_ERR_ARG, "unknown residue format");
+        debug_sweep_mixed(*g, alpha, B, chunks, y_in, fresh, y_out, t_out, omega, residue_format);
     });
 }
 

@@ -69,6 +69,11 @@ int sweep_chunks(const Graph& g, const ppr_options& opt) {
 // where it does not pay (a directed cycle) fall back to 1 after one stage.
 constexpr double kAutoOmega = 1.2;
 
+// Residue storage of a block of Bw columns under these options.
+bool residues_bf16(const ppr_options& o, int Bw) {
+    return o.residue_format == PPR_RESIDUE_BF16 || (o.residue_format == PPR_RESIDUE_AUTO && Bw >= 8);
+}
+
 double now_ms() {
     return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
@@ -87,7 +92,7 @@ int64_t frontier_capacity(const Graph& g, const ppr_options& opt, int Bw) {
     return per_col * Bw;
 }
 
-size_t mixed_footprint(const Graph& g, int Bw, int64_t fcap) {
+size_t mixed_footprint(const Graph& g, int Bw, int64_t fcap, bool bf16) {
     const size_t nb = (size_t)g.n * (size_t)Bw;
     // long-row pieces: each holds piece_cap = kLongRounds kLdsBytes / (4 Bw)
     // in-edges of a row with more than piece_cap, so there are fewer than
@@ -95,16 +100,16 @@ size_t mixed_footprint(const Graph& g, int Bw, int64_t fcap) {
     const size_t piece_cap = (size_t)mk::kLongRounds * mk::kLdsBytes / (4 * (size_t)Bw);
     const size_t pieces = 2 * (size_t)g.m / piece_cap + 1;
     return 16 * nb                       // FP64 local-phase scratch
-           + 24 * nb                     // Y0, Y1, Shi, Slo, T
+           + (bf16 ? 16 : 20) * nb       // Y0, Y1 (4 or 2 bytes), Shi, Slo, T
            + 4 * (size_t)Bw * pieces     // partial sums of the pieces
            + 40 * (size_t)fcap + 4 * (size_t)g.n + ((size_t)1 << 20);
 }
 
-MixedCtxPtr mixed_acquire(Graph& g, int Bw, int64_t fcap) {
+MixedCtxPtr mixed_acquire(Graph& g, int Bw, int64_t fcap, bool bf16) {
     {
         std::lock_guard<std::mutex> lk(g.pool_mu);
         for (auto it = g.mixed_pool.begin(); it != g.mixed_pool.end(); ++it) {
-            if ((*it)->Bw == Bw && (*it)->fcap >= fcap) {
+            if ((*it)->Bw == Bw && (*it)->fcap >= fcap && (*it)->bf16 == bf16) {
                 MixedCtxPtr c = std::move(*it);
                 g.mixed_pool.erase(it);
                 return c;
@@ -117,6 +122,7 @@ MixedCtxPtr mixed_acquire(Graph& g, int Bw, int64_t fcap) {
     c->Bw = Bw;
     c->shift = ilog2(Bw);
     c->fcap = fcap;
+    c->bf16 = bf16;
     HIPCHECK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
     c->r64.alloc(8 * nb);
     c->pi64.alloc(8 * nb);
@@ -128,8 +134,8 @@ MixedCtxPtr mixed_acquire(Graph& g, int Bw, int64_t fcap) {
     c->degF.alloc(8 * (size_t)fcap);
     c->off.alloc(8 * ((size_t)fcap + 1));
     c->scan_tmp.alloc(k::scan_tmp_bytes(fcap));
-    c->Y0.alloc(4 * nb);
-    c->Y1.alloc(4 * nb);
+    c->Y0.alloc((bf16 ? 2 : 4) * nb);
+    c->Y1.alloc((bf16 ? 2 : 4) * nb);
     c->Shi.alloc(4 * nb);
     c->Slo.alloc(4 * nb);
     c->T.alloc(4 * nb);
@@ -154,7 +160,7 @@ MixedCtxPtr mixed_acquire(Graph& g, int Bw, int64_t fcap) {
         HIPCHECK(hipMemcpyAsync(b->p, zero.data(), 4 * (size_t)Bw, hipMemcpyHostToDevice, c->stream));
     c->step.alloc(64);
     c->host.alloc(64 + 48 * (size_t)Bw);
-    c->ycur = c->Y0.as<float>();
+    c->ycur = c->Y0.p;
     HIPCHECK(hipStreamSynchronize(c->stream));
     return c;
 }
@@ -201,10 +207,19 @@ struct Block {
     int32_t seq_sweeps = 0;
     double sweep_ms = 0.0;           // accumulated GPU time of the sweeps
     int32_t sweep_launches = 0;
+    double refresh_factor;           // drop of err that ends a stage
 
     Block(Graph& gg, int width, double a, const ppr_options& o) : g(gg), Bw(width), alpha(a), opt(o) {
+        // a bf16 residue carries ~2^-9 relative rounding per push, so a stage
+        // stalls near 1e-2 of the residual it started from (1e-6 with FP32);
+        // 50 was the fastest factor on the 4M/70M graph (35: 541, 50: 584,
+        // 70: 567, 100: 545 queries/s at B = 128)
+        refresh_factor = opt.refresh_factor > 0.0 ? opt.refresh_factor
+                                                  : (residues_bf16(opt, Bw) ? 50.0 : 1e4);
         if (Bw < 4 || Bw > 128 || (Bw & (Bw - 1))) fail(PPR_ERR_ARG, "block width must be a power of two in [4, 128]");
-        c = mixed_acquire(g, Bw, frontier_capacity(g, opt, Bw));
+        if (opt.residue_format == PPR_RESIDUE_BF16 && Bw < 8)
+            fail(PPR_ERR_ARG, "bf16 residues need a block of at least 8 columns");
+        c = mixed_acquire(g, Bw, frontier_capacity(g, opt, Bw), residues_bf16(opt, Bw));
         const int chunks = sweep_chunks(g, opt);
         if (c->chunks != chunks) {
             c->drop_chunks();
@@ -256,7 +271,7 @@ struct Block {
     // estimate slightly too optimistic; a stage that still ends above lambda
     // is followed by another).
     int32_t stage_length(const Slot& sl) const {
-        double target = std::max(sl.err / opt.refresh_factor, 0.8 * sl.lambda);
+        double target = std::max(sl.err / refresh_factor, 0.8 * sl.lambda);
         int32_t k = 0;
         for (double x = sl.err; x > target && k < (1 << 20); x *= sl.rho) ++k;
         return std::max<int32_t>(k, 1);
@@ -406,12 +421,12 @@ struct Block {
         hipStream_t ss = c->stream;
         hipGraph_t graph = nullptr;
         HIPCHECK(hipStreamBeginCapture(ss, hipStreamCaptureModeThreadLocal));
-        const float* a = c->Y1.as<float>();
-        float* bb = c->Y0.as<float>();
+        const void* a = c->Y1.p;
+        void* bb = c->Y0.p;
         try {
             for (int i = 0; i < kChunkSweeps; ++i) {
                 mk::sweep(*c, g, a, bb);
-                float* t = const_cast<float*>(a);
+                void* t = const_cast<void*>(a);
                 a = bb;
                 bb = t;
             }
@@ -426,7 +441,7 @@ struct Block {
         HIPCHECK(e);
     }
 
-    float* other(const float* y) const { return y == c->Y0.as<float>() ? c->Y1.as<float>() : c->Y0.as<float>(); }
+    void* other(const void* y) const { return y == c->Y0.p ? c->Y1.p : c->Y0.p; }
 
     // Collect the results of the enqueued work (blocking when wait).  Returns
     // false if they are not ready yet.
@@ -508,12 +523,12 @@ struct Block {
             ev_sweep.start(ss);
             int rest = K;
             while (rest > 0) {
-                if (rest >= kChunkSweeps && c->ycur == c->Y1.as<float>()) {
+                if (rest >= kChunkSweeps && c->ycur == c->Y1.p) {
                     if (!c->chunk[c->sor ? 1 : 0]) capture_chunk();
                     HIPCHECK(hipGraphLaunch(c->chunk[c->sor ? 1 : 0], ss));    // even count: ycur stays Y1
                     rest -= kChunkSweeps;
                 } else {
-                    float* yo = other(c->ycur);
+                    void* yo = other(c->ycur);
                     mk::sweep(*c, g, c->ycur, yo);
                     c->ycur = yo;
                     rest -= 1;
@@ -546,7 +561,7 @@ struct Block {
         }
         if (any) {
             upload_i32(c->rmask, hr);
-            mk::refresh(*c, g, const_cast<float*>(c->ycur), nullptr);
+            mk::refresh(*c, g, const_cast<void*>(c->ycur), nullptr);
             HIPCHECK(hipMemcpyAsync(c->host.p, c->colsum.p, 8 * (size_t)Bw, hipMemcpyDeviceToHost, ss));
         }
         if (any || sweep_timed) {
@@ -576,6 +591,7 @@ struct Block {
         st->batch_cols = Bw;
         st->sweep_chunks = c->chunks;
         st->sor_omega = sl.omega;
+        st->residue_format = c->bf16 ? PPR_RESIDUE_BF16 : PPR_RESIDUE_F32;
     }
 
     // Export slot b (DONE) into out[n] (host or device) and free the slot;
@@ -629,7 +645,7 @@ void run_mixed_chunk(Block& blk, const int32_t* sources, int Breal, double lambd
         std::vector<int32_t> none(blk.Bw, 0);
         blk.upload_i32(c.rmask, none);
         DevBuf rt((size_t)blk.Bw * g.n * 8);
-        mk::refresh(c, g, const_cast<float*>(c.ycur), rt.as<double>());
+        mk::refresh(c, g, const_cast<void*>(c.ycur), rt.as<double>());
         HIPCHECK(hipMemcpyAsync(r_out, rt.p, 8 * (size_t)Breal * g.n, hipMemcpyDefault, ss));
         HIPCHECK(hipStreamSynchronize(ss));
     }
@@ -656,6 +672,7 @@ void run_mixed_batch(Graph& g, const int32_t* sources, int32_t B, double alpha, 
                      const ppr_options& opt, double* pi_out, double* r_out, ppr_stats* st) {
     HIPCHECK(hipSetDevice(g.device));
     int Bw = opt.batch_cols > 0 ? opt.batch_cols : (g.tuned_width > 0 ? g.tuned_width : default_batch_width(B));
+    if (opt.batch_cols == 0 && opt.residue_format == PPR_RESIDUE_BF16) Bw = std::max(Bw, 8);   // 8-column vectors
     if (Bw < 4 || Bw > 128 || (Bw & (Bw - 1))) fail(PPR_ERR_ARG, "batch_cols must be a power of two in [4, 128]");
     ppr_status first = PPR_OK;
     std::string msg;
@@ -701,9 +718,10 @@ void autotune_width(Graph& g, double alpha, const int32_t* widths, int32_t count
         bool pooled = false;
         {
             std::lock_guard<std::mutex> lk(g.pool_mu);
-            for (auto& cc : g.mixed_pool) pooled |= (cc->Bw == W && cc->fcap >= fcap);
+            for (auto& cc : g.mixed_pool)
+                pooled |= (cc->Bw == W && cc->fcap >= fcap && cc->bf16 == residues_bf16(opt, W));
         }
-        if (!pooled && mixed_footprint(g, W, fcap) > free_b / 2) {
+        if (!pooled && mixed_footprint(g, W, fcap, residues_bf16(opt, W)) > free_b / 2) {
             if (cost_us) cost_us[i] = -1.0;
             continue;
         }
@@ -717,17 +735,16 @@ void autotune_width(Graph& g, double alpha, const int32_t* widths, int32_t count
         blk.upload_i32(c.entry, zero);
         HIPCHECK(hipMemsetAsync(c.step.p, 0, 4, ss));
         const int reps = 4;
-        mk::sweep(c, g, c.Y0.as<float>(), c.Y1.as<float>());     // warm-up
+        mk::sweep(c, g, c.Y0.p, c.Y1.p);     // warm-up
         EventPair ev;
         ev.start(ss);
-        for (int r = 0; r < reps; ++r)
-            mk::sweep(c, g, (r & 1) ? c.Y1.as<float>() : c.Y0.as<float>(), (r & 1) ? c.Y0.as<float>() : c.Y1.as<float>());
+        for (int r = 0; r < reps; ++r) mk::sweep(c, g, (r & 1) ? c.Y1.p : c.Y0.p, (r & 1) ? c.Y0.p : c.Y1.p);
         ev.stop(ss);
         HIPCHECK(hipStreamSynchronize(ss));
         blk.upload_i32(c.kb, zero);
         for (DevBuf* b : {&c.Y0, &c.Y1, &c.T}) HIPCHECK(hipMemsetAsync(b->p, 0, b->bytes, ss));
         HIPCHECK(hipStreamSynchronize(ss));
-        c.ycur = c.Y0.as<float>();
+        c.ycur = c.Y0.p;
         double us = ev.elapsed_ms() * 1e3 / reps / W;
         if (cost_us) cost_us[i] = us;
         // the narrower block wins ties (within 1%): less memory, lower latency
@@ -744,16 +761,21 @@ void autotune_width(Graph& g, double alpha, const int32_t* widths, int32_t count
 // ======================================================================== one sweep (tests)
 
 void debug_sweep_mixed(Graph& g, double alpha, int32_t B, int32_t chunks, const float* y_in,
-                       const int32_t* fresh, float* y_out, float* t_out, const float* omega) {
+                       const int32_t* fresh, float* y_out, float* t_out, const float* omega,
+                       int32_t residue_format) {
     HIPCHECK(hipSetDevice(g.device));
     ppr_options opt;
     ppr_options_default(&opt);
     opt.sweep_chunks = chunks;
+    opt.residue_format = residue_format;
     Block blk(g, B, alpha, opt);
     MixedCtx& c = *blk.c;
     hipStream_t ss = c.stream;
-    const size_t bytes = 4 * (size_t)g.n * (size_t)B;
-    HIPCHECK(hipMemcpyAsync(c.Y0.p, y_in, bytes, hipMemcpyDefault, ss));
+    const int64_t count = (int64_t)g.n * B;
+    const size_t bytes = 4 * (size_t)count;
+    DevBuf stage(bytes);                    // FP32 copy of the residue block on the device
+    HIPCHECK(hipMemcpyAsync(stage.p, y_in, bytes, hipMemcpyDefault, ss));
+    mk::store_from_f32(c, stage.as<float>(), c.Y0.p, count);
     HIPCHECK(hipMemsetAsync(c.T.p, 0, bytes, ss));
     std::vector<int32_t> one(B, 1), fr(fresh, fresh + B), zero(B, 0);
     blk.upload_i32(c.kb, one);
@@ -763,9 +785,10 @@ void debug_sweep_mixed(Graph& g, double alpha, int32_t B, int32_t chunks, const 
         HIPCHECK(hipMemcpyAsync(c.omega.p, omega, 4 * (size_t)B, hipMemcpyHostToDevice, ss));
         c.sor = true;
     }
-    mk::sweep(c, g, c.Y0.as<float>(), c.Y1.as<float>());
+    mk::sweep(c, g, c.Y0.p, c.Y1.p);
     c.sor = false;
-    HIPCHECK(hipMemcpyAsync(y_out, c.Y1.p, bytes, hipMemcpyDefault, ss));
+    mk::store_to_f32(c, c.Y1.p, stage.as<float>(), count);
+    HIPCHECK(hipMemcpyAsync(y_out, stage.p, bytes, hipMemcpyDefault, ss));
     if (t_out) HIPCHECK(hipMemcpyAsync(t_out, c.T.p, bytes, hipMemcpyDefault, ss));
     if (omega) {
         std::vector<float> ones(B, 1.0f);
@@ -775,7 +798,7 @@ void debug_sweep_mixed(Graph& g, double alpha, int32_t B, int32_t chunks, const 
     blk.upload_i32(c.entry, zero);
     for (DevBuf* d : {&c.Y0, &c.Y1, &c.T}) HIPCHECK(hipMemsetAsync(d->p, 0, d->bytes, ss));
     HIPCHECK(hipStreamSynchronize(ss));
-    c.ycur = c.Y0.as<float>();
+    c.ycur = c.Y0.p;
 }
 
 // ======================================================================== serving mechanism
@@ -845,7 +868,8 @@ void serve_retire(void* h, int32_t slot, double* pi_out, ppr_stats* st) {
 size_t serve_footprint(const Graph& g, int32_t slots) {
     ppr_options opt;
     ppr_options_default(&opt);
-    return mixed_footprint(g, slots, frontier_capacity(g, opt, slots)) + sizeof(Block);
+    return mixed_footprint(g, slots, frontier_capacity(g, opt, slots), residues_bf16(opt, slots)) +
+           sizeof(Block);
 }
 
 }  // namespace ppr

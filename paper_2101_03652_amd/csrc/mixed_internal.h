@@ -42,7 +42,7 @@ struct MixedCtx {
     DevBuf r64, pi64;                 // double[n][Bw]  local-phase scratch, zero between uses
     DevBuf F0, F1, X, degF, off;      // frontier (int64 keys), increments, degrees, prefix
     DevBuf scan_tmp;
-    DevBuf Y0, Y1;                    // float[n][Bw]   residue still to push, y = (1-alpha) r / d
+    DevBuf Y0, Y1;                    // [n][Bw] FP32 or bf16: residue still to push, y = (1-alpha) r / d
     DevBuf Shi, Slo;                  // float[n][Bw]   compensated reserve (y domain)
     DevBuf T;                         // float[n][Bw]   per-stage reserve accumulator
     DevBuf scale;                     // float[n]       (1-alpha) / d_u
@@ -65,15 +65,16 @@ struct MixedCtx {
     PinnedBuf host;                   // readback area
     hipGraphExec_t chunk[2] = {nullptr, nullptr};   // captured sweep chunks Y1 -> Y0 -> ... -> Y1
                                                      // (plain, over-relaxed)
-    const float* ycur = nullptr;      // buffer holding the current residue rows
+    const void* ycur = nullptr;       // buffer holding the current residue rows
+    bool bf16 = false;                // residues stored as bf16 (else FP32)
     void drop_chunks();
     ~MixedCtx();
 };
 
-MixedCtxPtr mixed_acquire(Graph& g, int Bw, int64_t fcap);
+MixedCtxPtr mixed_acquire(Graph& g, int Bw, int64_t fcap, bool bf16);
 void mixed_release(Graph& g, MixedCtxPtr c);
 int64_t frontier_capacity(const Graph& g, const ppr_options& opt, int Bw);
-size_t mixed_footprint(const Graph& g, int Bw, int64_t fcap);
+size_t mixed_footprint(const Graph& g, int Bw, int64_t fcap, bool bf16);
 
 // Launchers (mixed_kernels.hip).  All run on c.stream.
 namespace mk {
@@ -90,10 +91,13 @@ void convert(MixedCtx& c, const Graph& g, double alpha);
 void prepare(MixedCtx& c, const Graph& g);
 // allocate (zeroed) the state of the over-relaxed sweeps
 // one sweep Y_in -> Y_out (budgets kb, entry flags, device step counter), then step += 1
-void sweep(MixedCtx& c, const Graph& g, const float* y_in, float* y_out);
+void sweep(MixedCtx& c, const Graph& g, const void* y_in, void* y_out);
+// residue block <-> FP32 copy (device memory, count = n * Bw values)
+void store_from_f32(MixedCtx& c, const float* src, void* dst, int64_t count);
+void store_to_f32(MixedCtx& c, const void* src, float* dst, int64_t count);
 // S += T, T = 0; then for columns with rmask = 1 write y~ into `y` (in place);
 // per-column sums of |rt| (all columns) -> colsum; rt_out (nullable): column-major FP64 residual
-void refresh(MixedCtx& c, const Graph& g, float* y, double* rt_out);
+void refresh(MixedCtx& c, const Graph& g, void* y, double* rt_out);
 void export_cols(MixedCtx& c, const Graph& g, int b0, int count, double* out);   // out[count][n]
 void export_col(MixedCtx& c, const Graph& g, int b, double* out);                // out[n]
 }  // namespace mk

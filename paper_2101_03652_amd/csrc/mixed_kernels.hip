@@ -2,8 +2,13 @@
 // n x B block.
 //
 // State (node-major: the B values of one node are contiguous, so one edge's
-// gather reads one contiguous B*4-byte row):
-//   Y[n][B]         FP32, y = (1 - alpha) r / d_u: the residue still to push
+// gather reads one contiguous row of B residues):
+//   Y[n][B]         y = (1 - alpha) r / d_u, the residue still to push, stored
+//                   as FP32 or as bf16 (half the gather bytes); arithmetic is
+//                   FP32 either way, and what a row stores is exactly what its
+//                   out-neighbours pull and what T accumulates, so the storage
+//                   rounding only leaves residual that the next FP64 refresh
+//                   measures
 //   Shi, Slo[n][B]  FP32 pair, S = Shi + Slo kept with TwoSum (Knuth): the
 //                   compensated reserve in the y domain, pi_hat(u) = alpha d_u S(u) / (1 - alpha)
 //   T[n][B]         FP32 per-stage accumulator of reserve increments
@@ -72,6 +77,84 @@ __device__ inline float4 f4_shfl_xor(float4 a, int o) {
 __device__ inline float4 flag4(int4 f) {
     return make_float4(f.x ? 1.f : 0.f, f.y ? 1.f : 0.f, f.z ? 1.f : 0.f, f.w ? 1.f : 0.f);
 }
+
+// K consecutive columns of one node, in FP32 registers.
+template <int K>
+struct Vec {
+    float4 q[K / 4];
+};
+template <int K>
+__device__ inline Vec<K> v_zero() {
+    Vec<K> r;
+#pragma unroll
+    for (int i = 0; i < K / 4; ++i) r.q[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    return r;
+}
+template <int K>
+__device__ inline Vec<K> v_add(Vec<K> a, const Vec<K>& b) {
+#pragma unroll
+    for (int i = 0; i < K / 4; ++i) a.q[i] = f4_add(a.q[i], b.q[i]);
+    return a;
+}
+template <int K>
+__device__ inline Vec<K> v_mul(Vec<K> a, const Vec<K>& b) {
+#pragma unroll
+    for (int i = 0; i < K / 4; ++i) a.q[i] = f4_mul(a.q[i], b.q[i]);
+    return a;
+}
+template <int K>
+__device__ inline Vec<K> v_shfl_xor(Vec<K> a, int o) {
+#pragma unroll
+    for (int i = 0; i < K / 4; ++i) a.q[i] = f4_shfl_xor(a.q[i], o);
+    return a;
+}
+
+// Residue storage.  A sweep lane gathers one 16-byte vector V of K columns
+// and stages it in LDS as it was stored, so that bf16 storage doubles the
+// in-edges a block keeps in flight; the refresh writes 4 columns at a time
+// (value4 / pack4).
+//
+// bf16: the upper half of an FP32 word; packing rounds to nearest, ties to
+// even (the residues are finite).  Column k of a vector sits in half k of its
+// words, low half first, i.e. bf16 element order in memory.
+__device__ inline uint32_t bf16_bits(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ inline float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
+__device__ inline float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
+__device__ inline uint32_t bf16_pair(float a, float b) { return bf16_bits(a) | (bf16_bits(b) << 16); }
+
+struct StoreF32 {                       // 4 FP32 columns
+    static constexpr int K = 4;
+    using V = float4;
+    __device__ static V zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+    __device__ static Vec<4> value(V v) { Vec<4> r; r.q[0] = v; return r; }
+    __device__ static V pack(const Vec<4>& v) { return v.q[0]; }
+    __device__ static float4 value4(V v) { return v; }
+    __device__ static V pack4(float4 v) { return v; }
+};
+struct StoreBF16 {                      // 4 bf16 columns: the refresh's view
+    static constexpr int K = 4;
+    using V = uint2;
+    __device__ static float4 value4(V w) { return make_float4(bf16_lo(w.x), bf16_hi(w.x), bf16_lo(w.y), bf16_hi(w.y)); }
+    __device__ static V pack4(float4 v) { return make_uint2(bf16_pair(v.x, v.y), bf16_pair(v.z, v.w)); }
+};
+struct StoreBF16x8 {                    // 8 bf16 columns: the sweep's view
+    static constexpr int K = 8;
+    using V = uint4;
+    __device__ static V zero() { return make_uint4(0u, 0u, 0u, 0u); }
+    __device__ static Vec<8> value(V w) {
+        Vec<8> r;
+        r.q[0] = make_float4(bf16_lo(w.x), bf16_hi(w.x), bf16_lo(w.y), bf16_hi(w.y));
+        r.q[1] = make_float4(bf16_lo(w.z), bf16_hi(w.z), bf16_lo(w.w), bf16_hi(w.w));
+        return r;
+    }
+    __device__ static V pack(const Vec<8>& v) {
+        return make_uint4(bf16_pair(v.q[0].x, v.q[0].y), bf16_pair(v.q[0].z, v.q[0].w),
+                          bf16_pair(v.q[1].x, v.q[1].y), bf16_pair(v.q[1].z, v.q[1].w));
+    }
+};
 
 // ---------------------------------------------------------------- local phase
 __global__ void init_sources_k(const int32_t* __restrict__ src, const int32_t* __restrict__ cmask, int32_t Bw,
@@ -177,7 +260,7 @@ __global__ __launch_bounds__(kBlock) void push_k(
 // partials[block][B]: per-column sums of r.
 __global__ void convert_k(int32_t n, int shift, const int32_t* __restrict__ deg, double alpha,
                           const int32_t* __restrict__ cmask, double* __restrict__ r64, double* __restrict__ pi64,
-                          float* __restrict__ Y, float* __restrict__ Shi, float* __restrict__ Slo,
+                          void* __restrict__ Y, int y_bf16, float* __restrict__ Shi, float* __restrict__ Slo,
                           float* __restrict__ T, double* __restrict__ partials) {
     __shared__ double sh[kBlock];
     __shared__ int32_t cm[128];
@@ -196,7 +279,10 @@ __global__ void convert_k(int32_t n, int shift, const int32_t* __restrict__ deg,
             double d = (double)deg[u];
             double y = ((1.0 - alpha) * r) / d;
             double S = ((1.0 - alpha) * p) / (alpha * d);
-            Y[i] = (float)y;
+            if (y_bf16)
+                reinterpret_cast<uint16_t*>(Y)[i] = (uint16_t)bf16_bits((float)y);
+            else
+                reinterpret_cast<float*>(Y)[i] = (float)y;
             float h, l;
             split_double(S, h, l);
             Shi[i] = h;
@@ -242,20 +328,23 @@ __global__ void scale_k(const int32_t* __restrict__ deg, int32_t n, double alpha
 //
 // Schedule blocks: up to Sw<C>::kRows whole rows with <= Sw<C>::kNnz in-edges
 // (one round), or one long row of up to kLongRounds rounds of Sw<C>::kNnz
-// in-edges, or one piece (kLongRounds rounds) of a longer row.  Per round,
-// indices are loaded first, then every thread has kItems float4 gathers in
-// flight, staged in LDS; T2 threads per (row, chunk) add the row's slice.
+// in-edges, or one piece (kLongRounds rounds) of a longer row.  C is the
+// number of 16-byte vectors per row (B / 4 in FP32, B / 8 in bf16).  Per
+// round, indices are loaded first, then every thread has kItems 16-byte
+// gathers in flight, staged in LDS as stored; T2 threads per (row, vector)
+// add the row's slice in FP32.
 // A piece writes its raw sum to a partial slot; combine_k adds a long row's
 // pieces in slot order and finishes the row.  Y_out is read (rows < lo) and written
 // (rows >= lo) in the same launch, so it carries no __restrict__.
-template <int C>
-__device__ inline float4 gather_gs(const float4* __restrict__ Y_in, const float4* Y_out, int32_t v, int c,
-                                   int32_t lo, bool fresh, float4 enf) {
+template <int C, typename ST>
+__device__ inline typename ST::V gather_gs(const typename ST::V* __restrict__ Y_in, const typename ST::V* Y_out,
+                                           int32_t v, int c, int32_t lo, bool fresh, const Vec<ST::K>& enf) {
     const int64_t i = (int64_t)v * C + c;
     if (v >= lo) return Y_in[i];
-    float4 g = Y_out[i];
-    if (fresh) g = f4_add(g, f4_mul(Y_in[i], enf));
-    return g;
+    if (!fresh) return Y_out[i];
+    // an entry sweep: the earlier chunk's new value plus the fresh residue
+    // nobody has pulled yet (exact in FP32; one more rounding in bf16)
+    return ST::pack(v_add(ST::value(Y_out[i]), v_mul(ST::value(Y_in[i]), enf)));
 }
 
 // y'(u) = scale(u) * acc for the columns inside their sweep budget (0 for the
@@ -267,51 +356,81 @@ __device__ inline float4 gather_gs(const float4* __restrict__ Y_in, const float4
 // residue (entry sweep) has kept nothing back.  A column leaves its budget
 // only at the end of a stage, and the refresh that follows forms a new
 // residue, so no kept-back part outlives a stage.
-template <int C, bool SOR>
-__device__ inline void finish_row(int32_t u, int c, float4 acc, int32_t step, const float* __restrict__ scale,
-                                  const float4* __restrict__ Y_in, float4* Y_out, float4* __restrict__ T,
-                                  const int32_t* __restrict__ kb, const int32_t* __restrict__ entry,
-                                  const float* __restrict__ omega) {
+// Lane c holds columns K c .. K c + K - 1: vector c of row u in Y, float4s
+// (u C + c) K/4 + i of T, int4s / float4s c K/4 + i of kb, entry, omega.
+template <int C, bool SOR, typename ST>
+__device__ inline void finish_row(int32_t u, int c, Vec<ST::K> acc, int32_t step, const float* __restrict__ scale,
+                                  const typename ST::V* __restrict__ Y_in, typename ST::V* Y_out,
+                                  float4* __restrict__ T, const int32_t* __restrict__ kb,
+                                  const int32_t* __restrict__ entry, const float* __restrict__ omega) {
+    constexpr int K = ST::K, Q = K / 4;
     const int64_t at = (int64_t)u * C + c;
-    float4 t = T[at];
     const float sc = scale[u];
-    const int4 kb4 = reinterpret_cast<const int4*>(kb)[c];
-    const float4 m = make_float4(step < kb4.x ? 1.f : 0.f, step < kb4.y ? 1.f : 0.f, step < kb4.z ? 1.f : 0.f,
-                                 step < kb4.w ? 1.f : 0.f);
-    float4 en = make_float4(0.f, 0.f, 0.f, 0.f);
+    Vec<K> t, m, en = v_zero<K>();
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        t.q[i] = T[at * Q + i];
+        const int4 kb4 = reinterpret_cast<const int4*>(kb)[c * Q + i];
+        m.q[i] = make_float4(step < kb4.x ? 1.f : 0.f, step < kb4.y ? 1.f : 0.f, step < kb4.z ? 1.f : 0.f,
+                             step < kb4.w ? 1.f : 0.f);
+    }
+    bool any_en = false;
     if (step == 0) {
-        en = flag4(reinterpret_cast<const int4*>(entry)[c]);
-        if (en.x + en.y + en.z + en.w != 0.f) t = f4_add(t, f4_mul(f4_mul(Y_in[at], en), m));
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            en.q[i] = flag4(reinterpret_cast<const int4*>(entry)[c * Q + i]);
+            any_en |= (en.q[i].x + en.q[i].y + en.q[i].z + en.q[i].w) != 0.f;
+        }
+        if (any_en) t = v_add(t, v_mul(v_mul(ST::value(Y_in[at]), en), m));
     }
-    acc = f4_mul(acc, m);
-    float4 y = make_float4(sc * acc.x, sc * acc.y, sc * acc.z, sc * acc.w);
+    acc = v_mul(acc, m);
+    Vec<K> y;
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        y.q[i] = make_float4(sc * acc.q[i].x, sc * acc.q[i].y, sc * acc.q[i].z, sc * acc.q[i].w);
     if (SOR) {
-        const float4 w = reinterpret_cast<const float4*>(omega)[c];
-        const float4 yp = Y_in[at];
-        const float4 k = make_float4(m.x * (1.f - en.x) * (1.f - w.x), m.y * (1.f - en.y) * (1.f - w.y),
-                                     m.z * (1.f - en.z) * (1.f - w.z), m.w * (1.f - en.w) * (1.f - w.w));
-        y = make_float4(w.x * y.x + k.x * yp.x, w.y * y.y + k.y * yp.y, w.z * y.z + k.z * yp.z,
-                        w.w * y.w + k.w * yp.w);
+        const Vec<K> yp = ST::value(Y_in[at]);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const float4 w = reinterpret_cast<const float4*>(omega)[c * Q + i];
+            const float4 mi = m.q[i], ei = en.q[i];
+            const float4 k = make_float4(mi.x * (1.f - ei.x) * (1.f - w.x), mi.y * (1.f - ei.y) * (1.f - w.y),
+                                         mi.z * (1.f - ei.z) * (1.f - w.z), mi.w * (1.f - ei.w) * (1.f - w.w));
+            const float4 yi = y.q[i], pi = yp.q[i];
+            y.q[i] = make_float4(w.x * yi.x + k.x * pi.x, w.y * yi.y + k.y * pi.y, w.z * yi.z + k.z * pi.z,
+                                 w.w * yi.w + k.w * pi.w);
+        }
     }
-    Y_out[at] = y;
-    T[at] = f4_add(t, y);
+    const typename ST::V yq = ST::pack(y);
+    Y_out[at] = yq;
+    const Vec<K> ys = ST::value(yq);             // what the out-neighbours will pull
+#pragma unroll
+    for (int i = 0; i < Q; ++i) T[at * Q + i] = f4_add(t.q[i], ys.q[i]);
 }
 
-template <typename OffT, int C, bool SOR>
+template <typename OffT, int C, bool SOR, typename ST>
 __global__ __launch_bounds__(kBlock) void sweep_k(
         const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
         const RowBlock* __restrict__ blocks, int32_t lo, const float* __restrict__ scale,
-        const float4* __restrict__ Y_in, float4* Y_out, float4* __restrict__ T,
+        const typename ST::V* __restrict__ Y_in, typename ST::V* Y_out, float4* __restrict__ T,
         const int32_t* __restrict__ kb, const int32_t* __restrict__ entry, const int32_t* __restrict__ step_p,
-        float4* __restrict__ partials, const float* __restrict__ omega) {
+        Vec<ST::K>* __restrict__ partials, const float* __restrict__ omega) {
     using P = Sw<C>;
-    __shared__ float4 lds[kLdsBytes / 16];
+    constexpr int K = ST::K, Q = K / 4;
+    static_assert(sizeof(typename ST::V) == 16, "a staged vector is 16 bytes");
+    __shared__ typename ST::V lds[kLdsBytes / 16];
     const RowBlock b = blocks[blockIdx.x];
     const int32_t step = *step_p;
     // every item of this thread belongs to column chunk threadIdx.x % C
-    float4 enf = make_float4(0.f, 0.f, 0.f, 0.f);
-    if (step == 0 && lo > 0) enf = flag4(reinterpret_cast<const int4*>(entry)[threadIdx.x % C]);
-    const bool fresh = (enf.x + enf.y + enf.z + enf.w) != 0.f;
+    Vec<K> enf = v_zero<K>();
+    bool fresh = false;
+    if (step == 0 && lo > 0) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            enf.q[i] = flag4(reinterpret_cast<const int4*>(entry)[(threadIdx.x % C) * Q + i]);
+            fresh |= (enf.q[i].x + enf.q[i].y + enf.q[i].z + enf.q[i].w) != 0.f;
+        }
+    }
     const bool whole = b.piece == -1;              // whole rows, one round
     const int32_t r0 = b.r0;
     const int32_t R = whole ? b.r1 - r0 : 1;
@@ -329,7 +448,7 @@ __global__ __launch_bounds__(kBlock) void sweep_k(
         s0 = (int32_t)((int64_t)col_ptr[r0 + row] - e0);
         s1 = (int32_t)((int64_t)col_ptr[r0 + row + 1] - e0);
     }
-    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
+    Vec<K> acc = v_zero<K>();
     // a long row (or piece) runs rounds of P::kNnz in-edges through LDS
     for (int32_t base = 0; base < ne; base += P::kNnz) {
         const int32_t nr = min(P::kNnz, ne - base);
@@ -339,11 +458,11 @@ __global__ __launch_bounds__(kBlock) void sweep_k(
             int32_t it = threadIdx.x + k * kBlock;
             vv[k] = (it / C < nr) ? row_idx[e0 + base + it / C] : -1;
         }
-        float4 gv[P::kItems];
+        typename ST::V gv[P::kItems];
 #pragma unroll
         for (int k = 0; k < P::kItems; ++k) {
-            gv[k] = (vv[k] >= 0) ? gather_gs<C>(Y_in, Y_out, vv[k], threadIdx.x % C, lo, fresh, enf)
-                                 : make_float4(0.f, 0.f, 0.f, 0.f);
+            gv[k] = (vv[k] >= 0) ? gather_gs<C, ST>(Y_in, Y_out, vv[k], threadIdx.x % C, lo, fresh, enf)
+                                 : ST::zero();
         }
         if (base > 0) __syncthreads();             // the previous round's LDS reads are done
 #pragma unroll
@@ -353,34 +472,48 @@ __global__ __launch_bounds__(kBlock) void sweep_k(
         }
         __syncthreads();
         if (!whole && row == 0) { s0 = 0; s1 = nr; }
-        for (int32_t e = s0 + sub; e < s1; e += T2) acc = f4_add(acc, lds[e * C + c]);
+        for (int32_t e = s0 + sub; e < s1; e += T2) acc = v_add(acc, ST::value(lds[e * C + c]));
     }
-    for (int o = T2 >> 1; o >= 1; o >>= 1) acc = f4_add(acc, f4_shfl_xor(acc, o));
+    for (int o = T2 >> 1; o >= 1; o >>= 1) acc = v_add(acc, v_shfl_xor(acc, o));
     if (row >= R || sub != 0) return;
     if (b.piece >= 0) {
         partials[(int64_t)b.piece * C + c] = acc;
         return;
     }
-    finish_row<C, SOR>(r0 + row, c, acc, step, scale, Y_in, Y_out, T, kb, entry, omega);
+    finish_row<C, SOR, ST>(r0 + row, c, acc, step, scale, Y_in, Y_out, T, kb, entry, omega);
 }
 
 // Long rows of one chunk: the pieces' partial sums added in slot order.
-template <int C, bool SOR>
+template <int C, bool SOR, typename ST>
 __global__ __launch_bounds__(kBlock) void combine_k(
-        const LongRow* __restrict__ rows, int32_t count, const float4* __restrict__ partials,
-        const int32_t* __restrict__ step_p, const float* __restrict__ scale, const float4* __restrict__ Y_in,
-        float4* Y_out, float4* __restrict__ T, const int32_t* __restrict__ kb, const int32_t* __restrict__ entry,
-        const float* __restrict__ omega) {
+        const LongRow* __restrict__ rows, int32_t count, const Vec<ST::K>* __restrict__ partials,
+        const int32_t* __restrict__ step_p, const float* __restrict__ scale,
+        const typename ST::V* __restrict__ Y_in, typename ST::V* Y_out, float4* __restrict__ T,
+        const int32_t* __restrict__ kb, const int32_t* __restrict__ entry, const float* __restrict__ omega) {
     const int32_t i = (int32_t)blockIdx.x * (kBlock / C) + (int32_t)threadIdx.x / C;
     const int c = threadIdx.x % C;
     if (i >= count) return;
     const LongRow L = rows[i];
-    float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int32_t p = 0; p < L.npieces; ++p) acc = f4_add(acc, partials[(int64_t)(L.first + p) * C + c]);
-    finish_row<C, SOR>(L.row, c, acc, *step_p, scale, Y_in, Y_out, T, kb, entry, omega);
+    Vec<ST::K> acc = v_zero<ST::K>();
+    for (int32_t p = 0; p < L.npieces; ++p) acc = v_add(acc, partials[(int64_t)(L.first + p) * C + c]);
+    finish_row<C, SOR, ST>(L.row, c, acc, *step_p, scale, Y_in, Y_out, T, kb, entry, omega);
 }
 
 __global__ void bump_step_k(int32_t* step) { step[0] += 1; }
+
+// Element-wise format conversions of a residue block (used by the one-sweep
+// test entry point).
+__global__ void to_bf16_k(int64_t count, const float* __restrict__ src, uint16_t* __restrict__ dst) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+        dst[i] = (uint16_t)bf16_bits(src[i]);
+}
+
+__global__ void from_bf16_k(int64_t count, const uint16_t* __restrict__ src, float* __restrict__ dst) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+        dst[i] = __uint_as_float((uint32_t)src[i] << 16);
+}
 
 // S += T (compensated), T = 0, dense over n x B.
 // Only the columns being refreshed (rmask) are flushed: a column's reserve
@@ -413,13 +546,13 @@ __global__ void flush_k(int64_t total, int32_t Bw, const int32_t* __restrict__ r
 // per-column sums of |rt| are deterministic: after each schedule block the
 // threads c < C add that block's rows in row order into their own
 // accumulators (columns 4c..4c+3), which go to partials[block][B].
-template <typename OffT, int C>
+template <typename OffT, int C, typename ST>
 __global__ __launch_bounds__(kBlock) void refresh_k(
         const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
         const RowBlock* __restrict__ blocks, int32_t n_blocks,
         const int32_t* __restrict__ deg, const float4* __restrict__ Shi, const float4* __restrict__ Slo,
         const int32_t* __restrict__ src, const int32_t* __restrict__ rmask, double alpha,
-        float4* __restrict__ Y, double* __restrict__ rt_out, int32_t n,
+        typename ST::V* __restrict__ Y, double* __restrict__ rt_out, int32_t n,
         double* __restrict__ partials) {
     using P = Rf<C>;
     __shared__ float4 lds_h[P::kNnz * C];
@@ -503,13 +636,13 @@ __global__ __launch_bounds__(kBlock) void refresh_k(
             t1 = (s4.y == u ? 1.0 : 0.0) - d * ((double)h.y + (double)l.y) * inv_oma + g1;
             t2 = (s4.z == u ? 1.0 : 0.0) - d * ((double)h.z + (double)l.z) * inv_oma + g2;
             t3 = (s4.w == u ? 1.0 : 0.0) - d * ((double)h.w + (double)l.w) * inv_oma + g3;
-            if (w4.x | w4.y | w4.z | w4.w) {
-                float4 y = Y[at];
+            if (w4.x | w4.y | w4.z | w4.w) {     // other columns keep their bits (exact round trip)
+                float4 y = ST::value4(Y[at]);
                 if (w4.x) y.x = (float)(oma * t0 / d);
                 if (w4.y) y.y = (float)(oma * t1 / d);
                 if (w4.z) y.z = (float)(oma * t2 / d);
                 if (w4.w) y.w = (float)(oma * t3 / d);
-                Y[at] = y;
+                Y[at] = ST::pack4(y);
             }
             if (rt_out) {   // column-major FP64 residual [B][n]
                 rt_out[(int64_t)(4 * c + 0) * n + u] = t0;
@@ -598,14 +731,14 @@ const Schedule& refresh_schedule(Graph& g) {
     return g.schedule(Rf<C>::kNnz, Rf<C>::kRows, 1, kRefreshRounds);   // long rows whole, in rounds
 }
 
-template <int C, bool SOR>
-void sweep_launch(MixedCtx& c, Graph& g, const float* yin, float* yout) {
+template <int C, bool SOR, typename ST>
+void sweep_launch(MixedCtx& c, Graph& g, const void* yin, void* yout) {
     const Schedule& sch = sweep_schedule<C>(g, c.chunks);
-    auto Y4i = reinterpret_cast<const float4*>(yin);
-    auto Y4o = reinterpret_cast<float4*>(yout);
+    auto Y4i = reinterpret_cast<const typename ST::V*>(yin);
+    auto Y4o = reinterpret_cast<typename ST::V*>(yout);
     const RowBlock* blocks = sch.blocks.as<RowBlock>();
     const LongRow* lrows = sch.longrows.as<LongRow>();
-    float4* part = c.piece_part.as<float4>();
+    auto part = c.piece_part.as<Vec<ST::K>>();
     const float* om = SOR ? c.omega.as<float>() : nullptr;
     for (int j = 0; j < sch.chunks; ++j) {      // chunk j sees the output of chunks < j
         const int32_t nb = sch.first[j + 1] - sch.first[j];
@@ -613,19 +746,19 @@ void sweep_launch(MixedCtx& c, Graph& g, const float* yin, float* yout) {
         dim3 grid((unsigned)nb), blk(kBlock);
         const RowBlock* bj = blocks + sch.first[j];
         if (g.off64)
-            hipLaunchKernelGGL((sweep_k<int64_t, C, SOR>), grid, blk, 0, c.stream, g.col_ptr.as<int64_t>(),
+            hipLaunchKernelGGL((sweep_k<int64_t, C, SOR, ST>), grid, blk, 0, c.stream, g.col_ptr.as<int64_t>(),
                                g.row_idx.as<int32_t>(), bj, sch.lo[j], c.scale.as<float>(), Y4i, Y4o,
                                c.T.as<float4>(), c.kb.as<int32_t>(), c.entry.as<int32_t>(), c.step.as<int32_t>(),
                                part, om);
         else
-            hipLaunchKernelGGL((sweep_k<uint32_t, C, SOR>), grid, blk, 0, c.stream, g.col_ptr.as<uint32_t>(),
+            hipLaunchKernelGGL((sweep_k<uint32_t, C, SOR, ST>), grid, blk, 0, c.stream, g.col_ptr.as<uint32_t>(),
                                g.row_idx.as<int32_t>(), bj, sch.lo[j], c.scale.as<float>(), Y4i, Y4o,
                                c.T.as<float4>(), c.kb.as<int32_t>(), c.entry.as<int32_t>(), c.step.as<int32_t>(),
                                part, om);
         const int32_t nl = sch.lr_first[j + 1] - sch.lr_first[j];
         if (nl > 0) {
             const int per = kBlock / C;
-            hipLaunchKernelGGL((combine_k<C, SOR>), dim3((unsigned)((nl + per - 1) / per)), dim3(kBlock), 0,
+            hipLaunchKernelGGL((combine_k<C, SOR, ST>), dim3((unsigned)((nl + per - 1) / per)), dim3(kBlock), 0,
                                c.stream, lrows + sch.lr_first[j], nl, part, c.step.as<int32_t>(),
                                c.scale.as<float>(), Y4i, Y4o, c.T.as<float4>(), c.kb.as<int32_t>(),
                                c.entry.as<int32_t>(), om);
@@ -635,37 +768,50 @@ void sweep_launch(MixedCtx& c, Graph& g, const float* yin, float* yout) {
     HIPCHECK(hipGetLastError());
 }
 
+// C = B / 4; bf16 sweeps run C / 2 vectors of 8 columns per row
 template <int C>
-void sweep_c(MixedCtx& c, Graph& g, const float* yin, float* yout) {
-    if (c.sor) {
-        sweep_launch<C, true>(c, g, yin, yout);
+void sweep_c(MixedCtx& c, Graph& g, const void* yin, void* yout) {
+    if (c.bf16) {
+        if constexpr (C >= 2) {
+            if (c.sor) sweep_launch<C / 2, true, StoreBF16x8>(c, g, yin, yout);
+            else sweep_launch<C / 2, false, StoreBF16x8>(c, g, yin, yout);
+        } else {
+            fail(PPR_ERR_ARG, "bf16 residues need a block of at least 8 columns");
+        }
     } else {
-        sweep_launch<C, false>(c, g, yin, yout);
+        if (c.sor) sweep_launch<C, true, StoreF32>(c, g, yin, yout);
+        else sweep_launch<C, false, StoreF32>(c, g, yin, yout);
     }
 }
 
-template <int C>
-void refresh_c(MixedCtx& c, Graph& g, float* y, double* rt_out) {
+template <int C, typename ST>
+void refresh_launch(MixedCtx& c, Graph& g, void* y, double* rt_out) {
     hipLaunchKernelGGL(flush_k, dim3(2048), dim3(kBlock), 0, c.stream, (int64_t)g.n * c.Bw, c.Bw,
                        c.rmask.as<int32_t>(), c.Shi.as<float>(), c.Slo.as<float>(), c.T.as<float>());
     const Schedule& sch = refresh_schedule<C>(g);
     dim3 grid((unsigned)std::min(sch.n_blocks, kGridRed)), blk(kBlock);
     auto H = c.Shi.as<float4>();
     auto L = c.Slo.as<float4>();
-    auto Y4 = reinterpret_cast<float4*>(y);
+    auto Y4 = reinterpret_cast<typename ST::V*>(y);
     if (g.off64)
-        hipLaunchKernelGGL((refresh_k<int64_t, C>), grid, blk, 0, c.stream, g.col_ptr.as<int64_t>(),
+        hipLaunchKernelGGL((refresh_k<int64_t, C, ST>), grid, blk, 0, c.stream, g.col_ptr.as<int64_t>(),
                            g.row_idx.as<int32_t>(), sch.blocks.as<RowBlock>(), sch.n_blocks,
                            g.deg.as<int32_t>(), H, L, c.src.as<int32_t>(), c.rmask.as<int32_t>(), c.alpha, Y4,
                            rt_out, g.n, c.partials.as<double>());
     else
-        hipLaunchKernelGGL((refresh_k<uint32_t, C>), grid, blk, 0, c.stream, g.col_ptr.as<uint32_t>(),
+        hipLaunchKernelGGL((refresh_k<uint32_t, C, ST>), grid, blk, 0, c.stream, g.col_ptr.as<uint32_t>(),
                            g.row_idx.as<int32_t>(), sch.blocks.as<RowBlock>(), sch.n_blocks,
                            g.deg.as<int32_t>(), H, L, c.src.as<int32_t>(), c.rmask.as<int32_t>(), c.alpha, Y4,
                            rt_out, g.n, c.partials.as<double>());
     hipLaunchKernelGGL(reduce_cols_k, dim3(1), dim3(256), 0, c.stream, c.partials.as<double>(), (int)grid.x, c.Bw,
                        c.colsum.as<double>());
     HIPCHECK(hipGetLastError());
+}
+
+template <int C>
+void refresh_c(MixedCtx& c, Graph& g, void* y, double* rt_out) {
+    if (c.bf16) refresh_launch<C, StoreBF16>(c, g, y, rt_out);
+    else refresh_launch<C, StoreF32>(c, g, y, rt_out);
 }
 
 template <int C>
@@ -727,8 +873,8 @@ void convert(MixedCtx& c, const Graph& g, double alpha) {
     const unsigned gc = 1024;
     hipLaunchKernelGGL(convert_k, dim3(gc), dim3(kBlock), 0, c.stream, g.n, c.shift, g.deg.as<int32_t>(), alpha,
                        c.cmask.as<int32_t>(), c.r64.as<double>(), c.pi64.as<double>(),
-                       const_cast<float*>(c.ycur), c.Shi.as<float>(), c.Slo.as<float>(), c.T.as<float>(),
-                       c.partials.as<double>());
+                       const_cast<void*>(c.ycur), c.bf16 ? 1 : 0, c.Shi.as<float>(), c.Slo.as<float>(),
+                       c.T.as<float>(), c.partials.as<double>());
     hipLaunchKernelGGL(reduce_cols_k, dim3(1), dim3(256), 0, c.stream, c.partials.as<double>(), (int)gc, c.Bw,
                        c.colsum.as<double>());
     HIPCHECK(hipGetLastError());
@@ -737,8 +883,15 @@ void convert(MixedCtx& c, const Graph& g, double alpha) {
 void prepare(MixedCtx& c, const Graph& g) {
     Graph& gg = const_cast<Graph&>(g);
     by_width(c.Bw, [&](auto cc) {
-        const Schedule& sch = sweep_schedule<decltype(cc)::value>(gg, c.chunks);
-        const size_t need = (size_t)std::max(sch.n_pieces, 1) * (size_t)decltype(cc)::value * 16;
+        constexpr int C = decltype(cc)::value;
+        int32_t n_pieces = 0;
+        if (c.bf16) {
+            if constexpr (C >= 2) n_pieces = sweep_schedule<C / 2>(gg, c.chunks).n_pieces;
+            else fail(PPR_ERR_ARG, "bf16 residues need a block of at least 8 columns");
+        } else {
+            n_pieces = sweep_schedule<C>(gg, c.chunks).n_pieces;
+        }
+        const size_t need = (size_t)std::max(n_pieces, 1) * (size_t)c.Bw * 4;   // FP32 per piece and column
         if (c.piece_part.bytes < need) {
             c.drop_chunks();                   // a captured chunk holds the old buffer
             c.piece_part.alloc(need);
@@ -747,12 +900,32 @@ void prepare(MixedCtx& c, const Graph& g) {
     });
 }
 
-void sweep(MixedCtx& c, const Graph& g, const float* y_in, float* y_out) {
+void sweep(MixedCtx& c, const Graph& g, const void* y_in, void* y_out) {
     Graph& gg = const_cast<Graph&>(g);
     by_width(c.Bw, [&](auto cc) { sweep_c<decltype(cc)::value>(c, gg, y_in, y_out); });
 }
 
-void refresh(MixedCtx& c, const Graph& g, float* y, double* rt_out) {
+void store_from_f32(MixedCtx& c, const float* src, void* dst, int64_t count) {
+    if (!c.bf16) {
+        HIPCHECK(hipMemcpyAsync(dst, src, 4 * (size_t)count, hipMemcpyDeviceToDevice, c.stream));
+        return;
+    }
+    hipLaunchKernelGGL(to_bf16_k, dim3(1024), dim3(kBlock), 0, c.stream, count, src,
+                       reinterpret_cast<uint16_t*>(dst));
+    HIPCHECK(hipGetLastError());
+}
+
+void store_to_f32(MixedCtx& c, const void* src, float* dst, int64_t count) {
+    if (!c.bf16) {
+        HIPCHECK(hipMemcpyAsync(dst, src, 4 * (size_t)count, hipMemcpyDeviceToDevice, c.stream));
+        return;
+    }
+    hipLaunchKernelGGL(from_bf16_k, dim3(1024), dim3(kBlock), 0, c.stream, count,
+                       reinterpret_cast<const uint16_t*>(src), dst);
+    HIPCHECK(hipGetLastError());
+}
+
+void refresh(MixedCtx& c, const Graph& g, void* y, double* rt_out) {
     Graph& gg = const_cast<Graph&>(g);
     by_width(c.Bw, [&](auto cc) { refresh_c<decltype(cc)::value>(c, gg, y, rt_out); });
 }

@@ -248,7 +248,8 @@ void autotune_width(Graph& g, double alpha, const int32_t* widths, int32_t count
                     double* cost_us);
 
 void debug_sweep_mixed(Graph& g, double alpha, int32_t B, int32_t chunks, const float* y_in,
-                       const int32_t* fresh, float* y_out, float* t_out, const float* omega);
+                       const int32_t* fresh, float* y_out, float* t_out, const float* omega,
+                       int32_t residue_format);
 
 // serving blocks (continuous batching); the handle is an opaque Block*
 void* serve_block_create(Graph& g, int32_t slots, double alpha, const ppr_options& opt);

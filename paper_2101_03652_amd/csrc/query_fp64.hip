@@ -276,6 +276,7 @@ void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_
         st->batch_cols = 1;
         st->sweep_chunks = 1;
         st->sor_omega = 1.0;
+        st->residue_format = PPR_RESIDUE_F32;
         st->local_levels = levels;
         st->sweeps = sweeps;
         st->refreshes = 0;

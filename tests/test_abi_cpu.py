@@ -28,7 +28,7 @@ def test_library_exports_every_declared_symbol():
 def test_options_default():
     o = P.options()
     assert o.precision == P.FP64 and o.switch_rule == P.SWITCH_EDGES
-    assert o.switch_param == 32.0 and o.max_sweeps == 4096 and o.refresh_factor == 1e4
+    assert o.switch_param == 32.0 and o.max_sweeps == 4096 and o.refresh_factor == 0.0 and o.residue_format == 2
 
 
 def _create(row_ptr, col, n, flags=0):
@@ -81,7 +81,7 @@ def test_serving_and_debug_entry_points_reject_bad_arguments():
     assert lib.ppr_block_step(None, 4) == -1
     assert lib.ppr_block_poll(None, 0, None, None, None, None) == -1
     assert lib.ppr_slot_retire(None, 0, None, None) == -1
-    assert lib.ppr_debug_sweep_mixed(None, 0.2, 8, 1, None, None, None, None, None) == -1
+    assert lib.ppr_debug_sweep_mixed(None, 0.2, 8, 1, None, None, None, None, None, 0) == -1
 
 
 def test_null_and_range_arguments():

@@ -69,16 +69,20 @@ def test_ragged_batch_and_duplicates(c1, c1_truth):
     assert np.abs(out[5] - out[2]).sum() <= 2e-8 + SLACK
 
 
+@pytest.mark.parametrize("fmt", ["f32", "bf16"])
 @pytest.mark.parametrize("chunks", [1, 4])
-def test_alone_equals_in_mix(c1, chunks):
+def test_alone_equals_in_mix(c1, chunks, fmt):
     """A column's sweep budget depends on its own error only, so a source
-    answered alone and inside a block of 32 runs the same schedule; the two
-    results differ only by FP32 summation order."""
+    answered alone (the narrowest block of its storage format) and inside a
+    block of 32 runs the same schedule; the two results differ only by FP32
+    summation order."""
     srcs = [int(s) for s in synth.sources(c1.n, 40)][:32]
     G = P.Graph.from_synth(c1)
-    mix, smix = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=32, sweep_chunks=chunks)
+    rf = P.RESIDUE_F32 if fmt == "f32" else P.RESIDUE_BF16
+    mix, smix = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=32, sweep_chunks=chunks, residue_format=rf)
     for b in (0, 7, 31):
-        alone, sal = G.query_batch([srcs[b]], ALPHA, 1e-8, P.MIXED, batch_cols=4, sweep_chunks=chunks)
+        alone, sal = G.query_batch([srcs[b]], ALPHA, 1e-8, P.MIXED, batch_cols=4 if fmt == "f32" else 8,
+                                   sweep_chunks=chunks, residue_format=rf)
         assert sal[0]["sweeps"] == smix[b]["sweeps"]
         assert sal[0]["refreshes"] == smix[b]["refreshes"]
         assert np.abs(alone[0] - mix[b]).sum() <= SLACK
@@ -257,7 +261,7 @@ def test_over_relaxed_sweeps_certified(c1, c1_truth, omega):
     _, st1 = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=32, sweep_chunks=4, sor_omega=1.0)
     assert np.mean([s["sweeps"] for s in st]) < np.mean([s["sweeps"] for s in st1])
     for b in (0, 13):
-        alone, sal = G.query_batch([srcs[b]], ALPHA, 1e-8, P.MIXED, batch_cols=4, sweep_chunks=4,
+        alone, sal = G.query_batch([srcs[b]], ALPHA, 1e-8, P.MIXED, batch_cols=8, sweep_chunks=4,
                                    sor_omega=omega)
         assert sal[0]["sweeps"] == st[b]["sweeps"]
         assert np.abs(alone[0] - out[b]).sum() <= SLACK
@@ -278,6 +282,57 @@ def test_automatic_over_relaxation(c1):
             assert all(s["sor_omega"] == 1.0 for s in st)
     with pytest.raises(P.PPRError):
         G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, sor_omega=0.9)
+    G.close()
+
+
+@pytest.mark.parametrize("chunks,lam", [(1, 1e-8), (4, 1e-8), (4, 1e-6)])
+def test_bf16_residues_certified(c1, c1_truth, chunks, lam):
+    """bf16 residue storage: every column still ends certified within lambda
+    of the truth (the FP64 refresh measures what the storage rounding left
+    behind), with more refresh stages than FP32 storage needs, and a column's
+    result does not depend on the block it ran in."""
+    srcs = [int(s) for s in synth.sources(c1.n, 40)][:32]
+    print(f"[gpu] bf16 residues c1 chunks={chunks} lam={lam}", flush=True)
+    G = P.Graph.from_synth(c1)
+    out, st = G.query_batch(srcs, ALPHA, lam, P.MIXED, batch_cols=32, sweep_chunks=chunks,
+                            residue_format=P.RESIDUE_BF16)
+    _check_batch(c1, srcs, out, st, lam, c1_truth)
+    _, st32 = G.query_batch(srcs, ALPHA, lam, P.MIXED, batch_cols=32, sweep_chunks=chunks,
+                            residue_format=P.RESIDUE_F32)
+    assert np.mean([s["refreshes"] for s in st]) > np.mean([s["refreshes"] for s in st32])
+    for b in (0, 17):
+        alone, sal = G.query_batch([srcs[b]], ALPHA, lam, P.MIXED, sweep_chunks=chunks,
+                                   residue_format=P.RESIDUE_BF16)         # default width: 8 columns
+        assert sal[0]["batch_cols"] == 8
+        assert sal[0]["sweeps"] == st[b]["sweeps"] and sal[0]["refreshes"] == st[b]["refreshes"]
+        assert np.abs(alone[0] - out[b]).sum() <= SLACK
+    G.close()
+
+
+def test_bf16_serving_block(c1, c1_truth):
+    """A serving block with bf16 residues: slots refilled as they retire, every
+    result certified."""
+    G = P.Graph.from_synth(c1)
+    srcs = [int(s) for s in synth.sources(c1.n, 10)]
+    with pytest.raises(P.PPRError):                  # bf16 vectors hold 8 columns
+        P.Block(G, 4, ALPHA, residue_format=P.RESIDUE_BF16)
+    blk = P.Block(G, 8, ALPHA, sweep_chunks=4, residue_format=P.RESIDUE_BF16)
+    pending, slot_of, res = list(range(10)), {}, {}
+    steps = 0
+    while len(res) < 10:
+        for slot in blk.poll(wait=True)["done"]:
+            k = slot_of.pop(slot)
+            res[k] = blk.retire(slot)
+        while pending and len(slot_of) < 6:
+            k = pending.pop(0)
+            slot_of[blk.admit(srcs[k], 1e-8)] = k
+        if slot_of:
+            blk.step(5)
+            steps += 1
+        assert steps < 10000
+    blk.close()
+    _check_batch(c1, srcs, np.stack([res[k][0] for k in range(10)]), [res[k][1] for k in range(10)], 1e-8,
+                 c1_truth)
     G.close()
 
 

@@ -112,3 +112,83 @@ def test_over_relaxed_sweep_matches_oracle(graphs, name, width, chunks):
         # next sweep's q, read back from y_out
         np.testing.assert_allclose(want_q, (1.0 - w) / w * want_y, rtol=1e-13, atol=1e-300)
     G.close()
+
+
+def _bf16(x):
+    """Round FP32 values to bf16 (nearest, ties to even), returned as FP32."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32)
+
+
+UB = 2.0 ** -8     # bf16 unit roundoff (8-bit significand)
+
+
+@pytest.mark.parametrize("name", ["c1", "hub"])
+@pytest.mark.parametrize("width,chunks,sor", [(8, 1, False), (8, 5, True), (32, 3, False), (128, 1, False),
+                                              (128, 8, False), (32, 4, True), (128, 8, True)])
+def test_bf16_sweep_matches_oracle(graphs, name, width, chunks, sor):
+    """bf16 residue storage: the library rounds y_in to bf16, sweeps in FP32
+    and stores every new residue as bf16; the oracle sweeps the same bf16
+    inputs in FP64.  Every output is a bf16 value.  A row of chunk j reads the
+    stored, rounded values of chunks < j, so by induction its value is within
+    j + 1 bf16 roundings of the oracle's (relative to the same recursion on
+    absolute values), plus the FP32 summation bound; a fresh column's row
+    reads an earlier chunk's new value plus the fresh residue as one more
+    rounded value (j + 2).  The stage accumulator holds exactly the stored
+    values (plus the fresh input residue)."""
+    g = graphs[name]
+    print(f"[gpu] bf16 sweep parity {name} width={width} chunks={chunks} sor={sor}", flush=True)
+    G = P.Graph.from_synth(g)
+    rng = np.random.default_rng(width * 31 + chunks + (7 if sor else 0))
+    y = rng.random((g.n, width)).astype(np.float32)
+    y[rng.random((g.n, width)) < 0.3] = 0.0
+    fresh = (rng.random(width) < 0.5).astype(np.int32)
+    fresh[0], fresh[-1] = 1, 0
+    om = None
+    if sor:
+        om = (1.0 + 0.3 * rng.random(width)).astype(np.float32)
+        om[1] = 1.0
+    t_out = np.empty_like(y)
+    got = P.debug_sweep_mixed(G, ALPHA, y, fresh, chunks=chunks, t_out=t_out, omega=om,
+                              residue_format=P.RESIDUE_BF16)
+    assert not np.any(got.view(np.uint32) & 0xFFFF)                 # bf16 values
+    yb = _bf16(y)
+    csc_arrays = oracle.csc(g)
+    din = np.diff(csc_arrays[0]).astype(np.float64)
+    lo = oracle.chunk_bounds(g, chunks)
+    chunk_of = np.searchsorted(lo, np.arange(g.n), side="right") - 1        # row -> its chunk j
+    for b in range(width):
+        rounds = chunk_of + 1 + (1 if fresh[b] else 0) * (chunk_of > 0)
+        rel = (1.0 + UB) ** rounds - 1.0 + (din + din.max() + 6) * U
+        yb_b = yb[:, b].astype(np.float64)
+        if sor:
+            w = float(om[b])
+            q = np.zeros(g.n) if fresh[b] else (1.0 - w) / w * yb_b
+            want, _ = oracle.block_sor_sweep(g, ALPHA, lo, yb_b, bool(fresh[b]), w, q, csc_arrays=csc_arrays)
+            mag, _ = oracle.block_sor_sweep(g, ALPHA, lo, yb_b, bool(fresh[b]), w, np.abs(q), csc_arrays=csc_arrays)
+        else:
+            want = oracle.block_gs_sweep(g, ALPHA, lo, yb_b, bool(fresh[b]), csc_arrays=csc_arrays)
+            mag = want
+        err = np.abs(got[:, b] - want)
+        assert np.all(err <= rel * mag + 1e-38), (b, int(np.argmax(err - rel * mag)))
+        # T = (fresh input residue) + the stored value, in FP32
+        t_want = (yb[:, b] if fresh[b] else np.zeros(g.n, np.float32)) + got[:, b]
+        np.testing.assert_array_equal(t_out[:, b], t_want.astype(np.float32))
+    G.close()
+
+
+def test_bf16_device_buffers_and_errors(graphs):
+    """Device and host buffers give the same bits; an unknown format is
+    refused."""
+    g = graphs["c1"]
+    G = P.Graph.from_synth(g)
+    y = torch.rand((g.n, 8), dtype=torch.float32, device="cuda")
+    a = P.debug_sweep_mixed(G, ALPHA, y, [1] * 8, chunks=2, residue_format=P.RESIDUE_BF16)
+    h = P.debug_sweep_mixed(G, ALPHA, y.cpu().numpy(), [1] * 8, chunks=2, residue_format=P.RESIDUE_BF16)
+    assert np.array_equal(a.cpu().numpy(), h)
+    with pytest.raises(P.PPRError):
+        P.debug_sweep_mixed(G, ALPHA, y, [1] * 8, residue_format=5)
+    with pytest.raises(P.PPRError):                      # bf16 vectors hold 8 columns
+        P.debug_sweep_mixed(G, ALPHA, y[:, :4].contiguous(), [1] * 4, residue_format=P.RESIDUE_BF16)
+    G.close()
