@@ -71,7 +71,7 @@ typedef enum {
                               stored residue takes is residual that the next FP64 refresh
                               measures, so stages are shorter (refresh factor 50).  Blocks
                               of at least 8 columns (a sweep lane holds 8) */
-    PPR_RESIDUE_AUTO = 2   /* bf16 for blocks of at least 8 columns, else FP32 (default) */
+    PPR_RESIDUE_AUTO = 2   /* bf16 for blocks of at least 32 columns, else FP32 (default) */
 } ppr_residue_format;
 
 /* Rule that ends the local (frontier) phase and starts the global sweeps. */
@@ -279,7 +279,7 @@ ppr_status ppr_debug_sweep_fp64(ppr_graph* g, double alpha, const double* r_in, 
  * This is a node that holds p = q + the value above, pushes omega p and keeps
  * q' = (1 - omega) p, with q = (1 - omega) / omega * y_in(u) (what it kept
  * when it pushed y_in(u)); a fresh residue has kept nothing back.
- * residue_format: ppr_residue_format (PPR_RESIDUE_AUTO: bf16 when B >= 8).
+ * residue_format: ppr_residue_format (PPR_RESIDUE_AUTO: bf16 when B >= 32).
  * With bf16 storage (B >= 8) the block is stored in bf16: y_in is
  * rounded to bf16 (nearest, ties to even) on the way in, every y_out value
  * is the bf16 value the row stored (its out-neighbours pull exactly that),

@@ -262,7 +262,7 @@ def test_over_relaxed_sweeps_certified(c1, c1_truth, omega):
     assert np.mean([s["sweeps"] for s in st]) < np.mean([s["sweeps"] for s in st1])
     for b in (0, 13):
         alone, sal = G.query_batch([srcs[b]], ALPHA, 1e-8, P.MIXED, batch_cols=8, sweep_chunks=4,
-                                   sor_omega=omega)
+                                   sor_omega=omega, residue_format=st[b]["residue_format"])
         assert sal[0]["sweeps"] == st[b]["sweeps"]
         assert np.abs(alone[0] - out[b]).sum() <= SLACK
     G.close()
