@@ -82,10 +82,16 @@ def batched(c4, G, srcs):
     torch.cuda.synchronize()
     s0 = st[0]
     per = s0["sweep_ms"] / max(s0["sweep_launches"], 1)
-    bytes_per = 4 * M + 8 * N + 16 * N * 16
+    # per node and column: residue read and written, stage accumulator read and
+    # written, and the previous push when over-relaxed
+    rb = 2 if s0["residue_format"] == P.RESIDUE_BF16 else 4
+    per_col = 2 * rb + 8 + (rb if s0["sor_omega"] > 1.0 else 0)
+    bytes_per = 4 * M + 8 * N + per_col * N * 16
     REPORT["batched"] = {"sources": 16, "batch_cols": 16, "sweep_chunks": s0["sweep_chunks"],
+                         "residues": "bf16" if rb == 2 else "f32", "sor_omega": s0["sor_omega"],
                          "ms": s0["ms"], "queries_per_s": 16 / (s0["ms"] * 1e-3),
                          "sweeps_per_query": float(np.mean([s["sweeps"] for s in st])),
+                         "refreshes_per_query": float(np.mean([s["refreshes"] for s in st])),
                          "ms_per_sweep": per, "algorithmic_GBps": bytes_per / (per * 1e-3) / 1e9,
                          "max_cert": max(s["cert_l1"] for s in st)}
     print(f"[gpu] large batched: {REPORT['batched']}", flush=True)
