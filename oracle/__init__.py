@@ -97,6 +97,17 @@ def _load():
     lib.oracle_powitr.argtypes = [i32, vp, vp, i32, f64, i32, vp]
     lib.oracle_certificate.restype = f64
     lib.oracle_certificate.argtypes = [i32, vp, vp, i32, f64, vp, vp]
+    u64 = ctypes.c_uint64
+    lib.oracle_walk_budget.restype = f64
+    lib.oracle_walk_budget.argtypes = [i32, f64, f64]
+    lib.oracle_splitmix64.restype = u64
+    lib.oracle_splitmix64.argtypes = [u64]
+    lib.oracle_walk_endpoint.restype = i32
+    lib.oracle_walk_endpoint.argtypes = [vp, vp, f64, u64, i32, ctypes.c_uint32, i32]
+    lib.oracle_refine_sync.restype = i32
+    lib.oracle_refine_sync.argtypes = [i32, vp, vp, f64, f64, vp, vp, vp]
+    lib.oracle_mc_phase.restype = i64
+    lib.oracle_mc_phase.argtypes = [i32, vp, vp, f64, f64, u64, i32, vp, vp]
     lib.oracle_powerpush_many.restype = ctypes.c_int
     lib.oracle_powerpush_many.argtypes = [i32, i64, vp, vp, vp, i32, f64, f64, vp, vp, vp, i32]
     _lib = lib
@@ -280,3 +291,47 @@ def powerpush_many(g, sources, alpha: float, lam: float, threads: int):
     if rc != 0:
         raise MemoryError("oracle_powerpush_many")
     return pi, [s.as_dict() for s in st]
+
+
+# ---------------------------------------------------------------- SpeedPPR (Section 6)
+MAX_WALK_STEPS = 4096     # a walk alive after this many steps stops where it is
+
+
+def walk_budget(n: int, eps: float, mu: float) -> float:
+    """W of Eq. 8 (natural logarithm)."""
+    return _load().oracle_walk_budget(int(n), float(eps), float(mu))
+
+
+def splitmix64(z: int) -> int:
+    return int(_load().oracle_splitmix64(ctypes.c_uint64(z & (2 ** 64 - 1))))
+
+
+def walk_endpoint(g, alpha: float, seed: int, v: int, j: int, max_steps: int = MAX_WALK_STEPS) -> int:
+    """Stop node of walk j from v (see oracle_walk_endpoint)."""
+    rp, col = _g(g)
+    return int(_load().oracle_walk_endpoint(_p(rp), _p(col), alpha, ctypes.c_uint64(seed), int(v), int(j),
+                                            int(max_steps)))
+
+
+def refine_sync(g, alpha: float, rmax: float, pi: np.ndarray, r: np.ndarray):
+    """Algorithm 4's refinement, level-synchronous, in place on (pi, r).
+    Returns (levels, edge_pushes)."""
+    rp, col = _g(g)
+    assert pi.dtype == np.float64 and r.dtype == np.float64 and pi.flags.c_contiguous and r.flags.c_contiguous
+    ep = ctypes.c_int64()
+    lv = _load().oracle_refine_sync(g.n, _p(rp), _p(col), alpha, rmax, _p(pi), _p(r), ctypes.byref(ep))
+    if lv < 0:
+        raise MemoryError("oracle_refine_sync")
+    return int(lv), int(ep.value)
+
+
+def mc_phase(g, alpha: float, W: float, seed: int, r: np.ndarray, pi: np.ndarray,
+             max_steps: int = MAX_WALK_STEPS) -> int:
+    """Algorithm 4's Monte Carlo phase: adds the walks' estimates to pi in
+    place.  Returns the number of walks."""
+    rp, col = _g(g)
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    assert pi.dtype == np.float64 and pi.flags.c_contiguous
+    return int(_load().oracle_mc_phase(g.n, _p(rp), _p(col), alpha, float(W), ctypes.c_uint64(seed),
+                                       int(max_steps), _p(r), _p(pi)))
+

@@ -570,3 +570,114 @@ int oracle_powerpush_many(int32_t n, int64_t m, const int64_t* row_ptr, const in
     }
     return rc;
 }
+
+/* ================================================================== */
+/* Approximate SSPPR: SpeedPPR (Section 6, Algorithm 4).              */
+/* ================================================================== */
+
+/* W of Eq. 8: the number of alpha-random walks from s that the Monte  */
+/* Carlo method needs for relative error eps on every node with        */
+/* pi(s, v) >= mu, with probability 1 - 1/n (Chernoff bound).  Reading: */
+/* "log" is the natural logarithm.                                      */
+double oracle_walk_budget(int32_t n, double eps, double mu) {
+    return 2.0 * (2.0 * eps / 3.0 + 2.0) * log((double)n) / (eps * eps * mu);
+}
+
+/* SplitMix64 (Steele, Lea, Flood, OOPSLA 2014): the output for state z */
+/* is mix(z + gamma).  Used as a counter-based generator: draw k of the  */
+/* generator seeded with b is oracle_splitmix64(b + k * gamma).          */
+#define ORACLE_GAMMA 0x9E3779B97F4A7C15ULL
+uint64_t oracle_splitmix64(uint64_t z) {
+    z += ORACLE_GAMMA;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+    return z ^ (z >> 31);
+}
+
+/* Stop node of walk j from v (an alpha-random walk, Section 2: at each   */
+/* node it stops with probability alpha, else moves to an out-neighbour   */
+/* chosen uniformly).  The walk's draws come from SplitMix64 seeded with  */
+/* b = splitmix64(seed ^ splitmix64(v << 32 | j)); step t uses draw 2t    */
+/* for the stop test (top 53 bits as a uniform in [0, 1): stop when it is */
+/* < alpha) and draw 2t + 1 for the neighbour (index = (top 32 bits * d)  */
+/* >> 32, i.e. floor of a uniform times d).  A walk still alive after     */
+/* max_steps steps stops where it is (probability (1 - alpha)^max_steps). */
+int32_t oracle_walk_endpoint(const int64_t* row_ptr, const int32_t* col, double alpha, uint64_t seed,
+                             int32_t v, uint32_t j, int32_t max_steps) {
+    uint64_t b = oracle_splitmix64(seed ^ oracle_splitmix64(((uint64_t)(uint32_t)v << 32) | (uint64_t)j));
+    int32_t cur = v;
+    for (int32_t t = 0; t < max_steps; ++t) {
+        uint64_t x = oracle_splitmix64(b + (uint64_t)(2 * t) * ORACLE_GAMMA);
+        double u = (double)(x >> 11) * (1.0 / 9007199254740992.0);   /* 2^-53 */
+        if (u < alpha) break;
+        uint64_t y = oracle_splitmix64(b + (uint64_t)(2 * t + 1) * ORACLE_GAMMA);
+        uint64_t d = (uint64_t)(row_ptr[cur + 1] - row_ptr[cur]);
+        uint64_t idx = ((y >> 32) * d) >> 32;
+        cur = col[row_ptr[cur] + (int64_t)idx];
+    }
+    return cur;
+}
+
+/* The refinement of Algorithm 4 (no node active w.r.t. rmax), taken       */
+/* level-synchronously: S = { v : r(v) > d_v rmax }; every node of S pushes */
+/* at once the residue it holds (x = r(v), r(v) = 0, pi(v) += alpha x, each */
+/* out-neighbour gets (1 - alpha) x / d_v); the next S holds the nodes      */
+/* active after the distribution; until S is empty.  Returns the number of  */
+/* levels; *edge_pushes (nullable) receives sum of d_v over the pushes.      */
+int32_t oracle_refine_sync(int32_t n, const int64_t* row_ptr, const int32_t* col, double alpha, double rmax,
+                           double* pi, double* r, int64_t* edge_pushes) {
+    double* x = (double*)malloc(sizeof(double) * (size_t)n);
+    int32_t* S = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    if (!x || !S) { free(x); free(S); return -2; }
+    int32_t levels = 0;
+    int64_t pushes = 0;
+    for (;;) {
+        int32_t ns = 0;
+        for (int32_t v = 0; v < n; ++v) {
+            double d = (double)(row_ptr[v + 1] - row_ptr[v]);
+            if (r[v] > d * rmax) S[ns++] = v;
+        }
+        if (ns == 0) break;
+        for (int32_t i = 0; i < ns; ++i) {
+            int32_t v = S[i];
+            x[i] = r[v];
+            r[v] = 0.0;
+            pi[v] += alpha * x[i];
+        }
+        for (int32_t i = 0; i < ns; ++i) {
+            int32_t v = S[i];
+            int64_t d = row_ptr[v + 1] - row_ptr[v];
+            double inc = (1.0 - alpha) * x[i] / (double)d;
+            for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) r[col[e]] += inc;
+            pushes += d;
+        }
+        levels++;
+    }
+    free(x);
+    free(S);
+    if (edge_pushes) *edge_pushes = pushes;
+    return levels;
+}
+
+/* The Monte Carlo phase of Algorithm 4 (FORA's second phase, Eqs. 9-10):  */
+/* for every v with r(v) > 0, W_v = ceil(r(v) W) walks from v (capped at   */
+/* d_v, which a refined residue meets up to rounding: r(v) <= d_v / W);    */
+/* each walk that stops at u adds r(v) / W_v to pi(u).  Walk j of v is     */
+/* oracle_walk_endpoint(.., v, j, ..).  Returns the number of walks.        */
+int64_t oracle_mc_phase(int32_t n, const int64_t* row_ptr, const int32_t* col, double alpha, double W,
+                        uint64_t seed, int32_t max_steps, const double* r, double* pi) {
+    int64_t walks = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        if (!(r[v] > 0.0)) continue;
+        int64_t d = row_ptr[v + 1] - row_ptr[v];
+        int64_t wv = (int64_t)ceil(r[v] * W);
+        if (wv > d) wv = d;
+        double share = r[v] / (double)wv;
+        for (int64_t j = 0; j < wv; ++j) {
+            int32_t u = oracle_walk_endpoint(row_ptr, col, alpha, seed, v, (uint32_t)j, max_steps);
+            pi[u] += share;
+        }
+        walks += wv;
+    }
+    return walks;
+}
