@@ -218,6 +218,70 @@ ppr_status ppr_query_ex(ppr_graph* g, const int32_t* sources, int32_t B, double 
                         double lambda, const ppr_options* opt, double* pi_out, double* r_out,
                         ppr_stats* stats);
 
+/* ------------------------------------------------------------------ */
+/* Approximate SSPPR: SpeedPPR (Section 6, Algorithm 4).               */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    int32_t source;
+    int32_t local_levels;        /* PowerPush local iterations (phase 1) */
+    int32_t sweeps;              /* PowerPush global sweeps (phase 1) */
+    int32_t refine_levels;       /* refinement iterations (every active node pushes at once) */
+    int64_t refine_edge_pushes;  /* residue updates of the refinement */
+    int64_t walks;               /* alpha-random walks of the Monte Carlo phase (index entries
+                                    read when the index is used) */
+    double W;                    /* Eq. 8 */
+    double lambda;               /* phase 1 threshold m / W (at most 1) */
+    double r_sum;                /* residue mass the walks distribute */
+    double ms_push, ms_refine, ms_walks, ms;   /* host wall time per phase and in all */
+    int32_t used_index;
+    int32_t reserved;
+} ppr_approx_stats;
+
+/*
+ * One approximate query (Algorithm 4): with W = 2 (2 eps / 3 + 2) ln n /
+ * (eps^2 mu) (Eq. 8), PowerPush to lambda = min(m / W, 1), the refinement
+ * until no node is active w.r.t. rmax = 1 / W, then for every v with r(v) > 0
+ * W_v = ceil(r(v) W) <= d_v alpha-random walks from v, each adding
+ * r(v) / W_v to pi_hat at its stop node (Eqs. 9-10).  The estimate has
+ * |pi_hat(v) - pi_s(v)| <= eps pi_s(v) for every v with pi_s(v) >= mu with
+ * probability 1 - 1/n (Section 2's Approx-SSPPR).
+ *   eps in (0, 1]; mu in (0, 1] (the literature's 1/n is the usual choice).
+ *   seed: the walks' generator seed (walk j from v is a function of seed, v, j
+ *   and the graph; see ppr_walk_index_build).
+ *   use_index: 1 = read the walks from the graph's index (built with the same
+ *   alpha and seed, else PPR_ERR_ARG); the result is then the same as
+ *   without the index.
+ *   pi_out: double[n], host or device.
+ */
+ppr_status ppr_query_approx(ppr_graph* g, int32_t s, double alpha, double eps, double mu, uint64_t seed,
+                            int32_t use_index, double* pi_out, ppr_approx_stats* stats);
+
+/*
+ * The SpeedPPR index (Section 6): walk j from v for every j < d_v, m walks in
+ * all, independent of eps; stored on the device beside the graph (4 m bytes)
+ * until the graph is destroyed or the index rebuilt.  Walk j from v draws
+ * from SplitMix64 seeded with splitmix(seed ^ splitmix(v << 32 | j)) (output
+ * k of SplitMix64 seeded with b being mix(b + (k + 1) 0x9E3779B97F4A7C15));
+ * step t stops when (draw 2t >> 11) 2^-53 < alpha, else moves along out-edge
+ * ((draw 2t+1 >> 32) d_v) >> 32 of the CSR; a walk alive after 4096 steps
+ * stops where it is.  *ms (nullable) receives the build time.
+ */
+ppr_status ppr_walk_index_build(ppr_graph* g, double alpha, uint64_t seed, double* ms);
+/* Host copy of the index: int32[m], entry row_ptr[v] + j = stop node of walk j from v. */
+ppr_status ppr_walk_index_copy(const ppr_graph* g, int32_t* out);
+
+/*
+ * The two phases on caller data, for tests (pi, r: double[n] in device
+ * memory).  ppr_debug_refine: the refinement w.r.t. rmax in place (levels,
+ * edge_pushes nullable).  ppr_debug_walks: the Monte Carlo phase for budget W
+ * on residue r, adding into pi; W_v = min(ceil(r(v) W), d_v); *walks
+ * (nullable) receives the number of walks.
+ */
+ppr_status ppr_debug_refine(ppr_graph* g, double alpha, double rmax, double* pi, double* r, int32_t* levels,
+                            int64_t* edge_pushes);
+ppr_status ppr_debug_walks(ppr_graph* g, double alpha, double W, uint64_t seed, int32_t use_index,
+                           const double* r, double* pi, int64_t* walks);
+
 /* One point of a convergence trace (see ppr_query_trace). */
 typedef struct {
     double ms;              /* host time since the call started, taken once the iteration has

@@ -42,6 +42,7 @@ EXPORTS = [
     "ppr_debug_sweep_fp64", "ppr_version", "ppr_last_error", "ppr_autotune",
     "ppr_block_create", "ppr_block_destroy", "ppr_block_footprint", "ppr_slot_admit",
     "ppr_block_step", "ppr_block_poll", "ppr_slot_retire", "ppr_debug_sweep_mixed", "ppr_query_trace",
+    "ppr_query_approx", "ppr_walk_index_build", "ppr_walk_index_copy", "ppr_debug_refine", "ppr_debug_walks",
 ]
 
 
@@ -63,6 +64,20 @@ class Stats(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ApproxStats(ctypes.Structure):
+    _fields_ = [("source", ctypes.c_int32), ("local_levels", ctypes.c_int32), ("sweeps", ctypes.c_int32),
+                ("refine_levels", ctypes.c_int32), ("refine_edge_pushes", ctypes.c_int64),
+                ("walks", ctypes.c_int64), ("W", ctypes.c_double), ("lambda_", ctypes.c_double),
+                ("r_sum", ctypes.c_double), ("ms_push", ctypes.c_double), ("ms_refine", ctypes.c_double),
+                ("ms_walks", ctypes.c_double), ("ms", ctypes.c_double), ("used_index", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        d["lambda"] = d.pop("lambda_")
+        return d
 
 
 # one ppr_trace_point
@@ -109,6 +124,11 @@ def load() -> ctypes.CDLL:
         "ppr_query_batch": (st, [vp, vp, i32, f64, f64, ctypes.c_int, vp, vp]),
         "ppr_query_ex": (st, [vp, vp, i32, f64, f64, vp, vp, vp, vp]),
         "ppr_query_trace": (st, [vp, i32, f64, f64, vp, vp, vp, i32, vp, vp]),
+        "ppr_query_approx": (st, [vp, i32, f64, f64, f64, ctypes.c_uint64, i32, vp, vp]),
+        "ppr_walk_index_build": (st, [vp, f64, ctypes.c_uint64, vp]),
+        "ppr_walk_index_copy": (st, [vp, vp]),
+        "ppr_debug_refine": (st, [vp, f64, f64, vp, vp, vp, vp]),
+        "ppr_debug_walks": (st, [vp, f64, f64, ctypes.c_uint64, i32, vp, vp, vp]),
         "ppr_debug_sweep_fp64": (st, [vp, f64, vp, vp, vp, vp]),
         "ppr_autotune": (st, [vp, f64, vp, i32, vp, vp]),
         "ppr_debug_sweep_mixed": (st, [vp, f64, i32, i32, vp, vp, vp, vp, vp, i32]),
@@ -247,6 +267,45 @@ class Graph:
         if cnt.value > capacity:
             raise PPRError(-1, f"trace needs {cnt.value} points, capacity is {capacity}")
         return out, tr[:cnt.value].copy(), st.as_dict()
+
+    def query_approx(self, s: int, alpha: float = 0.2, eps: float = 0.5, mu: float | None = None,
+                     seed: int = 0, use_index: bool = False, out=None):
+        """Approximate query (SpeedPPR, Algorithm 4): relative error eps on
+        every node with pi >= mu (default 1/n) with probability 1 - 1/n.
+        Returns (pi_hat, stats)."""
+        if out is None:
+            out = np.empty(self.n, dtype=np.float64)
+        st = ApproxStats()
+        mu = 1.0 / self.n if mu is None else mu
+        _check(load().ppr_query_approx(self._h, int(s), float(alpha), float(eps), float(mu),
+                                       ctypes.c_uint64(seed), 1 if use_index else 0, _ptr(out), ctypes.byref(st)))
+        return out, st.as_dict()
+
+    def build_walk_index(self, alpha: float = 0.2, seed: int = 0) -> float:
+        """Pre-compute d_v walks per node (m in all); returns the build time (ms)."""
+        ms = ctypes.c_double()
+        _check(load().ppr_walk_index_build(self._h, float(alpha), ctypes.c_uint64(seed), ctypes.byref(ms)))
+        return ms.value
+
+    def walk_index(self) -> np.ndarray:
+        out = np.empty(max(self.m, 1), dtype=np.int32)
+        _check(load().ppr_walk_index_copy(self._h, _ptr(out)))
+        return out[:self.m]
+
+    def debug_refine(self, alpha: float, rmax: float, pi, r):
+        """Refinement in place on device tensors; returns (levels, edge_pushes)."""
+        lv = ctypes.c_int32()
+        ep = ctypes.c_int64()
+        _check(load().ppr_debug_refine(self._h, float(alpha), float(rmax), _ptr(pi), _ptr(r), ctypes.byref(lv),
+                                       ctypes.byref(ep)))
+        return lv.value, ep.value
+
+    def debug_walks(self, alpha: float, W: float, seed: int, r, pi, use_index: bool = False) -> int:
+        """Monte Carlo phase on device tensors (adds into pi); returns the walks."""
+        nw = ctypes.c_int64()
+        _check(load().ppr_debug_walks(self._h, float(alpha), float(W), ctypes.c_uint64(seed),
+                                      1 if use_index else 0, _ptr(r), _ptr(pi), ctypes.byref(nw)))
+        return nw.value
 
     def autotune(self, alpha: float = 0.2, widths=None) -> dict:
         """Pick the batched block width by timing sweeps on this graph; the

@@ -240,6 +240,68 @@ ppr_status ppr_debug_sweep_mixed(ppr_graph* gh, double alpha, int32_t B, int32_t
     });
 }
 
+// ---------------------------------------------------------------- approximate SSPPR
+
+ppr_status ppr_query_approx(ppr_graph* gh, int32_t s, double alpha, double eps, double mu, uint64_t seed,
+                            int32_t use_index, double* pi_out, ppr_approx_stats* stats) {
+    return guarded([&] {
+        Graph* g = reinterpret_cast<Graph*>(gh);
+        check_query_args(g, &s, 1, alpha, 1.0, pi_out);
+        if (!(eps > 0.0 && eps <= 1.0)) fail(PPR_ERR_ARG, "eps must lie in (0, 1]");
+        if (!(mu > 0.0 && mu <= 1.0)) fail(PPR_ERR_ARG, "mu must lie in (0, 1]");
+        if (use_index != 0 && use_index != 1) fail(PPR_ERR_ARG, "use_index must be 0 or 1");
+        HIPCHECK(hipSetDevice(g->device));
+        (void)is_device_ptr(pi_out, g->device);
+        run_approx_query(*g, s, alpha, eps, mu, seed, use_index == 1, pi_out, stats);
+    });
+}
+
+ppr_status ppr_walk_index_build(ppr_graph* gh, double alpha, uint64_t seed, double* ms) {
+    return guarded([&] {
+        Graph* g = reinterpret_cast<Graph*>(gh);
+        if (!g) fail(PPR_ERR_ARG, "graph is NULL");
+        if (!(alpha > 0.0 && alpha < 1.0)) fail(PPR_ERR_ARG, "alpha must lie in (0, 1)");
+        build_walk_index(*g, alpha, seed, ms);
+    });
+}
+
+ppr_status ppr_walk_index_copy(const ppr_graph* gh, int32_t* out) {
+    return guarded([&] {
+        const Graph* g = reinterpret_cast<const Graph*>(gh);
+        if (!g || !out) fail(PPR_ERR_ARG, "NULL argument");
+        copy_walk_index(*g, out);
+    });
+}
+
+ppr_status ppr_debug_refine(ppr_graph* gh, double alpha, double rmax, double* pi, double* r, int32_t* levels,
+                            int64_t* edge_pushes) {
+    return guarded([&] {
+        Graph* g = reinterpret_cast<Graph*>(gh);
+        if (!g || !pi || !r) fail(PPR_ERR_ARG, "NULL argument");
+        if (!(alpha > 0.0 && alpha < 1.0)) fail(PPR_ERR_ARG, "alpha must lie in (0, 1)");
+        if (!(rmax > 0.0)) fail(PPR_ERR_ARG, "rmax must be > 0");
+        HIPCHECK(hipSetDevice(g->device));
+        if (!is_device_ptr(pi, g->device) || !is_device_ptr(r, g->device))
+            fail(PPR_ERR_ARG, "pi and r must be device memory");
+        debug_refine(*g, alpha, rmax, pi, r, levels, edge_pushes);
+    });
+}
+
+ppr_status ppr_debug_walks(ppr_graph* gh, double alpha, double W, uint64_t seed, int32_t use_index,
+                           const double* r, double* pi, int64_t* walks) {
+    return guarded([&] {
+        Graph* g = reinterpret_cast<Graph*>(gh);
+        if (!g || !pi || !r) fail(PPR_ERR_ARG, "NULL argument");
+        if (!(alpha > 0.0 && alpha < 1.0)) fail(PPR_ERR_ARG, "alpha must lie in (0, 1)");
+        if (!(W >= 1.0) || std::isinf(W)) fail(PPR_ERR_ARG, "W must be finite and >= 1");
+        if (use_index != 0 && use_index != 1) fail(PPR_ERR_ARG, "use_index must be 0 or 1");
+        HIPCHECK(hipSetDevice(g->device));
+        if (!is_device_ptr(pi, g->device) || !is_device_ptr(r, g->device))
+            fail(PPR_ERR_ARG, "pi and r must be device memory");
+        debug_walks(*g, alpha, W, seed, use_index == 1, r, pi, walks);
+    });
+}
+
 // ---------------------------------------------------------------- serving
 
 ppr_status ppr_block_create(ppr_graph* gh, int32_t slots, double alpha, const ppr_options* opt, ppr_block** out) {

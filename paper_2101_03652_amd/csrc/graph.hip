@@ -154,7 +154,7 @@ Graph::~Graph() {
 }
 
 size_t Graph::device_bytes() const {
-    size_t b = row_ptr.bytes + col.bytes + col_ptr.bytes + row_idx.bytes + deg.bytes;
+    size_t b = row_ptr.bytes + col.bytes + col_ptr.bytes + row_idx.bytes + deg.bytes + walk_index.bytes;
     return b;
 }
 

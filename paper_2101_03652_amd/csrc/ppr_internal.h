@@ -137,6 +137,9 @@ struct Graph {
     std::vector<std::unique_ptr<QueryCtx>> pool;       // idle FP64 query contexts
     std::vector<MixedCtxPtr> mixed_pool;               // idle batched contexts (any width)
     int tuned_width = 0;                               // autotuner's choice (0 = not tuned)
+    DevBuf walk_index;                                 // int32[m]: stop nodes of d_v walks per node
+    double walk_alpha = -1.0;                          // the index's alpha (-1: none)
+    uint64_t walk_seed = 0;                            // the index's seed
     int live_blocks = 0;                               // serving blocks on this graph (pool_mu)
     ~Graph();
     size_t device_bytes() const;
@@ -242,6 +245,18 @@ struct TraceSink {
 
 void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_options& opt,
                     double* pi_out, double* r_out, ppr_stats* st, TraceSink* trace = nullptr);
+
+// Approximate SSPPR (SpeedPPR).  A walk alive after kMaxWalkSteps steps stops
+// where it is (probability (1 - alpha)^4096).
+constexpr int32_t kMaxWalkSteps = 4096;
+double walk_budget(int32_t n, double eps, double mu);
+void run_approx_query(Graph& g, int32_t s, double alpha, double eps, double mu, uint64_t seed, bool use_index,
+                      double* pi_out, ppr_approx_stats* st);
+void build_walk_index(Graph& g, double alpha, uint64_t seed, double* ms);
+void copy_walk_index(const Graph& g, int32_t* out);
+void debug_refine(Graph& g, double alpha, double rmax, double* pi, double* r, int32_t* levels, int64_t* edges);
+void debug_walks(Graph& g, double alpha, double W, uint64_t seed, bool use_index, const double* r, double* pi,
+                 int64_t* nwalks);
 void run_mixed_batch(Graph& g, const int32_t* sources, int32_t B, double alpha, double lambda,
                      const ppr_options& opt, double* pi_out, double* r_out, ppr_stats* st);
 void autotune_width(Graph& g, double alpha, const int32_t* widths, int32_t count, int32_t* best,
