@@ -95,6 +95,8 @@ def main() -> int:
                     help="FP64 queries with Algorithm 3's epoch thresholds in the global phase")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--approx-queries", type=int, default=8,
+                    help="SpeedPPR queries timed per eps and mode (0: skip)")
     ap.add_argument("--f32-leg", type=int, default=1,
                     help="1: also time one step with FP32 residue storage (0: skip)")
     ap.add_argument("--extra-widths", default="8,32",
@@ -248,6 +250,33 @@ def main() -> int:
                           "residues": "bf16" if st_w[0]["residue_format"] == 1 else "f32"}
         print(f"[bench] width {w}: {widths[str(w)]}", flush=True, file=sys.stderr)
 
+    # approximate queries (SpeedPPR, Algorithm 4): index-free and with the walk index
+    approx = None
+    if args.approx_queries > 0:
+        approx = {"mu": "1/n", "queries": args.approx_queries}
+        ms_idx = G.build_walk_index(args.alpha, seed=1)
+        approx["index_build_ms"] = round(ms_idx, 1)
+        approx["index_bytes"] = 4 * g.m
+        one = torch.empty(g.n, dtype=torch.float64, device="cuda")
+        for eps in (0.5, 0.1):
+            row = {}
+            for use_index in (False, True):
+                G.query_approx(srcs[0], args.alpha, eps, seed=1, use_index=use_index, out=one)   # warm-up
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                sts = [G.query_approx(s_, args.alpha, eps, seed=1, use_index=use_index, out=one)[1]
+                       for s_ in srcs[:args.approx_queries]]
+                torch.cuda.synchronize()
+                dt1 = time.perf_counter() - t1
+                mean = lambda k: sum(x[k] for x in sts) / len(sts)
+                row["index" if use_index else "index_free"] = {
+                    "value": round(len(sts) / dt1, 2), "unit": "queries/s", "W": sts[0]["W"],
+                    "lambda": sts[0]["lambda"], "sweeps": mean("sweeps"), "refine_levels": mean("refine_levels"),
+                    "walks": mean("walks"), "ms_push": round(mean("ms_push"), 2),
+                    "ms_refine": round(mean("ms_refine"), 2), "ms_walks": round(mean("ms_walks"), 2)}
+            approx[f"eps={eps:g}"] = row
+            print(f"[bench] speedppr eps={eps:g}: {row}", file=sys.stderr, flush=True)
+
     # sources one at a time: plain FP64 path against the mixed path (one column)
     single = {}
     if args.single_sources > 0:
@@ -344,6 +373,7 @@ def main() -> int:
         "sweeps_per_query": round(sum(s["sweeps"] for st in stats_all for s in st) / q, 2),
         "refreshes_per_query": round(sum(s["refreshes"] for st in stats_all for s in st) / q, 2),
         "f32_residues": f32_leg,
+        "approx_speedppr": approx,
         "batched_widths": widths,
         "single_source": single,
         "cpu_baseline": cpu,

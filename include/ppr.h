@@ -251,10 +251,14 @@ typedef struct {
  *   use_index: 1 = read the walks from the graph's index (built with the same
  *   alpha and seed, else PPR_ERR_ARG); the result is then the same as
  *   without the index.
+ *   opt: options of the phase-1 PowerPush (NULL = defaults with
+ *   PPR_GLOBAL_EPOCHS, Algorithm 3's own thresholds, which leave fewer nodes
+ *   active for the refinement than threshold-0 sweeps; it runs the PPR_FP64
+ *   path whatever opt->precision says).
  *   pi_out: double[n], host or device.
  */
 ppr_status ppr_query_approx(ppr_graph* g, int32_t s, double alpha, double eps, double mu, uint64_t seed,
-                            int32_t use_index, double* pi_out, ppr_approx_stats* stats);
+                            int32_t use_index, const ppr_options* opt, double* pi_out, ppr_approx_stats* stats);
 
 /*
  * The SpeedPPR index (Section 6): walk j from v for every j < d_v, m walks in

@@ -124,7 +124,7 @@ def load() -> ctypes.CDLL:
         "ppr_query_batch": (st, [vp, vp, i32, f64, f64, ctypes.c_int, vp, vp]),
         "ppr_query_ex": (st, [vp, vp, i32, f64, f64, vp, vp, vp, vp]),
         "ppr_query_trace": (st, [vp, i32, f64, f64, vp, vp, vp, i32, vp, vp]),
-        "ppr_query_approx": (st, [vp, i32, f64, f64, f64, ctypes.c_uint64, i32, vp, vp]),
+        "ppr_query_approx": (st, [vp, i32, f64, f64, f64, ctypes.c_uint64, i32, vp, vp, vp]),
         "ppr_walk_index_build": (st, [vp, f64, ctypes.c_uint64, vp]),
         "ppr_walk_index_copy": (st, [vp, vp]),
         "ppr_debug_refine": (st, [vp, f64, f64, vp, vp, vp, vp]),
@@ -269,16 +269,20 @@ class Graph:
         return out, tr[:cnt.value].copy(), st.as_dict()
 
     def query_approx(self, s: int, alpha: float = 0.2, eps: float = 0.5, mu: float | None = None,
-                     seed: int = 0, use_index: bool = False, out=None):
+                     seed: int = 0, use_index: bool = False, out=None, **opt):
         """Approximate query (SpeedPPR, Algorithm 4): relative error eps on
         every node with pi >= mu (default 1/n) with probability 1 - 1/n.
-        Returns (pi_hat, stats)."""
+        Keyword options go to the phase-1 PowerPush (default: Algorithm 3's
+        epoch thresholds).  Returns (pi_hat, stats)."""
         if out is None:
             out = np.empty(self.n, dtype=np.float64)
+        opt.setdefault("global_rule", GLOBAL_EPOCHS)
         st = ApproxStats()
         mu = 1.0 / self.n if mu is None else mu
+        o = options(precision=FP64, **opt)
         _check(load().ppr_query_approx(self._h, int(s), float(alpha), float(eps), float(mu),
-                                       ctypes.c_uint64(seed), 1 if use_index else 0, _ptr(out), ctypes.byref(st)))
+                                       ctypes.c_uint64(seed), 1 if use_index else 0, ctypes.byref(o), _ptr(out),
+                                       ctypes.byref(st)))
         return out, st.as_dict()
 
     def build_walk_index(self, alpha: float = 0.2, seed: int = 0) -> float:

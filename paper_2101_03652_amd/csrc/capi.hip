@@ -243,16 +243,25 @@ ppr_status ppr_debug_sweep_mixed(ppr_graph* gh, double alpha, int32_t B, int32_t
 // ---------------------------------------------------------------- approximate SSPPR
 
 ppr_status ppr_query_approx(ppr_graph* gh, int32_t s, double alpha, double eps, double mu, uint64_t seed,
-                            int32_t use_index, double* pi_out, ppr_approx_stats* stats) {
+                            int32_t use_index, const ppr_options* opt, double* pi_out, ppr_approx_stats* stats) {
     return guarded([&] {
         Graph* g = reinterpret_cast<Graph*>(gh);
         check_query_args(g, &s, 1, alpha, 1.0, pi_out);
         if (!(eps > 0.0 && eps <= 1.0)) fail(PPR_ERR_ARG, "eps must lie in (0, 1]");
         if (!(mu > 0.0 && mu <= 1.0)) fail(PPR_ERR_ARG, "mu must lie in (0, 1]");
         if (use_index != 0 && use_index != 1) fail(PPR_ERR_ARG, "use_index must be 0 or 1");
+        ppr_options o;
+        if (opt) {
+            o = *opt;
+        } else {
+            ppr_options_default(&o);
+            o.global_rule = PPR_GLOBAL_EPOCHS;      // Algorithm 3's thresholds: fewer refinement levels
+        }
+        o.precision = PPR_FP64;
+        check_options(o);
         HIPCHECK(hipSetDevice(g->device));
         (void)is_device_ptr(pi_out, g->device);
-        run_approx_query(*g, s, alpha, eps, mu, seed, use_index == 1, pi_out, stats);
+        run_approx_query(*g, s, alpha, eps, mu, seed, use_index == 1, o, pi_out, stats);
     });
 }
 

@@ -152,6 +152,8 @@ void graph_validate(const int64_t* row_ptr, const int32_t* col, int32_t n, int64
 void graph_copy_csc(const Graph& g, int64_t* col_ptr, int32_t* row_idx, int32_t* deg);
 
 // ---------------------------------------------------------------- FP64 query context
+constexpr int64_t kAuxLen = 4 * 1024 + 16;
+
 struct QueryCtx {
     hipStream_t stream = nullptr;
     int32_t n = 0;
@@ -166,6 +168,7 @@ struct QueryCtx {
     DevBuf scan_tmp;   // scan scratch
     DevBuf ctr;        // int64[8] counters: [0] |F'|, [1] vol(F'), [2..] spare
     DevBuf dsum;       // double[8]: [0] reduced sum
+    DevBuf aux;        // int64[kAuxLen]: per-block counts and their scans (frontier compaction)
     PinnedBuf host;    // 64 bytes readback
     hipGraphExec_t chunk_exec = nullptr;   // captured FOLD sweep pairs
     int chunk_pairs = 0;
@@ -251,7 +254,7 @@ void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_
 constexpr int32_t kMaxWalkSteps = 4096;
 double walk_budget(int32_t n, double eps, double mu);
 void run_approx_query(Graph& g, int32_t s, double alpha, double eps, double mu, uint64_t seed, bool use_index,
-                      double* pi_out, ppr_approx_stats* st);
+                      const ppr_options& opt, double* pi_out, ppr_approx_stats* st);
 void build_walk_index(Graph& g, double alpha, uint64_t seed, double* ms);
 void copy_walk_index(const Graph& g, int32_t* out);
 void debug_refine(Graph& g, double alpha, double rmax, double* pi, double* r, int32_t* levels, int64_t* edges);

@@ -38,7 +38,8 @@ std::unique_ptr<QueryCtx> ctx_acquire(Graph& g) {
     const Schedule& sch = g.schedule(k::sweep_nnz_cap(), k::sweep_row_cap());
     size_t parts = std::max<size_t>({(size_t)sch.n_blocks, 4096, (n + 255) / 256});
     c->partials.alloc(8 * parts);
-    c->scan_tmp.alloc(k::scan_tmp_bytes(g.n));
+    c->scan_tmp.alloc(k::scan_tmp_bytes(std::max<int64_t>(g.n, 4096)));
+    c->aux.alloc(8 * (size_t)kAuxLen);
     c->ctr.alloc(64);
     c->dsum.alloc(64);
     c->host.alloc(64);
