@@ -60,8 +60,9 @@ typedef enum {
 
 typedef enum {
     PPR_FP64 = 0,    /* plain path: residues, reserves and sums in double precision */
-    PPR_MIXED = 1    /* FP32 residues, compensated FP32 (hi, lo) reserves; FP64 r_sum,
-                        FP64 residual refresh and FP64 final flush */
+    PPR_MIXED = 1    /* FP32 arithmetic on FP32 or bf16 residues with an FP32 stage
+                        accumulator; FP64 reserves; every stage ends with an FP64
+                        residual refresh that certifies the result */
 } ppr_precision;
 
 /* Storage of the batched path's residue block (arithmetic is FP32 either way). */
@@ -69,7 +70,7 @@ typedef enum {
     PPR_RESIDUE_F32 = 0,   /* 4 bytes per residue */
     PPR_RESIDUE_BF16 = 1,  /* 2 bytes: half the bytes each sweep gathers; the rounding a
                               stored residue takes is residual that the next FP64 refresh
-                              measures, so stages are shorter (refresh factor 50).  Blocks
+                              measures, so stages are shorter (refresh factor 40).  Blocks
                               of at least 8 columns (a sweep lane holds 8) */
     PPR_RESIDUE_AUTO = 2   /* bf16 for blocks of at least 32 columns, else FP32 (default) */
 } ppr_residue_format;
@@ -123,7 +124,7 @@ typedef struct {
     int32_t certify;        /* PPR_FP64: also compute cert_l1; default 0 */
     double refresh_factor;  /* PPR_MIXED: refresh the residual in FP64 whenever r_sum has
                                fallen by this factor since the last refresh; 0 = chosen by
-                               the residue format (1e4 for FP32, 50 for bf16; default) */
+                               the residue format (1e3 for FP32, 40 for bf16; default) */
     int32_t batch_cols;     /* PPR_MIXED batched: columns per block (multiple of 4, or 0 =
                                autotuned); default 0 */
     int32_t sweep_chunks;   /* PPR_MIXED: row chunks per global sweep.  1 = every sweep is

@@ -103,7 +103,7 @@ size_t mixed_footprint(const Graph& g, int Bw, int64_t fcap, bool bf16) {
     const size_t piece_cap = (size_t)mk::kLongRounds * mk::kLdsBytes / (4 * (size_t)Bw);
     const size_t pieces = 2 * (size_t)g.m / piece_cap + 1;
     return 16 * nb                       // FP64 local-phase scratch
-           + (bf16 ? 16 : 20) * nb       // Y0, Y1 (4 or 2 bytes), Shi, Slo, T
+           + (bf16 ? 24 : 28) * nb       // Y0, Y1 (4 or 2 bytes), S, AS (8), T (4)
            + 4 * (size_t)Bw * pieces     // partial sums of the pieces
            + 40 * (size_t)fcap + 4 * (size_t)g.n + ((size_t)1 << 20);
 }
@@ -139,10 +139,10 @@ MixedCtxPtr mixed_acquire(Graph& g, int Bw, int64_t fcap, bool bf16) {
     c->scan_tmp.alloc(k::scan_tmp_bytes(fcap));
     c->Y0.alloc((bf16 ? 2 : 4) * nb);
     c->Y1.alloc((bf16 ? 2 : 4) * nb);
-    c->Shi.alloc(4 * nb);
-    c->Slo.alloc(4 * nb);
+    c->S.alloc(8 * nb);
+    c->AS.alloc(8 * nb);
     c->T.alloc(4 * nb);
-    for (DevBuf* b : {&c->Y0, &c->Y1, &c->Shi, &c->Slo, &c->T}) HIPCHECK(hipMemsetAsync(b->p, 0, b->bytes, c->stream));
+    for (DevBuf* b : {&c->Y0, &c->Y1, &c->S, &c->AS, &c->T}) HIPCHECK(hipMemsetAsync(b->p, 0, b->bytes, c->stream));
     c->scale.alloc(4 * n);
     c->partials.alloc(8 * (size_t)mk::kGridRed * Bw);
     c->colsum.alloc(8 * (size_t)Bw);
@@ -214,11 +214,13 @@ struct Block {
 
     Block(Graph& gg, int width, double a, const ppr_options& o) : g(gg), Bw(width), alpha(a), opt(o) {
         // a bf16 residue carries ~2^-9 relative rounding per push, so a stage
-        // stalls near 1e-2 of the residual it started from (1e-6 with FP32);
-        // 50 was the fastest factor on the 4M/70M graph (35: 541, 50: 584,
-        // 70: 567, 100: 545 queries/s at B = 128)
+        // stalls near 1e-2 of the residual it started from (1e-6 with FP32,
+        // where the first stage also carries the local phase's reserve in the
+        // FP32 accumulator).  Fastest factors on the 4M/70M graph at B = 128:
+        // bf16 30 / 40 / 50 / 70: 606 / 660 / 635 / 612 queries/s; FP32
+        // 300 / 1e3 / 2e3 / 1e4: 463 / 491 / 468 / 415
         refresh_factor = opt.refresh_factor > 0.0 ? opt.refresh_factor
-                                                  : (residues_bf16(opt, Bw) ? 50.0 : 1e4);
+                                                  : (residues_bf16(opt, Bw) ? 40.0 : 1e3);
         if (Bw < 4 || Bw > 128 || (Bw & (Bw - 1))) fail(PPR_ERR_ARG, "block width must be a power of two in [4, 128]");
         if (opt.residue_format == PPR_RESIDUE_BF16 && Bw < 8)
             fail(PPR_ERR_ARG, "bf16 residues need a block of at least 8 columns");

@@ -20,13 +20,13 @@ struct Sw {
     static constexpr int kItems = kNnz * C / kBlock;   // = 4
     static constexpr int kSlots = kBlock / C;
 };
-// Refresh blocks gather the hi and lo reserve rows (2 x 16 C bytes per edge)
-// through a 32 KB stage per round.
+// Refresh blocks gather the in-neighbours' stage accumulator rows (16 C bytes
+// per edge) through a 32 KB stage per round.
 constexpr int kRfLdsBytes = 32768;
 template <int C>
 struct Rf {
-    static constexpr int kNnz = kRfLdsBytes / (32 * C);
-    static constexpr int kItems = kNnz * C / kBlock;   // = 4
+    static constexpr int kNnz = kRfLdsBytes / (16 * C);
+    static constexpr int kItems = kNnz * C / kBlock;   // = 8
     static constexpr int kRows = kBlock / C;
 };
 }  // namespace mk
@@ -43,7 +43,8 @@ struct MixedCtx {
     DevBuf F0, F1, X, degF, off;      // frontier (int64 keys), increments, degrees, prefix
     DevBuf scan_tmp;
     DevBuf Y0, Y1;                    // [n][Bw] FP32 or bf16: residue still to push, y = (1-alpha) r / d
-    DevBuf Shi, Slo;                  // float[n][Bw]   compensated reserve (y domain)
+    DevBuf S;                         // double[n][Bw]  reserve (y domain)
+    DevBuf AS;                        // double[n][Bw]  sum of S over each node's in-neighbours
     DevBuf T;                         // float[n][Bw]   per-stage reserve accumulator
     DevBuf scale;                     // float[n]       (1-alpha) / d_u
     DevBuf partials;                  // double[kGridRed][Bw]

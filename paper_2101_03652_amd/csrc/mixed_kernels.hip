@@ -9,10 +9,10 @@
 //                   out-neighbours pull and what T accumulates, so the storage
 //                   rounding only leaves residual that the next FP64 refresh
 //                   measures
-//   Shi, Slo[n][B]  FP32 pair, S = Shi + Slo kept with TwoSum (Knuth): the
-//                   compensated reserve in the y domain, pi_hat(u) = alpha d_u S(u) / (1 - alpha)
+//   S[n][B]         FP64 reserve in the y domain: pi_hat(u) = alpha d_u S(u) / (1 - alpha)
+//   AS[n][B]        FP64 running sum_{v in N_in(u)} S(v), kept up to date by each refresh
 //   T[n][B]         FP32 per-stage accumulator of reserve increments
-//
+
 // Columns are independent: each one is a query with its own source, its own
 // lambda and its own schedule.
 //  - local phase (FP64): the iteration sets S^(j) of Section 4.2 pushed
@@ -27,12 +27,15 @@
 //    column a budget kb[b]: the column runs sweeps while step < kb[b], then
 //    gets y' = 0 (its pending residue is dropped: the next refresh recomputes
 //    the exact residual from S) and its reserve stops changing;
-//  - refresh (FP64): S += T, then from S alone the exact residual of the
-//    current estimate (Eq. 1 rearranged)
-//        rt(u) = e_s(u) - d_u S(u) / (1 - alpha) + sum_{v in N_in(u)} S(v),
-//    whose l1 norm certifies ||pi_hat - pi_s||_1 <= ||rt||_1; for the columns
-//    being refreshed y~ = (1-alpha) rt / d replaces the drifting FP32 residue,
-//    and the first sweep after that folds its alpha-part into T (entry flag).
+//  - refresh (FP64): the exact residual of the estimate S + T (Eq. 1
+//    rearranged)
+//        rt(u) = e_s(u) - d_u S'(u) / (1 - alpha) + sum_{v in N_in(u)} S'(v),
+//    S' = S + T, whose l1 norm certifies ||pi_hat - pi_s||_1 <= ||rt||_1.  The
+//    in-neighbour sum is AS(u) + sum_{v in N_in(u)} T(v): only the FP32 stage
+//    accumulator is gathered (exactly, in FP64), not the whole reserve.  For
+//    the columns being refreshed AS takes the new sum, y~ = (1-alpha) rt / d
+//    replaces the drifting residue, and a flush then moves T into S; the
+//    first sweep after that folds y~'s alpha-part into T (entry flag).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -45,30 +48,6 @@ namespace mk {
 namespace {
 
 // ---------------------------------------------------------------- helpers
-// Knuth's TwoSum: s + e == a + b exactly.
-__device__ inline void two_sum(float a, float b, float& s, float& e) {
-    s = a + b;
-    float bp = s - a;
-    float ap = s - bp;
-    e = (a - ap) + (b - bp);
-}
-
-// (hi, lo) += y, compensated: the rounding error of hi + y is carried in lo
-// and the pair is renormalised (Fast2Sum) so that |lo| <= ulp(hi) / 2.
-__device__ inline void comp_add(float& hi, float& lo, float y) {
-    float s, e;
-    two_sum(hi, y, s, e);
-    float t = lo + e;
-    float h = s + t;
-    lo = t - (h - s);
-    hi = h;
-}
-
-__device__ inline void split_double(double x, float& hi, float& lo) {
-    hi = (float)x;
-    lo = (float)(x - (double)hi);
-}
-
 __device__ inline float4 f4_add(float4 a, float4 b) { return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w); }
 __device__ inline float4 f4_mul(float4 a, float4 m) { return make_float4(a.x * m.x, a.y * m.y, a.z * m.z, a.w * m.w); }
 __device__ inline float4 f4_shfl_xor(float4 a, int o) {
@@ -252,15 +231,17 @@ __global__ __launch_bounds__(kBlock) void push_k(
     }
 }
 
-// FP64 scratch -> FP32 block for the columns with cmask = 1, dense over
-// (u, b): y = (1-alpha) r / d, S = (1-alpha) pi / (alpha d), T = 0; the
-// scratch of those columns is cleared.  The residue is fresh (nobody has
+// FP64 scratch -> block for the columns with cmask = 1, dense over (u, b):
+// y = (1-alpha) r / d; the local phase's reserve (1-alpha) pi / (alpha d)
+// enters through the stage accumulator T (FP32), with S = AS = 0, so that the
+// first refresh gathers it like any stage's increments (its FP32 rounding is
+// residual that refresh measures); the scratch of those columns is cleared.  The residue is fresh (nobody has
 // pulled it), so the first sweep of the column runs with its entry flag:
 // it folds the alpha-part into T and pulls y along every in-edge.
 // partials[block][B]: per-column sums of r.
 __global__ void convert_k(int32_t n, int shift, const int32_t* __restrict__ deg, double alpha,
                           const int32_t* __restrict__ cmask, double* __restrict__ r64, double* __restrict__ pi64,
-                          void* __restrict__ Y, int y_bf16, float* __restrict__ Shi, float* __restrict__ Slo,
+                          void* __restrict__ Y, int y_bf16, double* __restrict__ S, double* __restrict__ AS,
                           float* __restrict__ T, double* __restrict__ partials) {
     __shared__ double sh[kBlock];
     __shared__ int32_t cm[128];
@@ -278,16 +259,13 @@ __global__ void convert_k(int32_t n, int shift, const int32_t* __restrict__ deg,
             int32_t u = (int32_t)(i >> shift);
             double d = (double)deg[u];
             double y = ((1.0 - alpha) * r) / d;
-            double S = ((1.0 - alpha) * p) / (alpha * d);
             if (y_bf16)
                 reinterpret_cast<uint16_t*>(Y)[i] = (uint16_t)bf16_bits((float)y);
             else
                 reinterpret_cast<float*>(Y)[i] = (float)y;
-            float h, l;
-            split_double(S, h, l);
-            Shi[i] = h;
-            Slo[i] = l;
-            T[i] = 0.f;
+            S[i] = 0.0;
+            AS[i] = 0.0;
+            T[i] = (float)(((1.0 - alpha) * p) / (alpha * d));
             r64[i] = 0.0;
             pi64[i] = 0.0;
             acc += r;
@@ -515,23 +493,20 @@ __global__ void from_bf16_k(int64_t count, const uint16_t* __restrict__ src, flo
         dst[i] = __uint_as_float((uint32_t)src[i] << 16);
 }
 
-// S += T (compensated), T = 0, dense over n x B.
+// S += T (FP64), T = 0, dense over n x B, after the refresh has gathered T.
 // Only the columns being refreshed (rmask) are flushed: a column's reserve
 // then takes the same roundings whichever other columns share the block and
 // whenever they refresh.  The grid stride is a multiple of the block width,
 // so a thread's column is fixed.
-__global__ void flush_k(int64_t total, int32_t Bw, const int32_t* __restrict__ rmask, float* __restrict__ Shi,
-                        float* __restrict__ Slo, float* __restrict__ T) {
+__global__ void flush_k(int64_t total, int32_t Bw, const int32_t* __restrict__ rmask, double* __restrict__ S,
+                        float* __restrict__ T) {
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (!rmask[i0 & (Bw - 1)]) return;
     for (int64_t i = i0; i < total; i += stride) {
-        float t = T[i];
+        const float t = T[i];
         if (t != 0.f) {
-            float h = Shi[i], l = Slo[i];
-            comp_add(h, l, t);
-            Shi[i] = h;
-            Slo[i] = l;
+            S[i] += (double)t;
             T[i] = 0.f;
         }
     }
@@ -541,22 +516,21 @@ __global__ void flush_k(int64_t total, int32_t Bw, const int32_t* __restrict__ r
 // Persistent grid: block k handles schedule blocks k, k + G, ...  A schedule
 // block is up to Rf<C>::kRows whole rows with <= Rf<C>::kNnz in-edges, or one
 // long row, which the block runs in rounds of Rf<C>::kNnz in-edges.  Per
-// round the hi and lo rows of the in-neighbours are staged in LDS and T2
-// threads per (row, chunk) add them in FP64, then a shuffle tree.  The
-// per-column sums of |rt| are deterministic: after each schedule block the
-// threads c < C add that block's rows in row order into their own
-// accumulators (columns 4c..4c+3), which go to partials[block][B].
+// round the in-neighbours' T rows are staged in LDS and T2 threads per (row,
+// chunk) add them in FP64, then a shuffle tree.  The per-column sums of |rt|
+// are deterministic: after each schedule block the threads c < C add that
+// block's rows in row order into their own accumulators (columns 4c..4c+3),
+// which go to partials[block][B].  S, AS: double[n][B], read as double2 pairs.
 template <typename OffT, int C, typename ST>
 __global__ __launch_bounds__(kBlock) void refresh_k(
         const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
         const RowBlock* __restrict__ blocks, int32_t n_blocks,
-        const int32_t* __restrict__ deg, const float4* __restrict__ Shi, const float4* __restrict__ Slo,
-        const int32_t* __restrict__ src, const int32_t* __restrict__ rmask, double alpha,
+        const int32_t* __restrict__ deg, const float4* __restrict__ T, const double2* __restrict__ S,
+        double2* __restrict__ AS, const int32_t* __restrict__ src, const int32_t* __restrict__ rmask, double alpha,
         typename ST::V* __restrict__ Y, double* __restrict__ rt_out, int32_t n,
         double* __restrict__ partials) {
     using P = Rf<C>;
-    __shared__ float4 lds_h[P::kNnz * C];
-    __shared__ float4 lds_l[P::kNnz * C];
+    __shared__ float4 lds[P::kNnz * C];
     __shared__ double red[kBlock * 4];
     double cs0 = 0.0, cs1 = 0.0, cs2 = 0.0, cs3 = 0.0;   // threads c < C: |rt| of columns 4c..4c+3
     const double inv_oma = 1.0 / (1.0 - alpha);
@@ -588,34 +562,24 @@ __global__ __launch_bounds__(kBlock) void refresh_k(
                 int32_t it = threadIdx.x + k * kBlock;
                 vv[k] = (it / C < nr) ? row_idx[e0 + base + it / C] : -1;
             }
-            float4 hv[P::kItems], lv[P::kItems];
+            float4 tv[P::kItems];
 #pragma unroll
-            for (int k = 0; k < P::kItems; ++k) {
-                const int64_t i = (int64_t)vv[k] * C + (threadIdx.x % C);
-                if (vv[k] >= 0) {
-                    hv[k] = Shi[i];
-                    lv[k] = Slo[i];
-                } else {
-                    hv[k] = lv[k] = make_float4(0.f, 0.f, 0.f, 0.f);
-                }
-            }
+            for (int k = 0; k < P::kItems; ++k)
+                tv[k] = (vv[k] >= 0) ? T[(int64_t)vv[k] * C + (threadIdx.x % C)] : make_float4(0.f, 0.f, 0.f, 0.f);
             __syncthreads();                       // the previous LDS reads are done
 #pragma unroll
             for (int k = 0; k < P::kItems; ++k) {
                 int32_t it = threadIdx.x + k * kBlock;
-                if (it / C < nr) {
-                    lds_h[it] = hv[k];
-                    lds_l[it] = lv[k];
-                }
+                if (it / C < nr) lds[it] = tv[k];
             }
             __syncthreads();
             if (!whole && row == 0) { s0 = 0; s1 = nr; }
             for (int32_t e = s0 + sub; e < s1; e += T2) {
-                float4 h = lds_h[e * C + c], l = lds_l[e * C + c];
-                g0 += (double)h.x + (double)l.x;
-                g1 += (double)h.y + (double)l.y;
-                g2 += (double)h.z + (double)l.z;
-                g3 += (double)h.w + (double)l.w;
+                const float4 t = lds[e * C + c];
+                g0 += (double)t.x;
+                g1 += (double)t.y;
+                g2 += (double)t.z;
+                g3 += (double)t.w;
             }
         }
         for (int o = T2 >> 1; o >= 1; o >>= 1) {
@@ -629,13 +593,21 @@ __global__ __launch_bounds__(kBlock) void refresh_k(
             const int32_t u = r0 + row;
             const int64_t at = (int64_t)u * C + c;
             const double d = (double)deg[u];
-            const float4 h = Shi[at], l = Slo[at];
+            const float4 t = T[at];
+            const double2 sa = S[2 * at], sb = S[2 * at + 1];
+            const double2 aa = AS[2 * at], ab = AS[2 * at + 1];
             const int4 s4 = reinterpret_cast<const int4*>(src)[c];
             const int4 w4 = reinterpret_cast<const int4*>(rmask)[c];
-            t0 = (s4.x == u ? 1.0 : 0.0) - d * ((double)h.x + (double)l.x) * inv_oma + g0;
-            t1 = (s4.y == u ? 1.0 : 0.0) - d * ((double)h.y + (double)l.y) * inv_oma + g1;
-            t2 = (s4.z == u ? 1.0 : 0.0) - d * ((double)h.z + (double)l.z) * inv_oma + g2;
-            t3 = (s4.w == u ? 1.0 : 0.0) - d * ((double)h.w + (double)l.w) * inv_oma + g3;
+            // the in-neighbour sums of S + T
+            const double a0 = aa.x + g0, a1 = aa.y + g1, a2 = ab.x + g2, a3 = ab.y + g3;
+            t0 = (s4.x == u ? 1.0 : 0.0) - d * (sa.x + (double)t.x) * inv_oma + a0;
+            t1 = (s4.y == u ? 1.0 : 0.0) - d * (sa.y + (double)t.y) * inv_oma + a1;
+            t2 = (s4.z == u ? 1.0 : 0.0) - d * (sb.x + (double)t.z) * inv_oma + a2;
+            t3 = (s4.w == u ? 1.0 : 0.0) - d * (sb.y + (double)t.w) * inv_oma + a3;
+            if (w4.x | w4.y | w4.z | w4.w) {     // the refreshed columns keep the new sums
+                AS[2 * at] = make_double2(w4.x ? a0 : aa.x, w4.y ? a1 : aa.y);
+                AS[2 * at + 1] = make_double2(w4.z ? a2 : ab.x, w4.w ? a3 : ab.y);
+            }
             if (w4.x | w4.y | w4.z | w4.w) {     // other columns keep their bits (exact round trip)
                 float4 y = ST::value4(Y[at]);
                 if (w4.x) y.x = (float)(oma * t0 / d);
@@ -678,7 +650,7 @@ __global__ __launch_bounds__(kBlock) void refresh_k(
 }
 
 // ---------------------------------------------------------------- export
-// pi_hat(u, b) = alpha d_u (Shi + Slo) / (1 - alpha) for columns [b0, b0 +
+// pi_hat(u, b) = alpha d_u S / (1 - alpha) for columns [b0, b0 +
 // count), written row-major [count][n] through an LDS transpose of
 // kNodes nodes x B columns.
 template <int C>
@@ -689,8 +661,7 @@ struct Ex {
 template <int C>
 __global__ __launch_bounds__(kBlock) void export_k(int32_t n, int32_t b0, int32_t count,
                                                    const int32_t* __restrict__ deg, double alpha,
-                                                   const float* __restrict__ Shi, const float* __restrict__ Slo,
-                                                   double* __restrict__ out) {
+                                                   const double* __restrict__ S, double* __restrict__ out) {
     constexpr int B = 4 * C;
     constexpr int kNodes = Ex<C>::kNodes;
     __shared__ double tile[kNodes * (B + 1)];
@@ -700,7 +671,7 @@ __global__ __launch_bounds__(kBlock) void export_k(int32_t n, int32_t b0, int32_
         int du = i / B, b = i % B;
         int64_t u = u0 + du;
         double v = 0.0;
-        if (u < n) v = f * (double)deg[u] * ((double)Shi[u * B + b] + (double)Slo[u * B + b]);
+        if (u < n) v = f * (double)deg[u] * S[u * B + b];
         tile[du * (B + 1) + b] = v;
     }
     __syncthreads();
@@ -712,12 +683,12 @@ __global__ __launch_bounds__(kBlock) void export_k(int32_t n, int32_t b0, int32_
 }
 
 __global__ void export_col_k(int32_t n, int shift, int32_t b, const int32_t* __restrict__ deg, double alpha,
-                             const float* __restrict__ Shi, const float* __restrict__ Slo, double* __restrict__ out) {
+                             const double* __restrict__ S, double* __restrict__ out) {
     const double f = alpha / (1.0 - alpha);
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
         int64_t i = (u << shift) + b;
-        out[u] = f * (double)deg[u] * ((double)Shi[i] + (double)Slo[i]);
+        out[u] = f * (double)deg[u] * S[i];
     }
 }
 
@@ -786,23 +757,25 @@ void sweep_c(MixedCtx& c, Graph& g, const void* yin, void* yout) {
 
 template <int C, typename ST>
 void refresh_launch(MixedCtx& c, Graph& g, void* y, double* rt_out) {
-    hipLaunchKernelGGL(flush_k, dim3(2048), dim3(kBlock), 0, c.stream, (int64_t)g.n * c.Bw, c.Bw,
-                       c.rmask.as<int32_t>(), c.Shi.as<float>(), c.Slo.as<float>(), c.T.as<float>());
     const Schedule& sch = refresh_schedule<C>(g);
     dim3 grid((unsigned)std::min(sch.n_blocks, kGridRed)), blk(kBlock);
-    auto H = c.Shi.as<float4>();
-    auto L = c.Slo.as<float4>();
+    auto T4 = c.T.as<float4>();
+    auto S2 = c.S.as<double2>();
+    auto A2 = c.AS.as<double2>();
     auto Y4 = reinterpret_cast<typename ST::V*>(y);
     if (g.off64)
         hipLaunchKernelGGL((refresh_k<int64_t, C, ST>), grid, blk, 0, c.stream, g.col_ptr.as<int64_t>(),
                            g.row_idx.as<int32_t>(), sch.blocks.as<RowBlock>(), sch.n_blocks,
-                           g.deg.as<int32_t>(), H, L, c.src.as<int32_t>(), c.rmask.as<int32_t>(), c.alpha, Y4,
+                           g.deg.as<int32_t>(), T4, S2, A2, c.src.as<int32_t>(), c.rmask.as<int32_t>(), c.alpha, Y4,
                            rt_out, g.n, c.partials.as<double>());
     else
         hipLaunchKernelGGL((refresh_k<uint32_t, C, ST>), grid, blk, 0, c.stream, g.col_ptr.as<uint32_t>(),
                            g.row_idx.as<int32_t>(), sch.blocks.as<RowBlock>(), sch.n_blocks,
-                           g.deg.as<int32_t>(), H, L, c.src.as<int32_t>(), c.rmask.as<int32_t>(), c.alpha, Y4,
+                           g.deg.as<int32_t>(), T4, S2, A2, c.src.as<int32_t>(), c.rmask.as<int32_t>(), c.alpha, Y4,
                            rt_out, g.n, c.partials.as<double>());
+    // every row has gathered T: now the refreshed columns move it into S
+    hipLaunchKernelGGL(flush_k, dim3(2048), dim3(kBlock), 0, c.stream, (int64_t)g.n * c.Bw, c.Bw,
+                       c.rmask.as<int32_t>(), c.S.as<double>(), c.T.as<float>());
     hipLaunchKernelGGL(reduce_cols_k, dim3(1), dim3(256), 0, c.stream, c.partials.as<double>(), (int)grid.x, c.Bw,
                        c.colsum.as<double>());
     HIPCHECK(hipGetLastError());
@@ -819,7 +792,7 @@ void export_c(MixedCtx& c, Graph& g, int b0, int count, double* out) {
     constexpr int kNodes = Ex<C>::kNodes;
     unsigned grid = (unsigned)((g.n + kNodes - 1) / kNodes);
     hipLaunchKernelGGL((export_k<C>), dim3(grid), dim3(kBlock), 0, c.stream, g.n, b0, count, g.deg.as<int32_t>(),
-                       c.alpha, c.Shi.as<float>(), c.Slo.as<float>(), out);
+                       c.alpha, c.S.as<double>(), out);
     HIPCHECK(hipGetLastError());
 }
 
@@ -873,7 +846,7 @@ void convert(MixedCtx& c, const Graph& g, double alpha) {
     const unsigned gc = 1024;
     hipLaunchKernelGGL(convert_k, dim3(gc), dim3(kBlock), 0, c.stream, g.n, c.shift, g.deg.as<int32_t>(), alpha,
                        c.cmask.as<int32_t>(), c.r64.as<double>(), c.pi64.as<double>(),
-                       const_cast<void*>(c.ycur), c.bf16 ? 1 : 0, c.Shi.as<float>(), c.Slo.as<float>(),
+                       const_cast<void*>(c.ycur), c.bf16 ? 1 : 0, c.S.as<double>(), c.AS.as<double>(),
                        c.T.as<float>(), c.partials.as<double>());
     hipLaunchKernelGGL(reduce_cols_k, dim3(1), dim3(256), 0, c.stream, c.partials.as<double>(), (int)gc, c.Bw,
                        c.colsum.as<double>());
@@ -937,7 +910,7 @@ void export_cols(MixedCtx& c, const Graph& g, int b0, int count, double* out) {
 
 void export_col(MixedCtx& c, const Graph& g, int b, double* out) {
     hipLaunchKernelGGL(export_col_k, dim3(2048), dim3(kBlock), 0, c.stream, g.n, c.shift, b, g.deg.as<int32_t>(),
-                       c.alpha, c.Shi.as<float>(), c.Slo.as<float>(), out);
+                       c.alpha, c.S.as<double>(), out);
     HIPCHECK(hipGetLastError());
 }
 
