@@ -266,8 +266,8 @@ __global__ void convert_k(int32_t n, int shift, const int32_t* __restrict__ deg,
             S[i] = 0.0;
             AS[i] = 0.0;
             T[i] = (float)(((1.0 - alpha) * p) / (alpha * d));
-            r64[i] = 0.0;
-            pi64[i] = 0.0;
+            if (r != 0.0) r64[i] = 0.0;        // the scratch is mostly zero already
+            if (p != 0.0) pi64[i] = 0.0;
             acc += r;
         }
     }
@@ -280,12 +280,21 @@ __global__ void convert_k(int32_t n, int shift, const int32_t* __restrict__ deg,
     }
 }
 
-__global__ void reduce_cols_k(const double* __restrict__ partials, int nparts, int B, double* __restrict__ out) {
-    int b = blockIdx.x * blockDim.x + threadIdx.x;      // one thread per column, fixed order
-    if (b >= B) return;
+// One block per column: thread t adds partials t, t + 256, ... in order, then
+// a fixed tree over the 256 thread sums (deterministic).
+__global__ __launch_bounds__(kBlock) void reduce_cols_k(const double* __restrict__ partials, int nparts, int B,
+                                                        double* __restrict__ out) {
+    __shared__ double sh[kBlock];
+    const int b = blockIdx.x;
     double t = 0.0;
-    for (int i = 0; i < nparts; ++i) t += partials[(int64_t)i * B + b];
-    out[b] = t;
+    for (int i = threadIdx.x; i < nparts; i += kBlock) t += partials[(int64_t)i * B + b];
+    sh[threadIdx.x] = t;
+    __syncthreads();
+    for (int s = kBlock / 2; s >= 1; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[b] = sh[0];
 }
 
 __global__ void scale_k(const int32_t* __restrict__ deg, int32_t n, double alpha, float* __restrict__ scale) {
@@ -776,7 +785,7 @@ void refresh_launch(MixedCtx& c, Graph& g, void* y, double* rt_out) {
     // every row has gathered T: now the refreshed columns move it into S
     hipLaunchKernelGGL(flush_k, dim3(2048), dim3(kBlock), 0, c.stream, (int64_t)g.n * c.Bw, c.Bw,
                        c.rmask.as<int32_t>(), c.S.as<double>(), c.T.as<float>());
-    hipLaunchKernelGGL(reduce_cols_k, dim3(1), dim3(256), 0, c.stream, c.partials.as<double>(), (int)grid.x, c.Bw,
+    hipLaunchKernelGGL(reduce_cols_k, dim3((unsigned)c.Bw), dim3(kBlock), 0, c.stream, c.partials.as<double>(), (int)grid.x, c.Bw,
                        c.colsum.as<double>());
     HIPCHECK(hipGetLastError());
 }
@@ -848,7 +857,7 @@ void convert(MixedCtx& c, const Graph& g, double alpha) {
                        c.cmask.as<int32_t>(), c.r64.as<double>(), c.pi64.as<double>(),
                        const_cast<void*>(c.ycur), c.bf16 ? 1 : 0, c.S.as<double>(), c.AS.as<double>(),
                        c.T.as<float>(), c.partials.as<double>());
-    hipLaunchKernelGGL(reduce_cols_k, dim3(1), dim3(256), 0, c.stream, c.partials.as<double>(), (int)gc, c.Bw,
+    hipLaunchKernelGGL(reduce_cols_k, dim3((unsigned)c.Bw), dim3(kBlock), 0, c.stream, c.partials.as<double>(), (int)gc, c.Bw,
                        c.colsum.as<double>());
     HIPCHECK(hipGetLastError());
 }
