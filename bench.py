@@ -32,13 +32,15 @@ HBM_PEAK_GBS = 8000.0
 
 
 def sweep_bytes(n: int, m: int, width: int, over_relaxed: bool = False, residue_bytes: int = 4) -> int:
-    """Algorithmic bytes of one batched global sweep (all its row chunks):
-    in-edge indices (4 m), per-node CSC offset and FP32 scale (8 n), and per
-    (node, column): the residue row read once and the new residue written
-    (residue_bytes each: 4 in FP32, 2 in bf16), the FP32 per-stage reserve
-    accumulator read and written (8); over-relaxed sweeps also read the row's
-    previous push (residue_bytes more)."""
-    per = 2 * residue_bytes + 8 + (residue_bytes if over_relaxed else 0)
+    """Algorithmic bytes of one batched global sweep (all its row chunks),
+    averaged over a pair of sweeps: in-edge indices (4 m), per-node CSC offset
+    and FP32 scale (8 n), and per (node, column): the residue row read once
+    and the new residue written (residue_bytes each: 4 in FP32, 2 in bf16),
+    the FP32 per-stage reserve accumulator read and written by every second
+    sweep (4 on average), which also reads the row's own input residue; an
+    over-relaxed sweep reads that residue every time (its previous push)."""
+    own = residue_bytes if over_relaxed else residue_bytes // 2
+    per = 2 * residue_bytes + 4 + own
     return 4 * m + 8 * n + per * n * width
 
 

@@ -365,6 +365,36 @@ ppr_status ppr_debug_sweep_mixed(ppr_graph* g, double alpha, int32_t B, int32_t 
                                  float* t_out, const float* omega, int32_t residue_format);
 
 /*
+ * Test entry point: one launch sequence of `sweeps` consecutive batched
+ * global sweeps, each the sweep of ppr_debug_sweep_mixed (Algorithm 3's
+ * global phase, Section 4.1, in block Gauss-Seidel order), with the stage
+ * accumulator carried through the sequence as a query carries it between
+ * refreshes.  ppr_debug_sweep_mixed is this with sweeps = 1, every budget 1
+ * and T starting at 0.  Over-relaxed sweeps derive what a row kept back
+ * from its previous push, so only the first sweep of a fresh column starts
+ * from nothing kept.
+ *   sweeps: in [1, 64].
+ *   entry: host int32[B]: 0 the column continues (its y_in is already in
+ *     T), 1 its y_in is a fresh residue (the first sweep adds it to T and
+ *     its rows pull it along every in-edge), 2 the same with T restarting
+ *     from y_in (t_in ignored for the column: a refresh has moved it into
+ *     the reserve).
+ *   budget: host int32[B] in [0, sweeps] (NULL: all `sweeps`): the sweeps
+ *     the column runs; after them it stores 0 and its T stops growing.
+ *   t_in: float[n][B], host or device, the accumulator at the start (NULL:
+ *     0).  y_out: the residue after the last sweep; t_out (nullable): the
+ *     accumulator after the sequence, i.e. t_in (unless entry 2), plus y_in
+ *     for entry columns with a budget of at least one sweep, plus every
+ *     residue the column's sweeps stored.
+ *   Other arguments as ppr_debug_sweep_mixed; PPR_ERR_ARG for values out of
+ *   range.
+ */
+ppr_status ppr_debug_sweeps_mixed(ppr_graph* g, double alpha, int32_t B, int32_t chunks, int32_t sweeps,
+                                  const float* y_in, const int32_t* entry, const int32_t* budget,
+                                  const float* t_in, float* y_out, float* t_out, const float* omega,
+                                  int32_t residue_format);
+
+/*
  * Autotuner of the batched path: for each candidate block width (a power of
  * two in [4, 128]; widths NULL = {8, 16, 32, 64, 128}) whose state fits half
  * of the free device memory, time a few global sweeps on this graph with

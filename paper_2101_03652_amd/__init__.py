@@ -43,6 +43,7 @@ EXPORTS = [
     "ppr_block_create", "ppr_block_destroy", "ppr_block_footprint", "ppr_slot_admit",
     "ppr_block_step", "ppr_block_poll", "ppr_slot_retire", "ppr_debug_sweep_mixed", "ppr_query_trace",
     "ppr_query_approx", "ppr_walk_index_build", "ppr_walk_index_copy", "ppr_debug_refine", "ppr_debug_walks",
+    "ppr_debug_sweeps_mixed",
 ]
 
 
@@ -132,6 +133,7 @@ def load() -> ctypes.CDLL:
         "ppr_debug_sweep_fp64": (st, [vp, f64, vp, vp, vp, vp]),
         "ppr_autotune": (st, [vp, f64, vp, i32, vp, vp]),
         "ppr_debug_sweep_mixed": (st, [vp, f64, i32, i32, vp, vp, vp, vp, vp, i32]),
+        "ppr_debug_sweeps_mixed": (st, [vp, f64, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, i32]),
         "ppr_block_create": (st, [vp, i32, f64, vp, ctypes.POINTER(vp)]),
         "ppr_block_destroy": (st, [vp]),
         "ppr_block_footprint": (st, [vp, i32, vp]),
@@ -410,6 +412,35 @@ def debug_sweep_mixed(graph: "Graph", alpha: float, y_in, fresh, chunks: int = 1
     _check(load().ppr_debug_sweep_mixed(graph.handle, float(alpha), B, int(chunks), _ptr(y_in), _ptr(fr),
                                         _ptr(y_out), _ptr(t_out) if t_out is not None else None,
                                         _ptr(om) if om is not None else None, int(residue_format)))
+    return y_out
+
+
+def debug_sweeps_mixed(graph: "Graph", alpha: float, y_in, entry, sweeps: int, budget=None, t_in=None,
+                       chunks: int = 1, t_out=None, omega=None, residue_format: int = RESIDUE_F32):
+    """One launch sequence of `sweeps` batched global sweeps carrying the
+    stage accumulator.  entry: B flags (0 continuing, 1 fresh, 2 fresh with
+    the accumulator restarting); budget: B sweep counts in [0, sweeps] (None:
+    all); t_in: float32[n, B] initial accumulator (None: 0).  Returns y_out
+    (same kind as y_in); t_out, if given, receives the accumulator."""
+    B = int(y_in.shape[1])
+    en = np.ascontiguousarray(np.asarray(entry, dtype=np.int32).reshape(-1))
+    if len(en) != B:
+        raise ValueError("entry needs one flag per column")
+    kb = None if budget is None else np.ascontiguousarray(np.asarray(budget, dtype=np.int32).reshape(-1))
+    if kb is not None and len(kb) != B:
+        raise ValueError("budget needs one count per column")
+    if isinstance(y_in, np.ndarray):
+        y_out = np.empty_like(y_in)
+    else:
+        y_out = y_in.new_empty(y_in.shape)
+    om = None if omega is None else np.ascontiguousarray(np.asarray(omega, dtype=np.float32).reshape(-1))
+    if om is not None and len(om) != B:
+        raise ValueError("omega needs one factor per column")
+    _check(load().ppr_debug_sweeps_mixed(graph.handle, float(alpha), B, int(chunks), int(sweeps), _ptr(y_in),
+                                         _ptr(en), _ptr(kb) if kb is not None else None,
+                                         _ptr(t_in) if t_in is not None else None, _ptr(y_out),
+                                         _ptr(t_out) if t_out is not None else None,
+                                         _ptr(om) if om is not None else None, int(residue_format)))
     return y_out
 
 

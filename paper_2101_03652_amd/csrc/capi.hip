@@ -220,23 +220,42 @@ ppr_status ppr_autotune(ppr_graph* gh, double alpha, const int32_t* widths, int3
 ppr_status ppr_debug_sweep_mixed(ppr_graph* gh, double alpha, int32_t B, int32_t chunks, const float* y_in,
                                  const int32_t* fresh, float* y_out, float* t_out, const float* omega,
                                  int32_t residue_format) {
+    if (!fresh || B < 4 || B > 128) return ppr_debug_sweeps_mixed(gh, alpha, B, chunks, 1, y_in, fresh, nullptr,
+                                                                  nullptr, y_out, t_out, omega, residue_format);
+    std::vector<int32_t> en(B);
+    for (int32_t b = 0; b < B; ++b) en[b] = fresh[b] ? 1 : 0;
+    return ppr_debug_sweeps_mixed(gh, alpha, B, chunks, 1, y_in, en.data(), nullptr, nullptr, y_out, t_out, omega,
+                                  residue_format);
+}
+
+ppr_status ppr_debug_sweeps_mixed(ppr_graph* gh, double alpha, int32_t B, int32_t chunks, int32_t sweeps,
+                                  const float* y_in, const int32_t* entry, const int32_t* budget,
+                                  const float* t_in, float* y_out, float* t_out, const float* omega,
+                                  int32_t residue_format) {
     return guarded([&] {
         Graph* g = reinterpret_cast<Graph*>(gh);
-        if (!g || !y_in || !fresh || !y_out) fail(PPR_ERR_ARG, "NULL argument");
+        if (!g || !y_in || !entry || !y_out) fail(PPR_ERR_ARG, "NULL argument");
         if (!(alpha > 0.0 && alpha < 1.0)) fail(PPR_ERR_ARG, "alpha must lie in (0, 1)");
         if (B < 4 || B > 128 || (B & (B - 1))) fail(PPR_ERR_ARG, "B must be a power of two in [4, 128]");
         if (chunks < 1 || chunks > 64) fail(PPR_ERR_ARG, "chunks must lie in [1, 64]");
+        if (sweeps < 1 || sweeps > 64) fail(PPR_ERR_ARG, "sweeps must lie in [1, 64]");
+        for (int32_t b = 0; b < B; ++b) {
+            if (entry[b] < 0 || entry[b] > 2) fail(PPR_ERR_ARG, "entry flags must be 0, 1 or 2");
+            if (budget && (budget[b] < 0 || budget[b] > sweeps)) fail(PPR_ERR_ARG, "budgets must lie in [0, sweeps]");
+        }
         HIPCHECK(hipSetDevice(g->device));
         (void)is_device_ptr(y_in, g->device);              // rejects another device's memory
         (void)is_device_ptr(y_out, g->device);
         if (t_out) (void)is_device_ptr(t_out, g->device);
+        if (t_in) (void)is_device_ptr(t_in, g->device);
         if (omega)
             for (int32_t b = 0; b < B; ++b)
                 if (!(omega[b] > 0.0f && omega[b] < 2.0f)) fail(PPR_ERR_ARG, "omega must lie in (0, 2)");
         if (residue_format != PPR_RESIDUE_F32 && residue_format != PPR_RESIDUE_BF16 &&
             residue_format != PPR_RESIDUE_AUTO)
             fail(PPR_ERR_ARG, "unknown residue format");
-        debug_sweep_mixed(*g, alpha, B, chunks, y_in, fresh, y_out, t_out, omega, residue_format);
+        debug_sweeps_mixed(*g, alpha, B, chunks, sweeps, y_in, entry, budget, t_in, y_out, t_out, omega,
+                           residue_format);
     });
 }
 

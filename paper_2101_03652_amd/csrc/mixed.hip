@@ -184,6 +184,7 @@ struct Block {
         int32_t stage_left = 0;      // sweeps left in the current stage
         bool entry = false;          // the residue is fresh: the next sweep folds its alpha-part
                                      // and pulls it along every in-edge
+        bool t_moved = false;        // the last refresh moved T into S: the entry sweep restarts T
         bool refreshing = false;     // in the refresh whose result is in flight
         bool failed = false;         // reached max_sweeps with a certificate above lambda
         double cert = -1.0;
@@ -327,6 +328,13 @@ struct Block {
         HIPCHECK(hipMemcpyAsync(d.p, h.data(), 4 * (size_t)Bw, hipMemcpyHostToDevice, c->stream));
     }
 
+    // A launch sequence starts at step 0; its step `last` adds its output to T
+    // whatever the step's parity.
+    void set_steps(int32_t last) {
+        const int32_t h[2] = {0, last};
+        HIPCHECK(hipMemcpyAsync(c->step.p, h, sizeof(h), hipMemcpyHostToDevice, c->stream));
+    }
+
     // Local phase (FP64) of every PENDING slot, all in one frontier list, and
     // the conversion of those columns into the block.
     void run_local_phase() {
@@ -415,6 +423,7 @@ struct Block {
             sl.state = RUNNING;
             sl.err = (1.0 - alpha) * hcol[b];
             sl.entry = true;
+            sl.t_moved = false;          // T holds the local phase's reserve
             const double w = opt.sor_omega == 0.0 ? kAutoOmega : opt.sor_omega;
             sl.omega = (c->chunks > 1 && w > 1.0) ? w : 1.0;
             sl.rho = first_rate(sl);
@@ -510,7 +519,7 @@ struct Block {
                 Slot& sl = slots[b];
                 if (sl.state != RUNNING) continue;
                 hkb[b] = std::min(std::min(sl.stage_left, sweeps_left(sl)), K);
-                hen[b] = (sl.entry && hkb[b] > 0) ? 1 : 0;
+                hen[b] = (sl.entry && hkb[b] > 0) ? (sl.t_moved ? 2 : 1) : 0;
             }
             upload_i32(c->kb, hkb);
             upload_i32(c->entry, hen);
@@ -524,7 +533,7 @@ struct Block {
                 }
             if (any_sor) HIPCHECK(hipMemcpyAsync(c->omega.p, hom.data(), 4 * (size_t)Bw, hipMemcpyHostToDevice, ss));
             c->sor = any_sor;
-            HIPCHECK(hipMemsetAsync(c->step.p, 0, 4, ss));
+            set_steps(K - 1);
             ev_sweep.start(ss);
             int rest = K;
             while (rest > 0) {
@@ -549,7 +558,10 @@ struct Block {
                 sl.stage_sweeps += hkb[b];
                 sl.stage_left -= hkb[b];
                 sl.err *= std::pow(sl.rho, hkb[b]);
-                if (hkb[b] > 0) sl.entry = false;
+                if (hkb[b] > 0) {
+                    sl.entry = false;
+                    sl.t_moved = false;
+                }
             }
         }
         // refresh the slots whose stage has ended, and those out of sweeps
@@ -559,7 +571,10 @@ struct Block {
         for (int b = 0; b < Bw; ++b) {
             Slot& sl = slots[b];
             if (sl.state == RUNNING && (sl.stage_left <= 0 || out_of_sweeps(sl))) {
+                // T holds this stage's increments unless a refresh already moved it
+                if (sl.t_moved) fail(PPR_ERR_DEVICE, "internal: refresh of a column without a stage");
                 hr[b] = 1;
+                sl.t_moved = true;
                 sl.refreshing = true;
                 any = true;
             }
@@ -649,6 +664,8 @@ void run_mixed_chunk(Block& blk, const int32_t* sources, int Breal, double lambd
         // FP64 residual of the exported estimates, row-major [Breal][n]
         std::vector<int32_t> none(blk.Bw, 0);
         blk.upload_i32(c.rmask, none);
+        // every column's last refresh moved its T into S
+        HIPCHECK(hipMemsetAsync(c.T.p, 0, c.T.bytes, ss));
         DevBuf rt((size_t)blk.Bw * g.n * 8);
         mk::refresh(c, g, const_cast<void*>(c.ycur), rt.as<double>());
         HIPCHECK(hipMemcpyAsync(r_out, rt.p, 8 * (size_t)Breal * g.n, hipMemcpyDefault, ss));
@@ -738,7 +755,7 @@ void autotune_width(Graph& g, double alpha, const int32_t* widths, int32_t count
         std::vector<int32_t> kb(W, 1 << 30), zero(W, 0);
         blk.upload_i32(c.kb, kb);
         blk.upload_i32(c.entry, zero);
-        HIPCHECK(hipMemsetAsync(c.step.p, 0, 4, ss));
+        blk.set_steps(1 << 30);              // odd and even steps alternate, as in a query
         const int reps = 4;
         mk::sweep(c, g, c.Y0.p, c.Y1.p);     // warm-up
         EventPair ev;
@@ -763,11 +780,11 @@ void autotune_width(Graph& g, double alpha, const int32_t* widths, int32_t count
     if (best) *best = best_w;
 }
 
-// ======================================================================== one sweep (tests)
+// ======================================================================== sweep sequences (tests)
 
-void debug_sweep_mixed(Graph& g, double alpha, int32_t B, int32_t chunks, const float* y_in,
-                       const int32_t* fresh, float* y_out, float* t_out, const float* omega,
-                       int32_t residue_format) {
+void debug_sweeps_mixed(Graph& g, double alpha, int32_t B, int32_t chunks, int32_t sweeps, const float* y_in,
+                        const int32_t* entry, const int32_t* budget, const float* t_in, float* y_out,
+                        float* t_out, const float* omega, int32_t residue_format) {
     HIPCHECK(hipSetDevice(g.device));
     ppr_options opt;
     ppr_options_default(&opt);
@@ -781,18 +798,25 @@ void debug_sweep_mixed(Graph& g, double alpha, int32_t B, int32_t chunks, const 
     DevBuf stage(bytes);                    // FP32 copy of the residue block on the device
     HIPCHECK(hipMemcpyAsync(stage.p, y_in, bytes, hipMemcpyDefault, ss));
     mk::store_from_f32(c, stage.as<float>(), c.Y0.p, count);
-    HIPCHECK(hipMemsetAsync(c.T.p, 0, bytes, ss));
-    std::vector<int32_t> one(B, 1), fr(fresh, fresh + B), zero(B, 0);
-    blk.upload_i32(c.kb, one);
-    blk.upload_i32(c.entry, fr);
-    HIPCHECK(hipMemsetAsync(c.step.p, 0, 4, ss));
+    if (t_in) HIPCHECK(hipMemcpyAsync(c.T.p, t_in, bytes, hipMemcpyDefault, ss));
+    else HIPCHECK(hipMemsetAsync(c.T.p, 0, bytes, ss));
+    std::vector<int32_t> kb(B, sweeps), en(entry, entry + B), zero(B, 0);
+    if (budget) kb.assign(budget, budget + B);
+    blk.upload_i32(c.kb, kb);
+    blk.upload_i32(c.entry, en);
+    blk.set_steps(sweeps - 1);
     if (omega) {
         HIPCHECK(hipMemcpyAsync(c.omega.p, omega, 4 * (size_t)B, hipMemcpyHostToDevice, ss));
         c.sor = true;
     }
-    mk::sweep(c, g, c.Y0.p, c.Y1.p);
+    void* a = c.Y0.p;
+    void* o = c.Y1.p;
+    for (int32_t k = 0; k < sweeps; ++k) {
+        mk::sweep(c, g, a, o);
+        std::swap(a, o);
+    }
     c.sor = false;
-    mk::store_to_f32(c, c.Y1.p, stage.as<float>(), count);
+    mk::store_to_f32(c, a, stage.as<float>(), count);
     HIPCHECK(hipMemcpyAsync(y_out, stage.p, bytes, hipMemcpyDefault, ss));
     if (t_out) HIPCHECK(hipMemcpyAsync(t_out, c.T.p, bytes, hipMemcpyDefault, ss));
     if (omega) {

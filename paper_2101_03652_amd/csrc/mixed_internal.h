@@ -54,11 +54,12 @@ struct MixedCtx {
     DevBuf active;                    // uint8[Bw]  local phase: column pushes this level
     DevBuf src;                       // int32[Bw]  source per column (-1: free)
     DevBuf kb;                        // int32[Bw]  sweeps each column runs in this launch sequence
-    DevBuf entry;                     // int32[Bw]  1: fold the refreshed residue on the first sweep
+    DevBuf entry;                     // int32[Bw]  1: fold the fresh residue into T on the first sweep,
+                                      //            2: the same, restarting T (the refresh moved it into S)
     DevBuf rmask;                     // int32[Bw]  1: refresh writes this column's residue
     DevBuf cmask;                     // int32[Bw]  1: conversion writes this column
     DevBuf rmaxb;                     // double[Bw] lambda_b / m: activity threshold per column
-    DevBuf step;                      // int32[1]   sweeps done in the current sequence
+    DevBuf step;                      // int32[2]   sweeps done in the current sequence, its last step
     DevBuf stage;                     // double[Bw][n] host-output staging (lazy)
     DevBuf piece_part;                // float[pieces][Bw]: partial sums of long-row pieces
     DevBuf omega;                     // float[Bw]      over-relaxation factor per column

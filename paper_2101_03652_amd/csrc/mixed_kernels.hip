@@ -23,7 +23,7 @@
 //    y domain), over row chunks in block Gauss-Seidel order (the rows of a
 //    chunk see the residues earlier chunks produced in the same sweep, as the
 //    in-place scan of Algorithm 3 does); the alpha-part of the new residue
-//    goes into T at once.  Per
+//    goes into T (two sweeps' residues at a time, by the odd step).  Per
 //    column a budget kb[b]: the column runs sweeps while step < kb[b], then
 //    gets y' = 0 (its pending residue is dropped: the next refresh recomputes
 //    the exact residual from S) and its reserve stops changing;
@@ -34,8 +34,8 @@
 //    in-neighbour sum is AS(u) + sum_{v in N_in(u)} T(v): only the FP32 stage
 //    accumulator is gathered (exactly, in FP64), not the whole reserve.  For
 //    the columns being refreshed AS takes the new sum, y~ = (1-alpha) rt / d
-//    replaces the drifting residue, and a flush then moves T into S; the
-//    first sweep after that folds y~'s alpha-part into T (entry flag).
+//    replaces the drifting residue, and S += T; the first sweep after that
+//    starts T afresh with y~'s alpha-part (entry flag 2).
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -335,7 +335,14 @@ __device__ inline typename ST::V gather_gs(const typename ST::V* __restrict__ Y_
 }
 
 // y'(u) = scale(u) * acc for the columns inside their sweep budget (0 for the
-// others); T += y' (plus, on an entry sweep, the fresh residue's alpha-part).
+// others).  T collects, per column, the fresh residue of an entry sweep and
+// every residue a sweep stores (what the out-neighbours pull).  Sweeps go in
+// pairs: an odd step adds its input (the stored output of the even step
+// before it) and its own output, and an even step leaves T alone, except the
+// last step of a sequence, which adds its output whatever its parity.  A
+// column past its budget stores 0, so the odd step after its last sweep still
+// adds that sweep's output.  Entry flag 2 marks a column whose T the refresh
+// has already moved into S: its entry sweep overwrites T instead of adding.
 // SOR: the node holds p = q + scale(u) * acc, where q is what it kept back
 // last sweep, pushes y' = omega p and keeps (1 - omega) p.  What it kept back
 // is (1 - omega) / omega times what it pushed, i.e. y' = omega scale(u) acc +
@@ -346,17 +353,17 @@ __device__ inline typename ST::V gather_gs(const typename ST::V* __restrict__ Y_
 // Lane c holds columns K c .. K c + K - 1: vector c of row u in Y, float4s
 // (u C + c) K/4 + i of T, int4s / float4s c K/4 + i of kb, entry, omega.
 template <int C, bool SOR, typename ST>
-__device__ inline void finish_row(int32_t u, int c, Vec<ST::K> acc, int32_t step, const float* __restrict__ scale,
+__device__ inline void finish_row(int32_t u, int c, Vec<ST::K> acc, int32_t step, int32_t last,
+                                  const float* __restrict__ scale,
                                   const typename ST::V* __restrict__ Y_in, typename ST::V* Y_out,
                                   float4* __restrict__ T, const int32_t* __restrict__ kb,
                                   const int32_t* __restrict__ entry, const float* __restrict__ omega) {
     constexpr int K = ST::K, Q = K / 4;
     const int64_t at = (int64_t)u * C + c;
     const float sc = scale[u];
-    Vec<K> t, m, en = v_zero<K>();
+    Vec<K> m, en = v_zero<K>(), keep;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        t.q[i] = T[at * Q + i];
         const int4 kb4 = reinterpret_cast<const int4*>(kb)[c * Q + i];
         m.q[i] = make_float4(step < kb4.x ? 1.f : 0.f, step < kb4.y ? 1.f : 0.f, step < kb4.z ? 1.f : 0.f,
                              step < kb4.w ? 1.f : 0.f);
@@ -365,18 +372,25 @@ __device__ inline void finish_row(int32_t u, int c, Vec<ST::K> acc, int32_t step
     if (step == 0) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            en.q[i] = flag4(reinterpret_cast<const int4*>(entry)[c * Q + i]);
+            const int4 e4 = reinterpret_cast<const int4*>(entry)[c * Q + i];
+            en.q[i] = flag4(e4);
+            keep.q[i] = make_float4(e4.x == 2 ? 0.f : 1.f, e4.y == 2 ? 0.f : 1.f, e4.z == 2 ? 0.f : 1.f,
+                                    e4.w == 2 ? 0.f : 1.f);
             any_en |= (en.q[i].x + en.q[i].y + en.q[i].z + en.q[i].w) != 0.f;
         }
-        if (any_en) t = v_add(t, v_mul(v_mul(ST::value(Y_in[at]), en), m));
     }
+    const bool odd = (step & 1) != 0;
+    // the row's own input residue: the previous push (over-relaxation), the
+    // even step's output (odd steps), the fresh residue (entry sweep)
+    Vec<K> yin = v_zero<K>();
+    if (SOR || odd || any_en) yin = ST::value(Y_in[at]);
     acc = v_mul(acc, m);
     Vec<K> y;
 #pragma unroll
     for (int i = 0; i < Q; ++i)
         y.q[i] = make_float4(sc * acc.q[i].x, sc * acc.q[i].y, sc * acc.q[i].z, sc * acc.q[i].w);
     if (SOR) {
-        const Vec<K> yp = ST::value(Y_in[at]);
+        const Vec<K> yp = yin;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const float4 w = reinterpret_cast<const float4*>(omega)[c * Q + i];
@@ -391,8 +405,18 @@ __device__ inline void finish_row(int32_t u, int c, Vec<ST::K> acc, int32_t step
     const typename ST::V yq = ST::pack(y);
     Y_out[at] = yq;
     const Vec<K> ys = ST::value(yq);             // what the out-neighbours will pull
+    if (odd) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) T[at * Q + i] = f4_add(t.q[i], ys.q[i]);
+        for (int i = 0; i < Q; ++i) T[at * Q + i] = f4_add(f4_add(T[at * Q + i], yin.q[i]), ys.q[i]);
+    } else if (any_en || step == last) {
+        Vec<K> t;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) t.q[i] = T[at * Q + i];
+        if (any_en) t = v_add(v_mul(t, keep), v_mul(v_mul(yin, en), m));
+        if (step == last) t = v_add(t, ys);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) T[at * Q + i] = t.q[i];
+    }
 }
 
 template <typename OffT, int C, bool SOR, typename ST>
@@ -407,7 +431,7 @@ __global__ __launch_bounds__(kBlock) void sweep_k(
     static_assert(sizeof(typename ST::V) == 16, "a staged vector is 16 bytes");
     __shared__ typename ST::V lds[kLdsBytes / 16];
     const RowBlock b = blocks[blockIdx.x];
-    const int32_t step = *step_p;
+    const int32_t step = step_p[0];
     // every item of this thread belongs to column chunk threadIdx.x % C
     Vec<K> enf = v_zero<K>();
     bool fresh = false;
@@ -467,7 +491,7 @@ __global__ __launch_bounds__(kBlock) void sweep_k(
         partials[(int64_t)b.piece * C + c] = acc;
         return;
     }
-    finish_row<C, SOR, ST>(r0 + row, c, acc, step, scale, Y_in, Y_out, T, kb, entry, omega);
+    finish_row<C, SOR, ST>(r0 + row, c, acc, step, step_p[1], scale, Y_in, Y_out, T, kb, entry, omega);
 }
 
 // Long rows of one chunk: the pieces' partial sums added in slot order.
@@ -483,7 +507,7 @@ __global__ __launch_bounds__(kBlock) void combine_k(
     const LongRow L = rows[i];
     Vec<ST::K> acc = v_zero<ST::K>();
     for (int32_t p = 0; p < L.npieces; ++p) acc = v_add(acc, partials[(int64_t)(L.first + p) * C + c]);
-    finish_row<C, SOR, ST>(L.row, c, acc, *step_p, scale, Y_in, Y_out, T, kb, entry, omega);
+    finish_row<C, SOR, ST>(L.row, c, acc, step_p[0], step_p[1], scale, Y_in, Y_out, T, kb, entry, omega);
 }
 
 __global__ void bump_step_k(int32_t* step) { step[0] += 1; }
@@ -502,25 +526,6 @@ __global__ void from_bf16_k(int64_t count, const uint16_t* __restrict__ src, flo
         dst[i] = __uint_as_float((uint32_t)src[i] << 16);
 }
 
-// S += T (FP64), T = 0, dense over n x B, after the refresh has gathered T.
-// Only the columns being refreshed (rmask) are flushed: a column's reserve
-// then takes the same roundings whichever other columns share the block and
-// whenever they refresh.  The grid stride is a multiple of the block width,
-// so a thread's column is fixed.
-__global__ void flush_k(int64_t total, int32_t Bw, const int32_t* __restrict__ rmask, double* __restrict__ S,
-                        float* __restrict__ T) {
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    const int64_t i0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (!rmask[i0 & (Bw - 1)]) return;
-    for (int64_t i = i0; i < total; i += stride) {
-        const float t = T[i];
-        if (t != 0.f) {
-            S[i] += (double)t;
-            T[i] = 0.f;
-        }
-    }
-}
-
 // ---------------------------------------------------------------- refresh (FP64)
 // Persistent grid: block k handles schedule blocks k, k + G, ...  A schedule
 // block is up to Rf<C>::kRows whole rows with <= Rf<C>::kNnz in-edges, or one
@@ -530,11 +535,15 @@ __global__ void flush_k(int64_t total, int32_t Bw, const int32_t* __restrict__ r
 // are deterministic: after each schedule block the threads c < C add that
 // block's rows in row order into their own accumulators (columns 4c..4c+3),
 // which go to partials[block][B].  S, AS: double[n][B], read as double2 pairs.
+// A refreshed column (rmask) also moves its stage accumulator into the
+// reserve, S += T: every access to S is the row's own, so this is safe while
+// other blocks still gather T; the column's T is then stale, and its next
+// entry sweep overwrites it (entry flag 2).
 template <typename OffT, int C, typename ST>
 __global__ __launch_bounds__(kBlock) void refresh_k(
         const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
         const RowBlock* __restrict__ blocks, int32_t n_blocks,
-        const int32_t* __restrict__ deg, const float4* __restrict__ T, const double2* __restrict__ S,
+        const int32_t* __restrict__ deg, const float4* __restrict__ T, double2* __restrict__ S,
         double2* __restrict__ AS, const int32_t* __restrict__ src, const int32_t* __restrict__ rmask, double alpha,
         typename ST::V* __restrict__ Y, double* __restrict__ rt_out, int32_t n,
         double* __restrict__ partials) {
@@ -616,6 +625,8 @@ __global__ __launch_bounds__(kBlock) void refresh_k(
             if (w4.x | w4.y | w4.z | w4.w) {     // the refreshed columns keep the new sums
                 AS[2 * at] = make_double2(w4.x ? a0 : aa.x, w4.y ? a1 : aa.y);
                 AS[2 * at + 1] = make_double2(w4.z ? a2 : ab.x, w4.w ? a3 : ab.y);
+                S[2 * at] = make_double2(w4.x ? sa.x + (double)t.x : sa.x, w4.y ? sa.y + (double)t.y : sa.y);
+                S[2 * at + 1] = make_double2(w4.z ? sb.x + (double)t.z : sb.x, w4.w ? sb.y + (double)t.w : sb.y);
             }
             if (w4.x | w4.y | w4.z | w4.w) {     // other columns keep their bits (exact round trip)
                 float4 y = ST::value4(Y[at]);
@@ -782,9 +793,6 @@ void refresh_launch(MixedCtx& c, Graph& g, void* y, double* rt_out) {
                            g.row_idx.as<int32_t>(), sch.blocks.as<RowBlock>(), sch.n_blocks,
                            g.deg.as<int32_t>(), T4, S2, A2, c.src.as<int32_t>(), c.rmask.as<int32_t>(), c.alpha, Y4,
                            rt_out, g.n, c.partials.as<double>());
-    // every row has gathered T: now the refreshed columns move it into S
-    hipLaunchKernelGGL(flush_k, dim3(2048), dim3(kBlock), 0, c.stream, (int64_t)g.n * c.Bw, c.Bw,
-                       c.rmask.as<int32_t>(), c.S.as<double>(), c.T.as<float>());
     hipLaunchKernelGGL(reduce_cols_k, dim3((unsigned)c.Bw), dim3(kBlock), 0, c.stream, c.partials.as<double>(), (int)grid.x, c.Bw,
                        c.colsum.as<double>());
     HIPCHECK(hipGetLastError());

@@ -265,9 +265,9 @@ void run_mixed_batch(Graph& g, const int32_t* sources, int32_t B, double alpha, 
 void autotune_width(Graph& g, double alpha, const int32_t* widths, int32_t count, int32_t* best,
                     double* cost_us);
 
-void debug_sweep_mixed(Graph& g, double alpha, int32_t B, int32_t chunks, const float* y_in,
-                       const int32_t* fresh, float* y_out, float* t_out, const float* omega,
-                       int32_t residue_format);
+void debug_sweeps_mixed(Graph& g, double alpha, int32_t B, int32_t chunks, int32_t sweeps, const float* y_in,
+                        const int32_t* entry, const int32_t* budget, const float* t_in, float* y_out,
+                        float* t_out, const float* omega, int32_t residue_format);
 
 // serving blocks (continuous batching); the handle is an opaque Block*
 void* serve_block_create(Graph& g, int32_t slots, double alpha, const ppr_options& opt);

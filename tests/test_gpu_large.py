@@ -83,9 +83,10 @@ def batched(c4, G, srcs):
     s0 = st[0]
     per = s0["sweep_ms"] / max(s0["sweep_launches"], 1)
     # per node and column: residue read and written, stage accumulator read and
-    # written, and the previous push when over-relaxed
+    # written every second sweep with the row's own input residue, which an
+    # over-relaxed sweep reads every time (its previous push)
     rb = 2 if s0["residue_format"] == P.RESIDUE_BF16 else 4
-    per_col = 2 * rb + 8 + (rb if s0["sor_omega"] > 1.0 else 0)
+    per_col = 2 * rb + 4 + (rb if s0["sor_omega"] > 1.0 else rb // 2)
     bytes_per = 4 * M + 8 * N + per_col * N * 16
     REPORT["batched"] = {"sources": 16, "batch_cols": 16, "sweep_chunks": s0["sweep_chunks"],
                          "residues": "bf16" if rb == 2 else "f32", "sor_omega": s0["sor_omega"],

@@ -192,3 +192,108 @@ def test_bf16_device_buffers_and_errors(graphs):
     with pytest.raises(P.PPRError):                      # bf16 vectors hold 8 columns
         P.debug_sweep_mixed(G, ALPHA, y[:, :4].contiguous(), [1] * 4, residue_format=P.RESIDUE_BF16)
     G.close()
+
+
+def _sequence_by_single_sweeps(G, y, entry, budget, sweeps, chunks, om, fmt):
+    """The stored residues y_0 (input as stored), y_1, .., y_sweeps of a
+    sequence, produced one sweep at a time by the single-sweep entry point
+    (fresh only on the first), a column set to 0 after its budget."""
+    ys = []
+    cur = y
+    for k in range(sweeps):
+        fr = (entry != 0).astype(np.int32) if k == 0 else np.zeros_like(entry)
+        nxt = P.debug_sweep_mixed(G, ALPHA, cur, fr, chunks=chunks, omega=om, residue_format=fmt)
+        nxt[:, budget <= k] = 0.0
+        ys.append(nxt)
+        cur = nxt
+    y0 = _bf16(y) if fmt == P.RESIDUE_BF16 else y
+    return [y0] + ys
+
+
+@pytest.mark.parametrize("name", ["c1", "hub"])
+@pytest.mark.parametrize("width,chunks,sweeps,sor,fmt", [
+    (8, 3, 1, False, 0), (8, 3, 2, False, 0), (32, 4, 5, False, 0), (32, 4, 4, True, 0), (16, 1, 3, True, 0),
+    (128, 8, 5, True, 1), (128, 8, 6, False, 1), (8, 2, 7, True, 1)])
+def test_sweep_sequence_stage_accumulator(graphs, name, width, chunks, sweeps, sor, fmt):
+    """A launch sequence of several sweeps with per-column budgets and the
+    three entry kinds (continuing, fresh, fresh with the accumulator
+    restarting).  The accumulator is updated by every second sweep, which
+    adds its input and its output, and by the last sweep; whatever the
+    pairing, it must hold t_in (unless restarting) + the fresh residue + every
+    residue stored.  Checked two ways: (1) bit for bit against the same
+    sweeps run one at a time through the single-sweep entry point, adding
+    the stored values in the order the kernel adds them (FP32); (2) in FP32
+    storage, against the oracle's block Gauss-Seidel (or over-relaxed) sweeps
+    chained in FP64, within the one-sweep FP32 bound (module docstring)
+    taken once per sweep."""
+    g = graphs[name]
+    print(f"[gpu] sweep sequence {name} width={width} chunks={chunks} sweeps={sweeps} sor={sor} fmt={fmt}",
+          flush=True)
+    G = P.Graph.from_synth(g)
+    rng = np.random.default_rng(width * 13 + chunks * 5 + sweeps + (3 if sor else 0) + 97 * fmt)
+    y = rng.random((g.n, width)).astype(np.float32)
+    y[rng.random((g.n, width)) < 0.3] = 0.0
+    t_in = rng.random((g.n, width)).astype(np.float32)
+    entry = rng.integers(0, 3, width).astype(np.int32)
+    entry[:3] = [0, 1, 2]
+    budget = rng.integers(0, sweeps + 1, width).astype(np.int32)
+    budget[:4] = sweeps
+    budget[-1] = 0
+    budget[-2] = max(sweeps - 1, 0)
+    om = None
+    if sor:
+        om = (1.0 + 0.3 * rng.random(width)).astype(np.float32)
+        om[0] = 1.0
+    t_out = np.empty_like(y)
+    got = P.debug_sweeps_mixed(G, ALPHA, y, entry, sweeps, budget=budget, t_in=t_in, chunks=chunks,
+                               t_out=t_out, omega=om, residue_format=fmt)
+    ys = _sequence_by_single_sweeps(G, y, entry, budget, sweeps, chunks, om, fmt)
+    np.testing.assert_array_equal(got, ys[-1])
+    # the accumulator, in the kernel's order of FP32 additions
+    t = t_in.copy()
+    t[:, entry == 2] = 0.0
+    first = (entry != 0) & (budget > 0)
+    t = t + np.where(first[None, :], ys[0], np.float32(0.0))
+    for k in range(sweeps):
+        if k % 2 == 1:
+            t = (t + ys[k]) + ys[k + 1]
+        elif k == sweeps - 1:
+            t = t + ys[k + 1]
+    np.testing.assert_array_equal(t_out, t)
+    if fmt == P.RESIDUE_F32:
+        csc_arrays = oracle.csc(g)
+        din = np.diff(csc_arrays[0]).astype(np.float64)
+        lo = oracle.chunk_bounds(g, chunks)
+        rel = sweeps * (2 * din.max() + 6) * U
+        for b in range(width):
+            w = float(om[b]) if sor else 1.0
+            cur = y[:, b].astype(np.float64)
+            q = np.zeros(g.n) if entry[b] else (1.0 - w) / w * cur
+            mag, qm = cur.copy(), np.abs(q)
+            t_want = (0.0 if entry[b] == 2 else t_in[:, b].astype(np.float64)) + (cur if first[b] else 0.0)
+            t_mag = np.abs(t_want)
+            for k in range(sweeps):
+                fresh = bool(entry[b]) and k == 0
+                if k >= budget[b]:
+                    cur, q, mag, qm = (np.zeros(g.n),) * 4
+                    break
+                cur, q = oracle.block_sor_sweep(g, ALPHA, lo, cur, fresh, w, q, csc_arrays=csc_arrays)
+                mag, qm = oracle.block_sor_sweep(g, ALPHA, lo, mag, fresh, w, qm, csc_arrays=csc_arrays)
+                qm = np.abs(qm)                # the same recursion on absolute values
+                t_want = t_want + cur
+                t_mag = t_mag + mag
+            assert np.all(np.abs(got[:, b] - cur) <= rel * mag + 1e-38), b
+            assert np.all(np.abs(t_out[:, b] - t_want) <= (rel + (sweeps + 2) * U) * t_mag + 1e-38), b
+    G.close()
+
+
+def test_sweep_sequence_arguments(graphs):
+    g = graphs["c1"]
+    G = P.Graph.from_synth(g)
+    y = np.zeros((g.n, 8), np.float32)
+    for kw in ({"sweeps": 0}, {"sweeps": 65}, {"entry": [3] * 8}, {"budget": [5] * 8}, {"budget": [-1] * 8}):
+        args = {"sweeps": 4, "entry": [0] * 8}
+        args.update(kw)
+        with pytest.raises(P.PPRError):
+            P.debug_sweeps_mixed(G, ALPHA, y, args["entry"], args["sweeps"], budget=args.get("budget"))
+    G.close()
