@@ -199,19 +199,22 @@ def main() -> int:
                 "queries": args.fp64_queries}
         print(f"[bench] fp64: {f64_qps:.1f} q/s, sweep {f64_sweep_ms:.3f} ms", file=sys.stderr, flush=True)
     if args.fp64_epoch_queries > 0 and fp64 is not None:
+        # Algorithm 3's epochs; scans direction-optimizing (default), all pull, all push
         out1 = torch.empty((1, g.n), dtype=torch.float64, device="cuda")
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        ep = [G.query_batch([s_], args.alpha, args.lam, P.FP64, out=out1, global_rule=P.GLOBAL_EPOCHS)[1][0]
-              for s_ in srcs[:args.fp64_epoch_queries]]
-        torch.cuda.synchronize()
-        ep_dt = time.perf_counter() - t1
-        fp64["epochs"] = {"value": round(len(ep) / ep_dt, 3), "unit": "queries/s",
-                          "scans_per_query": round(sum(e["sweeps"] for e in ep) / len(ep), 1),
-                          "edge_pushes_per_query_over_m": round(sum(e["edge_pushes"] for e in ep) / len(ep) / g.m, 2),
-                          "threshold0_sweeps_per_query": round(sum(e["sweeps"] for e in f64_stats) / len(f64_stats), 1),
-                          "queries": len(ep)}
-        print(f"[bench] fp64 epochs: {fp64['epochs']}", file=sys.stderr, flush=True)
+        for key, form in (("epochs", P.SCAN_AUTO), ("epochs_pull", P.SCAN_PULL), ("epochs_push", P.SCAN_PUSH)):
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            ep = [G.query_batch([s_], args.alpha, args.lam, P.FP64, out=out1, global_rule=P.GLOBAL_EPOCHS,
+                                scan_form=form)[1][0] for s_ in srcs[:args.fp64_epoch_queries]]
+            torch.cuda.synchronize()
+            ep_dt = time.perf_counter() - t1
+            fp64[key] = {"value": round(len(ep) / ep_dt, 3), "unit": "queries/s",
+                         "scans_per_query": round(sum(e["sweeps"] for e in ep) / len(ep), 1),
+                         "push_scans_per_query": round(sum(e["push_scans"] for e in ep) / len(ep), 1),
+                         "edge_pushes_per_query_over_m": round(sum(e["edge_pushes"] for e in ep) / len(ep) / g.m, 2),
+                         "queries": len(ep)}
+            print(f"[bench] fp64 {key}: {fp64[key]}", file=sys.stderr, flush=True)
+        fp64["epochs"]["threshold0_sweeps_per_query"] = round(sum(e["sweeps"] for e in f64_stats) / len(f64_stats), 1)
 
     # the same step with FP32 residue storage (one timed step)
     f32_leg = None

@@ -104,7 +104,8 @@ typedef struct {
     double sor_omega;       /* over-relaxation factor of the query's last stage (1 = none) */
     int32_t residue_format; /* storage of the residues the query swept: PPR_RESIDUE_F32 or
                                PPR_RESIDUE_BF16 (PPR_FP64: F32, though it sweeps in double) */
-    int32_t reserved;
+    int32_t push_scans;     /* PPR_GLOBAL_EPOCHS: scans taken in push form (the rest of
+                               `sweeps` in pull form); 0 otherwise */
 } ppr_stats;
 
 /* Global phase of the PPR_FP64 path. */
@@ -114,6 +115,22 @@ typedef enum {
                                scans while r_sum > m rmax_i; each scan pushes, at once,
                                the nodes active at its start (r(v) > d_v rmax_i) */
 } ppr_global_rule;
+
+/* Form of a thresholded scan of PPR_GLOBAL_EPOCHS (both push, at once, every
+ * node active at the scan's start: the same scan, the same result up to FP64
+ * rounding order). */
+typedef enum {
+    PPR_SCAN_AUTO = 0,  /* push form when switch_param * vol <= m for the active set's
+                           out-edge volume vol, pull form otherwise (direction-optimizing;
+                           default) */
+    PPR_SCAN_PULL = 1,  /* pull form: a threshold pass over all nodes, then every in-edge
+                           list reads the pushing nodes' shares (no atomics; reads all m
+                           edges) */
+    PPR_SCAN_PUSH = 2   /* push form: the active nodes, listed, add their shares along
+                           their out-edges with FP64 atomics (reads vol edges); the next
+                           scan's active nodes are the ones such an add carried across
+                           their threshold */
+} ppr_scan_form;
 
 /* Query options (ppr_options_default fills the defaults). */
 typedef struct {
@@ -141,7 +158,8 @@ typedef struct {
                                measured contraction shows no gain falls back to 1; the FP64
                                certificate bounds the result either way */
     int32_t residue_format; /* PPR_MIXED: ppr_residue_format; default PPR_RESIDUE_AUTO */
-    int32_t reserved;
+    int32_t scan_form;      /* PPR_FP64 with PPR_GLOBAL_EPOCHS: ppr_scan_form; default
+                               PPR_SCAN_AUTO */
 } ppr_options;
 
 /* Read-only facts about a created graph. */

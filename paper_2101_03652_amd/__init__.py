@@ -32,6 +32,9 @@ GLOBAL_EPOCHS = 1
 RESIDUE_F32 = 0
 RESIDUE_BF16 = 1
 RESIDUE_AUTO = 2
+SCAN_AUTO = 0
+SCAN_PULL = 1
+SCAN_PUSH = 2
 GRAPH_TRUST_INPUT = 1
 GRAPH_WIDE_OFFSETS = 2
 
@@ -61,7 +64,7 @@ class Stats(ctypes.Structure):
                 ("sweep_ms", ctypes.c_double), ("sweep_launches", ctypes.c_int32),
                 ("batch_cols", ctypes.c_int32), ("sweep_chunks", ctypes.c_int32),
                 ("sor_omega", ctypes.c_double), ("residue_format", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("push_scans", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -92,7 +95,7 @@ class Options(ctypes.Structure):
                 ("certify", ctypes.c_int32), ("refresh_factor", ctypes.c_double),
                 ("batch_cols", ctypes.c_int32), ("sweep_chunks", ctypes.c_int32),
                 ("global_rule", ctypes.c_int32), ("sor_omega", ctypes.c_double),
-                ("residue_format", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("residue_format", ctypes.c_int32), ("scan_form", ctypes.c_int32)]
 
 
 class GraphInfo(ctypes.Structure):

@@ -222,25 +222,7 @@ void refine(Graph& g, QueryCtx& c, double alpha, double rmax, int32_t* levels_ou
     auto* ctr = c.ctr.as<int64_t>();
     int32_t* F = c.F0.as<int32_t>();
     int32_t* Fn = c.F1.as<int32_t>();
-    // per-block counts and volumes, then their scans
-    static_assert(4 * (kCompactBlocks + 1) <= kAuxLen, "compaction scratch");
-    int64_t* bc = c.aux.as<int64_t>();
-    int64_t* bv = bc + kCompactBlocks;
-    int64_t* oc = bv + kCompactBlocks;
-    int64_t* ov = oc + kCompactBlocks + 1;
-    auto frontier = [&](int32_t* out) {
-        hipLaunchKernelGGL(active_count_kernel, dim3(kCompactBlocks), dim3(kBlock), 0, ss, c.r.as<double>(),
-                           g.deg.as<int32_t>(), g.n, rmax, bc, bv);
-        HIPCHECK(hipGetLastError());
-        k::exclusive_scan_i64(bc, oc, kCompactBlocks, c.scan_tmp.p, ss);
-        k::exclusive_scan_i64(bv, ov, kCompactBlocks, c.scan_tmp.p, ss);
-        hipLaunchKernelGGL(active_write_kernel, dim3(kCompactBlocks), dim3(kBlock), 0, ss, c.r.as<double>(),
-                           g.deg.as<int32_t>(), g.n, rmax, oc, out);
-        HIPCHECK(hipGetLastError());
-        HIPCHECK(hipMemcpyAsync(hctr, oc + kCompactBlocks, 8, hipMemcpyDeviceToHost, ss));
-        HIPCHECK(hipMemcpyAsync(hctr + 1, ov + kCompactBlocks, 8, hipMemcpyDeviceToHost, ss));
-        HIPCHECK(hipStreamSynchronize(ss));
-    };
+    auto frontier = [&](int32_t* out) { active_set(g, c, rmax, out, &hctr[0], &hctr[1]); };
     frontier(F);
     int64_t nf = hctr[0], vol = hctr[1];
     int32_t levels = 0;
@@ -310,6 +292,32 @@ const int32_t* index_for(const Graph& g, double alpha, uint64_t seed, bool use) 
 }
 
 }  // namespace
+
+void active_set(const Graph& g, QueryCtx& c, double rmax, int32_t* out, int64_t* count, int64_t* vol) {
+    hipStream_t ss = c.stream;
+    // per-block counts and volumes, then their scans
+    static_assert(4 * (kCompactBlocks + 1) <= kAuxLen, "compaction scratch");
+    int64_t* bc = c.aux.as<int64_t>();
+    int64_t* bv = bc + kCompactBlocks;
+    int64_t* oc = bv + kCompactBlocks;
+    int64_t* ov = oc + kCompactBlocks + 1;
+    hipLaunchKernelGGL(active_count_kernel, dim3(kCompactBlocks), dim3(kBlock), 0, ss, c.r.as<double>(),
+                       g.deg.as<int32_t>(), g.n, rmax, bc, bv);
+    HIPCHECK(hipGetLastError());
+    k::exclusive_scan_i64(bc, oc, kCompactBlocks, c.scan_tmp.p, ss);
+    k::exclusive_scan_i64(bv, ov, kCompactBlocks, c.scan_tmp.p, ss);
+    if (out) {
+        hipLaunchKernelGGL(active_write_kernel, dim3(kCompactBlocks), dim3(kBlock), 0, ss, c.r.as<double>(),
+                           g.deg.as<int32_t>(), g.n, rmax, oc, out);
+        HIPCHECK(hipGetLastError());
+    }
+    int64_t* h = c.host.as<int64_t>() + 6;
+    HIPCHECK(hipMemcpyAsync(h, oc + kCompactBlocks, 8, hipMemcpyDeviceToHost, ss));
+    HIPCHECK(hipMemcpyAsync(h + 1, ov + kCompactBlocks, 8, hipMemcpyDeviceToHost, ss));
+    HIPCHECK(hipStreamSynchronize(ss));
+    *count = h[0];
+    *vol = h[1];
+}
 
 double walk_budget(int32_t n, double eps, double mu) {
     return 2.0 * (2.0 * eps / 3.0 + 2.0) * std::log((double)n) / (eps * eps * mu);

@@ -55,6 +55,8 @@ void check_options(const ppr_options& o) {
     if (o.residue_format != PPR_RESIDUE_F32 && o.residue_format != PPR_RESIDUE_BF16 &&
         o.residue_format != PPR_RESIDUE_AUTO)
         fail(PPR_ERR_ARG, "unknown residue format");
+    if (o.scan_form != PPR_SCAN_AUTO && o.scan_form != PPR_SCAN_PULL && o.scan_form != PPR_SCAN_PUSH)
+        fail(PPR_ERR_ARG, "unknown scan form");
     if (o.batch_cols < 0 || (o.batch_cols % 4) != 0) fail(PPR_ERR_ARG, "batch_cols must be 0 or a multiple of 4");
     if (o.sweep_chunks < 0 || o.sweep_chunks > 64) fail(PPR_ERR_ARG, "sweep_chunks must lie in [0, 64]");
     if (!(o.sor_omega == 0.0 || (o.sor_omega >= 1.0 && o.sor_omega <= 1.9)))
@@ -80,6 +82,7 @@ void ppr_options_default(ppr_options* o) {
     o->refresh_factor = 0.0;
     o->batch_cols = 0;
     o->residue_format = PPR_RESIDUE_AUTO;
+    o->scan_form = PPR_SCAN_AUTO;
 }
 
 const char* ppr_version(void) { return "libppr 0.1 (gfx950)"; }

@@ -612,6 +612,7 @@ struct Block {
         st->sweep_chunks = c->chunks;
         st->sor_omega = sl.omega;
         st->residue_format = c->bf16 ? PPR_RESIDUE_BF16 : PPR_RESIDUE_F32;
+        st->push_scans = 0;
     }
 
     // Export slot b (DONE) into out[n] (host or device) and free the slot;

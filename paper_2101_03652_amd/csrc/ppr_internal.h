@@ -253,6 +253,9 @@ void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_
 // where it is (probability (1 - alpha)^4096).
 constexpr int32_t kMaxWalkSteps = 4096;
 double walk_budget(int32_t n, double eps, double mu);
+// The active nodes of c.r w.r.t. rmax (r(v) > d_v rmax), in node order, into
+// out (nullable: count only), with their number and edge volume.
+void active_set(const Graph& g, QueryCtx& c, double rmax, int32_t* out, int64_t* count, int64_t* vol);
 void run_approx_query(Graph& g, int32_t s, double alpha, double eps, double mu, uint64_t seed, bool use_index,
                       const ppr_options& opt, double* pi_out, ppr_approx_stats* st);
 void build_walk_index(Graph& g, double alpha, uint64_t seed, double* ms);

@@ -162,23 +162,82 @@ void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_
     double sweep_ms = 0.0;
     int32_t timed_sweeps = 0;
     EventPair ev;
+    int32_t push_scans = 0;
     if (opt.global_rule == PPR_GLOBAL_EPOCHS && r_sum > lambda) {
         // ---- global phase, Algorithm 3's epochs: rmax_i = lambda^(i/8) / m,
         // scans while r_sum > m rmax_i (as printed); each scan pushes at once the
         // nodes active at its start.  A scan with no active node ends the epoch;
         // scans at rmax_8 continue while rounding leaves r_sum above lambda.
+        // A scan runs in push form over the listed active set when that set's
+        // out-edge volume is small (scan_form), else in pull form over all
+        // in-edges.  After a push scan the next active set is the list of
+        // nodes its atomic adds carried across the threshold (every other
+        // node is below it and unchanged); a new epoch lowers the threshold,
+        // and a pull scan leaves no list, so the set is then listed afresh:
+        // under PPR_SCAN_AUTO only when the last pull scan's volume was within
+        // twice the push bound (sizing the set costs a pass over all nodes and
+        // a host round trip), and counted before it is listed.
         ev.start(ss);
         double* y = c.y0.as<double>();
         bool capped = false;
+        int32_t* F = c.F0.as<int32_t>();
+        int32_t* Fn = c.F1.as<int32_t>();
+        const auto push_pays = [&](int64_t v) {
+            return opt.scan_form == PPR_SCAN_PUSH ||
+                   (opt.scan_form == PPR_SCAN_AUTO && opt.switch_param * (double)v <= (double)g.m);
+        };
         for (int i = 1; i <= 9 && !capped; ++i) {
             const bool last = (i == 9);
             const double rmax_i = std::pow(lambda, (double)(last ? 8 : i) / 8.0) / (double)g.m;
+            bool listed = false;         // F holds exactly the nodes active w.r.t. rmax_i
+            int64_t nfa = 0, vola = 0;
+            double last_pull = -1.0;     // volume of the last pull scan of this epoch
             for (;;) {
                 if (last ? !(r_sum > lambda) : !(r_sum > (double)g.m * rmax_i)) break;
                 if (sweeps >= opt.max_sweeps) {
                     capped = true;
                     break;
                 }
+                if (opt.scan_form == PPR_SCAN_PUSH && !listed) {
+                    active_set(g, c, rmax_i, F, &nfa, &vola);
+                    if (nfa == 0) break;      // nothing is active: the scan would move nothing
+                    listed = true;
+                } else if (opt.scan_form == PPR_SCAN_AUTO && !listed &&
+                           (last_pull < 0.0 || push_pays((int64_t)(last_pull / 2.0)))) {
+                    active_set(g, c, rmax_i, nullptr, &nfa, &vola);
+                    if (nfa == 0) break;
+                    if (push_pays(vola)) {
+                        active_set(g, c, rmax_i, F, &nfa, &vola);
+                        listed = true;
+                    }
+                }
+                if (listed && push_pays(vola)) {
+                    if (nfa == 0) break;
+                    int np = 0;
+                    k::frontier_snapshot(F, (int32_t)nfa, deg, alpha, r, pi, c.X.as<double>(),
+                                         c.degF.as<int64_t>(), partials, &np, ss);
+                    k::exclusive_scan_i64(c.degF.as<int64_t>(), c.off.as<int64_t>(), nfa, c.scan_tmp.p, ss);
+                    HIPCHECK(hipMemsetAsync(c.ctr.p, 0, 16, ss));
+                    k::frontier_push(F, c.off.as<int64_t>(), (int32_t)nfa, vola, g.row_ptr.as<int64_t>(),
+                                     g.col.as<int32_t>(), deg, c.X.as<double>(), rmax_i, r, Fn,
+                                     c.ctr.as<int64_t>(), ss);
+                    // the exact residue sum after the scan
+                    k::prep_y(r, deg, alpha, g.n, y, partials, &np, ss);
+                    k::reduce_sum(partials, np, c.dsum.as<double>(), ss);
+                    HIPCHECK(hipMemcpyAsync(hctr, c.ctr.p, 16, hipMemcpyDeviceToHost, ss));
+                    HIPCHECK(hipMemcpyAsync(hd + 2, c.dsum.p, 8, hipMemcpyDeviceToHost, ss));
+                    HIPCHECK(hipStreamSynchronize(ss));
+                    ++sweeps;
+                    ++push_scans;
+                    edge_pushes += vola;
+                    r_sum = hd[2];
+                    nfa = hctr[0];
+                    vola = hctr[1];
+                    std::swap(F, Fn);
+                    if (trace) trace->note(1, sweeps, edge_pushes, r_sum);
+                    continue;
+                }
+                listed = false;                // a pull scan leaves no list
                 int np = 0;
                 k::threshold_snapshot(deg, g.n, alpha, rmax_i, r, pi, y, partials, &np, ss);
                 k::reduce_sum(partials, np, c.dsum.as<double>() + 1, ss);
@@ -188,6 +247,7 @@ void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_
                 HIPCHECK(hipStreamSynchronize(ss));
                 if (hd[1] == 0.0) break;      // nothing was active: the scan moved nothing
                 ++sweeps;
+                last_pull = hd[1];
                 edge_pushes += (int64_t)hd[1];
                 r_sum = hd[0];
                 if (trace) trace->note(1, sweeps, edge_pushes, r_sum);
@@ -278,6 +338,7 @@ void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_
         st->sweep_chunks = 1;
         st->sor_omega = 1.0;
         st->residue_format = PPR_RESIDUE_F32;
+        st->push_scans = push_scans;
         st->local_levels = levels;
         st->sweeps = sweeps;
         st->refreshes = 0;

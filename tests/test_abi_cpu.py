@@ -29,6 +29,7 @@ def test_options_default():
     o = P.options()
     assert o.precision == P.FP64 and o.switch_rule == P.SWITCH_EDGES
     assert o.switch_param == 32.0 and o.max_sweeps == 4096 and o.refresh_factor == 0.0 and o.residue_format == 2
+    assert o.scan_form == P.SCAN_AUTO
 
 
 def _create(row_ptr, col, n, flags=0):

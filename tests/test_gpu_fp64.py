@@ -229,19 +229,30 @@ def test_query_argument_errors(c1):
     assert ei.value.status == -7
 
 
+@pytest.mark.parametrize("form", [P.SCAN_AUTO, P.SCAN_PULL, P.SCAN_PUSH])
 @pytest.mark.parametrize("lam", [1e-6, 1e-8])
-def test_epochs_global_phase_matches_oracle(c1, hub, lam):
+def test_epochs_global_phase_matches_oracle(c1, hub, lam, form):
     """The PPR_GLOBAL_EPOCHS global phase (Algorithm 3's epochs, each scan taken
     at once over the nodes active at its start) against the oracle's same
     schedule: equal local levels, scans and edge pushes, equal vectors to
-    FP64 summation order, and within lambda of the power-iteration truth."""
+    FP64 summation order, and within lambda of the power-iteration truth;
+    with every scan in pull form, every scan in push form (the active set
+    listed, atomic adds along out-edges, the next set from the adds that
+    cross the threshold), and the two mixed by edge volume (AUTO: push when
+    switch_param * vol <= m)."""
     for g, srcs in ((c1, [int(s) for s in synth.sources(c1.n, 3)]), (hub, [0, 12345])):
         G = P.Graph.from_synth(g)
         for s in srcs:
             for param in (8.0, 1e30):          # 1e30: straight to the global phase
-                print(f"[gpu] fp64 epochs n={g.n} s={s} lam={lam} param={param}", flush=True)
+                print(f"[gpu] fp64 epochs n={g.n} s={s} lam={lam} param={param} form={form}", flush=True)
                 pi, st = G.query(s, ALPHA, lam, P.FP64, switch_param=param, global_rule=P.GLOBAL_EPOCHS,
-                                 certify=1)
+                                 certify=1, scan_form=form)
+                if form == P.SCAN_PULL or (form == P.SCAN_AUTO and param == 1e30):
+                    assert st["push_scans"] == 0
+                elif form == P.SCAN_PUSH:
+                    assert st["push_scans"] == st["sweeps"]
+                else:
+                    assert 0 <= st["push_scans"] <= st["sweeps"]
                 pio, ro, sto, _, _ = oracle.powerpush_sync(g, s, ALPHA, lam, P.SWITCH_EDGES, param,
                                                            global_rule=oracle.GLOBAL_EPOCHS)
                 assert st["local_levels"] == sto["local_levels"]
@@ -266,6 +277,24 @@ def test_epochs_rule_is_fp64_only(c1):
     with pytest.raises(P.PPRError) as ei:
         G.query(1, ALPHA, 1e-8, P.FP64, global_rule=7)
     assert ei.value.status == -1
+    with pytest.raises(P.PPRError) as ei:
+        G.query(1, ALPHA, 1e-8, P.FP64, global_rule=P.GLOBAL_EPOCHS, scan_form=3)
+    assert ei.value.status == -1
+    G.close()
+
+
+def test_epoch_scan_forms_agree_on_the_hub_graph(hub):
+    """Push-form and pull-form epoch scans on the hub graph (a 12,000
+    in-degree hub, long out-edge lists): the same schedule, vectors equal to
+    FP64 summation order (the push form adds with atomics in no fixed order)."""
+    G = P.Graph.from_synth(hub)
+    for s in (0, 777):
+        a, sa = G.query(s, ALPHA, 1e-8, P.FP64, global_rule=P.GLOBAL_EPOCHS, scan_form=P.SCAN_PULL)
+        b, sb = G.query(s, ALPHA, 1e-8, P.FP64, global_rule=P.GLOBAL_EPOCHS, scan_form=P.SCAN_PUSH)
+        assert (sa["sweeps"], sa["edge_pushes"], sa["local_levels"]) == \
+               (sb["sweeps"], sb["edge_pushes"], sb["local_levels"])
+        assert sb["push_scans"] == sb["sweeps"] and sa["push_scans"] == 0
+        np.testing.assert_allclose(a, b, rtol=RTOL, atol=ATOL)
     G.close()
 
 
