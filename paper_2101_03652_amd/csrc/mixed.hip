@@ -185,6 +185,7 @@ struct Block {
         bool entry = false;          // the residue is fresh: the next sweep folds its alpha-part
                                      // and pulls it along every in-edge
         bool t_moved = false;        // the last refresh moved T into S: the entry sweep restarts T
+        bool s_unset = false;        // converted, not refreshed yet: S and AS hold another query's values
         bool refreshing = false;     // in the refresh whose result is in flight
         bool failed = false;         // reached max_sweeps with a certificate above lambda
         double cert = -1.0;
@@ -424,6 +425,7 @@ struct Block {
             sl.err = (1.0 - alpha) * hcol[b];
             sl.entry = true;
             sl.t_moved = false;          // T holds the local phase's reserve
+            sl.s_unset = true;           // the first refresh takes S = AS = 0 (rmask 2)
             const double w = opt.sor_omega == 0.0 ? kAutoOmega : opt.sor_omega;
             sl.omega = (c->chunks > 1 && w > 1.0) ? w : 1.0;
             sl.rho = first_rate(sl);
@@ -573,8 +575,9 @@ struct Block {
             if (sl.state == RUNNING && (sl.stage_left <= 0 || out_of_sweeps(sl))) {
                 // T holds this stage's increments unless a refresh already moved it
                 if (sl.t_moved) fail(PPR_ERR_DEVICE, "internal: refresh of a column without a stage");
-                hr[b] = 1;
+                hr[b] = sl.s_unset ? 2 : 1;
                 sl.t_moved = true;
+                sl.s_unset = false;
                 sl.refreshing = true;
                 any = true;
             }

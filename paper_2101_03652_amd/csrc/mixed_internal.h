@@ -56,7 +56,8 @@ struct MixedCtx {
     DevBuf kb;                        // int32[Bw]  sweeps each column runs in this launch sequence
     DevBuf entry;                     // int32[Bw]  1: fold the fresh residue into T on the first sweep,
                                       //            2: the same, restarting T (the refresh moved it into S)
-    DevBuf rmask;                     // int32[Bw]  1: refresh writes this column's residue
+    DevBuf rmask;                     // int32[Bw]  1: refresh writes this column's residue (and S, AS),
+                                      //            2: the same, its S and AS taken as 0 (first refresh)
     DevBuf cmask;                     // int32[Bw]  1: conversion writes this column
     DevBuf rmaxb;                     // double[Bw] lambda_b / m: activity threshold per column
     DevBuf step;                      // int32[2]   sweeps done in the current sequence, its last step

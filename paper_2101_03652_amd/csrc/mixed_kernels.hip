@@ -233,16 +233,17 @@ __global__ __launch_bounds__(kBlock) void push_k(
 
 // FP64 scratch -> block for the columns with cmask = 1, dense over (u, b):
 // y = (1-alpha) r / d; the local phase's reserve (1-alpha) pi / (alpha d)
-// enters through the stage accumulator T (FP32), with S = AS = 0, so that the
-// first refresh gathers it like any stage's increments (its FP32 rounding is
-// residual that refresh measures); the scratch of those columns is cleared.  The residue is fresh (nobody has
+// enters through the stage accumulator T (FP32), with S = AS = 0 (not
+// written here: the column's first refresh runs with rmask 2 and takes both
+// as 0), so that the first refresh gathers it like any stage's increments
+// (its FP32 rounding is residual that refresh measures); the scratch of
+// those columns is cleared.  The residue is fresh (nobody has
 // pulled it), so the first sweep of the column runs with its entry flag:
 // it folds the alpha-part into T and pulls y along every in-edge.
 // partials[block][B]: per-column sums of r.
 __global__ void convert_k(int32_t n, int shift, const int32_t* __restrict__ deg, double alpha,
                           const int32_t* __restrict__ cmask, double* __restrict__ r64, double* __restrict__ pi64,
-                          void* __restrict__ Y, int y_bf16, double* __restrict__ S, double* __restrict__ AS,
-                          float* __restrict__ T, double* __restrict__ partials) {
+                          void* __restrict__ Y, int y_bf16, float* __restrict__ T, double* __restrict__ partials) {
     __shared__ double sh[kBlock];
     __shared__ int32_t cm[128];
     const int B = 1 << shift;
@@ -263,8 +264,6 @@ __global__ void convert_k(int32_t n, int shift, const int32_t* __restrict__ deg,
                 reinterpret_cast<uint16_t*>(Y)[i] = (uint16_t)bf16_bits((float)y);
             else
                 reinterpret_cast<float*>(Y)[i] = (float)y;
-            S[i] = 0.0;
-            AS[i] = 0.0;
             T[i] = (float)(((1.0 - alpha) * p) / (alpha * d));
             if (r != 0.0) r64[i] = 0.0;        // the scratch is mostly zero already
             if (p != 0.0) pi64[i] = 0.0;
@@ -538,7 +537,9 @@ __global__ void from_bf16_k(int64_t count, const uint16_t* __restrict__ src, flo
 // A refreshed column (rmask) also moves its stage accumulator into the
 // reserve, S += T: every access to S is the row's own, so this is safe while
 // other blocks still gather T; the column's T is then stale, and its next
-// entry sweep overwrites it (entry flag 2).
+// entry sweep overwrites it (entry flag 2).  rmask 2 marks a column's first
+// refresh after its conversion: its S and AS are taken as 0 (the conversion
+// does not clear them).
 template <typename OffT, int C, typename ST>
 __global__ __launch_bounds__(kBlock) void refresh_k(
         const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
@@ -612,10 +613,14 @@ __global__ __launch_bounds__(kBlock) void refresh_k(
             const int64_t at = (int64_t)u * C + c;
             const double d = (double)deg[u];
             const float4 t = T[at];
-            const double2 sa = S[2 * at], sb = S[2 * at + 1];
-            const double2 aa = AS[2 * at], ab = AS[2 * at + 1];
             const int4 s4 = reinterpret_cast<const int4*>(src)[c];
             const int4 w4 = reinterpret_cast<const int4*>(rmask)[c];
+            double2 sa = S[2 * at], sb = S[2 * at + 1];
+            double2 aa = AS[2 * at], ab = AS[2 * at + 1];
+            if (w4.x == 2) sa.x = aa.x = 0.0;    // first refresh after the conversion
+            if (w4.y == 2) sa.y = aa.y = 0.0;
+            if (w4.z == 2) sb.x = ab.x = 0.0;
+            if (w4.w == 2) sb.y = ab.y = 0.0;
             // the in-neighbour sums of S + T
             const double a0 = aa.x + g0, a1 = aa.y + g1, a2 = ab.x + g2, a3 = ab.y + g3;
             t0 = (s4.x == u ? 1.0 : 0.0) - d * (sa.x + (double)t.x) * inv_oma + a0;
@@ -863,8 +868,7 @@ void convert(MixedCtx& c, const Graph& g, double alpha) {
     const unsigned gc = 1024;
     hipLaunchKernelGGL(convert_k, dim3(gc), dim3(kBlock), 0, c.stream, g.n, c.shift, g.deg.as<int32_t>(), alpha,
                        c.cmask.as<int32_t>(), c.r64.as<double>(), c.pi64.as<double>(),
-                       const_cast<void*>(c.ycur), c.bf16 ? 1 : 0, c.S.as<double>(), c.AS.as<double>(),
-                       c.T.as<float>(), c.partials.as<double>());
+                       const_cast<void*>(c.ycur), c.bf16 ? 1 : 0, c.T.as<float>(), c.partials.as<double>());
     hipLaunchKernelGGL(reduce_cols_k, dim3((unsigned)c.Bw), dim3(kBlock), 0, c.stream, c.partials.as<double>(), (int)gc, c.Bw,
                        c.colsum.as<double>());
     HIPCHECK(hipGetLastError());
