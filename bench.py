@@ -105,6 +105,8 @@ def main() -> int:
                     help="also time one step at these block widths (empty: skip)")
     ap.add_argument("--single-sources", type=int, default=32,
                     help="sources answered one at a time by the FP64 and the mixed path (0: skip)")
+    ap.add_argument("--host-output", type=int, default=1,
+                    help="1: also time one step into pinned and one into pageable host memory (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0,
                     help="also copy a 1 GiB device buffer (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -255,6 +257,30 @@ def main() -> int:
                           "residues": "bf16" if st_w[0]["residue_format"] == 1 else "f32"}
         print(f"[bench] width {w}: {widths[str(w)]}", flush=True, file=sys.stderr)
 
+    # the same step with the results delivered to host memory (device staging
+    # plus a PCIe copy of 8 n bytes per query); reported beside the device-resident rate
+    host_out = None
+    if args.host_output:
+        host_out = {}
+        for kind in ("pinned", "pageable"):
+            if kind == "pinned":
+                hbuf = torch.empty((args.sources, g.n), dtype=torch.float64, pin_memory=True)
+            else:
+                hbuf = np.empty((args.sources, g.n), dtype=np.float64)
+                hbuf.fill(0.0)                     # first touch outside the timed step
+            G.query_batch(srcs, args.alpha, args.lam, P.MIXED, out=hbuf, batch_cols=width)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            st_h = G.query_batch(srcs, args.alpha, args.lam, P.MIXED, out=hbuf, batch_cols=width)[1]
+            torch.cuda.synchronize()
+            dt_h = time.perf_counter() - t1
+            host_out[kind] = {"value": round(args.sources / dt_h, 3), "unit": "queries/s",
+                              "ms_per_step": round(dt_h * 1e3, 2),
+                              "bytes_to_host": 8 * args.sources * g.n,
+                              "max_cert_l1": max(s_["cert_l1"] for s_ in st_h)}
+            del hbuf
+        print(f"[bench] host output: {host_out}", file=sys.stderr, flush=True)
+
     # approximate queries (SpeedPPR, Algorithm 4): index-free and with the walk index
     approx = None
     if args.approx_queries > 0:
@@ -380,6 +406,7 @@ def main() -> int:
         "f32_residues": f32_leg,
         "approx_speedppr": approx,
         "batched_widths": widths,
+        "host_output": host_out,
         "single_source": single,
         "cpu_baseline": cpu,
         "paper_context": {"figure": "PowerPush < 40 s per query (no GPU or throughput figures in the paper)",
