@@ -97,10 +97,13 @@ class Server:
     block's enqueued work, retire the finished slots, refill the free slots
     from the graph's queue, enqueue the next sweeps.  The library calls
     release the interpreter lock, so one block's waits (and the local phase
-    of newly admitted queries) never hold up the others."""
+    of newly admitted queries) never hold up the others.  A step runs until
+    the longest current stage among its running slots ends, at most
+    sweeps_per_step sweeps; the default 32 lies above the usual stage
+    length, so a stage is not split across host round trips."""
 
     def __init__(self, graphs, budget_bytes: int, slots: int = 32, alpha: float = 0.2,
-                 sweeps_per_step: int = 8, max_queue: int = 100000, keep_results: bool = False):
+                 sweeps_per_step: int = 32, max_queue: int = 100000, keep_results: bool = False):
         import threading
         import torch
         import paper_2101_03652_amd as P
@@ -329,7 +332,7 @@ def main() -> int:
     ap.add_argument("--alpha", type=float, default=0.2)
     ap.add_argument("--queries", type=int, default=400, help="queries per arrival rate")
     ap.add_argument("--rates", default="0.3,0.7,1.0", help="fractions of the saturated throughput")
-    ap.add_argument("--sweeps-per-step", type=int, default=8)
+    ap.add_argument("--sweeps-per-step", type=int, default=32)
     ap.add_argument("--budget-gib", type=float, default=0.0, help="0 = 90%% of free device memory")
     args = ap.parse_args()
 
