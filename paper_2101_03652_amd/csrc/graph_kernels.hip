@@ -33,7 +33,7 @@ __global__ void count_kernel(const int32_t* __restrict__ col, int64_t m,
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kBlock * kScanItems;      // 4096 elements per tile
 constexpr int kScanTopThreads = 1024;
-constexpr int kScanTopItems = 64;                   // up to 65536 tiles
+constexpr int kScanTopItems = 64;                   // scan_top takes up to 65536 tiles (larger scans recurse)
 
 __device__ inline int64_t block_exclusive_scan(int64_t v, int64_t* sh, int64_t* total) {
     // Hillis-Steele over the block (kBlock threads) in shared memory
@@ -65,30 +65,30 @@ __global__ void scan_tiles_reduce(const int64_t* __restrict__ in, int64_t len, i
     if (threadIdx.x == 0) tile_sums[blockIdx.x] = tot;
 }
 
-__global__ void scan_top(int64_t* __restrict__ tile_sums, int64_t ntiles) {
-    // single workgroup of kScanTopThreads: exclusive scan in place
+__global__ __launch_bounds__(kScanTopThreads) void scan_top(int64_t* __restrict__ tile_sums, int64_t ntiles) {
+    // single workgroup: exclusive scan in place, kScanTopThreads tile sums per
+    // round (one load and one store per thread) with a running carry; no
+    // per-thread arrays, so nothing spills and a small scan is two memory
+    // round trips (it sits on the critical path of every frontier level)
     __shared__ int64_t sh[kScanTopThreads];
-    int t = threadIdx.x;
-    int64_t local[kScanTopItems];
-    int64_t s = 0;
-    for (int i = 0; i < kScanTopItems; ++i) {
-        int64_t idx = (int64_t)t * kScanTopItems + i;
-        local[i] = (idx < ntiles) ? tile_sums[idx] : 0;
-        s += local[i];
-    }
-    sh[t] = s;
-    __syncthreads();
-    for (int off = 1; off < kScanTopThreads; off <<= 1) {
-        int64_t add = (t >= off) ? sh[t - off] : 0;
+    const int t = threadIdx.x;
+    int64_t carry = 0;
+    for (int64_t base = 0; base < ntiles; base += kScanTopThreads) {
+        const int64_t idx = base + t;
+        const int64_t v = (idx < ntiles) ? tile_sums[idx] : 0;
+        sh[t] = v;
         __syncthreads();
-        sh[t] += add;
-        __syncthreads();
-    }
-    int64_t run = sh[t] - s;
-    for (int i = 0; i < kScanTopItems; ++i) {
-        int64_t idx = (int64_t)t * kScanTopItems + i;
-        if (idx < ntiles) tile_sums[idx] = run;
-        run += local[i];
+        for (int off = 1; off < kScanTopThreads; off <<= 1) {
+            const int64_t add = (t >= off) ? sh[t - off] : 0;
+            __syncthreads();
+            sh[t] += add;
+            __syncthreads();
+        }
+        const int64_t incl = sh[t];
+        const int64_t total = sh[kScanTopThreads - 1];
+        if (idx < ntiles) tile_sums[idx] = carry + incl - v;
+        carry += total;
+        __syncthreads();                           // sh is rewritten by the next round
     }
 }
 
