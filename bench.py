@@ -62,12 +62,12 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(width: int, chunks: int, residues: str):
+def measured_traffic(width: int, chunks: int, residues: str, tile: int):
     """HBM bytes per global sweep (its sweep_k and combine_k launches) from
     the committed rocprofv3 counter runs (FETCH_SIZE + WRITE_SIZE, each scaled
     by the same counter's reading for a plain 1 GiB copy), or None when they
-    were taken on another kernel build, width, chunk count or residue
-    storage."""
+    were taken on another kernel build, width, chunk count, residue storage
+    or row tile."""
     path = os.path.join(ROOT, "profiles", "sweep_k_traffic.json")
     try:
         with open(path) as f:
@@ -75,7 +75,8 @@ def measured_traffic(width: int, chunks: int, residues: str):
     except (OSError, ValueError):
         return None
     if (t.get("source_digest") != kernel_source_digest() or t.get("batch_cols") != width
-            or t.get("sweep_chunks") != chunks or t.get("residues") != residues):
+            or t.get("sweep_chunks") != chunks or t.get("residues") != residues
+            or t.get("sweep_tile_bytes") != tile):
         return None
     return t.get("bytes_per_sweep")
 
@@ -92,6 +93,8 @@ def main() -> int:
     ap.add_argument("--lam", type=float, default=1e-8)
     ap.add_argument("--alpha", type=float, default=0.2)
     ap.add_argument("--batch-cols", type=int, default=0, help="0 = autotuned")
+    ap.add_argument("--sweep-tile", type=int, default=0,
+                    help="LDS stage bytes of a sweep block (0 = the autotuner's choice, else 16384)")
     ap.add_argument("--fp64-queries", type=int, default=8)
     ap.add_argument("--fp64-epoch-queries", type=int, default=4,
                     help="FP64 queries with Algorithm 3's epoch thresholds in the global phase")
@@ -145,7 +148,8 @@ def main() -> int:
     out = torch.empty((args.sources, g.n), dtype=torch.float64, device="cuda")
 
     def step():
-        return G.query_batch(srcs, args.alpha, args.lam, P.MIXED, out=out, batch_cols=width)[1]
+        return G.query_batch(srcs, args.alpha, args.lam, P.MIXED, out=out, batch_cols=width,
+                             sweep_tile=args.sweep_tile)[1]
 
     for _ in range(args.warmup):
         step()
@@ -343,7 +347,8 @@ def main() -> int:
     omegas = sorted({round(s["sor_omega"], 4) for sts in stats_all for s in sts})
     sk_name = (f"sweep_k<C={width // (8 if bf16 else 4)}{', over-relaxed' if over_relaxed else ''}"
                f"{', bf16 residues' if bf16 else ''}>")
-    traffic = measured_traffic(width, chunks, "bf16" if bf16 else "f32")
+    tile = stats_all[0][0]["sweep_tile_bytes"]
+    traffic = measured_traffic(width, chunks, "bf16" if bf16 else "f32", tile)
 
     cpu = None
     if args.cpu_baseline:
@@ -386,6 +391,7 @@ def main() -> int:
                         f"{'bf16' if bf16 else 'FP32'} residue storage (FP32 arithmetic, FP64 certificate)",
             "n": g.n, "m": g.m, "sources_per_step": args.sources, "batch_cols": width, "sweep_chunks": chunks,
             "sor_omega_final": omegas, "residue_storage": "bf16" if bf16 else "f32",
+            "sweep_tile_bytes": tile,
             "alpha": args.alpha, "lambda": args.lam,
         },
         "gteps": round(edges / dt / 1e9, 3),

@@ -106,6 +106,9 @@ typedef struct {
                                PPR_RESIDUE_BF16 (PPR_FP64: F32, though it sweeps in double) */
     int32_t push_scans;     /* PPR_GLOBAL_EPOCHS: scans taken in push form (the rest of
                                `sweeps` in pull form); 0 otherwise */
+    int32_t sweep_tile_bytes; /* LDS stage of a batched sweep block (its row tile: in-edges
+                               and rows per block), chosen per width by ppr_autotune;
+                               0 for PPR_FP64 */
 } ppr_stats;
 
 /* Global phase of the PPR_FP64 path. */
@@ -160,6 +163,10 @@ typedef struct {
     int32_t residue_format; /* PPR_MIXED: ppr_residue_format; default PPR_RESIDUE_AUTO */
     int32_t scan_form;      /* PPR_FP64 with PPR_GLOBAL_EPOCHS: ppr_scan_form; default
                                PPR_SCAN_AUTO */
+    int32_t sweep_tile;     /* PPR_MIXED: LDS stage (row tile) of a sweep block in bytes,
+                               12288, 16384 or 24576; 0 = the tile ppr_autotune chose for
+                               the block width on this graph, else 16384 (default).  Any
+                               other value: PPR_ERR_ARG */
 } ppr_options;
 
 /* Read-only facts about a created graph. */
@@ -404,23 +411,30 @@ ppr_status ppr_debug_sweep_mixed(ppr_graph* g, double alpha, int32_t B, int32_t 
  *     accumulator after the sequence, i.e. t_in (unless entry 2), plus y_in
  *     for entry columns with a budget of at least one sweep, plus every
  *     residue the column's sweeps stored.
+ *   sweep_tile: the LDS stage of a sweep block as ppr_options.sweep_tile
+ *     (0: the graph's choice for width B).
  *   Other arguments as ppr_debug_sweep_mixed; PPR_ERR_ARG for values out of
  *   range.
  */
 ppr_status ppr_debug_sweeps_mixed(ppr_graph* g, double alpha, int32_t B, int32_t chunks, int32_t sweeps,
                                   const float* y_in, const int32_t* entry, const int32_t* budget,
                                   const float* t_in, float* y_out, float* t_out, const float* omega,
-                                  int32_t residue_format);
+                                  int32_t residue_format, int32_t sweep_tile);
 
 /*
  * Autotuner of the batched path: for each candidate block width (a power of
  * two in [4, 128]; widths NULL = {8, 16, 32, 64, 128}) whose state fits half
- * of the free device memory, time a few global sweeps on this graph with
- * HIP events and pick the width with the lowest time per column-sweep.  The
- * choice is kept in the graph and used when ppr_options.batch_cols = 0.
+ * of the free device memory, and for each row tile of the sweep (an LDS
+ * stage of 12, 16 or 24 KB per block, which sets the in-edges and rows a
+ * block takes), time a few global sweeps on this graph with HIP events.
+ * Each width keeps its fastest tile (16 KB unless another is more than 1%
+ * faster), and the width with the lowest time per column-sweep wins.  Both
+ * choices are kept in the graph: the tiles for every later batched block of
+ * that width (queries and serving blocks), the width for ppr_options.batch_cols = 0.
  *   widths: host int32[count] or NULL.  best_width: out.  cost_us: out,
  *   host double[count] (or [5] when widths is NULL), microseconds per
- *   column-sweep, -1 for a width skipped for memory; nullable.
+ *   column-sweep at the width's chosen tile, -1 for a width skipped for
+ *   memory; nullable.
  */
 ppr_status ppr_autotune(ppr_graph* g, double alpha, const int32_t* widths, int32_t count,
                         int32_t* best_width, double* cost_us);

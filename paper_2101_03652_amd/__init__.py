@@ -64,7 +64,7 @@ class Stats(ctypes.Structure):
                 ("sweep_ms", ctypes.c_double), ("sweep_launches", ctypes.c_int32),
                 ("batch_cols", ctypes.c_int32), ("sweep_chunks", ctypes.c_int32),
                 ("sor_omega", ctypes.c_double), ("residue_format", ctypes.c_int32),
-                ("push_scans", ctypes.c_int32)]
+                ("push_scans", ctypes.c_int32), ("sweep_tile_bytes", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -95,7 +95,8 @@ class Options(ctypes.Structure):
                 ("certify", ctypes.c_int32), ("refresh_factor", ctypes.c_double),
                 ("batch_cols", ctypes.c_int32), ("sweep_chunks", ctypes.c_int32),
                 ("global_rule", ctypes.c_int32), ("sor_omega", ctypes.c_double),
-                ("residue_format", ctypes.c_int32), ("scan_form", ctypes.c_int32)]
+                ("residue_format", ctypes.c_int32), ("scan_form", ctypes.c_int32),
+                ("sweep_tile", ctypes.c_int32)]
 
 
 class GraphInfo(ctypes.Structure):
@@ -136,7 +137,7 @@ def load() -> ctypes.CDLL:
         "ppr_debug_sweep_fp64": (st, [vp, f64, vp, vp, vp, vp]),
         "ppr_autotune": (st, [vp, f64, vp, i32, vp, vp]),
         "ppr_debug_sweep_mixed": (st, [vp, f64, i32, i32, vp, vp, vp, vp, vp, i32]),
-        "ppr_debug_sweeps_mixed": (st, [vp, f64, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, i32]),
+        "ppr_debug_sweeps_mixed": (st, [vp, f64, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, i32, i32]),
         "ppr_block_create": (st, [vp, i32, f64, vp, ctypes.POINTER(vp)]),
         "ppr_block_destroy": (st, [vp]),
         "ppr_block_footprint": (st, [vp, i32, vp]),
@@ -317,8 +318,9 @@ class Graph:
         return nw.value
 
     def autotune(self, alpha: float = 0.2, widths=None) -> dict:
-        """Pick the batched block width by timing sweeps on this graph; the
-        choice becomes the default of later batched queries."""
+        """Pick the batched block width, and the sweep row tile for each width,
+        by timing sweeps on this graph; the choices become the defaults of
+        later batched queries and serving blocks."""
         w = None if widths is None else np.ascontiguousarray(widths, dtype=np.int32)
         cnt = 5 if w is None else len(w)
         cost = np.zeros(cnt, dtype=np.float64)
@@ -419,11 +421,13 @@ def debug_sweep_mixed(graph: "Graph", alpha: float, y_in, fresh, chunks: int = 1
 
 
 def debug_sweeps_mixed(graph: "Graph", alpha: float, y_in, entry, sweeps: int, budget=None, t_in=None,
-                       chunks: int = 1, t_out=None, omega=None, residue_format: int = RESIDUE_F32):
+                       chunks: int = 1, t_out=None, omega=None, residue_format: int = RESIDUE_F32,
+                       sweep_tile: int = 0):
     """One launch sequence of `sweeps` batched global sweeps carrying the
     stage accumulator.  entry: B flags (0 continuing, 1 fresh, 2 fresh with
     the accumulator restarting); budget: B sweep counts in [0, sweeps] (None:
-    all); t_in: float32[n, B] initial accumulator (None: 0).  Returns y_out
+    all); t_in: float32[n, B] initial accumulator (None: 0); sweep_tile: LDS
+    stage bytes of a sweep block (0: the graph's choice).  Returns y_out
     (same kind as y_in); t_out, if given, receives the accumulator."""
     B = int(y_in.shape[1])
     en = np.ascontiguousarray(np.asarray(entry, dtype=np.int32).reshape(-1))
@@ -443,7 +447,8 @@ def debug_sweeps_mixed(graph: "Graph", alpha: float, y_in, entry, sweeps: int, b
                                          _ptr(en), _ptr(kb) if kb is not None else None,
                                          _ptr(t_in) if t_in is not None else None, _ptr(y_out),
                                          _ptr(t_out) if t_out is not None else None,
-                                         _ptr(om) if om is not None else None, int(residue_format)))
+                                         _ptr(om) if om is not None else None, int(residue_format),
+                                         int(sweep_tile)))
     return y_out
 
 

@@ -62,6 +62,13 @@ int sweep_chunks(const Graph& g, const ppr_options& opt) {
     return (int)std::max<int64_t>(1, std::min<int64_t>(8, g.m >> 21));
 }
 
+// LDS stage (row tile) of the sweep blocks at width Bw: the autotuner's
+// choice for this graph and width, else the default.
+int sweep_tile(const Graph& g, int Bw) {
+    const int t = g.tuned_tile[ilog2(Bw) & 7];
+    return t > 0 ? t : mk::kLdsBytes;
+}
+
 // Automatic over-relaxation factor of block Gauss-Seidel sweeps.  On
 // Chung-Lu power-law graphs (n = 4M, m = 70M, 8 chunks, lambda = 1e-8) the
 // sweeps per query go 46.6 -> 34.5 -> 31.6 -> 38.9 -> 52.0 for omega = 1,
@@ -97,10 +104,10 @@ int64_t frontier_capacity(const Graph& g, const ppr_options& opt, int Bw) {
 
 size_t mixed_footprint(const Graph& g, int Bw, int64_t fcap, bool bf16) {
     const size_t nb = (size_t)g.n * (size_t)Bw;
-    // long-row pieces: each holds piece_cap = kLongRounds kLdsBytes / (4 Bw)
-    // in-edges of a row with more than piece_cap, so there are fewer than
-    // 2 m / piece_cap
-    const size_t piece_cap = (size_t)mk::kLongRounds * mk::kLdsBytes / (4 * (size_t)Bw);
+    // long-row pieces: each holds piece_cap = kLongRounds L / (4 Bw) in-edges
+    // of a row with more than piece_cap (L the sweep stage, at least
+    // kMinTile), so there are fewer than 2 m / piece_cap
+    const size_t piece_cap = (size_t)mk::kLongRounds * mk::kMinTile / (4 * (size_t)Bw);
     const size_t pieces = 2 * (size_t)g.m / piece_cap + 1;
     return 16 * nb                       // FP64 local-phase scratch
            + (bf16 ? 24 : 28) * nb       // Y0, Y1 (4 or 2 bytes), S, AS (8), T (4)
@@ -226,11 +233,22 @@ struct Block {
         if (Bw < 4 || Bw > 128 || (Bw & (Bw - 1))) fail(PPR_ERR_ARG, "block width must be a power of two in [4, 128]");
         if (opt.residue_format == PPR_RESIDUE_BF16 && Bw < 8)
             fail(PPR_ERR_ARG, "bf16 residues need a block of at least 8 columns");
+        int tile = sweep_tile(g, Bw);
+        if (opt.sweep_tile != 0) {
+            bool known = false;
+            for (int t : mk::kTiles) known |= (t == opt.sweep_tile);
+            if (!known) fail(PPR_ERR_ARG, "sweep_tile must be 0, 12288, 16384 or 24576");
+            tile = opt.sweep_tile;
+        }
         c = mixed_acquire(g, Bw, frontier_capacity(g, opt, Bw), residues_bf16(opt, Bw));
         const int chunks = sweep_chunks(g, opt);
         if (c->chunks != chunks) {
             c->drop_chunks();
             c->chunks = chunks;
+        }
+        if (c->tile != tile) {
+            c->drop_chunks();
+            c->tile = tile;
         }
         mk::prepare(*c, g);
         c->sor = false;              // set per launch sequence by step()
@@ -616,6 +634,7 @@ struct Block {
         st->sor_omega = sl.omega;
         st->residue_format = c->bf16 ? PPR_RESIDUE_BF16 : PPR_RESIDUE_F32;
         st->push_scans = 0;
+        st->sweep_tile_bytes = c->tile;
     }
 
     // Export slot b (DONE) into out[n] (host or device) and free the slot;
@@ -760,18 +779,40 @@ void autotune_width(Graph& g, double alpha, const int32_t* widths, int32_t count
         blk.upload_i32(c.kb, kb);
         blk.upload_i32(c.entry, zero);
         blk.set_steps(1 << 30);              // odd and even steps alternate, as in a query
+        // each candidate row tile (LDS stage of a sweep block); the default
+        // stage keeps the width unless another is more than 1% faster
         const int reps = 4;
-        mk::sweep(c, g, c.Y0.p, c.Y1.p);     // warm-up
-        EventPair ev;
-        ev.start(ss);
-        for (int r = 0; r < reps; ++r) mk::sweep(c, g, (r & 1) ? c.Y1.p : c.Y0.p, (r & 1) ? c.Y0.p : c.Y1.p);
-        ev.stop(ss);
-        HIPCHECK(hipStreamSynchronize(ss));
+        double tile_us[mk::kTileCount];
+        for (int ti = 0; ti < mk::kTileCount; ++ti) {
+            c.drop_chunks();
+            c.tile = mk::kTiles[ti];
+            mk::prepare(c, g);                   // the tile's schedule and piece buffer
+            mk::sweep(c, g, c.Y0.p, c.Y1.p);     // warm-up
+            EventPair ev;
+            ev.start(ss);
+            for (int r = 0; r < reps; ++r) mk::sweep(c, g, (r & 1) ? c.Y1.p : c.Y0.p, (r & 1) ? c.Y0.p : c.Y1.p);
+            ev.stop(ss);
+            HIPCHECK(hipStreamSynchronize(ss));
+            tile_us[ti] = ev.elapsed_ms() * 1e3 / reps / W;
+        }
+        int tile = mk::kLdsBytes;
+        double us = 0.0;
+        for (int ti = 0; ti < mk::kTileCount; ++ti)
+            if (mk::kTiles[ti] == mk::kLdsBytes) us = tile_us[ti];
+        const double us_default = us;
+        for (int ti = 0; ti < mk::kTileCount; ++ti)
+            if (tile_us[ti] < us_default * 0.99 && tile_us[ti] < us) {
+                us = tile_us[ti];
+                tile = mk::kTiles[ti];
+            }
+        g.tuned_tile[ilog2(W) & 7] = tile;
+        c.drop_chunks();
+        c.tile = tile;
+        mk::prepare(c, g);
         blk.upload_i32(c.kb, zero);
         for (DevBuf* b : {&c.Y0, &c.Y1, &c.T}) HIPCHECK(hipMemsetAsync(b->p, 0, b->bytes, ss));
         HIPCHECK(hipStreamSynchronize(ss));
         c.ycur = c.Y0.p;
-        double us = ev.elapsed_ms() * 1e3 / reps / W;
         if (cost_us) cost_us[i] = us;
         // the narrower block wins ties (within 1%): less memory, lower latency
         if (best_w == 0 || us < best_cost * 0.99) {
@@ -788,12 +829,13 @@ void autotune_width(Graph& g, double alpha, const int32_t* widths, int32_t count
 
 void debug_sweeps_mixed(Graph& g, double alpha, int32_t B, int32_t chunks, int32_t sweeps, const float* y_in,
                         const int32_t* entry, const int32_t* budget, const float* t_in, float* y_out,
-                        float* t_out, const float* omega, int32_t residue_format) {
+                        float* t_out, const float* omega, int32_t residue_format, int32_t sweep_tile) {
     HIPCHECK(hipSetDevice(g.device));
     ppr_options opt;
     ppr_options_default(&opt);
     opt.sweep_chunks = chunks;
     opt.residue_format = residue_format;
+    opt.sweep_tile = sweep_tile;
     Block blk(g, B, alpha, opt);
     MixedCtx& c = *blk.c;
     hipStream_t ss = c.stream;

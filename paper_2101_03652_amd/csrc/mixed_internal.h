@@ -7,18 +7,25 @@ namespace ppr {
 
 namespace mk {
 constexpr int kBlock = 256;
-constexpr int kLdsBytes = 16384;   // staging budget of the sweep / refresh blocks
+constexpr int kLdsBytes = 16384;   // default LDS stage of a sweep block (its row tile)
+// Sweep stages the autotuner tries per block width (3, 4 or 6 gathers of 16
+// bytes in flight per thread); the smallest bounds the long-row piece count.
+constexpr int kTileCount = 3;
+constexpr int kTiles[kTileCount] = {12288, 16384, 24576};
+constexpr int kMinTile = 12288;
 constexpr int kGridRed = 2048;     // persistent grid of the refresh (fixed -> deterministic sums)
 constexpr int kLongRounds = 8;     // edge rounds one sweep block runs on a long row
 constexpr int kRefreshRounds = 1 << 20;   // a refresh block runs a long row whole
 
-// Sweep blocks: <= kNnz in-edges (B = 4C columns, C float4 chunks) and <= kRows rows.
-template <int C>
+// Sweep blocks with an L-byte LDS stage: <= kNnz in-edges (C 16-byte vectors
+// per row) and <= kRows rows.
+template <int C, int L = kLdsBytes>
 struct Sw {
-    static constexpr int kNnz = kLdsBytes / (16 * C);
+    static constexpr int kNnz = L / (16 * C);
     static constexpr int kRows = kBlock / C;
-    static constexpr int kItems = kNnz * C / kBlock;   // = 4
+    static constexpr int kItems = kNnz * C / kBlock;   // 3, 4 or 6
     static constexpr int kSlots = kBlock / C;
+    static_assert(kItems * kBlock == kNnz * C, "a stage holds a whole number of gathers per thread");
 };
 // Refresh blocks gather the in-neighbours' stage accumulator rows (16 C bytes
 // per edge) through a 32 KB stage per round.
@@ -37,6 +44,7 @@ struct MixedCtx {
     int32_t n = 0;
     int Bw = 0, shift = 0;
     int chunks = 1;                   // row chunks per sweep (block Gauss-Seidel order when > 1)
+    int tile = mk::kLdsBytes;         // LDS stage of a sweep block, one of mk::kTiles
     double alpha = -1.0;              // alpha the scale table holds
     int64_t fcap = 0;                 // frontier capacity (entries)
     DevBuf r64, pi64;                 // double[n][Bw]  local-phase scratch, zero between uses

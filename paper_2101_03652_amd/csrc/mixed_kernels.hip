@@ -39,6 +39,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "mixed_internal.h"
 
@@ -312,8 +313,8 @@ __global__ void scale_k(const int32_t* __restrict__ deg, int32_t n, double alpha
 // set holds a fresh residue in Y_in that nobody has pulled yet: its rows pull
 // it along every in-edge, in addition to the new values of earlier chunks.
 //
-// Schedule blocks: up to Sw<C>::kRows whole rows with <= Sw<C>::kNnz in-edges
-// (one round), or one long row of up to kLongRounds rounds of Sw<C>::kNnz
+// Schedule blocks: up to Sw<C, L>::kRows whole rows with <= Sw<C, L>::kNnz in-edges
+// (one round), or one long row of up to kLongRounds rounds of Sw<C, L>::kNnz
 // in-edges, or one piece (kLongRounds rounds) of a longer row.  C is the
 // number of 16-byte vectors per row (B / 4 in FP32, B / 8 in bf16).  Per
 // round, indices are loaded first, then every thread has kItems 16-byte
@@ -418,17 +419,17 @@ __device__ inline void finish_row(int32_t u, int c, Vec<ST::K> acc, int32_t step
     }
 }
 
-template <typename OffT, int C, bool SOR, typename ST>
+template <typename OffT, int C, bool SOR, typename ST, int L>
 __global__ __launch_bounds__(kBlock) void sweep_k(
         const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
         const RowBlock* __restrict__ blocks, int32_t lo, const float* __restrict__ scale,
         const typename ST::V* __restrict__ Y_in, typename ST::V* Y_out, float4* __restrict__ T,
         const int32_t* __restrict__ kb, const int32_t* __restrict__ entry, const int32_t* __restrict__ step_p,
         Vec<ST::K>* __restrict__ partials, const float* __restrict__ omega) {
-    using P = Sw<C>;
+    using P = Sw<C, L>;
     constexpr int K = ST::K, Q = K / 4;
     static_assert(sizeof(typename ST::V) == 16, "a staged vector is 16 bytes");
-    __shared__ typename ST::V lds[kLdsBytes / 16];
+    __shared__ typename ST::V lds[L / 16];
     const RowBlock b = blocks[blockIdx.x];
     const int32_t step = step_p[0];
     // every item of this thread belongs to column chunk threadIdx.x % C
@@ -718,18 +719,28 @@ __global__ void export_col_k(int32_t n, int shift, int32_t b, const int32_t* __r
 }
 
 // ---------------------------------------------------------------- launch helpers
-template <int C>
+template <int C, int L>
 const Schedule& sweep_schedule(Graph& g, int chunks) {
-    return g.schedule(Sw<C>::kNnz, Sw<C>::kRows, chunks, kLongRounds);
+    return g.schedule(Sw<C, L>::kNnz, Sw<C, L>::kRows, chunks, kLongRounds);
+}
+// f(std::integral_constant<int, L>) for the context's sweep stage L
+template <typename F>
+void by_tile(int tile, F&& f) {
+    switch (tile) {
+        case kTiles[0]: f(std::integral_constant<int, kTiles[0]>{}); break;
+        case kTiles[1]: f(std::integral_constant<int, kTiles[1]>{}); break;
+        case kTiles[2]: f(std::integral_constant<int, kTiles[2]>{}); break;
+        default: fail(PPR_ERR_ARG, "unsupported sweep tile");
+    }
 }
 template <int C>
 const Schedule& refresh_schedule(Graph& g) {
     return g.schedule(Rf<C>::kNnz, Rf<C>::kRows, 1, kRefreshRounds);   // long rows whole, in rounds
 }
 
-template <int C, bool SOR, typename ST>
+template <int C, bool SOR, typename ST, int L>
 void sweep_launch(MixedCtx& c, Graph& g, const void* yin, void* yout) {
-    const Schedule& sch = sweep_schedule<C>(g, c.chunks);
+    const Schedule& sch = sweep_schedule<C, L>(g, c.chunks);
     auto Y4i = reinterpret_cast<const typename ST::V*>(yin);
     auto Y4o = reinterpret_cast<typename ST::V*>(yout);
     const RowBlock* blocks = sch.blocks.as<RowBlock>();
@@ -742,12 +753,12 @@ void sweep_launch(MixedCtx& c, Graph& g, const void* yin, void* yout) {
         dim3 grid((unsigned)nb), blk(kBlock);
         const RowBlock* bj = blocks + sch.first[j];
         if (g.off64)
-            hipLaunchKernelGGL((sweep_k<int64_t, C, SOR, ST>), grid, blk, 0, c.stream, g.col_ptr.as<int64_t>(),
+            hipLaunchKernelGGL((sweep_k<int64_t, C, SOR, ST, L>), grid, blk, 0, c.stream, g.col_ptr.as<int64_t>(),
                                g.row_idx.as<int32_t>(), bj, sch.lo[j], c.scale.as<float>(), Y4i, Y4o,
                                c.T.as<float4>(), c.kb.as<int32_t>(), c.entry.as<int32_t>(), c.step.as<int32_t>(),
                                part, om);
         else
-            hipLaunchKernelGGL((sweep_k<uint32_t, C, SOR, ST>), grid, blk, 0, c.stream, g.col_ptr.as<uint32_t>(),
+            hipLaunchKernelGGL((sweep_k<uint32_t, C, SOR, ST, L>), grid, blk, 0, c.stream, g.col_ptr.as<uint32_t>(),
                                g.row_idx.as<int32_t>(), bj, sch.lo[j], c.scale.as<float>(), Y4i, Y4o,
                                c.T.as<float4>(), c.kb.as<int32_t>(), c.entry.as<int32_t>(), c.step.as<int32_t>(),
                                part, om);
@@ -767,17 +778,20 @@ void sweep_launch(MixedCtx& c, Graph& g, const void* yin, void* yout) {
 // C = B / 4; bf16 sweeps run C / 2 vectors of 8 columns per row
 template <int C>
 void sweep_c(MixedCtx& c, Graph& g, const void* yin, void* yout) {
-    if (c.bf16) {
-        if constexpr (C >= 2) {
-            if (c.sor) sweep_launch<C / 2, true, StoreBF16x8>(c, g, yin, yout);
-            else sweep_launch<C / 2, false, StoreBF16x8>(c, g, yin, yout);
+    by_tile(c.tile, [&](auto tl) {
+        constexpr int L = decltype(tl)::value;
+        if (c.bf16) {
+            if constexpr (C >= 2) {
+                if (c.sor) sweep_launch<C / 2, true, StoreBF16x8, L>(c, g, yin, yout);
+                else sweep_launch<C / 2, false, StoreBF16x8, L>(c, g, yin, yout);
+            } else {
+                fail(PPR_ERR_ARG, "bf16 residues need a block of at least 8 columns");
+            }
         } else {
-            fail(PPR_ERR_ARG, "bf16 residues need a block of at least 8 columns");
+            if (c.sor) sweep_launch<C, true, StoreF32, L>(c, g, yin, yout);
+            else sweep_launch<C, false, StoreF32, L>(c, g, yin, yout);
         }
-    } else {
-        if (c.sor) sweep_launch<C, true, StoreF32>(c, g, yin, yout);
-        else sweep_launch<C, false, StoreF32>(c, g, yin, yout);
-    }
+    });
 }
 
 template <int C, typename ST>
@@ -879,12 +893,15 @@ void prepare(MixedCtx& c, const Graph& g) {
     by_width(c.Bw, [&](auto cc) {
         constexpr int C = decltype(cc)::value;
         int32_t n_pieces = 0;
-        if (c.bf16) {
-            if constexpr (C >= 2) n_pieces = sweep_schedule<C / 2>(gg, c.chunks).n_pieces;
-            else fail(PPR_ERR_ARG, "bf16 residues need a block of at least 8 columns");
-        } else {
-            n_pieces = sweep_schedule<C>(gg, c.chunks).n_pieces;
-        }
+        by_tile(c.tile, [&](auto tl) {
+            constexpr int L = decltype(tl)::value;
+            if (c.bf16) {
+                if constexpr (C >= 2) n_pieces = sweep_schedule<C / 2, L>(gg, c.chunks).n_pieces;
+                else fail(PPR_ERR_ARG, "bf16 residues need a block of at least 8 columns");
+            } else {
+                n_pieces = sweep_schedule<C, L>(gg, c.chunks).n_pieces;
+            }
+        });
         const size_t need = (size_t)std::max(n_pieces, 1) * (size_t)c.Bw * 4;   // FP32 per piece and column
         if (c.piece_part.bytes < need) {
             c.drop_chunks();                   // a captured chunk holds the old buffer

@@ -137,6 +137,7 @@ struct Graph {
     std::vector<std::unique_ptr<QueryCtx>> pool;       // idle FP64 query contexts
     std::vector<MixedCtxPtr> mixed_pool;               // idle batched contexts (any width)
     int tuned_width = 0;                               // autotuner's choice (0 = not tuned)
+    int tuned_tile[8] = {};                            // sweep stage bytes per log2(width) (0 = default)
     DevBuf walk_index;                                 // int32[m]: stop nodes of d_v walks per node
     double walk_alpha = -1.0;                          // the index's alpha (-1: none)
     uint64_t walk_seed = 0;                            // the index's seed
@@ -270,7 +271,7 @@ void autotune_width(Graph& g, double alpha, const int32_t* widths, int32_t count
 
 void debug_sweeps_mixed(Graph& g, double alpha, int32_t B, int32_t chunks, int32_t sweeps, const float* y_in,
                         const int32_t* entry, const int32_t* budget, const float* t_in, float* y_out,
-                        float* t_out, const float* omega, int32_t residue_format);
+                        float* t_out, const float* omega, int32_t residue_format, int32_t sweep_tile);
 
 // serving blocks (continuous batching); the handle is an opaque Block*
 void* serve_block_create(Graph& g, int32_t slots, double alpha, const ppr_options& opt);

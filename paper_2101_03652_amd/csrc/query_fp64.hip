@@ -339,6 +339,7 @@ void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_
         st->sor_omega = 1.0;
         st->residue_format = PPR_RESIDUE_F32;
         st->push_scans = push_scans;
+        st->sweep_tile_bytes = 0;
         st->local_levels = levels;
         st->sweeps = sweeps;
         st->refreshes = 0;

@@ -297,3 +297,75 @@ def test_sweep_sequence_arguments(graphs):
         with pytest.raises(P.PPRError):
             P.debug_sweeps_mixed(G, ALPHA, y, args["entry"], args["sweeps"], budget=args.get("budget"))
     G.close()
+
+
+@pytest.mark.parametrize("tile", [12288, 24576])
+@pytest.mark.parametrize("name", ["c1", "hub"])
+@pytest.mark.parametrize("width,chunks,fmt", [(32, 3, "f32"), (128, 4, "f32"), (32, 8, "bf16"), (128, 8, "bf16")])
+def test_sweep_tiles_match_oracle(graphs, tile, name, width, chunks, fmt):
+    """The row tiles the autotuner may pick (LDS stages of 12 and 24 KB; the
+    16 KB default is the tile of the tests above) compute the same sweep:
+    other in-edge counts per block, rows per block and long-row pieces, the
+    same bounds as above."""
+    g = graphs[name]
+    print(f"[gpu] sweep tile parity tile={tile} {name} width={width} chunks={chunks} {fmt}", flush=True)
+    G = P.Graph.from_synth(g)
+    rng = np.random.default_rng(tile + width * 7 + chunks)
+    y = rng.random((g.n, width)).astype(np.float32)
+    y[rng.random((g.n, width)) < 0.3] = 0.0
+    fresh = (rng.random(width) < 0.5).astype(np.int32)
+    fresh[0], fresh[-1] = 1, 0
+    bf16 = fmt == "bf16"
+    t_out = np.empty_like(y)
+    got = P.debug_sweeps_mixed(G, ALPHA, y, fresh, 1, chunks=chunks, t_out=t_out, sweep_tile=tile,
+                               residue_format=P.RESIDUE_BF16 if bf16 else P.RESIDUE_F32)
+    yin = _bf16(y) if bf16 else y
+    csc_arrays = oracle.csc(g)
+    din = np.diff(csc_arrays[0]).astype(np.float64)
+    lo = oracle.chunk_bounds(g, chunks)
+    chunk_of = np.searchsorted(lo, np.arange(g.n), side="right") - 1
+    for b in range(width):
+        want = oracle.block_gs_sweep(g, ALPHA, lo, yin[:, b].astype(np.float64), bool(fresh[b]),
+                                     csc_arrays=csc_arrays)
+        if bf16:
+            rounds = chunk_of + 1 + (1 if fresh[b] else 0) * (chunk_of > 0)
+            rel = (1.0 + UB) ** rounds - 1.0 + (din + din.max() + 6) * U
+        else:
+            rel = (din + din.max() + 3) * U
+        err = np.abs(got[:, b] - want)
+        assert np.all(err <= rel * want + 1e-38), (b, int(np.argmax(err - rel * want)))
+        t_want = (yin[:, b] if fresh[b] else np.zeros(g.n, np.float32)) + got[:, b]
+        if bf16:
+            np.testing.assert_array_equal(t_out[:, b], t_want.astype(np.float32))
+        else:
+            assert np.all(np.abs(t_out[:, b] - t_want) <= 2 * U * t_want + 1e-38), b
+    G.close()
+
+
+def test_tiled_queries_and_tile_errors(graphs):
+    """Whole batched queries at each row tile are certified and report their
+    tile; the autotuner keeps one of the candidate tiles for every width it
+    times and the width's queries use it; an unknown tile is an argument
+    error."""
+    g = graphs["hub"]
+    G = P.Graph.from_synth(g)
+    srcs = [int(s) for s in synth.sources(g.n, 8)]
+    outs = []
+    for tile in (12288, 16384, 24576):
+        out, st = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=8, sweep_tile=tile)
+        assert all(s["sweep_tile_bytes"] == tile for s in st)
+        assert max(s["cert_l1"] for s in st) <= 1e-8
+        outs.append(out)
+    for o in outs[1:]:                       # each within lambda of pi_s, so within 2 lambda of each other
+        assert np.abs(o - outs[0]).sum(axis=1).max() <= 2e-8 + 1e-9
+    res = G.autotune(ALPHA, widths=[8, 32])
+    for w in (8, 32):
+        _, st = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=w)
+        assert st[0]["sweep_tile_bytes"] in (12288, 16384, 24576)
+        assert max(s["cert_l1"] for s in st) <= 1e-8
+    assert res["best"] in (8, 32)
+    with pytest.raises(P.PPRError):
+        G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=8, sweep_tile=1000)
+    _, st = G.query_batch(srcs[:1], ALPHA, 1e-8, P.FP64)
+    assert st[0]["sweep_tile_bytes"] == 0
+    G.close()
