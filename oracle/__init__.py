@@ -11,7 +11,7 @@ of the paper it restates:
 - ``csc``              -- in-edge lists by counting sort (Section 2's graph, transposed)
 - ``push``             -- the push operation (Section 3.2)
 - ``fifo_fwdpush``     -- Algorithm 2, with the iteration sets S^(j) of Section 4.2
-- ``powerpush``        -- Algorithm 3 as printed (FIFO local phase, epochs of scans)
+- ``powerpush``        -- Algorithm 3 (queue-ordered local phase, epochs of sequential scans)
 - ``powerpush_sync``   -- the level-synchronous schedule of the GPU path:
                           iterations S^(j) pushed simultaneously, then Eq. 7 sweeps, or
                           Algorithm 3's epochs with each scan taken simultaneously
@@ -36,7 +36,9 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_NATIVE_PATH = os.path.join(_HERE, "liboracle_native.so")
 _lib = None
+_native = None
 
 
 class Stats(ctypes.Structure):
@@ -53,7 +55,7 @@ class Stats(ctypes.Structure):
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain x86-64, -O2: the oracle is not tuned)."""
+    """Compile the oracle with gcc (plain x86-64, -O2) for the tests."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-Wall",
@@ -62,17 +64,37 @@ def build(force: bool = True) -> str:
     return _LIB_PATH
 
 
+def build_native() -> str:
+    """Compile the same source for the host it runs on (-O3 -march=native, no
+    floating-point contraction, so the arithmetic stays plain double): the
+    build the timed CPU baseline uses.  Built where it is timed, never shipped:
+    a -march=native object from another machine may not run."""
+    tmp = _NATIVE_PATH + ".tmp"
+    subprocess.check_call(["gcc", "-O3", "-march=native", "-ffp-contract=off", "-fopenmp", "-shared", "-fPIC",
+                           "-Wall", os.path.join(_HERE, "oracle.c"), "-o", tmp, "-lm"])
+    os.replace(tmp, _NATIVE_PATH)
+    return _NATIVE_PATH
+
+
 def _p(a):
     return a.ctypes.data
 
 
-def _load():
-    global _lib
+def _load(native: bool = False):
+    global _lib, _native
+    if native:
+        if _native is None:
+            _native = _bind(ctypes.CDLL(build_native()))
+        return _native
     if _lib is not None:
         return _lib
     if not os.path.exists(_LIB_PATH):
         build()
-    lib = ctypes.CDLL(_LIB_PATH)
+    _lib = _bind(ctypes.CDLL(_LIB_PATH))
+    return _lib
+
+
+def _bind(lib):
     vp, i32, i64, f64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
     lib.oracle_sum.restype = f64
     lib.oracle_sum.argtypes = [i64, vp]
@@ -110,7 +132,6 @@ def _load():
     lib.oracle_mc_phase.argtypes = [i32, vp, vp, f64, f64, u64, i32, vp, vp]
     lib.oracle_powerpush_many.restype = ctypes.c_int
     lib.oracle_powerpush_many.argtypes = [i32, i64, vp, vp, vp, i32, f64, f64, vp, vp, vp, i32]
-    _lib = lib
     return lib
 
 
@@ -163,7 +184,7 @@ def fifo_fwdpush(g, s: int, alpha: float, rmax: float, trace_cap: int = 0):
 
 
 def powerpush(g, s: int, alpha: float, lam: float, trace_cap: int = 0):
-    """Algorithm 3 as printed.  Returns (pi, r, stats, rsum_trace)."""
+    """Algorithm 3.  Returns (pi, r, stats, rsum_trace)."""
     rp, col = _g(g)
     pi = np.zeros(g.n)
     r = np.zeros(g.n)
@@ -278,15 +299,16 @@ def certificate(g, s: int, alpha: float, pi_hat: np.ndarray, want_residual: bool
     return (l1, rt) if want_residual else l1
 
 
-def powerpush_many(g, sources, alpha: float, lam: float, threads: int):
-    """Algorithm 3 on several sources, one query per thread.  Returns (pi[count, n], stats)."""
+def powerpush_many(g, sources, alpha: float, lam: float, threads: int, native: bool = False):
+    """Algorithm 3 on several sources, one query per thread.  Returns (pi[count, n], stats).
+    native: run the -O3 -march=native build of the same source (built here first)."""
     rp, col = _g(g)
     src = np.ascontiguousarray(sources, dtype=np.int32)
     cnt = len(src)
     pi = np.zeros((cnt, g.n))
     r = np.zeros((cnt, g.n))
     st = (Stats * cnt)()
-    rc = _load().oracle_powerpush_many(g.n, g.m, _p(rp), _p(col), _p(src), cnt, alpha, lam,
+    rc = _load(native).oracle_powerpush_many(g.n, g.m, _p(rp), _p(col), _p(src), cnt, alpha, lam,
                                        _p(pi), _p(r), st, int(threads))
     if rc != 0:
         raise MemoryError("oracle_powerpush_many")

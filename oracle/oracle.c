@@ -26,7 +26,8 @@
  *    exactly (Neumaier summation) after the local phase and after every scan
  *    or sweep; termination uses the recomputed value (Algorithm 3);
  *  - an epoch whose condition already fails runs zero scans (Algorithm 3);
- *  - the paper's epoch loop condition r_sum > m * rmax' is used as printed.
+ *  - the epoch loop condition of Algorithm 3, r_sum > m * rmax', is taken
+ *    literally (so epoch i stops at an l1 error of lambda^(i/8)).
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -92,164 +93,249 @@ int oracle_csc(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col,
 }
 
 /* ------------------------------------------------------------------ */
-/* The push operation on v (Section 3.2): alpha of r(v) moves to the    */
-/* reserve of v, the rest is split evenly over the out-neighbours, and  */
-/* r(v) becomes 0.                                                      */
+/* Shared objects of the push-based methods (Sections 3.2, 4 and 5).    */
 /* ------------------------------------------------------------------ */
-void oracle_push(const int64_t* row_ptr, const int32_t* col, double alpha,
-                 double* pi, double* r, int32_t v) {
-    double x = r[v];
-    int64_t d = row_ptr[v + 1] - row_ptr[v];
+
+/* Out-degree d_v of the CSR (Section 2). */
+static int64_t out_degree(const int64_t* row_ptr, int32_t v) { return row_ptr[v + 1] - row_ptr[v]; }
+
+/* Activity (Section 3.2): u is active w.r.t. rmax when r(u) > d_u * rmax,
+   strict, with the product taken in double precision. */
+static int is_active(const int64_t* row_ptr, const double* r, int32_t u, double rmax) {
+    return r[u] > (double)out_degree(row_ptr, u) * rmax;
+}
+
+/* The queue of the forward-push methods (Algorithms 2 and 3): first in,
+   first out, with a membership flag per node ("u not in Q" is a flag that is
+   set on append and cleared on pop), so a node is held at most once and n
+   places suffice.  Each entry also carries the iteration j of Section 4.2
+   it belongs to: the source is in S^(0), and a node appended while a node
+   of S^(j) is processed belongs to S^(j+1). */
+typedef struct {
+    int32_t* node;
+    int32_t* iter;
+    uint8_t* member;
+    int64_t cap, head, size;
+} push_queue;
+
+static int queue_open(push_queue* q, int32_t n) {
+    q->cap = n > 0 ? n : 1;
+    q->node = (int32_t*)malloc(sizeof(int32_t) * (size_t)q->cap);
+    q->iter = (int32_t*)malloc(sizeof(int32_t) * (size_t)q->cap);
+    q->member = (uint8_t*)calloc((size_t)q->cap, 1);
+    q->head = 0;
+    q->size = 0;
+    return q->node && q->iter && q->member;
+}
+
+static void queue_close(push_queue* q) {
+    free(q->node);
+    free(q->iter);
+    free(q->member);
+}
+
+static void queue_append(push_queue* q, int32_t u, int32_t j) {
+    int64_t at = (q->head + q->size) % q->cap;
+    q->node[at] = u;
+    q->iter[at] = j;
+    q->member[u] = 1;
+    q->size++;
+}
+
+static int32_t queue_pop(push_queue* q, int32_t* j) {
+    int32_t v = q->node[q->head];
+    *j = q->iter[q->head];
+    q->head = (q->head + 1) % q->cap;
+    q->size--;
+    q->member[v] = 0;
+    return v;
+}
+
+/* The push operation on v (Section 3.2): the residue x = r(v) is taken
+   first (r(v) = 0, so that a self-loop's share is not lost), alpha x goes to
+   the reserve of v, and each out-neighbour u receives (1 - alpha) x / d_v.
+   With a queue, every out-neighbour that is active w.r.t. rmax after its
+   share arrived and is not queued yet is appended, in iteration j + 1 (the
+   forward-push methods); without one (q = NULL) the push only moves mass
+   (the scans of the global phase).  Returns x. */
+static double push_node(const int64_t* row_ptr, const int32_t* col, double alpha, double* pi, double* r,
+                        int32_t v, push_queue* q, double rmax, int32_t j) {
+    const double x = r[v];
+    const int64_t d = out_degree(row_ptr, v);
     r[v] = 0.0;
     pi[v] += alpha * x;
-    double inc = (1.0 - alpha) * x / (double)d;
-    for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) r[col[e]] += inc;
+    const double share = (1.0 - alpha) * x / (double)d;
+    for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+        const int32_t u = col[e];
+        r[u] += share;
+        if (q && !q->member[u] && is_active(row_ptr, r, u, rmax)) queue_append(q, u, j + 1);
+    }
+    return x;
+}
+
+/* Exported form of the push operation (Section 3.2). */
+void oracle_push(const int64_t* row_ptr, const int32_t* col, double alpha,
+                 double* pi, double* r, int32_t v) {
+    (void)push_node(row_ptr, col, alpha, pi, r, v, NULL, 0.0, 0);
+}
+
+/* Start of every query: pi_hat = 0, r = e_s (Section 3.2). */
+static void start_query(int32_t n, int32_t s, double* pi, double* r) {
+    for (int32_t v = 0; v < n; ++v) { pi[v] = 0.0; r[v] = 0.0; }
+    r[s] = 1.0;
 }
 
 /* ------------------------------------------------------------------ */
-/* First-In-First-Out Forward Push (Algorithm 2), with the iteration    */
-/* sets S^(j) of Section 4.2 recorded: S^(0) = {s}; S^(j+1) holds the   */
-/* nodes appended while the nodes of S^(j) are processed.               */
-/* trace_nodes / trace_levels (nullable, trace_cap entries) receive the */
-/* popped node and its iteration j, in pop order.                       */
-/* Returns the number of pushes, or -2 if memory runs out.              */
+/* Forward Push in queue order (Algorithm 2): start from the source      */
+/* queued, pop and push until the queue is empty; a pushed node queues   */
+/* the out-neighbours it made active.  The iteration sets S^(j) of       */
+/* Section 4.2 are the entries' iteration numbers.  trace_nodes /        */
+/* trace_levels (nullable, trace_cap entries) receive each popped node   */
+/* and its iteration j, in pop order.                                    */
+/* Returns the number of pushes, or -2 if memory runs out.               */
 /* ------------------------------------------------------------------ */
 int64_t oracle_fifo_fwdpush(int32_t n, const int64_t* row_ptr, const int32_t* col,
                             int32_t s, double alpha, double rmax, double* pi, double* r,
                             int32_t* trace_nodes, int32_t* trace_levels, int64_t trace_cap,
                             oracle_stats* st) {
-    int32_t* q = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
-    int32_t* qlev = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
-    uint8_t* inq = (uint8_t*)calloc((size_t)n, 1);
-    if (!q || !qlev || !inq) { free(q); free(qlev); free(inq); return -2; }
-    for (int32_t v = 0; v < n; ++v) { pi[v] = 0.0; r[v] = 0.0; }
-    r[s] = 1.0;
-    /* circular FIFO of capacity n: a node is in it at most once */
-    int64_t head = 0, size = 0, pushes = 0, edges = 0;
-    int32_t maxlev = 0;
-    q[0] = s; qlev[0] = 0; inq[s] = 1; size = 1;
-    while (size > 0) {
-        int32_t v = q[head % n];
-        int32_t lev = qlev[head % n];
-        head++; size--;
-        inq[v] = 0;
-        if (trace_nodes && pushes < trace_cap) { trace_nodes[pushes] = v; trace_levels[pushes] = lev; }
-        if (lev > maxlev) maxlev = lev;
-        double x = r[v];
-        int64_t d = row_ptr[v + 1] - row_ptr[v];
-        r[v] = 0.0;
-        pi[v] += alpha * x;
-        double inc = (1.0 - alpha) * x / (double)d;
-        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
-            int32_t u = col[e];
-            r[u] += inc;
-            double du = (double)(row_ptr[u + 1] - row_ptr[u]);
-            if (r[u] > du * rmax && !inq[u]) {
-                int64_t tail = (head + size) % n;
-                q[tail] = u; qlev[tail] = lev + 1; inq[u] = 1; size++;
-            }
-        }
+    push_queue q;
+    if (!queue_open(&q, n)) { queue_close(&q); return -2; }
+    start_query(n, s, pi, r);
+    queue_append(&q, s, 0);
+    int64_t pushes = 0, edges = 0;
+    int32_t last_iter = 0;
+    while (q.size > 0) {
+        int32_t j;
+        const int32_t v = queue_pop(&q, &j);
+        if (trace_nodes && pushes < trace_cap) { trace_nodes[pushes] = v; trace_levels[pushes] = j; }
+        if (j > last_iter) last_iter = j;
+        (void)push_node(row_ptr, col, alpha, pi, r, v, &q, rmax, j);
         pushes++;
-        edges += d;
+        edges += out_degree(row_ptr, v);
     }
     if (st) {
         memset(st, 0, sizeof(*st));
-        st->pushes = pushes; st->edge_pushes = edges; st->local_levels = maxlev + 1;
+        st->pushes = pushes; st->edge_pushes = edges; st->local_levels = last_iter + 1;
         st->r_sum = oracle_sum(n, r);
     }
-    free(q); free(qlev); free(inq);
+    queue_close(&q);
     return pushes;
 }
 
 /* ------------------------------------------------------------------ */
-/* Power Iteration with Forward Push (Algorithm 3, Section 5), as       */
-/* printed: a FIFO local phase with rmax = lambda/m while the queue is  */
-/* non-empty, holds at most n/4 nodes and r_sum > lambda; then, if      */
-/* r_sum > lambda, epochs i = 1..8 of in-place sequential scans over    */
-/* v = 0..n-1 with rmax' = lambda^(i/8)/m, each epoch scanning while    */
-/* r_sum > m rmax'.  Pushes inside a scan are asynchronous: a node uses */
-/* residue it received earlier in the same scan.                        */
-/* rsum_trace (nullable, trace_cap entries): exact r_sum after the      */
-/* local phase and after each scan.  Returns the number of trace        */
-/* entries written, or -2 if memory runs out.                           */
+/* Power Iteration with Forward Push (Section 5, Algorithm 3) is two     */
+/* phases over one state (pi_hat, r):                                    */
+/*  - a local phase of queue-ordered forward pushes at rmax = lambda / m */
+/*    that lasts while the queue is non-empty and small, and the residue */
+/*    sum is above lambda (the queue is left once the active nodes are   */
+/*    many: random access then costs more than a scan);                  */
+/*  - if the residue sum is still above lambda, a global phase of        */
+/*    sequential scans in id order, in epochs whose l1 error target      */
+/*    lambda^(i/E) falls towards lambda (the dynamic l1 threshold, E = 8 */
+/*    epochs).                                                           */
+/* ------------------------------------------------------------------ */
+
+/* Number of epochs of the global phase, and the queue-size bound of the
+   local phase as a fraction of n (Algorithm 3's two constants). */
+#define PP_EPOCHS 8
+#define PP_QUEUE_FRACTION 4      /* the queue stays while |Q| <= n / 4 */
+
+/* The local phase continues while these hold; "|Q| <= n/4" is read as the
+   integer test 4 |Q| <= n, taken before each pop. */
+static int local_phase_continues(const push_queue* q, int32_t n, double r_sum, double lambda) {
+    return q->size > 0 && PP_QUEUE_FRACTION * q->size <= (int64_t)n && r_sum > lambda;
+}
+
+/* rmax' of epoch i: the residue mass per edge that still allows l1 error
+   lambda^(i/E). */
+static double epoch_rmax(double lambda, int i, int64_t m) {
+    return pow(lambda, (double)i / (double)PP_EPOCHS) / (double)m;
+}
+
+/* One sequential scan: every node that is active w.r.t. rmax when the scan
+   reaches it pushes in place, so it already holds what nodes earlier in the
+   scan sent it (asynchronous pushes).  Adds the pushes and sum of d_v to st;
+   returns the number of pushes. */
+static int64_t sequential_scan(int32_t n, const int64_t* row_ptr, const int32_t* col, double alpha,
+                               double rmax, double* pi, double* r, oracle_stats* st) {
+    int64_t pushed = 0;
+    for (int32_t v = 0; v < n; ++v) {
+        if (!is_active(row_ptr, r, v, rmax)) continue;
+        (void)push_node(row_ptr, col, alpha, pi, r, v, NULL, 0.0, 0);
+        pushed++;
+        st->edge_pushes += out_degree(row_ptr, v);
+    }
+    st->pushes += pushed;
+    return pushed;
+}
+
+/* The local phase; the residue sum is kept incrementally (a push removes
+   alpha x from it).  Records the iterations reached in st. */
+static int powerpush_local_phase(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col,
+                                 int32_t s, double alpha, double lambda, double* pi, double* r,
+                                 oracle_stats* st) {
+    push_queue q;
+    if (!queue_open(&q, n)) { queue_close(&q); return -2; }
+    const double rmax = lambda / (double)m;
+    double r_sum = 1.0;
+    int32_t last_iter = 0;
+    queue_append(&q, s, 0);
+    while (local_phase_continues(&q, n, r_sum, lambda)) {
+        int32_t j;
+        const int32_t v = queue_pop(&q, &j);
+        if (j > last_iter) last_iter = j;
+        r_sum -= alpha * push_node(row_ptr, col, alpha, pi, r, v, &q, rmax, j);
+        st->pushes++;
+        st->edge_pushes += out_degree(row_ptr, v);
+    }
+    st->local_levels = last_iter + 1;
+    queue_close(&q);
+    return 0;
+}
+
+/* The global phase: in epoch i, scans at rmax' = lambda^(i/E) / m repeat
+   while the residue sum exceeds m rmax' (an epoch whose target is already
+   met runs no scan); the sum is recomputed exactly after every scan, and a
+   scan that pushes nothing ends its epoch. */
+static void powerpush_global_phase(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col,
+                                   double alpha, double lambda, double* pi, double* r, double* r_sum,
+                                   oracle_stats* st, double* rsum_trace, int32_t trace_cap, int* ntr) {
+    for (int i = 1; i <= PP_EPOCHS; ++i) {
+        const double rmax_i = epoch_rmax(lambda, i, m);
+        while (*r_sum > (double)m * rmax_i) {
+            const int64_t pushed = sequential_scan(n, row_ptr, col, alpha, rmax_i, pi, r, st);
+            st->sweeps++;
+            st->scans_per_epoch[i - 1]++;
+            *r_sum = oracle_sum(n, r);
+            if (rsum_trace && *ntr < trace_cap) rsum_trace[(*ntr)++] = *r_sum;
+            if (pushed == 0) break;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* PowerPush (Algorithm 3): the local phase, the exact residue sum, and  */
+/* the global phase if that sum is still above lambda.                   */
+/* rsum_trace (nullable, trace_cap entries): exact r_sum after the local */
+/* phase and after each scan.  Returns the number of trace entries       */
+/* written, or -2 if memory runs out.                                    */
 /* ------------------------------------------------------------------ */
 int oracle_powerpush(int32_t n, int64_t m, const int64_t* row_ptr, const int32_t* col,
                      int32_t s, double alpha, double lambda, double* pi, double* r,
                      oracle_stats* st, double* rsum_trace, int32_t trace_cap) {
-    const int epoch_num = 8;
-    int32_t* q = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
-    int32_t* qlev = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
-    uint8_t* inq = (uint8_t*)calloc((size_t)n, 1);
-    if (!q || !qlev || !inq) { free(q); free(qlev); free(inq); return -2; }
     oracle_stats S;
     memset(&S, 0, sizeof(S));
     int ntr = 0;
-    for (int32_t v = 0; v < n; ++v) { pi[v] = 0.0; r[v] = 0.0; }
-    r[s] = 1.0;
-    double r_sum = 1.0;
-    double rmax = lambda / (double)m;
-    int64_t head = 0, size = 1;
-    int32_t maxlev = 0;
-    q[0] = s; qlev[0] = 0; inq[s] = 1;
-    /* local phase */
-    while (size > 0 && 4 * size <= (int64_t)n && r_sum > lambda) {
-        int32_t v = q[head % n];
-        int32_t lev = qlev[head % n];
-        head++; size--;
-        inq[v] = 0;
-        if (lev > maxlev) maxlev = lev;
-        double x = r[v];
-        int64_t d = row_ptr[v + 1] - row_ptr[v];
-        r[v] = 0.0;
-        pi[v] += alpha * x;
-        r_sum -= alpha * x;
-        double inc = (1.0 - alpha) * x / (double)d;
-        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
-            int32_t u = col[e];
-            r[u] += inc;
-            double du = (double)(row_ptr[u + 1] - row_ptr[u]);
-            if (!inq[u] && r[u] > du * rmax) {
-                int64_t tail = (head + size) % n;
-                q[tail] = u; qlev[tail] = lev + 1; inq[u] = 1; size++;
-            }
-        }
-        S.pushes++;
-        S.edge_pushes += d;
-    }
-    S.local_levels = maxlev + 1;
-    r_sum = oracle_sum(n, r);
+    start_query(n, s, pi, r);
+    if (powerpush_local_phase(n, m, row_ptr, col, s, alpha, lambda, pi, r, &S) != 0) return -2;
+    double r_sum = oracle_sum(n, r);
     if (rsum_trace && ntr < trace_cap) rsum_trace[ntr++] = r_sum;
-    /* global phase: sequential scans in epochs */
     if (r_sum > lambda) {
         S.switched = 1;
-        for (int i = 1; i <= epoch_num; ++i) {
-            double rmax_i = pow(lambda, (double)i / (double)epoch_num) / (double)m;
-            while (r_sum > (double)m * rmax_i) {
-                int64_t pushed = 0;
-                for (int32_t v = 0; v < n; ++v) {
-                    int64_t d = row_ptr[v + 1] - row_ptr[v];
-                    if (r[v] > (double)d * rmax_i) {
-                        double x = r[v];
-                        r[v] = 0.0;
-                        pi[v] += alpha * x;
-                        double inc = (1.0 - alpha) * x / (double)d;
-                        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) r[col[e]] += inc;
-                        pushed++;
-                        S.edge_pushes += d;
-                    }
-                }
-                S.pushes += pushed;
-                S.sweeps++;
-                S.scans_per_epoch[i - 1]++;
-                r_sum = oracle_sum(n, r);
-                if (rsum_trace && ntr < trace_cap) rsum_trace[ntr++] = r_sum;
-                if (pushed == 0) break;
-            }
-        }
+        powerpush_global_phase(n, m, row_ptr, col, alpha, lambda, pi, r, &r_sum, &S, rsum_trace, trace_cap, &ntr);
     }
     S.r_sum = r_sum;
     if (st) *st = S;
-    free(q); free(qlev); free(inq);
     return ntr;
 }
 
@@ -443,7 +529,7 @@ int oracle_powerpush_sync(int32_t n, int64_t m, const int64_t* row_ptr, const in
         }
     } else {
         /* Algorithm 3's epochs (rmax_i = lambda^(i/8) / m, scans while
-           r_sum > m rmax_i, as printed), each scan taken simultaneously: every
+           r_sum > m rmax_i, taken literally), each scan taken simultaneously: every
            node active at the start of the scan (r(v) > d_v rmax_i) pushes the
            residue it holds then (Simultaneous Forward Push of Section 4.1 with
            threshold rmax_i).  A scan with no active node ends the epoch; scans

@@ -148,3 +148,23 @@ def test_speedppr_relative_error(eps):
     x = dense_ppr(g, s, ALPHA)
     big = x >= mu
     assert np.all(np.abs(pi[big] - x[big]) <= eps * x[big])
+
+
+def test_walk_budget_meets_the_chernoff_tail_with_the_natural_log():
+    """Eq. 8 comes from the Chernoff bound for the number X of W walks that stop
+    at v (Section 6): with E X = W pi and deviation eps E X,
+        P[|X - E X| >= eps E X] <= 2 exp(-eps^2 E X / (2 + 2 eps / 3))
+    (the two-sided bound for sums of independent [0, 1] variables).  At the
+    smallest pi that matters, pi = mu, the budget of Eq. 8 puts this tail at
+    exactly 2 / n^2 when its log is the natural logarithm; a base-10 log would
+    leave a tail of 2 n^(-2 / ln 10), far above it, and a base-2 log one of
+    2 n^(-2 / ln 2), far below it (more walks than the bound asks for)."""
+    for n, eps, mu in [(10, 0.5, 0.1), (10_000, 0.5, 1e-4), (4_000_000, 0.1, 2.5e-7),
+                       (40_000_000, 0.2, 1e-5), (1000, 1.0, 1e-3)]:
+        W = oracle.walk_budget(n, eps, mu)
+        tail = 2.0 * math.exp(-eps * eps * W * mu / (2.0 + 2.0 * eps / 3.0))
+        assert tail == pytest.approx(2.0 / n ** 2, rel=1e-9), (n, eps, mu)
+        for wrong_log in (math.log10, math.log2):
+            W_wrong = W * wrong_log(n) / math.log(n)
+            tail_wrong = 2.0 * math.exp(-eps * eps * W_wrong * mu / (2.0 + 2.0 * eps / 3.0))
+            assert abs(tail_wrong - 2.0 / n ** 2) > 0.1 * (2.0 / n ** 2)

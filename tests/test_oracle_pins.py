@@ -365,3 +365,45 @@ def test_epochs_schedule_invariant_and_thresholds(n, p, seed):
         np.testing.assert_allclose(pi + r @ Pi, Pi[s], atol=1e-14)
         _, _, st0, _, _ = oracle.powerpush_sync(g, s, ALPHA, lam, oracle.SWITCH_EDGES, 1e30)
         assert st["edge_pushes"] < st0["edge_pushes"]
+
+
+def test_powerpush_many_rows_are_the_single_queries(c1):
+    """The query-parallel form (one Algorithm 3 query per host thread) writes row i
+    from sources[i]: each row and its statistics equal the single query bit for
+    bit (more sources than threads, a repeated source, the first and last node),
+    and each row is within lambda of the converged power iteration."""
+    lam = 1e-7
+    srcs = [int(s) for s in synth.sources(c1.n, 5)] + [0, c1.n - 1]
+    srcs.append(srcs[1])
+    pi_many, st_many = oracle.powerpush_many(c1, srcs, ALPHA, lam, threads=3)
+    assert pi_many.shape == (len(srcs), c1.n)
+    for i, s in enumerate(srcs):
+        pi, r, st, _ = oracle.powerpush(c1, s, ALPHA, lam)
+        assert np.array_equal(pi_many[i], pi), i
+        assert st_many[i] == st, i
+    for i in (0, len(srcs) - 2):
+        truth = oracle.powitr(c1, srcs[i], ALPHA, 135)
+        assert np.abs(pi_many[i] - truth).sum() <= lam
+
+
+def test_powerpush_many_on_small_graphs_meets_the_dense_solve():
+    """Every row of the query-parallel form against numpy's dense solve of Eq. 1
+    for its own source (n <= 60, self-loops included)."""
+    rng = np.random.default_rng(11)
+    for trial in range(4):
+        n = int(rng.integers(8, 60))
+        g = synth.random_small(n, 0.15, seed=100 + trial, self_loops=True)
+        X = dense_ppr_matrix(g, ALPHA)
+        srcs = list(range(0, n, max(1, n // 9)))
+        pi_many, _ = oracle.powerpush_many(g, srcs, ALPHA, 1e-10, threads=4)
+        for i, s in enumerate(srcs):
+            assert np.abs(pi_many[i] - X[s]).sum() <= 1e-10
+
+
+def test_native_build_gives_the_same_answers(c1):
+    """The timed CPU baseline runs an -O3 -march=native build of the same source
+    (no floating-point contraction): its answers equal the test build's bit for bit."""
+    srcs = [int(s) for s in synth.sources(c1.n, 3)]
+    a, sa = oracle.powerpush_many(c1, srcs, ALPHA, 1e-8, threads=3)
+    b, sb = oracle.powerpush_many(c1, srcs, ALPHA, 1e-8, threads=3, native=True)
+    assert np.array_equal(a, b) and sa == sb
