@@ -496,6 +496,41 @@ ppr_status ppr_block_poll(ppr_block* blk, int32_t wait, uint8_t* done, int32_t* 
  * still receive its estimate and certificate, and the slot is freed. */
 ppr_status ppr_slot_retire(ppr_block* blk, int32_t slot, double* pi_out, ppr_stats* stats);
 
+/* ------------------------------------------------------------------ */
+/* Allocation-free query.                                              */
+/* ------------------------------------------------------------------ */
+/*
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * computation as ppr_query with PPR_FP64 and the default options (the local
+ * phase over the iteration sets S^(j), then threshold-0 sweeps of Eq. 7
+ * until r_sum <= lambda; the same kernels), but its working state lives in a
+ * fixed device array of PPR_NOALLOC_SCRATCH_BYTES that the library holds on
+ * every device it runs on until the process ends, and the reserve is written
+ * straight into pi_out.  The call allocates no device or pinned memory and
+ * creates no stream, event or HIP graph.
+ *   Limits: n <= PPR_NOALLOC_MAX_NODES and at most
+ *   PPR_NOALLOC_MAX_SWEEP_BLOCKS blocks in the graph's FP64 sweep schedule
+ *   (about n / 256 + 3 m / 2048; m up to about 80M edges at the node limit);
+ *   larger graphs give PPR_ERR_ARG and nothing runs.
+ *   hip_stream: the caller's hipStream_t (NULL: the null stream); every
+ *   kernel and copy of the call goes there, after the stream's earlier work.
+ *   The call synchronises the stream before it returns.
+ *   pi_out: double[n], device memory of the graph's device (host memory:
+ *   PPR_ERR_ARG).  stats nullable; cert_l1 and sweep_ms are -1 (no
+ *   certificate pass, no timing events).
+ * The array is shared by every call on one device and keeps the last call's
+ * contents; each call first writes everything it later reads.  Calls on one
+ * device are serialised by a lock inside the library (one at a time per
+ * device in this process); callers that overlap calls on one device wait.
+ * Errors as ppr_query, plus PPR_ERR_ARG for the limits above.
+ */
+#define PPR_NOALLOC_MAX_NODES (1 << 20)
+#define PPR_NOALLOC_MAX_SWEEP_BLOCKS (1 << 17)
+#define PPR_NOALLOC_SCRATCH_BYTES 43057920u   /* 41.1 MiB per device */
+ppr_status ppr_query_fp64_noalloc(ppr_graph* g, int32_t s, double alpha, double lambda, void* hip_stream,
+                                  double* pi_out, ppr_stats* stats);
+
 /* Library version string. */
 const char* ppr_version(void);
 

@@ -37,6 +37,7 @@ SCAN_PULL = 1
 SCAN_PUSH = 2
 GRAPH_TRUST_INPUT = 1
 GRAPH_WIDE_OFFSETS = 2
+NOALLOC_MAX_NODES = 1 << 20          # ppr_query_fp64_noalloc's node limit
 
 # every symbol include/ppr.h declares (checked by the CPU tests)
 EXPORTS = [
@@ -46,7 +47,7 @@ EXPORTS = [
     "ppr_block_create", "ppr_block_destroy", "ppr_block_footprint", "ppr_slot_admit",
     "ppr_block_step", "ppr_block_poll", "ppr_slot_retire", "ppr_debug_sweep_mixed", "ppr_query_trace",
     "ppr_query_approx", "ppr_walk_index_build", "ppr_walk_index_copy", "ppr_debug_refine", "ppr_debug_walks",
-    "ppr_debug_sweeps_mixed",
+    "ppr_debug_sweeps_mixed", "ppr_query_fp64_noalloc",
 ]
 
 
@@ -145,6 +146,7 @@ def load() -> ctypes.CDLL:
         "ppr_block_step": (st, [vp, i32]),
         "ppr_block_poll": (st, [vp, i32, vp, vp, vp, vp]),
         "ppr_slot_retire": (st, [vp, i32, vp, vp]),
+        "ppr_query_fp64_noalloc": (st, [vp, i32, f64, f64, vp, vp, vp]),
         "ppr_version": (ctypes.c_char_p, []),
         "ppr_last_error": (ctypes.c_char_p, []),
     }
@@ -255,6 +257,16 @@ class Graph:
                                  _ptr(out), _ptr(r_out) if r_out is not None else None, st)
         _check(rc)
         return out, [s.as_dict() for s in st]
+
+    def query_noalloc(self, s: int, alpha: float, lam: float, out, stream=None) -> dict:
+        """The allocation-free FP64 query (ppr_query_fp64_noalloc): pi_hat into
+        `out`, a float64[n] device tensor; `stream`: a torch.cuda.Stream (None:
+        the null stream).  Returns the statistics."""
+        st = Stats()
+        h = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+        _check(load().ppr_query_fp64_noalloc(self._h, int(s), float(alpha), float(lam), h, _ptr(out),
+                                             ctypes.byref(st)))
+        return st.as_dict()
 
     def query_trace(self, s: int, alpha: float = 0.2, lam: float = 1e-8, out=None, capacity: int = 4096,
                     **opt):

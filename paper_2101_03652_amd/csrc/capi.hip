@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <utility>
 
 #include "ppr_internal.h"
 
@@ -13,23 +14,7 @@ namespace {
 
 template <class F>
 ppr_status guarded(F&& f) {
-    try {
-        f();
-        set_error("");
-        return PPR_OK;
-    } catch (const Failure& e) {
-        set_error(e.msg);
-        return e.status;
-    } catch (const std::bad_alloc&) {
-        set_error("host allocation failed");
-        return PPR_ERR_OOM;
-    } catch (const std::exception& e) {
-        set_error(e.what());
-        return PPR_ERR_DEVICE;
-    } catch (...) {
-        set_error("unknown failure");
-        return PPR_ERR_DEVICE;
-    }
+    return guarded_call(std::forward<F>(f));
 }
 
 void check_query_args(const Graph* g, const int32_t* sources, int32_t B, double alpha, double lambda,

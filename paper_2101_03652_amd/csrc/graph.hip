@@ -158,6 +158,17 @@ size_t Graph::device_bytes() const {
     return b;
 }
 
+const Schedule* Graph::find_schedule(int32_t nnz_cap, int32_t row_cap, int32_t chunks, int32_t rounds) {
+    std::lock_guard<std::mutex> lk(sched_mu);
+    chunks = std::max<int32_t>(1, std::min<int32_t>(chunks, n));
+    const bool split = rounds > 0;
+    for (auto& s : schedules)
+        if (s->nnz_cap == nnz_cap && s->row_cap == row_cap && s->chunks == chunks && s->split == split &&
+            s->rounds == std::max(rounds, 1))
+            return s.get();
+    return nullptr;
+}
+
 const Schedule& Graph::schedule(int32_t nnz_cap, int32_t row_cap, int32_t chunks, int32_t rounds) {
     std::lock_guard<std::mutex> lk(sched_mu);
     chunks = std::max<int32_t>(1, std::min<int32_t>(chunks, n));
@@ -317,6 +328,7 @@ Graph* graph_create(const int64_t* row_ptr, const int32_t* col, int32_t n, int64
     }
     g->max_in = mi;
     g->max_out = mo;
+    (void)g->schedule(k::sweep_nnz_cap(), k::sweep_row_cap());   // the FP64 sweep's, used by every query path
     g->build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return g.release();
 }

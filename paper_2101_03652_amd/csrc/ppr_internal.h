@@ -8,6 +8,8 @@
 #include <cstdio>
 #include <memory>
 #include <mutex>
+#include <new>
+#include <stdexcept>
 #include <string>
 #include <vector>
 
@@ -25,6 +27,30 @@ struct Failure {
 [[noreturn]] void fail(ppr_status st, const std::string& msg);
 void check_hip(hipError_t e, const char* what, const char* file, int line);
 #define HIPCHECK(x) ::ppr::check_hip((x), #x, __FILE__, __LINE__)
+
+// Runs f and turns every failure (Failure, std::bad_alloc, other exceptions)
+// into a status code and the thread-local message: nothing throws across the
+// C ABI.
+template <class F>
+ppr_status guarded_call(F&& f) {
+    try {
+        f();
+        set_error("");
+        return PPR_OK;
+    } catch (const Failure& e) {
+        set_error(e.msg);
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        set_error("host allocation failed");
+        return PPR_ERR_OOM;
+    } catch (const std::exception& e) {
+        set_error(e.what());
+        return PPR_ERR_DEVICE;
+    } catch (...) {
+        set_error("unknown failure");
+        return PPR_ERR_DEVICE;
+    }
+}
 
 // True if p is device (or managed) memory of `device`; false for host memory
 // (pageable, pinned or unregistered).  Device memory of another device is an
@@ -145,6 +171,8 @@ struct Graph {
     ~Graph();
     size_t device_bytes() const;
     const Schedule& schedule(int32_t nnz_cap, int32_t row_cap, int32_t chunks = 1, int32_t rounds = 0);
+    // The schedule if it has been built, else nullptr (allocates nothing).
+    const Schedule* find_schedule(int32_t nnz_cap, int32_t row_cap, int32_t chunks = 1, int32_t rounds = 0);
 };
 
 Graph* graph_create(const int64_t* row_ptr, const int32_t* col, int32_t n, int64_t m,
@@ -249,6 +277,10 @@ struct TraceSink {
 
 void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_options& opt,
                     double* pi_out, double* r_out, ppr_stats* st, TraceSink* trace = nullptr);
+// The same query with the default options, its state in a static device
+// array (no allocation); pi: device memory.
+void run_fp64_query_noalloc(Graph& g, int32_t s, double alpha, double lambda, hipStream_t stream, double* pi,
+                            ppr_stats* st);
 
 // Approximate SSPPR (SpeedPPR).  A walk alive after kMaxWalkSteps steps stops
 // where it is (probability (1 - alpha)^4096).
