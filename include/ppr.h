@@ -25,9 +25,18 @@
  *  - Output buffers are caller-owned and may be host or device memory (the
  *    library detects which with hipPointerGetAttributes).  A device output
  *    must be on the device the graph was created on.
- *  - A ppr_graph is immutable after creation; queries on one graph from
- *    different threads are safe (each call takes its own state slot and HIP
- *    stream from the graph's pool).  A ppr_block is used from one thread.
+ *  - A ppr_graph's structure is immutable after creation; queries on one
+ *    graph from different threads are safe (each call takes its own state
+ *    slot and HIP stream from the graph's pool).  ppr_autotune changes the
+ *    graph's defaults (block width, row tiles) and must not run while other
+ *    calls use the graph.  A ppr_block is used from one thread.
+ *  - Streams: by default every call runs on a stream of its own state slot.
+ *    With ppr_options.use_stream = 1 a query (ppr_query_ex, ppr_query_trace)
+ *    or a serving block runs every launch and copy on the caller's HIP stream
+ *    ppr_options.stream instead (NULL: the null stream), after the work the
+ *    caller enqueued there earlier; a PyTorch stream's handle passes straight
+ *    through.  HIP graphs the library replays are captured on its own streams
+ *    and launched on the caller's.
  *  - Node ids are 0..n-1 (int32).  Edge counts and offsets are int64.
  *  - All calls are synchronous unless stated: they return once results are
  *    in the caller's buffer.
@@ -60,9 +69,10 @@ typedef enum {
 
 typedef enum {
     PPR_FP64 = 0,    /* plain path: residues, reserves and sums in double precision */
-    PPR_MIXED = 1    /* FP32 arithmetic on FP32 or bf16 residues with an FP32 stage
-                        accumulator; FP64 reserves; every stage ends with an FP64
-                        residual refresh that certifies the result */
+    PPR_MIXED = 1    /* FP32 arithmetic on FP32 or bf16 residues (block Gauss-Seidel,
+                        over-relaxed push sweeps) with an FP32 stage accumulator;
+                        FP64 reserves; every stage ends with an FP64 residual
+                        refresh that certifies the result */
 } ppr_precision;
 
 /* Storage of the batched path's residue block (arithmetic is FP32 either way). */
@@ -109,6 +119,10 @@ typedef struct {
     int32_t sweep_tile_bytes; /* LDS stage of a batched sweep block (its row tile: in-edges
                                and rows per block), chosen per width by ppr_autotune;
                                0 for PPR_FP64 */
+    double refresh_ms;      /* PPR_MIXED: GPU time of the FP64 refresh passes of the query's block
+                               (HIP events on the library's stream, whole block); 0 for PPR_FP64 */
+    int32_t refresh_launches; /* refresh passes that refresh_ms covers */
+    int32_t reserved;
 } ppr_stats;
 
 /* Global phase of the PPR_FP64 path. */
@@ -167,6 +181,12 @@ typedef struct {
                                12288, 16384 or 24576; 0 = the tile ppr_autotune chose for
                                the block width on this graph, else 16384 (default).  Any
                                other value: PPR_ERR_ARG */
+    int32_t use_stream;     /* 1: run on `stream` (below); 0: on the library's own streams
+                               (default) */
+    void* stream;           /* hipStream_t of the caller when use_stream = 1 (NULL: the null
+                               stream).  Synchronous calls still return only once their
+                               results are in the caller's buffers; a serving block's steps
+                               are enqueued there and collected by ppr_block_poll */
 } ppr_options;
 
 /* Read-only facts about a created graph. */
@@ -442,23 +462,32 @@ ppr_status ppr_autotune(ppr_graph* g, double alpha, const int32_t* widths, int32
 /*
  * Serving: continuous batching of mixed-precision queries on one graph.
  *
- * A block holds `slots` query slots (the columns of one n x slots FP32 state
- * in device memory).  Each slot answers one single-source query with its own
- * source and its own lambda, by the same computation as ppr_query_ex with
+ * A block holds `slots` query slots (the columns of one n x slots state in
+ * device memory).  Each slot answers one single-source query with its own
+ * source, alpha and lambda, by the same computation as ppr_query_ex with
  * PPR_MIXED: a frontier local phase over the iteration sets S^(j) of
- * Section 4.2 in FP64, global sweeps of Eq. 7 in FP32, and FP64 refreshes
- * whose residual (Eq. 1 rearranged) certifies ||pi_hat - pi_s||_1 <= lambda.
- * A slot's schedule depends on its own source and lambda only, so a query's
- * result is the same whichever other queries share the block (up to FP32
- * summation order).  Slots free up and refill while the others run.
+ * Section 4.2 in FP64, global push sweeps in FP32 arithmetic (block
+ * Gauss-Seidel order over row chunks, over-relaxed, residues stored in bf16
+ * from 32 slots up), and FP64 refreshes whose residual (Eq. 1 rearranged)
+ * certifies ||pi_hat - pi_s||_1 <= lambda.  A slot's schedule depends on its
+ * own source, alpha and lambda only, so a query's result is the same
+ * whichever other queries share the block (up to FP32 summation order).
+ * Slots free up and refill while the others run.
  *
  * A block is used by one host thread at a time.  Blocks must be destroyed
  * before their graph (ppr_graph_destroy returns PPR_ERR_BUSY otherwise).
  */
 
-/* Create a block.  slots: power of two in [4, 128]; alpha in (0, 1); opt
- * (nullable): switch rule, max_sweeps (a cap on each query's sweeps),
- * refresh_factor; precision is ignored.  PPR_ERR_OOM if the device memory
+/* Create a block.  slots: power of two in [4, 128].  alpha in (0, 1): the
+ * block's reference stop probability, the default of ppr_slot_admit (the
+ * per-node scale table of the FP32 sweeps holds (1 - alpha) / d_u; a slot
+ * admitted with another alpha_b multiplies it by the FP32 factor
+ * (1 - alpha_b) / (1 - alpha), one more rounding in its sweeps, which its FP64
+ * refresh measures like any other).  opt (nullable): switch rule, max_sweeps
+ * (a cap on each query's sweeps), refresh_factor, use_stream / stream (the
+ * stream that carries every step of the block); opt->precision must be
+ * PPR_MIXED (a block is the batched mixed path; PPR_FP64 queries go through
+ * ppr_query_ex), else PPR_ERR_ARG.  PPR_ERR_OOM if the device memory
  * (ppr_block_footprint) cannot be allocated. */
 ppr_status ppr_block_create(ppr_graph* g, int32_t slots, double alpha, const ppr_options* opt,
                             ppr_block** out);
@@ -467,13 +496,30 @@ ppr_status ppr_block_create(ppr_graph* g, int32_t slots, double alpha, const ppr
 ppr_status ppr_block_destroy(ppr_block* blk);
 
 /* Device bytes a block of `slots` slots allocates on this graph (for
- * admission against a memory budget). */
+ * admission against a memory budget); equal to ppr_footprint_bytes's
+ * state_bytes for the graph's n and m. */
 ppr_status ppr_block_footprint(const ppr_graph* g, int32_t slots, size_t* bytes);
 
+/* Device memory before any graph exists (admission of a graph and its
+ * queries against a budget), from the sizes alone:
+ *   graph_bytes (nullable): what ppr_graph_create keeps for n nodes and m
+ *     edges (CSR, CSC with uint32 offsets below 2^32 - 1 edges, degrees; the
+ *     row schedules, a few percent more, are built on demand);
+ *   state_bytes (nullable): PPR_MIXED: a serving block of `slots` columns
+ *     (power of two in [4, 128]) with the default options, exactly what
+ *     ppr_block_create allocates and ppr_block_footprint reports; PPR_FP64:
+ *     an upper bound on `slots` (>= 1) concurrent PPR_FP64 queries, one
+ *     pooled context each.
+ * n >= 1 and n <= m <= n^2, else PPR_ERR_ARG. */
+ppr_status ppr_footprint_bytes(int32_t n, int64_t m, int32_t slots, ppr_precision precision, size_t* graph_bytes,
+                               size_t* state_bytes);
+
 /* Put a query into a free slot; *slot receives its index.  The query starts
- * at the next ppr_block_step.  PPR_ERR_BUSY if every slot is taken,
- * PPR_ERR_ARG for a source outside [0, n) or lambda outside (0, 1]. */
-ppr_status ppr_slot_admit(ppr_block* blk, int32_t source, double lambda, int32_t* slot);
+ * at the next ppr_block_step.  alpha: the query's stop probability in (0, 1)
+ * (0: the block's reference alpha); each slot has its own alpha and lambda.
+ * PPR_ERR_BUSY if every slot is taken, PPR_ERR_ARG for a source outside
+ * [0, n), alpha outside (0, 1) and not 0, or lambda outside (0, 1]. */
+ppr_status ppr_slot_admit(ppr_block* blk, int32_t source, double alpha, double lambda, int32_t* slot);
 
 /* Advance the block: collect the previous step's results (waiting for them),
  * run the local phase of newly admitted slots, then enqueue up to max_sweeps

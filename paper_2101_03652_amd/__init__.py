@@ -47,7 +47,7 @@ EXPORTS = [
     "ppr_block_create", "ppr_block_destroy", "ppr_block_footprint", "ppr_slot_admit",
     "ppr_block_step", "ppr_block_poll", "ppr_slot_retire", "ppr_debug_sweep_mixed", "ppr_query_trace",
     "ppr_query_approx", "ppr_walk_index_build", "ppr_walk_index_copy", "ppr_debug_refine", "ppr_debug_walks",
-    "ppr_debug_sweeps_mixed", "ppr_query_fp64_noalloc",
+    "ppr_debug_sweeps_mixed", "ppr_query_fp64_noalloc", "ppr_footprint_bytes",
 ]
 
 
@@ -65,7 +65,9 @@ class Stats(ctypes.Structure):
                 ("sweep_ms", ctypes.c_double), ("sweep_launches", ctypes.c_int32),
                 ("batch_cols", ctypes.c_int32), ("sweep_chunks", ctypes.c_int32),
                 ("sor_omega", ctypes.c_double), ("residue_format", ctypes.c_int32),
-                ("push_scans", ctypes.c_int32), ("sweep_tile_bytes", ctypes.c_int32)]
+                ("push_scans", ctypes.c_int32), ("sweep_tile_bytes", ctypes.c_int32),
+                ("refresh_ms", ctypes.c_double), ("refresh_launches", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -97,7 +99,8 @@ class Options(ctypes.Structure):
                 ("batch_cols", ctypes.c_int32), ("sweep_chunks", ctypes.c_int32),
                 ("global_rule", ctypes.c_int32), ("sor_omega", ctypes.c_double),
                 ("residue_format", ctypes.c_int32), ("scan_form", ctypes.c_int32),
-                ("sweep_tile", ctypes.c_int32)]
+                ("sweep_tile", ctypes.c_int32), ("use_stream", ctypes.c_int32),
+                ("stream", ctypes.c_void_p)]
 
 
 class GraphInfo(ctypes.Structure):
@@ -142,7 +145,8 @@ def load() -> ctypes.CDLL:
         "ppr_block_create": (st, [vp, i32, f64, vp, ctypes.POINTER(vp)]),
         "ppr_block_destroy": (st, [vp]),
         "ppr_block_footprint": (st, [vp, i32, vp]),
-        "ppr_slot_admit": (st, [vp, i32, f64, vp]),
+        "ppr_slot_admit": (st, [vp, i32, f64, f64, vp]),
+        "ppr_footprint_bytes": (st, [i32, i64, i32, ctypes.c_int, vp, vp]),
         "ppr_block_step": (st, [vp, i32]),
         "ppr_block_poll": (st, [vp, i32, vp, vp, vp, vp]),
         "ppr_slot_retire": (st, [vp, i32, vp, vp]),
@@ -176,14 +180,36 @@ def _ptr(x):
     raise TypeError(f"unsupported buffer type {type(x)}")
 
 
+def stream_handle(stream):
+    """The hipStream_t of a torch.cuda.Stream (or a raw integer handle)."""
+    return int(stream) if isinstance(stream, int) else int(stream.cuda_stream)
+
+
 def options(**kw) -> Options:
+    """ppr_options with the defaults, then the given fields.  stream=<a
+    torch.cuda.Stream or a raw handle> sets use_stream = 1 and the handle
+    (torch's default stream is the null stream, handle 0)."""
     o = Options()
     load().ppr_options_default(ctypes.byref(o))
+    if kw.get("stream") is not None:
+        o.use_stream = 1
+        o.stream = stream_handle(kw.pop("stream"))
+    kw.pop("stream", None)
     for k, v in kw.items():
         if not hasattr(o, k):
             raise KeyError(k)
         setattr(o, k, v)
     return o
+
+
+def footprint_bytes(n: int, m: int, slots: int, precision: int = MIXED) -> tuple[int, int]:
+    """(graph bytes, state bytes) on the device for a graph of n nodes and m
+    edges and `slots` query slots (ppr_footprint_bytes), before any graph
+    exists."""
+    gb, sb = ctypes.c_size_t(), ctypes.c_size_t()
+    _check(load().ppr_footprint_bytes(int(n), int(m), int(slots), int(precision), ctypes.byref(gb),
+                                      ctypes.byref(sb)))
+    return gb.value, sb.value
 
 
 class Graph:
@@ -358,6 +384,8 @@ class Block:
     certified result out and frees its slot for the next query."""
 
     def __init__(self, graph: Graph, slots: int, alpha: float = 0.2, **opt):
+        """opt: ppr_options fields; stream=<torch.cuda.Stream> runs the block
+        on that stream."""
         self.graph = graph          # keeps the graph alive while the block exists
         self.slots = int(slots)
         self.alpha = float(alpha)
@@ -385,9 +413,11 @@ class Block:
         except Exception:
             pass
 
-    def admit(self, source: int, lam: float) -> int:
+    def admit(self, source: int, lam: float, alpha: float | None = None) -> int:
+        """Admit a query; alpha None takes the block's reference alpha."""
         slot = ctypes.c_int32(-1)
-        _check(load().ppr_slot_admit(self._h, int(source), float(lam), ctypes.byref(slot)))
+        _check(load().ppr_slot_admit(self._h, int(source), 0.0 if alpha is None else float(alpha), float(lam),
+                                     ctypes.byref(slot)))
         return slot.value
 
     def step(self, max_sweeps: int = 16) -> None:

@@ -50,6 +50,7 @@ void check_options(const ppr_options& o) {
         fail(PPR_ERR_ARG, "unknown global rule");
     if (o.global_rule == PPR_GLOBAL_EPOCHS && o.precision != PPR_FP64)
         fail(PPR_ERR_ARG, "the epoch global phase is a PPR_FP64 option");
+    if (o.use_stream != 0 && o.use_stream != 1) fail(PPR_ERR_ARG, "use_stream must be 0 or 1");
 }
 
 }  // namespace
@@ -68,6 +69,8 @@ void ppr_options_default(ppr_options* o) {
     o->batch_cols = 0;
     o->residue_format = PPR_RESIDUE_AUTO;
     o->scan_form = PPR_SCAN_AUTO;
+    o->use_stream = 0;
+    o->stream = NULL;
 }
 
 const char* ppr_version(void) { return "libppr 0.1 (gfx950)"; }
@@ -328,8 +331,14 @@ ppr_status ppr_block_create(ppr_graph* gh, int32_t slots, double alpha, const pp
         if (!(alpha > 0.0 && alpha < 1.0)) fail(PPR_ERR_ARG, "alpha must lie in (0, 1)");
         if (slots < 4 || slots > 128 || (slots & (slots - 1))) fail(PPR_ERR_ARG, "slots must be a power of two in [4, 128]");
         ppr_options o;
-        if (opt) o = *opt; else ppr_options_default(&o);
-        o.precision = PPR_MIXED;
+        if (opt) {
+            o = *opt;
+            if (o.precision != PPR_MIXED)
+                fail(PPR_ERR_ARG, "a serving block runs the batched PPR_MIXED path (PPR_FP64 queries: ppr_query_ex)");
+        } else {
+            ppr_options_default(&o);
+            o.precision = PPR_MIXED;
+        }
         check_options(o);
         *out = reinterpret_cast<ppr_block*>(serve_block_create(*g, slots, alpha, o));
     });
@@ -344,15 +353,34 @@ ppr_status ppr_block_footprint(const ppr_graph* gh, int32_t slots, size_t* bytes
         const Graph* g = reinterpret_cast<const Graph*>(gh);
         if (!g || !bytes) fail(PPR_ERR_ARG, "NULL argument");
         if (slots < 4 || slots > 128 || (slots & (slots - 1))) fail(PPR_ERR_ARG, "slots must be a power of two in [4, 128]");
-        *bytes = serve_footprint(*g, slots);
+        *bytes = serve_footprint(g->n, g->m, slots);
     });
 }
 
-ppr_status ppr_slot_admit(ppr_block* blk, int32_t source, double lambda, int32_t* slot) {
+ppr_status ppr_footprint_bytes(int32_t n, int64_t m, int32_t slots, ppr_precision precision, size_t* graph_bytes,
+                               size_t* state_bytes) {
+    return guarded([&] {
+        if (n < 1 || m < n) fail(PPR_ERR_ARG, "need n >= 1 and m >= n (every node has an out-edge)");
+        if ((double)m > (double)n * (double)n) fail(PPR_ERR_ARG, "m exceeds n^2 (A is a 0/1 matrix)");
+        if (precision == PPR_MIXED) {
+            if (slots < 4 || slots > 128 || (slots & (slots - 1)))
+                fail(PPR_ERR_ARG, "slots must be a power of two in [4, 128]");
+        } else if (precision == PPR_FP64) {
+            if (slots < 1) fail(PPR_ERR_ARG, "slots must be >= 1");
+        } else {
+            fail(PPR_ERR_ARG, "unknown precision");
+        }
+        if (graph_bytes) *graph_bytes = graph_footprint(n, m);
+        if (state_bytes)
+            *state_bytes = precision == PPR_MIXED ? serve_footprint(n, m, slots) : (size_t)slots * fp64_ctx_footprint(n);
+    });
+}
+
+ppr_status ppr_slot_admit(ppr_block* blk, int32_t source, double alpha, double lambda, int32_t* slot) {
     return guarded([&] {
         if (!blk || !slot) fail(PPR_ERR_ARG, "NULL argument");
         *slot = -1;
-        *slot = serve_admit(blk, source, lambda);
+        *slot = serve_admit(blk, source, alpha, lambda);
     });
 }
 

@@ -153,6 +153,14 @@ Graph::~Graph() {
     pool.clear();
 }
 
+size_t graph_footprint(int32_t n, int64_t m) {
+    const size_t nn = (size_t)n, mm = (size_t)m;
+    const size_t off = (m >= (int64_t)UINT32_MAX) ? 8 : 4;  // CSC offsets: uint32 below 2^32 - 1 edges
+    return 8 * (nn + 1) + 4 * mm            // CSR: row_ptr, col
+           + off * (nn + 1) + 4 * mm        // CSC: col_ptr, row_idx
+           + 4 * nn;                        // out-degrees
+}
+
 size_t Graph::device_bytes() const {
     size_t b = row_ptr.bytes + col.bytes + col_ptr.bytes + row_idx.bytes + deg.bytes + walk_index.bytes;
     return b;

@@ -7,9 +7,9 @@
 // (stages of sweeps, each ended by an FP64 refresh of that slot) -> DONE (its
 // FP64 certificate is <= its lambda; its reserve no longer changes) ->
 // retired (exported) -> FREE.  A slot's schedule (local levels, stage
-// lengths, refresh points) depends on its own source and lambda only, so a
-// query's result is the same whichever other slots share the block, up to
-// the FP32 summation order of the block width.
+// lengths, refresh points) depends on its own source, alpha and lambda only,
+// so a query's result is the same whichever other slots share the block, up
+// to the FP32 summation order of the block width.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -30,7 +30,7 @@ void MixedCtx::drop_chunks() {
 
 MixedCtx::~MixedCtx() {
     drop_chunks();
-    if (stream) (void)hipStreamDestroy(stream);
+    if (own) (void)hipStreamDestroy(own);
 }
 
 void MixedCtxDeleter::operator()(MixedCtx* c) const { delete c; }
@@ -64,8 +64,8 @@ int sweep_chunks(const Graph& g, const ppr_options& opt) {
 
 // LDS stage (row tile) of the sweep blocks at width Bw: the autotuner's
 // choice for this graph and width, else the default.
-int sweep_tile(const Graph& g, int Bw) {
-    const int t = g.tuned_tile[ilog2(Bw) & 7];
+int sweep_tile(const Graph& g, int Bw, bool bf16) {
+    const int t = g.tuned_tile[bf16 ? 1 : 0][ilog2(Bw) & 7].load();
     return t > 0 ? t : mk::kLdsBytes;
 }
 
@@ -92,27 +92,29 @@ constexpr int kChunkSweeps = 16;
 enum SlotState : int { FREE = 0, PENDING = 1, RUNNING = 2, DONE = 3 };
 }  // namespace
 
-int64_t frontier_capacity(const Graph& g, const ppr_options& opt, int Bw) {
-    // a level runs only if the column's next frontier (at most vol_b entries)
-    // fits its share of the capacity
-    int64_t per_col = g.n;
+int64_t frontier_capacity(int32_t n, int64_t m, const ppr_options& opt, int Bw) {
+    // A level runs only if the column's next frontier (at most vol_b entries,
+    // at most n) fits its share of the capacity.  Under the edge rule a level
+    // runs only while switch_param * kBatchRef * vol_b <= m, so that share
+    // never stops a level the rule allows; it depends on (n, m, options) only,
+    // so the footprint is known before the graph exists.
+    int64_t per_col = n;
     if (opt.switch_rule == PPR_SWITCH_EDGES && opt.switch_param > 0)
-        per_col = std::min<int64_t>(per_col, (int64_t)((double)g.m / (opt.switch_param * kBatchRef)) + 1);
-    per_col = std::max<int64_t>(per_col, 1 + g.max_out);
-    return per_col * Bw;
+        per_col = std::min<int64_t>(per_col, (int64_t)((double)m / (opt.switch_param * kBatchRef)) + 1);
+    return std::max<int64_t>(per_col, 1) * Bw;
 }
 
-size_t mixed_footprint(const Graph& g, int Bw, int64_t fcap, bool bf16) {
-    const size_t nb = (size_t)g.n * (size_t)Bw;
+size_t mixed_footprint(int32_t n, int64_t m, int Bw, int64_t fcap, bool bf16) {
+    const size_t nb = (size_t)n * (size_t)Bw;
     // long-row pieces: each holds piece_cap = kLongRounds L / (4 Bw) in-edges
     // of a row with more than piece_cap (L the sweep stage, at least
     // kMinTile), so there are fewer than 2 m / piece_cap
     const size_t piece_cap = (size_t)mk::kLongRounds * mk::kMinTile / (4 * (size_t)Bw);
-    const size_t pieces = 2 * (size_t)g.m / piece_cap + 1;
+    const size_t pieces = 2 * (size_t)m / piece_cap + 1;
     return 16 * nb                       // FP64 local-phase scratch
            + (bf16 ? 24 : 28) * nb       // Y0, Y1 (4 or 2 bytes), S, AS (8), T (4)
            + 4 * (size_t)Bw * pieces     // partial sums of the pieces
-           + 40 * (size_t)fcap + 4 * (size_t)g.n + ((size_t)1 << 20);
+           + 40 * (size_t)fcap + 4 * (size_t)n + ((size_t)1 << 20);
 }
 
 MixedCtxPtr mixed_acquire(Graph& g, int Bw, int64_t fcap, bool bf16) {
@@ -133,7 +135,8 @@ MixedCtxPtr mixed_acquire(Graph& g, int Bw, int64_t fcap, bool bf16) {
     c->shift = ilog2(Bw);
     c->fcap = fcap;
     c->bf16 = bf16;
-    HIPCHECK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    HIPCHECK(hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
+    c->stream = c->own;
     c->r64.alloc(8 * nb);
     c->pi64.alloc(8 * nb);
     HIPCHECK(hipMemsetAsync(c->r64.p, 0, 8 * nb, c->stream));
@@ -159,6 +162,8 @@ MixedCtxPtr mixed_acquire(Graph& g, int Bw, int64_t fcap, bool bf16) {
     for (DevBuf* b : {&c->src, &c->kb, &c->entry, &c->rmask, &c->cmask}) b->alloc(4 * (size_t)Bw);
     c->rmaxb.alloc(8 * (size_t)Bw);
     c->omega.alloc(4 * (size_t)Bw);
+    c->acoef.alloc(32 * (size_t)Bw);
+    c->afac.alloc(4 * (size_t)Bw);
     {
         std::vector<float> ones(Bw, 1.0f);
         HIPCHECK(hipMemcpyAsync(c->omega.p, ones.data(), 4 * (size_t)Bw, hipMemcpyHostToDevice, c->stream));
@@ -186,6 +191,7 @@ struct Block {
     struct Slot {
         int state = FREE;
         int32_t src = -1;
+        double alpha = 0.0;          // the query's stop probability
         double lambda = 0.0;
         double err = 0.0;            // bound on ||pi_hat - pi_s||_1 (exact right after a refresh)
         int32_t stage_left = 0;      // sweeps left in the current stage
@@ -208,7 +214,7 @@ struct Block {
     Graph& g;
     MixedCtxPtr c;
     int Bw;
-    double alpha;
+    double alpha;                    // reference alpha: the scale table's, and the default of a slot
     ppr_options opt;
     std::vector<Slot> slots;
     bool scratch_dirty = false;      // the FP64 scratch holds a local phase's values
@@ -219,6 +225,10 @@ struct Block {
     int32_t seq_sweeps = 0;
     double sweep_ms = 0.0;           // accumulated GPU time of the sweeps
     int32_t sweep_launches = 0;
+    EventPair ev_refresh;
+    bool refresh_timed = false;      // ev_refresh brackets the last refresh pass
+    double refresh_ms = 0.0;         // accumulated GPU time of the refresh passes
+    int32_t refresh_launches = 0;
     double refresh_factor;           // drop of err that ends a stage
 
     Block(Graph& gg, int width, double a, const ppr_options& o) : g(gg), Bw(width), alpha(a), opt(o) {
@@ -233,14 +243,17 @@ struct Block {
         if (Bw < 4 || Bw > 128 || (Bw & (Bw - 1))) fail(PPR_ERR_ARG, "block width must be a power of two in [4, 128]");
         if (opt.residue_format == PPR_RESIDUE_BF16 && Bw < 8)
             fail(PPR_ERR_ARG, "bf16 residues need a block of at least 8 columns");
-        int tile = sweep_tile(g, Bw);
+        int tile = sweep_tile(g, Bw, residues_bf16(opt, Bw));
         if (opt.sweep_tile != 0) {
             bool known = false;
             for (int t : mk::kTiles) known |= (t == opt.sweep_tile);
             if (!known) fail(PPR_ERR_ARG, "sweep_tile must be 0, 12288, 16384 or 24576");
             tile = opt.sweep_tile;
         }
-        c = mixed_acquire(g, Bw, frontier_capacity(g, opt, Bw), residues_bf16(opt, Bw));
+        c = mixed_acquire(g, Bw, frontier_capacity(g.n, g.m, opt, Bw), residues_bf16(opt, Bw));
+        // the caller's stream, if it gave one, carries every launch and copy of
+        // this block; HIP graphs are still captured on the context's own stream
+        if (opt.use_stream) c->stream = static_cast<hipStream_t>(opt.stream);
         const int chunks = sweep_chunks(g, opt);
         if (c->chunks != chunks) {
             c->drop_chunks();
@@ -259,6 +272,7 @@ struct Block {
             c->drop_chunks();
             c->alpha = alpha;
         }
+        upload_alphas();
     }
 
     ~Block() {
@@ -273,22 +287,43 @@ struct Block {
     void release() {
         if (!c) return;
         hipError_t e = hipStreamSynchronize(c->stream);
+        c->stream = c->own;
         if (!scratch_dirty && e == hipSuccess) mixed_release(g, std::move(c));
         else c.reset();
     }
 
-    int admit(int32_t s, double lambda) {
+    int admit(int32_t s, double a, double lambda) {
         for (int b = 0; b < Bw; ++b) {
             if (slots[b].state != FREE) continue;
             Slot& sl = slots[b];
             sl = Slot();
             sl.state = PENDING;
             sl.src = s;
+            sl.alpha = a;
             sl.lambda = lambda;
             sl.t_admit = now_ms();
             return b;
         }
         return -1;
+    }
+
+    // Per-column alpha coefficients (acoef, afac) of every slot; a free slot
+    // takes the reference alpha.  Running columns keep their values.
+    void upload_alphas() {
+        std::vector<double> co(4 * (size_t)Bw);
+        std::vector<float> fac(Bw);
+        for (int b = 0; b < Bw; ++b) {
+            const double a = slots[b].state == FREE ? alpha : slots[b].alpha;
+            co[b] = a;
+            co[Bw + b] = 1.0 - a;
+            co[2 * Bw + b] = 1.0 / (1.0 - a);
+            co[3 * Bw + b] = a / (1.0 - a);
+            fac[b] = a == alpha ? 1.0f : (float)((1.0 - a) / (1.0 - alpha));
+        }
+        HIPCHECK(hipMemcpyAsync(c->acoef.p, co.data(), 32 * (size_t)Bw, hipMemcpyHostToDevice, c->stream));
+        HIPCHECK(hipMemcpyAsync(c->afac.p, fac.data(), 4 * (size_t)Bw, hipMemcpyHostToDevice, c->stream));
+        // the host vectors die here: wait for the copies
+        HIPCHECK(hipStreamSynchronize(c->stream));
     }
 
     // Sweeps of one stage: until err has fallen by refresh_factor, or to
@@ -314,8 +349,8 @@ struct Block {
     // power-law graphs they contract like (1 - alpha)^1.5 .. (1 - alpha)^1.7);
     // a stage that falls short is simply followed by another.
     double first_rate(const Slot& sl) const {
-        if (c->chunks <= 1) return 1.0 - alpha;
-        return std::pow(1.0 - alpha, sl.omega > 1.0 ? 1.8 : 1.4);
+        if (c->chunks <= 1) return 1.0 - sl.alpha;
+        return std::pow(1.0 - sl.alpha, sl.omega > 1.0 ? 1.8 : 1.4);
     }
 
     // Contraction for the next stage's length.  A Jacobi sweep (one chunk)
@@ -333,14 +368,14 @@ struct Block {
     void update_rate(Slot& sl, double cert) const {
         if (c->chunks <= 1 || sl.stage_sweeps <= 0 || !(sl.stage_err0 > 0.0) || !(cert > 0.0)) return;
         double r = std::pow(cert / sl.stage_err0, 1.0 / sl.stage_sweeps);
-        if (sl.omega > 1.0 && !(r < std::pow(1.0 - alpha, 1.4))) {
+        if (sl.omega > 1.0 && !(r < std::pow(1.0 - sl.alpha, 1.4))) {
             sl.omega = 1.0;
             sl.rho = first_rate(sl);
             return;
         }
         r = std::pow(r, 0.95);
         r = std::ceil(r * 1024.0) / 1024.0;
-        sl.rho = std::min(1.0 - alpha, std::max(0.05, r));
+        sl.rho = std::min(1.0 - sl.alpha, std::max(0.05, r));
     }
 
     void upload_i32(DevBuf& d, const std::vector<int32_t>& h) {
@@ -371,6 +406,7 @@ struct Block {
         for (int b : cols) hc[b] = 1;
         upload_i32(c->src, hsrc);
         upload_i32(c->cmask, hc);
+        upload_alphas();
         HIPCHECK(hipMemcpyAsync(c->rmaxb.p, hrmax.data(), 8 * (size_t)Bw, hipMemcpyHostToDevice, ss));
         scratch_dirty = true;
         mk::init_sources(*c);
@@ -408,7 +444,7 @@ struct Block {
             HIPCHECK(hipMemcpyAsync(c->active.p, act.data(), (size_t)Bw, hipMemcpyHostToDevice, ss));
             HIPCHECK(hipMemsetAsync(c->ctr.p, 0, 8 * nctr, ss));
             HIPCHECK(hipMemsetAsync(c->taken.p, 0, 8 * (size_t)Bw, ss));
-            mk::snapshot(*c, g, F, nf, alpha);
+            mk::snapshot(*c, g, F, nf);
             k::exclusive_scan_i64(c->degF.as<int64_t>(), c->off.as<int64_t>(), nf, c->scan_tmp.p, ss);
             mk::push(*c, g, F, nf, vol, Fn);
             HIPCHECK(hipMemcpyAsync(hb, c->ctr.p, 8 * nctr, hipMemcpyDeviceToHost, ss));
@@ -432,7 +468,7 @@ struct Block {
             std::swap(F, Fn);
         }
         // FP64 -> block for these columns (alpha-part of the residue folded in)
-        mk::convert(*c, g, alpha);
+        mk::convert(*c, g);
         HIPCHECK(hipMemcpyAsync(hb, c->colsum.p, 8 * (size_t)Bw, hipMemcpyDeviceToHost, ss));
         HIPCHECK(hipStreamSynchronize(ss));
         scratch_dirty = false;
@@ -440,7 +476,7 @@ struct Block {
         for (int b : cols) {
             Slot& sl = slots[b];
             sl.state = RUNNING;
-            sl.err = (1.0 - alpha) * hcol[b];
+            sl.err = (1.0 - sl.alpha) * hcol[b];
             sl.entry = true;
             sl.t_moved = false;          // T holds the local phase's reserve
             sl.s_unset = true;           // the first refresh takes S = AS = 0 (rmask 2)
@@ -451,9 +487,13 @@ struct Block {
         }
     }
 
+    // Capture on the context's own stream (never the caller's, which may be
+    // the null stream); the work stream only launches the instantiated graph.
     void capture_chunk() {
-        hipStream_t ss = c->stream;
+        hipStream_t ss = c->own;
         hipGraph_t graph = nullptr;
+        const hipStream_t work = c->stream;
+        c->stream = ss;
         HIPCHECK(hipStreamBeginCapture(ss, hipStreamCaptureModeThreadLocal));
         const void* a = c->Y1.p;
         void* bb = c->Y0.p;
@@ -466,9 +506,11 @@ struct Block {
             }
         } catch (...) {
             (void)hipStreamEndCapture(ss, &graph);
+            c->stream = work;
             if (graph) (void)hipGraphDestroy(graph);
             throw;
         }
+        c->stream = work;
         HIPCHECK(hipStreamEndCapture(ss, &graph));
         hipError_t e = hipGraphInstantiate(&c->chunk[c->sor ? 1 : 0], graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
@@ -495,6 +537,11 @@ struct Block {
             sweep_ms += ev_sweep.elapsed_ms();
             sweep_launches += seq_sweeps;
             sweep_timed = false;
+        }
+        if (refresh_timed) {
+            refresh_ms += ev_refresh.elapsed_ms();
+            refresh_launches += 1;
+            refresh_timed = false;
         }
         const double* hcol = c->host.as<double>();
         for (int b = 0; b < Bw; ++b) {
@@ -602,7 +649,10 @@ struct Block {
         }
         if (any) {
             upload_i32(c->rmask, hr);
+            ev_refresh.start(ss);
             mk::refresh(*c, g, const_cast<void*>(c->ycur), nullptr);
+            ev_refresh.stop(ss);
+            refresh_timed = true;
             HIPCHECK(hipMemcpyAsync(c->host.p, c->colsum.p, 8 * (size_t)Bw, hipMemcpyDeviceToHost, ss));
         }
         if (any || sweep_timed) {
@@ -635,6 +685,9 @@ struct Block {
         st->residue_format = c->bf16 ? PPR_RESIDUE_BF16 : PPR_RESIDUE_F32;
         st->push_scans = 0;
         st->sweep_tile_bytes = c->tile;
+        st->refresh_ms = refresh_ms;
+        st->refresh_launches = refresh_launches;
+        st->reserved = 0;
     }
 
     // Export slot b (DONE) into out[n] (host or device) and free the slot;
@@ -668,7 +721,7 @@ void run_mixed_chunk(Block& blk, const int32_t* sources, int Breal, double lambd
     Graph& g = blk.g;
     MixedCtx& c = *blk.c;
     for (int b = 0; b < Breal; ++b)
-        if (blk.admit(sources[b], lambda) != b) fail(PPR_ERR_ARG, "internal: batch slot order");
+        if (blk.admit(sources[b], blk.alpha, lambda) != b) fail(PPR_ERR_ARG, "internal: batch slot order");
     while (!blk.settled()) {     // each slot ends: certified, or at its sweep cap
         blk.step(1 << 30);
         blk.collect(true);
@@ -716,7 +769,8 @@ int default_batch_width(int32_t B) {
 void run_mixed_batch(Graph& g, const int32_t* sources, int32_t B, double alpha, double lambda,
                      const ppr_options& opt, double* pi_out, double* r_out, ppr_stats* st) {
     HIPCHECK(hipSetDevice(g.device));
-    int Bw = opt.batch_cols > 0 ? opt.batch_cols : (g.tuned_width > 0 ? g.tuned_width : default_batch_width(B));
+    const int tw = g.tuned_width.load();
+    int Bw = opt.batch_cols > 0 ? opt.batch_cols : (tw > 0 ? tw : default_batch_width(B));
     if (opt.batch_cols == 0 && opt.residue_format == PPR_RESIDUE_BF16) Bw = std::max(Bw, 8);   // 8-column vectors
     if (Bw < 4 || Bw > 128 || (Bw & (Bw - 1))) fail(PPR_ERR_ARG, "batch_cols must be a power of two in [4, 128]");
     ppr_status first = PPR_OK;
@@ -759,14 +813,14 @@ void autotune_width(Graph& g, double alpha, const int32_t* widths, int32_t count
     for (int32_t i = 0; i < count; ++i) {
         int W = widths[i];
         if (W < 4 || W > 128 || (W & (W - 1))) fail(PPR_ERR_ARG, "candidate widths must be powers of two in [4, 128]");
-        int64_t fcap = frontier_capacity(g, opt, W);
+        int64_t fcap = frontier_capacity(g.n, g.m, opt, W);
         bool pooled = false;
         {
             std::lock_guard<std::mutex> lk(g.pool_mu);
             for (auto& cc : g.mixed_pool)
                 pooled |= (cc->Bw == W && cc->fcap >= fcap && cc->bf16 == residues_bf16(opt, W));
         }
-        if (!pooled && mixed_footprint(g, W, fcap, residues_bf16(opt, W)) > free_b / 2) {
+        if (!pooled && mixed_footprint(g.n, g.m, W, fcap, residues_bf16(opt, W)) > free_b / 2) {
             if (cost_us) cost_us[i] = -1.0;
             continue;
         }
@@ -805,7 +859,7 @@ void autotune_width(Graph& g, double alpha, const int32_t* widths, int32_t count
                 us = tile_us[ti];
                 tile = mk::kTiles[ti];
             }
-        g.tuned_tile[ilog2(W) & 7] = tile;
+        g.tuned_tile[c.bf16 ? 1 : 0][ilog2(W) & 7].store(tile);
         c.drop_chunks();
         c.tile = tile;
         mk::prepare(c, g);
@@ -900,12 +954,14 @@ void serve_block_destroy(void* h) {
     g.live_blocks -= 1;
 }
 
-int32_t serve_admit(void* h, int32_t s, double lambda) {
+int32_t serve_admit(void* h, int32_t s, double alpha, double lambda) {
     Block* blk = static_cast<Block*>(h);
     HIPCHECK(hipSetDevice(blk->g.device));
     if (s < 0 || s >= blk->g.n) fail(PPR_ERR_ARG, "source outside [0, n)");
+    if (alpha == 0.0) alpha = blk->alpha;          // the block's reference alpha
+    if (!(alpha > 0.0 && alpha < 1.0)) fail(PPR_ERR_ARG, "alpha must lie in (0, 1), or be 0 for the block's");
     if (!(lambda > 0.0 && lambda <= 1.0)) fail(PPR_ERR_ARG, "lambda must lie in (0, 1]");
-    int b = blk->admit(s, lambda);
+    int b = blk->admit(s, alpha, lambda);
     if (b < 0) fail(PPR_ERR_BUSY, "no free slot in the block");
     return b;
 }
@@ -940,11 +996,10 @@ void serve_retire(void* h, int32_t slot, double* pi_out, ppr_stats* st) {
     blk->retire(slot, pi_out, st);
 }
 
-size_t serve_footprint(const Graph& g, int32_t slots) {
+size_t serve_footprint(int32_t n, int64_t m, int32_t slots) {
     ppr_options opt;
     ppr_options_default(&opt);
-    return mixed_footprint(g, slots, frontier_capacity(g, opt, slots), residues_bf16(opt, slots)) +
-           sizeof(Block);
+    return mixed_footprint(n, m, slots, frontier_capacity(n, m, opt, slots), residues_bf16(opt, slots));
 }
 
 }  // namespace ppr

@@ -40,12 +40,13 @@ struct Rf {
 
 // Device state of one block of Bw columns on one graph.
 struct MixedCtx {
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;     // work stream: `own`, or the caller's stream while a block uses it
+    hipStream_t own = nullptr;        // the context's own stream (created with it; HIP graphs are captured here)
     int32_t n = 0;
     int Bw = 0, shift = 0;
     int chunks = 1;                   // row chunks per sweep (block Gauss-Seidel order when > 1)
     int tile = mk::kLdsBytes;         // LDS stage of a sweep block, one of mk::kTiles
-    double alpha = -1.0;              // alpha the scale table holds
+    double alpha = -1.0;              // alpha the scale table holds (the block's reference alpha)
     int64_t fcap = 0;                 // frontier capacity (entries)
     DevBuf r64, pi64;                 // double[n][Bw]  local-phase scratch, zero between uses
     DevBuf F0, F1, X, degF, off;      // frontier (int64 keys), increments, degrees, prefix
@@ -72,6 +73,10 @@ struct MixedCtx {
     DevBuf stage;                     // double[Bw][n] host-output staging (lazy)
     DevBuf piece_part;                // float[pieces][Bw]: partial sums of long-row pieces
     DevBuf omega;                     // float[Bw]      over-relaxation factor per column
+    DevBuf acoef;                     // double[4][Bw]  per column: alpha_b, 1 - alpha_b, 1 / (1 - alpha_b),
+                                      //                alpha_b / (1 - alpha_b)
+    DevBuf afac;                      // float[Bw]      (1 - alpha_b) / (1 - alpha): the column's factor on
+                                      //                the scale table (exactly 1 when alpha_b = alpha)
     bool sor = false;                 // the next sweeps run the over-relaxed update
     PinnedBuf host;                   // readback area
     hipGraphExec_t chunk[2] = {nullptr, nullptr};   // captured sweep chunks Y1 -> Y0 -> ... -> Y1
@@ -84,19 +89,20 @@ struct MixedCtx {
 
 MixedCtxPtr mixed_acquire(Graph& g, int Bw, int64_t fcap, bool bf16);
 void mixed_release(Graph& g, MixedCtxPtr c);
-int64_t frontier_capacity(const Graph& g, const ppr_options& opt, int Bw);
-size_t mixed_footprint(const Graph& g, int Bw, int64_t fcap, bool bf16);
+int64_t frontier_capacity(int32_t n, int64_t m, const ppr_options& opt, int Bw);
+size_t mixed_footprint(int32_t n, int64_t m, int Bw, int64_t fcap, bool bf16);
 
 // Launchers (mixed_kernels.hip).  All run on c.stream.
 namespace mk {
 void set_scale(Graph& g, MixedCtx& c, double alpha);
 // r64 = e_s for the columns with cmask = 1
 void init_sources(MixedCtx& c);
-void snapshot(MixedCtx& c, const Graph& g, const int64_t* F, int64_t nf, double alpha);
+// per-column alpha: c.acoef
+void snapshot(MixedCtx& c, const Graph& g, const int64_t* F, int64_t nf);
 // rmax per column: c.rmaxb (lambda_b / m)
 void push(MixedCtx& c, const Graph& g, const int64_t* F, int64_t nf, int64_t vol, int64_t* F_next);
 // FP64 scratch -> block for the columns with cmask = 1 (others untouched); per-column sums of r -> colsum
-void convert(MixedCtx& c, const Graph& g, double alpha);
+void convert(MixedCtx& c, const Graph& g);
 // build the graph's sweep and refresh schedules for this width (they allocate,
 // so this runs before any stream capture)
 void prepare(MixedCtx& c, const Graph& g);

@@ -14,7 +14,13 @@
 //   T[n][B]         FP32 per-stage accumulator of reserve increments
 
 // Columns are independent: each one is a query with its own source, its own
-// lambda and its own schedule.
+// alpha, its own lambda and its own schedule.  The per-node scale table holds
+// (1 - alpha) / d_u for the block's reference alpha; a column with another
+// alpha_b multiplies it by the FP32 factor (1 - alpha_b) / (1 - alpha), which
+// is exactly 1 for the reference alpha, and every FP64 step (local phase,
+// conversion, refresh, export) takes alpha_b itself from the per-column
+// coefficients acoef = [alpha_b | 1 - alpha_b | 1 / (1 - alpha_b) |
+// alpha_b / (1 - alpha_b)] (each Bw long).
 //  - local phase (FP64): the iteration sets S^(j) of Section 4.2 pushed
 //    simultaneously, one frontier list of (node << log2 B | column) keys, FP64
 //    atomics into a dense FP64 scratch; then conversion into the block (the
@@ -149,7 +155,8 @@ __global__ void init_sources_k(const int32_t* __restrict__ src, const int32_t* _
 // Frontier entry i: key = (node << shift) | column.  Columns whose local
 // phase is over (active[b] == 0) are skipped; their residue stays in place.
 __global__ void snapshot_k(const int64_t* __restrict__ F, int64_t nf, int shift,
-                           const uint8_t* __restrict__ active, const int32_t* __restrict__ deg, double alpha,
+                           const uint8_t* __restrict__ active, const int32_t* __restrict__ deg,
+                           const double* __restrict__ alpha_b,
                            double* __restrict__ r64, double* __restrict__ pi64, double* __restrict__ X,
                            int64_t* __restrict__ degF, double* __restrict__ taken) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -162,6 +169,7 @@ __global__ void snapshot_k(const int64_t* __restrict__ F, int64_t nf, int shift,
         degF[i] = 0;
         return;
     }
+    const double alpha = alpha_b[b];
     double x = atomicExch(&r64[key], 0.0);      // a key listed twice would push once
     pi64[key] += alpha * x;
     atomicAdd(&taken[b], alpha * x);
@@ -242,7 +250,7 @@ __global__ __launch_bounds__(kBlock) void push_k(
 // pulled it), so the first sweep of the column runs with its entry flag:
 // it folds the alpha-part into T and pulls y along every in-edge.
 // partials[block][B]: per-column sums of r.
-__global__ void convert_k(int32_t n, int shift, const int32_t* __restrict__ deg, double alpha,
+__global__ void convert_k(int32_t n, int shift, const int32_t* __restrict__ deg, const double* __restrict__ alpha_b,
                           const int32_t* __restrict__ cmask, double* __restrict__ r64, double* __restrict__ pi64,
                           void* __restrict__ Y, int y_bf16, float* __restrict__ T, double* __restrict__ partials) {
     __shared__ double sh[kBlock];
@@ -253,6 +261,7 @@ __global__ void convert_k(int32_t n, int shift, const int32_t* __restrict__ deg,
     const int64_t total = (int64_t)n << shift;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;     // a multiple of B
     const int b = threadIdx.x & (B - 1);                          // this thread's column, fixed
+    const double alpha = alpha_b[b];
     double acc = 0.0;
     if (cm[b]) {
         for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
@@ -354,19 +363,21 @@ __device__ inline typename ST::V gather_gs(const typename ST::V* __restrict__ Y_
 // (u C + c) K/4 + i of T, int4s / float4s c K/4 + i of kb, entry, omega.
 template <int C, bool SOR, typename ST>
 __device__ inline void finish_row(int32_t u, int c, Vec<ST::K> acc, int32_t step, int32_t last,
-                                  const float* __restrict__ scale,
+                                  const float* __restrict__ scale, const float* __restrict__ afac,
                                   const typename ST::V* __restrict__ Y_in, typename ST::V* Y_out,
                                   float4* __restrict__ T, const int32_t* __restrict__ kb,
                                   const int32_t* __restrict__ entry, const float* __restrict__ omega) {
     constexpr int K = ST::K, Q = K / 4;
     const int64_t at = (int64_t)u * C + c;
     const float sc = scale[u];
-    Vec<K> m, en = v_zero<K>(), keep;
+    Vec<K> m, mf, en = v_zero<K>(), keep;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int4 kb4 = reinterpret_cast<const int4*>(kb)[c * Q + i];
         m.q[i] = make_float4(step < kb4.x ? 1.f : 0.f, step < kb4.y ? 1.f : 0.f, step < kb4.z ? 1.f : 0.f,
                              step < kb4.w ? 1.f : 0.f);
+        // the column's alpha factor on the scale table (1 for the reference alpha)
+        mf.q[i] = f4_mul(m.q[i], reinterpret_cast<const float4*>(afac)[c * Q + i]);
     }
     bool any_en = false;
     if (step == 0) {
@@ -384,7 +395,7 @@ __device__ inline void finish_row(int32_t u, int c, Vec<ST::K> acc, int32_t step
     // even step's output (odd steps), the fresh residue (entry sweep)
     Vec<K> yin = v_zero<K>();
     if (SOR || odd || any_en) yin = ST::value(Y_in[at]);
-    acc = v_mul(acc, m);
+    acc = v_mul(acc, mf);
     Vec<K> y;
 #pragma unroll
     for (int i = 0; i < Q; ++i)
@@ -423,6 +434,7 @@ template <typename OffT, int C, bool SOR, typename ST, int L>
 __global__ __launch_bounds__(kBlock) void sweep_k(
         const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
         const RowBlock* __restrict__ blocks, int32_t lo, const float* __restrict__ scale,
+        const float* __restrict__ afac,
         const typename ST::V* __restrict__ Y_in, typename ST::V* Y_out, float4* __restrict__ T,
         const int32_t* __restrict__ kb, const int32_t* __restrict__ entry, const int32_t* __restrict__ step_p,
         Vec<ST::K>* __restrict__ partials, const float* __restrict__ omega) {
@@ -491,14 +503,14 @@ __global__ __launch_bounds__(kBlock) void sweep_k(
         partials[(int64_t)b.piece * C + c] = acc;
         return;
     }
-    finish_row<C, SOR, ST>(r0 + row, c, acc, step, step_p[1], scale, Y_in, Y_out, T, kb, entry, omega);
+    finish_row<C, SOR, ST>(r0 + row, c, acc, step, step_p[1], scale, afac, Y_in, Y_out, T, kb, entry, omega);
 }
 
 // Long rows of one chunk: the pieces' partial sums added in slot order.
 template <int C, bool SOR, typename ST>
 __global__ __launch_bounds__(kBlock) void combine_k(
         const LongRow* __restrict__ rows, int32_t count, const Vec<ST::K>* __restrict__ partials,
-        const int32_t* __restrict__ step_p, const float* __restrict__ scale,
+        const int32_t* __restrict__ step_p, const float* __restrict__ scale, const float* __restrict__ afac,
         const typename ST::V* __restrict__ Y_in, typename ST::V* Y_out, float4* __restrict__ T,
         const int32_t* __restrict__ kb, const int32_t* __restrict__ entry, const float* __restrict__ omega) {
     const int32_t i = (int32_t)blockIdx.x * (kBlock / C) + (int32_t)threadIdx.x / C;
@@ -507,7 +519,7 @@ __global__ __launch_bounds__(kBlock) void combine_k(
     const LongRow L = rows[i];
     Vec<ST::K> acc = v_zero<ST::K>();
     for (int32_t p = 0; p < L.npieces; ++p) acc = v_add(acc, partials[(int64_t)(L.first + p) * C + c]);
-    finish_row<C, SOR, ST>(L.row, c, acc, step_p[0], step_p[1], scale, Y_in, Y_out, T, kb, entry, omega);
+    finish_row<C, SOR, ST>(L.row, c, acc, step_p[0], step_p[1], scale, afac, Y_in, Y_out, T, kb, entry, omega);
 }
 
 __global__ void bump_step_k(int32_t* step) { step[0] += 1; }
@@ -546,15 +558,16 @@ __global__ __launch_bounds__(kBlock) void refresh_k(
         const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
         const RowBlock* __restrict__ blocks, int32_t n_blocks,
         const int32_t* __restrict__ deg, const float4* __restrict__ T, double2* __restrict__ S,
-        double2* __restrict__ AS, const int32_t* __restrict__ src, const int32_t* __restrict__ rmask, double alpha,
+        double2* __restrict__ AS, const int32_t* __restrict__ src, const int32_t* __restrict__ rmask,
+        const double* __restrict__ acoef, int32_t Bw,
         typename ST::V* __restrict__ Y, double* __restrict__ rt_out, int32_t n,
         double* __restrict__ partials) {
     using P = Rf<C>;
     __shared__ float4 lds[P::kNnz * C];
     __shared__ double red[kBlock * 4];
     double cs0 = 0.0, cs1 = 0.0, cs2 = 0.0, cs3 = 0.0;   // threads c < C: |rt| of columns 4c..4c+3
-    const double inv_oma = 1.0 / (1.0 - alpha);
-    const double oma = 1.0 - alpha;
+    const double* __restrict__ oma_b = acoef + Bw;         // 1 - alpha_b
+    const double* __restrict__ inv_b = acoef + 2 * Bw;     // 1 / (1 - alpha_b)
     for (int32_t bi = blockIdx.x; bi < n_blocks; bi += gridDim.x) {
         const RowBlock b = blocks[bi];
         const bool whole = b.piece == -1;
@@ -624,10 +637,12 @@ __global__ __launch_bounds__(kBlock) void refresh_k(
             if (w4.w == 2) sb.y = ab.y = 0.0;
             // the in-neighbour sums of S + T
             const double a0 = aa.x + g0, a1 = aa.y + g1, a2 = ab.x + g2, a3 = ab.y + g3;
-            t0 = (s4.x == u ? 1.0 : 0.0) - d * (sa.x + (double)t.x) * inv_oma + a0;
-            t1 = (s4.y == u ? 1.0 : 0.0) - d * (sa.y + (double)t.y) * inv_oma + a1;
-            t2 = (s4.z == u ? 1.0 : 0.0) - d * (sb.x + (double)t.z) * inv_oma + a2;
-            t3 = (s4.w == u ? 1.0 : 0.0) - d * (sb.y + (double)t.w) * inv_oma + a3;
+            const double2 i01 = reinterpret_cast<const double2*>(inv_b)[2 * c];
+            const double2 i23 = reinterpret_cast<const double2*>(inv_b)[2 * c + 1];
+            t0 = (s4.x == u ? 1.0 : 0.0) - d * (sa.x + (double)t.x) * i01.x + a0;
+            t1 = (s4.y == u ? 1.0 : 0.0) - d * (sa.y + (double)t.y) * i01.y + a1;
+            t2 = (s4.z == u ? 1.0 : 0.0) - d * (sb.x + (double)t.z) * i23.x + a2;
+            t3 = (s4.w == u ? 1.0 : 0.0) - d * (sb.y + (double)t.w) * i23.y + a3;
             if (w4.x | w4.y | w4.z | w4.w) {     // the refreshed columns keep the new sums
                 AS[2 * at] = make_double2(w4.x ? a0 : aa.x, w4.y ? a1 : aa.y);
                 AS[2 * at + 1] = make_double2(w4.z ? a2 : ab.x, w4.w ? a3 : ab.y);
@@ -636,10 +651,12 @@ __global__ __launch_bounds__(kBlock) void refresh_k(
             }
             if (w4.x | w4.y | w4.z | w4.w) {     // other columns keep their bits (exact round trip)
                 float4 y = ST::value4(Y[at]);
-                if (w4.x) y.x = (float)(oma * t0 / d);
-                if (w4.y) y.y = (float)(oma * t1 / d);
-                if (w4.z) y.z = (float)(oma * t2 / d);
-                if (w4.w) y.w = (float)(oma * t3 / d);
+                const double2 o01 = reinterpret_cast<const double2*>(oma_b)[2 * c];
+                const double2 o23 = reinterpret_cast<const double2*>(oma_b)[2 * c + 1];
+                if (w4.x) y.x = (float)(o01.x * t0 / d);
+                if (w4.y) y.y = (float)(o01.y * t1 / d);
+                if (w4.z) y.z = (float)(o23.x * t2 / d);
+                if (w4.w) y.w = (float)(o23.y * t3 / d);
                 Y[at] = ST::pack4(y);
             }
             if (rt_out) {   // column-major FP64 residual [B][n]
@@ -676,9 +693,9 @@ __global__ __launch_bounds__(kBlock) void refresh_k(
 }
 
 // ---------------------------------------------------------------- export
-// pi_hat(u, b) = alpha d_u S / (1 - alpha) for columns [b0, b0 +
+// pi_hat(u, b) = alpha_b d_u S / (1 - alpha_b) for columns [b0, b0 +
 // count), written row-major [count][n] through an LDS transpose of
-// kNodes nodes x B columns.
+// kNodes nodes x B columns (f: alpha_b / (1 - alpha_b) per column).
 template <int C>
 struct Ex {
     static constexpr int kNodes = (4 * C >= 128) ? 32 : 64;
@@ -686,18 +703,17 @@ struct Ex {
 
 template <int C>
 __global__ __launch_bounds__(kBlock) void export_k(int32_t n, int32_t b0, int32_t count,
-                                                   const int32_t* __restrict__ deg, double alpha,
+                                                   const int32_t* __restrict__ deg, const double* __restrict__ f,
                                                    const double* __restrict__ S, double* __restrict__ out) {
     constexpr int B = 4 * C;
     constexpr int kNodes = Ex<C>::kNodes;
     __shared__ double tile[kNodes * (B + 1)];
     const int64_t u0 = (int64_t)blockIdx.x * kNodes;
-    const double f = alpha / (1.0 - alpha);
     for (int i = threadIdx.x; i < kNodes * B; i += kBlock) {
         int du = i / B, b = i % B;
         int64_t u = u0 + du;
         double v = 0.0;
-        if (u < n) v = f * (double)deg[u] * S[u * B + b];
+        if (u < n) v = f[b] * (double)deg[u] * S[u * B + b];
         tile[du * (B + 1) + b] = v;
     }
     __syncthreads();
@@ -708,9 +724,9 @@ __global__ __launch_bounds__(kBlock) void export_k(int32_t n, int32_t b0, int32_
     }
 }
 
-__global__ void export_col_k(int32_t n, int shift, int32_t b, const int32_t* __restrict__ deg, double alpha,
-                             const double* __restrict__ S, double* __restrict__ out) {
-    const double f = alpha / (1.0 - alpha);
+__global__ void export_col_k(int32_t n, int shift, int32_t b, const int32_t* __restrict__ deg,
+                             const double* __restrict__ fb, const double* __restrict__ S, double* __restrict__ out) {
+    const double f = fb[b];
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
         int64_t i = (u << shift) + b;
@@ -754,12 +770,12 @@ void sweep_launch(MixedCtx& c, Graph& g, const void* yin, void* yout) {
         const RowBlock* bj = blocks + sch.first[j];
         if (g.off64)
             hipLaunchKernelGGL((sweep_k<int64_t, C, SOR, ST, L>), grid, blk, 0, c.stream, g.col_ptr.as<int64_t>(),
-                               g.row_idx.as<int32_t>(), bj, sch.lo[j], c.scale.as<float>(), Y4i, Y4o,
+                               g.row_idx.as<int32_t>(), bj, sch.lo[j], c.scale.as<float>(), c.afac.as<float>(), Y4i, Y4o,
                                c.T.as<float4>(), c.kb.as<int32_t>(), c.entry.as<int32_t>(), c.step.as<int32_t>(),
                                part, om);
         else
             hipLaunchKernelGGL((sweep_k<uint32_t, C, SOR, ST, L>), grid, blk, 0, c.stream, g.col_ptr.as<uint32_t>(),
-                               g.row_idx.as<int32_t>(), bj, sch.lo[j], c.scale.as<float>(), Y4i, Y4o,
+                               g.row_idx.as<int32_t>(), bj, sch.lo[j], c.scale.as<float>(), c.afac.as<float>(), Y4i, Y4o,
                                c.T.as<float4>(), c.kb.as<int32_t>(), c.entry.as<int32_t>(), c.step.as<int32_t>(),
                                part, om);
         const int32_t nl = sch.lr_first[j + 1] - sch.lr_first[j];
@@ -767,7 +783,7 @@ void sweep_launch(MixedCtx& c, Graph& g, const void* yin, void* yout) {
             const int per = kBlock / C;
             hipLaunchKernelGGL((combine_k<C, SOR, ST>), dim3((unsigned)((nl + per - 1) / per)), dim3(kBlock), 0,
                                c.stream, lrows + sch.lr_first[j], nl, part, c.step.as<int32_t>(),
-                               c.scale.as<float>(), Y4i, Y4o, c.T.as<float4>(), c.kb.as<int32_t>(),
+                               c.scale.as<float>(), c.afac.as<float>(), Y4i, Y4o, c.T.as<float4>(), c.kb.as<int32_t>(),
                                c.entry.as<int32_t>(), om);
         }
     }
@@ -805,12 +821,12 @@ void refresh_launch(MixedCtx& c, Graph& g, void* y, double* rt_out) {
     if (g.off64)
         hipLaunchKernelGGL((refresh_k<int64_t, C, ST>), grid, blk, 0, c.stream, g.col_ptr.as<int64_t>(),
                            g.row_idx.as<int32_t>(), sch.blocks.as<RowBlock>(), sch.n_blocks,
-                           g.deg.as<int32_t>(), T4, S2, A2, c.src.as<int32_t>(), c.rmask.as<int32_t>(), c.alpha, Y4,
+                           g.deg.as<int32_t>(), T4, S2, A2, c.src.as<int32_t>(), c.rmask.as<int32_t>(), c.acoef.as<double>(), c.Bw, Y4,
                            rt_out, g.n, c.partials.as<double>());
     else
         hipLaunchKernelGGL((refresh_k<uint32_t, C, ST>), grid, blk, 0, c.stream, g.col_ptr.as<uint32_t>(),
                            g.row_idx.as<int32_t>(), sch.blocks.as<RowBlock>(), sch.n_blocks,
-                           g.deg.as<int32_t>(), T4, S2, A2, c.src.as<int32_t>(), c.rmask.as<int32_t>(), c.alpha, Y4,
+                           g.deg.as<int32_t>(), T4, S2, A2, c.src.as<int32_t>(), c.rmask.as<int32_t>(), c.acoef.as<double>(), c.Bw, Y4,
                            rt_out, g.n, c.partials.as<double>());
     hipLaunchKernelGGL(reduce_cols_k, dim3((unsigned)c.Bw), dim3(kBlock), 0, c.stream, c.partials.as<double>(), (int)grid.x, c.Bw,
                        c.colsum.as<double>());
@@ -828,7 +844,7 @@ void export_c(MixedCtx& c, Graph& g, int b0, int count, double* out) {
     constexpr int kNodes = Ex<C>::kNodes;
     unsigned grid = (unsigned)((g.n + kNodes - 1) / kNodes);
     hipLaunchKernelGGL((export_k<C>), dim3(grid), dim3(kBlock), 0, c.stream, g.n, b0, count, g.deg.as<int32_t>(),
-                       c.alpha, c.S.as<double>(), out);
+                       c.acoef.as<double>() + 3 * c.Bw, c.S.as<double>(), out);
     HIPCHECK(hipGetLastError());
 }
 
@@ -860,10 +876,10 @@ void init_sources(MixedCtx& c) {
     HIPCHECK(hipGetLastError());
 }
 
-void snapshot(MixedCtx& c, const Graph& g, const int64_t* F, int64_t nf, double alpha) {
+void snapshot(MixedCtx& c, const Graph& g, const int64_t* F, int64_t nf) {
     unsigned gs = (unsigned)((nf + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(snapshot_k, dim3(gs), dim3(kBlock), 0, c.stream, F, nf, c.shift, c.active.as<uint8_t>(),
-                       g.deg.as<int32_t>(), alpha, c.r64.as<double>(), c.pi64.as<double>(), c.X.as<double>(),
+                       g.deg.as<int32_t>(), c.acoef.as<double>(), c.r64.as<double>(), c.pi64.as<double>(), c.X.as<double>(),
                        c.degF.as<int64_t>(), c.taken.as<double>());
     HIPCHECK(hipGetLastError());
 }
@@ -878,9 +894,10 @@ void push(MixedCtx& c, const Graph& g, const int64_t* F, int64_t nf, int64_t vol
     HIPCHECK(hipGetLastError());
 }
 
-void convert(MixedCtx& c, const Graph& g, double alpha) {
+void convert(MixedCtx& c, const Graph& g) {
     const unsigned gc = 1024;
-    hipLaunchKernelGGL(convert_k, dim3(gc), dim3(kBlock), 0, c.stream, g.n, c.shift, g.deg.as<int32_t>(), alpha,
+    hipLaunchKernelGGL(convert_k, dim3(gc), dim3(kBlock), 0, c.stream, g.n, c.shift, g.deg.as<int32_t>(),
+                       c.acoef.as<double>(),
                        c.cmask.as<int32_t>(), c.r64.as<double>(), c.pi64.as<double>(),
                        const_cast<void*>(c.ycur), c.bf16 ? 1 : 0, c.T.as<float>(), c.partials.as<double>());
     hipLaunchKernelGGL(reduce_cols_k, dim3((unsigned)c.Bw), dim3(kBlock), 0, c.stream, c.partials.as<double>(), (int)gc, c.Bw,
@@ -948,7 +965,7 @@ void export_cols(MixedCtx& c, const Graph& g, int b0, int count, double* out) {
 
 void export_col(MixedCtx& c, const Graph& g, int b, double* out) {
     hipLaunchKernelGGL(export_col_k, dim3(2048), dim3(kBlock), 0, c.stream, g.n, c.shift, b, g.deg.as<int32_t>(),
-                       c.alpha, c.S.as<double>(), out);
+                       c.acoef.as<double>() + 3 * c.Bw, c.S.as<double>(), out);
     HIPCHECK(hipGetLastError());
 }
 

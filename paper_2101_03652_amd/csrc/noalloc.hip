@@ -207,6 +207,9 @@ void run_fp64_query_noalloc(Graph& g, int32_t s, double alpha, double lambda, hi
         st->residue_format = PPR_RESIDUE_F32;
         st->push_scans = 0;
         st->sweep_tile_bytes = 0;
+        st->refresh_ms = 0.0;
+        st->refresh_launches = 0;
+        st->reserved = 0;
     }
     if (r_sum > lambda) fail(PPR_ERR_NOT_CONVERGED, "max_sweeps reached before r_sum <= lambda");
 }

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <chrono>
 #include <cstdint>
 #include <cstdio>
@@ -162,8 +163,11 @@ struct Graph {
     std::mutex pool_mu;
     std::vector<std::unique_ptr<QueryCtx>> pool;       // idle FP64 query contexts
     std::vector<MixedCtxPtr> mixed_pool;               // idle batched contexts (any width)
-    int tuned_width = 0;                               // autotuner's choice (0 = not tuned)
-    int tuned_tile[8] = {};                            // sweep stage bytes per log2(width) (0 = default)
+    // autotuner's choices (ppr_autotune; atomics: a query may read them while it
+    // runs): the block width (0 = not tuned) and the sweep stage bytes per
+    // residue format (0 FP32, 1 bf16) and log2(width) (0 = default)
+    std::atomic<int> tuned_width{0};
+    std::atomic<int> tuned_tile[2][8] = {};
     DevBuf walk_index;                                 // int32[m]: stop nodes of d_v walks per node
     double walk_alpha = -1.0;                          // the index's alpha (-1: none)
     uint64_t walk_seed = 0;                            // the index's seed
@@ -184,7 +188,8 @@ void graph_copy_csc(const Graph& g, int64_t* col_ptr, int32_t* row_idx, int32_t*
 constexpr int64_t kAuxLen = 4 * 1024 + 16;
 
 struct QueryCtx {
-    hipStream_t stream = nullptr;
+    hipStream_t stream = nullptr;   // work stream: `own`, or the caller's stream during a query on it
+    hipStream_t own = nullptr;      // the context's own stream (HIP graphs are captured here)
     int32_t n = 0;
     DevBuf r;          // double[n]  residue
     DevBuf pi;         // double[n]  reserve
@@ -308,10 +313,16 @@ void debug_sweeps_mixed(Graph& g, double alpha, int32_t B, int32_t chunks, int32
 // serving blocks (continuous batching); the handle is an opaque Block*
 void* serve_block_create(Graph& g, int32_t slots, double alpha, const ppr_options& opt);
 void serve_block_destroy(void* blk);
-int32_t serve_admit(void* blk, int32_t s, double lambda);
+int32_t serve_admit(void* blk, int32_t s, double alpha, double lambda);
 void serve_step(void* blk, int32_t max_sweeps);
 void serve_poll(void* blk, int wait, uint8_t* done, int32_t* n_done, int32_t* n_busy, int32_t* ready);
 void serve_retire(void* blk, int32_t slot, double* pi_out, ppr_stats* st);
-size_t serve_footprint(const Graph& g, int32_t slots);
+// device bytes of a serving block of `slots` columns on a graph of n nodes and
+// m edges (default options), and of one FP64 query context on n nodes; both
+// depend on the sizes only
+size_t serve_footprint(int32_t n, int64_t m, int32_t slots);
+size_t fp64_ctx_footprint(int32_t n);
+// device bytes of a graph's CSR, CSC and degree table (its row schedules not counted)
+size_t graph_footprint(int32_t n, int64_t m);
 
 }  // namespace ppr

@@ -10,7 +10,7 @@ namespace ppr {
 
 QueryCtx::~QueryCtx() {
     if (chunk_exec) (void)hipGraphExecDestroy(chunk_exec);
-    if (stream) (void)hipStreamDestroy(stream);
+    if (own) (void)hipStreamDestroy(own);
 }
 
 std::unique_ptr<QueryCtx> ctx_acquire(Graph& g) {
@@ -25,7 +25,8 @@ std::unique_ptr<QueryCtx> ctx_acquire(Graph& g) {
     auto c = std::make_unique<QueryCtx>();
     const size_t n = (size_t)g.n;
     c->n = g.n;
-    HIPCHECK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    HIPCHECK(hipStreamCreateWithFlags(&c->own, hipStreamNonBlocking));
+    c->stream = c->own;
     c->r.alloc(8 * n);
     c->pi.alloc(8 * n);
     c->y0.alloc(8 * n);
@@ -51,15 +52,30 @@ void ctx_release(Graph& g, std::unique_ptr<QueryCtx> c) {
     g.pool.push_back(std::move(c));
 }
 
+// Upper bound on what ctx_acquire allocates for n nodes: seven n-vectors of
+// 8 bytes and two of 4 (state, frontier lists, increments, degrees, prefix),
+// per-block partials (a sweep schedule has at most one block per row), the
+// scan scratch, the compaction counters and the readback area.
+size_t fp64_ctx_footprint(int32_t n) {
+    const size_t nn = (size_t)n;
+    return 8 * 7 * nn + 4 * 2 * nn + 8 + 8 * std::max<size_t>({nn, 4096, (nn + 255) / 256}) +
+           k::scan_tmp_bytes(std::max<int64_t>(n, 4096)) + 8 * (size_t)kAuxLen + 192;
+}
+
 namespace {
 
+// A pooled context for one query; with the caller's stream (options
+// use_stream) every launch and copy of the query goes there.
 struct CtxLease {
     Graph& g;
     std::unique_ptr<QueryCtx> c;
-    explicit CtxLease(Graph& gg) : g(gg), c(ctx_acquire(gg)) {}
+    CtxLease(Graph& gg, const ppr_options& opt) : g(gg), c(ctx_acquire(gg)) {
+        if (opt.use_stream) c->stream = static_cast<hipStream_t>(opt.stream);
+    }
     ~CtxLease() {
         if (c) {
             (void)hipStreamSynchronize(c->stream);
+            c->stream = c->own;
             ctx_release(g, std::move(c));
         }
     }
@@ -67,7 +83,9 @@ struct CtxLease {
 
 constexpr int kChunkPairs = 8;   // a captured chunk is 16 FOLD sweeps
 
-// Capture [FOLD y1 -> y0, FOLD y0 -> y1] x kChunkPairs on the context's stream.
+// Capture [FOLD y1 -> y0, FOLD y0 -> y1] x kChunkPairs on the context's own
+// stream (the work stream may be the caller's null stream, which cannot be
+// captured); the work stream launches the instantiated graph.
 void ensure_chunk(Graph& g, QueryCtx& c, const Schedule& sch, double alpha) {
     if (c.chunk_exec && c.chunk_alpha == alpha) return;
     if (c.chunk_exec) {
@@ -75,20 +93,20 @@ void ensure_chunk(Graph& g, QueryCtx& c, const Schedule& sch, double alpha) {
         c.chunk_exec = nullptr;
     }
     hipGraph_t graph = nullptr;
-    HIPCHECK(hipStreamBeginCapture(c.stream, hipStreamCaptureModeThreadLocal));
+    HIPCHECK(hipStreamBeginCapture(c.own, hipStreamCaptureModeThreadLocal));
     try {
         for (int p = 0; p < kChunkPairs; ++p) {
             k::sweep_f64(g, sch, k::SW_FOLD, alpha, c.y1.as<double>(), c.y0.as<double>(), c.pi.as<double>(),
-                         nullptr, nullptr, c.partials.as<double>(), c.stream);
+                         nullptr, nullptr, c.partials.as<double>(), c.own);
             k::sweep_f64(g, sch, k::SW_FOLD, alpha, c.y0.as<double>(), c.y1.as<double>(), c.pi.as<double>(),
-                         nullptr, nullptr, c.partials.as<double>(), c.stream);
+                         nullptr, nullptr, c.partials.as<double>(), c.own);
         }
     } catch (...) {
-        (void)hipStreamEndCapture(c.stream, &graph);
+        (void)hipStreamEndCapture(c.own, &graph);
         if (graph) (void)hipGraphDestroy(graph);
         throw;
     }
-    HIPCHECK(hipStreamEndCapture(c.stream, &graph));
+    HIPCHECK(hipStreamEndCapture(c.own, &graph));
     hipError_t e = hipGraphInstantiate(&c.chunk_exec, graph, nullptr, nullptr, 0);
     (void)hipGraphDestroy(graph);
     HIPCHECK(e);
@@ -107,7 +125,7 @@ void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_
                     double* pi_out, double* r_out, ppr_stats* st, TraceSink* trace) {
     auto t0 = std::chrono::steady_clock::now();
     HIPCHECK(hipSetDevice(g.device));
-    CtxLease lease(g);
+    CtxLease lease(g, opt);
     QueryCtx& c = *lease.c;
     hipStream_t ss = c.stream;
     const Schedule& sch = g.schedule(k::sweep_nnz_cap(), k::sweep_row_cap());
@@ -340,6 +358,9 @@ void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_
         st->residue_format = PPR_RESIDUE_F32;
         st->push_scans = push_scans;
         st->sweep_tile_bytes = 0;
+        st->refresh_ms = 0.0;
+        st->refresh_launches = 0;
+        st->reserved = 0;
         st->local_levels = levels;
         st->sweeps = sweeps;
         st->refreshes = 0;

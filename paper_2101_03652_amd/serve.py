@@ -79,6 +79,7 @@ class Request:
     source: int
     lam: float
     t_arrival: float
+    alpha: float = 0.0          # the query's stop probability (0: the server's alpha)
     future: Future = field(default_factory=Future)
 
 
@@ -140,9 +141,13 @@ class Server:
             t.start()
 
     # -------------------------------------------------------- admission
-    def submit(self, graph: int, source: int, lam: float, t_arrival: float | None = None) -> Future:
+    def submit(self, graph: int, source: int, lam: float, t_arrival: float | None = None,
+               alpha: float | None = None) -> Future:
+        """Queue a query (alpha None: the server's alpha; each slot of a block
+        has its own alpha and lambda)."""
         req = Request(self._rid, int(graph), int(source), float(lam),
-                      time.perf_counter() if t_arrival is None else t_arrival)
+                      time.perf_counter() if t_arrival is None else t_arrival,
+                      0.0 if alpha is None else float(alpha))
         g = self.graphs[req.graph]
         small = self.P.Block.footprint(g, 4)
         with self._cv:
@@ -241,7 +246,7 @@ class Server:
             while self.queues[i] and len(self.slot_req[i]) + len(take) < blk.slots:
                 take.append(self.queues[i].popleft())
         for req in take:
-            slot = blk.admit(req.source, req.lam)
+            slot = blk.admit(req.source, req.lam, alpha=req.alpha or None)
             with self._cv:
                 self.slot_req[i][slot] = req
         if self.slot_req[i]:

@@ -78,7 +78,7 @@ def test_serving_and_debug_entry_points_reject_bad_arguments():
     b = ctypes.c_size_t()
     assert lib.ppr_block_footprint(None, 8, ctypes.byref(b)) == -1
     slot = ctypes.c_int32()
-    assert lib.ppr_slot_admit(None, 0, 1e-8, ctypes.byref(slot)) == -1
+    assert lib.ppr_slot_admit(None, 0, 0.2, 1e-8, ctypes.byref(slot)) == -1
     assert lib.ppr_block_step(None, 4) == -1
     assert lib.ppr_block_poll(None, 0, None, None, None, None) == -1
     assert lib.ppr_slot_retire(None, 0, None, None) == -1
@@ -109,3 +109,38 @@ def test_large_generated_graph_passes_validation_fast():
     assert rc in (0, -6)
     if rc == 0:
         P.load().ppr_graph_destroy(h)
+
+
+def test_footprint_bytes_without_a_graph():
+    """ppr_footprint_bytes is host arithmetic: it answers before any graph or
+    GPU exists.  Graph: CSR (8 (n+1) + 4 m), CSC (4 or 8 bytes per offset, 4 m)
+    and degrees (4 n).  A mixed block of B slots holds per (node, column) the
+    FP64 local-phase scratch (16 bytes), two residue buffers (2 bytes each in
+    bf16 from 32 slots up, else 4), the FP64 reserve and its in-neighbour sums
+    (16) and the FP32 stage accumulator (4), plus the frontier and the
+    long-row partial sums."""
+    n, m = 4_000_000, 70_000_000
+    for B in (4, 8, 16, 32, 64, 128):
+        gb, sb = P.footprint_bytes(n, m, B, P.MIXED)
+        assert gb == 8 * (n + 1) + 4 * m + 4 * (n + 1) + 4 * m + 4 * n
+        per = 16 + 16 + 4 + (2 * 2 if B >= 32 else 2 * 4)
+        assert per * n * B <= sb <= per * n * B * 1.15 + (64 << 20), (B, sb)
+    # int64 CSC offsets from 2^32 - 1 edges on
+    gb, _ = P.footprint_bytes(40_000_000, 2 ** 32 - 1, 16, P.MIXED)
+    assert gb == 8 * (40_000_001) + 4 * (2 ** 32 - 1) + 8 * 40_000_001 + 4 * (2 ** 32 - 1) + 4 * 40_000_000
+    gb1, s1 = P.footprint_bytes(n, m, 1, P.FP64)
+    _, s2 = P.footprint_bytes(n, m, 2, P.FP64)
+    assert s2 == 2 * s1 and 72 * n <= s1 <= 100 * n
+    for args in ((0, 10, 4, P.MIXED), (10, 9, 4, P.MIXED), (10, 101, 4, P.MIXED), (10, 20, 6, P.MIXED),
+                 (10, 20, 256, P.MIXED), (10, 20, 0, P.FP64), (10, 20, 4, 7)):
+        with pytest.raises(P.PPRError):
+            P.footprint_bytes(*args)
+
+
+def test_options_stream_fields():
+    o = P.options()
+    assert o.use_stream == 0 and not o.stream
+    o = P.options(stream=0)                # torch's default stream: the null stream
+    assert o.use_stream == 1 and not o.stream
+    o = P.options(stream=0x1234)
+    assert o.use_stream == 1 and o.stream == 0x1234

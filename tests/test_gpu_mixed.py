@@ -3,7 +3,7 @@
 Contract (per column): ||pi_hat - pi_s||_1 <= lambda + 1e-9 against the
 converged FP64 power iteration, where the slack 1e-9 is measurement slack for
 the FP32 residues; the path itself stops only when its FP64 certificate
-||rt||_1 (computed from the compensated reserves) is <= lambda, and the
+||rt||_1 (computed in FP64 from the FP64 reserves) is <= lambda, and the
 certificate is re-checked here by the oracle on the exported vector.
 Column independence: a source answered alone (batch width 4) and inside a
 batch agree to <= 1e-9 in l1 (the block width changes the FP32 summation

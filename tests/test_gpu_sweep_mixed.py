@@ -2,13 +2,28 @@
 element: one block Gauss-Seidel sweep (Eq. 7 for one chunk) on FP32 inputs,
 computed by the library in FP32 and by the oracle in FP64 from the same
 FP32 values, every column (fresh and continuing ones mixed), widths 4..128,
-1..8 row chunks, long rows cut into pieces (the hub graph).
+1..8 row chunks, long rows cut into pieces (the hub graph), every row tile.
 
-Tolerance: all inputs are >= 0, so a row sum of k terms in FP32 is within
-(k - 1) u of the exact value relative to itself (u = 2^-24); a row also
-inherits the relative error of the values earlier chunks produced in the
-same sweep, themselves sums of at most max_in terms, and the FP32 scale adds
-one rounding.  Per element: (d_in(u) + max_in + 3) u relative.
+Three checks, from exact to semantic:
+- exact: with dyadic inputs (small integers times 2^-20, bf16-representable)
+  every FP32 row sum is exact in any order, so one Eq. 7 sweep must equal,
+  bit for bit, the FP32 product of the FP32 scale (1 - alpha) / d_u and the
+  exact sum (then rounded to bf16 in bf16 storage).  A dropped or doubled
+  in-edge anywhere (a round seam, a piece seam, a tile) changes the sum by at
+  least one unit and fails.  A seam graph puts rows at in-degrees on both
+  sides of every round and piece boundary of every tile and width.
+- own inputs: each row against the oracle's Eq. 7 sweep of exactly the values
+  that row pulls (the library's stored outputs of earlier chunks, plus the
+  fresh residue rounded as stored, and y_in for the rest).  Only the row's
+  own FP32 summation and the final product differ: at most (h + 3) u times
+  the sum of the terms' magnitudes, h the depth of the row's summation in the
+  sweep block (a lane's chain of ceil(min(d, piece) / T2) + rounds terms, a
+  log2 T2 shuffle tree, the pieces added in order; h <= d + 6 for a row that
+  fits one round); in bf16 the stored value must be the rounding of a value
+  in that interval.
+- semantics: against the oracle's block Gauss-Seidel sweep run from y_in
+  alone, where rows also inherit the rounding of earlier chunks' outputs:
+  (d_in(u) + max_in + 3) u relative (non-negative inputs).
 """
 import numpy as np
 import pytest
@@ -24,9 +39,112 @@ ALPHA = 0.2
 U = 2.0 ** -24
 
 
+TILES = (12288, 16384, 24576)
+
+
+def _vectors(B, bf16):
+    """16-byte vectors per row: 4 FP32 or 8 bf16 columns."""
+    return B // (8 if bf16 else 4)
+
+
+def _seam_degrees():
+    """In-degrees on both sides of every round (kNnz in-edges) and piece
+    (8 rounds) boundary of every tile and vector count, and past several
+    pieces."""
+    ds = set()
+    for C in (1, 2, 4, 8, 16, 32):
+        for L in TILES:
+            k = L // (16 * C)
+            pc = 8 * k
+            ds.update({k - 1, k, k + 1, pc - 1, pc, pc + 1, 2 * pc, 2 * pc + 1, 3 * pc + 5})
+    return sorted(d for d in ds if d >= 1)
+
+
+def _seam_graph():
+    """Rows 0.. get the in-degrees of _seam_degrees (distinct random
+    sources); every node also gets one out-edge into the filler rows."""
+    rng = np.random.default_rng(11)
+    degs = _seam_degrees()
+    n = max(degs) + 64
+    edges = set()
+    for u, d in enumerate(degs):
+        for v in rng.choice(np.setdiff1d(np.arange(n), [u]), size=d, replace=False):
+            edges.add((int(v), u))
+    fill = np.arange(len(degs), n)
+    for v in range(n):
+        w = int(fill[rng.integers(0, len(fill))])
+        if w != v:
+            edges.add((v, w))
+        else:
+            edges.add((v, int(fill[0]) if w != fill[0] else int(fill[1])))
+    return synth.from_edges(n, sorted(edges), "seam")
+
+
 def _graphs():
     from test_gpu_fp64 import _hub_graph
-    return {"c1": synth.chunglu(10_000, 100_000, 2.1), "hub": _hub_graph()}
+    return {"c1": synth.chunglu(10_000, 100_000, 2.1), "hub": _hub_graph(), "seam": _seam_graph()}
+
+
+def _depth(din, B, bf16, tile):
+    """Bound on the additions a term of row u undergoes in the sweep block
+    (see the module docstring)."""
+    C = _vectors(B, bf16)
+    knnz = tile // (16 * C)
+    pc = 8 * knnz
+    t2 = min(64, 256 // C)
+    lg = int(np.log2(t2))
+    din = din.astype(np.float64)
+    long_chain = np.ceil(np.minimum(din, pc) / t2) + 8 + lg
+    pieces = np.where(din > pc, np.ceil(din / pc), 0.0)
+    return np.where(din <= knnz, din + 6, long_chain + pieces)
+
+
+def _own_input_ref(g, csc_arrays, lo, yin, got, fresh, bf16):
+    """Per row u of chunk j, the oracle's Eq. 7 sweep of the values the row
+    pulls: got(v) for v in earlier chunks (plus yin(v), added in FP32 and
+    stored as the block stores, for a fresh column), yin(v) otherwise.
+    Returns (value, the same sweep of the terms' magnitudes)."""
+    n = g.n
+    ids = np.arange(n)
+    early_val = got
+    if fresh:
+        early_val = np.float32(got) + np.float32(yin)
+        if bf16:
+            early_val = _bf16(early_val)
+    want = np.zeros(n)
+    mag = np.zeros(n)
+    one = np.array([0, n], dtype=np.int32)
+    for j in range(len(lo) - 1):
+        a, b = int(lo[j]), int(lo[j + 1])
+        if a == b:
+            continue
+        ymix = np.where(ids < a, early_val, yin).astype(np.float64)
+        want[a:b] = oracle.block_gs_sweep(g, ALPHA, one, ymix, False, csc_arrays=csc_arrays)[a:b]
+        mag[a:b] = oracle.block_gs_sweep(g, ALPHA, one, np.abs(ymix), False, csc_arrays=csc_arrays)[a:b]
+    return want, mag
+
+
+def _assert_own_inputs(g, csc_arrays, lo, yin, got, fresh, B, bf16, tile, omega=None, where=""):
+    """got (one column) against its own-input reference; omega: over-relaxed
+    (the row pushes omega * value + (1 - omega) * yin(u) unless fresh)."""
+    want, mag = _own_input_ref(g, csc_arrays, lo, yin, got, fresh, bf16)
+    din = np.diff(csc_arrays[0])
+    tol = (_depth(din, B, bf16, tile) + 3) * U
+    if omega is not None and omega != 1.0:
+        k = 0.0 if fresh else (1.0 - omega)
+        want = omega * want + k * yin.astype(np.float64)
+        mag = abs(omega) * mag + abs(k) * np.abs(yin.astype(np.float64))
+        tol = tol + 3 * U
+    if not bf16:
+        err = np.abs(got.astype(np.float64) - want)
+        bad = err > tol * mag + 1e-38
+        assert not bad.any(), (where, int(np.argmax(err - tol * mag)), int(bad.sum()))
+    else:
+        lo_b = _bf16(np.float32(want - tol * mag)).astype(np.float64)
+        hi_b = _bf16(np.float32(want + tol * mag)).astype(np.float64)
+        g64 = got.astype(np.float64)
+        bad = (g64 < lo_b) | (g64 > hi_b)
+        assert not bad.any(), (where, int(np.argmax(bad)), int(bad.sum()))
 
 
 @pytest.fixture(scope="module")
@@ -34,7 +152,7 @@ def graphs():
     return _graphs()
 
 
-@pytest.mark.parametrize("name", ["c1", "hub", "hub-wide"])
+@pytest.mark.parametrize("name", ["c1", "hub", "hub-wide", "seam"])
 @pytest.mark.parametrize("width,chunks", [(4, 1), (4, 5), (32, 1), (32, 3), (32, 8), (128, 1), (128, 4)])
 def test_sweep_matches_oracle(graphs, name, width, chunks):
     """hub-wide: the hub graph with int64 device CSC offsets."""
@@ -58,10 +176,63 @@ def test_sweep_matches_oracle(graphs, name, width, chunks):
                                      csc_arrays=csc_arrays)
         err = np.abs(got[:, b] - want)
         assert np.all(err <= tol_rel * want + 1e-38), (b, int(np.argmax(err - tol_rel * want)))
-        # stage accumulator: the new residue, plus the fresh residue's alpha-part
-        t_want = want + (y[:, b] if fresh[b] else 0.0)
-        assert np.all(np.abs(t_out[:, b] - t_want) <= tol_rel * t_want + 2 * U * t_want + 1e-38), b
+        _assert_own_inputs(g, csc_arrays, lo, y[:, b], got[:, b], bool(fresh[b]), width, False, 16384, where=b)
+        # stage accumulator: the stored new residue, plus the fresh residue (FP32 add)
+        t_want = (y[:, b] if fresh[b] else np.zeros(g.n, np.float32)) + got[:, b]
+        np.testing.assert_array_equal(t_out[:, b], t_want.astype(np.float32))
     G.close()
+
+
+@pytest.fixture(scope="module")
+def devgraphs(graphs):
+    gs = {k: P.Graph.from_synth(v) for k, v in graphs.items()}
+    yield gs
+    for G in gs.values():
+        G.close()
+
+
+@pytest.mark.parametrize("tile", TILES)
+@pytest.mark.parametrize("name", ["c1", "hub", "seam"])
+@pytest.mark.parametrize("width,fmt", [(4, "f32"), (8, "f32"), (32, "f32"), (128, "f32"),
+                                       (8, "bf16"), (32, "bf16"), (128, "bf16")])
+def test_dyadic_sweep_bit_exact(graphs, devgraphs, tile, name, width, fmt):
+    """One Eq. 7 sweep (one chunk) on dyadic residues k 2^-20, k in [1, 255]
+    (bf16-representable; every row sum below 2^24 units, so exact in FP32 in
+    any order): the stored output is exactly fl32(fl32((1 - alpha) / d_u) *
+    sum), rounded to bf16 in bf16 storage, and the stage accumulator exactly
+    the stored value plus the fresh residue.  One dropped or doubled in-edge
+    changes a row sum by at least one unit (a relative change of at least
+    2^-22 here, or 1/255 of a bf16-scale term for the sparse columns) and
+    fails."""
+    g = graphs[name]
+    G = devgraphs[name]
+    bf16 = fmt == "bf16"
+    print(f"[gpu] dyadic sweep {name} width={width} tile={tile} {fmt}", flush=True)
+    rng = np.random.default_rng(tile + 3 * width + (1 if bf16 else 0))
+    k = rng.integers(1, 256, size=(g.n, width)).astype(np.float64)
+    # sparse columns: a dropped term moves a bf16 output too
+    for b in range(1, width, 2):
+        keep = rng.random(g.n) < 0.01
+        k[~keep, b] = 0.0
+        k[keep, b] = rng.integers(128, 256, size=int(keep.sum()))
+    y = (k * 2.0 ** -20).astype(np.float32)
+    fresh = (rng.random(width) < 0.5).astype(np.int32)
+    t_out = np.empty_like(y)
+    got = P.debug_sweeps_mixed(G, ALPHA, y, fresh, 1, chunks=1, t_out=t_out, sweep_tile=tile,
+                               residue_format=P.RESIDUE_BF16 if bf16 else P.RESIDUE_F32)
+    col_ptr, row_idx, deg = oracle.csc(g)
+    assert np.diff(col_ptr).max() * 255 < 2 ** 24
+    # exact row sums (float64 holds them exactly), per column
+    rows = np.repeat(np.arange(g.n), np.diff(col_ptr))
+    S = np.zeros((g.n, width))
+    np.add.at(S, rows, y[row_idx].astype(np.float64))
+    sc = np.float32((1.0 - ALPHA) / deg.astype(np.float64)).astype(np.float64)
+    want = np.float32(sc[:, None] * S)          # one rounding of an exact product
+    if bf16:
+        want = _bf16(want)
+    np.testing.assert_array_equal(got, want)
+    t_want = np.where(fresh[None, :] != 0, y, np.float32(0.0)) + want
+    np.testing.assert_array_equal(t_out, t_want.astype(np.float32))
 
 
 def test_sweep_device_buffers_and_errors(graphs):
@@ -108,6 +279,8 @@ def test_over_relaxed_sweep_matches_oracle(graphs, name, width, chunks):
         want_y, want_q = oracle.block_sor_sweep(g, ALPHA, lo, yb, bool(fresh[b]), w, qb, csc_arrays=csc_arrays)
         mag_y, _ = oracle.block_sor_sweep(g, ALPHA, lo, yb, bool(fresh[b]), w, np.abs(qb), csc_arrays=csc_arrays)
         assert np.all(np.abs(got[:, b] - want_y) <= tol_rel * mag_y + 1e-38), b
+        _assert_own_inputs(g, csc_arrays, lo, y[:, b], got[:, b], bool(fresh[b]), width, False, 16384, omega=w,
+                           where=b)
         # what the row keeps is (1 - omega) / omega times what it pushes: the
         # next sweep's q, read back from y_out
         np.testing.assert_allclose(want_q, (1.0 - w) / w * want_y, rtol=1e-13, atol=1e-300)
@@ -124,7 +297,7 @@ def _bf16(x):
 UB = 2.0 ** -8     # bf16 unit roundoff (8-bit significand)
 
 
-@pytest.mark.parametrize("name", ["c1", "hub"])
+@pytest.mark.parametrize("name", ["c1", "hub", "seam"])
 @pytest.mark.parametrize("width,chunks,sor", [(8, 1, False), (8, 5, True), (32, 3, False), (128, 1, False),
                                               (128, 8, False), (32, 4, True), (128, 8, True)])
 def test_bf16_sweep_matches_oracle(graphs, name, width, chunks, sor):
@@ -172,6 +345,8 @@ def test_bf16_sweep_matches_oracle(graphs, name, width, chunks, sor):
             mag = want
         err = np.abs(got[:, b] - want)
         assert np.all(err <= rel * mag + 1e-38), (b, int(np.argmax(err - rel * mag)))
+        _assert_own_inputs(g, csc_arrays, lo, yb[:, b], got[:, b], bool(fresh[b]), width, True, 16384,
+                           omega=float(om[b]) if sor else None, where=b)
         # T = (fresh input residue) + the stored value, in FP32
         t_want = (yb[:, b] if fresh[b] else np.zeros(g.n, np.float32)) + got[:, b]
         np.testing.assert_array_equal(t_out[:, b], t_want.astype(np.float32))
@@ -260,6 +435,18 @@ def test_sweep_sequence_stage_accumulator(graphs, name, width, chunks, sweeps, s
         elif k == sweeps - 1:
             t = t + ys[k + 1]
     np.testing.assert_array_equal(t_out, t)
+    # every step of the sequence against the oracle on the values it pulled
+    csc_arrays = oracle.csc(g)
+    lo = oracle.chunk_bounds(g, chunks)
+    for k in range(sweeps):
+        for b in range(width):
+            if budget[b] <= k:
+                assert not ys[k + 1][:, b].any()
+                continue
+            w = float(om[b]) if sor else None
+            fr = bool(entry[b]) and k == 0
+            _assert_own_inputs(g, csc_arrays, lo, ys[k][:, b], ys[k + 1][:, b], fr, width, fmt == P.RESIDUE_BF16,
+                               16384, omega=w, where=(k, b))
     if fmt == P.RESIDUE_F32:
         csc_arrays = oracle.csc(g)
         din = np.diff(csc_arrays[0]).astype(np.float64)
@@ -300,7 +487,7 @@ def test_sweep_sequence_arguments(graphs):
 
 
 @pytest.mark.parametrize("tile", [12288, 24576])
-@pytest.mark.parametrize("name", ["c1", "hub"])
+@pytest.mark.parametrize("name", ["c1", "hub", "seam"])
 @pytest.mark.parametrize("width,chunks,fmt", [(32, 3, "f32"), (128, 4, "f32"), (32, 8, "bf16"), (128, 8, "bf16")])
 def test_sweep_tiles_match_oracle(graphs, tile, name, width, chunks, fmt):
     """The row tiles the autotuner may pick (LDS stages of 12 and 24 KB; the
@@ -334,11 +521,9 @@ def test_sweep_tiles_match_oracle(graphs, tile, name, width, chunks, fmt):
             rel = (din + din.max() + 3) * U
         err = np.abs(got[:, b] - want)
         assert np.all(err <= rel * want + 1e-38), (b, int(np.argmax(err - rel * want)))
+        _assert_own_inputs(g, csc_arrays, lo, yin[:, b], got[:, b], bool(fresh[b]), width, bf16, tile, where=b)
         t_want = (yin[:, b] if fresh[b] else np.zeros(g.n, np.float32)) + got[:, b]
-        if bf16:
-            np.testing.assert_array_equal(t_out[:, b], t_want.astype(np.float32))
-        else:
-            assert np.all(np.abs(t_out[:, b] - t_want) <= 2 * U * t_want + 1e-38), b
+        np.testing.assert_array_equal(t_out[:, b], t_want.astype(np.float32))
     G.close()
 
 
