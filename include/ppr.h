@@ -442,21 +442,28 @@ ppr_status ppr_debug_sweeps_mixed(ppr_graph* g, double alpha, int32_t B, int32_t
                                   int32_t residue_format, int32_t sweep_tile);
 
 /*
- * Autotuner of the batched path: for each candidate block width (a power of
- * two in [4, 128]; widths NULL = {8, 16, 32, 64, 128}) whose state fits half
- * of the free device memory, and for each row tile of the sweep (an LDS
- * stage of 12, 16 or 24 KB per block, which sets the in-edges and rows a
- * block takes), time a few global sweeps on this graph with HIP events.
- * Each width keeps its fastest tile (16 KB unless another is more than 1%
- * faster), and the width with the lowest time per column-sweep wins.  Both
- * choices are kept in the graph: the tiles for every later batched block of
- * that width (queries and serving blocks), the width for ppr_options.batch_cols = 0.
+ * Autotuner of the batched path.  For each candidate block width (a power of
+ * two in [4, 128]; widths NULL = {8, 16, 32, 64, 128}) and each residue
+ * storage (FP32; bf16 from 8 columns) whose state fits half of the free
+ * device memory: first the row tile of the sweep (an LDS stage of 12, 16 or
+ * 24 KB per block, which sets the in-edges and rows a block takes) by timing
+ * a few global sweeps with HIP events (16 KB unless another is more than 1%
+ * faster); then, at that tile, one batch of `width` queries (sources spread
+ * over the ids, this alpha and lambda) answered end to end after a warm-up
+ * batch: local phase, sweeps, refreshes.  Each width keeps the storage with
+ * the lower time per query, and the width with the lowest time per query
+ * wins (a narrower width within 1%: less memory, lower latency).  The
+ * choices are kept in the graph: the tile per (width, storage) for every
+ * later batched block (queries and serving blocks), the storage per width
+ * for queries with residue_format PPR_RESIDUE_AUTO, and the width for
+ * ppr_options.batch_cols = 0.  Must not run while other calls use the graph.
+ *   alpha in (0, 1), lambda in (0, 1]: the workload the batch times.
  *   widths: host int32[count] or NULL.  best_width: out.  cost_us: out,
- *   host double[count] (or [5] when widths is NULL), microseconds per
- *   column-sweep at the width's chosen tile, -1 for a width skipped for
+ *   host double[count] (or [5] when widths is NULL), microseconds per query
+ *   at the width's chosen storage and tile, -1 for a width skipped for
  *   memory; nullable.
  */
-ppr_status ppr_autotune(ppr_graph* g, double alpha, const int32_t* widths, int32_t count,
+ppr_status ppr_autotune(ppr_graph* g, double alpha, double lambda, const int32_t* widths, int32_t count,
                         int32_t* best_width, double* cost_us);
 
 /*

@@ -139,7 +139,7 @@ def load() -> ctypes.CDLL:
         "ppr_debug_refine": (st, [vp, f64, f64, vp, vp, vp, vp]),
         "ppr_debug_walks": (st, [vp, f64, f64, ctypes.c_uint64, i32, vp, vp, vp]),
         "ppr_debug_sweep_fp64": (st, [vp, f64, vp, vp, vp, vp]),
-        "ppr_autotune": (st, [vp, f64, vp, i32, vp, vp]),
+        "ppr_autotune": (st, [vp, f64, f64, vp, i32, vp, vp]),
         "ppr_debug_sweep_mixed": (st, [vp, f64, i32, i32, vp, vp, vp, vp, vp, i32]),
         "ppr_debug_sweeps_mixed": (st, [vp, f64, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, i32, i32]),
         "ppr_block_create": (st, [vp, i32, f64, vp, ctypes.POINTER(vp)]),
@@ -355,18 +355,20 @@ class Graph:
                                       1 if use_index else 0, _ptr(r), _ptr(pi), ctypes.byref(nw)))
         return nw.value
 
-    def autotune(self, alpha: float = 0.2, widths=None) -> dict:
-        """Pick the batched block width, and the sweep row tile for each width,
-        by timing sweeps on this graph; the choices become the defaults of
-        later batched queries and serving blocks."""
+    def autotune(self, alpha: float = 0.2, lam: float = 1e-8, widths=None) -> dict:
+        """Pick the batched block width, the residue storage per width and
+        the sweep row tile per (width, storage) by timing sweeps and one batch
+        of queries end to end per candidate on this graph; the choices become
+        the defaults of later batched queries (and the tiles of serving
+        blocks)."""
         w = None if widths is None else np.ascontiguousarray(widths, dtype=np.int32)
         cnt = 5 if w is None else len(w)
         cost = np.zeros(cnt, dtype=np.float64)
         best = ctypes.c_int32()
-        _check(load().ppr_autotune(self._h, float(alpha), _ptr(w) if w is not None else None,
+        _check(load().ppr_autotune(self._h, float(alpha), float(lam), _ptr(w) if w is not None else None,
                                    cnt, ctypes.byref(best), _ptr(cost)))
         ws = [8, 16, 32, 64, 128] if w is None else w.tolist()
-        return {"best": best.value, "us_per_column_sweep": dict(zip(ws, cost.round(3).tolist()))}
+        return {"best": best.value, "us_per_query": dict(zip(ws, cost.round(3).tolist()))}
 
     def debug_sweep(self, alpha: float, r_in, r_out, pi) -> float:
         """One Eq. 7 sweep on device tensors: r_out = (1-alpha) r_in P, pi += alpha r_in."""

@@ -197,14 +197,15 @@ ppr_status ppr_query_batch(ppr_graph* g, const int32_t* sources, int32_t B, doub
     return ppr_query_ex(g, sources, B, alpha, lambda, &o, pi_out, nullptr, stats);
 }
 
-ppr_status ppr_autotune(ppr_graph* gh, double alpha, const int32_t* widths, int32_t count,
+ppr_status ppr_autotune(ppr_graph* gh, double alpha, double lambda, const int32_t* widths, int32_t count,
                         int32_t* best_width, double* cost_us) {
     return guarded([&] {
         Graph* g = reinterpret_cast<Graph*>(gh);
         if (!g) fail(PPR_ERR_ARG, "graph is NULL");
         if (!(alpha > 0.0 && alpha < 1.0)) fail(PPR_ERR_ARG, "alpha must lie in (0, 1)");
+        if (!(lambda > 0.0 && lambda <= 1.0)) fail(PPR_ERR_ARG, "lambda must lie in (0, 1]");
         if (widths && count < 1) fail(PPR_ERR_ARG, "count must be >= 1");
-        autotune_width(*g, alpha, widths, count, best_width, cost_us);
+        autotune_width(*g, alpha, lambda, widths, count, best_width, cost_us);
     });
 }
 

@@ -265,6 +265,10 @@ struct Block {
         }
         mk::prepare(*c, g);
         c->sor = false;              // set per launch sequence by step()
+        if (c->af) {                 // a pooled context may carry another block's choice
+            c->drop_chunks();
+            c->af = false;
+        }
         slots.resize(Bw);
         HIPCHECK(hipEventCreateWithFlags(&ev_ready, hipEventDisableTiming));
         if (c->alpha != alpha) {
@@ -600,6 +604,14 @@ struct Block {
                 }
             if (any_sor) HIPCHECK(hipMemcpyAsync(c->omega.p, hom.data(), 4 * (size_t)Bw, hipMemcpyHostToDevice, ss));
             c->sor = any_sor;
+            // per-column alpha factors only while a running slot has another alpha
+            // than the block's (the captured chunks hold the choice)
+            bool any_af = false;
+            for (const Slot& sl : slots) any_af |= (sl.state == RUNNING && sl.alpha != alpha);
+            if (any_af != c->af) {
+                c->drop_chunks();
+                c->af = any_af;
+            }
             set_steps(K - 1);
             ev_sweep.start(ss);
             int rest = K;
@@ -773,11 +785,15 @@ void run_mixed_batch(Graph& g, const int32_t* sources, int32_t B, double alpha, 
     int Bw = opt.batch_cols > 0 ? opt.batch_cols : (tw > 0 ? tw : default_batch_width(B));
     if (opt.batch_cols == 0 && opt.residue_format == PPR_RESIDUE_BF16) Bw = std::max(Bw, 8);   // 8-column vectors
     if (Bw < 4 || Bw > 128 || (Bw & (Bw - 1))) fail(PPR_ERR_ARG, "batch_cols must be a power of two in [4, 128]");
+    // the autotuner's residue format for this width, unless the caller chose one
+    ppr_options o = opt;
+    const int tf = g.tuned_fmt[ilog2(Bw) & 7].load();
+    if (o.residue_format == PPR_RESIDUE_AUTO && tf > 0) o.residue_format = tf - 1;
     ppr_status first = PPR_OK;
     std::string msg;
     for (int32_t b0 = 0; b0 < B; b0 += Bw) {
         int Breal = std::min<int32_t>(Bw, B - b0);
-        Block blk(g, Bw, alpha, opt);
+        Block blk(g, Bw, alpha, o);
         try {
             run_mixed_chunk(blk, sources + b0, Breal, lambda, pi_out + (size_t)b0 * g.n,
                             r_out ? r_out + (size_t)b0 * g.n : nullptr, st ? st + b0 : nullptr);
@@ -795,7 +811,81 @@ void run_mixed_batch(Graph& g, const int32_t* sources, int32_t B, double alpha, 
 
 // ======================================================================== autotuner
 
-void autotune_width(Graph& g, double alpha, const int32_t* widths, int32_t count, int32_t* best,
+namespace {
+
+// Sources of a tuning batch of W queries: ids spread by a multiplicative hash.
+std::vector<int32_t> tuning_sources(int32_t n, int W) {
+    std::vector<int32_t> s(W);
+    for (int k = 0; k < W; ++k) s[k] = (int32_t)(((uint64_t)(k + 1) * 2654435761ull + 12345ull) % (uint64_t)n);
+    return s;
+}
+
+// The sweep tile of this block's width and residue format: time a few
+// sweeps at each candidate LDS stage; the default stage stays unless another
+// is more than 1% faster.  Leaves the block at that tile, its state cleared.
+int tune_tile(Graph& g, Block& blk) {
+    MixedCtx& c = *blk.c;
+    hipStream_t ss = c.stream;
+    const int W = blk.Bw;
+    // every column active for the timing; the cost of a sweep does not
+    // depend on the values it moves
+    std::vector<int32_t> kb(W, 1 << 30), zero(W, 0);
+    blk.upload_i32(c.kb, kb);
+    blk.upload_i32(c.entry, zero);
+    blk.set_steps(1 << 30);              // odd and even steps alternate, as in a query
+    const int reps = 4;
+    double tile_us[mk::kTileCount];
+    for (int ti = 0; ti < mk::kTileCount; ++ti) {
+        c.drop_chunks();
+        c.tile = mk::kTiles[ti];
+        mk::prepare(c, g);                   // the tile's schedule and piece buffer
+        mk::sweep(c, g, c.Y0.p, c.Y1.p);     // warm-up
+        EventPair ev;
+        ev.start(ss);
+        for (int r = 0; r < reps; ++r) mk::sweep(c, g, (r & 1) ? c.Y1.p : c.Y0.p, (r & 1) ? c.Y0.p : c.Y1.p);
+        ev.stop(ss);
+        HIPCHECK(hipStreamSynchronize(ss));
+        tile_us[ti] = ev.elapsed_ms() * 1e3 / reps;
+    }
+    int tile = mk::kLdsBytes;
+    double us = 0.0;
+    for (int ti = 0; ti < mk::kTileCount; ++ti)
+        if (mk::kTiles[ti] == mk::kLdsBytes) us = tile_us[ti];
+    const double us_default = us;
+    for (int ti = 0; ti < mk::kTileCount; ++ti)
+        if (tile_us[ti] < us_default * 0.99 && tile_us[ti] < us) {
+            us = tile_us[ti];
+            tile = mk::kTiles[ti];
+        }
+    c.drop_chunks();
+    c.tile = tile;
+    mk::prepare(c, g);
+    blk.upload_i32(c.kb, zero);
+    for (DevBuf* b : {&c.Y0, &c.Y1, &c.T}) HIPCHECK(hipMemsetAsync(b->p, 0, b->bytes, ss));
+    HIPCHECK(hipStreamSynchronize(ss));
+    c.ycur = c.Y0.p;
+    return tile;
+}
+
+// Wall time (ms) of one batch of queries answered by the block, from
+// admission to the last certificate (no export).
+double time_batch(Block& blk, const std::vector<int32_t>& src, double lambda) {
+    HIPCHECK(hipStreamSynchronize(blk.c->stream));
+    const double t0 = now_ms();
+    for (size_t b = 0; b < src.size(); ++b)
+        if (blk.admit(src[b], blk.alpha, lambda) != (int)b) fail(PPR_ERR_ARG, "internal: tuning slot order");
+    while (!blk.settled()) {
+        blk.step(1 << 30);
+        blk.collect(true);
+    }
+    const double ms = now_ms() - t0;
+    for (auto& sl : blk.slots) sl = Block::Slot();
+    return ms;
+}
+
+}  // namespace
+
+void autotune_width(Graph& g, double alpha, double lambda, const int32_t* widths, int32_t count, int32_t* best,
                     double* cost_us) {
     HIPCHECK(hipSetDevice(g.device));
     static const int32_t kDefault[5] = {8, 16, 32, 64, 128};
@@ -804,8 +894,6 @@ void autotune_width(Graph& g, double alpha, const int32_t* widths, int32_t count
         count = 5;
     }
     if (count < 1) fail(PPR_ERR_ARG, "no candidate widths");
-    ppr_options opt;
-    ppr_options_default(&opt);
     size_t free_b = 0, total_b = 0;
     HIPCHECK(hipMemGetInfo(&free_b, &total_b));
     double best_cost = 1e300;
@@ -813,64 +901,44 @@ void autotune_width(Graph& g, double alpha, const int32_t* widths, int32_t count
     for (int32_t i = 0; i < count; ++i) {
         int W = widths[i];
         if (W < 4 || W > 128 || (W & (W - 1))) fail(PPR_ERR_ARG, "candidate widths must be powers of two in [4, 128]");
-        int64_t fcap = frontier_capacity(g.n, g.m, opt, W);
-        bool pooled = false;
-        {
-            std::lock_guard<std::mutex> lk(g.pool_mu);
-            for (auto& cc : g.mixed_pool)
-                pooled |= (cc->Bw == W && cc->fcap >= fcap && cc->bf16 == residues_bf16(opt, W));
-        }
-        if (!pooled && mixed_footprint(g.n, g.m, W, fcap, residues_bf16(opt, W)) > free_b / 2) {
-            if (cost_us) cost_us[i] = -1.0;
-            continue;
-        }
-        Block blk(g, W, alpha, opt);
-        MixedCtx& c = *blk.c;
-        hipStream_t ss = c.stream;
-        // every column active for the timing; the cost of a sweep does not
-        // depend on the values it moves
-        std::vector<int32_t> kb(W, 1 << 30), zero(W, 0);
-        blk.upload_i32(c.kb, kb);
-        blk.upload_i32(c.entry, zero);
-        blk.set_steps(1 << 30);              // odd and even steps alternate, as in a query
-        // each candidate row tile (LDS stage of a sweep block); the default
-        // stage keeps the width unless another is more than 1% faster
-        const int reps = 4;
-        double tile_us[mk::kTileCount];
-        for (int ti = 0; ti < mk::kTileCount; ++ti) {
-            c.drop_chunks();
-            c.tile = mk::kTiles[ti];
-            mk::prepare(c, g);                   // the tile's schedule and piece buffer
-            mk::sweep(c, g, c.Y0.p, c.Y1.p);     // warm-up
-            EventPair ev;
-            ev.start(ss);
-            for (int r = 0; r < reps; ++r) mk::sweep(c, g, (r & 1) ? c.Y1.p : c.Y0.p, (r & 1) ? c.Y0.p : c.Y1.p);
-            ev.stop(ss);
-            HIPCHECK(hipStreamSynchronize(ss));
-            tile_us[ti] = ev.elapsed_ms() * 1e3 / reps / W;
-        }
-        int tile = mk::kLdsBytes;
-        double us = 0.0;
-        for (int ti = 0; ti < mk::kTileCount; ++ti)
-            if (mk::kTiles[ti] == mk::kLdsBytes) us = tile_us[ti];
-        const double us_default = us;
-        for (int ti = 0; ti < mk::kTileCount; ++ti)
-            if (tile_us[ti] < us_default * 0.99 && tile_us[ti] < us) {
-                us = tile_us[ti];
-                tile = mk::kTiles[ti];
+        if (cost_us) cost_us[i] = -1.0;
+        double w_cost = 1e300;
+        int w_fmt = -1;
+        for (int fmt : {PPR_RESIDUE_F32, PPR_RESIDUE_BF16}) {
+            if (fmt == PPR_RESIDUE_BF16 && W < 8) continue;       // bf16 vectors hold 8 columns
+            ppr_options opt;
+            ppr_options_default(&opt);
+            opt.precision = PPR_MIXED;
+            opt.residue_format = fmt;
+            const bool bf = fmt == PPR_RESIDUE_BF16;
+            const int64_t fcap = frontier_capacity(g.n, g.m, opt, W);
+            bool pooled = false;
+            {
+                std::lock_guard<std::mutex> lk(g.pool_mu);
+                for (auto& cc : g.mixed_pool) pooled |= (cc->Bw == W && cc->fcap >= fcap && cc->bf16 == bf);
             }
-        g.tuned_tile[c.bf16 ? 1 : 0][ilog2(W) & 7].store(tile);
-        c.drop_chunks();
-        c.tile = tile;
-        mk::prepare(c, g);
-        blk.upload_i32(c.kb, zero);
-        for (DevBuf* b : {&c.Y0, &c.Y1, &c.T}) HIPCHECK(hipMemsetAsync(b->p, 0, b->bytes, ss));
-        HIPCHECK(hipStreamSynchronize(ss));
-        c.ycur = c.Y0.p;
-        if (cost_us) cost_us[i] = us;
+            if (!pooled && mixed_footprint(g.n, g.m, W, fcap, bf) > free_b / 2) continue;
+            opt.sweep_tile = mk::kLdsBytes;
+            Block blk(g, W, alpha, opt);
+            const int tile = tune_tile(g, blk);
+            g.tuned_tile[bf ? 1 : 0][ilog2(W) & 7].store(tile);
+            // end to end on a batch of W queries: local phase, sweeps and
+            // refreshes (the refresh count depends on the residue format, the
+            // sweeps per query on the width), after one warm-up batch
+            const std::vector<int32_t> src = tuning_sources(g.n, W);
+            (void)time_batch(blk, src, lambda);
+            const double us = time_batch(blk, src, lambda) * 1e3 / W;
+            if (us < w_cost * 0.99 || (us < w_cost && fmt == PPR_RESIDUE_F32)) {
+                w_cost = us;
+                w_fmt = fmt;
+            }
+        }
+        if (w_fmt < 0) continue;                                    // no format fits the memory
+        g.tuned_fmt[ilog2(W) & 7].store(w_fmt + 1);
+        if (cost_us) cost_us[i] = w_cost;
         // the narrower block wins ties (within 1%): less memory, lower latency
-        if (best_w == 0 || us < best_cost * 0.99) {
-            best_cost = us;
+        if (best_w == 0 || w_cost < best_cost * 0.99) {
+            best_cost = w_cost;
             best_w = W;
         }
     }

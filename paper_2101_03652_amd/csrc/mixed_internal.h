@@ -78,6 +78,7 @@ struct MixedCtx {
     DevBuf afac;                      // float[Bw]      (1 - alpha_b) / (1 - alpha): the column's factor on
                                       //                the scale table (exactly 1 when alpha_b = alpha)
     bool sor = false;                 // the next sweeps run the over-relaxed update
+    bool af = false;                  // the next sweeps apply the per-column alpha factors (afac)
     PinnedBuf host;                   // readback area
     hipGraphExec_t chunk[2] = {nullptr, nullptr};   // captured sweep chunks Y1 -> Y0 -> ... -> Y1
                                                      // (plain, over-relaxed)

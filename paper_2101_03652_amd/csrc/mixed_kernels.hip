@@ -361,7 +361,7 @@ __device__ inline typename ST::V gather_gs(const typename ST::V* __restrict__ Y_
 // residue, so no kept-back part outlives a stage.
 // Lane c holds columns K c .. K c + K - 1: vector c of row u in Y, float4s
 // (u C + c) K/4 + i of T, int4s / float4s c K/4 + i of kb, entry, omega.
-template <int C, bool SOR, typename ST>
+template <int C, bool SOR, typename ST, bool AF>
 __device__ inline void finish_row(int32_t u, int c, Vec<ST::K> acc, int32_t step, int32_t last,
                                   const float* __restrict__ scale, const float* __restrict__ afac,
                                   const typename ST::V* __restrict__ Y_in, typename ST::V* Y_out,
@@ -370,14 +370,12 @@ __device__ inline void finish_row(int32_t u, int c, Vec<ST::K> acc, int32_t step
     constexpr int K = ST::K, Q = K / 4;
     const int64_t at = (int64_t)u * C + c;
     const float sc = scale[u];
-    Vec<K> m, mf, en = v_zero<K>(), keep;
+    Vec<K> m, en = v_zero<K>(), keep;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int4 kb4 = reinterpret_cast<const int4*>(kb)[c * Q + i];
         m.q[i] = make_float4(step < kb4.x ? 1.f : 0.f, step < kb4.y ? 1.f : 0.f, step < kb4.z ? 1.f : 0.f,
                              step < kb4.w ? 1.f : 0.f);
-        // the column's alpha factor on the scale table (1 for the reference alpha)
-        mf.q[i] = f4_mul(m.q[i], reinterpret_cast<const float4*>(afac)[c * Q + i]);
     }
     bool any_en = false;
     if (step == 0) {
@@ -395,7 +393,15 @@ __device__ inline void finish_row(int32_t u, int c, Vec<ST::K> acc, int32_t step
     // even step's output (odd steps), the fresh residue (entry sweep)
     Vec<K> yin = v_zero<K>();
     if (SOR || odd || any_en) yin = ST::value(Y_in[at]);
-    acc = v_mul(acc, mf);
+    acc = v_mul(acc, m);
+    if constexpr (AF) {
+        // the column's alpha factor on the scale table (instantiated only while
+        // some column has another alpha than the block's reference alpha)
+        Vec<K> f;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f.q[i] = reinterpret_cast<const float4*>(afac)[c * Q + i];
+        acc = v_mul(acc, f);
+    }
     Vec<K> y;
 #pragma unroll
     for (int i = 0; i < Q; ++i)
@@ -430,7 +436,7 @@ __device__ inline void finish_row(int32_t u, int c, Vec<ST::K> acc, int32_t step
     }
 }
 
-template <typename OffT, int C, bool SOR, typename ST, int L>
+template <typename OffT, int C, bool SOR, typename ST, int L, bool AF>
 __global__ __launch_bounds__(kBlock) void sweep_k(
         const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
         const RowBlock* __restrict__ blocks, int32_t lo, const float* __restrict__ scale,
@@ -503,11 +509,11 @@ __global__ __launch_bounds__(kBlock) void sweep_k(
         partials[(int64_t)b.piece * C + c] = acc;
         return;
     }
-    finish_row<C, SOR, ST>(r0 + row, c, acc, step, step_p[1], scale, afac, Y_in, Y_out, T, kb, entry, omega);
+    finish_row<C, SOR, ST, AF>(r0 + row, c, acc, step, step_p[1], scale, afac, Y_in, Y_out, T, kb, entry, omega);
 }
 
 // Long rows of one chunk: the pieces' partial sums added in slot order.
-template <int C, bool SOR, typename ST>
+template <int C, bool SOR, typename ST, bool AF>
 __global__ __launch_bounds__(kBlock) void combine_k(
         const LongRow* __restrict__ rows, int32_t count, const Vec<ST::K>* __restrict__ partials,
         const int32_t* __restrict__ step_p, const float* __restrict__ scale, const float* __restrict__ afac,
@@ -519,7 +525,7 @@ __global__ __launch_bounds__(kBlock) void combine_k(
     const LongRow L = rows[i];
     Vec<ST::K> acc = v_zero<ST::K>();
     for (int32_t p = 0; p < L.npieces; ++p) acc = v_add(acc, partials[(int64_t)(L.first + p) * C + c]);
-    finish_row<C, SOR, ST>(L.row, c, acc, step_p[0], step_p[1], scale, afac, Y_in, Y_out, T, kb, entry, omega);
+    finish_row<C, SOR, ST, AF>(L.row, c, acc, step_p[0], step_p[1], scale, afac, Y_in, Y_out, T, kb, entry, omega);
 }
 
 __global__ void bump_step_k(int32_t* step) { step[0] += 1; }
@@ -552,7 +558,15 @@ __global__ void from_bf16_k(int64_t count, const uint16_t* __restrict__ src, flo
 // other blocks still gather T; the column's T is then stale, and its next
 // entry sweep overwrites it (entry flag 2).  rmask 2 marks a column's first
 // refresh after its conversion: its S and AS are taken as 0 (the conversion
-// does not clear them).
+// does not clear them).  The per-column values every row reads (source,
+// rmask, 1 - alpha_b, 1 / (1 - alpha_b)) are copied into LDS once per block;
+// the |rt| reduction reuses the LDS stage after a barrier.
+template <int B>
+struct RfParams {
+    int32_t src[B], rmask[B];
+    double oma[B], inv[B];
+};
+
 template <typename OffT, int C, typename ST>
 __global__ __launch_bounds__(kBlock) void refresh_k(
         const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
@@ -564,10 +578,17 @@ __global__ __launch_bounds__(kBlock) void refresh_k(
         double* __restrict__ partials) {
     using P = Rf<C>;
     __shared__ float4 lds[P::kNnz * C];
-    __shared__ double red[kBlock * 4];
+    static_assert(sizeof(lds) >= kBlock * 4 * sizeof(double), "the |rt| reduction fits the stage");
+    double* red = reinterpret_cast<double*>(lds);
+    __shared__ RfParams<4 * C> rp;
+    if ((int)threadIdx.x < 4 * C) {
+        rp.src[threadIdx.x] = src[threadIdx.x];
+        rp.rmask[threadIdx.x] = rmask[threadIdx.x];
+        rp.oma[threadIdx.x] = acoef[Bw + threadIdx.x];        // 1 - alpha_b
+        rp.inv[threadIdx.x] = acoef[2 * Bw + threadIdx.x];    // 1 / (1 - alpha_b)
+    }
+    __syncthreads();
     double cs0 = 0.0, cs1 = 0.0, cs2 = 0.0, cs3 = 0.0;   // threads c < C: |rt| of columns 4c..4c+3
-    const double* __restrict__ oma_b = acoef + Bw;         // 1 - alpha_b
-    const double* __restrict__ inv_b = acoef + 2 * Bw;     // 1 / (1 - alpha_b)
     for (int32_t bi = blockIdx.x; bi < n_blocks; bi += gridDim.x) {
         const RowBlock b = blocks[bi];
         const bool whole = b.piece == -1;
@@ -627,8 +648,8 @@ __global__ __launch_bounds__(kBlock) void refresh_k(
             const int64_t at = (int64_t)u * C + c;
             const double d = (double)deg[u];
             const float4 t = T[at];
-            const int4 s4 = reinterpret_cast<const int4*>(src)[c];
-            const int4 w4 = reinterpret_cast<const int4*>(rmask)[c];
+            const int4 s4 = reinterpret_cast<const int4*>(rp.src)[c];
+            const int4 w4 = reinterpret_cast<const int4*>(rp.rmask)[c];
             double2 sa = S[2 * at], sb = S[2 * at + 1];
             double2 aa = AS[2 * at], ab = AS[2 * at + 1];
             if (w4.x == 2) sa.x = aa.x = 0.0;    // first refresh after the conversion
@@ -637,8 +658,8 @@ __global__ __launch_bounds__(kBlock) void refresh_k(
             if (w4.w == 2) sb.y = ab.y = 0.0;
             // the in-neighbour sums of S + T
             const double a0 = aa.x + g0, a1 = aa.y + g1, a2 = ab.x + g2, a3 = ab.y + g3;
-            const double2 i01 = reinterpret_cast<const double2*>(inv_b)[2 * c];
-            const double2 i23 = reinterpret_cast<const double2*>(inv_b)[2 * c + 1];
+            const double2 i01 = reinterpret_cast<const double2*>(rp.inv)[2 * c];
+            const double2 i23 = reinterpret_cast<const double2*>(rp.inv)[2 * c + 1];
             t0 = (s4.x == u ? 1.0 : 0.0) - d * (sa.x + (double)t.x) * i01.x + a0;
             t1 = (s4.y == u ? 1.0 : 0.0) - d * (sa.y + (double)t.y) * i01.y + a1;
             t2 = (s4.z == u ? 1.0 : 0.0) - d * (sb.x + (double)t.z) * i23.x + a2;
@@ -651,8 +672,8 @@ __global__ __launch_bounds__(kBlock) void refresh_k(
             }
             if (w4.x | w4.y | w4.z | w4.w) {     // other columns keep their bits (exact round trip)
                 float4 y = ST::value4(Y[at]);
-                const double2 o01 = reinterpret_cast<const double2*>(oma_b)[2 * c];
-                const double2 o23 = reinterpret_cast<const double2*>(oma_b)[2 * c + 1];
+                const double2 o01 = reinterpret_cast<const double2*>(rp.oma)[2 * c];
+                const double2 o23 = reinterpret_cast<const double2*>(rp.oma)[2 * c + 1];
                 if (w4.x) y.x = (float)(o01.x * t0 / d);
                 if (w4.y) y.y = (float)(o01.y * t1 / d);
                 if (w4.z) y.z = (float)(o23.x * t2 / d);
@@ -666,7 +687,9 @@ __global__ __launch_bounds__(kBlock) void refresh_k(
                 rt_out[(int64_t)(4 * c + 3) * n + u] = t3;
             }
         }
-        // |rt| of this block's rows into the accumulators of threads c < C, in row order
+        // |rt| of this block's rows into the accumulators of threads c < C, in row
+        // order; red aliases the stage, so every thread must be done reading it
+        __syncthreads();
         red[threadIdx.x * 4 + 0] = fabs(t0);
         red[threadIdx.x * 4 + 1] = fabs(t1);
         red[threadIdx.x * 4 + 2] = fabs(t2);
@@ -754,7 +777,7 @@ const Schedule& refresh_schedule(Graph& g) {
     return g.schedule(Rf<C>::kNnz, Rf<C>::kRows, 1, kRefreshRounds);   // long rows whole, in rounds
 }
 
-template <int C, bool SOR, typename ST, int L>
+template <int C, bool SOR, typename ST, int L, bool AF>
 void sweep_launch(MixedCtx& c, Graph& g, const void* yin, void* yout) {
     const Schedule& sch = sweep_schedule<C, L>(g, c.chunks);
     auto Y4i = reinterpret_cast<const typename ST::V*>(yin);
@@ -763,27 +786,28 @@ void sweep_launch(MixedCtx& c, Graph& g, const void* yin, void* yout) {
     const LongRow* lrows = sch.longrows.as<LongRow>();
     auto part = c.piece_part.as<Vec<ST::K>>();
     const float* om = SOR ? c.omega.as<float>() : nullptr;
+    const float* af = AF ? c.afac.as<float>() : nullptr;
     for (int j = 0; j < sch.chunks; ++j) {      // chunk j sees the output of chunks < j
         const int32_t nb = sch.first[j + 1] - sch.first[j];
         if (nb == 0) continue;
         dim3 grid((unsigned)nb), blk(kBlock);
         const RowBlock* bj = blocks + sch.first[j];
         if (g.off64)
-            hipLaunchKernelGGL((sweep_k<int64_t, C, SOR, ST, L>), grid, blk, 0, c.stream, g.col_ptr.as<int64_t>(),
-                               g.row_idx.as<int32_t>(), bj, sch.lo[j], c.scale.as<float>(), c.afac.as<float>(), Y4i, Y4o,
+            hipLaunchKernelGGL((sweep_k<int64_t, C, SOR, ST, L, AF>), grid, blk, 0, c.stream, g.col_ptr.as<int64_t>(),
+                               g.row_idx.as<int32_t>(), bj, sch.lo[j], c.scale.as<float>(), af, Y4i, Y4o,
                                c.T.as<float4>(), c.kb.as<int32_t>(), c.entry.as<int32_t>(), c.step.as<int32_t>(),
                                part, om);
         else
-            hipLaunchKernelGGL((sweep_k<uint32_t, C, SOR, ST, L>), grid, blk, 0, c.stream, g.col_ptr.as<uint32_t>(),
-                               g.row_idx.as<int32_t>(), bj, sch.lo[j], c.scale.as<float>(), c.afac.as<float>(), Y4i, Y4o,
+            hipLaunchKernelGGL((sweep_k<uint32_t, C, SOR, ST, L, AF>), grid, blk, 0, c.stream, g.col_ptr.as<uint32_t>(),
+                               g.row_idx.as<int32_t>(), bj, sch.lo[j], c.scale.as<float>(), af, Y4i, Y4o,
                                c.T.as<float4>(), c.kb.as<int32_t>(), c.entry.as<int32_t>(), c.step.as<int32_t>(),
                                part, om);
         const int32_t nl = sch.lr_first[j + 1] - sch.lr_first[j];
         if (nl > 0) {
             const int per = kBlock / C;
-            hipLaunchKernelGGL((combine_k<C, SOR, ST>), dim3((unsigned)((nl + per - 1) / per)), dim3(kBlock), 0,
+            hipLaunchKernelGGL((combine_k<C, SOR, ST, AF>), dim3((unsigned)((nl + per - 1) / per)), dim3(kBlock), 0,
                                c.stream, lrows + sch.lr_first[j], nl, part, c.step.as<int32_t>(),
-                               c.scale.as<float>(), c.afac.as<float>(), Y4i, Y4o, c.T.as<float4>(), c.kb.as<int32_t>(),
+                               c.scale.as<float>(), af, Y4i, Y4o, c.T.as<float4>(), c.kb.as<int32_t>(),
                                c.entry.as<int32_t>(), om);
         }
     }
@@ -796,17 +820,22 @@ template <int C>
 void sweep_c(MixedCtx& c, Graph& g, const void* yin, void* yout) {
     by_tile(c.tile, [&](auto tl) {
         constexpr int L = decltype(tl)::value;
-        if (c.bf16) {
-            if constexpr (C >= 2) {
-                if (c.sor) sweep_launch<C / 2, true, StoreBF16x8, L>(c, g, yin, yout);
-                else sweep_launch<C / 2, false, StoreBF16x8, L>(c, g, yin, yout);
+        auto go = [&](auto af) {
+            constexpr bool AF = decltype(af)::value;
+            if (c.bf16) {
+                if constexpr (C >= 2) {
+                    if (c.sor) sweep_launch<C / 2, true, StoreBF16x8, L, AF>(c, g, yin, yout);
+                    else sweep_launch<C / 2, false, StoreBF16x8, L, AF>(c, g, yin, yout);
+                } else {
+                    fail(PPR_ERR_ARG, "bf16 residues need a block of at least 8 columns");
+                }
             } else {
-                fail(PPR_ERR_ARG, "bf16 residues need a block of at least 8 columns");
+                if (c.sor) sweep_launch<C, true, StoreF32, L, AF>(c, g, yin, yout);
+                else sweep_launch<C, false, StoreF32, L, AF>(c, g, yin, yout);
             }
-        } else {
-            if (c.sor) sweep_launch<C, true, StoreF32, L>(c, g, yin, yout);
-            else sweep_launch<C, false, StoreF32, L>(c, g, yin, yout);
-        }
+        };
+        if (c.af) go(std::true_type{});
+        else go(std::false_type{});
     });
 }
 

@@ -168,6 +168,7 @@ struct Graph {
     // residue format (0 FP32, 1 bf16) and log2(width) (0 = default)
     std::atomic<int> tuned_width{0};
     std::atomic<int> tuned_tile[2][8] = {};
+    std::atomic<int> tuned_fmt[8] = {};                // residue format + 1 per log2(width) (0 = not tuned)
     DevBuf walk_index;                                 // int32[m]: stop nodes of d_v walks per node
     double walk_alpha = -1.0;                          // the index's alpha (-1: none)
     uint64_t walk_seed = 0;                            // the index's seed
@@ -303,7 +304,7 @@ void debug_walks(Graph& g, double alpha, double W, uint64_t seed, bool use_index
                  int64_t* nwalks);
 void run_mixed_batch(Graph& g, const int32_t* sources, int32_t B, double alpha, double lambda,
                      const ppr_options& opt, double* pi_out, double* r_out, ppr_stats* st);
-void autotune_width(Graph& g, double alpha, const int32_t* widths, int32_t count, int32_t* best,
+void autotune_width(Graph& g, double alpha, double lambda, const int32_t* widths, int32_t count, int32_t* best,
                     double* cost_us);
 
 void debug_sweeps_mixed(Graph& g, double alpha, int32_t B, int32_t chunks, int32_t sweeps, const float* y_in,

@@ -184,14 +184,26 @@ def test_graph_recreated_between_batches(c1):
 
 
 def test_autotune_picks_a_width_and_queries_use_it(c1):
+    """The autotuner times each (width, residue storage) end to end; later
+    queries with batch_cols = 0 use the chosen width and that width's
+    storage, an explicit storage overrides it, and every result stays
+    certified."""
     G = P.Graph.from_synth(c1)
-    res = G.autotune(ALPHA, widths=[4, 16])
+    res = G.autotune(ALPHA, 1e-8, widths=[4, 16])
     assert res["best"] in (4, 16)
-    assert all(v > 0 for v in res["us_per_column_sweep"].values())
+    assert all(v > 0 for v in res["us_per_query"].values())
     srcs = [int(s) for s in synth.sources(c1.n, 40)][:6]
     out, st = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED)          # batch_cols = 0: tuned width
     assert all(s["batch_cols"] == res["best"] for s in st)
     assert max(s["cert_l1"] for s in st) <= 1e-8
+    if res["best"] == 4:
+        assert all(s["residue_format"] == P.RESIDUE_F32 for s in st)
+    _, st16 = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=16, residue_format=P.RESIDUE_F32)
+    assert all(s["residue_format"] == P.RESIDUE_F32 for s in st16)
+    _, st16 = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=16, residue_format=P.RESIDUE_BF16)
+    assert all(s["residue_format"] == P.RESIDUE_BF16 for s in st16)
+    with pytest.raises(P.PPRError):
+        G.autotune(ALPHA, 0.0, widths=[4])
 
 
 @pytest.mark.parametrize("self_loops", [False, True])
@@ -354,3 +366,4 @@ def test_over_relaxation_falls_back_on_a_cycle():
     assert st[0]["refreshes"] >= 2
     assert st[0]["sor_omega"] == 1.0            # fell back
     G.close()
+
