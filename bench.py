@@ -170,6 +170,64 @@ def serve_leg(args, P, synth, torch, g_main, G_main) -> dict:
                                              "not_converged", "max_cert_l1")}}}
 
 
+def large_leg(args, P, synth, torch) -> dict | None:
+    """Directed Chung-Lu n = 40M, m = 1.4B (exponent 2.0, int32 indices):
+    16 sources at B = 16 (one warm-up batch of 4, then the timed batch) and one
+    FP64 single-source query, device outputs, every result certified.  Global
+    sweep time from HIP events; bytes per sweep on the compulsory model.
+    Skipped (with the reason) when the host or the device lacks the memory."""
+    n, m = 40_000_000, 1_400_000_000
+    host = os.sysconf("SC_PAGE_SIZE") * os.sysconf("SC_PHYS_PAGES")
+    free, _ = torch.cuda.mem_get_info()
+    if host < 96 * 2 ** 30 or free < 64 * 10 ** 9:
+        return {"skipped": f"needs 96 GiB host and 64 GB free device memory (host {host >> 30} GiB, "
+                           f"device {free / 1e9:.0f} GB free)"}
+    t0 = time.time()
+    gl = synth.chunglu(n, m, 2.0, cache=False)
+    gen_s = time.time() - t0
+    GL = P.Graph.from_synth(gl, trust_input=True)
+    info = GL.info()
+    del gl
+    srcs = synth.sources(n, 16).tolist()
+    out = torch.empty((16, n), dtype=torch.float64, device="cuda")
+    GL.query_batch(srcs[:4], args.alpha, args.lam, P.MIXED, batch_cols=16, out=out[:4])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _, st = GL.query_batch(srcs, args.alpha, args.lam, P.MIXED, batch_cols=16, out=out)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t1
+    per = st[0]["sweep_ms"] / max(st[0]["sweep_launches"], 1)
+    sums = out.sum(dim=1).cpu().numpy()
+    one = torch.empty(n, dtype=torch.float64, device="cuda")
+    t2 = time.perf_counter()
+    _, s64 = GL.query(srcs[0], args.alpha, args.lam, P.FP64, out=one, certify=1)
+    torch.cuda.synchronize()
+    dt64 = time.perf_counter() - t2
+    per64 = s64["sweep_ms"] / max(s64["sweep_launches"], 1)
+    res = {"workload": f"chung-lu n={n} m={m} gamma=2.0 alpha={args.alpha} lambda={args.lam:g}",
+           "generate_s": round(gen_s, 1), "graph_create_ms": round(info["build_ms"], 1),
+           "graph_device_bytes": info["device_bytes"],
+           "batched": {"sources": 16, "batch_cols": 16, "value": round(16 / dt, 3), "unit": "queries/s",
+                       "residues": "bf16" if st[0]["residue_format"] == P.RESIDUE_BF16 else "f32",
+                       "sweeps_per_query": round(sum(s["sweeps"] for s in st) / 16, 2),
+                       "refreshes_per_query": round(sum(s["refreshes"] for s in st) / 16, 2),
+                       "ms_per_sweep": round(per, 3),
+                       "sweep_GBps_compulsory": round(compulsory_sweep_bytes(n, m, 16) / (per * 1e-3) / 1e9, 1),
+                       "max_cert_l1": max(s["cert_l1"] for s in st),
+                       "max_mass_error": float(abs(sums - 1.0).max())},
+           "fp64_single": {"value": round(1 / dt64, 3), "unit": "queries/s", "sweeps": s64["sweeps"],
+                           "ms_per_sweep": round(per64, 3),
+                           "sweep_GBps_compulsory": round((4 * m + 8 * n + 32 * n) / (per64 * 1e-3) / 1e9, 1),
+                           "cert_l1": s64["cert_l1"]}}
+    if not (res["batched"]["max_cert_l1"] <= args.lam and s64["cert_l1"] <= args.lam):
+        raise RuntimeError(f"large-graph answers not certified: {res}")
+    print(f"[bench] large graph: {res}", file=sys.stderr, flush=True)
+    GL.close()
+    del out, one
+    torch.cuda.empty_cache()
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,6 +265,9 @@ def main() -> int:
                     help="serving leg: Poisson arrival rate as a fraction of the measured saturation")
     ap.add_argument("--serve-graphs", default="1000000:15000000,4000000:70000000,16000000:300000000",
                     help="serving leg: n:m of the resident graphs")
+    ap.add_argument("--large", type=int, default=1,
+                    help="1: also run the large-graph leg (n=40M, m=1.4B, exponent 2.0: 16 sources at B=16 and "
+                         "one FP64 query) when host and device memory allow (0: skip)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -451,6 +512,11 @@ def main() -> int:
     if args.serve_queries > 0:
         serving = serve_leg(args, P, synth, torch, g, G)
 
+    # large-graph leg (the Twitter-sized configuration)
+    large = None
+    if args.large:
+        large = large_leg(args, P, synth, torch)
+
     chunks = stats_all[0][0]["sweep_chunks"]
     omegas = sorted({round(s["sor_omega"], 4) for sts in stats_all for s in sts})
     sk_name = (f"sweep_k<C={width // (8 if bf16 else 4)}{', over-relaxed' if over_relaxed else ''}"
@@ -537,6 +603,7 @@ def main() -> int:
         "host_output": host_out,
         "single_source": single,
         "serving": serving,
+        "large_graph": large,
         "cpu_baseline": cpu,
         "paper_context": {"figure": "PowerPush < 40 s per query (no GPU or throughput figures in the paper)",
                           "hardware": "one Intel 2.0 GHz CPU server, 144 GB RAM, sequential C++ (GCC 9.3 -O3)",
