@@ -142,6 +142,36 @@ struct StoreBF16x8 {                    // 8 bf16 columns: the sweep's view
     }
 };
 
+// In-edge indices of one round of a row-tile block: item k of thread t is
+// edge (t + 256 k) / C of the round (C lanes per edge, one per 16-byte vector
+// of the row).  A wave's 64 lanes then need only 64 / C distinct edges per
+// item.  When all G kItems of them (G = 64 / C) fit the wave, lane
+// L = j + G k loads edge (wave's first) + j + k 256 / C once and the lanes
+// take their kItems indices from it with shuffles, instead of every lane
+// loading each of its kItems indices.  -1 marks an item beyond the round's
+// nr edges.
+template <int C, int kItems>
+__device__ inline void round_indices(const int32_t* __restrict__ row_idx, int64_t first, int32_t nr,
+                                     int32_t (&vv)[kItems]) {
+    constexpr int G = (C <= 64) ? 64 / C : 0;      // distinct edges per item per wave
+    if constexpr (G > 0 && G * kItems <= 64) {
+        const int lane = threadIdx.x & 63;
+        const int32_t w0 = (int32_t)(threadIdx.x >> 6) * G;   // the wave's first edge of item 0
+        // loader lane L = j + G k holds edge w0 + j + k (256 / C)
+        const int j = lane % G, kk = lane / G;
+        const int32_t el = w0 + j + kk * (kBlock / C);
+        const int32_t mine = (lane < G * kItems && el < nr) ? row_idx[first + el] : -1;
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) vv[k] = __shfl(mine, (lane / C) + G * k, 64);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kItems; ++k) {
+            const int32_t it = threadIdx.x + k * kBlock;
+            vv[k] = (it / C < nr) ? row_idx[first + it / C] : -1;
+        }
+    }
+}
+
 // ---------------------------------------------------------------- local phase
 __global__ void init_sources_k(const int32_t* __restrict__ src, const int32_t* __restrict__ cmask, int32_t Bw,
                                int shift, double* __restrict__ r64) {
@@ -437,7 +467,7 @@ __device__ inline void finish_row(int32_t u, int c, Vec<ST::K> acc, int32_t step
 }
 
 template <typename OffT, int C, bool SOR, typename ST, int L, bool AF>
-__global__ __launch_bounds__(kBlock) void sweep_k(
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) void sweep_k(
         const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
         const RowBlock* __restrict__ blocks, int32_t lo, const float* __restrict__ scale,
         const float* __restrict__ afac,
@@ -482,11 +512,7 @@ __global__ __launch_bounds__(kBlock) void sweep_k(
     for (int32_t base = 0; base < ne; base += P::kNnz) {
         const int32_t nr = min(P::kNnz, ne - base);
         int32_t vv[P::kItems];
-#pragma unroll
-        for (int k = 0; k < P::kItems; ++k) {
-            int32_t it = threadIdx.x + k * kBlock;
-            vv[k] = (it / C < nr) ? row_idx[e0 + base + it / C] : -1;
-        }
+        round_indices<C, P::kItems>(row_idx, e0 + base, nr, vv);
         typename ST::V gv[P::kItems];
 #pragma unroll
         for (int k = 0; k < P::kItems; ++k) {
@@ -611,11 +637,7 @@ __global__ __launch_bounds__(kBlock) void refresh_k(
         for (int32_t base = 0; base < ne; base += P::kNnz) {
             const int32_t nr = min(P::kNnz, ne - base);
             int32_t vv[P::kItems];
-#pragma unroll
-            for (int k = 0; k < P::kItems; ++k) {
-                int32_t it = threadIdx.x + k * kBlock;
-                vv[k] = (it / C < nr) ? row_idx[e0 + base + it / C] : -1;
-            }
+            round_indices<C, P::kItems>(row_idx, e0 + base, nr, vv);
             float4 tv[P::kItems];
 #pragma unroll
             for (int k = 0; k < P::kItems; ++k)
