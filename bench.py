@@ -103,13 +103,21 @@ def measured_traffic(width: int, chunks: int, residues: str, tile: int):
 
 
 def cpu_model() -> str:
-    """The host CPU's model name as lscpu reports it (else /proc/cpuinfo)."""
+    """The host CPU as lscpu reports it: model name, family / model / stepping,
+    sockets, cores per socket, threads per core (else /proc/cpuinfo's name)."""
     import subprocess
     try:
         out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        f = {}
         for line in out.splitlines():
-            if line.startswith("Model name:"):
-                return line.split(":", 1)[1].strip()
+            if ":" in line:
+                k, v = line.split(":", 1)
+                f[k.strip()] = v.strip()
+        if "Model name" in f:
+            extra = ", ".join(f"{k.lower()} {f[k]}" for k in ("CPU family", "Model", "Stepping", "Socket(s)",
+                                                                "Core(s) per socket", "Thread(s) per core",
+                                                                "CPU max MHz") if k in f)
+            return f"{f['Model name']} ({extra})" if extra else f["Model name"]
     except (OSError, subprocess.SubprocessError):
         pass
     try:
