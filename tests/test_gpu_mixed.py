@@ -134,15 +134,19 @@ def test_small_graphs_and_hubs():
     _check_batch(h, srcs, out, st, 1e-9, None)
 
 
-def test_outputs_device_and_residual(c1):
-    srcs = [int(s) for s in synth.sources(c1.n, 40)][:8]
+@pytest.mark.parametrize("width", [8, 32])
+def test_outputs_device_and_residual(c1, width):
+    """The FP64 residual output (the flush) equals the oracle's residual of the
+    exported estimate, in FP32 (width 8) and bf16 (width 32) residue storage."""
+    srcs = [int(s) for s in synth.sources(c1.n, 40)][:width]
     G = P.Graph.from_synth(c1)
-    out = torch.empty((8, c1.n), dtype=torch.float64, device="cuda")
-    r_out = torch.empty((8, c1.n), dtype=torch.float64, device="cuda")
-    G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=8, out=out, r_out=r_out)
+    out = torch.empty((width, c1.n), dtype=torch.float64, device="cuda")
+    r_out = torch.empty((width, c1.n), dtype=torch.float64, device="cuda")
+    _, st = G.query_batch(srcs, ALPHA, 1e-8, P.MIXED, batch_cols=width, out=out, r_out=r_out)
+    assert all(s["residue_format"] == (P.RESIDUE_BF16 if width >= 32 else P.RESIDUE_F32) for s in st)
     pi = out.cpu().numpy()
     r = r_out.cpu().numpy()
-    for b, s in enumerate(srcs):
+    for b, s in enumerate(srcs[:8]):
         cert, rt = oracle.certificate(c1, s, ALPHA, pi[b], want_residual=True)
         # rt is a difference of terms of size pi_hat(u) / alpha <= 5: FP64
         # cancellation leaves an absolute error of a few 1e-16
