@@ -142,6 +142,16 @@ struct StoreBF16x8 {                    // 8 bf16 columns: the sweep's view
     }
 };
 
+// 16 bytes per lane from global memory straight into LDS: lane l of the wave
+// writes vector l after dst (dst is the same for the whole wave).  Device
+// pass only (the builtin has no host form; the host pass needs only the
+// kernel's signature).
+__device__ inline void lds_dma16(const void* src, void* dst) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_amdgcn_global_load_lds(src, dst, 16, 0, 0);
+#endif
+}
+
 // In-edge indices of one round of a row-tile block: item k of thread t is
 // edge (t + 256 k) / C of the round (C lanes per edge, one per 16-byte vector
 // of the row).  A wave's 64 lanes then need only 64 / C distinct edges per
@@ -483,7 +493,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
     // every item of this thread belongs to column chunk threadIdx.x % C
     Vec<K> enf = v_zero<K>();
     bool fresh = false;
-    if (step == 0 && lo > 0) {
+    const bool entry_gs = step == 0 && lo > 0;     // a first sweep of a later chunk: register path
+    if (entry_gs) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             enf.q[i] = flag4(reinterpret_cast<const int4*>(entry)[(threadIdx.x % C) * Q + i]);
@@ -513,17 +524,34 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         const int32_t nr = min(P::kNnz, ne - base);
         int32_t vv[P::kItems];
         round_indices<C, P::kItems>(row_idx, e0 + base, nr, vv);
-        typename ST::V gv[P::kItems];
+        if (!entry_gs) {
+            // the gathers land in the stage directly (LDS DMA: 16 bytes per lane,
+            // a wave's 64 lanes fill 64 consecutive vectors, exactly the layout
+            // lds[t + 256 k]); they may only start once the previous round's
+            // stage has been read
+            if (base > 0) __syncthreads();
 #pragma unroll
-        for (int k = 0; k < P::kItems; ++k) {
-            gv[k] = (vv[k] >= 0) ? gather_gs<C, ST>(Y_in, Y_out, vv[k], threadIdx.x % C, lo, fresh, enf)
-                                 : ST::zero();
-        }
-        if (base > 0) __syncthreads();             // the previous round's LDS reads are done
+            for (int k = 0; k < P::kItems; ++k) {
+                if (vv[k] >= 0) {
+                    const int64_t i = (int64_t)vv[k] * C + (threadIdx.x % C);
+                    const typename ST::V* src = vv[k] >= lo ? Y_in + i : Y_out + i;
+                    lds_dma16(src, lds + (threadIdx.x & ~63u) + k * kBlock);
+                }
+            }
+        } else {
+            // an entry sweep of a later chunk combines two values per gather
+            typename ST::V gv[P::kItems];
 #pragma unroll
-        for (int k = 0; k < P::kItems; ++k) {
-            int32_t it = threadIdx.x + k * kBlock;
-            if (it / C < nr) lds[it] = gv[k];
+            for (int k = 0; k < P::kItems; ++k) {
+                gv[k] = (vv[k] >= 0) ? gather_gs<C, ST>(Y_in, Y_out, vv[k], threadIdx.x % C, lo, fresh, enf)
+                                     : ST::zero();
+            }
+            if (base > 0) __syncthreads();             // the previous round's LDS reads are done
+#pragma unroll
+            for (int k = 0; k < P::kItems; ++k) {
+                int32_t it = threadIdx.x + k * kBlock;
+                if (it / C < nr) lds[it] = gv[k];
+            }
         }
         __syncthreads();
         if (!whole && row == 0) { s0 = 0; s1 = nr; }
