@@ -666,16 +666,12 @@ __global__ __launch_bounds__(kBlock) void refresh_k(
             const int32_t nr = min(P::kNnz, ne - base);
             int32_t vv[P::kItems];
             round_indices<C, P::kItems>(row_idx, e0 + base, nr, vv);
-            float4 tv[P::kItems];
+            __syncthreads();                       // the previous LDS reads are done
+            // the in-neighbours' accumulator rows land in the stage by DMA (16
+            // bytes per lane at the stage's wave layout lds[t + 256 k])
 #pragma unroll
             for (int k = 0; k < P::kItems; ++k)
-                tv[k] = (vv[k] >= 0) ? T[(int64_t)vv[k] * C + (threadIdx.x % C)] : make_float4(0.f, 0.f, 0.f, 0.f);
-            __syncthreads();                       // the previous LDS reads are done
-#pragma unroll
-            for (int k = 0; k < P::kItems; ++k) {
-                int32_t it = threadIdx.x + k * kBlock;
-                if (it / C < nr) lds[it] = tv[k];
-            }
+                if (vv[k] >= 0) lds_dma16(T + (int64_t)vv[k] * C + (threadIdx.x % C), lds + (threadIdx.x & ~63u) + k * kBlock);
             __syncthreads();
             if (!whole && row == 0) { s0 = 0; s1 = nr; }
             for (int32_t e = s0 + sub; e < s1; e += T2) {
