@@ -142,6 +142,27 @@ struct StoreBF16x8 {                    // 8 bf16 columns: the sweep's view
     }
 };
 
+// Non-temporal loads and stores.  The sweep uses them for what it streams
+// once (a row's own input residue, new residue and stage accumulator, the
+// in-edge indices), so that these do not push the gathered residue rows, which
+// many in-edges reuse, out of the caches.  The gathers themselves keep the
+// default policy: they depend on those cache hits.
+template <typename V>
+__device__ inline V nt_ld(const V* p) {
+    using W = unsigned int __attribute__((ext_vector_type(sizeof(V) / 4)));
+    const W w = __builtin_nontemporal_load(reinterpret_cast<const W*>(p));
+    V v;
+    __builtin_memcpy(&v, &w, sizeof(V));
+    return v;
+}
+template <typename V>
+__device__ inline void nt_st(const V& v, V* p) {
+    using W = unsigned int __attribute__((ext_vector_type(sizeof(V) / 4)));
+    W w;
+    __builtin_memcpy(&w, &v, sizeof(V));
+    __builtin_nontemporal_store(w, reinterpret_cast<W*>(p));
+}
+
 // 16 bytes per lane from global memory straight into LDS: lane l of the wave
 // writes vector l after dst (dst is the same for the whole wave).  Device
 // pass only (the builtin has no host form; the host pass needs only the
@@ -159,8 +180,8 @@ __device__ inline void lds_dma16(const void* src, void* dst) {
 // L = j + G k loads edge (wave's first) + j + k 256 / C once and the lanes
 // take their kItems indices from it with shuffles, instead of every lane
 // loading each of its kItems indices.  -1 marks an item beyond the round's
-// nr edges.
-template <int C, int kItems>
+// nr edges.  NT: the index loads are non-temporal.
+template <int C, int kItems, bool NT>
 __device__ inline void round_indices(const int32_t* __restrict__ row_idx, int64_t first, int32_t nr,
                                      int32_t (&vv)[kItems]) {
     constexpr int G = (C <= 64) ? 64 / C : 0;      // distinct edges per item per wave
@@ -170,7 +191,8 @@ __device__ inline void round_indices(const int32_t* __restrict__ row_idx, int64_
         // loader lane L = j + G k holds edge w0 + j + k (256 / C)
         const int j = lane % G, kk = lane / G;
         const int32_t el = w0 + j + kk * (kBlock / C);
-        const int32_t mine = (lane < G * kItems && el < nr) ? row_idx[first + el] : -1;
+        int32_t mine = -1;
+        if (lane < G * kItems && el < nr) mine = NT ? __builtin_nontemporal_load(&row_idx[first + el]) : row_idx[first + el];
 #pragma unroll
         for (int k = 0; k < kItems; ++k) vv[k] = __shfl(mine, (lane / C) + G * k, 64);
     } else {
@@ -432,7 +454,7 @@ __device__ inline void finish_row(int32_t u, int c, Vec<ST::K> acc, int32_t step
     // the row's own input residue: the previous push (over-relaxation), the
     // even step's output (odd steps), the fresh residue (entry sweep)
     Vec<K> yin = v_zero<K>();
-    if (SOR || odd || any_en) yin = ST::value(Y_in[at]);
+    if (SOR || odd || any_en) yin = ST::value(nt_ld(&Y_in[at]));
     acc = v_mul(acc, m);
     if constexpr (AF) {
         // the column's alpha factor on the scale table (instantiated only while
@@ -460,11 +482,11 @@ __device__ inline void finish_row(int32_t u, int c, Vec<ST::K> acc, int32_t step
         }
     }
     const typename ST::V yq = ST::pack(y);
-    Y_out[at] = yq;
+    nt_st(yq, &Y_out[at]);
     const Vec<K> ys = ST::value(yq);             // what the out-neighbours will pull
     if (odd) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) T[at * Q + i] = f4_add(f4_add(T[at * Q + i], yin.q[i]), ys.q[i]);
+        for (int i = 0; i < Q; ++i) nt_st(f4_add(f4_add(nt_ld(&T[at * Q + i]), yin.q[i]), ys.q[i]), &T[at * Q + i]);
     } else if (any_en || step == last) {
         Vec<K> t;
 #pragma unroll
@@ -523,7 +545,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
     for (int32_t base = 0; base < ne; base += P::kNnz) {
         const int32_t nr = min(P::kNnz, ne - base);
         int32_t vv[P::kItems];
-        round_indices<C, P::kItems>(row_idx, e0 + base, nr, vv);
+        round_indices<C, P::kItems, true>(row_idx, e0 + base, nr, vv);
         if (!entry_gs) {
             // the gathers land in the stage directly (LDS DMA: 16 bytes per lane,
             // a wave's 64 lanes fill 64 consecutive vectors, exactly the layout
@@ -665,7 +687,7 @@ __global__ __launch_bounds__(kBlock) void refresh_k(
         for (int32_t base = 0; base < ne; base += P::kNnz) {
             const int32_t nr = min(P::kNnz, ne - base);
             int32_t vv[P::kItems];
-            round_indices<C, P::kItems>(row_idx, e0 + base, nr, vv);
+            round_indices<C, P::kItems, false>(row_idx, e0 + base, nr, vv);
             __syncthreads();                       // the previous LDS reads are done
             // the in-neighbours' accumulator rows land in the stage by DMA (16
             // bytes per lane at the stage's wave layout lds[t + 256 k])
