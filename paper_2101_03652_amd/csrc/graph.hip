@@ -70,10 +70,18 @@ void DevBuf::alloc(size_t b) {
     bytes = b;
 }
 
+void DevBuf::view(void* base, size_t b) {
+    release();
+    p = base;
+    bytes = b;
+    owned = false;
+}
+
 void DevBuf::release() {
-    if (p) (void)hipFree(p);
+    if (p && owned) (void)hipFree(p);
     p = nullptr;
     bytes = 0;
+    owned = true;
 }
 
 void PinnedBuf::alloc(size_t b) {

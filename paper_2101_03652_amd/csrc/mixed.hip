@@ -147,8 +147,9 @@ MixedCtxPtr mixed_acquire(Graph& g, int Bw, int64_t fcap, bool bf16) {
     c->degF.alloc(8 * (size_t)fcap);
     c->off.alloc(8 * ((size_t)fcap + 1));
     c->scan_tmp.alloc(k::scan_tmp_bytes(fcap));
-    c->Y0.alloc((bf16 ? 2 : 4) * nb);
-    c->Y1.alloc((bf16 ? 2 : 4) * nb);
+    c->Y01.alloc(2 * (bf16 ? 2 : 4) * nb);
+    c->Y0.view(c->Y01.p, (bf16 ? 2 : 4) * nb);
+    c->Y1.view(static_cast<char*>(c->Y01.p) + (bf16 ? 2 : 4) * nb, (bf16 ? 2 : 4) * nb);
     c->S.alloc(8 * nb);
     c->AS.alloc(8 * nb);
     c->T.alloc(4 * nb);

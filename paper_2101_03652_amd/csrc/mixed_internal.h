@@ -51,7 +51,8 @@ struct MixedCtx {
     DevBuf r64, pi64;                 // double[n][Bw]  local-phase scratch, zero between uses
     DevBuf F0, F1, X, degF, off;      // frontier (int64 keys), increments, degrees, prefix
     DevBuf scan_tmp;
-    DevBuf Y0, Y1;                    // [n][Bw] FP32 or bf16: residue still to push, y = (1-alpha) r / d
+    DevBuf Y01;                       // Y0 and Y1 back to back (a sweep gathers both at 32-bit offsets)
+    DevBuf Y0, Y1;                    // [n][Bw] FP32 or bf16: residue still to push, y = (1-alpha) r / d (views of Y01)
     DevBuf S;                         // double[n][Bw]  reserve (y domain)
     DevBuf AS;                        // double[n][Bw]  sum of S over each node's in-neighbours
     DevBuf T;                         // float[n][Bw]   per-stage reserve accumulator

@@ -102,14 +102,21 @@ __device__ inline Vec<K> v_shfl_xor(Vec<K> a, int o) {
 //
 // bf16: the upper half of an FP32 word; packing rounds to nearest, ties to
 // even (the residues are finite).  Column k of a vector sits in half k of its
-// words, low half first, i.e. bf16 element order in memory.
+// words, low half first, i.e. bf16 element order in memory.  bf16_bits rounds
+// on the bits; bf16_pair converts two values with the FP32 -> bf16 conversion
+// instruction of gfx950 (one instruction per pair; the same rounding, denormal
+// inputs included).
 __device__ inline uint32_t bf16_bits(float f) {
     const uint32_t u = __float_as_uint(f);
     return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
 }
 __device__ inline float bf16_lo(uint32_t w) { return __uint_as_float(w << 16); }
 __device__ inline float bf16_hi(uint32_t w) { return __uint_as_float(w & 0xffff0000u); }
-__device__ inline uint32_t bf16_pair(float a, float b) { return bf16_bits(a) | (bf16_bits(b) << 16); }
+__device__ inline uint32_t bf16_pair(float a, float b) {
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    const bf16x2 v = {(__bf16)a, (__bf16)b};
+    return __builtin_bit_cast(uint32_t, v);
+}
 
 struct StoreF32 {                       // 4 FP32 columns
     static constexpr int K = 4;
@@ -505,7 +512,8 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         const float* __restrict__ afac,
         const typename ST::V* __restrict__ Y_in, typename ST::V* Y_out, float4* __restrict__ T,
         const int32_t* __restrict__ kb, const int32_t* __restrict__ entry, const int32_t* __restrict__ step_p,
-        Vec<ST::K>* __restrict__ partials, const float* __restrict__ omega) {
+        Vec<ST::K>* __restrict__ partials, const float* __restrict__ omega,
+        const char* ybase, uint32_t oin, uint32_t oout, int32_t off32) {
     using P = Sw<C, L>;
     constexpr int K = ST::K, Q = K / 4;
     static_assert(sizeof(typename ST::V) == 16, "a staged vector is 16 bytes");
@@ -541,6 +549,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
         s1 = (int32_t)((int64_t)col_ptr[r0 + row + 1] - e0);
     }
     Vec<K> acc = v_zero<K>();
+    // the wave's part of the stage (wave-uniform, so the DMA's LDS base is scalar)
+    typename ST::V* const ldsw = lds + __builtin_amdgcn_readfirstlane(threadIdx.x & ~63u);
+    const uint32_t lane16 = (threadIdx.x % C) * 16u;
     // a long row (or piece) runs rounds of P::kNnz in-edges through LDS
     for (int32_t base = 0; base < ne; base += P::kNnz) {
         const int32_t nr = min(P::kNnz, ne - base);
@@ -552,12 +563,25 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
             // lds[t + 256 k]); they may only start once the previous round's
             // stage has been read
             if (base > 0) __syncthreads();
+            if (off32) {
+                // both residue blocks in one buffer of < 4 GiB: a 32-bit offset
+                // from its base (the input block at oin, the output block at oout)
+                const uint32_t lin = lane16 + oin, dout = oout - oin;   // mod 2^32
 #pragma unroll
-            for (int k = 0; k < P::kItems; ++k) {
-                if (vv[k] >= 0) {
-                    const int64_t i = (int64_t)vv[k] * C + (threadIdx.x % C);
-                    const typename ST::V* src = vv[k] >= lo ? Y_in + i : Y_out + i;
-                    lds_dma16(src, lds + (threadIdx.x & ~63u) + k * kBlock);
+                for (int k = 0; k < P::kItems; ++k) {
+                    if (vv[k] >= 0) {
+                        const uint32_t o = (uint32_t)vv[k] * (uint32_t)(C * 16) + lin + (vv[k] < lo ? dout : 0u);
+                        lds_dma16(ybase + o, ldsw + k * kBlock);
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < P::kItems; ++k) {
+                    if (vv[k] >= 0) {
+                        const int64_t i = (int64_t)vv[k] * C + (threadIdx.x % C);
+                        const typename ST::V* src = vv[k] >= lo ? Y_in + i : Y_out + i;
+                        lds_dma16(src, ldsw + k * kBlock);
+                    }
                 }
             }
         } else {
@@ -855,6 +879,14 @@ void sweep_launch(MixedCtx& c, Graph& g, const void* yin, void* yout) {
     auto part = c.piece_part.as<Vec<ST::K>>();
     const float* om = SOR ? c.omega.as<float>() : nullptr;
     const float* af = AF ? c.afac.as<float>() : nullptr;
+    // 32-bit gather offsets when both blocks lie in the joint buffer and it is < 4 GiB
+    const char* yb = c.Y01.as<const char>();
+    const auto inside = [&](const void* y) {
+        return static_cast<const char*>(y) >= yb && static_cast<const char*>(y) < yb + c.Y01.bytes;
+    };
+    const int32_t off32 = (yb && c.Y01.bytes <= 0xffffffffull && inside(yin) && inside(yout)) ? 1 : 0;
+    const uint32_t oin = off32 ? (uint32_t)(static_cast<const char*>(yin) - yb) : 0u;
+    const uint32_t oout = off32 ? (uint32_t)(static_cast<const char*>(yout) - yb) : 0u;
     for (int j = 0; j < sch.chunks; ++j) {      // chunk j sees the output of chunks < j
         const int32_t nb = sch.first[j + 1] - sch.first[j];
         if (nb == 0) continue;
@@ -864,12 +896,12 @@ void sweep_launch(MixedCtx& c, Graph& g, const void* yin, void* yout) {
             hipLaunchKernelGGL((sweep_k<int64_t, C, SOR, ST, L, AF>), grid, blk, 0, c.stream, g.col_ptr.as<int64_t>(),
                                g.row_idx.as<int32_t>(), bj, sch.lo[j], c.scale.as<float>(), af, Y4i, Y4o,
                                c.T.as<float4>(), c.kb.as<int32_t>(), c.entry.as<int32_t>(), c.step.as<int32_t>(),
-                               part, om);
+                               part, om, yb, oin, oout, off32);
         else
             hipLaunchKernelGGL((sweep_k<uint32_t, C, SOR, ST, L, AF>), grid, blk, 0, c.stream, g.col_ptr.as<uint32_t>(),
                                g.row_idx.as<int32_t>(), bj, sch.lo[j], c.scale.as<float>(), af, Y4i, Y4o,
                                c.T.as<float4>(), c.kb.as<int32_t>(), c.entry.as<int32_t>(), c.step.as<int32_t>(),
-                               part, om);
+                               part, om, yb, oin, oout, off32);
         const int32_t nl = sch.lr_first[j + 1] - sch.lr_first[j];
         if (nl > 0) {
             const int per = kBlock / C;

@@ -74,12 +74,14 @@ struct EventPair {
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    bool owned = true;         // false: a view into another buffer (not freed here)
     DevBuf() = default;
     explicit DevBuf(size_t b) { alloc(b); }
     ~DevBuf() { release(); }
     DevBuf(const DevBuf&) = delete;
     DevBuf& operator=(const DevBuf&) = delete;
     void alloc(size_t b);
+    void view(void* base, size_t b);   // b bytes at base, owned by another buffer
     void release();
     template <class T> T* as() const { return static_cast<T*>(p); }
 };
