@@ -433,13 +433,19 @@ ppr_status ppr_debug_sweep_mixed(ppr_graph* g, double alpha, int32_t B, int32_t 
  *     residue the column's sweeps stored.
  *   sweep_tile: the LDS stage of a sweep block as ppr_options.sweep_tile
  *     (0: the graph's choice for width B).
+ *   flags: 0, or PPR_DEBUG_WIDE_GATHER: the sweeps run on two residue
+ *     buffers allocated apart, so that the gathers take full 64-bit addresses
+ *     (the form used when a block's two residue buffers do not fit one
+ *     4 GiB buffer; otherwise they gather at 32-bit offsets from its base).
+ *     The results are the same bit for bit.
  *   Other arguments as ppr_debug_sweep_mixed; PPR_ERR_ARG for values out of
  *   range.
  */
+#define PPR_DEBUG_WIDE_GATHER 1
 ppr_status ppr_debug_sweeps_mixed(ppr_graph* g, double alpha, int32_t B, int32_t chunks, int32_t sweeps,
                                   const float* y_in, const int32_t* entry, const int32_t* budget,
                                   const float* t_in, float* y_out, float* t_out, const float* omega,
-                                  int32_t residue_format, int32_t sweep_tile);
+                                  int32_t residue_format, int32_t sweep_tile, int32_t flags);
 
 /*
  * Autotuner of the batched path.  For each candidate block width (a power of

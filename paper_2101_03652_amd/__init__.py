@@ -32,6 +32,7 @@ GLOBAL_EPOCHS = 1
 RESIDUE_F32 = 0
 RESIDUE_BF16 = 1
 RESIDUE_AUTO = 2
+DEBUG_WIDE_GATHER = 1                    # ppr_debug_sweeps_mixed flag: 64-bit gather addresses
 SCAN_AUTO = 0
 SCAN_PULL = 1
 SCAN_PUSH = 2
@@ -141,7 +142,7 @@ def load() -> ctypes.CDLL:
         "ppr_debug_sweep_fp64": (st, [vp, f64, vp, vp, vp, vp]),
         "ppr_autotune": (st, [vp, f64, f64, vp, i32, vp, vp]),
         "ppr_debug_sweep_mixed": (st, [vp, f64, i32, i32, vp, vp, vp, vp, vp, i32]),
-        "ppr_debug_sweeps_mixed": (st, [vp, f64, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, i32, i32]),
+        "ppr_debug_sweeps_mixed": (st, [vp, f64, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, i32, i32, i32]),
         "ppr_block_create": (st, [vp, i32, f64, vp, ctypes.POINTER(vp)]),
         "ppr_block_destroy": (st, [vp]),
         "ppr_block_footprint": (st, [vp, i32, vp]),
@@ -466,13 +467,15 @@ def debug_sweep_mixed(graph: "Graph", alpha: float, y_in, fresh, chunks: int = 1
 
 def debug_sweeps_mixed(graph: "Graph", alpha: float, y_in, entry, sweeps: int, budget=None, t_in=None,
                        chunks: int = 1, t_out=None, omega=None, residue_format: int = RESIDUE_F32,
-                       sweep_tile: int = 0):
+                       sweep_tile: int = 0, wide_gather: bool = False):
     """One launch sequence of `sweeps` batched global sweeps carrying the
     stage accumulator.  entry: B flags (0 continuing, 1 fresh, 2 fresh with
     the accumulator restarting); budget: B sweep counts in [0, sweeps] (None:
     all); t_in: float32[n, B] initial accumulator (None: 0); sweep_tile: LDS
     stage bytes of a sweep block (0: the graph's choice).  Returns y_out
-    (same kind as y_in); t_out, if given, receives the accumulator."""
+    (same kind as y_in); t_out, if given, receives the accumulator.
+    wide_gather: run the sweeps on residue buffers allocated apart (64-bit
+    gather addresses instead of 32-bit offsets; same results)."""
     B = int(y_in.shape[1])
     en = np.ascontiguousarray(np.asarray(entry, dtype=np.int32).reshape(-1))
     if len(en) != B:
@@ -492,7 +495,7 @@ def debug_sweeps_mixed(graph: "Graph", alpha: float, y_in, entry, sweeps: int, b
                                          _ptr(t_in) if t_in is not None else None, _ptr(y_out),
                                          _ptr(t_out) if t_out is not None else None,
                                          _ptr(om) if om is not None else None, int(residue_format),
-                                         int(sweep_tile)))
+                                         int(sweep_tile), DEBUG_WIDE_GATHER if wide_gather else 0))
     return y_out
 
 

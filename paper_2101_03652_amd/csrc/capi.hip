@@ -213,17 +213,17 @@ ppr_status ppr_debug_sweep_mixed(ppr_graph* gh, double alpha, int32_t B, int32_t
                                  const int32_t* fresh, float* y_out, float* t_out, const float* omega,
                                  int32_t residue_format) {
     if (!fresh || B < 4 || B > 128) return ppr_debug_sweeps_mixed(gh, alpha, B, chunks, 1, y_in, fresh, nullptr,
-                                                                  nullptr, y_out, t_out, omega, residue_format, 0);
+                                                                  nullptr, y_out, t_out, omega, residue_format, 0, 0);
     std::vector<int32_t> en(B);
     for (int32_t b = 0; b < B; ++b) en[b] = fresh[b] ? 1 : 0;
     return ppr_debug_sweeps_mixed(gh, alpha, B, chunks, 1, y_in, en.data(), nullptr, nullptr, y_out, t_out, omega,
-                                  residue_format, 0);
+                                  residue_format, 0, 0);
 }
 
 ppr_status ppr_debug_sweeps_mixed(ppr_graph* gh, double alpha, int32_t B, int32_t chunks, int32_t sweeps,
                                   const float* y_in, const int32_t* entry, const int32_t* budget,
                                   const float* t_in, float* y_out, float* t_out, const float* omega,
-                                  int32_t residue_format, int32_t sweep_tile) {
+                                  int32_t residue_format, int32_t sweep_tile, int32_t flags) {
     return guarded([&] {
         Graph* g = reinterpret_cast<Graph*>(gh);
         if (!g || !y_in || !entry || !y_out) fail(PPR_ERR_ARG, "NULL argument");
@@ -246,8 +246,9 @@ ppr_status ppr_debug_sweeps_mixed(ppr_graph* gh, double alpha, int32_t B, int32_
         if (residue_format != PPR_RESIDUE_F32 && residue_format != PPR_RESIDUE_BF16 &&
             residue_format != PPR_RESIDUE_AUTO)
             fail(PPR_ERR_ARG, "unknown residue format");
+        if (flags & ~PPR_DEBUG_WIDE_GATHER) fail(PPR_ERR_ARG, "unknown debug flags");
         debug_sweeps_mixed(*g, alpha, B, chunks, sweeps, y_in, entry, budget, t_in, y_out, t_out, omega,
-                           residue_format, sweep_tile);
+                           residue_format, sweep_tile, (flags & PPR_DEBUG_WIDE_GATHER) != 0);
     });
 }
 

@@ -952,7 +952,8 @@ void autotune_width(Graph& g, double alpha, double lambda, const int32_t* widths
 
 void debug_sweeps_mixed(Graph& g, double alpha, int32_t B, int32_t chunks, int32_t sweeps, const float* y_in,
                         const int32_t* entry, const int32_t* budget, const float* t_in, float* y_out,
-                        float* t_out, const float* omega, int32_t residue_format, int32_t sweep_tile) {
+                        float* t_out, const float* omega, int32_t residue_format, int32_t sweep_tile,
+                        bool wide_gather) {
     HIPCHECK(hipSetDevice(g.device));
     ppr_options opt;
     ppr_options_default(&opt);
@@ -980,6 +981,15 @@ void debug_sweeps_mixed(Graph& g, double alpha, int32_t B, int32_t chunks, int32
     }
     void* a = c.Y0.p;
     void* o = c.Y1.p;
+    DevBuf w0, w1;                          // residue buffers apart from the joint one (64-bit gathers)
+    if (wide_gather) {
+        w0.alloc(c.Y0.bytes);
+        w1.alloc(c.Y1.bytes);
+        HIPCHECK(hipMemcpyAsync(w0.p, c.Y0.p, c.Y0.bytes, hipMemcpyDeviceToDevice, ss));
+        HIPCHECK(hipMemsetAsync(w1.p, 0, w1.bytes, ss));
+        a = w0.p;
+        o = w1.p;
+    }
     for (int32_t k = 0; k < sweeps; ++k) {
         mk::sweep(c, g, a, o);
         std::swap(a, o);

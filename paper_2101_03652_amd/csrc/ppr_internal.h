@@ -311,7 +311,8 @@ void autotune_width(Graph& g, double alpha, double lambda, const int32_t* widths
 
 void debug_sweeps_mixed(Graph& g, double alpha, int32_t B, int32_t chunks, int32_t sweeps, const float* y_in,
                         const int32_t* entry, const int32_t* budget, const float* t_in, float* y_out,
-                        float* t_out, const float* omega, int32_t residue_format, int32_t sweep_tile);
+                        float* t_out, const float* omega, int32_t residue_format, int32_t sweep_tile,
+                        bool wide_gather);
 
 // serving blocks (continuous batching); the handle is an opaque Block*
 void* serve_block_create(Graph& g, int32_t slots, double alpha, const ppr_options& opt);

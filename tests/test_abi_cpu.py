@@ -83,7 +83,7 @@ def test_serving_and_debug_entry_points_reject_bad_arguments():
     assert lib.ppr_block_poll(None, 0, None, None, None, None) == -1
     assert lib.ppr_slot_retire(None, 0, None, None) == -1
     assert lib.ppr_debug_sweep_mixed(None, 0.2, 8, 1, None, None, None, None, None, 0) == -1
-    assert lib.ppr_debug_sweeps_mixed(None, 0.2, 8, 1, 2, None, None, None, None, None, None, None, 0, 0) == -1
+    assert lib.ppr_debug_sweeps_mixed(None, 0.2, 8, 1, 2, None, None, None, None, None, None, None, 0, 0, 0) == -1
 
 
 def test_null_and_range_arguments():

@@ -554,3 +554,33 @@ def test_tiled_queries_and_tile_errors(graphs):
     _, st = G.query_batch(srcs[:1], ALPHA, 1e-8, P.FP64)
     assert st[0]["sweep_tile_bytes"] == 0
     G.close()
+
+
+@pytest.mark.parametrize("name", ["c1", "hub", "seam"])
+@pytest.mark.parametrize("width,chunks,fmt,sweeps", [(4, 3, "f32", 3), (32, 8, "bf16", 3), (128, 8, "bf16", 2),
+                                                     (128, 4, "f32", 1), (64, 1, "bf16", 2)])
+def test_wide_gather_addresses_same_bits(graphs, devgraphs, name, width, chunks, fmt, sweeps):
+    """A block whose two residue buffers fit one buffer of < 4 GiB gathers at
+    32-bit offsets from its base (the other tests); the full-address form of
+    larger blocks, run here on buffers allocated apart, gives the same bits:
+    outputs and stage accumulator, over chunk seams, both buffer orders
+    (several sweeps) and entry and continuing columns, with over-relaxation."""
+    g = graphs[name]
+    G = devgraphs[name]
+    print(f"[gpu] wide gather {name} width={width} chunks={chunks} {fmt} sweeps={sweeps}", flush=True)
+    rng = np.random.default_rng(width * 11 + chunks + sweeps)
+    y = rng.random((g.n, width)).astype(np.float32)
+    y[rng.random((g.n, width)) < 0.3] = 0.0
+    entry = rng.integers(0, 3, size=width).astype(np.int32)
+    t_in = rng.random((g.n, width)).astype(np.float32)
+    om = np.where(rng.random(width) < 0.5, 1.2, 1.0).astype(np.float32)
+    fmt_id = P.RESIDUE_BF16 if fmt == "bf16" else P.RESIDUE_F32
+    outs = []
+    for wide in (False, True):
+        t_out = np.empty_like(y)
+        got = P.debug_sweeps_mixed(G, ALPHA, y, entry, sweeps, t_in=t_in, chunks=chunks, t_out=t_out, omega=om,
+                                   residue_format=fmt_id, wide_gather=wide)
+        outs.append((got, t_out))
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
+    assert np.any(outs[0][0] != 0)
