@@ -198,6 +198,8 @@ typedef struct {
     int32_t offsets_64bit;  /* 1 if the device CSC offsets are int64 (m >= 2^32) */
     double build_ms;        /* wall time of ppr_graph_create */
     size_t device_bytes;    /* device memory held by the graph */
+    int32_t fp64_slices;    /* source slices of the FP64 sweep (1: none) */
+    int32_t reserved;
 } ppr_graph_info;
 
 /* Default options. */
@@ -212,14 +214,25 @@ void ppr_options_default(ppr_options* opt);
  *   n >= 1, m >= n (every node needs an out-edge).
  *   flags:   PPR_GRAPH_TRUST_INPUT skips the O(n + m) host validation;
  *            PPR_GRAPH_WIDE_OFFSETS stores the device CSC offsets as int64 even
- *            when m < 2^32 (they are int64 whenever m >= 2^32).
+ *            when m < 2^32 (they are int64 whenever m >= 2^32);
+ *            PPR_GRAPH_FP64_SLICES(S), S in [1, 64], sets the number of source
+ *            slices of the FP64 sweep (see below; 0 or absent: the library's
+ *            choice, one slice per 12 MiB of FP64 residue vector, at most 16).
  * Validation (unless skipped): PPR_ERR_CSR, PPR_ERR_DANGLING, PPR_ERR_DUPLICATE.
  * Self-loops are allowed.  The library builds on the current HIP device the
  * in-edge lists (CSC, each list ascending by source id), the out-degree
- * table and the sweep schedule.  *out receives the handle.
+ * table and the sweep schedule.  With S > 1 source slices it also keeps a
+ * copy of the in-edges grouped by the slice of their source (slice s holds
+ * the sources [ceil(s n / S), ceil((s + 1) n / S))): an FP64 sweep (Eq. 7)
+ * then makes one pass per slice, each gathering from an S-th of the residue
+ * vector, which stays in the GPU's caches, and the last pass finishes the
+ * rows.  The sum over a row's in-edges is then taken slice by slice (the
+ * rounding of FP64 sums changes, nothing else); ppr_graph_info.fp64_slices
+ * reports S and device_bytes includes the copy.  *out receives the handle.
  */
 #define PPR_GRAPH_TRUST_INPUT 1u
 #define PPR_GRAPH_WIDE_OFFSETS 2u
+#define PPR_GRAPH_FP64_SLICES(S) ((uint32_t)(S) << 8)
 ppr_status ppr_graph_create(const int64_t* row_ptr, const int32_t* col, int32_t n, int64_t m,
                             uint32_t flags, ppr_graph** out);
 
@@ -371,7 +384,8 @@ ppr_status ppr_query_trace(ppr_graph* g, int32_t s, double alpha, double lambda,
  * One global sweep on caller data, for verification of the sweep kernel:
  * r_out = (1 - alpha) r_in P and pi += alpha r_in (Simultaneous Forward Push,
  * Eq. 7), all double[n] in device memory; *r_sum_out (host) receives
- * sum(r_out) in FP64.
+ * sum(r_out) in FP64.  The sweep of the FP64 queries: one pass per source
+ * slice when the graph has them.
  */
 ppr_status ppr_debug_sweep_fp64(ppr_graph* g, double alpha, const double* r_in, double* r_out,
                                 double* pi, double* r_sum_out);

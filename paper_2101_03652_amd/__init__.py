@@ -107,7 +107,8 @@ class Options(ctypes.Structure):
 class GraphInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("max_in_degree", ctypes.c_int32), ("m", ctypes.c_int64),
                 ("max_out_degree", ctypes.c_int32), ("offsets_64bit", ctypes.c_int32),
-                ("build_ms", ctypes.c_double), ("device_bytes", ctypes.c_size_t)]
+                ("build_ms", ctypes.c_double), ("device_bytes", ctypes.c_size_t),
+                ("fp64_slices", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 _lib = None
@@ -217,7 +218,8 @@ class Graph:
     """A device-resident graph (CSC built on the GPU from CSR out-edges)."""
 
     def __init__(self, row_ptr: np.ndarray, col: np.ndarray, n: int | None = None,
-                 trust_input: bool = False, wide_offsets: bool = False):
+                 trust_input: bool = False, wide_offsets: bool = False, fp64_slices: int = 0):
+        """fp64_slices: source slices of the FP64 sweep (0: the library's choice)."""
         lib = load()
         self._row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
         self._col = np.ascontiguousarray(col, dtype=np.int32)
@@ -227,14 +229,17 @@ class Graph:
         _check(lib.ppr_graph_create(_ptr(self._row_ptr), _ptr(self._col) if self.m else None,
                                     self.n, self.m,
                                     (GRAPH_TRUST_INPUT if trust_input else 0) |
-                                    (GRAPH_WIDE_OFFSETS if wide_offsets else 0),
+                                    (GRAPH_WIDE_OFFSETS if wide_offsets else 0) |
+                                    ((int(fp64_slices) & 0xff) << 8),
                                     ctypes.byref(h)))
         self._h = h
         del self._row_ptr, self._col
 
     @classmethod
-    def from_synth(cls, g, trust_input: bool = False, wide_offsets: bool = False) -> "Graph":
-        return cls(g.row_ptr, g.col, g.n, trust_input=trust_input, wide_offsets=wide_offsets)
+    def from_synth(cls, g, trust_input: bool = False, wide_offsets: bool = False,
+                   fp64_slices: int = 0) -> "Graph":
+        return cls(g.row_ptr, g.col, g.n, trust_input=trust_input, wide_offsets=wide_offsets,
+                   fp64_slices=fp64_slices)
 
     @property
     def handle(self):

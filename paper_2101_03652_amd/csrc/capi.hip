@@ -112,6 +112,8 @@ ppr_status ppr_graph_get_info(const ppr_graph* gh, ppr_graph_info* info) {
         info->offsets_64bit = g->off64 ? 1 : 0;
         info->build_ms = g->build_ms;
         info->device_bytes = g->device_bytes();
+        info->fp64_slices = g->fp64_slices;
+        info->reserved = 0;
     });
 }
 
@@ -418,14 +420,16 @@ ppr_status ppr_debug_sweep_fp64(ppr_graph* gh, double alpha, const double* r_in,
         if (!is_device_ptr(r_in, g->device) || !is_device_ptr(r_out, g->device) || !is_device_ptr(pi, g->device))
             fail(PPR_ERR_ARG, "ppr_debug_sweep_fp64 takes device buffers");
         const Schedule& sch = g->schedule(k::sweep_nnz_cap(), k::sweep_row_cap());
-        DevBuf y((size_t)g->n * 8), yo((size_t)g->n * 8);
-        DevBuf parts(8 * (size_t)std::max(sch.n_blocks, 1024)), sum(8);
+        DevBuf y((size_t)g->n * 8), yo((size_t)g->n * 8), acc((size_t)g->n * 8);
+        int32_t nb = std::max(sch.n_blocks, 1024);
+        for (const auto& ss : g->sl_sched) nb = std::max(nb, ss->n_blocks);
+        DevBuf parts(8 * (size_t)nb), sum(8);
         int np = 0;
         hipStream_t s = nullptr;
         k::prep_y(r_in, g->deg.as<int32_t>(), alpha, g->n, y.as<double>(), parts.as<double>(), &np, s);
         k::sweep_f64(*g, sch, k::SW_ENTRY | k::SW_WRITE_R, alpha, y.as<double>(), yo.as<double>(), pi, r_in,
-                     r_out, parts.as<double>(), s);
-        k::reduce_sum(parts.as<double>(), k::sweep_parts(sch), sum.as<double>(), s);
+                     r_out, parts.as<double>(), s, acc.as<double>());
+        k::reduce_sum(parts.as<double>(), k::sweep_parts(*g, sch, acc.as<double>()), sum.as<double>(), s);
         double h = 0;
         HIPCHECK(hipMemcpy(&h, sum.p, 8, hipMemcpyDeviceToHost));
         if (r_sum_out) *r_sum_out = h;

@@ -260,13 +260,15 @@ __device__ inline void pull_rows(const OffT* __restrict__ col_ptr, const int32_t
     if (row < R && sub == 0) u = r0 + row;
 }
 
+// acc_in (nullable): the row sums of the earlier source slices, added first
+// (the last slice's pass of a sliced sweep).
 template <typename OffT, int FLAGS>
 __global__ __launch_bounds__(kBlock) void sweep_kernel(
         const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
         const int32_t* __restrict__ deg, const RowBlock* __restrict__ blocks, int32_t n_long,
         const double* __restrict__ y_in, double* __restrict__ y_out, double* __restrict__ pi,
         const double* r_in, double* r_out, double alpha,   // r_in and r_out may alias
-        double* __restrict__ partials) {
+        double* __restrict__ partials, const double* __restrict__ acc_in) {
     __shared__ double lds[kNnzCap];
     __shared__ double sh[kBlock / 64];
     const double oma = 1.0 - alpha;
@@ -276,6 +278,7 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(
                     acc);
     double contrib = 0.0;
     if (u >= 0) {
+        if (acc_in) acc = acc_in[u] + acc;
         if (FLAGS & SW_ENTRY) pi[u] += alpha * r_in[u];
         if (FLAGS & SW_FOLD) pi[u] += alpha * acc;
         if (FLAGS & SW_ACCUM) {
@@ -290,6 +293,24 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(
     }
     double t = block_sum(contrib, sh);
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// One source slice's pass of a sliced sweep (not the last): the row sums over
+// the slice's in-edges written (first slice) or added (the others) to acc.  A
+// zero sum is not added (every y is >= 0, so that changes no bit).
+template <typename OffT, bool FIRST>
+__global__ __launch_bounds__(kBlock) void slice_pass_kernel(
+        const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
+        const RowBlock* __restrict__ blocks, int32_t n_long, const double* __restrict__ y_in,
+        double* __restrict__ acc) {
+    __shared__ double lds[kNnzCap];
+    __shared__ double sh[kBlock / 64];
+    int32_t u;
+    double a;
+    pull_rows<OffT>(col_ptr, row_idx, blocks[blockIdx.x], (int32_t)blockIdx.x < n_long, y_in, lds, sh, u, a);
+    if (u < 0) return;
+    if (FIRST) acc[u] = a;
+    else if (a != 0.0) acc[u] += a;
 }
 
 // ---- residual certificate (FP64): q(v) = pi(v) / d_v gathered over in-edges,
@@ -326,15 +347,38 @@ __global__ __launch_bounds__(kBlock) void cert_kernel(
 template <typename OffT>
 void launch_sweep(const Graph& g, const Schedule& sch, int flags, double alpha, const double* y_in,
                   double* y_out, double* pi, const double* r_in, double* r_out, double* partials,
-                  hipStream_t s) {
+                  hipStream_t s, double* acc) {
+    const bool sliced = acc != nullptr && g.fp64_slices > 1;
     const OffT* cp = g.col_ptr.as<const OffT>();
-    const RowBlock* bl = sch.blocks.as<const RowBlock>();
-    dim3 grid((unsigned)sch.n_blocks), blk(kBlock);
+    const int32_t* ri = g.row_idx.as<int32_t>();
+    const Schedule* fin = &sch;
+    if (sliced) {
+        // passes over the source slices but the last, each gathering from its
+        // S-th of y_in, the row sums collected in acc
+        const int32_t S = g.fp64_slices;
+        cp = g.sl_ptr.as<const OffT>();
+        ri = g.sl_idx.as<int32_t>();
+        for (int32_t sl = 0; sl + 1 < S; ++sl) {
+            const Schedule& ss = *g.sl_sched[(size_t)sl];
+            const OffT* cps = cp + (int64_t)sl * g.n;
+            if (sl == 0)
+                hipLaunchKernelGGL((slice_pass_kernel<OffT, true>), dim3((unsigned)ss.n_blocks), dim3(kBlock), 0, s,
+                                   cps, ri, ss.blocks.as<const RowBlock>(), ss.n_long, y_in, acc);
+            else
+                hipLaunchKernelGGL((slice_pass_kernel<OffT, false>), dim3((unsigned)ss.n_blocks), dim3(kBlock), 0, s,
+                                   cps, ri, ss.blocks.as<const RowBlock>(), ss.n_long, y_in, acc);
+        }
+        fin = g.sl_sched.back().get();
+        cp += (int64_t)(S - 1) * g.n;
+    }
+    const RowBlock* bl = fin->blocks.as<const RowBlock>();
+    const double* acc_in = sliced ? acc : nullptr;
+    dim3 grid((unsigned)fin->n_blocks), blk(kBlock);
 #define PPR_SWEEP_CASE(F)                                                                        \
     case F:                                                                                      \
-        hipLaunchKernelGGL((sweep_kernel<OffT, F>), grid, blk, 0, s, cp, g.row_idx.as<int32_t>(), \
-                           g.deg.as<int32_t>(), bl, sch.n_long, y_in, y_out, pi, r_in, r_out,     \
-                           alpha, partials);                                                     \
+        hipLaunchKernelGGL((sweep_kernel<OffT, F>), grid, blk, 0, s, cp, ri,                      \
+                           g.deg.as<int32_t>(), bl, fin->n_long, y_in, y_out, pi, r_in, r_out,    \
+                           alpha, partials, acc_in);                                             \
         break;
     switch (flags) {
         PPR_SWEEP_CASE(0)
@@ -410,14 +454,17 @@ void reduce_sum(const double* partials, int nparts, double* out, hipStream_t s) 
 
 void sweep_f64(const Graph& g, const Schedule& sch, int flags, double alpha, const double* y_in,
                double* y_out, double* pi, const double* r_in, double* r_out, double* partials,
-               hipStream_t s) {
+               hipStream_t s, double* acc) {
     if (g.off64)
-        launch_sweep<int64_t>(g, sch, flags, alpha, y_in, y_out, pi, r_in, r_out, partials, s);
+        launch_sweep<int64_t>(g, sch, flags, alpha, y_in, y_out, pi, r_in, r_out, partials, s, acc);
     else
-        launch_sweep<uint32_t>(g, sch, flags, alpha, y_in, y_out, pi, r_in, r_out, partials, s);
+        launch_sweep<uint32_t>(g, sch, flags, alpha, y_in, y_out, pi, r_in, r_out, partials, s, acc);
 }
 
 int sweep_parts(const Schedule& sch) { return sch.n_blocks; }
+int sweep_parts(const Graph& g, const Schedule& sch, const double* acc) {
+    return (acc != nullptr && g.fp64_slices > 1) ? g.sl_sched.back()->n_blocks : sch.n_blocks;
+}
 
 void cert_f64(const Graph& g, const Schedule& sch, double alpha, int32_t src, const double* pi,
               double* q, double* rt_out, double* partials, hipStream_t s) {

@@ -318,6 +318,65 @@ void sort_segments(const int64_t* col_ptr, int32_t* row_idx, int32_t n, int32_t 
     HIPCHECK(hipStreamSynchronize(s));
 }
 
+// ---- source slices of the FP64 sweep
+// The first node of slice s of S: ceil(s n / S) (node v is in slice floor(v S / n)).
+__device__ inline int32_t slice_first(int32_t s, int32_t n, int32_t S) {
+    return (int32_t)(((int64_t)s * n + S - 1) / S);
+}
+// First position in the ascending list row_idx[a, b) whose source is >= v.
+__device__ inline int64_t lower_src(const int32_t* __restrict__ row_idx, int64_t a, int64_t b, int32_t v) {
+    while (a < b) {
+        const int64_t mid = a + (b - a) / 2;
+        if (row_idx[mid] < v) a = mid + 1;
+        else b = mid;
+    }
+    return a;
+}
+__global__ void slice_count_kernel(const int64_t* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
+                                   int32_t n, int32_t S, int64_t* __restrict__ cnt) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
+        const int64_t b = col_ptr[u + 1];
+        int64_t lo = col_ptr[u];
+        for (int32_t s = 0; s < S; ++s) {
+            const int64_t hi = (s + 1 < S) ? lower_src(row_idx, lo, b, slice_first(s + 1, n, S)) : b;
+            cnt[(int64_t)s * n + u] = hi - lo;
+            lo = hi;
+        }
+    }
+}
+__global__ void slice_scatter_kernel(const int64_t* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
+                                     int32_t n, int32_t S, const int64_t* __restrict__ off,
+                                     int32_t* __restrict__ sl_idx) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
+        const int64_t b = col_ptr[u + 1];
+        int64_t lo = col_ptr[u];
+        for (int32_t s = 0; s < S; ++s) {
+            const int64_t hi = (s + 1 < S) ? lower_src(row_idx, lo, b, slice_first(s + 1, n, S)) : b;
+            int64_t o = off[(int64_t)s * n + u];
+            for (int64_t e = lo; e < hi; ++e) sl_idx[o++] = row_idx[e];
+            lo = hi;
+        }
+    }
+}
+
+void slice_count(const int64_t* col_ptr, const int32_t* row_idx, int32_t n, int32_t S, int64_t* cnt,
+                 hipStream_t s) {
+    unsigned g = grid_for(n);
+    if (g > 16384) g = 16384;
+    hipLaunchKernelGGL(slice_count_kernel, dim3(g), dim3(kBlock), 0, s, col_ptr, row_idx, n, S, cnt);
+    HIPCHECK(hipGetLastError());
+}
+
+void slice_scatter(const int64_t* col_ptr, const int32_t* row_idx, int32_t n, int32_t S, const int64_t* off,
+                   int32_t* sl_idx, hipStream_t s) {
+    unsigned g = grid_for(n);
+    if (g > 16384) g = 16384;
+    hipLaunchKernelGGL(slice_scatter_kernel, dim3(g), dim3(kBlock), 0, s, col_ptr, row_idx, n, S, off, sl_idx);
+    HIPCHECK(hipGetLastError());
+}
+
 void narrow_offsets(const int64_t* in, uint32_t* out, int64_t len, hipStream_t s) {
     hipLaunchKernelGGL(narrow_kernel, dim3(grid_for(len)), dim3(kBlock), 0, s, in, out, len);
     HIPCHECK(hipGetLastError());

@@ -156,6 +156,16 @@ struct Graph {
     DevBuf col_ptr;            // uint32 or int64 [n+1]
     DevBuf row_idx;            // int32[m]
     DevBuf deg;                // int32[n] out-degree
+    // Source slices of the FP64 sweep: the in-edges regrouped by the slice of
+    // their source, slice s = sources [ceil(s n / S), ceil((s + 1) n / S)), so
+    // that one pass gathers from an S-th of the residue vector only (it stays
+    // in the caches).  sl_ptr: OffT[S n + 1], slice s's CSC offsets are
+    // sl_ptr[s n .. s n + n]; sl_idx: int32[m], the in-edges of slice s of row u
+    // at sl_idx[sl_ptr[s n + u] .. sl_ptr[s n + u + 1]), ascending.  S = 1: none.
+    int32_t fp64_slices = 1;
+    DevBuf sl_ptr;
+    DevBuf sl_idx;
+    std::vector<std::unique_ptr<Schedule>> sl_sched;   // the FP64 sweep's schedule of each slice
     std::vector<int64_t> h_col_ptr;   // host copy of the CSC offsets (schedules)
     std::vector<int32_t> h_deg;       // host copy of the out-degrees
     std::mutex sched_mu;
@@ -184,6 +194,12 @@ struct Graph {
 
 Graph* graph_create(const int64_t* row_ptr, const int32_t* col, int32_t n, int64_t m,
                     uint32_t flags);
+// The schedule of row blocks over CSC offsets cp[0..n] (Graph::schedule's rules).
+std::unique_ptr<Schedule> make_schedule(const int64_t* cp, int32_t n, int32_t nnz_cap, int32_t row_cap,
+                                        int32_t chunks, int32_t rounds);
+// Source slices of the FP64 sweep for n nodes: the count the library picks
+// (flags without PPR_GRAPH_FP64_SLICES), or the forced count of the flags.
+int32_t fp64_slice_count(int32_t n, uint32_t flags);
 void graph_validate(const int64_t* row_ptr, const int32_t* col, int32_t n, int64_t m);
 void graph_copy_csc(const Graph& g, int64_t* col_ptr, int32_t* row_idx, int32_t* deg);
 
@@ -202,6 +218,7 @@ struct QueryCtx {
     DevBuf degF;       // int64[n]   out-degrees of the frontier entries
     DevBuf off;        // int64[n+1] degree prefix of the frontier
     DevBuf partials;   // double[max blocks]
+    DevBuf acc;        // double[n]  row sums across the source slices of a sweep (graphs with slices)
     DevBuf scan_tmp;   // scan scratch
     DevBuf ctr;        // int64[8] counters: [0] |F'|, [1] vol(F'), [2..] spare
     DevBuf dsum;       // double[8]: [0] reduced sum
@@ -228,6 +245,12 @@ void scatter_in(const int64_t* row_ptr, const int32_t* col, int32_t n, const int
 void sort_segments(const int64_t* col_ptr, int32_t* row_idx, int32_t n, int32_t max_len,
                    hipStream_t s);
 void narrow_offsets(const int64_t* in, uint32_t* out, int64_t len, hipStream_t s);
+// source slices: per (slice, row) in-edge counts cnt[s n + u], then the edges
+// copied to their slice-major places (off: the exclusive scan of cnt)
+void slice_count(const int64_t* col_ptr, const int32_t* row_idx, int32_t n, int32_t S, int64_t* cnt,
+                 hipStream_t s);
+void slice_scatter(const int64_t* col_ptr, const int32_t* row_idx, int32_t n, int32_t S, const int64_t* off,
+                   int32_t* sl_idx, hipStream_t s);
 
 // local phase (FP64, one query)
 void query_init(double* r, double* pi, int32_t n, int32_t s_node, int32_t* F, hipStream_t st);
@@ -248,12 +271,17 @@ void reduce_sum(const double* partials, int nparts, double* out, hipStream_t s);
 void threshold_snapshot(const int32_t* deg, int32_t n, double alpha, double rmax, double* r, double* pi,
                         double* y, double* partials, int* nparts, hipStream_t s);
 
-// FP64 pull sweep: flags (SW_ACCUM: r_out = r_in + the pulled sum, no y_out)
+// FP64 pull sweep: flags (SW_ACCUM: r_out = r_in + the pulled sum, no y_out).
+// With acc (double[n] scratch) and a graph with source slices, the sweep runs
+// one pass per slice (the row sums collected in acc) and the last pass
+// finishes the rows; acc = nullptr: one pass over the whole CSC.  The sweep's
+// partial sums are then sweep_parts(g, sch, acc) values.
 enum : int { SW_ENTRY = 1, SW_FOLD = 2, SW_WRITE_R = 4, SW_ACCUM = 8 };
 void sweep_f64(const Graph& g, const Schedule& sch, int flags, double alpha, const double* y_in,
                double* y_out, double* pi, const double* r_in, double* r_out, double* partials,
-               hipStream_t s);
+               hipStream_t s, double* acc = nullptr);
 int sweep_parts(const Schedule& sch);
+int sweep_parts(const Graph& g, const Schedule& sch, const double* acc);
 int32_t sweep_nnz_cap();
 int32_t sweep_row_cap();
 // certificate pass: q(v) = pi(v) / d_v, then rt(u) = e_s(u) - (pi(u) - (1-alpha) sum q) / alpha;

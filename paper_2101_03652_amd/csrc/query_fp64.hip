@@ -38,7 +38,9 @@ std::unique_ptr<QueryCtx> ctx_acquire(Graph& g) {
     c->off.alloc(8 * (n + 1));
     const Schedule& sch = g.schedule(k::sweep_nnz_cap(), k::sweep_row_cap());
     size_t parts = std::max<size_t>({(size_t)sch.n_blocks, 4096, (n + 255) / 256});
+    for (const auto& ss : g.sl_sched) parts = std::max(parts, (size_t)ss->n_blocks);
     c->partials.alloc(8 * parts);
+    if (g.fp64_slices > 1) c->acc.alloc(8 * n);
     c->scan_tmp.alloc(k::scan_tmp_bytes(std::max<int64_t>(g.n, 4096)));
     c->aux.alloc(8 * (size_t)kAuxLen);
     c->ctr.alloc(64);
@@ -52,13 +54,14 @@ void ctx_release(Graph& g, std::unique_ptr<QueryCtx> c) {
     g.pool.push_back(std::move(c));
 }
 
-// Upper bound on what ctx_acquire allocates for n nodes: seven n-vectors of
-// 8 bytes and two of 4 (state, frontier lists, increments, degrees, prefix),
-// per-block partials (a sweep schedule has at most one block per row), the
-// scan scratch, the compaction counters and the readback area.
+// Upper bound on what ctx_acquire allocates for n nodes: eight n-vectors of
+// 8 bytes and two of 4 (state, frontier lists, increments, degrees, prefix,
+// the row sums across source slices), per-block partials (a sweep schedule
+// has at most one block per row), the scan scratch, the compaction counters
+// and the readback area.
 size_t fp64_ctx_footprint(int32_t n) {
     const size_t nn = (size_t)n;
-    return 8 * 7 * nn + 4 * 2 * nn + 8 + 8 * std::max<size_t>({nn, 4096, (nn + 255) / 256}) +
+    return 8 * 8 * nn + 4 * 2 * nn + 8 + 8 * std::max<size_t>({nn, 4096, (nn + 255) / 256}) +
            k::scan_tmp_bytes(std::max<int64_t>(n, 4096)) + 8 * (size_t)kAuxLen + 192;
 }
 
@@ -97,9 +100,9 @@ void ensure_chunk(Graph& g, QueryCtx& c, const Schedule& sch, double alpha) {
     try {
         for (int p = 0; p < kChunkPairs; ++p) {
             k::sweep_f64(g, sch, k::SW_FOLD, alpha, c.y1.as<double>(), c.y0.as<double>(), c.pi.as<double>(),
-                         nullptr, nullptr, c.partials.as<double>(), c.own);
+                         nullptr, nullptr, c.partials.as<double>(), c.own, c.acc.as<double>());
             k::sweep_f64(g, sch, k::SW_FOLD, alpha, c.y0.as<double>(), c.y1.as<double>(), c.pi.as<double>(),
-                         nullptr, nullptr, c.partials.as<double>(), c.own);
+                         nullptr, nullptr, c.partials.as<double>(), c.own, c.acc.as<double>());
         }
     } catch (...) {
         (void)hipStreamEndCapture(c.own, &graph);
@@ -132,6 +135,7 @@ void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_
     double* r = c.r.as<double>();
     double* pi = c.pi.as<double>();
     double* partials = c.partials.as<double>();
+    double* acc = c.acc.as<double>();          // row sums across source slices (nullptr: none)
     int64_t* hctr = c.host.as<int64_t>();
     double* hd = c.host.as<double>();
     const int32_t* deg = g.deg.as<int32_t>();
@@ -259,8 +263,8 @@ void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_
                 int np = 0;
                 k::threshold_snapshot(deg, g.n, alpha, rmax_i, r, pi, y, partials, &np, ss);
                 k::reduce_sum(partials, np, c.dsum.as<double>() + 1, ss);
-                k::sweep_f64(g, sch, k::SW_ACCUM, alpha, y, nullptr, pi, r, r, partials, ss);
-                k::reduce_sum(partials, k::sweep_parts(sch), c.dsum.as<double>(), ss);
+                k::sweep_f64(g, sch, k::SW_ACCUM, alpha, y, nullptr, pi, r, r, partials, ss, acc);
+                k::reduce_sum(partials, k::sweep_parts(g, sch, acc), c.dsum.as<double>(), ss);
                 HIPCHECK(hipMemcpyAsync(hd, c.dsum.p, 16, hipMemcpyDeviceToHost, ss));
                 HIPCHECK(hipStreamSynchronize(ss));
                 if (hd[1] == 0.0) break;      // nothing was active: the scan moved nothing
@@ -283,7 +287,7 @@ void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_
         double* y0 = c.y0.as<double>();
         double* y1 = c.y1.as<double>();
         auto sweep = [&](int flags, const double* yi, double* yo) {
-            k::sweep_f64(g, sch, flags, alpha, yi, yo, pi, r, r, partials, ss);
+            k::sweep_f64(g, sch, flags, alpha, yi, yo, pi, r, r, partials, ss, acc);
         };
         const double* yc = y0;   // buffer holding the current y
         double* yn = y1;
@@ -298,7 +302,7 @@ void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_
             // exact r_sum (the sweep's partials hold the new residues' sums)
             for (int32_t j = 1; j <= K; ++j) {
                 advance((j == 1 ? k::SW_ENTRY : 0) | (j == K ? k::SW_WRITE_R : k::SW_FOLD));
-                k::reduce_sum(partials, k::sweep_parts(sch), c.dsum.as<double>(), ss);
+                k::reduce_sum(partials, k::sweep_parts(g, sch, acc), c.dsum.as<double>(), ss);
                 HIPCHECK(hipMemcpyAsync(hd, c.dsum.p, 8, hipMemcpyDeviceToHost, ss));
                 HIPCHECK(hipStreamSynchronize(ss));
                 trace->note(1, j, edge_pushes + (int64_t)j * g.m, hd[0]);
@@ -318,7 +322,7 @@ void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_
         }
         sweeps = K;
         ev.stop(ss);
-        k::reduce_sum(partials, k::sweep_parts(sch), c.dsum.as<double>(), ss);
+        k::reduce_sum(partials, k::sweep_parts(g, sch, acc), c.dsum.as<double>(), ss);
         HIPCHECK(hipMemcpyAsync(hd, c.dsum.p, 8, hipMemcpyDeviceToHost, ss));
         HIPCHECK(hipStreamSynchronize(ss));
         r_sum = hd[0];
@@ -328,7 +332,7 @@ void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_
         while (r_sum > lambda && sweeps < opt.max_sweeps) {
             advance(k::SW_ENTRY | k::SW_WRITE_R);
             ++sweeps;
-            k::reduce_sum(partials, k::sweep_parts(sch), c.dsum.as<double>(), ss);
+            k::reduce_sum(partials, k::sweep_parts(g, sch, acc), c.dsum.as<double>(), ss);
             HIPCHECK(hipMemcpyAsync(hd, c.dsum.p, 8, hipMemcpyDeviceToHost, ss));
             HIPCHECK(hipStreamSynchronize(ss));
             r_sum = hd[0];

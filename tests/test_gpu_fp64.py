@@ -92,11 +92,15 @@ def test_fig3_sweep_values():
     assert s2 == pytest.approx(0.64, abs=1e-15)
 
 
+@pytest.mark.parametrize("slices", [1, 3, 8])
 @pytest.mark.parametrize("which", ["c1", "hub"])
-def test_one_sweep_matches_eq7(which, c1, hub):
+def test_one_sweep_matches_eq7(which, slices, c1, hub):
+    """One Eq. 7 sweep, also split into passes over source slices (the hub
+    graph's 12000-in-edge row is spread over all of them)."""
     g = {"c1": c1, "hub": hub}[which]
-    print(f"[gpu] sweep {which}", flush=True)
-    G = P.Graph.from_synth(g)
+    print(f"[gpu] sweep {which} slices={slices}", flush=True)
+    G = P.Graph.from_synth(g, fp64_slices=slices)
+    assert G.info()["fp64_slices"] == slices
     rng = np.random.default_rng(3)
     r_in = rng.random(g.n) * (rng.random(g.n) < 0.3)
     pi0 = rng.random(g.n) * 1e-3
@@ -117,11 +121,12 @@ def _sync(g, s, lam, rule, param):
     return pi, r, st
 
 
-@pytest.mark.parametrize("rule,param,wide", [(P.SWITCH_EDGES, 8.0, False), (P.SWITCH_NODES, 1.0, False),
-                                             (P.SWITCH_EDGES, 8.0, True)])
+@pytest.mark.parametrize("rule,param,wide,slices", [(P.SWITCH_EDGES, 8.0, False, 0), (P.SWITCH_NODES, 1.0, False, 0),
+                                                    (P.SWITCH_EDGES, 8.0, True, 0), (P.SWITCH_EDGES, 8.0, False, 5),
+                                                    (P.SWITCH_EDGES, 8.0, True, 4)])
 @pytest.mark.parametrize("lam", [1e-6, 1e-8])
-def test_query_matches_oracle_sync_c1(c1, rule, param, wide, lam):
-    G = P.Graph.from_synth(c1, wide_offsets=wide)
+def test_query_matches_oracle_sync_c1(c1, rule, param, wide, slices, lam):
+    G = P.Graph.from_synth(c1, wide_offsets=wide, fp64_slices=slices)
     truth_cache = {}
     for s in synth.sources(c1.n, 3):
         s = int(s)
@@ -267,6 +272,40 @@ def test_epochs_global_phase_matches_oracle(c1, hub, lam, form):
                 # two summation orders may differ by ~ (sum pi / alpha) * few ulps
                 assert st["cert_l1"] == pytest.approx(oracle.certificate(g, s, ALPHA, pi), rel=1e-9, abs=2e-14)
         G.close()
+
+
+@pytest.mark.parametrize("slices", [2, 7])
+def test_source_slices(c1, hub, slices):
+    """The FP64 sweep split into passes over source slices: the graph holds S n + 1
+    slice offsets and a copy of the in-edges (device bytes), the epoch path's pull
+    scans match the oracle's schedule as without slices, and queries give the
+    unsliced graph's answer up to FP64 summation order."""
+    G1 = P.Graph.from_synth(c1)
+    G = P.Graph.from_synth(c1, fp64_slices=slices)
+    i1, i = G1.info(), G.info()
+    assert i1["fp64_slices"] == 1 and i["fp64_slices"] == slices
+    assert i["device_bytes"] == i1["device_bytes"] + 4 * (slices * c1.n + 1) + 4 * c1.m
+    for s in [int(x) for x in synth.sources(c1.n, 2)]:
+        print(f"[gpu] fp64 sliced s={s} slices={slices}", flush=True)
+        a, sa = G1.query(s, ALPHA, 1e-8, P.FP64)
+        b, sb = G.query(s, ALPHA, 1e-8, P.FP64)
+        assert sa["sweeps"] == sb["sweeps"] and sa["local_levels"] == sb["local_levels"]
+        np.testing.assert_allclose(b, a, rtol=1e-12, atol=1e-20)
+        pi, st = G.query(s, ALPHA, 1e-8, P.FP64, global_rule=P.GLOBAL_EPOCHS, scan_form=P.SCAN_PULL, certify=1)
+        pio, ro, sto, _, _ = oracle.powerpush_sync(c1, s, ALPHA, 1e-8, P.SWITCH_EDGES, P.options().switch_param,
+                                                   global_rule=oracle.GLOBAL_EPOCHS)
+        assert st["sweeps"] == sto["sweeps"] and st["edge_pushes"] == sto["edge_pushes"]
+        np.testing.assert_allclose(pi, pio, rtol=RTOL, atol=ATOL)
+        assert st["cert_l1"] <= 1e-8
+    G.close()
+    G1.close()
+    # a hub row (12000 in-edges) cut across the slices: one query against the oracle
+    G = P.Graph.from_synth(hub, fp64_slices=slices)
+    pi, st = G.query(0, ALPHA, 1e-8, P.FP64, certify=1)
+    pio, ro, sto = _sync(hub, 0, 1e-8, P.SWITCH_EDGES, P.options().switch_param)
+    assert st["sweeps"] == sto["sweeps"]
+    np.testing.assert_allclose(pi, pio, rtol=RTOL, atol=ATOL)
+    G.close()
 
 
 def test_epochs_rule_is_fp64_only(c1):

@@ -77,11 +77,14 @@ def test_powerpush_trace_matches_oracle(c1, lam):
     G.close()
 
 
-def test_power_iteration_trace_is_eq6(c1):
+@pytest.mark.parametrize("slices", [0, 3, 8])
+def test_power_iteration_trace_is_eq6(c1, slices):
     """switch_param = 1e30: no local phase; from e_s the residue sum after k
     sweeps is (1 - alpha)^k exactly (Eq. 6), which is also the l1 error of
-    power iteration after k steps."""
-    G = P.Graph.from_synth(c1)
+    power iteration after k steps; also with the sweep split into passes over
+    source slices (slices > 1)."""
+    G = P.Graph.from_synth(c1, fp64_slices=slices)
+    assert G.info()["fp64_slices"] == max(slices, 1)
     s = int(synth.sources(c1.n, 1)[0])
     pi, tr, st = G.query_trace(s, ALPHA, 1e-8, switch_param=1e30)
     loc, glo = _check_common(tr, st)
