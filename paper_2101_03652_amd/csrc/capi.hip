@@ -426,6 +426,7 @@ ppr_status ppr_debug_sweep_fp64(ppr_graph* gh, double alpha, const double* r_in,
         DevBuf parts(8 * (size_t)nb), sum(8);
         int np = 0;
         hipStream_t s = nullptr;
+        HIPCHECK(hipMemsetAsync(acc.p, 0, acc.bytes, s));
         k::prep_y(r_in, g->deg.as<int32_t>(), alpha, g->n, y.as<double>(), parts.as<double>(), &np, s);
         k::sweep_f64(*g, sch, k::SW_ENTRY | k::SW_WRITE_R, alpha, y.as<double>(), yo.as<double>(), pi, r_in,
                      r_out, parts.as<double>(), s, acc.as<double>());

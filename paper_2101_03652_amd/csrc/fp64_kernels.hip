@@ -261,14 +261,14 @@ __device__ inline void pull_rows(const OffT* __restrict__ col_ptr, const int32_t
 }
 
 // acc_in (nullable): the row sums of the earlier source slices, added first
-// (the last slice's pass of a sliced sweep).
+// and reset to 0 for the next sweep (the last slice's pass of a sliced sweep).
 template <typename OffT, int FLAGS>
 __global__ __launch_bounds__(kBlock) void sweep_kernel(
         const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
         const int32_t* __restrict__ deg, const RowBlock* __restrict__ blocks, int32_t n_long,
         const double* __restrict__ y_in, double* __restrict__ y_out, double* __restrict__ pi,
         const double* r_in, double* r_out, double alpha,   // r_in and r_out may alias
-        double* __restrict__ partials, const double* __restrict__ acc_in) {
+        double* __restrict__ partials, double* __restrict__ acc_in) {
     __shared__ double lds[kNnzCap];
     __shared__ double sh[kBlock / 64];
     const double oma = 1.0 - alpha;
@@ -278,7 +278,10 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(
                     acc);
     double contrib = 0.0;
     if (u >= 0) {
-        if (acc_in) acc = acc_in[u] + acc;
+        if (acc_in) {
+            acc = acc_in[u] + acc;
+            acc_in[u] = 0.0;
+        }
         if (FLAGS & SW_ENTRY) pi[u] += alpha * r_in[u];
         if (FLAGS & SW_FOLD) pi[u] += alpha * acc;
         if (FLAGS & SW_ACCUM) {
@@ -295,22 +298,23 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(
     if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
-// One source slice's pass of a sliced sweep (not the last): the row sums over
-// the slice's in-edges written (first slice) or added (the others) to acc.  A
-// zero sum is not added (every y is >= 0, so that changes no bit).
-template <typename OffT, bool FIRST>
+// One source slice's pass of a sliced sweep (not the last): over the slice's
+// listed rows (those with in-edges in it; list position k holds row rows[k]),
+// each row's sum over its in-edges in the slice added to acc[row].  acc is 0
+// at the start of a sweep (the last pass resets it).  A zero sum is not added
+// (every y is >= 0, so that changes no bit).
+template <typename OffT>
 __global__ __launch_bounds__(kBlock) void slice_pass_kernel(
-        const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
+        const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx, const int32_t* __restrict__ rows,
         const RowBlock* __restrict__ blocks, int32_t n_long, const double* __restrict__ y_in,
         double* __restrict__ acc) {
     __shared__ double lds[kNnzCap];
     __shared__ double sh[kBlock / 64];
-    int32_t u;
+    int32_t k;
     double a;
-    pull_rows<OffT>(col_ptr, row_idx, blocks[blockIdx.x], (int32_t)blockIdx.x < n_long, y_in, lds, sh, u, a);
-    if (u < 0) return;
-    if (FIRST) acc[u] = a;
-    else if (a != 0.0) acc[u] += a;
+    pull_rows<OffT>(col_ptr, row_idx, blocks[blockIdx.x], (int32_t)blockIdx.x < n_long, y_in, lds, sh, k, a);
+    if (k < 0 || a == 0.0) return;
+    acc[rows[k]] += a;
 }
 
 // ---- residual certificate (FP64): q(v) = pi(v) / d_v gathered over in-edges,
@@ -356,23 +360,20 @@ void launch_sweep(const Graph& g, const Schedule& sch, int flags, double alpha, 
         // passes over the source slices but the last, each gathering from its
         // S-th of y_in, the row sums collected in acc
         const int32_t S = g.fp64_slices;
-        cp = g.sl_ptr.as<const OffT>();
         ri = g.sl_idx.as<int32_t>();
         for (int32_t sl = 0; sl + 1 < S; ++sl) {
             const Schedule& ss = *g.sl_sched[(size_t)sl];
-            const OffT* cps = cp + (int64_t)sl * g.n;
-            if (sl == 0)
-                hipLaunchKernelGGL((slice_pass_kernel<OffT, true>), dim3((unsigned)ss.n_blocks), dim3(kBlock), 0, s,
-                                   cps, ri, ss.blocks.as<const RowBlock>(), ss.n_long, y_in, acc);
-            else
-                hipLaunchKernelGGL((slice_pass_kernel<OffT, false>), dim3((unsigned)ss.n_blocks), dim3(kBlock), 0, s,
-                                   cps, ri, ss.blocks.as<const RowBlock>(), ss.n_long, y_in, acc);
+            if (ss.n_blocks == 0) continue;                 // no in-edge has its source in the slice
+            const int64_t f = g.sl_first[(size_t)sl];
+            hipLaunchKernelGGL((slice_pass_kernel<OffT>), dim3((unsigned)ss.n_blocks), dim3(kBlock), 0, s,
+                               g.sl_cptr.as<const OffT>() + f, ri, g.sl_rows.as<const int32_t>() + f,
+                               ss.blocks.as<const RowBlock>(), ss.n_long, y_in, acc);
         }
         fin = g.sl_sched.back().get();
-        cp += (int64_t)(S - 1) * g.n;
+        cp = g.sl_last.as<const OffT>();
     }
     const RowBlock* bl = fin->blocks.as<const RowBlock>();
-    const double* acc_in = sliced ? acc : nullptr;
+    double* acc_in = sliced ? acc : nullptr;
     dim3 grid((unsigned)fin->n_blocks), blk(kBlock);
 #define PPR_SWEEP_CASE(F)                                                                        \
     case F:                                                                                      \

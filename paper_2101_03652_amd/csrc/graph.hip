@@ -185,15 +185,20 @@ size_t graph_footprint(int32_t n, int64_t m) {
     const size_t nn = (size_t)n, mm = (size_t)m;
     const size_t off = (m >= (int64_t)UINT32_MAX) ? 8 : 4;  // CSC offsets: uint32 below 2^32 - 1 edges
     const size_t S = (size_t)fp64_slice_count(n, 0);
+    // source slices: the in-edges, the listed (slice, row) pairs of all slices
+    // but the last (at most (S - 1) n and at most m of them: row and offset
+    // each) and the last slice's offsets; an upper bound (the pairs depend on
+    // the graph)
+    const size_t K = S > 1 ? std::min((S - 1) * nn, mm) : 0;
     return 8 * (nn + 1) + 4 * mm            // CSR: row_ptr, col
            + off * (nn + 1) + 4 * mm        // CSC: col_ptr, row_idx
            + 4 * nn                         // out-degrees
-           + (S > 1 ? off * (S * nn + 1) + 4 * mm : 0);   // source slices: offsets, in-edges
+           + (S > 1 ? 4 * mm + (4 + off) * K + off + off * (nn + 1) : 0);
 }
 
 size_t Graph::device_bytes() const {
     size_t b = row_ptr.bytes + col.bytes + col_ptr.bytes + row_idx.bytes + deg.bytes + walk_index.bytes +
-               sl_ptr.bytes + sl_idx.bytes;
+               sl_idx.bytes + sl_rows.bytes + sl_cptr.bytes + sl_last.bytes;
     return b;
 }
 
@@ -365,11 +370,15 @@ Graph* graph_create(const int64_t* row_ptr, const int32_t* col, int32_t n, int64
     }
     // source slices of the FP64 sweep: counts per (slice, row), one scan over
     // them in slice-major order (so slice s's offsets are entries s n .. s n + n),
-    // the in-edges copied to their places
+    // the in-edges copied to their places; then the non-empty (slice, row) pairs
+    // of all slices but the last listed with their offsets (the run of a listed
+    // pair ends where the next listed one starts, the last one where the last
+    // slice starts)
     g->fp64_slices = fp64_slice_count(n, flags);
     if (g->fp64_slices > 1) {
         const int32_t S = g->fp64_slices;
         const int64_t len = (int64_t)S * n;
+        const int64_t head = (int64_t)(S - 1) * n;       // pairs of the listed slices
         DevBuf scnt(sizeof(int64_t) * ((size_t)len + 1));
         DevBuf soff(sizeof(int64_t) * ((size_t)len + 1));
         DevBuf stmp(k::scan_tmp_bytes(len));
@@ -378,21 +387,49 @@ Graph* graph_create(const int64_t* row_ptr, const int32_t* col, int32_t n, int64
         g->sl_idx.alloc(sizeof(int32_t) * (size_t)m);
         k::slice_scatter(cp64.as<int64_t>(), g->row_idx.as<int32_t>(), n, S, soff.as<int64_t>(),
                          g->sl_idx.as<int32_t>(), s);
+        DevBuf flag(sizeof(int64_t) * ((size_t)head + 1));
+        DevBuf pos(sizeof(int64_t) * ((size_t)head + 1));
+        k::nonzero_flags(scnt.as<int64_t>(), head, flag.as<int64_t>(), s);
+        k::exclusive_scan_i64(flag.as<int64_t>(), pos.as<int64_t>(), head, stmp.p, s);
+        // slice starts among the listed pairs: pos[s n], and the total K = pos[head]
+        std::vector<int64_t> first((size_t)S);
+        for (int32_t sl = 0; sl < S; ++sl)
+            HIPCHECK(hipMemcpyAsync(&first[(size_t)sl], pos.as<int64_t>() + (int64_t)sl * n, sizeof(int64_t),
+                                    hipMemcpyDeviceToHost, s));
+        HIPCHECK(hipStreamSynchronize(s));
+        const int64_t K = first[(size_t)S - 1];
+        DevBuf cp_list(sizeof(int64_t) * ((size_t)K + 1));
+        g->sl_rows.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(K, 1));
+        k::slice_compact(scnt.as<int64_t>(), pos.as<int64_t>(), soff.as<int64_t>(), head, n,
+                         g->sl_rows.as<int32_t>(), cp_list.as<int64_t>(), s);
+        HIPCHECK(hipMemcpyAsync(cp_list.as<int64_t>() + K, soff.as<int64_t>() + head, sizeof(int64_t),
+                                hipMemcpyDeviceToDevice, s));
+        const size_t ob = g->off64 ? 8 : 4;
+        g->sl_cptr.alloc(ob * ((size_t)K + 1));
+        g->sl_last.alloc(ob * ((size_t)n + 1));
         if (g->off64) {
-            g->sl_ptr.alloc(sizeof(int64_t) * ((size_t)len + 1));
-            HIPCHECK(hipMemcpyAsync(g->sl_ptr.p, soff.p, sizeof(int64_t) * ((size_t)len + 1),
+            HIPCHECK(hipMemcpyAsync(g->sl_cptr.p, cp_list.p, 8 * ((size_t)K + 1), hipMemcpyDeviceToDevice, s));
+            HIPCHECK(hipMemcpyAsync(g->sl_last.p, soff.as<int64_t>() + head, 8 * ((size_t)n + 1),
                                     hipMemcpyDeviceToDevice, s));
         } else {
-            g->sl_ptr.alloc(sizeof(uint32_t) * ((size_t)len + 1));
-            k::narrow_offsets(soff.as<int64_t>(), g->sl_ptr.as<uint32_t>(), len + 1, s);
+            k::narrow_offsets(cp_list.as<int64_t>(), g->sl_cptr.as<uint32_t>(), K + 1, s);
+            k::narrow_offsets(soff.as<int64_t>() + head, g->sl_last.as<uint32_t>(), (int64_t)n + 1, s);
         }
-        std::vector<int64_t> hoff((size_t)n + 1);
+        g->sl_first = first;
+        g->sl_first.push_back(K);
+        // one FP64 sweep schedule per slice: over the listed rows of the first
+        // S - 1 slices (their offsets are consecutive entries of the list), over
+        // all rows for the last
+        std::vector<int64_t> hoff;
         for (int32_t sl = 0; sl < S; ++sl) {
-            HIPCHECK(hipMemcpyAsync(hoff.data(), soff.as<int64_t>() + (int64_t)sl * n,
-                                    sizeof(int64_t) * ((size_t)n + 1), hipMemcpyDeviceToHost, s));
+            const bool last = sl + 1 == S;
+            const int64_t rows = last ? n : g->sl_first[(size_t)sl + 1] - g->sl_first[(size_t)sl];
+            hoff.resize((size_t)rows + 1);
+            const int64_t* src = last ? soff.as<int64_t>() + head : cp_list.as<int64_t>() + g->sl_first[(size_t)sl];
+            HIPCHECK(hipMemcpyAsync(hoff.data(), src, sizeof(int64_t) * ((size_t)rows + 1), hipMemcpyDeviceToHost, s));
             HIPCHECK(hipStreamSynchronize(s));
-            if (sl + 1 == S && hoff[n] != m) fail(PPR_ERR_DEVICE, "source slices hold a wrong edge count");
-            g->sl_sched.push_back(make_schedule(hoff.data(), n, k::sweep_nnz_cap(), k::sweep_row_cap(), 1, 0));
+            if (last && hoff[(size_t)n] != m) fail(PPR_ERR_DEVICE, "source slices hold a wrong edge count");
+            g->sl_sched.push_back(make_schedule(hoff.data(), (int32_t)rows, k::sweep_nnz_cap(), k::sweep_row_cap(), 1, 0));
         }
     }
     g->h_col_ptr.resize((size_t)n + 1);

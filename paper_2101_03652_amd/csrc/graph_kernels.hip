@@ -361,6 +361,37 @@ __global__ void slice_scatter_kernel(const int64_t* __restrict__ col_ptr, const 
     }
 }
 
+__global__ void nonzero_flags_kernel(const int64_t* __restrict__ cnt, int64_t len, int64_t* __restrict__ f) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) f[i] = cnt[i] > 0 ? 1 : 0;
+}
+__global__ void slice_compact_kernel(const int64_t* __restrict__ cnt, const int64_t* __restrict__ pos,
+                                     const int64_t* __restrict__ off, int64_t len, int32_t n,
+                                     int32_t* __restrict__ rows, int64_t* __restrict__ cptr) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) {
+        if (cnt[i] > 0) {
+            rows[pos[i]] = (int32_t)(i % n);
+            cptr[pos[i]] = off[i];
+        }
+    }
+}
+
+void nonzero_flags(const int64_t* cnt, int64_t len, int64_t* flags, hipStream_t s) {
+    unsigned g = grid_for(len);
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(nonzero_flags_kernel, dim3(g), dim3(kBlock), 0, s, cnt, len, flags);
+    HIPCHECK(hipGetLastError());
+}
+
+void slice_compact(const int64_t* cnt, const int64_t* pos, const int64_t* off, int64_t len, int32_t n,
+                   int32_t* rows, int64_t* cptr, hipStream_t s) {
+    unsigned g = grid_for(len);
+    if (g > 65536) g = 65536;
+    hipLaunchKernelGGL(slice_compact_kernel, dim3(g), dim3(kBlock), 0, s, cnt, pos, off, len, n, rows, cptr);
+    HIPCHECK(hipGetLastError());
+}
+
 void slice_count(const int64_t* col_ptr, const int32_t* row_idx, int32_t n, int32_t S, int64_t* cnt,
                  hipStream_t s) {
     unsigned g = grid_for(n);

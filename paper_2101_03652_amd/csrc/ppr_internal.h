@@ -159,12 +159,17 @@ struct Graph {
     // Source slices of the FP64 sweep: the in-edges regrouped by the slice of
     // their source, slice s = sources [ceil(s n / S), ceil((s + 1) n / S)), so
     // that one pass gathers from an S-th of the residue vector only (it stays
-    // in the caches).  sl_ptr: OffT[S n + 1], slice s's CSC offsets are
-    // sl_ptr[s n .. s n + n]; sl_idx: int32[m], the in-edges of slice s of row u
-    // at sl_idx[sl_ptr[s n + u] .. sl_ptr[s n + u + 1]), ascending.  S = 1: none.
+    // in the caches).  sl_idx: int32[m], slice-major: slice s's in-edges of
+    // row u form one run, rows ascending, runs of slice s before those of s + 1.
+    // Slices s < S - 1 list only their rows with in-edges: the K such (slice,
+    // row) pairs in that order are sl_rows (int32[K], the row) and sl_cptr
+    // (OffT[K + 1], the run's start in sl_idx; entry K is the start of the last
+    // slice), slice s being positions [sl_first[s], sl_first[s + 1]).  The last
+    // slice, whose pass finishes every row, keeps full CSC offsets sl_last
+    // (OffT[n + 1]).  S = 1: none.
     int32_t fp64_slices = 1;
-    DevBuf sl_ptr;
-    DevBuf sl_idx;
+    DevBuf sl_idx, sl_rows, sl_cptr, sl_last;
+    std::vector<int64_t> sl_first;                     // S entries: slice starts in sl_rows, then K
     std::vector<std::unique_ptr<Schedule>> sl_sched;   // the FP64 sweep's schedule of each slice
     std::vector<int64_t> h_col_ptr;   // host copy of the CSC offsets (schedules)
     std::vector<int32_t> h_deg;       // host copy of the out-degrees
@@ -246,11 +251,16 @@ void sort_segments(const int64_t* col_ptr, int32_t* row_idx, int32_t n, int32_t 
                    hipStream_t s);
 void narrow_offsets(const int64_t* in, uint32_t* out, int64_t len, hipStream_t s);
 // source slices: per (slice, row) in-edge counts cnt[s n + u], then the edges
-// copied to their slice-major places (off: the exclusive scan of cnt)
+// copied to their slice-major places (off: the exclusive scan of cnt); the
+// non-empty pairs of the first len pairs listed (flags: 1 per non-empty pair,
+// pos: their exclusive scan): rows[pos[i]] = i mod n, cptr[pos[i]] = off[i]
 void slice_count(const int64_t* col_ptr, const int32_t* row_idx, int32_t n, int32_t S, int64_t* cnt,
                  hipStream_t s);
 void slice_scatter(const int64_t* col_ptr, const int32_t* row_idx, int32_t n, int32_t S, const int64_t* off,
                    int32_t* sl_idx, hipStream_t s);
+void nonzero_flags(const int64_t* cnt, int64_t len, int64_t* flags, hipStream_t s);
+void slice_compact(const int64_t* cnt, const int64_t* pos, const int64_t* off, int64_t len, int32_t n,
+                   int32_t* rows, int64_t* cptr, hipStream_t s);
 
 // local phase (FP64, one query)
 void query_init(double* r, double* pi, int32_t n, int32_t s_node, int32_t* F, hipStream_t st);

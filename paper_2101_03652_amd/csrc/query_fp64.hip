@@ -40,7 +40,10 @@ std::unique_ptr<QueryCtx> ctx_acquire(Graph& g) {
     size_t parts = std::max<size_t>({(size_t)sch.n_blocks, 4096, (n + 255) / 256});
     for (const auto& ss : g.sl_sched) parts = std::max(parts, (size_t)ss->n_blocks);
     c->partials.alloc(8 * parts);
-    if (g.fp64_slices > 1) c->acc.alloc(8 * n);
+    if (g.fp64_slices > 1) {
+        c->acc.alloc(8 * n);
+        HIPCHECK(hipMemset(c->acc.p, 0, 8 * n));   // a sliced sweep starts from 0 and leaves 0
+    }
     c->scan_tmp.alloc(k::scan_tmp_bytes(std::max<int64_t>(g.n, 4096)));
     c->aux.alloc(8 * (size_t)kAuxLen);
     c->ctr.alloc(64);
@@ -136,6 +139,7 @@ void run_fp64_query(Graph& g, int32_t s, double alpha, double lambda, const ppr_
     double* pi = c.pi.as<double>();
     double* partials = c.partials.as<double>();
     double* acc = c.acc.as<double>();          // row sums across source slices (nullptr: none)
+    if (acc) HIPCHECK(hipMemsetAsync(acc, 0, 8 * (size_t)g.n, ss));   // whatever an earlier query left
     int64_t* hctr = c.host.as<int64_t>();
     double* hd = c.host.as<double>();
     const int32_t* deg = g.deg.as<int32_t>();

@@ -124,8 +124,11 @@ def test_footprint_bytes_without_a_graph():
     """ppr_footprint_bytes is host arithmetic: it answers before any graph or
     GPU exists.  Graph: CSR (8 (n+1) + 4 m), CSC (4 or 8 bytes per offset, 4 m),
     degrees (4 n) and, above 1.5M nodes, the FP64 sweep's source slices (one
-    per 12 MiB of FP64 vector, at most 16: S n + 1 offsets and a copy of the
-    in-edges).  A mixed block of B slots holds per (node, column) the
+    per 12 MiB of FP64 vector, at most 16: a copy of the in-edges, the listed
+    (slice, row) pairs of all slices but the last, at most min((S - 1) n, m)
+    of them with a row id and an offset each, and the last slice's n + 1
+    offsets; the pairs depend on the graph, so this part is an upper bound).
+    A mixed block of B slots holds per (node, column) the
     FP64 local-phase scratch (16 bytes), two residue buffers (2 bytes each in
     bf16 from 32 slots up, else 4), the FP64 reserve and its in-neighbour sums
     (16) and the FP32 stage accumulator (4), plus the frontier and the
@@ -133,19 +136,19 @@ def test_footprint_bytes_without_a_graph():
     n, m = 4_000_000, 70_000_000
     for B in (4, 8, 16, 32, 64, 128):
         gb, sb = P.footprint_bytes(n, m, B, P.MIXED)
-        assert gb == 8 * (n + 1) + 4 * m + 4 * (n + 1) + 4 * m + 4 * n + 4 * (3 * n + 1) + 4 * m
+        assert gb == 8 * (n + 1) + 4 * m + 4 * (n + 1) + 4 * m + 4 * n + 4 * m + 8 * (2 * n) + 4 + 4 * (n + 1)
         per = 16 + 16 + 4 + (2 * 2 if B >= 32 else 2 * 4)
         assert per * n * B <= sb <= per * n * B * 1.15 + (64 << 20), (B, sb)
     # int64 CSC offsets from 2^32 - 1 edges on
     gb, _ = P.footprint_bytes(40_000_000, 2 ** 32 - 1, 16, P.MIXED)
     assert gb == (8 * (40_000_001) + 4 * (2 ** 32 - 1) + 8 * 40_000_001 + 4 * (2 ** 32 - 1) + 4 * 40_000_000
-                  + 8 * (16 * 40_000_000 + 1) + 4 * (2 ** 32 - 1))
+                  + 4 * (2 ** 32 - 1) + 12 * (15 * 40_000_000) + 8 + 8 * 40_000_001)
     # no slices while the FP64 vector fits 12 MiB; 2 from just above
     gb, _ = P.footprint_bytes(1_500_000, 5_000_000, 4, P.MIXED)
     assert gb == 8 * 1_500_001 + 4 * 5_000_000 + 4 * 1_500_001 + 4 * 5_000_000 + 4 * 1_500_000
     gb, _ = P.footprint_bytes(1_600_000, 5_000_000, 4, P.MIXED)
     assert gb == (8 * 1_600_001 + 4 * 5_000_000 + 4 * 1_600_001 + 4 * 5_000_000 + 4 * 1_600_000
-                  + 4 * (2 * 1_600_000 + 1) + 4 * 5_000_000)
+                  + 4 * 5_000_000 + 8 * 1_600_000 + 4 + 4 * 1_600_001)
     gb1, s1 = P.footprint_bytes(n, m, 1, P.FP64)
     _, s2 = P.footprint_bytes(n, m, 2, P.FP64)
     assert s2 == 2 * s1 and 80 * n <= s1 <= 100 * n

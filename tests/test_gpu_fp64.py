@@ -276,15 +276,21 @@ def test_epochs_global_phase_matches_oracle(c1, hub, lam, form):
 
 @pytest.mark.parametrize("slices", [2, 7])
 def test_source_slices(c1, hub, slices):
-    """The FP64 sweep split into passes over source slices: the graph holds S n + 1
-    slice offsets and a copy of the in-edges (device bytes), the epoch path's pull
-    scans match the oracle's schedule as without slices, and queries give the
-    unsliced graph's answer up to FP64 summation order."""
+    """The FP64 sweep split into passes over source slices: the graph holds a copy
+    of the in-edges, the K non-empty (slice, row) pairs of all slices but the
+    last (row id and offset each, plus one end offset) and the last slice's
+    n + 1 offsets (device bytes); the epoch path's pull scans match the oracle's
+    schedule as without slices, and queries give the unsliced graph's answer up
+    to FP64 summation order."""
     G1 = P.Graph.from_synth(c1)
     G = P.Graph.from_synth(c1, fp64_slices=slices)
     i1, i = G1.info(), G.info()
     assert i1["fp64_slices"] == 1 and i["fp64_slices"] == slices
-    assert i["device_bytes"] == i1["device_bytes"] + 4 * (slices * c1.n + 1) + 4 * c1.m
+    col_ptr, row_idx, _ = oracle.csc(c1)
+    rows = np.repeat(np.arange(c1.n, dtype=np.int64), np.diff(col_ptr))
+    pair = (row_idx.astype(np.int64) * slices) // c1.n * c1.n + rows      # slice-major (slice, row) id
+    K = int(np.count_nonzero(np.unique(pair) < (slices - 1) * c1.n))
+    assert i["device_bytes"] == i1["device_bytes"] + 4 * c1.m + 4 * K + 4 * (K + 1) + 4 * (c1.n + 1)
     for s in [int(x) for x in synth.sources(c1.n, 2)]:
         print(f"[gpu] fp64 sliced s={s} slices={slices}", flush=True)
         a, sa = G1.query(s, ALPHA, 1e-8, P.FP64)
