@@ -149,8 +149,11 @@ def test_query_matches_oracle_sync_c1(c1, rule, param, wide, slices, lam):
         assert st["cert_l1"] >= err - 2e-15
 
 
+@pytest.mark.parametrize("slices", [0, 64])
 @pytest.mark.parametrize("name", ["fig1", "cycle", "star", "complete", "loop"])
-def test_query_small_graphs_closed_forms(name):
+def test_query_small_graphs_closed_forms(name, slices):
+    """Closed forms; slices = 64 asks for more source slices than nodes: one
+    node per slice (the single-node graph keeps one)."""
     a = 1 - ALPHA
     if name == "fig1":
         g, s = synth.fig1(), 0
@@ -177,7 +180,8 @@ def test_query_small_graphs_closed_forms(name):
         g, s = synth.self_loop(), 0
         x = np.array([1.0])
         tol = None
-    G = P.Graph.from_synth(g)
+    G = P.Graph.from_synth(g, fp64_slices=slices)
+    assert G.info()["fp64_slices"] == (min(slices, g.n) if slices else 1)
     for lam in (1e-4, 1e-10):
         pi, st = G.query(s, ALPHA, lam, P.FP64)
         err = np.abs(pi - x).sum()
