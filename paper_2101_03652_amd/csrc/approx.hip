@@ -228,13 +228,16 @@ void refine(Graph& g, QueryCtx& c, double alpha, double rmax, int32_t* levels_ou
     int32_t levels = 0;
     int64_t edges = 0;
     const Schedule& sch = g.schedule(k::sweep_nnz_cap(), k::sweep_row_cap());
+    // pull levels sweep over the source slices (if the graph has them): their
+    // row sums start from 0
+    if (c.acc.p) HIPCHECK(hipMemsetAsync(c.acc.p, 0, c.acc.bytes, ss));
     while (nf > 0) {
         if (vol * kPullRatio > g.m) {
             int np = 0;
             k::threshold_snapshot(g.deg.as<int32_t>(), g.n, alpha, rmax, c.r.as<double>(), c.pi.as<double>(),
                                   c.y0.as<double>(), c.partials.as<double>(), &np, ss);
             k::sweep_f64(g, sch, k::SW_ACCUM, alpha, c.y0.as<double>(), nullptr, c.pi.as<double>(),
-                         c.r.as<double>(), c.r.as<double>(), c.partials.as<double>(), ss);
+                         c.r.as<double>(), c.r.as<double>(), c.partials.as<double>(), ss, c.acc.as<double>());
             edges += vol;
             ++levels;
             frontier(F);

@@ -50,11 +50,13 @@ def _pushed_state(g, s, lam):
     return pi, r
 
 
-@pytest.mark.parametrize("name,rmax", [("c1", 1e-7), ("c1", 1e-9), ("hub", 1e-8)])
-def test_refinement_matches_oracle(graphs, name, rmax):
+@pytest.mark.parametrize("name,rmax,slices", [("c1", 1e-7, 0), ("c1", 1e-9, 0), ("hub", 1e-8, 0),
+                                               ("c1", 1e-9, 4), ("hub", 1e-8, 3)])
+def test_refinement_matches_oracle(graphs, name, rmax, slices):
+    """slices > 1: the refinement's pull levels sweep over source slices."""
     g = graphs[name]
-    print(f"[gpu] refinement {name} rmax={rmax}", flush=True)
-    G = P.Graph.from_synth(g)
+    print(f"[gpu] refinement {name} rmax={rmax} slices={slices}", flush=True)
+    G = P.Graph.from_synth(g, fp64_slices=slices)
     pi0, r0 = _pushed_state(g, 3, 0.05)
     pi_d, r_d = _dev(pi0), _dev(r0)
     levels, ep = G.debug_refine(ALPHA, rmax, pi_d, r_d)
