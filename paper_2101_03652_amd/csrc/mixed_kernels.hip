@@ -223,28 +223,37 @@ __global__ void init_sources_k(const int32_t* __restrict__ src, const int32_t* _
 
 // Frontier entry i: key = (node << shift) | column.  Columns whose local
 // phase is over (active[b] == 0) are skipped; their residue stays in place.
-__global__ void snapshot_k(const int64_t* __restrict__ F, int64_t nf, int shift,
+// The reserve taken per column is summed in LDS first: one global atomic per
+// block and column.
+__global__ __launch_bounds__(kBlock) void snapshot_k(const int64_t* __restrict__ F, int64_t nf, int shift,
                            const uint8_t* __restrict__ active, const int32_t* __restrict__ deg,
                            const double* __restrict__ alpha_b,
                            double* __restrict__ r64, double* __restrict__ pi64, double* __restrict__ X,
                            int64_t* __restrict__ degF, double* __restrict__ taken) {
+    __shared__ double s_taken[128];
+    const int Bw = 1 << shift;
+    if ((int)threadIdx.x < 128) s_taken[threadIdx.x] = 0.0;
+    __syncthreads();
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= nf) return;
-    int64_t key = F[i];
-    int32_t b = (int32_t)(key & ((1 << shift) - 1));
-    int32_t v = (int32_t)(key >> shift);
-    if (!active[b]) {
-        X[i] = 0.0;
-        degF[i] = 0;
-        return;
+    if (i < nf) {
+        int64_t key = F[i];
+        int32_t b = (int32_t)(key & (Bw - 1));
+        int32_t v = (int32_t)(key >> shift);
+        if (!active[b]) {
+            X[i] = 0.0;
+            degF[i] = 0;
+        } else {
+            const double alpha = alpha_b[b];
+            double x = atomicExch(&r64[key], 0.0);      // a key listed twice would push once
+            pi64[key] += alpha * x;
+            if (x != 0.0) atomicAdd(&s_taken[b], alpha * x);
+            int32_t d = deg[v];
+            X[i] = ((1.0 - alpha) * x) / (double)d;
+            degF[i] = d;
+        }
     }
-    const double alpha = alpha_b[b];
-    double x = atomicExch(&r64[key], 0.0);      // a key listed twice would push once
-    pi64[key] += alpha * x;
-    atomicAdd(&taken[b], alpha * x);
-    int32_t d = deg[v];
-    X[i] = ((1.0 - alpha) * x) / (double)d;
-    degF[i] = d;
+    __syncthreads();
+    if ((int)threadIdx.x < Bw && s_taken[threadIdx.x] != 0.0) atomicAdd(&taken[threadIdx.x], s_taken[threadIdx.x]);
 }
 
 // First index i with a[i] <= key < a[i+1] (a ascending, a[0] = 0 <= key < a[len]).
@@ -257,9 +266,26 @@ __device__ inline int64_t find_owner64(const int64_t* __restrict__ a, int64_t le
     return lo;
 }
 
+// First index i in [lo, hi] with a[i] <= key < a[i+1], given a[lo] <= key and
+// key < a[hi + 1].
+__device__ inline int64_t find_owner_in(const int64_t* __restrict__ a, int64_t lo, int64_t hi, int64_t key) {
+    int64_t h = hi + 1;
+    while (h - lo > 1) {
+        int64_t mid = lo + ((h - lo) >> 1);
+        if (a[mid] <= key) lo = mid; else h = mid;
+    }
+    return lo;
+}
+
 // Edge slot t of the frontier's out-edges: r(u) += X (FP64 atomic).  Residues
 // only grow here, so exactly one add carries r(u) across d_u * rmax; that
-// lane appends (u, column) to the next frontier (ballot, one atomic per wave).
+// lane appends (u, column) to the next frontier.  Persistent blocks take 256
+// consecutive slots per round.  A round's crossings are counted in LDS: one
+// global atomic per block and round reserves their next-frontier entries,
+// and the per-column counts and volumes reach the global counters once per
+// block and column at the end (a global atomic per crossing serialized on
+// the few counter addresses).  A slot's owner (frontier entry) is searched
+// between the owners of the round's first and last slot.
 __global__ __launch_bounds__(kBlock) void push_k(
         const int64_t* __restrict__ F, const int64_t* __restrict__ off, int64_t nf, int64_t vol, int shift,
         const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col, const int32_t* __restrict__ deg,
@@ -267,17 +293,28 @@ __global__ __launch_bounds__(kBlock) void push_k(
         int64_t* __restrict__ F_next,
         int64_t cap, unsigned long long* __restrict__ tail, unsigned long long* __restrict__ cnt_b,
         unsigned long long* __restrict__ vol_b) {
+    __shared__ unsigned long long s_cnt[128], s_vol[128];
+    __shared__ int64_t s_lo, s_hi;
+    __shared__ unsigned long long s_base;
+    __shared__ unsigned int s_n;
     const int lane = threadIdx.x & 63;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int Bw = 1 << shift;
+    if ((int)threadIdx.x < 128) s_cnt[threadIdx.x] = s_vol[threadIdx.x] = 0ull;
+    if (threadIdx.x == 0) s_n = 0u;
     if (off[nf] < vol) vol = off[nf];
-    for (int64_t wb = (int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63); wb < vol; wb += stride) {
-        int64_t t = wb + lane;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t t0 = (int64_t)blockIdx.x * kBlock; t0 < vol; t0 += stride) {
+        if (threadIdx.x == 0) s_lo = find_owner64(off, nf, t0);
+        if (threadIdx.x == 64) s_hi = find_owner64(off, nf, min(t0 + kBlock, vol) - 1);
+        __syncthreads();
+        const int64_t lo = s_lo, hi = s_hi;
+        const int64_t t = t0 + threadIdx.x;
         bool crossed = false;
         int64_t tkey = 0;
         if (t < vol) {
-            int64_t i = find_owner64(off, nf, t);
+            int64_t i = find_owner_in(off, lo, hi, t);
             int64_t key = F[i];
-            int32_t b = (int32_t)(key & ((1 << shift) - 1));
+            int32_t b = (int32_t)(key & (Bw - 1));
             int32_t v = (int32_t)(key >> shift);
             int64_t e = row_ptr[v] + (t - off[i]);
             int32_t u = col[e];
@@ -289,23 +326,36 @@ __global__ __launch_bounds__(kBlock) void push_k(
             double thr = (double)du * rmaxb[b];     // rmax = lambda_b / m of this column
             crossed = (old <= thr) && (now > thr);
             if (crossed) {
-                atomicAdd(&cnt_b[b], 1ull);
-                atomicAdd(&vol_b[b], (unsigned long long)du);
+                atomicAdd(&s_cnt[b], 1ull);
+                atomicAdd(&s_vol[b], (unsigned long long)du);
             }
         }
-        uint64_t mask = __ballot(crossed);
+        const uint64_t mask = __ballot(crossed);
+        const int leader = mask ? __ffsll((unsigned long long)mask) - 1 : 0;
+        unsigned int woff = 0u;
+        if (mask && lane == leader) woff = atomicAdd(&s_n, (unsigned int)__popcll(mask));
+        __syncthreads();                             // the round's counts are in s_n
+        if (threadIdx.x == 0) {
+            const unsigned int tot = s_n;
+            s_n = 0u;
+            s_base = tot ? atomicAdd(tail, (unsigned long long)tot) : 0ull;
+        }
+        __syncthreads();                             // s_base holds the round's first entry
         if (mask) {
-            int leader = __ffsll((unsigned long long)mask) - 1;
-            unsigned long long base = 0;
-            if (lane == leader) base = atomicAdd(tail, (unsigned long long)__popcll(mask));
-            base = __shfl(base, leader, 64);
-            unsigned int below = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
-                                   __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+            woff = __shfl(woff, leader, 64);
+            const unsigned int below = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                         __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
             // the host sizes F_next for the worst case; the guard keeps a
             // violation of that bound from writing out of bounds (the host
             // then sees tail > cap and fails the call)
-            if (crossed && (int64_t)(base + below) < cap) F_next[base + below] = tkey;
+            const unsigned long long slot = s_base + woff + below;
+            if (crossed && (int64_t)slot < cap) F_next[slot] = tkey;
         }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < Bw && s_cnt[threadIdx.x]) {
+        atomicAdd(&cnt_b[threadIdx.x], s_cnt[threadIdx.x]);
+        atomicAdd(&vol_b[threadIdx.x], s_vol[threadIdx.x]);
     }
 }
 
@@ -1015,7 +1065,8 @@ void snapshot(MixedCtx& c, const Graph& g, const int64_t* F, int64_t nf) {
 
 void push(MixedCtx& c, const Graph& g, const int64_t* F, int64_t nf, int64_t vol, int64_t* F_next) {
     if (vol <= 0) return;
-    unsigned gp = (unsigned)std::min<int64_t>((vol + kBlock - 1) / kBlock, 16384);
+    // persistent: 8 blocks per CU of a 256-CU device
+    unsigned gp = (unsigned)std::min<int64_t>((vol + kBlock - 1) / kBlock, 2048);
     auto* ctr = reinterpret_cast<unsigned long long*>(c.ctr.p);
     hipLaunchKernelGGL(push_k, dim3(gp), dim3(kBlock), 0, c.stream, F, c.off.as<int64_t>(), nf, vol, c.shift,
                        g.row_ptr.as<int64_t>(), g.col.as<int32_t>(), g.deg.as<int32_t>(), c.X.as<double>(),
