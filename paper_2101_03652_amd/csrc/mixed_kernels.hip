@@ -369,47 +369,97 @@ __global__ __launch_bounds__(kBlock) void push_k(
 // pulled it), so the first sweep of the column runs with its entry flag:
 // it folds the alpha-part into T and pulls y along every in-edge.
 // partials[block][B]: per-column sums of r.
-__global__ void convert_k(int32_t n, int shift, const int32_t* __restrict__ deg, const double* __restrict__ alpha_b,
-                          const int32_t* __restrict__ cmask, double* __restrict__ r64, double* __restrict__ pi64,
-                          void* __restrict__ Y, int y_bf16, float* __restrict__ T, double* __restrict__ partials) {
-    __shared__ double sh[kBlock];
-    __shared__ int32_t cm[128];
-    const int B = 1 << shift;
-    if (threadIdx.x < B) cm[threadIdx.x] = cmask[threadIdx.x];
-    __syncthreads();
-    const int64_t total = (int64_t)n << shift;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;     // a multiple of B
-    const int b = threadIdx.x & (B - 1);                          // this thread's column, fixed
-    const double alpha = alpha_b[b];
-    double acc = 0.0;
-    if (cm[b]) {
-        for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += stride) {
-            double r = r64[i];
-            double p = pi64[i];
-            int32_t u = (int32_t)(i >> shift);
-            double d = (double)deg[u];
-            double y = ((1.0 - alpha) * r) / d;
-            if (y_bf16)
-                reinterpret_cast<uint16_t*>(Y)[i] = (uint16_t)bf16_bits((float)y);
-            else
-                reinterpret_cast<float*>(Y)[i] = (float)y;
-            T[i] = (float)(((1.0 - alpha) * p) / (alpha * d));
-            if (r != 0.0) r64[i] = 0.0;        // the scratch is mostly zero already
-            if (p != 0.0) pi64[i] = 0.0;
-            acc += r;
-        }
-    }
-    sh[threadIdx.x] = acc;
-    __syncthreads();
-    if (threadIdx.x < B) {
-        double t = 0.0;
-        for (int j = threadIdx.x; j < kBlock; j += B) t += sh[j];
-        partials[(int64_t)blockIdx.x * B + threadIdx.x] = t;
-    }
+// Each thread takes four consecutive elements (one node, columns 4j .. 4j + 3;
+// j fixed, since the grid's thread count is a multiple of B / 4) per step:
+// two 32-byte loads of each FP64 array and one vector store of each output
+// when all four columns convert, one element at a time otherwise.
+__device__ inline void convert_one(int64_t i, double alpha, double d, double* __restrict__ r64,
+                                   double* __restrict__ pi64, void* __restrict__ Y, int y_bf16,
+                                   float* __restrict__ T, double& acc) {
+    const double r = r64[i];
+    const double p = pi64[i];
+    const double y = ((1.0 - alpha) * r) / d;
+    if (y_bf16)
+        reinterpret_cast<uint16_t*>(Y)[i] = (uint16_t)bf16_bits((float)y);
+    else
+        reinterpret_cast<float*>(Y)[i] = (float)y;
+    T[i] = (float)(((1.0 - alpha) * p) / (alpha * d));
+    if (r != 0.0) r64[i] = 0.0;        // the scratch is mostly zero already
+    if (p != 0.0) pi64[i] = 0.0;
+    acc += r;
 }
 
-// One block per column: thread t adds partials t, t + 256, ... in order, then
-// a fixed tree over the 256 thread sums (deterministic).
+__global__ __launch_bounds__(kBlock) void convert_k(int32_t n, int shift, const int32_t* __restrict__ deg,
+                                                    const double* __restrict__ alpha_b,
+                                                    const int32_t* __restrict__ cmask, double* __restrict__ r64,
+                                                    double* __restrict__ pi64, void* __restrict__ Y, int y_bf16,
+                                                    float* __restrict__ T, double* __restrict__ partials) {
+    __shared__ double sh[kBlock * 4];
+    const int B = 1 << shift;
+    const int Q = B >> 2;
+    const int j = threadIdx.x & (Q - 1);
+    const int b0 = 4 * j;
+    const bool m0 = cmask[b0] != 0, m1 = cmask[b0 + 1] != 0, m2 = cmask[b0 + 2] != 0, m3 = cmask[b0 + 3] != 0;
+    const double a0 = alpha_b[b0], a1 = alpha_b[b0 + 1], a2 = alpha_b[b0 + 2], a3 = alpha_b[b0 + 3];
+    double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+    const int64_t quads = (int64_t)n << (shift - 2);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (m0 && m1 && m2 && m3) {
+        for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < quads; q += stride) {
+            const double d = (double)deg[q >> (shift - 2)];
+            double2* r2 = reinterpret_cast<double2*>(r64) + 2 * q;
+            double2* p2 = reinterpret_cast<double2*>(pi64) + 2 * q;
+            const double2 ra = r2[0], rb = r2[1], pa = p2[0], pb = p2[1];
+            const float y0 = (float)(((1.0 - a0) * ra.x) / d), y1 = (float)(((1.0 - a1) * ra.y) / d);
+            const float y2 = (float)(((1.0 - a2) * rb.x) / d), y3 = (float)(((1.0 - a3) * rb.y) / d);
+            if (y_bf16)
+                reinterpret_cast<uint2*>(Y)[q] = make_uint2(bf16_bits(y0) | (bf16_bits(y1) << 16),
+                                                            bf16_bits(y2) | (bf16_bits(y3) << 16));
+            else
+                reinterpret_cast<float4*>(Y)[q] = make_float4(y0, y1, y2, y3);
+            reinterpret_cast<float4*>(T)[q] = make_float4((float)(((1.0 - a0) * pa.x) / (a0 * d)),
+                                                          (float)(((1.0 - a1) * pa.y) / (a1 * d)),
+                                                          (float)(((1.0 - a2) * pb.x) / (a2 * d)),
+                                                          (float)(((1.0 - a3) * pb.y) / (a3 * d)));
+            const double2 z = make_double2(0.0, 0.0);
+            if (ra.x != 0.0 || ra.y != 0.0) r2[0] = z;
+            if (rb.x != 0.0 || rb.y != 0.0) r2[1] = z;
+            if (pa.x != 0.0 || pa.y != 0.0) p2[0] = z;
+            if (pb.x != 0.0 || pb.y != 0.0) p2[1] = z;
+            c0 += ra.x;
+            c1 += ra.y;
+            c2 += rb.x;
+            c3 += rb.y;
+        }
+    } else if (m0 || m1 || m2 || m3) {
+        for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < quads; q += stride) {
+            const double d = (double)deg[q >> (shift - 2)];
+            if (m0) convert_one(4 * q, a0, d, r64, pi64, Y, y_bf16, T, c0);
+            if (m1) convert_one(4 * q + 1, a1, d, r64, pi64, Y, y_bf16, T, c1);
+            if (m2) convert_one(4 * q + 2, a2, d, r64, pi64, Y, y_bf16, T, c2);
+            if (m3) convert_one(4 * q + 3, a3, d, r64, pi64, Y, y_bf16, T, c3);
+        }
+    }
+    sh[4 * threadIdx.x + 0] = c0;
+    sh[4 * threadIdx.x + 1] = c1;
+    sh[4 * threadIdx.x + 2] = c2;
+    sh[4 * threadIdx.x + 3] = c3;
+    __syncthreads();
+    if ((int)threadIdx.x < Q) {
+        double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0;
+        for (int t = threadIdx.x; t < kBlock; t += Q) {
+            t0 += sh[4 * t + 0];
+            t1 += sh[4 * t + 1];
+            t2 += sh[4 * t + 2];
+            t3 += sh[4 * t + 3];
+        }
+        double* out = partials + (int64_t)blockIdx.x * B + b0;
+        out[0] = t0;
+        out[1] = t1;
+        out[2] = t2;
+        out[3] = t3;
+    }
+}
 __global__ __launch_bounds__(kBlock) void reduce_cols_k(const double* __restrict__ partials, int nparts, int B,
                                                         double* __restrict__ out) {
     __shared__ double sh[kBlock];
@@ -874,18 +924,26 @@ __global__ __launch_bounds__(kBlock) void export_k(int32_t n, int32_t b0, int32_
     constexpr int kNodes = Ex<C>::kNodes;
     __shared__ double tile[kNodes * (B + 1)];
     const int64_t u0 = (int64_t)blockIdx.x * kNodes;
-    for (int i = threadIdx.x; i < kNodes * B; i += kBlock) {
-        int du = i / B, b = i % B;
-        int64_t u = u0 + du;
-        double v = 0.0;
-        if (u < n) v = f[b] * (double)deg[u] * S[u * B + b];
-        tile[du * (B + 1) + b] = v;
+    // reserve pairs in (16-byte loads), the output streamed out (nobody
+    // reads it back here)
+    for (int i = threadIdx.x; i < kNodes * B / 2; i += kBlock) {
+        const int du = (2 * i) / B, b = (2 * i) % B;
+        const int64_t u = u0 + du;
+        double2 v = make_double2(0.0, 0.0);
+        if (u < n) {
+            const double d = (double)deg[u];
+            const double2 sv = reinterpret_cast<const double2*>(S)[(u * B + b) >> 1];
+            v = make_double2(f[b] * d * sv.x, f[b + 1] * d * sv.y);
+        }
+        tile[du * (B + 1) + b] = v.x;
+        tile[du * (B + 1) + b + 1] = v.y;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < kNodes * B; i += kBlock) {
         int b = i / kNodes, du = i % kNodes;
         int64_t u = u0 + du;
-        if (b >= b0 && b < b0 + count && u < n) out[(int64_t)(b - b0) * n + u] = tile[du * (B + 1) + b];
+        if (b >= b0 && b < b0 + count && u < n)
+            __builtin_nontemporal_store(tile[du * (B + 1) + b], &out[(int64_t)(b - b0) * n + u]);
     }
 }
 
@@ -1075,7 +1133,7 @@ void push(MixedCtx& c, const Graph& g, const int64_t* F, int64_t nf, int64_t vol
 }
 
 void convert(MixedCtx& c, const Graph& g) {
-    const unsigned gc = 1024;
+    const unsigned gc = kGridRed;       // partials hold kGridRed rows
     hipLaunchKernelGGL(convert_k, dim3(gc), dim3(kBlock), 0, c.stream, g.n, c.shift, g.deg.as<int32_t>(),
                        c.acoef.as<double>(),
                        c.cmask.as<int32_t>(), c.r64.as<double>(), c.pi64.as<double>(),
