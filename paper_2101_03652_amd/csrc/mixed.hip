@@ -114,6 +114,7 @@ size_t mixed_footprint(int32_t n, int64_t m, int Bw, int64_t fcap, bool bf16) {
     return 16 * nb                       // FP64 local-phase scratch
            + (bf16 ? 24 : 28) * nb       // Y0, Y1 (4 or 2 bytes), S, AS (8), T (4)
            + 4 * (size_t)Bw * pieces     // partial sums of the pieces
+           + 8 * (size_t)mk::kGridRed * Bw   // per-block column sums of the refresh
            + 40 * (size_t)fcap + 4 * (size_t)n + ((size_t)1 << 20);
 }
 

@@ -13,7 +13,13 @@ constexpr int kLdsBytes = 16384;   // default LDS stage of a sweep block (its ro
 constexpr int kTileCount = 3;
 constexpr int kTiles[kTileCount] = {12288, 16384, 24576};
 constexpr int kMinTile = 12288;
-constexpr int kGridRed = 2048;     // persistent grid of the refresh (fixed -> deterministic sums)
+// Persistent grid of the refresh and the conversion (fixed, so that the
+// per-column sums come out the same every run).  Block k of the refresh
+// takes schedule blocks k, k + G, ...: with G well above the blocks a device
+// holds at once, the rows in progress stay close together and a block's
+// share is short (refresh at B = 128 on 4M nodes, 70M edges: 9.78 / 9.44 /
+// 9.04 / 8.93 / 8.93 ms for G = 2048 / 4096 / 8192 / 16384 / 32768).
+constexpr int kGridRed = 16384;
 constexpr int kLongRounds = 8;     // edge rounds one sweep block runs on a long row
 constexpr int kRefreshRounds = 1 << 20;   // a refresh block runs a long row whole
 

@@ -131,8 +131,8 @@ def test_footprint_bytes_without_a_graph():
     A mixed block of B slots holds per (node, column) the
     FP64 local-phase scratch (16 bytes), two residue buffers (2 bytes each in
     bf16 from 32 slots up, else 4), the FP64 reserve and its in-neighbour sums
-    (16) and the FP32 stage accumulator (4), plus the frontier and the
-    long-row partial sums."""
+    (16) and the FP32 stage accumulator (4), plus the frontier, the
+    long-row partial sums and the refresh's per-block column sums."""
     n, m = 4_000_000, 70_000_000
     for B in (4, 8, 16, 32, 64, 128):
         gb, sb = P.footprint_bytes(n, m, B, P.MIXED)
