@@ -468,9 +468,10 @@ ppr_status ppr_debug_sweeps_mixed(ppr_graph* g, double alpha, int32_t B, int32_t
  * device memory: first the row tile of the sweep (an LDS stage of 12, 16 or
  * 24 KB per block, which sets the in-edges and rows a block takes) by timing
  * a few global sweeps with HIP events (16 KB unless another is more than 1%
- * faster); then, at that tile, one batch of `width` queries (sources spread
- * over the ids, this alpha and lambda) answered end to end after a warm-up
- * batch: local phase, sweeps, refreshes.  Each width keeps the storage with
+ * faster); then, at that tile, the same Q queries for every width (Q the
+ * largest candidate width; sources spread over the ids, this alpha and
+ * lambda) answered end to end in Q / width batches after a warm-up batch:
+ * local phase, sweeps, refreshes.  Each width keeps the storage with
  * the lower time per query, and the width with the lowest time per query
  * wins (a narrower width within 1%: less memory, lower latency).  The
  * choices are kept in the graph: the tile per (width, storage) for every

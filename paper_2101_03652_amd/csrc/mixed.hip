@@ -898,11 +898,16 @@ void autotune_width(Graph& g, double alpha, double lambda, const int32_t* widths
     if (count < 1) fail(PPR_ERR_ARG, "no candidate widths");
     size_t free_b = 0, total_b = 0;
     HIPCHECK(hipMemGetInfo(&free_b, &total_b));
+    int qmax = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        const int W = widths[i];
+        if (W < 4 || W > 128 || (W & (W - 1))) fail(PPR_ERR_ARG, "candidate widths must be powers of two in [4, 128]");
+        qmax = std::max(qmax, W);
+    }
     double best_cost = 1e300;
     int best_w = 0;
     for (int32_t i = 0; i < count; ++i) {
         int W = widths[i];
-        if (W < 4 || W > 128 || (W & (W - 1))) fail(PPR_ERR_ARG, "candidate widths must be powers of two in [4, 128]");
         if (cost_us) cost_us[i] = -1.0;
         double w_cost = 1e300;
         int w_fmt = -1;
@@ -924,12 +929,17 @@ void autotune_width(Graph& g, double alpha, double lambda, const int32_t* widths
             Block blk(g, W, alpha, opt);
             const int tile = tune_tile(g, blk);
             g.tuned_tile[bf ? 1 : 0][ilog2(W) & 7].store(tile);
-            // end to end on a batch of W queries: local phase, sweeps and
-            // refreshes (the refresh count depends on the residue format, the
-            // sweeps per query on the width), after one warm-up batch
-            const std::vector<int32_t> src = tuning_sources(g.n, W);
-            (void)time_batch(blk, src, lambda);
-            const double us = time_batch(blk, src, lambda) * 1e3 / W;
+            // end to end: local phase, sweeps and refreshes (the refresh
+            // count depends on the residue format, the sweeps per query on
+            // the width), after one warm-up batch; every width answers the
+            // same qmax queries, in qmax / W batches, so that the widths are
+            // compared on one workload
+            const std::vector<int32_t> src = tuning_sources(g.n, qmax);
+            (void)time_batch(blk, std::vector<int32_t>(src.begin(), src.begin() + W), lambda);
+            double ms = 0.0;
+            for (int q0 = 0; q0 < qmax; q0 += W)
+                ms += time_batch(blk, std::vector<int32_t>(src.begin() + q0, src.begin() + q0 + W), lambda);
+            const double us = ms * 1e3 / qmax;
             if (us < w_cost * 0.99 || (us < w_cost && fmt == PPR_RESIDUE_F32)) {
                 w_cost = us;
                 w_fmt = fmt;
