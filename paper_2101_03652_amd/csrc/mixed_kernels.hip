@@ -723,8 +723,18 @@ __global__ __launch_bounds__(kBlock) void combine_k(
     const int c = threadIdx.x % C;
     if (i >= count) return;
     const LongRow L = rows[i];
+    const Vec<ST::K>* part = partials + (int64_t)L.first * C + c;
     Vec<ST::K> acc = v_zero<ST::K>();
-    for (int32_t p = 0; p < L.npieces; ++p) acc = v_add(acc, partials[(int64_t)(L.first + p) * C + c]);
+    // eight pieces' loads in flight at a time; the sums still go in slot order
+    int32_t p = 0;
+    for (; p + 8 <= L.npieces; p += 8) {
+        Vec<ST::K> v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = part[(int64_t)(p + k) * C];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc = v_add(acc, v[k]);
+    }
+    for (; p < L.npieces; ++p) acc = v_add(acc, part[(int64_t)p * C]);
     finish_row<C, SOR, ST, AF>(L.row, c, acc, step_p[0], step_p[1], scale, afac, Y_in, Y_out, T, kb, entry, omega);
 }
 
