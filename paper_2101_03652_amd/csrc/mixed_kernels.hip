@@ -188,20 +188,40 @@ __device__ inline void lds_dma16(const void* src, void* dst) {
 // take their kItems indices from it with shuffles, instead of every lane
 // loading each of its kItems indices.  -1 marks an item beyond the round's
 // nr edges.  NT: the index loads are non-temporal.
+template <int C, int kItems>
+struct ShuffledIndices {
+    static constexpr int G = (C <= 64) ? 64 / C : 0;      // distinct edges per item per wave
+    static constexpr bool value = G > 0 && G * kItems <= 64;
+};
+
+// The shuffled form in two steps: the loader lanes' loads (issued early by a
+// caller that has other work to overlap them with), then the shuffles.
+template <int C, int kItems, bool NT>
+__device__ inline int32_t round_index_load(const int32_t* __restrict__ row_idx, int64_t first, int32_t nr) {
+    constexpr int G = ShuffledIndices<C, kItems>::G;
+    const int lane = threadIdx.x & 63;
+    const int32_t w0 = (int32_t)(threadIdx.x >> 6) * G;   // the wave's first edge of item 0
+    // loader lane L = j + G k holds edge w0 + j + k (256 / C)
+    const int j = lane % G, kk = lane / G;
+    const int32_t el = w0 + j + kk * (kBlock / C);
+    int32_t mine = -1;
+    if (lane < G * kItems && el < nr) mine = NT ? __builtin_nontemporal_load(&row_idx[first + el]) : row_idx[first + el];
+    return mine;
+}
+
+template <int C, int kItems>
+__device__ inline void round_index_spread(int32_t mine, int32_t (&vv)[kItems]) {
+    constexpr int G = ShuffledIndices<C, kItems>::G;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < kItems; ++k) vv[k] = __shfl(mine, (lane / C) + G * k, 64);
+}
+
 template <int C, int kItems, bool NT>
 __device__ inline void round_indices(const int32_t* __restrict__ row_idx, int64_t first, int32_t nr,
                                      int32_t (&vv)[kItems]) {
-    constexpr int G = (C <= 64) ? 64 / C : 0;      // distinct edges per item per wave
-    if constexpr (G > 0 && G * kItems <= 64) {
-        const int lane = threadIdx.x & 63;
-        const int32_t w0 = (int32_t)(threadIdx.x >> 6) * G;   // the wave's first edge of item 0
-        // loader lane L = j + G k holds edge w0 + j + k (256 / C)
-        const int j = lane % G, kk = lane / G;
-        const int32_t el = w0 + j + kk * (kBlock / C);
-        int32_t mine = -1;
-        if (lane < G * kItems && el < nr) mine = NT ? __builtin_nontemporal_load(&row_idx[first + el]) : row_idx[first + el];
-#pragma unroll
-        for (int k = 0; k < kItems; ++k) vv[k] = __shfl(mine, (lane / C) + G * k, 64);
+    if constexpr (ShuffledIndices<C, kItems>::value) {
+        round_index_spread<C, kItems>(round_index_load<C, kItems, NT>(row_idx, first, nr), vv);
     } else {
 #pragma unroll
         for (int k = 0; k < kItems; ++k) {
@@ -771,6 +791,32 @@ __global__ void from_bf16_k(int64_t count, const uint16_t* __restrict__ src, flo
 // does not clear them).  The per-column values every row reads (source,
 // rmask, 1 - alpha_b, 1 / (1 - alpha_b)) are copied into LDS once per block;
 // the |rt| reduction reuses the LDS stage after a barrier.
+// Threads per (row, column group) of a refresh block of R rows: the largest
+// power of two up to 64 with 2 T2 R C <= 256 (1 for a long row).
+template <int C>
+__device__ inline int rf_threads(int32_t R) {
+    int T2 = 1;
+    while (T2 < 64 && 2 * T2 * R * C <= kBlock) T2 <<= 1;
+    return T2;
+}
+
+// The loads a refresh block needs before its first gathers: its rows' in-edge
+// bounds and, in the shuffled index form, the loader lanes' indices of its
+// first round.  Every lane loads bounds (its own row's, or the block's first
+// row's when it has none), and the values are used only by the block's own
+// iteration, so that nothing here waits for them.
+template <typename OffT, int C, int kItems, bool kPre>
+__device__ inline void rf_prefetch(const OffT* __restrict__ col_ptr, const int32_t* __restrict__ row_idx,
+                                   const RowBlock& b, OffT& p0, OffT& p1, int32_t& mine) {
+    const bool whole = b.piece == -1;
+    const int32_t R = whole ? b.r1 - b.r0 : 1;
+    const int32_t row = (int32_t)(threadIdx.x / rf_threads<C>(R)) / C;
+    const int32_t at = (whole && row < R) ? b.r0 + row : b.r0;
+    p0 = col_ptr[at];
+    p1 = col_ptr[at + 1];
+    if constexpr (kPre) mine = round_index_load<C, kItems, false>(row_idx, b.e0, min(Rf<C>::kNnz, b.ne));
+}
+
 template <int B>
 struct RfParams {
     int32_t src[B], rmask[B];
@@ -799,30 +845,45 @@ __global__ __launch_bounds__(kBlock) void refresh_k(
     }
     __syncthreads();
     double cs0 = 0.0, cs1 = 0.0, cs2 = 0.0, cs3 = 0.0;   // threads c < C: |rt| of columns 4c..4c+3
+    // Software pipeline over the schedule blocks: the next block's descriptor
+    // is loaded during this block's gathers, and its rows' in-edge bounds and
+    // (shuffled form) its first round's indices before this block's row
+    // finish, so that those loads overlap this block's instead of waiting in
+    // front of the next block's gathers.
+    constexpr bool kPre = ShuffledIndices<C, P::kItems>::value;
+    RowBlock b{};
+    OffT p0 = 0, p1 = 0;
+    int32_t mine = -1;
+    if ((int32_t)blockIdx.x < n_blocks) {
+        b = blocks[blockIdx.x];
+        rf_prefetch<OffT, C, P::kItems, kPre>(col_ptr, row_idx, b, p0, p1, mine);
+    }
     for (int32_t bi = blockIdx.x; bi < n_blocks; bi += gridDim.x) {
-        const RowBlock b = blocks[bi];
+        const int32_t bn = bi + (int32_t)gridDim.x;
+        RowBlock nb = b;
         const bool whole = b.piece == -1;
         const int32_t r0 = b.r0;
         const int32_t R = whole ? b.r1 - r0 : 1;
         const int32_t ne = b.ne;
         const int64_t e0 = b.e0;
-        int T2 = 1;
-        while (T2 < 64 && 2 * T2 * R * C <= kBlock) T2 <<= 1;
+        const int T2 = rf_threads<C>(R);
         const int32_t grp = threadIdx.x / T2;
         const int sub = threadIdx.x % T2;
         const int32_t row = grp / C;
         const int c = grp % C;
         int32_t s0 = 0, s1 = 0;
         if (whole && row < R) {
-            s0 = (int32_t)((int64_t)col_ptr[r0 + row] - e0);
-            s1 = (int32_t)((int64_t)col_ptr[r0 + row + 1] - e0);
+            s0 = (int32_t)((int64_t)p0 - e0);
+            s1 = (int32_t)((int64_t)p1 - e0);
         }
         double g0 = 0.0, g1 = 0.0, g2 = 0.0, g3 = 0.0;
         for (int32_t base = 0; base < ne; base += P::kNnz) {
             const int32_t nr = min(P::kNnz, ne - base);
             int32_t vv[P::kItems];
-            round_indices<C, P::kItems, false>(row_idx, e0 + base, nr, vv);
+            if (kPre && base == 0) round_index_spread<C, P::kItems>(mine, vv);
+            else round_indices<C, P::kItems, false>(row_idx, e0 + base, nr, vv);
             __syncthreads();                       // the previous LDS reads are done
+            if (base == 0 && bn < n_blocks) nb = blocks[bn];
             // the in-neighbours' accumulator rows land in the stage by DMA (16
             // bytes per lane at the stage's wave layout lds[t + 256 k])
 #pragma unroll
@@ -838,6 +899,10 @@ __global__ __launch_bounds__(kBlock) void refresh_k(
                 g3 += (double)t.w;
             }
         }
+        if (ne <= 0 && bn < n_blocks) nb = blocks[bn];     // a block of rows without in-edges
+        OffT np0 = 0, np1 = 0;
+        int32_t nmine = -1;
+        if (bn < n_blocks) rf_prefetch<OffT, C, P::kItems, kPre>(col_ptr, row_idx, nb, np0, np1, nmine);
         for (int o = T2 >> 1; o >= 1; o >>= 1) {
             g0 += __shfl_xor(g0, o, 64);
             g1 += __shfl_xor(g1, o, 64);
@@ -907,6 +972,10 @@ __global__ __launch_bounds__(kBlock) void refresh_k(
             }
         }
         __syncthreads();                           // red and the LDS stage are reused
+        b = nb;
+        p0 = np0;
+        p1 = np1;
+        mine = nmine;
     }
     if ((int)threadIdx.x < C) {
         double* out = partials + (int64_t)blockIdx.x * (4 * C) + 4 * threadIdx.x;
