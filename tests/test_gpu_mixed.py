@@ -134,6 +134,34 @@ def test_small_graphs_and_hubs():
     _check_batch(h, srcs, out, st, 1e-9, None)
 
 
+def _no_in_edges_graph(n=3000, head=400, seed=11):
+    """Nodes 0 .. head-1 have out-edges only (into the rest), so whole sweep
+    and refresh schedule blocks at the start hold rows without in-edges; the
+    rest is a random graph of out-degree 5 on itself."""
+    rng = np.random.default_rng(seed)
+    edges = []
+    for u in range(head):
+        for v in rng.choice(np.arange(head, n), size=3, replace=False):
+            edges.append((u, int(v)))
+    for u in range(head, n):
+        for v in rng.choice(np.arange(head, n - 1), size=5, replace=False):
+            edges.append((u, int(v) if v < u else int(v) + 1))
+    return synth.from_edges(n, edges, "no-in-edges head")
+
+
+def test_blocks_of_rows_without_in_edges():
+    """Schedule blocks whose rows have no in-edges (ne = 0): the refresh's
+    pipelined loop loads the next block's descriptor after such a block too,
+    and the sweeps leave those rows' residue at zero after the first push."""
+    g = _no_in_edges_graph()
+    G = P.Graph.from_synth(g)
+    srcs = [0, 7, 399, 400, 1234, 2999, 5, 2000]
+    for width in (8, 32, 128):
+        for chunks in (1, 3):
+            out, st = G.query_batch(srcs, ALPHA, 1e-9, P.MIXED, batch_cols=width, sweep_chunks=chunks)
+            _check_batch(g, srcs, out, st, 1e-9, None)
+
+
 @pytest.mark.parametrize("width", [8, 32])
 def test_outputs_device_and_residual(c1, width):
     """The FP64 residual output (the flush) equals the oracle's residual of the
