@@ -87,22 +87,49 @@ __device__ inline int32_t find_owner(const int64_t* __restrict__ a, int32_t len,
     return lo;
 }
 
+// First index i in [lo, hi] with a[i] <= key < a[i+1], given a[lo] <= key and
+// key < a[hi + 1].
+__device__ inline int64_t find_owner_between(const int64_t* __restrict__ a, int64_t lo, int64_t hi, int64_t key) {
+    int64_t h = hi + 1;
+    while (h - lo > 1) {
+        int64_t mid = lo + ((h - lo) >> 1);
+        if (a[mid] <= key) lo = mid; else h = mid;
+    }
+    return lo;
+}
+
+// Edge slot t of the frontier's out-edges: r(u) += X (FP64 atomic); the lane
+// whose add carries r(u) across d_u rmax appends u.  Persistent blocks take
+// 256 consecutive slots per round; a round's appended nodes are counted in
+// LDS and reserve their entries with one global atomic per block and round,
+// and the appended volume reaches ctr[1] once per block (global atomics per
+// wave serialize on the two counter addresses when most waves append).
 __global__ __launch_bounds__(kBlock) void push_kernel(
         const int32_t* __restrict__ F, const int64_t* __restrict__ off, int32_t nf, int64_t vol,
         const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
         const int32_t* __restrict__ deg, const double* __restrict__ X, double rmax,
         double* __restrict__ r, int32_t* __restrict__ F_next, unsigned long long* __restrict__ ctr) {
+    __shared__ int64_t s_lo, s_hi;
+    __shared__ unsigned long long s_base, s_vol;
+    __shared__ unsigned int s_n;
     const int lane = threadIdx.x & 63;
-    const int64_t wave_base0 = ((int64_t)blockIdx.x * blockDim.x + (threadIdx.x & ~63));
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    if (threadIdx.x == 0) {
+        s_n = 0u;
+        s_vol = 0ull;
+    }
     if (off[nf] < vol) vol = off[nf];   // never address past the frontier's last out-edge
-    for (int64_t wb = wave_base0; wb < vol; wb += stride) {     // uniform per wave
-        int64_t t = wb + lane;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t t0 = (int64_t)blockIdx.x * kBlock; t0 < vol; t0 += stride) {   // uniform per block
+        if (threadIdx.x == 0) s_lo = find_owner(off, nf, t0);
+        if (threadIdx.x == 64) s_hi = find_owner(off, nf, min(t0 + kBlock, vol) - 1);
+        __syncthreads();
+        const int64_t lo = s_lo, hi = s_hi;
+        const int64_t t = t0 + threadIdx.x;
         bool crossed = false;
         int32_t u = 0;
         int32_t du = 0;
         if (t < vol) {
-            int32_t i = find_owner(off, nf, t);
+            const int64_t i = find_owner_between(off, lo, hi, t);
             int32_t v = F[i];
             int64_t e = row_ptr[v] + (t - off[i]);
             u = col[e];
@@ -113,24 +140,34 @@ __global__ __launch_bounds__(kBlock) void push_kernel(
             double thr = (double)du * rmax;
             crossed = (old <= thr) && (now > thr);
         }
-        uint64_t mask = __ballot(crossed);
+        const uint64_t mask = __ballot(crossed);
+        const int leader = mask ? __ffsll((unsigned long long)mask) - 1 : 0;
+        unsigned int woff = 0u;
         if (mask) {
-            int cnt = __popcll(mask);
-            int leader = __ffsll((unsigned long long)mask) - 1;
             // sum of out-degrees of the appended nodes (volume of S^(j+1))
             int64_t myvol = crossed ? du : 0;
             for (int o = 32; o >= 1; o >>= 1) myvol += __shfl_xor(myvol, o, 64);
-            unsigned long long base = 0;
             if (lane == leader) {
-                base = atomicAdd(&ctr[0], (unsigned long long)cnt);
-                atomicAdd(&ctr[1], (unsigned long long)myvol);
+                woff = atomicAdd(&s_n, (unsigned int)__popcll(mask));
+                atomicAdd(&s_vol, (unsigned long long)myvol);
             }
-            base = __shfl(base, leader, 64);
+        }
+        __syncthreads();                             // the round's appended nodes are counted
+        if (threadIdx.x == 0) {
+            const unsigned int tot = s_n;
+            s_n = 0u;
+            s_base = tot ? atomicAdd(&ctr[0], (unsigned long long)tot) : 0ull;
+        }
+        __syncthreads();                             // s_base: the round's first entry
+        if (mask) {
+            woff = __shfl(woff, leader, 64);
             unsigned int below = __builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
                                    __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
-            if (crossed) F_next[base + below] = u;
+            if (crossed) F_next[s_base + woff + below] = u;
         }
     }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_vol) atomicAdd(&ctr[1], s_vol);
 }
 
 __global__ void prep_kernel(const double* __restrict__ r, const int32_t* __restrict__ deg, double alpha,
@@ -427,7 +464,7 @@ void frontier_push(const int32_t* F, const int64_t* off, int32_t nf, int64_t vol
                    double rmax, double* r, int32_t* F_next, int64_t* ctr, hipStream_t s) {
     if (vol <= 0) return;
     unsigned g = grid_for(vol);
-    if (g > 16384) g = 16384;
+    if (g > 2048) g = 2048;             // persistent: 8 blocks per CU of a 256-CU device
     hipLaunchKernelGGL(push_kernel, dim3(g), dim3(kBlock), 0, s, F, off, nf, vol, row_ptr, col, deg, X,
                        rmax, r, F_next, reinterpret_cast<unsigned long long*>(ctr));
     HIPCHECK(hipGetLastError());
