@@ -521,15 +521,24 @@ __global__ void scale_k(const int32_t* __restrict__ deg, int32_t n, double alpha
 // A piece writes its raw sum to a partial slot; combine_k adds a long row's
 // pieces in slot order and finishes the row.  Y_out is read (rows < lo) and written
 // (rows >= lo) in the same launch, so it carries no __restrict__.
-template <int C, typename ST>
-__device__ inline typename ST::V gather_gs(const typename ST::V* __restrict__ Y_in, const typename ST::V* Y_out,
-                                           int32_t v, int c, int32_t lo, bool fresh, const Vec<ST::K>& enf) {
-    const int64_t i = (int64_t)v * C + c;
-    if (v >= lo) return Y_in[i];
-    if (!fresh) return Y_out[i];
-    // an entry sweep: the earlier chunk's new value plus the fresh residue
-    // nobody has pulled yet (exact in FP32; one more rounding in bf16)
-    return ST::pack(v_add(ST::value(Y_out[i]), v_mul(ST::value(Y_in[i]), enf)));
+// An entry sweep of a later chunk: what a source in an earlier chunk hands
+// over is its new value plus the fresh residue nobody has pulled yet (exact in
+// FP32; one more rounding in bf16), for the fresh columns (enf = 1); a source
+// in this or a later chunk hands over its fresh residue.
+// fm: bit j set when column j of the vector is fresh; the residue of a
+// column that is not fresh is multiplied by 0 (so the sum has the same bits
+// as with a 0/1 factor per column).
+__device__ inline float fresh_part(float x, uint32_t fm, int j) { return ((fm >> j) & 1u) ? x : x * 0.f; }
+
+template <typename ST>
+__device__ inline typename ST::V entry_value(typename ST::V y_out, typename ST::V y_in, uint32_t fm) {
+    if (fm == 0u) return y_out;
+    Vec<ST::K> r = ST::value(y_in);
+#pragma unroll
+    for (int i = 0; i < ST::K / 4; ++i)
+        r.q[i] = make_float4(fresh_part(r.q[i].x, fm, 4 * i), fresh_part(r.q[i].y, fm, 4 * i + 1),
+                             fresh_part(r.q[i].z, fm, 4 * i + 2), fresh_part(r.q[i].w, fm, 4 * i + 3));
+    return ST::pack(v_add(ST::value(y_out), r));
 }
 
 // y'(u) = scale(u) * acc for the columns inside their sweep budget (0 for the
@@ -640,17 +649,7 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
     __shared__ typename ST::V lds[L / 16];
     const RowBlock b = blocks[blockIdx.x];
     const int32_t step = step_p[0];
-    // every item of this thread belongs to column chunk threadIdx.x % C
-    Vec<K> enf = v_zero<K>();
-    bool fresh = false;
-    const bool entry_gs = step == 0 && lo > 0;     // a first sweep of a later chunk: register path
-    if (entry_gs) {
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            enf.q[i] = flag4(reinterpret_cast<const int4*>(entry)[(threadIdx.x % C) * Q + i]);
-            fresh |= (enf.q[i].x + enf.q[i].y + enf.q[i].z + enf.q[i].w) != 0.f;
-        }
-    }
+    const bool entry_gs = step == 0 && lo > 0;     // a first sweep of a later chunk
     const bool whole = b.piece == -1;              // whole rows, one round
     const int32_t r0 = b.r0;
     const int32_t R = whole ? b.r1 - r0 : 1;
@@ -705,18 +704,34 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8, 8))) 
                 }
             }
         } else {
-            // an entry sweep of a later chunk combines two values per gather
-            typename ST::V gv[P::kItems];
+            // an entry sweep of a later chunk: every source's fresh residue
+            // lands in the stage by DMA; a source in an earlier chunk also hands
+            // over its new value, loaded into registers first and then combined
+            // into this lane's own stage slot (lds[t + 256 k], where the DMA put
+            // the residue)
+            const int tc = threadIdx.x % C;
+            typename ST::V yo[P::kItems];
 #pragma unroll
-            for (int k = 0; k < P::kItems; ++k) {
-                gv[k] = (vv[k] >= 0) ? gather_gs<C, ST>(Y_in, Y_out, vv[k], threadIdx.x % C, lo, fresh, enf)
-                                     : ST::zero();
-            }
+            for (int k = 0; k < P::kItems; ++k)
+                if (vv[k] >= 0 && vv[k] < lo) yo[k] = Y_out[(int64_t)vv[k] * C + tc];
             if (base > 0) __syncthreads();             // the previous round's LDS reads are done
 #pragma unroll
+            for (int k = 0; k < P::kItems; ++k)
+                if (vv[k] >= 0) lds_dma16(Y_in + (int64_t)vv[k] * C + tc, ldsw + k * kBlock);
+            // the entry flags of this thread's columns (every item of the thread
+            // belongs to column chunk tc), read while the gathers are in flight
+            uint32_t fm = 0u;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const int4 e4 = reinterpret_cast<const int4*>(entry)[tc * Q + i];
+                fm |= ((e4.x ? 1u : 0u) | (e4.y ? 2u : 0u) | (e4.z ? 4u : 0u) | (e4.w ? 8u : 0u)) << (4 * i);
+            }
+#pragma unroll
             for (int k = 0; k < P::kItems; ++k) {
-                int32_t it = threadIdx.x + k * kBlock;
-                if (it / C < nr) lds[it] = gv[k];
+                if (vv[k] >= 0 && vv[k] < lo) {
+                    typename ST::V* slot = lds + threadIdx.x + k * kBlock;
+                    *slot = entry_value<ST>(yo[k], *slot, fm);
+                }
             }
         }
         __syncthreads();
