@@ -82,7 +82,9 @@ typedef enum {
                               stored residue takes is residual that the next FP64 refresh
                               measures, so stages are shorter (refresh factor 40).  Blocks
                               of at least 8 columns (a sweep lane holds 8) */
-    PPR_RESIDUE_AUTO = 2   /* bf16 for blocks of at least 32 columns, else FP32 (default) */
+    PPR_RESIDUE_AUTO = 2   /* the storage ppr_autotune chose for the block's width; on a
+                              graph not tuned at that width, bf16 for blocks of at least
+                              32 columns, else FP32 (default) */
 } ppr_residue_format;
 
 /* Rule that ends the local (frontier) phase and starts the global sweeps. */
